@@ -1,0 +1,128 @@
+"""CPU oracle (test infrastructure only).
+
+A plain FP64 OpenMP C implementation of the direct discrete sum for Phi and
+grad Phi, the vertex pseudonormals and the Newton chart projection, written
+from the paper (see ``oracle.c`` for the equations it follows).  Only the
+tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py``
+import this package; the product library never touches it.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force=True):
+    """Compile liboracle.so with gcc (plain -O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11",
+                               _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        L.oracle_radial.argtypes = [P, i64, f64, P, P]
+        L.oracle_nodes.argtypes = [P, P, i64, P, i32, P, P]
+        L.oracle_eval.argtypes = [P, P, i64, P, P, i64, P, i32, P, P, i64, P, P, P, P, ctypes.c_int]
+        L.oracle_pseudonormals.argtypes = [P, i64, P, i64, P]
+        L.oracle_project.argtypes = [P, i64, P, i64, P, i32, P, i64, P, i32, P, i32, P, i64,
+                                     f64, i32, P, P, P, P, ctypes.c_int]
+        L.oracle_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def threads():
+    return _load().oracle_threads()
+
+
+def radial(rho, sigma):
+    """K(rho) and F(rho) = K'(rho)/rho for one sigma (see oracle.c)."""
+    rho = _f64(rho).ravel()
+    K, F = np.empty_like(rho), np.empty_like(rho)
+    _load().oracle_radial(_p(rho), rho.size, float(sigma), _p(K), _p(F))
+    return K, F
+
+
+def nodes(verts, tris, rule):
+    """Quadrature nodes y (N, 3) and weighted area normals a = w J (N, 3)."""
+    verts, rule = _f64(verts), _f64(rule)
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    n = len(tris) * len(rule)
+    y, a = np.empty((n, 3)), np.empty((n, 3))
+    _load().oracle_nodes(_p(verts), _p(tris), len(tris), _p(rule), len(rule), _p(y), _p(a))
+    return y, a
+
+
+def evaluate(verts, tris, sigma, rule, x, tri_offsets=None, x_mesh=None,
+             with_abs=False, nthreads=0):
+    """Phi (n,) and grad Phi (n, 3) by the direct FP64 sum over all nodes."""
+    verts, rule, x = _f64(verts), _f64(rule), _f64(x).reshape(-1, 3)
+    sigma = _f64(np.atleast_1d(sigma))
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    off = None if tri_offsets is None else np.ascontiguousarray(tri_offsets, dtype=np.int64)
+    xm = None if x_mesh is None else np.ascontiguousarray(x_mesh, dtype=np.int32)
+    n = len(x)
+    phi, grad = np.empty(n), np.empty((n, 3))
+    aphi = np.empty(n) if with_abs else None
+    agrad = np.empty(n) if with_abs else None
+    _load().oracle_eval(_p(verts), _p(tris), len(tris), _p(off), _p(sigma), sigma.size,
+                        _p(rule), len(rule), _p(x), _p(xm), n, _p(phi), _p(grad),
+                        _p(aphi), _p(agrad), int(nthreads))
+    if with_abs:
+        return phi, grad, aphi, agrad
+    return phi, grad
+
+
+def pseudonormals(verts, tris):
+    verts = _f64(verts)
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    H = np.empty((len(verts), 3))
+    _load().oracle_pseudonormals(_p(verts), len(verts), _p(tris), len(tris), _p(H))
+    return H
+
+
+def project(verts, tris, sigma, rule, chart_uv, tau=1e-12, max_iter=40, sel=None,
+            tri_offsets=None, nthreads=0):
+    """Newton chart projection onto Phi = 1/2 for the chart nodes of the
+    triangles ``sel`` (all if None).  Returns h, x, status, iters with
+    index k * np + i."""
+    verts, rule, uv = _f64(verts), _f64(rule), _f64(chart_uv).reshape(-1, 2)
+    sigma = _f64(np.atleast_1d(sigma))
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    off = None if tri_offsets is None else np.ascontiguousarray(tri_offsets, dtype=np.int64)
+    nmesh = 0 if off is None else len(off) - 1
+    s = None if sel is None else np.ascontiguousarray(sel, dtype=np.int64)
+    nsel = len(tris) if s is None else len(s)
+    npn = len(uv)
+    tot = nsel * npn
+    h, xo = np.empty(tot), np.empty((tot, 3))
+    st, it = np.empty(tot, np.int8), np.empty(tot, np.int8)
+    _load().oracle_project(_p(verts), len(verts), _p(tris), len(tris), _p(off), nmesh,
+                           _p(sigma), sigma.size, _p(rule), len(rule), _p(uv), npn,
+                           _p(s), nsel, float(tau), int(max_iter), _p(h), _p(xo),
+                           _p(st), _p(it), int(nthreads))
+    return h, xo, st, it

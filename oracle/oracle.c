@@ -1,0 +1,329 @@
+/*
+ * Reference oracle for the smoothed-indicator level set (TEST INFRASTRUCTURE).
+ *
+ * This file is a plain, slow, FP64 CPU implementation of what the GPU path
+ * computes.  It exists only to check that path: the tests, the smoke check
+ * and the CPU-baseline leg of the benchmark load it; the product library never
+ * does.  It shares no code, header, table or constant with the GPU sources.
+ *
+ * What it computes (paper: Vico, Greengard, O'Neil, Rachh, "A fast boundary
+ * integral method for high-order multiscale mesh generation"):
+ *
+ *  - quadrature nodes on each flat skeleton triangle (eq. tparam; discrete
+ *    sum eq. discrete_int):  y = P1 + u (P2-P1) + v (P3-P1), with the
+ *    area-weighted outward normal  J = (P2-P1) x (P3-P1)  so that
+ *    N_hat da = J du dv;
+ *  - the level-set function as the direct discrete sum (eq. surf, kerpsi,
+ *    discrete_int)  Phi(x) = sum_nodes w psi_sigma(x, y)  with
+ *        psi da = -(J . d) K(rho) w du dv,   d = x - y,  rho = |d|,
+ *        K(rho) = erf(u)/(4 pi rho^3) - sqrt(2/pi) exp(-u^2)/(4 pi sigma rho^2),
+ *        u = rho / (sqrt(2) sigma);
+ *    sigma is the width attached to the source triangle (constant or one per
+ *    triangle);  for u < 1 the difference of the two singular terms is
+ *    replaced by its Taylor series (section 4.4, eq. kerpsi_asymp), summed
+ *    to 1e-18 relative instead of the printed five terms;
+ *  - the gradient as the exact x-derivative of the same sum:
+ *        grad psi da = [ -J K(rho) - (J . d) F(rho) d ] w du dv,
+ *        F(rho) = K'(rho) / rho
+ *    where F is the function the paper prints after eq. gradPhi.  (The paper's
+ *    eq. gradPhi carries the opposite sign on its second term, and its small-u
+ *    gradient series eq. kerpsi_asymp2 omits the (N.d) d term; the exact
+ *    derivative is used here, and F also gets its own series for u < 1.)
+ *    No cut-off and no far-field approximation: every pair uses the full
+ *    kernel, accumulated with Neumaier compensation;
+ *  - vertex pseudonormals (eq. mkvertexpn) and the linear pseudonormal field
+ *    on each triangle (eq. mkpseudovec);
+ *  - the chart projection: for chart node (u_i, v_i) of triangle j, the root
+ *    h of Phi(T + h H) = 1/2 (eq. newton) by Newton's iteration (eq. newtoneq,
+ *    derivative eq. newtonderiv) from h = 0, safeguarded by bisection inside
+ *    the bracket [lo, hi] the iterates establish, starting from
+ *    [-hmax, hmax] with hmax = 16 sigma_j / |H| (Phi decreases along H near
+ *    the level set, so g > 0 raises lo and g < 0 lowers hi; a Newton step that
+ *    leaves (lo, hi) or has H.grad Phi >= 0 is replaced by the midpoint).
+ *    Stop when |dh| <= tau sigma_j.  The safeguard, the scale-free stopping
+ *    test and the status codes are additions to the paper's plain iteration.
+ *
+ * Build: gcc -O2 -fopenmp -shared -fPIC oracle.c -o liboracle.so -lm
+ * (no -ffast-math: the order of floating-point operations is as written).
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <stdlib.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_PI 3.14159265358979323846264338327950288
+
+enum { ST_CONVERGED = 0, ST_MAXITER = 1, ST_NOBRACKET = 2, ST_DEGENERATE_H = 3 };
+
+/* ------------------------------------------------------------------ sums */
+typedef struct { double s, c; } nsum;           /* Neumaier compensated sum */
+
+static void nsum_add(nsum *a, double v)
+{
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v)) a->c += (a->s - t) + v;
+    else                       a->c += (v - t) + a->s;
+    a->s = t;
+}
+static double nsum_get(const nsum *a) { return a->s + a->c; }
+
+/* ------------------------------------------------------ radial functions */
+/* K(rho) and F(rho) = K'(rho)/rho for width sigma (see header). */
+static void radial_KF(double rho, double sigma, double *K, double *F)
+{
+    const double u = rho / (sqrt(2.0) * sigma);
+    if (u < 1.0) {
+        /* K = [sum_n 2 (-1)^n u^2n / (n! (2n+3))] / (4 sqrt(2 pi^3) sigma^3)
+         * F = -[sum_m 2 (-1)^m u^2m / (m! (2m+5))] / (4 sqrt(2 pi^3) sigma^5) */
+        const double u2 = u * u;
+        double p = 1.0;              /* (-1)^n u^2n / n! */
+        double sk = 0.0, sf = 0.0;
+        for (int n = 0; n < 40; ++n) {
+            double tk = 2.0 * p / (2.0 * n + 3.0);
+            double tf = 2.0 * p / (2.0 * n + 5.0);
+            sk += tk;
+            sf += tf;
+            if (fabs(tk) < 1e-18 * fabs(sk) && fabs(tf) < 1e-18 * fabs(sf)) break;
+            p *= -u2 / (double)(n + 1);
+        }
+        const double c = 1.0 / (4.0 * sqrt(2.0 * ORC_PI * ORC_PI * ORC_PI) * sigma * sigma * sigma);
+        *K = c * sk;
+        *F = -c * sf / (sigma * sigma);
+    } else {
+        const double e = exp(-u * u);
+        const double er = erf(u);
+        const double r2 = rho * rho, r3 = r2 * rho, r5 = r3 * r2;
+        const double s2 = sigma * sigma, s3 = s2 * sigma;
+        *K = er / (4.0 * ORC_PI * r3) - sqrt(2.0 / ORC_PI) * e / (4.0 * ORC_PI * sigma * r2);
+        /* F as printed after eq. gradPhi */
+        *F = (e * sqrt(2.0) * (r3 + 3.0 * rho * s2) - 3.0 * sqrt(ORC_PI) * s3 * er)
+             / (4.0 * pow(ORC_PI, 1.5) * r5 * s3);
+    }
+}
+
+/* exported for the kernel-function checks: K, F at rho for one sigma */
+void oracle_radial(const double *rho, int64_t n, double sigma, double *K, double *F)
+{
+    for (int64_t i = 0; i < n; ++i) radial_KF(rho[i], sigma, &K[i], &F[i]);
+}
+
+/* --------------------------------------------------------- quadrature nodes */
+static void tri_node(const double *verts, const int32_t *tri, const double *uvw,
+                     double y[3], double a[3])
+{
+    const double *P1 = verts + 3 * (int64_t)tri[0];
+    const double *P2 = verts + 3 * (int64_t)tri[1];
+    const double *P3 = verts + 3 * (int64_t)tri[2];
+    double tu[3], tv[3];
+    for (int c = 0; c < 3; ++c) {
+        tu[c] = P2[c] - P1[c];
+        tv[c] = P3[c] - P1[c];
+        y[c] = P1[c] + uvw[0] * tu[c] + uvw[1] * tv[c];
+    }
+    a[0] = uvw[2] * (tu[1] * tv[2] - tu[2] * tv[1]);
+    a[1] = uvw[2] * (tu[2] * tv[0] - tu[0] * tv[2]);
+    a[2] = uvw[2] * (tu[0] * tv[1] - tu[1] * tv[0]);
+}
+
+/* all nodes y and weighted normals a = w J, node index = tri * nq + m */
+void oracle_nodes(const double *verts, const int32_t *tris, int64_t ntris,
+                  const double *rule, int32_t nq, double *y, double *a)
+{
+    for (int64_t j = 0; j < ntris; ++j)
+        for (int m = 0; m < nq; ++m)
+            tri_node(verts, tris + 3 * j, rule + 3 * m, y + 3 * (j * nq + m), a + 3 * (j * nq + m));
+}
+
+/* ------------------------------------------------------------ evaluation */
+typedef struct {
+    const double *verts;
+    const int32_t *tris;
+    const int64_t *tri_off;   /* nmesh+1 or NULL */
+    int64_t ntris;
+    const double *sigma;      /* length 1 or ntris */
+    int64_t nsigma;
+    const double *rule;
+    int32_t nq;
+} srcset;
+
+static void eval_point(const srcset *S, const double x[3], int32_t mesh,
+                       double *phi, double grad[3], double *aphi, double *agrad)
+{
+    int64_t j0 = 0, j1 = S->ntris;
+    if (S->tri_off) { j0 = S->tri_off[mesh]; j1 = S->tri_off[mesh + 1]; }
+    nsum sp = {0, 0}, sg[3] = {{0, 0}, {0, 0}, {0, 0}}, ap = {0, 0}, ag = {0, 0};
+    for (int64_t j = j0; j < j1; ++j) {
+        const double sigma = S->nsigma == 1 ? S->sigma[0] : S->sigma[j];
+        for (int m = 0; m < S->nq; ++m) {
+            double y[3], a[3], d[3];
+            tri_node(S->verts, S->tris + 3 * j, S->rule + 3 * m, y, a);
+            d[0] = x[0] - y[0]; d[1] = x[1] - y[1]; d[2] = x[2] - y[2];
+            const double rho = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            double K, F;
+            radial_KF(rho, sigma, &K, &F);
+            const double ad = a[0] * d[0] + a[1] * d[1] + a[2] * d[2];
+            const double tphi = -ad * K;
+            double tg[3];
+            for (int c = 0; c < 3; ++c) tg[c] = -a[c] * K - ad * F * d[c];
+            nsum_add(&sp, tphi);
+            for (int c = 0; c < 3; ++c) nsum_add(&sg[c], tg[c]);
+            nsum_add(&ap, fabs(tphi));
+            nsum_add(&ag, sqrt(tg[0] * tg[0] + tg[1] * tg[1] + tg[2] * tg[2]));
+        }
+    }
+    *phi = nsum_get(&sp);
+    for (int c = 0; c < 3; ++c) grad[c] = nsum_get(&sg[c]);
+    if (aphi) *aphi = nsum_get(&ap);
+    if (agrad) *agrad = nsum_get(&ag);
+}
+
+static void set_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+}
+
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Phi and grad Phi at n targets.  x_mesh (may be NULL) selects, per target,
+ * the mesh (CSR range of tri_off) whose triangles are summed. aphi / agrad
+ * (may be NULL) receive sum |term| and sum ||grad term||. */
+void oracle_eval(const double *verts, const int32_t *tris, int64_t ntris,
+                 const int64_t *tri_off, const double *sigma, int64_t nsigma,
+                 const double *rule, int32_t nq,
+                 const double *x, const int32_t *x_mesh, int64_t n,
+                 double *phi, double *grad, double *aphi, double *agrad, int nthreads)
+{
+    srcset S = {verts, tris, tri_off, ntris, sigma, nsigma, rule, nq};
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < n; ++i)
+        eval_point(&S, x + 3 * i, x_mesh ? x_mesh[i] : 0, &phi[i], grad + 3 * i,
+                   aphi ? &aphi[i] : NULL, agrad ? &agrad[i] : NULL);
+}
+
+/* ----------------------------------------------------------- pseudonormals */
+/* H(P) = sum_T theta_P(T) N_hat(T) / sum_T theta_P(T)  (eq. mkvertexpn). */
+void oracle_pseudonormals(const double *verts, int64_t nverts, const int32_t *tris,
+                          int64_t ntris, double *H)
+{
+    double *A = (double *)calloc((size_t)nverts, sizeof(double));
+    for (int64_t i = 0; i < 3 * nverts; ++i) H[i] = 0.0;
+    for (int64_t j = 0; j < ntris; ++j) {
+        const int32_t *t = tris + 3 * j;
+        const double *P[3] = {verts + 3 * (int64_t)t[0], verts + 3 * (int64_t)t[1], verts + 3 * (int64_t)t[2]};
+        double e1[3], e2[3], N[3];
+        for (int c = 0; c < 3; ++c) { e1[c] = P[1][c] - P[0][c]; e2[c] = P[2][c] - P[0][c]; }
+        N[0] = e1[1] * e2[2] - e1[2] * e2[1];
+        N[1] = e1[2] * e2[0] - e1[0] * e2[2];
+        N[2] = e1[0] * e2[1] - e1[1] * e2[0];
+        const double nn = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+        if (nn == 0.0) continue;
+        for (int k = 0; k < 3; ++k) {
+            const double *A0 = P[k], *A1 = P[(k + 1) % 3], *A2 = P[(k + 2) % 3];
+            double p[3], q[3], cr[3];
+            for (int c = 0; c < 3; ++c) { p[c] = A1[c] - A0[c]; q[c] = A2[c] - A0[c]; }
+            cr[0] = p[1] * q[2] - p[2] * q[1];
+            cr[1] = p[2] * q[0] - p[0] * q[2];
+            cr[2] = p[0] * q[1] - p[1] * q[0];
+            const double theta = atan2(sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]),
+                                       p[0] * q[0] + p[1] * q[1] + p[2] * q[2]);
+            const int64_t v = t[k];
+            for (int c = 0; c < 3; ++c) H[3 * v + c] += theta * N[c] / nn;
+            A[v] += theta;
+        }
+    }
+    for (int64_t v = 0; v < nverts; ++v)
+        if (A[v] > 0.0)
+            for (int c = 0; c < 3; ++c) H[3 * v + c] /= A[v];
+    free(A);
+}
+
+/* ---------------------------------------------------------- Newton projection */
+/* For each selected triangle j (sel[k], or k if sel is NULL) and each chart
+ * node (u_i, v_i): T, H from eq. tparam / mkpseudovec, then the safeguarded
+ * Newton iteration described in the header.  Output index k * np + i. */
+void oracle_project(const double *verts, int64_t nverts, const int32_t *tris, int64_t ntris,
+                    const int64_t *tri_off, int32_t nmesh,
+                    const double *sigma, int64_t nsigma, const double *rule, int32_t nq,
+                    const double *chart_uv, int32_t np, const int64_t *sel, int64_t nsel,
+                    double tau, int32_t max_iter,
+                    double *h_out, double *x_out, int8_t *status, int8_t *iters,
+                    int nthreads)
+{
+    srcset S = {verts, tris, tri_off, ntris, sigma, nsigma, rule, nq};
+    double *Hv = (double *)malloc(sizeof(double) * 3 * (size_t)nverts);
+    oracle_pseudonormals(verts, nverts, tris, ntris, Hv);
+    set_threads(nthreads);
+    const int64_t total = nsel * (int64_t)np;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t idx = 0; idx < total; ++idx) {
+        const int64_t k = idx / np;
+        const int i = (int)(idx % np);
+        const int64_t j = sel ? sel[k] : k;
+        int32_t mesh = 0;
+        if (tri_off) {           /* mesh holding triangle j */
+            int32_t lo = 0, hi = nmesh;
+            while (hi - lo > 1) { int32_t mid = (lo + hi) / 2; if (tri_off[mid] <= j) lo = mid; else hi = mid; }
+            mesh = lo;
+        }
+        const double u = chart_uv[2 * i], v = chart_uv[2 * i + 1];
+        const int32_t *t = tris + 3 * j;
+        double T[3], H[3];
+        for (int c = 0; c < 3; ++c) {
+            const double p1 = verts[3 * (int64_t)t[0] + c], p2 = verts[3 * (int64_t)t[1] + c], p3 = verts[3 * (int64_t)t[2] + c];
+            const double h1 = Hv[3 * (int64_t)t[0] + c], h2 = Hv[3 * (int64_t)t[1] + c], h3 = Hv[3 * (int64_t)t[2] + c];
+            T[c] = p1 + u * (p2 - p1) + v * (p3 - p1);
+            H[c] = h1 + u * (h2 - h1) + v * (h3 - h1);
+        }
+        const double sj = nsigma == 1 ? sigma[0] : sigma[j];
+        const double nH = sqrt(H[0] * H[0] + H[1] * H[1] + H[2] * H[2]);
+        double h = 0.0;
+        int st = ST_MAXITER, it = 0;
+        if (!(nH >= 1e-3)) {
+            st = ST_DEGENERATE_H;
+        } else {
+            const double hmax = 16.0 * sj / nH;
+            double lo = -hmax, hi = hmax;
+            int done = 0;
+            for (int k2 = 1; k2 <= max_iter; ++k2) {
+                double x[3], phi, g[3];
+                for (int c = 0; c < 3; ++c) x[c] = T[c] + h * H[c];
+                eval_point(&S, x, mesh, &phi, g, NULL, NULL);
+                const double gv = phi - 0.5;
+                const double gp = H[0] * g[0] + H[1] * g[1] + H[2] * g[2];
+                it = k2;
+                if (gv > 0.0) lo = h;
+                else if (gv < 0.0) hi = h;
+                else { st = ST_CONVERGED; done = 1; break; }
+                double hn = (gp < 0.0) ? h - gv / gp : NAN;
+                if (!(hn > lo && hn < hi)) hn = 0.5 * (lo + hi);
+                const double dh = hn - h;
+                h = hn;
+                if (fabs(dh) <= tau * sj) { st = ST_CONVERGED; done = 1; break; }
+            }
+            /* not converged: NOBRACKET when the iterates were driven into the
+             * outer half of the search range |h| <= hmax (no root near the
+             * skeleton), MAXITER otherwise */
+            if (!done) st = (fabs(h) > 0.5 * hmax) ? ST_NOBRACKET : ST_MAXITER;
+        }
+        h_out[idx] = h;
+        for (int c = 0; c < 3; ++c) x_out[3 * idx + c] = T[c] + h * H[c];
+        status[idx] = (int8_t)st;
+        iters[idx] = (int8_t)it;
+    }
+    free(Hv);
+}

@@ -1,0 +1,384 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's own formula: each compares it with an
+independent definition (incomplete gamma functions, closed-form Gaussian
+convolutions of a box and a ball, Gauss's law / solid angles, finite
+differences, brute force at 30 digits, symmetry) or with constants printed in
+the paper (tests/golden/paper_constants.txt).
+"""
+import os
+from fractions import Fraction
+
+import mpmath as mp
+import numpy as np
+import pytest
+from scipy.special import erf
+from scipy.integrate import quad
+
+import oracle
+from workloads import (dunavant6, chart_nodes, cube_mesh, icosphere, star_surface,
+                       triangle_diameters, box_targets, shell_targets, configs)
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "paper_constants.txt")
+RT2, PI = np.sqrt(2.0), np.pi
+
+
+def golden():
+    out = {}
+    for line in open(GOLD):
+        if line.strip() and not line.startswith("#"):
+            k, *v = line.split()
+            out[k] = v
+    return out
+
+
+# ------------------------------------------------------------ closed forms
+def box_closed(x, s, lo=0.0, hi=1.0):
+    """Gaussian convolution of the box indicator and its gradient."""
+    f = 0.5 * (erf((hi - x) / (RT2 * s)) + erf((x - lo) / (RT2 * s)))
+    e = (np.exp(-(x - lo) ** 2 / (2 * s * s)) - np.exp(-(hi - x) ** 2 / (2 * s * s))) / (np.sqrt(2 * PI) * s)
+    P = f.prod(1)
+    G = np.stack([e[:, i] * np.prod(np.delete(f, i, 1), 1) for i in range(3)], 1)
+    return P, G
+
+
+def ball_closed(r, s):
+    """Gaussian convolution of the unit-ball indicator, Phi(r) and dPhi/dr."""
+    Em = np.exp(-(1 - r) ** 2 / (2 * s * s))
+    Ep = np.exp(-(1 + r) ** 2 / (2 * s * s))
+    phi = 0.5 * (erf((1 - r) / (RT2 * s)) + erf((1 + r) / (RT2 * s))) - s / (r * np.sqrt(2 * PI)) * (Em - Ep)
+    dphi = ((s / r ** 2 - 1 / (r * s)) * Em - (s / r ** 2 + 1 / (r * s)) * Ep) / np.sqrt(2 * PI)
+    return phi, dphi
+
+
+def test_ball_closed_form_is_the_convolution():
+    # the ball formula itself against direct radial quadrature of the convolution
+    s = 0.2
+    for r in (0.3, 0.9, 1.1, 1.7):
+        f = lambda q: (q / r) * (np.exp(-(r - q) ** 2 / (2 * s * s)) - np.exp(-(r + q) ** 2 / (2 * s * s)))
+        val = quad(f, 0, 1, epsabs=1e-14, epsrel=1e-14)[0] / (np.sqrt(2 * PI) * s)
+        assert abs(val - ball_closed(np.array([r]), s)[0][0]) < 1e-12
+        h = 1e-5
+        fd = (ball_closed(np.array([r + h]), s)[0] - ball_closed(np.array([r - h]), s)[0]) / (2 * h)
+        assert abs(fd[0] - ball_closed(np.array([r]), s)[1][0]) < 1e-8
+
+
+# -------------------------------------------------------- radial functions
+def test_radial_vs_incomplete_gamma():
+    mp.mp.dps = 40
+    for sigma in (0.05, 1.0):
+        c = 1 / (4 * mp.sqrt(2) * mp.pi ** 1.5 * mp.mpf(sigma) ** 3)
+        us = np.concatenate([np.linspace(1e-4, 3, 61), [0.999999, 1.0, 1.000001, 4, 5.66, 8, 12]])
+        rho = us * RT2 * sigma
+        K, F = oracle.radial(rho, sigma)
+        for i, u in enumerate(us):
+            u = mp.mpf(u)
+            Kx = c * mp.gammainc(1.5, 0, u * u) / u ** 3
+            Fx = -c * mp.gammainc(2.5, 0, u * u) / (u ** 5 * mp.mpf(sigma) ** 2)
+            assert abs(K[i] - float(Kx)) <= 2e-15 * abs(float(Kx)), (sigma, float(u))
+            assert abs(F[i] - float(Fx)) <= 1e-14 * abs(float(Fx)), (sigma, float(u))
+    # rho = 0: finite limits 2/3 c and -2/5 c / sigma^2
+    K, F = oracle.radial(np.array([0.0]), 1.0)
+    c0 = 1 / (4 * RT2 * PI ** 1.5)
+    assert abs(K[0] - 2 / 3 * c0) < 1e-16 and abs(F[0] + 2 / 5 * c0) < 1e-16
+
+
+def test_radial_matches_printed_series():
+    g = golden()
+    coef = [float(Fraction(c)) for c in g["series_K"]]
+    ucut, err = map(float, g["series_err_below_u"])
+    sigma = 0.3
+    c0 = 1 / (4 * np.sqrt(2 * PI ** 3) * sigma ** 3)
+    us = np.linspace(0, ucut, 41)
+    K, _ = oracle.radial(us * RT2 * sigma, sigma)
+    printed = sum(cf * us ** (2 * k) for k, cf in enumerate(coef))
+    # "about 1e-13": the first omitted term, -u^10/780, is 1.28e-13 in size at u = 0.1
+    assert np.max(np.abs(K / c0 - printed)) < 1.5 * err
+    assert np.max(np.abs(K / c0 - printed + us ** 10 / 780)) < 1e-15
+
+
+def test_far_kernel_is_dipole_beyond_8sigma():
+    # at rho >= 8 sigma K is the Laplace dipole factor 1/(4 pi rho^3) to the
+    # paper's tail bounds (section 4.4): erf deficit + exp term
+    g = golden()
+    b = float(g["tail_8sigma_erf"][0]) + float(g["tail_8sigma_exp"][0])
+    sigma = 0.01
+    rho = np.array([8.0, 9.0, 12.0]) * sigma
+    K, F = oracle.radial(rho, sigma)
+    dip = 1 / (4 * PI * rho ** 3)
+    rel = np.abs(K - dip) / dip
+    assert 1e-15 < rel[0] < 10 * b and np.all(rel[1:] < 1e-15)
+    # F = K'/rho -> -3/(4 pi rho^5); its exp term is larger by (rho/sigma)^3 / 3
+    relF = np.abs(F + 3 * dip / rho ** 2) / (3 * dip / rho ** 2)
+    bF = b * (1 + np.sqrt(2 / PI) * (rho / sigma) ** 3 / 3)
+    assert np.all(relF < 2 * bF) and relF[0] > 1e-13
+
+
+# ----------------------------------------------------------- quadrature nodes
+def test_nodes_closed_surface_identities():
+    v, t = cube_mesh(4)
+    y, a = oracle.nodes(v, t, dunavant6())
+    assert np.abs(a.sum(0)).max() < 1e-14                     # sum of w J over a closed surface
+    assert abs(np.sum(y * a) / 3 - 1.0) < 1e-13               # divergence theorem: volume
+    v, t = icosphere(3)
+    y, a = oracle.nodes(v, t, dunavant6())
+    # nodes lie on the triangles, normals outward
+    assert np.all(np.einsum("ij,ij->i", a, y) > 0)
+
+
+# ------------------------------------------------------- box (config 1 geometry)
+@pytest.mark.slow
+def test_box_closed_form_config1():
+    c = configs.config1()
+    phi, g = oracle.evaluate(c["verts"], c["tris"], c["sigma"], c["rule"], c["targets"])
+    P, G = box_closed(c["targets"], 0.1)
+    assert np.abs(phi - P).max() < 5e-11
+    assert np.abs(g - G).max() < 1e-9
+
+
+def test_box_closed_form_fine_mesh():
+    v, t = cube_mesh(32)
+    x = box_targets(64, seed=11)
+    phi, g = oracle.evaluate(v, t, [0.1], dunavant6(), x)
+    P, G = box_closed(x, 0.1)
+    assert np.abs(phi - P).max() < 2e-13
+    assert np.abs(g - G).max() < 5e-12
+
+
+def test_box_shifted_and_per_triangle_sigma_equal():
+    v, t = cube_mesh(16)
+    v2 = v * 2.0 - 0.5                       # box [-0.5, 1.5]^3, sigma scaled with it
+    x = box_targets(48, -1.0, 2.0, seed=3)
+    phi, g = oracle.evaluate(v2, t, np.full(len(t), 0.2), dunavant6(), x)
+    P, G = box_closed(x, 0.2, -0.5, 1.5)
+    assert np.abs(phi - P).max() < 5e-11 and np.abs(g - G).max() < 1e-9
+    phi1, g1 = oracle.evaluate(v2, t, [0.2], dunavant6(), x)
+    assert np.array_equal(phi, phi1) and np.array_equal(g, g1)
+
+
+# -------------------------------------------------------------- ball (config 2)
+def test_ball_far_and_near():
+    v, t = icosphere(5)
+    x = shell_targets(400, 0.5, 1.5, seed=2)
+    r = np.linalg.norm(x, axis=1)
+    far = np.abs(r - 1) >= 0.4
+    xs = np.concatenate([x[far][:60], x[~far][:40]])
+    rs = np.linalg.norm(xs, axis=1)
+    phi, g = oracle.evaluate(v, t, [0.05], dunavant6(), xs)
+    P, dP = ball_closed(rs, 0.05)
+    G = dP[:, None] * xs / rs[:, None]
+    assert np.abs(phi[:60] - P[:60]).max() < 1e-13
+    assert np.abs(g[:60] - G[:60]).max() < 1e-12
+    # near the surface the flat polyhedron differs from the ball by O(h^2)
+    assert np.abs(phi[60:] - P[60:]).max() < 5e-3
+
+
+def test_ball_near_error_is_second_order():
+    x = shell_targets(60, 0.9, 1.1, seed=7)
+    rs = np.linalg.norm(x, axis=1)
+    errs = []
+    for lev in (2, 3):
+        v, t = icosphere(lev)
+        phi, _ = oracle.evaluate(v, t, [0.2], dunavant6(), x)
+        errs.append(np.abs(phi - ball_closed(rs, 0.2)[0]).max())
+    assert 3.0 < errs[0] / errs[1] < 5.0
+
+
+# -------------------------------------------------- derivatives and symmetry
+def test_gradient_matches_finite_differences():
+    v, t = star_surface(6, seed=5)
+    sig = 0.5 * triangle_diameters(v, t)
+    rng = np.random.default_rng(1)
+    x = rng.uniform(-1.2, 1.2, size=(6, 3))
+    _, g = oracle.evaluate(v, t, sig, dunavant6(), x)
+    hs = 1e-3
+    fd = np.zeros_like(g)
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = 1
+
+        def D(h):
+            p = oracle.evaluate(v, t, sig, dunavant6(), np.concatenate([x + h * e, x - h * e]))[0]
+            return (p[:6] - p[6:]) / (2 * h)
+        fd[:, i] = (4 * D(hs / 2) - D(hs)) / 3
+    assert np.abs(fd - g).max() < 1e-7 * max(1.0, np.abs(g).max())
+
+
+def test_invariances():
+    v, t = star_surface(5, seed=2)
+    sig = 0.5 * triangle_diameters(v, t)
+    rule = dunavant6()
+    x = box_targets(20, -1.2, 1.2, seed=4)
+    phi, g = oracle.evaluate(v, t, sig, rule, x)
+    # translation
+    s = np.array([0.3, -1.1, 2.0])
+    p2, g2 = oracle.evaluate(v + s, t, sig, rule, x + s)
+    assert np.abs(p2 - phi).max() < 1e-13 and np.abs(g2 - g).max() < 1e-12
+    # rotation
+    Q, _ = np.linalg.qr(np.random.default_rng(0).normal(size=(3, 3)))
+    if np.linalg.det(Q) < 0:
+        Q[:, 0] *= -1
+    p3, g3 = oracle.evaluate(v @ Q.T, t, sig, rule, x @ Q.T)
+    assert np.abs(p3 - phi).max() < 1e-13 and np.abs(g3 - g @ Q.T).max() < 1e-12
+    # scaling geometry and sigma together
+    p4, g4 = oracle.evaluate(v * 3.0, t, sig * 3.0, rule, x * 3.0)
+    assert np.abs(p4 - phi).max() < 1e-13 and np.abs(g4 * 3.0 - g).max() < 1e-12
+    # permutation of the triangles
+    perm = np.random.default_rng(1).permutation(len(t))
+    p5, g5 = oracle.evaluate(v, t[perm], sig[perm], rule, x)
+    assert np.abs(p5 - phi).max() < 1e-14 and np.abs(g5 - g).max() < 1e-13
+    # orientation flip: Phi -> -Phi
+    p6, g6 = oracle.evaluate(v, t[:, ::-1].copy(), sig, rule, x)
+    assert np.abs(p6 + phi).max() < 1e-14 and np.abs(g6 + g).max() < 1e-13
+
+
+def test_additivity_and_batch_offsets():
+    v1, t1 = cube_mesh(4)
+    v2, t2 = icosphere(2)
+    v2 = v2 * 0.5 + 3.0
+    rule = dunavant6()
+    x = box_targets(10, -0.5, 3.5, seed=6)
+    pa, ga = oracle.evaluate(v1, t1, [0.1], rule, x)
+    pb, gb = oracle.evaluate(v2, t2, [0.1], rule, x)
+    V = np.concatenate([v1, v2])
+    T = np.concatenate([t1, t2 + len(v1)])
+    pc, gc = oracle.evaluate(V, T, [0.1], rule, x)
+    assert np.abs(pc - pa - pb).max() < 1e-14 and np.abs(gc - ga - gb).max() < 1e-12
+    # CSR offsets + per-target mesh ids select one mesh per target
+    off = np.array([0, len(t1), len(t1) + len(t2)])
+    xm = np.arange(10, dtype=np.int32) % 2
+    pd, gd = oracle.evaluate(V, T, [0.1], rule, x, tri_offsets=off, x_mesh=xm)
+    want = np.where(xm == 0, pa, pb)
+    assert np.array_equal(pd, want)
+
+
+# ------------------------------------------------------------ Gauss / solid angle
+def test_gauss_law_far_from_surface():
+    # far from a closed surface the kernel is the Laplace double layer, whose
+    # integral is 1 inside and 0 outside; the discrete sum approaches it as the
+    # quadrature resolves the surface
+    inside = np.array([[0.0, 0.0, 0.0], [0.05, -0.02, 0.03]])
+    outside = np.array([[4.0, 0.0, 0.0], [0.0, -5.0, 3.0]])
+    for nu, tol in ((16, 5e-12), (32, 1e-13)):
+        v, t = star_surface(nu, seed=8)
+        sig = 0.5 * triangle_diameters(v, t)
+        pin, _ = oracle.evaluate(v, t, sig, dunavant6(), inside)
+        pout, _ = oracle.evaluate(v, t, sig, dunavant6(), outside)
+        assert np.abs(pin - 1).max() < tol and np.abs(pout).max() < tol
+
+
+def test_single_triangle_far_field_solid_angle():
+    P = np.array([[0.0, 0, 0], [1.0, 0, 0], [0.2, 0.9, 0]])
+    t = np.array([[0, 1, 2]], np.int32)
+    x = np.array([[0.4, 0.3, -20.0], [15.0, 7.0, -9.0], [0.1, 0.2, 25.0]])
+    phi, _ = oracle.evaluate(P, t, [0.01], dunavant6(), x)
+    for k in range(3):
+        R = P - x[k]
+        r = np.linalg.norm(R, axis=1)
+        num = np.dot(R[0], np.cross(R[1], R[2]))
+        den = r.prod() + np.dot(R[0], R[1]) * r[2] + np.dot(R[0], R[2]) * r[1] + np.dot(R[1], R[2]) * r[0]
+        omega = 2 * np.arctan2(num, den)
+        assert abs(phi[k] - omega / (4 * PI)) < 1e-8 * abs(omega / (4 * PI))
+
+
+def test_bruteforce_30_digits():
+    mp.mp.dps = 30
+    P = np.array([[0.0, 0, 0], [1.0, 0.1, 0], [0.3, 0.8, 0.2], [0.5, 0.4, -0.7]])
+    t = np.array([[0, 1, 2], [0, 2, 3], [1, 3, 2]], np.int32)
+    sig = np.array([0.3, 0.15, 0.6])
+    rule = dunavant6()
+    y, a = oracle.nodes(P, t, rule)
+    # targets: generic points, one exactly on a node, one very close to a node
+    x = np.array([[0.4, 0.3, 0.1], [1.5, -0.4, 0.9], y[5], y[17] + 1e-9])
+    phi, g = oracle.evaluate(P, t, sig, rule, x)
+    for i in range(len(x)):
+        S = mp.mpf(0)
+        Gs = [mp.mpf(0)] * 3
+        for k in range(len(y)):
+            s = mp.mpf(sig[k // 12])
+            d = [mp.mpf(x[i, c]) - mp.mpf(y[k, c]) for c in range(3)]
+            rho = mp.sqrt(sum(q * q for q in d))
+            ak = [mp.mpf(a[k, c]) for c in range(3)]
+            ad = sum(ak[c] * d[c] for c in range(3))
+            u = rho / (mp.sqrt(2) * s)
+            if rho == 0:
+                Kv = 2 / (3 * 4 * mp.sqrt(2 * mp.pi ** 3) * s ** 3)
+                Fv = -2 / (5 * 4 * mp.sqrt(2 * mp.pi ** 3) * s ** 5)
+            else:
+                Kv = mp.erf(u) / (4 * mp.pi * rho ** 3) - mp.sqrt(2 / mp.pi) * mp.exp(-u * u) / (4 * mp.pi * s * rho ** 2)
+                Kp = mp.diff(lambda r: mp.erf(r / (mp.sqrt(2) * s)) / (4 * mp.pi * r ** 3)
+                             - mp.sqrt(2 / mp.pi) * mp.exp(-r * r / (2 * s * s)) / (4 * mp.pi * s * r ** 2), rho)
+                Fv = Kp / rho
+            S += -ad * Kv
+            for c in range(3):
+                Gs[c] += -ak[c] * Kv - ad * Fv * d[c]
+        scale = max(1.0, abs(float(S)))
+        assert abs(phi[i] - float(S)) < 1e-14 * scale, i
+        gs = max(1.0, max(abs(float(q)) for q in Gs))
+        for c in range(3):
+            assert abs(g[i, c] - float(Gs[c])) < 1e-13 * gs, (i, c)
+
+
+# --------------------------------------------------------------- pseudonormals
+def test_pseudonormals():
+    v, t = cube_mesh(3)
+    H = oracle.pseudonormals(v, t)
+    corner = np.all((v == 0) | (v == 1), axis=1)
+    exp = np.where(v[corner] > 0.5, 1.0, -1.0) / 3.0      # (n1 + n2 + n3) / 3 at a corner
+    assert np.abs(H[corner] - exp).max() < 1e-15
+    face = (np.sum((v == 0) | (v == 1), axis=1) == 1)
+    n = np.where(v[face] == 1, 1.0, np.where(v[face] == 0, -1.0, 0.0))
+    assert np.abs(H[face] - n).max() < 1e-15
+    v, t = icosphere(4)
+    H = oracle.pseudonormals(v, t)
+    cosang = np.einsum("ij,ij->i", H, v) / np.linalg.norm(H, axis=1)
+    assert cosang.min() > 1 - 1e-4
+
+
+# ---------------------------------------------------------------------- Newton
+def test_newton_flat_face_h_zero():
+    # cube 32x32 per face, sigma = 0.02: chart nodes of triangles whose nodes
+    # are all >= 8.5 sigma from every edge stay on the face (section 2: flat
+    # regions wider than the kernel are preserved on the 1/2 level set)
+    v, t = cube_mesh(32)
+    sigma = 0.02
+    cen = v[t].mean(1)
+    # distance of the centroid to the nearest cube edge within its face
+    inner = np.sort(np.minimum(cen, 1 - cen), axis=1)[:, 1]
+    sel = np.nonzero(inner > 8.5 * sigma + 1.0 / 32)[0][::97][:12]
+    uv = chart_nodes(4)
+    h, x, st, it = oracle.project(v, t, [sigma], dunavant6(), uv, tau=1e-12, sel=sel)
+    assert np.all(st == 0)
+    assert np.abs(h).max() < 1e-12 * sigma * 10
+    phi, _ = oracle.evaluate(v, t, [sigma], dunavant6(), x)
+    assert np.abs(phi - 0.5).max() < 1e-12
+
+
+def test_newton_sphere_level_set_and_status():
+    v, t = icosphere(3)
+    sigma = 0.1
+    uv = chart_nodes(2)
+    sel = np.arange(0, len(t), 97)
+    h, x, st, it = oracle.project(v, t, [sigma], dunavant6(), uv, sel=sel)
+    assert np.all(st == 0) and it.max() <= 8
+    phi, _ = oracle.evaluate(v, t, [sigma], dunavant6(), x)
+    assert np.abs(phi - 0.5).max() < 1e-12
+    # the 1/2 level set of the ball convolution (smoke check, O(h^2) polyhedron gap)
+    from scipy.optimize import brentq
+    rstar = brentq(lambda r: ball_closed(np.array([r]), sigma)[0][0] - 0.5, 0.5, 1.5)
+    assert np.abs(np.linalg.norm(x, axis=1) - rstar).max() < 0.02
+    # forced statuses: one iteration only -> MAXITER
+    _, _, st1, it1 = oracle.project(v, t, [sigma], dunavant6(), uv, sel=sel[:3], max_iter=1)
+    assert np.all(st1 == 1) and np.all(it1 == 1)
+
+
+def test_newton_nobracket_and_degenerate():
+    # tiny cube with sigma much larger than the cube: Phi < 1/2 everywhere
+    v, t = cube_mesh(1)
+    _, _, st, _ = oracle.project(v, t, [5.0], dunavant6(), chart_nodes(1), sel=[0, 5])
+    assert np.all(st == 2)
+    # two coincident triangles of opposite orientation: vertex pseudonormals vanish
+    P = np.array([[0.0, 0, 0], [1.0, 0, 0], [0, 1.0, 0]])
+    t2 = np.array([[0, 1, 2], [0, 2, 1]], np.int32)
+    h, x, st, it = oracle.project(P, t2, [0.1], dunavant6(), chart_nodes(1))
+    assert np.all(st == 3) and np.all(h == 0) and np.all(it == 0)

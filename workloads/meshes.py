@@ -1,0 +1,307 @@
+"""Water-tight, outward-oriented flat skeleton triangulations (section 3: the
+skeleton is a conforming, positively oriented triangle mesh).
+
+All generators return ``(verts, tris)`` with ``verts`` (nv, 3) float64 and
+``tris`` (nt, 3) int32, vertex order counter-clockwise seen from outside.
+"""
+import numpy as np
+
+
+# ----------------------------------------------------------------- cube
+def cube_mesh(n, lo=0.0, hi=1.0):
+    """Surface of the cube [lo, hi]^3, each face an n x n grid of squares,
+    each square cut into two triangles (12 n^2 triangles)."""
+    g = np.linspace(lo, hi, n + 1)
+    keys = {}
+    verts = []
+
+    def vid(p):
+        k = tuple(int(round((c - lo) / (hi - lo) * n)) for c in p)
+        i = keys.get(k)
+        if i is None:
+            i = len(verts)
+            keys[k] = i
+            verts.append(p)
+        return i
+
+    tris = []
+    # each face: fixed axis a at value s, outward normal sign sg, (b, c) in-plane axes
+    for a in range(3):
+        b, c = (a + 1) % 3, (a + 2) % 3
+        for s, sg in ((lo, -1.0), (hi, 1.0)):
+            for i in range(n):
+                for j in range(n):
+                    quad = []
+                    for di, dj in ((0, 0), (1, 0), (1, 1), (0, 1)):
+                        p = [0.0, 0.0, 0.0]
+                        p[a] = s
+                        p[b] = g[i + di]
+                        p[c] = g[j + dj]
+                        quad.append(vid(tuple(p)))
+                    # (b, c, a) is a right-handed frame, so quad order is CCW seen
+                    # from +a; reverse it on the -a face
+                    q0, q1, q2, q3 = quad if sg > 0 else quad[::-1]
+                    tris.append((q0, q1, q2))
+                    tris.append((q0, q2, q3))
+    return np.array(verts, dtype=np.float64), np.array(tris, dtype=np.int32)
+
+
+# ----------------------------------------------------------- icosahedral
+def _icosahedron():
+    t = (1.0 + 5.0 ** 0.5) / 2.0
+    v = np.array([[-1, t, 0], [1, t, 0], [-1, -t, 0], [1, -t, 0],
+                  [0, -1, t], [0, 1, t], [0, -1, -t], [0, 1, -t],
+                  [t, 0, -1], [t, 0, 1], [-t, 0, -1], [-t, 0, 1]], dtype=np.float64)
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    # faces = triples of mutually adjacent vertices (edge length is the minimum distance)
+    d = np.linalg.norm(v[:, None] - v[None], axis=2)
+    e = d.min(where=d > 1e-9, initial=10.0)
+    adj = np.abs(d - e) < 1e-6
+    faces = []
+    for i in range(12):
+        for j in range(i + 1, 12):
+            if not adj[i, j]:
+                continue
+            for k in range(j + 1, 12):
+                if adj[i, k] and adj[j, k]:
+                    f = [i, j, k]
+                    nrm = np.cross(v[j] - v[i], v[k] - v[i])
+                    if np.dot(nrm, v[i] + v[j] + v[k]) < 0:
+                        f = [i, k, j]
+                    faces.append(f)
+    return v, np.array(faces, dtype=np.int64)
+
+
+def geodesic_sphere(nu, project=True):
+    """Class-I geodesic sphere: every icosahedron face cut into nu^2 triangles
+    by a uniform barycentric grid, then (optionally) projected to |x| = 1.
+    20 nu^2 triangles, 10 nu^2 + 2 vertices."""
+    V, F = _icosahedron()
+    edges = {}
+    for f in F:
+        for a, b in ((f[0], f[1]), (f[1], f[2]), (f[2], f[0])):
+            key = (min(a, b), max(a, b))
+            if key not in edges:
+                edges[key] = len(edges)
+    ne = len(edges)
+    n_edge_pts = max(nu - 1, 0)
+    n_int = max((nu - 1) * (nu - 2) // 2, 0)
+    nv = 12 + ne * n_edge_pts + len(F) * n_int
+    verts = np.zeros((nv, 3))
+    verts[:12] = V
+
+    ii, jj = np.meshgrid(np.arange(nu + 1), np.arange(nu + 1), indexing="ij")
+    m = (ii + jj) <= nu
+    ii, jj = ii[m], jj[m]
+    kk = nu - ii - jj
+    lid = -np.ones((nu + 1, nu + 1), dtype=np.int64)
+    tris = []
+    int_base = 12 + ne * n_edge_pts
+    for fi, (A, B, C) in enumerate(F):
+        gid = np.empty(ii.shape, dtype=np.int64)
+        pos = V[A] + np.outer(ii / nu, V[B] - V[A]) + np.outer(jj / nu, V[C] - V[A])
+
+        def edge_ids(p, q, t):
+            # point at fraction t/nu from p towards q on edge (p, q)
+            e = edges[(min(p, q), max(p, q))]
+            tt = np.where(p < q, t, nu - t)
+            return 12 + e * n_edge_pts + (tt - 1)
+
+        corner_a = (ii == 0) & (jj == 0)
+        corner_b = ii == nu
+        corner_c = jj == nu
+        on_ab = (jj == 0) & (ii > 0) & (ii < nu)
+        on_ac = (ii == 0) & (jj > 0) & (jj < nu)
+        on_bc = (kk == 0) & (ii > 0) & (jj > 0)
+        inner = (ii > 0) & (jj > 0) & (kk > 0)
+        gid[corner_a] = A
+        gid[corner_b] = B
+        gid[corner_c] = C
+        gid[on_ab] = edge_ids(A, B, ii[on_ab])
+        gid[on_ac] = edge_ids(A, C, jj[on_ac])
+        gid[on_bc] = edge_ids(B, C, jj[on_bc])
+        n_in = int(inner.sum())
+        gid[inner] = int_base + fi * n_int + np.arange(n_in)
+        verts[gid] = pos
+        lid[ii, jj] = gid
+        # up triangles (i,j),(i+1,j),(i,j+1); down (i+1,j),(i+1,j+1),(i,j+1)
+        ui, uj = np.nonzero(np.add.outer(np.arange(nu + 1), np.arange(nu + 1)) <= nu - 1)
+        up = np.stack([lid[ui, uj], lid[ui + 1, uj], lid[ui, uj + 1]], 1)
+        di, dj = np.nonzero(np.add.outer(np.arange(nu + 1), np.arange(nu + 1)) <= nu - 2)
+        dn = np.stack([lid[di + 1, dj], lid[di + 1, dj + 1], lid[di, dj + 1]], 1)
+        tris.append(up)
+        tris.append(dn)
+    tris = np.concatenate(tris).astype(np.int32)
+    if project:
+        verts /= np.linalg.norm(verts, axis=1, keepdims=True)
+    return verts, tris
+
+
+def icosphere(level):
+    """Icosahedron subdivided ``level`` times (each face into 4^level flat
+    triangles) and projected to the unit sphere: 20 * 4^level triangles."""
+    return geodesic_sphere(2 ** level)
+
+
+# ------------------------------------------------------ spherical harmonics
+def _real_sph_harm_sum(theta, phi, coef, lmax):
+    """sum_{l<=lmax, |m|<=l} coef[l][m] Y_lm(theta, phi), real orthonormal Y_lm.
+    ``coef`` is a dict l -> array of length 2l+1 (m = -l..l)."""
+    ct, st = np.cos(theta), np.sin(theta)
+    out = np.zeros_like(theta)
+    pmm = np.full_like(theta, 0.5 / np.sqrt(np.pi))        # \bar P_0^0
+    for m in range(0, lmax + 1):
+        if m > 0:
+            pmm = -np.sqrt((2.0 * m + 1.0) / (2.0 * m)) * st * pmm
+        cm, sm = (np.cos(m * phi), np.sin(m * phi)) if m > 0 else (None, None)
+        p_lm2, p_lm1 = None, pmm
+        for l in range(m, lmax + 1):
+            if l == m:
+                p = pmm
+            elif l == m + 1:
+                p = np.sqrt(2.0 * m + 3.0) * ct * pmm
+            else:
+                a = np.sqrt((4.0 * l * l - 1.0) / (l * l - m * m))
+                b = np.sqrt(((l - 1.0) ** 2 - m * m) / (4.0 * (l - 1.0) ** 2 - 1.0))
+                p = a * (ct * p_lm1 - b * p_lm2)
+            if l >= 1 and l in coef:
+                c = coef[l]
+                if m == 0:
+                    out += c[l] * p
+                else:
+                    out += np.sqrt(2.0) * p * (c[l + m] * cm + c[l - m] * sm)
+            if l > m:
+                p_lm2, p_lm1 = p_lm1, p
+            else:
+                p_lm1 = p
+    return out
+
+
+def _sph(p):
+    r = np.linalg.norm(p, axis=1)
+    theta = np.arccos(np.clip(p[:, 2] / r, -1.0, 1.0))
+    phi = np.arctan2(p[:, 1], p[:, 0])
+    return theta, phi
+
+
+def _normals(verts, tris):
+    p0, p1, p2 = verts[tris[:, 0]], verts[tris[:, 1]], verts[tris[:, 2]]
+    return np.cross(p1 - p0, p2 - p0)
+
+
+def star_surface(nu, lmax=12, var0=0.1, seed=0, max_tries=50):
+    """Star-shaped genus-0 surface r = 1 + sum_{1<=l<=lmax} a_lm Y_lm on a
+    geodesic sphere of 20 nu^2 triangles, a_lm ~ N(0, var0 / l^2) (variance).
+    Redrawn (same generator stream) until min r >= 0.3 and every triangle
+    normal makes n . r_hat > 0.1 with its centroid direction."""
+    rng = np.random.default_rng(seed)
+    base, tris = geodesic_sphere(nu)
+    theta, phi = _sph(base)
+    for _ in range(max_tries):
+        coef = {l: rng.normal(0.0, np.sqrt(var0) / l, size=2 * l + 1) for l in range(1, lmax + 1)}
+        r = 1.0 + _real_sph_harm_sum(theta, phi, coef, lmax)
+        if r.min() < 0.3:
+            continue
+        v = base * r[:, None]
+        n = _normals(v, tris)
+        c = v[tris].mean(axis=1)
+        cosang = np.einsum("ij,ij->i", n, c) / (np.linalg.norm(n, axis=1) * np.linalg.norm(c, axis=1))
+        if cosang.min() > 0.1:
+            return v, tris
+    raise RuntimeError("star_surface: no admissible draw")
+
+
+def _mobius(p, lam):
+    """Conformal self-map of the unit sphere: stereographic projection from
+    the north pole, scaling by lam in the plane, inverse projection.  Local
+    length scale grows by lam at the south pole and shrinks by 1/lam at the
+    north pole (a lam^2 range), angles are preserved."""
+    x, y, z = p[:, 0], p[:, 1], p[:, 2]
+    den = np.maximum(1.0 - z, 1e-300)
+    wx, wy = lam * x / den, lam * y / den
+    w2 = wx * wx + wy * wy
+    out = np.stack([2 * wx, 2 * wy, w2 - 1.0], 1) / (w2 + 1.0)[:, None]
+    north = z > 1.0 - 1e-15
+    out[north] = (0.0, 0.0, 1.0)
+    return out
+
+
+def bumpy_sphere(nu, grade=10.0, lmax=64, amp=0.05, nbumps=2000, seed=5,
+                 height=(1e-3, 3e-2), width=(2e-3, 0.2), slope=0.3):
+    """Large multiscale star-shaped surface.
+
+    Geodesic sphere (20 nu^2 triangles) graded by the conformal map
+    ``_mobius(., grade)`` (edge length varies by grade^2 over the surface),
+    then displaced radially by r = 1 + sum_{1<=l<=lmax} a_lm Y_lm + bumps with
+    a_lm ~ N(0, (amp / l^2)^2), and ``nbumps`` Gaussian bumps with centres
+    uniform on the sphere, widths log-uniform in ``width`` and heights
+    log-uniform in ``height`` capped at ``slope`` * width (keeps the surface
+    star-shaped and the triangles outward-facing)."""
+    rng = np.random.default_rng(seed)
+    base, tris = geodesic_sphere(nu)
+    base = _mobius(base, grade)
+    theta, phi = _sph(base)
+    coef = {l: rng.normal(0.0, amp / l ** 2, size=2 * l + 1) for l in range(1, lmax + 1)}
+    r = 1.0 + _real_sph_harm_sum(theta, phi, coef, lmax)
+    if nbumps:
+        from scipy.spatial import cKDTree
+        c = rng.normal(size=(nbumps, 3))
+        c /= np.linalg.norm(c, axis=1, keepdims=True)
+        w = np.exp(rng.uniform(np.log(width[0]), np.log(width[1]), nbumps))
+        h = np.exp(rng.uniform(np.log(height[0]), np.log(height[1]), nbumps))
+        h = np.minimum(h, slope * w)
+        sgn = rng.choice([-1.0, 1.0], nbumps)
+        tree = cKDTree(base)
+        for b in range(nbumps):
+            idx = np.asarray(tree.query_ball_point(c[b], 6.0 * w[b]), dtype=np.int64)
+            if idx.size:
+                d2 = np.sum((base[idx] - c[b]) ** 2, axis=1)
+                r[idx] += sgn[b] * h[b] * np.exp(-d2 / (2.0 * w[b] ** 2))
+    return base * r[:, None], tris
+
+
+# ----------------------------------------------------------- utilities
+def refine_1to4(verts, tris):
+    """Split every triangle into four by its edge midpoints (section 4.5)."""
+    nv = len(verts)
+    e = np.concatenate([tris[:, [0, 1]], tris[:, [1, 2]], tris[:, [2, 0]]])
+    key = np.sort(e, axis=1)
+    uk, inv = np.unique(key, axis=0, return_inverse=True)
+    mid = 0.5 * (verts[uk[:, 0]] + verts[uk[:, 1]])
+    nt = len(tris)
+    m01, m12, m20 = (nv + inv[:nt], nv + inv[nt:2 * nt], nv + inv[2 * nt:])
+    a, b, c = tris[:, 0], tris[:, 1], tris[:, 2]
+    new = np.concatenate([np.stack([a, m01, m20], 1), np.stack([m01, b, m12], 1),
+                          np.stack([m20, m12, c], 1), np.stack([m01, m12, m20], 1)])
+    return np.concatenate([verts, mid]), new.astype(np.int32)
+
+
+def mesh_check(verts, tris):
+    """Return (closed, signed_volume): closed is True when every directed edge
+    appears exactly once and its reverse exactly once (water-tight, consistently
+    oriented, manifold)."""
+    e = np.concatenate([tris[:, [0, 1]], tris[:, [1, 2]], tris[:, [2, 0]]]).astype(np.int64)
+    n = int(verts.shape[0])
+    fwd = e[:, 0] * n + e[:, 1]
+    rev = e[:, 1] * n + e[:, 0]
+    u, cnt = np.unique(fwd, return_counts=True)
+    closed = bool(np.all(cnt == 1)) and bool(np.all(np.isin(rev, u)))
+    p0, p1, p2 = verts[tris[:, 0]], verts[tris[:, 1]], verts[tris[:, 2]]
+    vol = float(np.sum(np.einsum("ij,ij->i", p0, np.cross(p1, p2))) / 6.0)
+    return closed, vol
+
+
+def triangle_diameters(verts, tris):
+    """D_j: diameter of the smallest ball enclosing triangle j (section 2, the
+    multiscale mollifier): the longest edge for a right or obtuse triangle,
+    twice the circumradius otherwise."""
+    p0, p1, p2 = verts[tris[:, 0]], verts[tris[:, 1]], verts[tris[:, 2]]
+    a2 = np.sum((p1 - p2) ** 2, 1)
+    b2 = np.sum((p2 - p0) ** 2, 1)
+    c2 = np.sum((p0 - p1) ** 2, 1)
+    l2 = np.stack([a2, b2, c2], 1)
+    lmax2 = l2.max(1)
+    obtuse = 2.0 * lmax2 >= a2 + b2 + c2      # lmax^2 >= sum of the other two
+    area2 = np.linalg.norm(np.cross(p1 - p0, p2 - p0), axis=1)   # 2 * area
+    circ_d = np.sqrt(a2 * b2 * c2) / np.maximum(area2, 1e-300)   # 2R = abc / (2 area)
+    return np.where(obtuse, np.sqrt(lmax2), circ_d)
