@@ -1,0 +1,171 @@
+"""Benchmark: Phi + grad Phi target evaluations per second on one MI355X.
+
+One step = one pass of the hot path over the workload: source preparation
+(quadrature nodes and folded constants from the device-resident mesh and
+sigma; in FMM mode also the octree, expansions and translations) followed by
+Phi / grad Phi at every target, all inputs resident in HBM before the timed
+region.  Both precisions are timed in the same run; ``value`` is the mixed
+path (FP32 pair kernel, FP64 far field / updates) and the FP64 figure is
+reported beside it.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2|c5]
+
+Prints ONE JSON line.  The CPU oracle is timed on a bounded target sample of
+the same workload (rank 0 only) for the ``cpu_baseline`` field.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("Φ+∇Φ target evals/sec, mixed vs FP64 at 1e-6 / 1e-12, 2M-triangle mesh, 1 GPU")
+PEAK = {"f64": 78.6, "f32": 157.3}          # TFLOP/s, MI355X published dense vector peaks
+FLOP_PER_PAIR = 40.0                        # algorithmic FLOPs per (target, node) pair
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name, scale):
+    from workloads import configs
+    if name == "c2":
+        cfg = configs.config2(n_targets=int(1_000_000 * scale))
+        desc = "icosphere level 5 (20480 tri, 245760 Dunavant-6 nodes), sigma 0.05, " \
+               "%d targets r~U[0.5,1.5], direct sum" % len(cfg["targets"])
+        far = 0
+    elif name == "c5":
+        cfg = configs.config5(n_targets=int(50_000_000 * scale))
+        desc = "graded bumpy sphere (%d tri, %d nodes), sigma_j = D_j/2, %d near-surface targets, octree + FMM" % (
+            len(cfg["tris"]), 12 * len(cfg["tris"]), len(cfg["targets"]))
+        far = 1
+    else:
+        raise SystemExit("unknown config " + name)
+    return cfg, desc, far
+
+
+def time_variant(lss, torch, cfg, prec, far, steps, warmup):
+    dev = torch.device("cuda")
+    v = torch.as_tensor(cfg["verts"], device=dev)
+    t = torch.as_tensor(cfg["tris"], device=dev)
+    r = torch.as_tensor(cfg["rule"], device=dev)
+    s = torch.as_tensor(np.asarray(cfg["sigma"], float), device=dev)
+    x = torch.as_tensor(cfg["targets"], device=dev)
+    n = x.shape[0]
+    phi = torch.empty(n, dtype=torch.float64, device=dev)
+    grad = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    c = lss.Context(0)
+    c.set_sources(v, t, r)
+    c.set_sigma(s)
+    c.set_options(precision=prec, far_field=far)
+
+    def step():
+        c.set_sigma(s)            # invalidates the built state: the step rebuilds it
+        c.eval(x, phi=phi, grad=grad)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    kms, launches, pairs = 0.0, 0, 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    # pair-kernel duration from HIP events on the context stream (last step)
+    st = c.stats()
+    kms, launches, pairs = st["pair_kernel_ms"], st["pair_kernel_launches"], st["last_pairs"]
+    # eval-only timing (built state reused)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        c.eval(x, phi=phi, grad=grad)
+    torch.cuda.synchronize()
+    el_eval = time.perf_counter() - t1
+    c.close()
+    return dict(ms_per_step=1e3 * el / steps, value=n * steps / el, eval_only_per_s=n * steps / el_eval,
+                pair_kernel_ms=kms, pair_kernel_launches=launches, pairs_per_step=pairs,
+                pairs_per_s=pairs * steps / el, n_targets=n)
+
+
+def cpu_baseline(cfg, budget_s=15.0):
+    import oracle
+    x = cfg["targets"]
+    rng = np.random.default_rng(1234)
+    nsrc = len(cfg["tris"]) * len(cfg["rule"])
+    m = 64
+    idx = rng.choice(len(x), m, replace=False)
+    t0 = time.perf_counter()
+    oracle.evaluate(cfg["verts"], cfg["tris"], cfg["sigma"], cfg["rule"], x[idx])
+    dt = time.perf_counter() - t0
+    m2 = int(min(len(x), max(m, m * budget_s / max(dt, 1e-3))))
+    idx = rng.choice(len(x), m2, replace=False)
+    t0 = time.perf_counter()
+    oracle.evaluate(cfg["verts"], cfg["tris"], cfg["sigma"], cfg["rule"], x[idx])
+    dt = time.perf_counter() - t0
+    return {"value": m2 / dt, "unit": "target evals/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": "%d of %d targets (seeded), full direct FP64 sum over all %d nodes, %.1f s" % (
+                m2, len(x), nsrc, dt),
+            "pairs_per_s": m2 * nsrc / dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (the path is single-GPU; see DESIGN.md "
+              "for how it would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1909_13356_amd as lss
+    log("bench: building workload", args.config)
+    cfg, desc, far = workload(args.config, args.scale)
+    log("bench: workload ready:", desc)
+    res = {}
+    for prec, name in ((lss.FP64, "f64"), (lss.MIXED, "mixed")):
+        log("bench: timing", name)
+        res[name] = time_variant(lss, torch, cfg, prec, far, args.steps, args.warmup)
+        log("bench:", name, json.dumps(res[name]))
+    mixed, f64 = res["mixed"], res["f64"]
+
+    def roof(r, dt):
+        if r["pair_kernel_launches"] <= 0 or r["pair_kernel_ms"] <= 0:
+            return None
+        per_launch = r["pair_kernel_ms"] / r["pair_kernel_launches"] * 1e-3
+        ach = FLOP_PER_PAIR * r["pairs_per_step"] / r["pair_kernel_launches"] / per_launch / 1e12
+        return {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK[dt], "unit": "TFLOP/s",
+                "frac": round(ach / PEAK[dt], 4), "traffic": None,
+                "kernel": "k_p2p_direct_%s" % ("mixed" if dt == "f32" else "f64"),
+                "kernel_ms": round(per_launch * 1e3, 4)}
+
+    out = {
+        "metric": METRIC, "value": mixed["value"], "unit": "target evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": mixed["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 pair kernel / f64 accumulate+update", "data": "synthetic",
+        "config": {"workload": desc},
+        "roofline": roof(mixed, "f32"),
+        "fp64": {"value": f64["value"], "ms_per_step": f64["ms_per_step"], "roofline": roof(f64, "f64"),
+                 "eval_only_per_s": f64["eval_only_per_s"], "pairs_per_s": f64["pairs_per_s"]},
+        "mixed": {"eval_only_per_s": mixed["eval_only_per_s"], "pairs_per_s": mixed["pairs_per_s"]},
+    }
+    if not args.no_cpu:
+        log("bench: timing the CPU oracle on a sample")
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

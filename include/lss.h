@@ -1,0 +1,207 @@
+/*
+ * lss.h -- C ABI of liblss, the MI355X (gfx950) evaluator of the smoothed
+ * level-set function of a triangulated solid and of its chart projection.
+ *
+ * Method (Vico, Greengard, O'Neil, Rachh, "A fast boundary integral method
+ * for high-order multiscale mesh generation"):
+ *   Phi(x) is the Gaussian-smoothed indicator of the solid bounded by a flat
+ *   skeleton triangulation (section 2, eq. basemodelg).  By the divergence
+ *   theorem (section 4.1, eq. surf / kerpsi) it is a surface integral, and
+ *   after quadrature on every triangle (section 4.3, eq. discrete_int)
+ *
+ *     Phi(x)  = sum_k  -(a_k . d_k) K_k(rho_k),        d_k = x - y_k, rho_k = |d_k|
+ *     grad Phi(x) = sum_k [ -a_k K_k(rho_k) - (a_k . d_k) K_k'(rho_k)/rho_k d_k ]
+ *
+ *   over quadrature nodes y_k = P1 + u_m (P2-P1) + v_m (P3-P1) of triangle j,
+ *   a_k = w_m (P2-P1) x (P3-P1), and
+ *     K(rho) = erf(u)/(4 pi rho^3) - sqrt(2/pi) e^{-u^2}/(4 pi sigma rho^2),
+ *     u = rho/(sqrt 2 sigma), sigma = sigma_j (width of the source triangle).
+ *   Far from the node (rho >= 8 sigma) K is the Laplace dipole factor
+ *   1/(4 pi rho^3) (section 4.4, eq. kerapprox / kerdecomp).
+ *   The gradient is the exact derivative of the discrete sum (the paper's
+ *   printed eq. gradPhi has a sign slip in its second term).
+ *   Chart projection (section 3, eq. h / newton / newtonderiv; section 3.2,
+ *   eq. newtoneq): for chart node (u_i, v_i) on triangle j, find h with
+ *   Phi(T(u_i,v_i) + h H(u_i,v_i)) = 1/2 by Newton's method from h = 0, with
+ *   T the flat triangle (eq. tparam) and H the linear pseudonormal field
+ *   (eq. mkvertexpn, mkpseudovec).
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns LSS_OK (0) or a positive LSS_E* code; the
+ *     message of the last failure on a context is lss_last_error(ctx).
+ *     No C++ exception crosses this boundary.
+ *   - Pointers are host memory unless LSS_PTR_DEVICE is set in `flags`, in
+ *     which case every array argument of that call is HIP device memory of
+ *     the context's device.  With host pointers a call is synchronous: it
+ *     returns when outputs are written.  With device pointers the work is
+ *     queued on the context's stream and the call returns without waiting
+ *     (inputs must stay valid, outputs are defined, once the stream reaches
+ *     that point; lss_synchronize() waits).
+ *   - The caller owns every buffer it passes.  set_* calls copy their inputs
+ *     into context-owned device memory, so caller buffers may be released
+ *     after the call (host) or after the stream passes it (device).  The
+ *     library never hands out memory for the caller to free.
+ *   - A context is used by one host thread at a time.  Different contexts
+ *     may run concurrently on different streams.
+ *   - Row-major layouts: verts (nverts, 3) double; tris (ntris, 3) int32 with
+ *     0-based indices, counter-clockwise seen from outside (outward
+ *     orientation); targets (n, 3) double; grad (n, 3) double.
+ */
+#ifndef LSS_H
+#define LSS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lss_ctx lss_ctx;
+
+/* return codes */
+enum {
+    LSS_OK = 0,
+    LSS_EINVAL = 1,   /* bad argument: null pointer, negative or zero size, index out of range,
+                         sigma <= 0 or not finite, unknown option value */
+    LSS_ENOMEM = 2,   /* device or host allocation failed */
+    LSS_EHIP = 3,     /* HIP runtime error (message names the call) */
+    LSS_ESTATE = 4,   /* called out of order, e.g. lss_eval before lss_set_sources / lss_set_sigma */
+    LSS_EORIENT = 5   /* a mesh has non-positive signed volume (inward or open orientation) */
+};
+
+/* arithmetic of the pair evaluations */
+enum {
+    LSS_FP64 = 0,     /* every pair, sum and update in FP64 (target: 1e-12 relative to the oracle) */
+    LSS_MIXED = 1     /* pair kernel in FP32 with FP32 chunk sums folded by two-sum into
+                         float-float accumulators; positions differenced in FP64 before rounding;
+                         far field expansions, Newton update and bracketing in FP64
+                         (target: 1e-6 relative to the oracle) */
+};
+
+/* far-field treatment */
+enum {
+    LSS_FAR_DIRECT = 0,  /* every (target, node) pair with the full kernel: exact discrete sum */
+    LSS_FAR_FMM = 1      /* octree: pairs in adjacent leaves with the full kernel, the rest by a
+                            Laplace-dipole fast multipole method (section 4.4, eq. kerdecomp) */
+};
+
+/* per chart node status written by lss_project */
+enum {
+    LSS_NODE_CONVERGED = 0,
+    LSS_NODE_MAXITER = 1,     /* not converged after max_iter iterations */
+    LSS_NODE_NOBRACKET = 2,   /* iterates driven past |h| > hmax/2 (hmax = 16 sigma_j/|H|): no root near */
+    LSS_NODE_DEGENERATE_H = 3 /* |H| < 1e-3: no usable pseudonormal direction */
+};
+
+#define LSS_PTR_DEVICE 1u
+
+typedef struct lss_options {
+    int32_t precision;        /* LSS_FP64 (default) or LSS_MIXED */
+    int32_t far_field;        /* LSS_FAR_DIRECT (default) or LSS_FAR_FMM */
+    int32_t fmm_order;        /* multipole order p for LSS_FAR_FMM; 0 = default for the precision */
+    int32_t leaf_capacity;    /* octree: split a box holding more nodes than this; 0 = default */
+    double  cut_factor;       /* near/far cut radius in units of the source sigma; the near list of
+                                 a leaf covers every node within cut_factor * sigma_node;
+                                 0 = default (8 for FP64, sqrt(40) for MIXED) */
+    double  newton_tau;       /* converged when |h_k - h_{k-1}| <= newton_tau * sigma_j;
+                                 0 = default (1e-12 FP64, 1e-6 MIXED) */
+    int32_t newton_max_iter;  /* 0 = default 40 */
+    int32_t tile;             /* targets per workgroup of the pair kernels: 0 (default), 64, 128 or 256 */
+    int32_t reserved[8];      /* must be zero */
+} lss_options;
+
+typedef struct lss_stats {
+    int64_t n_tris;           /* triangles of the current source set */
+    int64_t n_nodes;          /* quadrature nodes (sources) = n_tris * nq */
+    int32_t n_mesh;
+    int32_t fmm_order;        /* order used by the last build (0 in direct mode) */
+    int64_t n_leaves;         /* octree leaves (0 in direct mode) */
+    int64_t n_boxes;          /* octree boxes */
+    int64_t n_m2l;            /* multipole-to-local translations of the last build */
+    int32_t tree_depth;
+    int32_t newton_iters;     /* iterations run by the last lss_project */
+    int64_t last_targets;     /* targets of the last lss_eval, or target evaluations summed over
+                                 the iterations of the last lss_project */
+    double  last_pairs;       /* pair-kernel evaluations of the last lss_eval / lss_project */
+    int64_t n_degenerate;     /* zero-area triangles in the source set (they contribute nothing) */
+    double  pair_kernel_ms;   /* device time of the pair-kernel launches of the last lss_eval /
+                                 lss_project, from HIP events recorded around them on the
+                                 context stream (waits for those events) */
+    int32_t pair_kernel_launches;  /* number of pair-kernel launches timed in pair_kernel_ms */
+    int32_t pad0;
+} lss_stats;
+
+/* Create a context on HIP device `hip_device`, queuing work on `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream).  *out receives the
+ * context or NULL on failure. */
+int lss_create(lss_ctx **out, int hip_device, void *hip_stream);
+
+/* Release the context and all its device memory (waits for its stream). NULL is a no-op. */
+void lss_destroy(lss_ctx *ctx);
+
+/* Message of the last failed call on ctx ("" if none); valid until the next call on ctx.
+ * With ctx == NULL: the message of the last failed lss_create on the calling thread. */
+const char *lss_last_error(const lss_ctx *ctx);
+
+/* Wait until all work queued on the context's stream has finished. */
+int lss_synchronize(lss_ctx *ctx);
+
+/* Set the skeleton mesh (section 3: water-tight, positively oriented flat
+ * triangles) and the quadrature rule on T0 (section 4.3).
+ *   verts (nverts,3), tris (ntris,3): see conventions; nverts, ntris >= 1.
+ *   mesh_tri_offsets: CSR of length nmesh+1 splitting the triangles into
+ *     independent meshes (a ragged batch); offsets[0] = 0, non-decreasing,
+ *     offsets[nmesh] = ntris.  NULL (with nmesh 0 or 1) = one mesh.
+ *   rule_uvw (nq,3): nodes (u_m, v_m) on T0 and weights w_m (sum 1/2), nq >= 1.
+ * Indices outside [0, nverts) give LSS_EINVAL.  A mesh with signed volume
+ * <= 0 gives LSS_EORIENT.  Invalidates sigma-dependent state: lss_set_sigma
+ * must follow before lss_build / lss_eval / lss_project. */
+int lss_set_sources(lss_ctx *ctx,
+                    const double *verts, int64_t nverts,
+                    const int32_t *tris, int64_t ntris,
+                    const int64_t *mesh_tri_offsets, int32_t nmesh,
+                    const double *rule_uvw, int32_t nq,
+                    unsigned flags);
+
+/* Set the smoothing width (section 2: sigma_j attached to triangle j).
+ *   n == 1: one constant sigma; n == ntris: one sigma per triangle.
+ * Any sigma <= 0 or not finite gives LSS_EINVAL. */
+int lss_set_sigma(lss_ctx *ctx, const double *sigma, int64_t n, unsigned flags);
+
+/* Set options (NULL = all defaults).  Unknown values give LSS_EINVAL. */
+int lss_set_options(lss_ctx *ctx, const lss_options *opt);
+int lss_get_options(const lss_ctx *ctx, lss_options *out);
+
+/* Prepare everything that depends only on sources, sigma and options:
+ * quadrature nodes and folded constants, vertex pseudonormals, and for
+ * LSS_FAR_FMM the octree, interaction lists, multipole and local expansions.
+ * Idempotent; eval / project call it implicitly when state is stale. */
+int lss_build(lss_ctx *ctx);
+
+/* Phi and grad Phi at n targets x (n,3).  x_mesh (n) gives, for a batch
+ * with nmesh > 1, the mesh whose nodes are summed for each target (NULL is
+ * allowed only for nmesh == 1); values outside [0, nmesh) give LSS_EINVAL
+ * (checked only for host pointers; device-side out-of-range ids are clamped).
+ * phi (n), grad (n,3) receive the results; grad may be NULL.  n == 0 is a
+ * no-op.  Non-finite targets give NaN outputs. */
+int lss_eval(lss_ctx *ctx, const double *x, const int32_t *x_mesh, int64_t n,
+             double *phi, double *grad, unsigned flags);
+
+/* Chart projection onto Phi = 1/2 for np chart nodes (u_i, v_i) on T0,
+ * chart_uv (np,2), on every triangle.  Output index j*np + i (triangle
+ * major): h (ntris*np) pseudonormal distance, xout (ntris*np, 3) projected
+ * point T + h H, status (ntris*np) LSS_NODE_*, iters (ntris*np) Newton
+ * iterations used.  xout, status and iters may be NULL.  Each iteration
+ * evaluates Phi and grad Phi only at nodes that have not converged. */
+int lss_project(lss_ctx *ctx, const double *chart_uv, int32_t np,
+                double *h, double *xout, int8_t *status, int8_t *iters,
+                unsigned flags);
+
+/* Counters of the context.  Waits for the events and counters of the last
+ * lss_eval / lss_project (so it synchronises with those calls). */
+int lss_get_stats(const lss_ctx *ctx, lss_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSS_H */

@@ -1,0 +1,257 @@
+"""ctypes binding of liblss.so with the names of include/lss.h.
+
+Arrays may be numpy arrays (host memory: synchronous calls) or torch tensors
+on the HIP device (device memory: the call is queued on the context stream,
+which is torch's current stream when the context was created).  No arithmetic
+of the method happens here; a missing library raises instead of falling back.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "liblss.so")
+
+FP64, MIXED = 0, 1
+FAR_DIRECT, FAR_FMM = 0, 1
+NODE_CONVERGED, NODE_MAXITER, NODE_NOBRACKET, NODE_DEGENERATE_H = 0, 1, 2, 3
+PTR_DEVICE = 1
+
+# every entry point declared in include/lss.h
+EXPORTED_SYMBOLS = ["lss_create", "lss_destroy", "lss_last_error", "lss_synchronize",
+                    "lss_set_sources", "lss_set_sigma", "lss_set_options", "lss_get_options",
+                    "lss_build", "lss_eval", "lss_project", "lss_get_stats"]
+
+_CODES = {1: "LSS_EINVAL", 2: "LSS_ENOMEM", 3: "LSS_EHIP", 4: "LSS_ESTATE", 5: "LSS_EORIENT"}
+
+
+class LssError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (_CODES.get(code, str(code)), msg))
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("far_field", ctypes.c_int32),
+                ("fmm_order", ctypes.c_int32), ("leaf_capacity", ctypes.c_int32),
+                ("cut_factor", ctypes.c_double), ("newton_tau", ctypes.c_double),
+                ("newton_max_iter", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 8)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_tris", ctypes.c_int64), ("n_nodes", ctypes.c_int64), ("n_mesh", ctypes.c_int32),
+                ("fmm_order", ctypes.c_int32), ("n_leaves", ctypes.c_int64), ("n_boxes", ctypes.c_int64),
+                ("n_m2l", ctypes.c_int64), ("tree_depth", ctypes.c_int32), ("newton_iters", ctypes.c_int32),
+                ("last_targets", ctypes.c_int64), ("last_pairs", ctypes.c_double),
+                ("n_degenerate", ctypes.c_int64), ("pair_kernel_ms", ctypes.c_double),
+                ("pair_kernel_launches", ctypes.c_int32), ("pad0", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def library_path():
+    return _LIBPATH
+
+
+def load_library():
+    """Load liblss.so; raises if it has not been built (no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIBPATH):
+        raise ImportError("liblss.so not built: run paper_1909_13356_amd/build.py "
+                          "(or __graft_entry__.build())")
+    # One HIP runtime per process: when PyTorch is present its bundled
+    # libamdhip64 (soname libamdhip64.so.7) must be loaded first so that the
+    # library binds to that same runtime instead of loading a second one.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = ctypes.CDLL(_LIBPATH)
+    P, i64, i32, u = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint
+    L.lss_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, P]
+    L.lss_destroy.argtypes = [P]
+    L.lss_destroy.restype = None
+    L.lss_last_error.argtypes = [P]
+    L.lss_last_error.restype = ctypes.c_char_p
+    L.lss_synchronize.argtypes = [P]
+    L.lss_set_sources.argtypes = [P, P, i64, P, i64, P, i32, P, i32, u]
+    L.lss_set_sigma.argtypes = [P, P, i64, u]
+    L.lss_set_options.argtypes = [P, ctypes.POINTER(Options)]
+    L.lss_get_options.argtypes = [P, ctypes.POINTER(Options)]
+    L.lss_build.argtypes = [P]
+    L.lss_eval.argtypes = [P, P, P, i64, P, P, u]
+    L.lss_project.argtypes = [P, P, i32, P, P, P, P, u]
+    L.lss_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
+    _lib = L
+    return L
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr(a, dtype, shape_last=None):
+    """(pointer, flags, keepalive) for a numpy array or a device torch tensor."""
+    if a is None:
+        return None, 0, None
+    if _is_torch(a):
+        import torch
+        want = {np.float64: torch.float64, np.int32: torch.int32, np.int64: torch.int64,
+                np.int8: torch.int8}[dtype]
+        if a.dtype != want:
+            raise TypeError("expected %s tensor, got %s" % (want, a.dtype))
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        if a.device.type != "cuda":
+            a = a.numpy()
+        else:
+            return ctypes.c_void_p(a.data_ptr()), PTR_DEVICE, a
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    return arr.ctypes.data_as(ctypes.c_void_p), 0, arr
+
+
+class Context:
+    """One liblss context: a source set, sigma, options and device state."""
+
+    def __init__(self, device=0, stream=None):
+        self._lib = load_library()
+        self._h = ctypes.c_void_p()
+        if stream is None:
+            try:
+                import torch
+                if torch.cuda.is_available():
+                    stream = torch.cuda.current_stream(device).cuda_stream
+            except Exception:
+                stream = None
+        self._check(self._lib.lss_create(ctypes.byref(self._h), int(device), ctypes.c_void_p(stream or 0)),
+                    "lss_create")
+        self.ntris = 0
+
+    def _check(self, rc, where=""):
+        if rc != 0:
+            msg = self._lib.lss_last_error(self._h if self._h else None).decode()
+            raise LssError(rc, msg or where)
+
+    def close(self):
+        if self._h:
+            self._lib.lss_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ------------------------------------------------------------ setters
+    def set_sources(self, verts, tris, rule, tri_offsets=None):
+        pv, fv, kv = _ptr(verts, np.float64)
+        pt, ft, kt = _ptr(tris, np.int32)
+        pr, fr, kr = _ptr(rule, np.float64)
+        po, fo, ko = _ptr(tri_offsets, np.int64)
+        flags = fv | ft | fr | fo
+        if len({f for f in (fv, ft, fr, fo if tri_offsets is not None else fv)}) != 1:
+            raise ValueError("all arrays of one call must live in the same memory (host or device)")
+        nverts, ntris = len(verts), len(tris)
+        nmesh = 0 if tri_offsets is None else len(tri_offsets) - 1
+        self._check(self._lib.lss_set_sources(self._h, pv, nverts, pt, ntris, po, nmesh, pr, len(rule), flags))
+        self.ntris = ntris
+
+    def set_sigma(self, sigma):
+        if np.isscalar(sigma):
+            sigma = np.array([float(sigma)])
+        ps, fs, ks = _ptr(sigma, np.float64)
+        self._check(self._lib.lss_set_sigma(self._h, ps, len(sigma), fs))
+
+    def set_options(self, precision=FP64, far_field=FAR_DIRECT, fmm_order=0, leaf_capacity=0,
+                    cut_factor=0.0, newton_tau=0.0, newton_max_iter=0, tile=0):
+        o = Options(precision, far_field, fmm_order, leaf_capacity, cut_factor, newton_tau,
+                    newton_max_iter, tile)
+        self._check(self._lib.lss_set_options(self._h, ctypes.byref(o)))
+
+    def get_options(self):
+        o = Options()
+        self._check(self._lib.lss_get_options(self._h, ctypes.byref(o)))
+        return {k: getattr(o, k) for k, _ in o._fields_ if k != "reserved"}
+
+    def build(self):
+        self._check(self._lib.lss_build(self._h))
+
+    def synchronize(self):
+        self._check(self._lib.lss_synchronize(self._h))
+
+    def stats(self):
+        s = Stats()
+        self._check(self._lib.lss_get_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    # -------------------------------------------------------------- calls
+    def eval(self, x, x_mesh=None, phi=None, grad=None, want_grad=True):
+        """Phi (n,) and grad Phi (n, 3) at targets x (n, 3).  With torch device
+        tensors the outputs are device tensors (allocated here if not given)
+        and the call is asynchronous on the context stream."""
+        n = len(x)
+        if _is_torch(x) and x.device.type == "cuda":
+            import torch
+            if phi is None:
+                phi = torch.empty(n, dtype=torch.float64, device=x.device)
+            if grad is None and want_grad:
+                grad = torch.empty((n, 3), dtype=torch.float64, device=x.device)
+        else:
+            if phi is None:
+                phi = np.empty(n)
+            if grad is None and want_grad:
+                grad = np.empty((n, 3))
+        px, fx, kx = _ptr(x, np.float64)
+        pm, fm, km = _ptr(x_mesh, np.int32)
+        pp, fp, kp = _ptr(phi, np.float64)
+        pg, fg, kg = _ptr(grad, np.float64)
+        flags = fx
+        for f, a in ((fm, x_mesh), (fp, phi), (fg, grad)):
+            if a is not None and f != flags:
+                raise ValueError("all arrays of one call must live in the same memory (host or device)")
+        self._check(self._lib.lss_eval(self._h, px, pm, n, pp, pg, flags))
+        if not flags and isinstance(phi, np.ndarray) and kp is not phi:
+            phi[...] = kp
+            if grad is not None:
+                grad[...] = kg
+        return phi, grad
+
+    def project(self, chart_uv, device=False):
+        """Newton projection of the chart nodes of every triangle.  Returns
+        h, x, status, iters with index j * np + i."""
+        npn = len(chart_uv)
+        N = self.ntris * npn
+        if device:
+            import torch
+            dev = torch.device("cuda")
+            uv = chart_uv if _is_torch(chart_uv) else torch.as_tensor(np.ascontiguousarray(chart_uv, np.float64), device=dev)
+            h = torch.empty(N, dtype=torch.float64, device=dev)
+            x = torch.empty((N, 3), dtype=torch.float64, device=dev)
+            st = torch.empty(N, dtype=torch.int8, device=dev)
+            it = torch.empty(N, dtype=torch.int8, device=dev)
+        else:
+            uv = np.ascontiguousarray(chart_uv, np.float64)
+            h, x = np.empty(N), np.empty((N, 3))
+            st, it = np.empty(N, np.int8), np.empty(N, np.int8)
+        pu, fu, ku = _ptr(uv, np.float64)
+        ph, fh, kh = _ptr(h, np.float64)
+        px, fx, kx = _ptr(x, np.float64)
+        ps, fs, ks = _ptr(st, np.int8)
+        pi, fi, ki = _ptr(it, np.int8)
+        self._check(self._lib.lss_project(self._h, pu, npn, ph, px, ps, pi, fu))
+        return h, x, st, it

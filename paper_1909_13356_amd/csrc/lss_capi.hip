@@ -1,0 +1,463 @@
+// C ABI of liblss (include/lss.h): argument checking, context state and the
+// orchestration of the kernels on the context's stream.
+#include <cstring>
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <new>
+
+#include "lss_internal.h"
+
+struct lss_ctx {
+    lss::Ctx c;
+};
+
+namespace lss {
+namespace {
+
+__global__ void k_check_tris(int64_t n3, const int32_t *__restrict__ tris, int64_t nverts, unsigned long long *bad) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n3) {
+        int32_t v = tris[i];
+        if (v < 0 || v >= nverts) atomicAdd(bad, 1ull);
+    }
+}
+
+__global__ void k_check_verts(int64_t n3, const double *__restrict__ v, unsigned long long *bad) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n3 && !isfinite(v[i])) atomicAdd(bad, 1ull);
+}
+
+// sigma: broadcast or copy, count invalid, min/max via the order of positive
+// doubles' bit patterns
+__global__ void k_sigma_set(int64_t ntris, const double *__restrict__ in, int64_t nin, double *out,
+                            unsigned long long *stat) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ntris) return;
+    double s = in[nin == 1 ? 0 : j];
+    out[j] = s;
+    if (!(s > 0.0) || !isfinite(s)) {
+        atomicAdd(&stat[0], 1ull);
+        return;
+    }
+    unsigned long long b = (unsigned long long)__double_as_longlong(s);
+    atomicMin(&stat[1], b);
+    atomicMax(&stat[2], b);
+}
+
+__global__ void k_check_mesh_ids(int64_t n, const int32_t *__restrict__ xm, int32_t nmesh, unsigned long long *bad) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && (xm[i] < 0 || xm[i] >= nmesh)) atomicAdd(bad, 1ull);
+}
+
+inline unsigned grid_for(int64_t n, int blk = 256) { return (unsigned)ceil_div(n > 0 ? n : 1, blk); }
+
+void fail(int code, const std::string &m) { throw Error{code, m}; }
+
+// copy n bytes of caller data (host or device) into a context buffer
+void upload(Ctx &c, DBuf &dst, const void *src, size_t nb, unsigned flags) {
+    dst.ensure(nb);
+    LSS_HIP(hipMemcpyAsync(dst.p, src, nb, (flags & LSS_PTR_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                           c.stream));
+}
+
+void validate_options(const lss_options &o) {
+    if (o.precision != LSS_FP64 && o.precision != LSS_MIXED) fail(LSS_EINVAL, "precision must be LSS_FP64 or LSS_MIXED");
+    if (o.far_field != LSS_FAR_DIRECT && o.far_field != LSS_FAR_FMM) fail(LSS_EINVAL, "unknown far_field");
+    if (o.fmm_order < 0 || o.fmm_order > 40) fail(LSS_EINVAL, "fmm_order must be in [0, 40]");
+    if (o.leaf_capacity < 0) fail(LSS_EINVAL, "leaf_capacity < 0");
+    if (!(o.cut_factor >= 0.0) || !std::isfinite(o.cut_factor)) fail(LSS_EINVAL, "cut_factor must be >= 0 and finite");
+    if (o.cut_factor != 0.0 && o.cut_factor < 4.0) fail(LSS_EINVAL, "cut_factor must be 0 (default) or >= 4");
+    if (!(o.newton_tau >= 0.0) || !std::isfinite(o.newton_tau)) fail(LSS_EINVAL, "newton_tau must be >= 0");
+    if (o.newton_max_iter < 0 || o.newton_max_iter > 120) fail(LSS_EINVAL, "newton_max_iter must be in [0, 120]");
+    if (o.tile != 0 && o.tile != 64 && o.tile != 128 && o.tile != 256) fail(LSS_EINVAL, "tile must be 0, 64, 128 or 256");
+    for (int k = 0; k < 8; ++k)
+        if (o.reserved[k] != 0) fail(LSS_EINVAL, "reserved option fields must be zero");
+}
+
+void build(Ctx &c) {
+    if (!c.have_sources) fail(LSS_ESTATE, "lss_build: no sources (call lss_set_sources)");
+    if (!c.have_sigma) fail(LSS_ESTATE, "lss_build: no sigma (call lss_set_sigma after lss_set_sources)");
+    if (c.built) return;
+    c.nnodes = c.ntris * (int64_t)c.nq;
+    c.src.ensure(sizeof(Src) * (size_t)c.nnodes);
+    launch_prep_sources(c);
+    launch_bbox(c);
+    launch_pseudonormals(c);
+    c.pairs.ensure(sizeof(double) * 4);
+    c.built = true;
+    c.stats.n_tris = c.ntris;
+    c.stats.n_nodes = c.nnodes;
+    c.stats.n_mesh = c.nmesh;
+}
+
+void ensure_targets(Ctx &c, int64_t n) {
+    c.tkey.ensure(sizeof(uint64_t) * n);
+    c.tkey2.ensure(sizeof(uint64_t) * n);
+    c.tperm.ensure(sizeof(int32_t) * n);
+    c.tperm2.ensure(sizeof(int32_t) * n);
+    c.tx.ensure(sizeof(double) * n);
+    c.ty.ensure(sizeof(double) * n);
+    c.tz.ensure(sizeof(double) * n);
+    c.tmesh.ensure(sizeof(int32_t) * n);
+}
+
+void eval(Ctx &c, const double *x, const int32_t *xm, int64_t n, double *phi, double *grad, unsigned flags) {
+    if (n < 0) fail(LSS_EINVAL, "lss_eval: n < 0");
+    if (n == 0) return;
+    if (n > (int64_t)INT32_MAX) fail(LSS_EINVAL, "lss_eval: n exceeds 2^31-1");
+    if (!x || !phi) fail(LSS_EINVAL, "lss_eval: x and phi must be non-null");
+    if (c.nmesh > 1 && !xm) fail(LSS_EINVAL, "lss_eval: x_mesh is required for a batch of meshes");
+    build(c);
+    const bool dev = flags & LSS_PTR_DEVICE;
+    DBuf hx, hxm, hphi, hgrad;
+    const double *dx = x;
+    const int32_t *dxm = c.nmesh > 1 ? xm : nullptr;
+    double *dphi = phi, *dgrad = grad;
+    if (!dev) {
+        upload(c, hx, x, sizeof(double) * 3 * n, 0);
+        dx = hx.as<double>();
+        if (dxm) {
+            upload(c, hxm, xm, sizeof(int32_t) * n, 0);
+            dxm = hxm.as<int32_t>();
+        }
+        hphi.ensure(sizeof(double) * n);
+        dphi = hphi.as<double>();
+        if (grad) {
+            hgrad.ensure(sizeof(double) * 3 * n);
+            dgrad = hgrad.as<double>();
+        }
+    }
+    if (dxm && !dev) {
+        DBuf bad;
+        bad.ensure(8);
+        LSS_HIP(hipMemsetAsync(bad.p, 0, 8, c.stream));
+        hipLaunchKernelGGL(k_check_mesh_ids, dim3(grid_for(n)), dim3(256), 0, c.stream, n, dxm, c.nmesh,
+                           bad.as<unsigned long long>());
+        unsigned long long nb = 0;
+        LSS_HIP(hipMemcpyAsync(&nb, bad.p, 8, hipMemcpyDeviceToHost, c.stream));
+        LSS_HIP(hipStreamSynchronize(c.stream));
+        if (nb) fail(LSS_EINVAL, "lss_eval: x_mesh values outside [0, nmesh)");
+    }
+    ensure_targets(c, n);
+    launch_target_keys(c, dx, dxm, n, c.tkey.as<uint64_t>(), c.tperm.as<int32_t>());
+    size_t tb = sort_pairs_u64_tmp_bytes(n);
+    c.sort_tmp.ensure(tb);
+    sort_pairs_u64(c.sort_tmp.p, tb, c.tkey.as<uint64_t>(), c.tkey2.as<uint64_t>(), c.tperm.as<int32_t>(),
+                   c.tperm2.as<int32_t>(), n, 0, 64, c.stream);
+    launch_gather_targets(c, dx, dxm, c.tperm2.as<int32_t>(), n, c.tx.as<double>(), c.ty.as<double>(),
+                          c.tz.as<double>(), c.tmesh.as<int32_t>());
+    LSS_HIP(hipMemsetAsync(c.pairs.p, 0, sizeof(double), c.stream));
+    c.ev_reset();
+    c.ev_begin();
+    launch_p2p_direct(c, n, nullptr, c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(),
+                      c.tmesh.as<int32_t>(), c.tperm2.as<int32_t>(), dphi, dgrad, 3);
+    c.ev_end();
+    if (!dev) {
+        LSS_HIP(hipMemcpyAsync(phi, dphi, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
+        if (grad) LSS_HIP(hipMemcpyAsync(grad, dgrad, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, c.stream));
+        LSS_HIP(hipStreamSynchronize(c.stream));
+        hx.release(); hxm.release(); hphi.release(); hgrad.release();
+    }
+    c.stats.last_targets = n;
+    c.pairs_pending = true;
+}
+
+void project(Ctx &c, const double *uv, int32_t np, double *h, double *xout, int8_t *st, int8_t *it, unsigned flags) {
+    if (np <= 0) fail(LSS_EINVAL, "lss_project: np must be >= 1");
+    if (!uv || !h) fail(LSS_EINVAL, "lss_project: chart_uv and h must be non-null");
+    build(c);
+    const int64_t N = c.ntris * (int64_t)np;
+    if (N > (int64_t)INT32_MAX) fail(LSS_EINVAL, "lss_project: ntris * np exceeds 2^31-1");
+    const bool dev = flags & LSS_PTR_DEVICE;
+    DBuf duv, dh, dx, dst, dit;
+    upload(c, duv, uv, sizeof(double) * 2 * np, flags);
+    const double tau = c.opt.newton_tau > 0 ? c.opt.newton_tau : (c.opt.precision == LSS_MIXED ? 1e-6 : 1e-12);
+    const int maxit = c.opt.newton_max_iter > 0 ? c.opt.newton_max_iter : kMaxIterDefault;
+    launch_chart_init(c, duv.as<double>(), np, N);
+    ensure_targets(c, N);
+    NewtonState &s = c.ns;
+    DBuf phi, grad;
+    phi.ensure(sizeof(double) * N);
+    grad.ensure(sizeof(double) * 3 * N);
+    LSS_HIP(hipMemsetAsync(c.pairs.p, 0, sizeof(double), c.stream));
+    int64_t evals = 0;
+    int iters_run = 0;
+    c.ev_reset();
+    for (int k = 0; k < maxit; ++k) {
+        int32_t nact = 0;
+        LSS_HIP(hipMemcpyAsync(&nact, s.nact.p, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+        LSS_HIP(hipStreamSynchronize(c.stream));
+        if (nact == 0) break;
+        evals += nact;
+        ++iters_run;
+        launch_newton_targets(c, N);
+        c.ev_begin();
+        launch_p2p_direct(c, N, s.nact.as<int32_t>(), c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(),
+                          c.tmesh.as<int32_t>(), nullptr, phi.as<double>(), grad.as<double>(), 3);
+        c.ev_end();
+        launch_newton_update(c, N, tau, phi.as<double>(), grad.as<double>());
+        launch_compact_active(c, N);
+    }
+    double *oh = h, *ox = xout;
+    int8_t *ost = st, *oit = it;
+    if (!dev) {
+        dh.ensure(sizeof(double) * N);
+        oh = dh.as<double>();
+        if (xout) { dx.ensure(sizeof(double) * 3 * N); ox = dx.as<double>(); }
+        if (st) { dst.ensure(N); ost = dst.as<int8_t>(); }
+        if (it) { dit.ensure(N); oit = dit.as<int8_t>(); }
+    }
+    launch_newton_output(c, N, oh, ox, ost, oit);
+    c.pairs_pending = true;
+    if (!dev) {
+        LSS_HIP(hipMemcpyAsync(h, oh, sizeof(double) * N, hipMemcpyDeviceToHost, c.stream));
+        if (xout) LSS_HIP(hipMemcpyAsync(xout, ox, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, c.stream));
+        if (st) LSS_HIP(hipMemcpyAsync(st, ost, N, hipMemcpyDeviceToHost, c.stream));
+        if (it) LSS_HIP(hipMemcpyAsync(it, oit, N, hipMemcpyDeviceToHost, c.stream));
+    }
+    LSS_HIP(hipStreamSynchronize(c.stream));
+    c.stats.last_targets = evals;
+    c.stats.newton_iters = iters_run;
+}
+
+template <class F> int guarded(lss_ctx *ctx, F &&f) {
+    if (!ctx) return LSS_EINVAL;
+    try {
+        LSS_HIP(hipSetDevice(ctx->c.device));
+        f(ctx->c);
+        ctx->c.err.clear();
+        return LSS_OK;
+    } catch (const Error &e) {
+        ctx->c.err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        ctx->c.err = "host allocation failed";
+        return LSS_ENOMEM;
+    } catch (...) {
+        ctx->c.err = "unexpected internal error";
+        return LSS_EHIP;
+    }
+}
+
+}  // namespace
+}  // namespace lss
+
+using lss::Ctx;
+using lss::DBuf;
+using lss::fail;
+using lss::upload;
+
+namespace {
+thread_local std::string g_create_err;   // message of the last failed lss_create on this thread
+}
+
+extern "C" {
+
+int lss_create(lss_ctx **out, int hip_device, void *hip_stream) {
+    g_create_err.clear();
+    if (!out) { g_create_err = "lss_create: out is null"; return LSS_EINVAL; }
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev <= 0) {
+        g_create_err = std::string("lss_create: hipGetDeviceCount: ") + hipGetErrorString(e) +
+                       " (devices: " + std::to_string(ndev) + ")";
+        return LSS_EHIP;
+    }
+    if (hip_device < 0 || hip_device >= ndev) { g_create_err = "lss_create: device index out of range"; return LSS_EINVAL; }
+    lss_ctx *ctx = new (std::nothrow) lss_ctx;
+    if (!ctx) return LSS_ENOMEM;
+    ctx->c.device = hip_device;
+    ctx->c.stream = static_cast<hipStream_t>(hip_stream);
+    *out = ctx;
+    return LSS_OK;
+}
+
+void lss_destroy(lss_ctx *ctx) {
+    if (!ctx) return;
+    Ctx &c = ctx->c;
+    (void)hipSetDevice(c.device);
+    (void)hipStreamSynchronize(c.stream);
+    DBuf *bufs[] = {&c.verts, &c.tris, &c.tri_off, &c.node_off, &c.rule, &c.sigma, &c.src, &c.vH, &c.tkey,
+                    &c.tkey2, &c.tperm, &c.tperm2, &c.tx, &c.ty, &c.tz, &c.tmesh, &c.sort_tmp, &c.pairs,
+                    &c.ns.T, &c.ns.H, &c.ns.h, &c.ns.lo, &c.ns.hi, &c.ns.sig, &c.ns.mesh, &c.ns.orig,
+                    &c.ns.status, &c.ns.iters, &c.ns.active, &c.ns.active2, &c.ns.flag, &c.ns.blocksum,
+                    &c.ns.nact};
+    for (DBuf *b : bufs) b->release();
+    for (hipEvent_t e : c.ev_start) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c.ev_stop) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+const char *lss_last_error(const lss_ctx *ctx) { return ctx ? ctx->c.err.c_str() : g_create_err.c_str(); }
+
+int lss_synchronize(lss_ctx *ctx) {
+    return lss::guarded(ctx, [&](Ctx &c) { LSS_HIP(hipStreamSynchronize(c.stream)); });
+}
+
+int lss_set_sources(lss_ctx *ctx, const double *verts, int64_t nverts, const int32_t *tris, int64_t ntris,
+                    const int64_t *mesh_tri_offsets, int32_t nmesh, const double *rule_uvw, int32_t nq,
+                    unsigned flags) {
+    return lss::guarded(ctx, [&](Ctx &c) {
+        if (!verts || !tris || !rule_uvw) fail(LSS_EINVAL, "lss_set_sources: null pointer");
+        if (nverts < 3 || ntris < 1 || nq < 1) fail(LSS_EINVAL, "lss_set_sources: need nverts >= 3, ntris >= 1, nq >= 1");
+        if (nverts > (int64_t)INT32_MAX || ntris * (int64_t)nq > ((int64_t)1 << 40))
+            fail(LSS_EINVAL, "lss_set_sources: mesh too large");
+        if (mesh_tri_offsets == nullptr && nmesh > 1) fail(LSS_EINVAL, "lss_set_sources: nmesh > 1 needs offsets");
+        if (nmesh < 0) fail(LSS_EINVAL, "lss_set_sources: nmesh < 0");
+        const bool dev = flags & LSS_PTR_DEVICE;
+        c.have_sources = false;
+        c.have_sigma = false;
+        c.built = false;
+        // mesh offsets: validated on the host (copied there if on the device)
+        int32_t nm = (mesh_tri_offsets && nmesh >= 1) ? nmesh : 1;
+        std::vector<int64_t> off(nm + 1);
+        if (mesh_tri_offsets && nmesh >= 1) {
+            LSS_HIP(hipMemcpy(off.data(), mesh_tri_offsets, sizeof(int64_t) * (nm + 1),
+                              dev ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+        } else {
+            off[0] = 0;
+            off[1] = ntris;
+        }
+        if (off[0] != 0 || off[nm] != ntris) fail(LSS_EINVAL, "lss_set_sources: offsets must start at 0 and end at ntris");
+        for (int32_t m = 0; m < nm; ++m)
+            if (off[m + 1] < off[m]) fail(LSS_EINVAL, "lss_set_sources: offsets must be non-decreasing");
+        std::vector<double> hrule(3 * (size_t)nq);
+        LSS_HIP(hipMemcpy(hrule.data(), rule_uvw, sizeof(double) * 3 * nq, dev ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+        for (int m = 0; m < nq; ++m)
+            if (!std::isfinite(hrule[3 * m]) || !std::isfinite(hrule[3 * m + 1]) || !std::isfinite(hrule[3 * m + 2]))
+                fail(LSS_EINVAL, "lss_set_sources: rule entries must be finite");
+        upload(c, c.verts, verts, sizeof(double) * 3 * nverts, flags);
+        upload(c, c.tris, tris, sizeof(int32_t) * 3 * ntris, flags);
+        upload(c, c.rule, hrule.data(), sizeof(double) * 3 * nq, 0);
+        c.tri_off.ensure(sizeof(int64_t) * (nm + 1));
+        LSS_HIP(hipMemcpyAsync(c.tri_off.p, off.data(), sizeof(int64_t) * (nm + 1), hipMemcpyHostToDevice, c.stream));
+        std::vector<int64_t> noff(nm + 1);
+        for (int32_t m = 0; m <= nm; ++m) noff[m] = off[m] * nq;
+        c.node_off.ensure(sizeof(int64_t) * (nm + 1));
+        LSS_HIP(hipMemcpyAsync(c.node_off.p, noff.data(), sizeof(int64_t) * (nm + 1), hipMemcpyHostToDevice, c.stream));
+        // index and coordinate checks on the device
+        DBuf bad;
+        bad.ensure(16);
+        LSS_HIP(hipMemsetAsync(bad.p, 0, 16, c.stream));
+        hipLaunchKernelGGL(lss::k_check_tris, dim3(lss::grid_for(3 * ntris)), dim3(256), 0, c.stream, 3 * ntris,
+                           c.tris.as<int32_t>(), nverts, bad.as<unsigned long long>());
+        hipLaunchKernelGGL(lss::k_check_verts, dim3(lss::grid_for(3 * nverts)), dim3(256), 0, c.stream, 3 * nverts,
+                           c.verts.as<double>(), bad.as<unsigned long long>() + 1);
+        unsigned long long nb[2] = {0, 0};
+        LSS_HIP(hipMemcpyAsync(nb, bad.p, 16, hipMemcpyDeviceToHost, c.stream));
+        LSS_HIP(hipStreamSynchronize(c.stream));
+        if (nb[0]) fail(LSS_EINVAL, "lss_set_sources: triangle vertex index outside [0, nverts)");
+        if (nb[1]) fail(LSS_EINVAL, "lss_set_sources: non-finite vertex coordinate");
+        c.nverts = nverts;
+        c.ntris = ntris;
+        c.nmesh = nm;
+        c.nq = nq;
+        c.h_tri_off = off;
+        std::vector<double> vol;
+        int64_t ndeg = 0;
+        double vmin = lss::launch_check_orientation(c, vol, ndeg);
+        c.stats = lss_stats{};
+        c.stats.n_degenerate = ndeg;
+        if (!(vmin > 0.0)) fail(LSS_EORIENT, "lss_set_sources: a mesh has non-positive signed volume (inward orientation?)");
+        c.have_sources = true;
+    });
+}
+
+int lss_set_sigma(lss_ctx *ctx, const double *sigma, int64_t n, unsigned flags) {
+    return lss::guarded(ctx, [&](Ctx &c) {
+        if (!c.have_sources) fail(LSS_ESTATE, "lss_set_sigma: call lss_set_sources first");
+        if (!sigma) fail(LSS_EINVAL, "lss_set_sigma: null pointer");
+        if (n != 1 && n != c.ntris) fail(LSS_EINVAL, "lss_set_sigma: n must be 1 or ntris");
+        c.have_sigma = false;
+        c.built = false;
+        DBuf in, stat;
+        upload(c, in, sigma, sizeof(double) * n, flags);
+        c.sigma.ensure(sizeof(double) * c.ntris);
+        stat.ensure(24);
+        unsigned long long init[3] = {0ull, ~0ull, 0ull};
+        LSS_HIP(hipMemcpyAsync(stat.p, init, 24, hipMemcpyHostToDevice, c.stream));
+        hipLaunchKernelGGL(lss::k_sigma_set, dim3(lss::grid_for(c.ntris)), dim3(256), 0, c.stream, c.ntris,
+                           in.as<double>(), n, c.sigma.as<double>(), stat.as<unsigned long long>());
+        LSS_CHECK_LAUNCH("k_sigma_set");
+        unsigned long long h[3];
+        LSS_HIP(hipMemcpyAsync(h, stat.p, 24, hipMemcpyDeviceToHost, c.stream));
+        LSS_HIP(hipStreamSynchronize(c.stream));
+        if (h[0]) fail(LSS_EINVAL, "lss_set_sigma: sigma must be positive and finite");
+        double mn, mx;
+        std::memcpy(&mn, &h[1], 8);
+        std::memcpy(&mx, &h[2], 8);
+        c.sigma_min = mn;
+        c.sigma_max = mx;
+        c.have_sigma = true;
+    });
+}
+
+int lss_set_options(lss_ctx *ctx, const lss_options *opt) {
+    return lss::guarded(ctx, [&](Ctx &c) {
+        lss_options o{};
+        if (opt) o = *opt;
+        lss::validate_options(o);
+        if (o.precision != c.opt.precision || o.far_field != c.opt.far_field || o.fmm_order != c.opt.fmm_order ||
+            o.leaf_capacity != c.opt.leaf_capacity || o.cut_factor != c.opt.cut_factor)
+            c.built = false;
+        c.opt = o;
+    });
+}
+
+int lss_get_options(const lss_ctx *ctx, lss_options *out) {
+    if (!ctx || !out) return LSS_EINVAL;
+    *out = ctx->c.opt;
+    return LSS_OK;
+}
+
+int lss_build(lss_ctx *ctx) {
+    return lss::guarded(ctx, [&](Ctx &c) { lss::build(c); });
+}
+
+int lss_eval(lss_ctx *ctx, const double *x, const int32_t *x_mesh, int64_t n, double *phi, double *grad,
+             unsigned flags) {
+    return lss::guarded(ctx, [&](Ctx &c) { lss::eval(c, x, x_mesh, n, phi, grad, flags); });
+}
+
+int lss_project(lss_ctx *ctx, const double *chart_uv, int32_t np, double *h, double *xout, int8_t *status,
+                int8_t *iters, unsigned flags) {
+    return lss::guarded(ctx, [&](Ctx &c) { lss::project(c, chart_uv, np, h, xout, status, iters, flags); });
+}
+
+int lss_get_stats(const lss_ctx *ctx, lss_stats *out) {
+    if (!ctx || !out) return LSS_EINVAL;
+    Ctx &c = const_cast<lss_ctx *>(ctx)->c;
+    if (c.ev_pending) {
+        (void)hipSetDevice(c.device);
+        double ms = 0.0;
+        for (int k = 0; k < c.ev_used; ++k) {
+            float t = 0.0f;
+            if (hipEventSynchronize(c.ev_stop[k]) != hipSuccess ||
+                hipEventElapsedTime(&t, c.ev_start[k], c.ev_stop[k]) != hipSuccess) {
+                c.err = "lss_get_stats: event timing failed";
+                return LSS_EHIP;
+            }
+            ms += t;
+        }
+        c.stats.pair_kernel_ms = ms;
+        c.stats.pair_kernel_launches = c.ev_used;
+        c.ev_pending = false;
+    }
+    if (c.pairs_pending) {
+        double pr = 0.0;
+        (void)hipSetDevice(c.device);
+        if (hipMemcpyAsync(&pr, c.pairs.p, sizeof(double), hipMemcpyDeviceToHost, c.stream) != hipSuccess ||
+            hipStreamSynchronize(c.stream) != hipSuccess) {
+            c.err = "lss_get_stats: reading the pair counter failed";
+            return LSS_EHIP;
+        }
+        c.stats.last_pairs = pr;
+        c.pairs_pending = false;
+    }
+    *out = c.stats;
+    return LSS_OK;
+}
+
+}  // extern "C"

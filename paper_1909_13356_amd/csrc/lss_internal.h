@@ -1,0 +1,183 @@
+// Internal declarations of liblss: the context, device buffers and the
+// host-side launch wrappers of the kernels.  Everything here is C++ behind
+// the C ABI of include/lss.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "lss.h"
+
+namespace lss {
+
+// ---------------------------------------------------------------- errors
+struct Error {
+    int code;
+    std::string msg;
+};
+
+#define LSS_HIP(call)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess)                                                      \
+            throw ::lss::Error{e_ == hipErrorOutOfMemory ? LSS_ENOMEM : LSS_EHIP,  \
+                               std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define LSS_CHECK_LAUNCH(name)                                                      \
+    do {                                                                            \
+        hipError_t e_ = hipGetLastError();                                          \
+        if (e_ != hipSuccess)                                                       \
+            throw ::lss::Error{LSS_EHIP, std::string("launch ") + (name) + ": " +   \
+                                             hipGetErrorString(e_)};                \
+    } while (0)
+
+// ------------------------------------------------------------ device buffer
+// Grow-only device allocation owned by the context.
+struct DBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    ~DBuf() { release(); }
+    void ensure(size_t nb) {
+        if (nb <= bytes) return;
+        release();
+        size_t want = nb < 256 ? 256 : nb;
+        LSS_HIP(hipMalloc(&p, want));
+        bytes = want;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// Packed quadrature-node record (one 64-byte line per node): position, the
+// folded dipole vector a' = c(sigma) w J, s2 = 1/(2 sigma^2) and 2 s2.
+struct alignas(64) Src {
+    double yx, yy, yz, s2;
+    double ax, ay, az, s2x2;
+};
+
+// FP32 staging record of the mixed path: position relative to a tile origin
+// as an unevaluated float-float sum hi + lo (lo = the FP64 remainder).
+struct alignas(16) SrcF {
+    float yx, yy, yz, s2;
+    float ax, ay, az, s2x2;
+    float lx, ly, lz, pad;
+};
+
+// Per-chart-node Newton state, structure of arrays in sorted order.
+struct NewtonState {
+    DBuf T, H;           // 3 doubles each, AoS
+    DBuf h, lo, hi;      // doubles
+    DBuf sig;            // sigma_j (double)
+    DBuf mesh;           // int32
+    DBuf orig;           // int32 original output index
+    DBuf status, iters;  // int8
+    DBuf active, active2, flag;   // int32 lists / flags
+    DBuf blocksum;       // int32 per block counts
+    DBuf nact;           // int32[2] active count (device)
+};
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    lss_options opt{};
+    lss_stats stats{};
+
+    // --- source set
+    int64_t nverts = 0, ntris = 0;
+    int32_t nmesh = 0, nq = 0;
+    std::vector<int64_t> h_tri_off;   // nmesh + 1
+    DBuf verts, tris, tri_off, node_off, rule;
+    bool have_sources = false;
+
+    // --- sigma
+    bool have_sigma = false;
+    DBuf sigma;               // ntris doubles (constant sigma broadcast)
+    double sigma_max = 0.0, sigma_min = 0.0;
+
+    // --- built state
+    bool built = false;
+    int64_t nnodes = 0;
+    DBuf src;                 // nnodes Src records
+    DBuf vH;                  // vertex pseudonormals (nverts * 3)
+    double bbox_lo[3] = {0, 0, 0}, bbox_hi[3] = {0, 0, 0};
+
+    // --- per-eval scratch
+    DBuf tkey, tkey2, tperm, tperm2, tx, ty, tz, tmesh, sort_tmp;
+    DBuf pairs;               // double accumulator of executed pairs (stats)
+    bool pairs_pending = false;   // counter not yet read back into stats.last_pairs
+    NewtonState ns;
+
+    // --- HIP events around the pair-kernel launches (stats.pair_kernel_ms)
+    std::vector<hipEvent_t> ev_start, ev_stop;
+    int ev_used = 0;
+    bool ev_pending = false;
+    void ev_reset() { ev_used = 0; ev_pending = false; }
+    void ev_begin() {
+        if (ev_used == (int)ev_start.size()) {
+            hipEvent_t a, b;
+            LSS_HIP(hipEventCreate(&a));
+            LSS_HIP(hipEventCreate(&b));
+            ev_start.push_back(a);
+            ev_stop.push_back(b);
+        }
+        LSS_HIP(hipEventRecord(ev_start[ev_used], stream));
+    }
+    void ev_end() {
+        LSS_HIP(hipEventRecord(ev_stop[ev_used], stream));
+        ++ev_used;
+        ev_pending = true;
+    }
+};
+
+// ------------------------------------------------------- launch wrappers
+// prep (lss_kernels.hip)
+void launch_prep_sources(Ctx &c);
+void launch_pseudonormals(Ctx &c);
+void launch_bbox(Ctx &c);
+double launch_check_orientation(Ctx &c, std::vector<double> &vol_per_mesh, int64_t &ndegenerate);
+
+// targets: Morton keys, sort, gather into SoA (lss_kernels.hip)
+void launch_target_keys(Ctx &c, const double *x, const int32_t *x_mesh, int64_t n,
+                        uint64_t *keys, int32_t *idx);
+void launch_gather_targets(Ctx &c, const double *x, const int32_t *x_mesh, const int32_t *perm,
+                           int64_t n, double *tx, double *ty, double *tz, int32_t *tmesh);
+
+// pair kernels (lss_p2p.hip)
+void launch_p2p_direct(Ctx &c, int64_t n, const int32_t *n_dev, const double *tx, const double *ty,
+                       const double *tz, const int32_t *tmesh, const int32_t *out_idx,
+                       double *phi, double *grad, int grad_stride);
+
+// Newton (lss_kernels.hip)
+void launch_chart_init(Ctx &c, const double *chart_uv, int32_t np, int64_t N);
+void launch_newton_targets(Ctx &c, int64_t N);
+void launch_newton_update(Ctx &c, int64_t N, double tau, const double *phi, const double *grad);
+void launch_compact_active(Ctx &c, int64_t N);
+void launch_newton_output(Ctx &c, int64_t N, double *h, double *xout, int8_t *status, int8_t *iters);
+
+// sorting and scans (lss_sort.hip)
+size_t sort_pairs_u64_tmp_bytes(int64_t n);
+void sort_pairs_u64(void *tmp, size_t tmp_bytes, const uint64_t *kin, uint64_t *kout,
+                    const int32_t *vin, int32_t *vout, int64_t n, int begin_bit, int end_bit,
+                    hipStream_t s);
+
+// ------------------------------------------------------------ constants
+constexpr int kMaxIterDefault = 40;
+constexpr double kCutFP64 = 8.0;                 // x = u^2 = 32 at the cut
+constexpr double kCutMixed = 6.324555320336759;  // sqrt(40): x = 20 at the cut
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace lss

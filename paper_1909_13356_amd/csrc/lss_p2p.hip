@@ -1,0 +1,303 @@
+// Pair kernels of liblss (gfx950): the direct sum of the smoothed-indicator
+// kernel over quadrature nodes (section 4.3, eq. discrete_int; kernel
+// section 4.1, eq. kerpsi; exact gradient of the discrete sum).
+//
+// Per pair, with d = x - y, x = |d|^2 s2 (s2 = 1/(2 sigma^2)) and the folded
+// dipole vector a' = c(sigma) w J:
+//     Phi      -= (a'.d) S(x)
+//     grad Phi += 2 s2 (a'.d) T(x) d - a' S(x)
+// S(x) = gamma(3/2,x)/x^1.5, T(x) = gamma(5/2,x)/x^2.5 come from the rational
+// fits of kfit_tables.h below the cut x = X (8 sigma in FP64, 6.32 sigma in
+// FP32) and from the Laplace dipole S = (sqrt(pi)/2) x^-1.5, T = 1.5 S/x
+// beyond it (section 4.4: the kernel equals the double-layer kernel there to
+// the tail bound of the cut).
+//
+// Mixed path: the FP64 differences to a tile origin are carried as float-float
+// (hi + lo) so that d keeps FP32 relative accuracy at any distance from it.
+//
+// Layout: one target per lane, TILE targets per workgroup (targets sorted by
+// mesh, then Morton order); quadrature nodes are streamed through LDS in
+// chunks of TILE packed records; each lane sums the nodes of its own mesh
+// (per-lane node range, so a tile may straddle meshes of a ragged batch).
+// Chunk partial sums are folded into compensated totals (two-sum).
+#include <cstring>
+#include <hip/hip_runtime.h>
+
+#include "kfit_tables.h"
+#include "lss_internal.h"
+
+namespace lss {
+
+namespace {
+
+constexpr double kSqrtPiHalf = 0.88622692545275801365;
+constexpr float kSqrtPiHalfF = 0.88622692545275801365f;
+
+__device__ __forceinline__ void two_sum(double &s, double &e, double v) {
+    double t = s + v;
+    double bp = t - s;
+    e += (s - (t - bp)) + (v - bp);
+    s = t;
+}
+
+__device__ __forceinline__ void two_sum_f(float &s, float &e, float v) {
+    float t = s + v;
+    float bp = t - s;
+    e += (s - (t - bp)) + (v - bp);
+    s = t;
+}
+
+// S, T in FP64
+__device__ __forceinline__ void kfun64(double x, double &S, double &T) {
+    if (x < KF64_X) {
+        const double t = x * KF64_INV_X;
+        double ps = kf64_ps[KF64_PS_DEG], pt = kf64_pt[KF64_PT_DEG], q = kf64_q[KF64_Q_DEG];
+#pragma unroll
+        for (int k = KF64_Q_DEG - 1; k >= 0; --k) {
+            ps = fma(ps, t, kf64_ps[k]);
+            pt = fma(pt, t, kf64_pt[k]);
+            q = fma(q, t, kf64_q[k]);
+        }
+        double r = __builtin_amdgcn_rcp(q);
+        r = fma(r, fma(-q, r, 1.0), r);
+        r = fma(r, fma(-q, r, 1.0), r);
+        S = ps * r;
+        T = pt * r;
+    } else {
+        double r = __builtin_amdgcn_rsq(x);
+        const double hx = 0.5 * x;
+        r = r * fma(-hx * r, r, 1.5);
+        r = r * fma(-hx * r, r, 1.5);
+        const double r2 = r * r;
+        S = kSqrtPiHalf * r2 * r;
+        T = 1.5 * S * r2;
+    }
+}
+
+// S, T in FP32
+__device__ __forceinline__ void kfun32(float x, float &S, float &T) {
+    if (x < (float)KF32_X) {
+        const float t = x * (float)KF32_INV_X;
+        float ps = kf32_ps[KF32_PS_DEG], pt = kf32_pt[KF32_PT_DEG], q = kf32_q[KF32_Q_DEG];
+#pragma unroll
+        for (int k = KF32_Q_DEG - 1; k >= 0; --k) {
+            ps = fmaf(ps, t, kf32_ps[k]);
+            pt = fmaf(pt, t, kf32_pt[k]);
+            q = fmaf(q, t, kf32_q[k]);
+        }
+        const float r = __builtin_amdgcn_rcpf(q);
+        S = ps * r;
+        T = pt * r;
+    } else {
+        const float r = __builtin_amdgcn_rsqf(x);
+        const float r2 = r * r;
+        S = kSqrtPiHalfF * r2 * r;
+        T = 1.5f * S * r2;
+    }
+}
+
+__device__ __forceinline__ void pair64(const Src &s, double x, double y, double z, double &p, double &gx,
+                                       double &gy, double &gz) {
+    const double dx = x - s.yx, dy = y - s.yy, dz = z - s.yz;
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    const double ad = fma(s.ax, dx, fma(s.ay, dy, s.az * dz));
+    double S, T;
+    kfun64(r2 * s.s2, S, T);
+    p = fma(-ad, S, p);
+    const double g = ad * T * s.s2x2;
+    gx = fma(g, dx, fma(-s.ax, S, gx));
+    gy = fma(g, dy, fma(-s.ay, S, gy));
+    gz = fma(g, dz, fma(-s.az, S, gz));
+}
+
+__device__ __forceinline__ void pair32(const SrcF &s, float x, float y, float z, float xl, float yl, float zl,
+                                       float &p, float &gx, float &gy, float &gz) {
+    // d = (x_hi - y_hi) + (x_lo - y_lo): positions carried as float-float
+    const float dx = (x - s.yx) + (xl - s.lx), dy = (y - s.yy) + (yl - s.ly), dz = (z - s.yz) + (zl - s.lz);
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const float ad = fmaf(s.ax, dx, fmaf(s.ay, dy, s.az * dz));
+    float S, T;
+    kfun32(r2 * s.s2, S, T);
+    p = fmaf(-ad, S, p);
+    const float g = ad * T * s.s2x2;
+    gx = fmaf(g, dx, fmaf(-s.ax, S, gx));
+    gy = fmaf(g, dy, fmaf(-s.ay, S, gy));
+    gz = fmaf(g, dz, fmaf(-s.az, S, gz));
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// ---------------------------------------------------------------- FP64
+template <int TILE>
+__global__ __launch_bounds__(TILE) void k_p2p_direct_f64(
+    int64_t nmax, const int32_t *__restrict__ n_dev, const double *__restrict__ tx,
+    const double *__restrict__ ty, const double *__restrict__ tz, const int32_t *__restrict__ tmesh,
+    const int64_t *__restrict__ node_off, const Src *__restrict__ src, const int32_t *__restrict__ out_idx,
+    double *__restrict__ phi, double *__restrict__ grad, double *__restrict__ pairs) {
+    __shared__ Src sh[TILE];
+    const int64_t n = n_dev ? (int64_t)*n_dev : nmax;
+    const int64_t t0 = (int64_t)blockIdx.x * TILE;
+    if (t0 >= n) return;
+    const int lane = threadIdx.x;
+    const int64_t i = t0 + lane;
+    const bool valid = i < n;
+    const int64_t ii = valid ? i : n - 1;
+    const double x = tx[ii], y = ty[ii], z = tz[ii];
+    const int32_t m = tmesh[ii];
+    const int64_t b = node_off[m], e = node_off[m + 1];
+    // targets are sorted by mesh: the tile's node range runs from the first
+    // target's mesh to the last target's mesh
+    const int64_t tl = (t0 + TILE < n ? t0 + TILE : n) - 1;
+    const int64_t lo = node_off[tmesh[t0]], hi = node_off[tmesh[tl] + 1];
+
+    double sp = 0, ep = 0, sx = 0, ex = 0, sy = 0, ey = 0, sz = 0, ez = 0;
+    for (int64_t c0 = lo; c0 < hi; c0 += TILE) {
+        const int cnt = (int)(hi - c0 < TILE ? hi - c0 : TILE);
+        __syncthreads();
+        if (lane < cnt) sh[lane] = src[c0 + lane];
+        __syncthreads();
+        double p = 0, gx = 0, gy = 0, gz = 0;
+        const bool full = c0 >= b && c0 + cnt <= e;
+        if (__all(full)) {
+#pragma unroll 2
+            for (int j = 0; j < cnt; ++j) pair64(sh[j], x, y, z, p, gx, gy, gz);
+        } else {
+            const int jb = (int)(b - c0 > 0 ? (b - c0 < cnt ? b - c0 : cnt) : 0);
+            const int je = (int)(e - c0 < cnt ? (e - c0 > 0 ? e - c0 : 0) : cnt);
+            for (int j = jb; j < je; ++j) pair64(sh[j], x, y, z, p, gx, gy, gz);
+        }
+        two_sum(sp, ep, p);
+        two_sum(sx, ex, gx);
+        two_sum(sy, ey, gy);
+        two_sum(sz, ez, gz);
+    }
+    if (valid) {
+        const int64_t o = out_idx ? (int64_t)out_idx[i] : i;
+        phi[o] = sp + ep;
+        if (grad) {
+            grad[3 * o] = sx + ex;
+            grad[3 * o + 1] = sy + ey;
+            grad[3 * o + 2] = sz + ez;
+        }
+    }
+    if (pairs) {
+        double w = wave_sum(valid ? (double)(e - b) : 0.0);
+        if ((lane & 63) == 0) atomicAdd(pairs, w);
+    }
+}
+
+// ---------------------------------------------------------------- mixed
+template <int TILE>
+__global__ __launch_bounds__(TILE) void k_p2p_direct_mixed(
+    int64_t nmax, const int32_t *__restrict__ n_dev, const double *__restrict__ tx,
+    const double *__restrict__ ty, const double *__restrict__ tz, const int32_t *__restrict__ tmesh,
+    const int64_t *__restrict__ node_off, const Src *__restrict__ src, const int32_t *__restrict__ out_idx,
+    double *__restrict__ phi, double *__restrict__ grad, double *__restrict__ pairs) {
+    __shared__ SrcF sh[TILE];
+    const int64_t n = n_dev ? (int64_t)*n_dev : nmax;
+    const int64_t t0 = (int64_t)blockIdx.x * TILE;
+    if (t0 >= n) return;
+    const int lane = threadIdx.x;
+    const int64_t i = t0 + lane;
+    const bool valid = i < n;
+    const int64_t ii = valid ? i : n - 1;
+    // tile origin: positions are differenced in FP64 against it, then rounded
+    const double ox = tx[t0], oy = ty[t0], oz = tz[t0];
+    const double dxo = tx[ii] - ox, dyo = ty[ii] - oy, dzo = tz[ii] - oz;
+    const float x = (float)dxo, y = (float)dyo, z = (float)dzo;
+    const float xl = (float)(dxo - (double)x), yl = (float)(dyo - (double)y), zl = (float)(dzo - (double)z);
+    const int32_t m = tmesh[ii];
+    const int64_t b = node_off[m], e = node_off[m + 1];
+    const int64_t tl = (t0 + TILE < n ? t0 + TILE : n) - 1;
+    const int64_t lo = node_off[tmesh[t0]], hi = node_off[tmesh[tl] + 1];
+
+    float sp = 0, ep = 0, sx = 0, ex = 0, sy = 0, ey = 0, sz = 0, ez = 0;
+    for (int64_t c0 = lo; c0 < hi; c0 += TILE) {
+        const int cnt = (int)(hi - c0 < TILE ? hi - c0 : TILE);
+        __syncthreads();
+        if (lane < cnt) {
+            const Src s = src[c0 + lane];
+            SrcF f;
+            const double qx = s.yx - ox, qy = s.yy - oy, qz = s.yz - oz;
+            f.yx = (float)qx;
+            f.yy = (float)qy;
+            f.yz = (float)qz;
+            f.lx = (float)(qx - (double)f.yx);
+            f.ly = (float)(qy - (double)f.yy);
+            f.lz = (float)(qz - (double)f.yz);
+            f.pad = 0.0f;
+            f.s2 = (float)s.s2;
+            f.ax = (float)s.ax;
+            f.ay = (float)s.ay;
+            f.az = (float)s.az;
+            f.s2x2 = (float)s.s2x2;
+            sh[lane] = f;
+        }
+        __syncthreads();
+        const bool full = c0 >= b && c0 + cnt <= e;
+        const int jb = full ? 0 : (int)(b - c0 > 0 ? (b - c0 < cnt ? b - c0 : cnt) : 0);
+        const int je = full ? cnt : (int)(e - c0 < cnt ? (e - c0 > 0 ? e - c0 : 0) : cnt);
+        const bool wave_full = __all(full);
+        // FP32 partials over sub-chunks of 32 nodes, folded by two-sum
+        for (int j0 = 0; j0 < cnt; j0 += 32) {
+            float p = 0, gx = 0, gy = 0, gz = 0;
+            const int j1 = j0 + 32 < cnt ? j0 + 32 : cnt;
+            if (wave_full) {
+#pragma unroll 4
+                for (int j = j0; j < j1; ++j) pair32(sh[j], x, y, z, xl, yl, zl, p, gx, gy, gz);
+            } else {
+                const int a0 = j0 > jb ? j0 : jb, a1 = j1 < je ? j1 : je;
+                for (int j = a0; j < a1; ++j) pair32(sh[j], x, y, z, xl, yl, zl, p, gx, gy, gz);
+            }
+            two_sum_f(sp, ep, p);
+            two_sum_f(sx, ex, gx);
+            two_sum_f(sy, ey, gy);
+            two_sum_f(sz, ez, gz);
+        }
+    }
+    if (valid) {
+        const int64_t o = out_idx ? (int64_t)out_idx[i] : i;
+        phi[o] = (double)sp + (double)ep;
+        if (grad) {
+            grad[3 * o] = (double)sx + (double)ex;
+            grad[3 * o + 1] = (double)sy + (double)ey;
+            grad[3 * o + 2] = (double)sz + (double)ez;
+        }
+    }
+    if (pairs) {
+        double w = wave_sum(valid ? (double)(e - b) : 0.0);
+        if ((lane & 63) == 0) atomicAdd(pairs, w);
+    }
+}
+
+template <int TILE>
+void launch_tile(Ctx &c, int64_t n, const int32_t *n_dev, const double *tx, const double *ty, const double *tz,
+                 const int32_t *tmesh, const int32_t *out_idx, double *phi, double *grad) {
+    dim3 grid((unsigned)ceil_div(n, TILE)), block(TILE);
+    double *pairs = c.pairs.as<double>();
+    if (c.opt.precision == LSS_MIXED)
+        hipLaunchKernelGGL(k_p2p_direct_mixed<TILE>, grid, block, 0, c.stream, n, n_dev, tx, ty, tz, tmesh,
+                           c.node_off.as<int64_t>(), c.src.as<Src>(), out_idx, phi, grad, pairs);
+    else
+        hipLaunchKernelGGL(k_p2p_direct_f64<TILE>, grid, block, 0, c.stream, n, n_dev, tx, ty, tz, tmesh,
+                           c.node_off.as<int64_t>(), c.src.as<Src>(), out_idx, phi, grad, pairs);
+    LSS_CHECK_LAUNCH("k_p2p_direct");
+}
+
+}  // namespace
+
+void launch_p2p_direct(Ctx &c, int64_t n, const int32_t *n_dev, const double *tx, const double *ty,
+                       const double *tz, const int32_t *tmesh, const int32_t *out_idx, double *phi,
+                       double *grad, int /*grad_stride*/) {
+    if (n <= 0) return;
+    switch (c.opt.tile) {
+        case 64: launch_tile<64>(c, n, n_dev, tx, ty, tz, tmesh, out_idx, phi, grad); break;
+        case 128: launch_tile<128>(c, n, n_dev, tx, ty, tz, tmesh, out_idx, phi, grad); break;
+        default: launch_tile<256>(c, n, n_dev, tx, ty, tz, tmesh, out_idx, phi, grad); break;
+    }
+}
+
+}  // namespace lss
