@@ -1,0 +1,219 @@
+// Solid harmonics and translation operators of the Laplace fast multipole
+// method used for the far field of the smoothed-indicator sum (section 4.4,
+// eq. kerdecomp: beyond the cut the kernel is the Laplace double layer, whose
+// sum the FMM evaluates).  Host + device, header only.
+//
+// Conventions (complex, m = -n..n):
+//   regular   U_n^m(r):  U_0^0 = 1,  U_m^m = -(x+iy)/(2m) U_{m-1}^{m-1},
+//                        U_n^m = ((2n-1) z U_{n-1}^m - r^2 U_{n-2}^m) / ((n+m)(n-m))
+//   irregular T_n^m(r):  T_0^0 = 1/r, T_m^m = -(2m-1)(x+iy)/r^2 T_{m-1}^{m-1},
+//                        T_n^m = ((2n-1) z T_{n-1}^m - (n-1+m)(n-1-m) T_{n-2}^m) / r^2
+//   U_n^{-m} = (-1)^m conj(U_n^m), same for T.  With these
+//     1/|x-y|        = sum conj(U_n^m(y)) T_n^m(x)                 (|y| < |x|)
+//     U_n^m(a+b)     = sum_{k,l} U_k^l(a) U_{n-k}^{m-l}(b)
+//     T_n^m(x-y)     = sum_{k,l} conj(U_k^l(y)) T_{n+k}^{m+l}(x)   (|y| < |x|)
+//     dz U_n^m = U_{n-1}^m,  (dx+i dy) U_n^m = U_{n-1}^{m+1},  (dx-i dy) U_n^m = -U_{n-1}^{m-1}.
+//
+// Expansions of a box of side s, centre c, are stored scaled, real layout:
+//   multipole  M~_n^m = M_n^m / s^n,   Phi(x) = sum M_n^m T_n^m(x - c)
+//   local      L~_k^l = L_k^l s^k,     Phi(x) = sum L_k^l U_k^l(x - c)
+// Real layout of coefficient (n, m >= 0): Re at n^2 (m = 0) or n^2 + 2m - 1,
+// Im at n^2 + 2m; (p+1)^2 reals per expansion.  The m < 0 half follows from
+// the symmetry of a real potential, M_n^{-m} = (-1)^m conj(M_n^m).
+//
+// Translations in scaled form are level independent:
+//   M2M (child c -> parent):  M~_n^m(P) = sum 2^{-n} conj(U_{n-k}^{m-l}(w)) M~_k^l(c)
+//   M2L (source S -> target T, same side s, v = (c_T - c_S)/s):
+//                             L~_k^l(T) = (1/s) (-1)^{k+l} sum T_{n+k}^{m-l}(v) M~_n^m(S)
+//   L2L (parent -> child):    L~_j^q(c) = sum 2^{-k} U_{k-j}^{l-q}(w) L~_k^l(P)
+// with w = (c_child - c_parent)/s_child in {-1/2, 1/2}^3.
+#pragma once
+
+#include <cmath>
+#include <cstdint>
+
+#if defined(__HIPCC__)
+#define LSS_HD __host__ __device__ inline
+#else
+#define LSS_HD inline
+#endif
+
+namespace lss {
+namespace fmm {
+
+LSS_HD int ncoef(int p) { return (p + 1) * (p + 1); }
+LSS_HD int ire(int n, int m) { return m == 0 ? n * n : n * n + 2 * m - 1; }
+LSS_HD int iim(int n, int m) { return n * n + 2 * m; }
+LSS_HD int tri(int n, int m) { return n * (n + 1) / 2 + m; }   // triangular table index, m >= 0
+
+struct cd {
+    double re, im;
+};
+LSS_HD cd cmul(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+LSS_HD cd cconj(cd a) { return {a.re, -a.im}; }
+LSS_HD cd cadd(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
+LSS_HD cd csub(cd a, cd b) { return {a.re - b.re, a.im - b.im}; }
+LSS_HD cd cscale(cd a, double s) { return {a.re * s, a.im * s}; }
+
+// U_n^m (m >= 0, n <= p) into a triangular table
+LSS_HD void regular_table(double x, double y, double z, int p, cd *U) {
+    const double r2 = x * x + y * y + z * z;
+    cd diag = {1.0, 0.0};
+    for (int m = 0; m <= p; ++m) {
+        if (m > 0) diag = cscale(cmul(diag, cd{x, y}), -1.0 / (2.0 * m));
+        U[tri(m, m)] = diag;
+        cd um2 = {0.0, 0.0}, um1 = diag;
+        for (int n = m + 1; n <= p; ++n) {
+            const double inv = 1.0 / ((double)(n + m) * (double)(n - m));
+            cd un = {((2 * n - 1) * z * um1.re - r2 * um2.re) * inv, ((2 * n - 1) * z * um1.im - r2 * um2.im) * inv};
+            U[tri(n, m)] = un;
+            um2 = um1;
+            um1 = un;
+        }
+    }
+}
+
+// T_n^m (m >= 0, n <= p) into a triangular table (r > 0)
+LSS_HD void irregular_table(double x, double y, double z, int p, cd *T) {
+    const double r2 = x * x + y * y + z * z;
+    const double ir2 = 1.0 / r2;
+    cd diag = {sqrt(ir2), 0.0};
+    for (int m = 0; m <= p; ++m) {
+        if (m > 0) diag = cscale(cmul(diag, cd{x, y}), -(2.0 * m - 1.0) * ir2);
+        T[tri(m, m)] = diag;
+        cd tm2 = {0.0, 0.0}, tm1 = diag;
+        for (int n = m + 1; n <= p; ++n) {
+            const double a = (2 * n - 1) * z, b = (double)(n - 1 + m) * (double)(n - 1 - m);
+            cd tn = {(a * tm1.re - b * tm2.re) * ir2, (a * tm1.im - b * tm2.im) * ir2};
+            T[tri(n, m)] = tn;
+            tm2 = tm1;
+            tm1 = tn;
+        }
+    }
+}
+
+// table access with any m in [-n, n] (0 outside)
+LSS_HD cd tget(const cd *tab, int n, int m) {
+    if (n < 0 || m > n || m < -n) return cd{0.0, 0.0};
+    if (m >= 0) return tab[tri(n, m)];
+    cd v = cconj(tab[tri(n, -m)]);
+    return (m & 1) ? cscale(v, -1.0) : v;
+}
+
+// Real-basis entry of a complex coefficient map L_k^l = sum_{n,m} A(k,l,n,m) M_n^m
+// acting on the real layouts: output row (k, l>=0, Re/Im), input column (n, m>=0, Re/Im).
+template <class F>
+LSS_HD double folded_entry(const F &A, int k, int l, bool out_im, int n, int m, bool in_im) {
+    cd c;
+    if (m == 0) {
+        if (in_im) return 0.0;
+        c = A(k, l, n, 0);
+    } else {
+        cd ap = A(k, l, n, m), am = A(k, l, n, -m);
+        if (m & 1) am = cscale(am, -1.0);
+        if (!in_im) c = cadd(ap, am);
+        else {
+            cd d = csub(ap, am);
+            c = cd{-d.im, d.re};   // i * d
+        }
+    }
+    return out_im ? c.im : c.re;
+}
+
+// decode a real-layout index into (n, m, is_im)
+LSS_HD void decode(int idx, int &n, int &m, bool &im) {
+    n = (int)sqrt((double)idx);
+    while (n * n > idx) --n;
+    while ((n + 1) * (n + 1) <= idx) ++n;
+    int r = idx - n * n;
+    if (r == 0) { m = 0; im = false; }
+    else { m = (r + 1) / 2; im = (r % 2) == 0; }
+}
+
+// operator entry functors --------------------------------------------------
+struct M2LMap {           // A(k,l,n,m) = (-1)^{k+l} T_{n+k}^{m-l}(v)   (table up to 2p)
+    const cd *Tv;
+    LSS_HD cd operator()(int k, int l, int n, int m) const {
+        cd t = tget(Tv, n + k, m - l);
+        return ((k + l) & 1) ? cscale(t, -1.0) : t;
+    }
+};
+struct M2MMap {           // A(n,m,k,l) = 2^{-n} conj(U_{n-k}^{m-l}(w))
+    const cd *Uw;
+    LSS_HD cd operator()(int n, int m, int k, int l) const {
+        if (k > n) return cd{0.0, 0.0};
+        cd u = cconj(tget(Uw, n - k, m - l));
+        return cscale(u, ldexp(1.0, -n));
+    }
+};
+struct L2LMap {           // A(j,q,k,l) = 2^{-k} U_{k-j}^{l-q}(w)
+    const cd *Uw;
+    LSS_HD cd operator()(int j, int q, int k, int l) const {
+        if (k < j) return cd{0.0, 0.0};
+        return cscale(tget(Uw, k - j, l - q), ldexp(1.0, -k));
+    }
+};
+
+// P2M of one dipole a at scaled position rt (relative to the box centre, in
+// units of the box side s): adds to M~ (real layout) the coefficients of
+// -(a . grad_y) 1/(4 pi |x - y|).  U is a scratch table of tri(p, p)+1 entries.
+LSS_HD void p2m_dipole(double rx, double ry, double rz, double ax, double ay, double az, double inv4pis, int p,
+                       cd *U, double *M) {
+    regular_table(rx, ry, rz, p, U);
+    for (int n = 1; n <= p; ++n)
+        for (int m = 0; m <= n; ++m) {
+            cd up = tget(U, n - 1, m + 1), dn = tget(U, n - 1, m - 1), zz = tget(U, n - 1, m);
+            // (a . grad) U_n^m = 1/2 (ax - i ay) U^{m+1} - 1/2 (ax + i ay) U^{m-1} + az U^m
+            cd t = cadd(cadd(cmul(cd{0.5 * ax, -0.5 * ay}, up), cmul(cd{-0.5 * ax, -0.5 * ay}, dn)), cscale(zz, az));
+            t = cscale(cconj(t), -inv4pis);
+            M[ire(n, m)] += t.re;
+            if (m > 0) M[iim(n, m)] += t.im;
+        }
+}
+
+// L2P: Phi and grad Phi of a local expansion at scaled position (rx,ry,rz)
+// (in units of the box side s); grad is returned in physical units (divided by s).
+LSS_HD void l2p(const double *L, double rx, double ry, double rz, double inv_s, int p, double &phi, double g[3]) {
+    const double r2 = rx * rx + ry * ry + rz * rz;
+    double ph = 0.0, gz = 0.0, Are = 0.0, Aim = 0.0;
+    cd diag = {1.0, 0.0};
+    auto Lget = [&](int n, int m) -> cd {
+        if (n > p || m > n || m < -n) return cd{0.0, 0.0};
+        int am = m < 0 ? -m : m;
+        cd v = {L[ire(n, am)], am == 0 ? 0.0 : L[iim(n, am)]};
+        if (m < 0) { v = cconj(v); if (am & 1) v = cscale(v, -1.0); }
+        return v;
+    };
+    for (int m = 0; m <= p; ++m) {
+        if (m > 0) diag = cscale(cmul(diag, cd{rx, ry}), -1.0 / (2.0 * m));
+        cd um2 = {0.0, 0.0}, u = diag;
+        for (int j = m; j <= p; ++j) {
+            if (j > m) {
+                const double inv = 1.0 / ((double)(j + m) * (double)(j - m));
+                cd un = {((2 * j - 1) * rz * u.re - r2 * um2.re) * inv, ((2 * j - 1) * rz * u.im - r2 * um2.im) * inv};
+                um2 = u;
+                u = un;
+            }
+            const double w = m == 0 ? 1.0 : 2.0;
+            cd Ljm = Lget(j, m);
+            ph += w * (Ljm.re * u.re - Ljm.im * u.im);
+            cd Lz = Lget(j + 1, m);
+            gz += w * (Lz.re * u.re - Lz.im * u.im);
+            cd a1 = cmul(Lget(j + 1, m - 1), u);     // s = m term of (dx + i dy)
+            Are += a1.re;
+            Aim += a1.im;
+            if (m > 0) {                              // s = -m term: -conj(L_{j+1}^{m+1} U_j^m)
+                cd a2 = cmul(Lget(j + 1, m + 1), u);
+                Are -= a2.re;
+                Aim += a2.im;
+            }
+        }
+    }
+    phi = ph;
+    g[0] = Are * inv_s;
+    g[1] = Aim * inv_s;
+    g[2] = gz * inv_s;
+}
+
+}  // namespace fmm
+}  // namespace lss

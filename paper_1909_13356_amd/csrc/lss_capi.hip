@@ -85,6 +85,9 @@ void build(Ctx &c) {
     launch_bbox(c);
     launch_pseudonormals(c);
     c.pairs.ensure(sizeof(double) * 4);
+    c.stats.n_boxes = c.stats.n_leaves = c.stats.n_m2l = 0;
+    c.stats.tree_depth = c.stats.fmm_order = 0;
+    if (c.opt.far_field == LSS_FAR_FMM) build_fmm(c);
     c.built = true;
     c.stats.n_tris = c.ntris;
     c.stats.n_nodes = c.nnodes;
@@ -100,6 +103,23 @@ void ensure_targets(Ctx &c, int64_t n) {
     c.ty.ensure(sizeof(double) * n);
     c.tz.ensure(sizeof(double) * n);
     c.tmesh.ensure(sizeof(int32_t) * n);
+}
+
+// FMM evaluation of the targets already in c.tx/ty/tz[0..n) (count *n_dev on
+// the device if given): leaf of each target, targets sorted by leaf, tiles,
+// near field + L2P.  Outputs at the target's index in tx/ty/tz.
+void eval_fmm_targets(Ctx &c, int64_t n, const int32_t *n_dev, double *phi, double *grad, bool reset_pairs = true) {
+    launch_locate_targets(c, n, n_dev, c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(), c.tkey.as<uint64_t>(),
+                          c.tperm.as<int32_t>());
+    sort_pairs(c, c.tkey.as<uint64_t>(), c.tkey2.as<uint64_t>(), c.tperm.as<int32_t>(), c.tperm2.as<int32_t>(), n, 64);
+    c.tstart.ensure(sizeof(int32_t) * (n + 1));
+    c.ntiles.ensure(16);
+    build_tiles(c, n, n_dev, c.tkey2.as<uint64_t>(), fmm_tile(c), c.tstart.as<int32_t>(), c.ntiles.as<int32_t>());
+    if (reset_pairs) LSS_HIP(hipMemsetAsync(c.pairs.p, 0, sizeof(double), c.stream));
+    c.ev_begin();
+    launch_eval_fmm(c, n, c.ntiles.as<int32_t>(), c.tstart.as<int32_t>(), n_dev, n, c.tkey2.as<uint64_t>(),
+                    c.tperm2.as<int32_t>(), c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(), nullptr, phi, grad);
+    c.ev_end();
 }
 
 void eval(Ctx &c, const double *x, const int32_t *xm, int64_t n, double *phi, double *grad, unsigned flags) {
@@ -140,6 +160,11 @@ void eval(Ctx &c, const double *x, const int32_t *xm, int64_t n, double *phi, do
         if (nb) fail(LSS_EINVAL, "lss_eval: x_mesh values outside [0, nmesh)");
     }
     ensure_targets(c, n);
+    c.ev_reset();
+    if (c.opt.far_field == LSS_FAR_FMM) {
+        launch_soa(c, dx, n, c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>());
+        eval_fmm_targets(c, n, nullptr, dphi, dgrad);
+    } else {
     launch_target_keys(c, dx, dxm, n, c.tkey.as<uint64_t>(), c.tperm.as<int32_t>());
     size_t tb = sort_pairs_u64_tmp_bytes(n);
     c.sort_tmp.ensure(tb);
@@ -148,11 +173,11 @@ void eval(Ctx &c, const double *x, const int32_t *xm, int64_t n, double *phi, do
     launch_gather_targets(c, dx, dxm, c.tperm2.as<int32_t>(), n, c.tx.as<double>(), c.ty.as<double>(),
                           c.tz.as<double>(), c.tmesh.as<int32_t>());
     LSS_HIP(hipMemsetAsync(c.pairs.p, 0, sizeof(double), c.stream));
-    c.ev_reset();
     c.ev_begin();
     launch_p2p_direct(c, n, nullptr, c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(),
                       c.tmesh.as<int32_t>(), c.tperm2.as<int32_t>(), dphi, dgrad, 3);
     c.ev_end();
+    }
     if (!dev) {
         LSS_HIP(hipMemcpyAsync(phi, dphi, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
         if (grad) LSS_HIP(hipMemcpyAsync(grad, dgrad, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, c.stream));
@@ -192,10 +217,14 @@ void project(Ctx &c, const double *uv, int32_t np, double *h, double *xout, int8
         evals += nact;
         ++iters_run;
         launch_newton_targets(c, N);
-        c.ev_begin();
-        launch_p2p_direct(c, N, s.nact.as<int32_t>(), c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(),
-                          c.tmesh.as<int32_t>(), nullptr, phi.as<double>(), grad.as<double>(), 3);
-        c.ev_end();
+        if (c.opt.far_field == LSS_FAR_FMM) {
+            eval_fmm_targets(c, N, s.nact.as<int32_t>(), phi.as<double>(), grad.as<double>(), false);
+        } else {
+            c.ev_begin();
+            launch_p2p_direct(c, N, s.nact.as<int32_t>(), c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(),
+                              c.tmesh.as<int32_t>(), nullptr, phi.as<double>(), grad.as<double>(), 3);
+            c.ev_end();
+        }
         launch_newton_update(c, N, tau, phi.as<double>(), grad.as<double>());
         launch_compact_active(c, N);
     }

@@ -1,0 +1,388 @@
+// Laplace-dipole fast multipole far field (section 4.4, eq. kerdecomp: beyond
+// the cut the kernel is the double-layer kernel, summed here by an FMM):
+// translation operators as dense real matrices, dipole P2M at the leaves, and
+// every translation (M2M, M2L, L2L) as a gathered matrix product
+//     Y[dst_j] += scale_j * Op * X[src_j]
+// on the FP64 matrix cores (v_mfma_f64_16x16x4f64).  M2L runs one launch per
+// displacement class (one dense operator per class, all levels share it in
+// box-scaled form); inside a launch every destination box appears once, so
+// the accumulation is race free and deterministic.
+#include <cstring>
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "fmm_math.h"
+#include "lss_internal.h"
+
+namespace lss {
+
+namespace {
+
+using fmm::cd;
+constexpr int kBlk = 256;
+constexpr int kR = 7;
+constexpr int kNClass = (2 * kR + 1) * (2 * kR + 1) * (2 * kR + 1);
+constexpr double kPi = 3.14159265358979323846;
+
+inline unsigned grid_for(int64_t n, int blk = kBlk) { return (unsigned)ceil_div(n > 0 ? n : 1, blk); }
+
+// ------------------------------------------------------------- operators
+// one table per operator: irregular (M2L, order 2p) or regular (M2M/L2L, order p)
+__global__ void k_op_tables(int nops, const double *__restrict__ vecs, int order, int irregular, int stride, cd *tabs) {
+    int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= nops) return;
+    const double *v = vecs + 3 * o;
+    if (irregular) fmm::irregular_table(v[0], v[1], v[2], order, tabs + (int64_t)o * stride);
+    else fmm::regular_table(v[0], v[1], v[2], order, tabs + (int64_t)o * stride);
+}
+
+// entry (row, k) of operator o stored k-major: opT[o][k * ncp + row]
+__global__ void k_fill_op(int kind, int p, int ncp, int nops, const cd *__restrict__ tabs, int stride, double *ops) {
+    const int64_t per = (int64_t)ncp * ncp;
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int o = blockIdx.y;
+    if (e >= per || o >= nops) return;
+    const int k = (int)(e / ncp), row = (int)(e - (int64_t)k * ncp);
+    const int nc = fmm::ncoef(p);
+    double v = 0.0;
+    if (row < nc && k < nc) {
+        int kk, l, n, m;
+        bool oi, ii;
+        fmm::decode(row, kk, l, oi);
+        fmm::decode(k, n, m, ii);
+        const cd *tab = tabs + (int64_t)o * stride;
+        if (kind == 0) v = fmm::folded_entry(fmm::M2LMap{tab}, kk, l, oi, n, m, ii);
+        else if (kind == 1) v = fmm::folded_entry(fmm::M2MMap{tab}, kk, l, oi, n, m, ii);
+        else v = fmm::folded_entry(fmm::L2LMap{tab}, kk, l, oi, n, m, ii);
+    }
+    ops[(int64_t)o * per + e] = v;
+}
+
+// ------------------------------------------------------------------ P2M
+constexpr int kG = 4;          // nodes per pass
+constexpr int kNPT = 4;        // coefficients per thread (p <= 40)
+
+struct Geo {
+    double o[3];
+    double L0;
+};
+
+__global__ __launch_bounds__(kBlk) void k_p2m(const int32_t *__restrict__ nleaf_dev, const int32_t *__restrict__ leaves,
+                                                int p, int ncp, Geo g, const int32_t *__restrict__ lev,
+                                                const int32_t *__restrict__ ijk, const int64_t *__restrict__ nb,
+                                                const int64_t *__restrict__ ne, const Src *__restrict__ src, double *M) {
+    extern __shared__ double smem[];
+    const int tstride = fmm::tri(p - 1, p - 1) + 1;
+    cd *U = reinterpret_cast<cd *>(smem);                 // kG tables
+    double *nd = smem + 2 * kG * tstride;                 // kG x (rx, ry, rz, ax, ay, az)
+    if ((int)blockIdx.x >= *nleaf_dev) return;
+    const int32_t b = leaves[blockIdx.x];
+    const double s = ldexp(g.L0, -lev[b]);
+    const double c0 = g.o[0] + (ijk[3 * b] + 0.5) * s, c1 = g.o[1] + (ijk[3 * b + 1] + 0.5) * s,
+                 c2 = g.o[2] + (ijk[3 * b + 2] + 0.5) * s;
+    const double inv4pis = 1.0 / (4.0 * kPi * s);
+    // coefficient slots of this thread: (n, m), n = 1..p, m = 0..n enumerated row by row
+    int qn[kNPT], qm[kNPT];
+    double are[kNPT], aim[kNPT];
+    const int ncplx = (p + 1) * (p + 2) / 2 - 1;
+    for (int u = 0; u < kNPT; ++u) {
+        int q = threadIdx.x + u * kBlk;
+        qn[u] = -1;
+        are[u] = aim[u] = 0.0;
+        if (q < ncplx) {
+            int idx = q + 1, n = 0;                        // skip (0, 0)
+            while ((n + 1) * (n + 2) / 2 <= idx) ++n;
+            qn[u] = n;
+            qm[u] = idx - n * (n + 1) / 2;
+        }
+    }
+    const int64_t b0 = nb[b], b1 = ne[b];
+    for (int64_t k0 = b0; k0 < b1; k0 += kG) {
+        const int gn = (int)(b1 - k0 < kG ? b1 - k0 : kG);
+        __syncthreads();
+        if ((int)threadIdx.x < gn) {
+            const Src sr = src[k0 + threadIdx.x];
+            // unfold the dipole: a = a' / c(sigma), 1/c = 4 sqrt2 pi^1.5 sigma^3, sigma^2 = 1/(2 s2)
+            const double sig3 = pow(0.5 / sr.s2, 1.5);
+            const double f = 4.0 * 1.4142135623730951 * 5.568327996831708 * sig3;
+            double *q = nd + 6 * threadIdx.x;
+            q[0] = (sr.yx - c0) / s;
+            q[1] = (sr.yy - c1) / s;
+            q[2] = (sr.yz - c2) / s;
+            q[3] = sr.ax * f;
+            q[4] = sr.ay * f;
+            q[5] = sr.az * f;
+        }
+        __syncthreads();
+        {   // column m of U(r_g), orders m..p-1
+            const int gi = threadIdx.x / 64, m = threadIdx.x % 64;
+            if (gi < gn && m <= p - 1) {
+                const double *q = nd + 6 * gi;
+                const double x = q[0], y = q[1], z = q[2], r2 = x * x + y * y + z * z;
+                cd d = {1.0, 0.0};
+                for (int t = 1; t <= m; ++t) d = fmm::cscale(fmm::cmul(d, cd{x, y}), -1.0 / (2.0 * t));
+                cd *Ug = U + gi * tstride;
+                Ug[fmm::tri(m, m)] = d;
+                cd um2 = {0.0, 0.0}, um1 = d;
+                for (int n = m + 1; n <= p - 1; ++n) {
+                    const double inv = 1.0 / ((double)(n + m) * (double)(n - m));
+                    cd un = {((2 * n - 1) * z * um1.re - r2 * um2.re) * inv, ((2 * n - 1) * z * um1.im - r2 * um2.im) * inv};
+                    Ug[fmm::tri(n, m)] = un;
+                    um2 = um1;
+                    um1 = un;
+                }
+            }
+        }
+        __syncthreads();
+        for (int u = 0; u < kNPT; ++u) {
+            if (qn[u] < 0) continue;
+            const int n = qn[u], m = qm[u];
+            for (int gi = 0; gi < gn; ++gi) {
+                const cd *Ug = U + gi * tstride;
+                const double *q = nd + 6 * gi;
+                const double ax = q[3], ay = q[4], az = q[5];
+                cd up = fmm::tget(Ug, n - 1, m + 1), dn = fmm::tget(Ug, n - 1, m - 1), zz = fmm::tget(Ug, n - 1, m);
+                cd t = fmm::cadd(fmm::cadd(fmm::cmul(cd{0.5 * ax, -0.5 * ay}, up), fmm::cmul(cd{-0.5 * ax, -0.5 * ay}, dn)),
+                                 fmm::cscale(zz, az));
+                are[u] -= inv4pis * t.re;       // conj, times -1/(4 pi s)
+                aim[u] += inv4pis * t.im;
+            }
+        }
+    }
+    double *Mb = M + (int64_t)b * ncp;
+    for (int u = 0; u < kNPT; ++u) {
+        if (qn[u] < 0) continue;
+        Mb[fmm::ire(qn[u], qm[u])] = are[u];
+        if (qm[u] > 0) Mb[fmm::iim(qn[u], qm[u])] = aim[u];
+    }
+}
+
+__global__ void k_leaf_flags(int64_t n, const int32_t *__restrict__ child, const int64_t *__restrict__ nb,
+                             const int64_t *__restrict__ ne, int32_t *flag, int32_t *ids) {
+    int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n) return;
+    flag[b] = (child[b] < 0 && ne[b] > nb[b]) ? 1 : 0;
+    ids[b] = (int32_t)b;
+}
+
+// --------------------------------------------------------- gathered GEMM
+typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int kKB = 32;
+
+enum { G_LIST = 0, G_M2M = 1, G_L2L = 2 };
+
+struct GemmArgs {
+    int mode, ncp;
+    int64_t npairs;
+    const double *opT;          // ncp x ncp, k-major
+    const double *X;
+    double *Y;
+    const uint64_t *mkey;       // G_LIST: dst = low 32 bits
+    const int32_t *mval;        // G_LIST: src
+    int64_t base;               // G_M2M / G_L2L: first child box of the level
+    int oct;
+    const int32_t *parent, *lev;
+    double L0;
+};
+
+__device__ inline void pair_of(const GemmArgs &a, int64_t j, int64_t &dst, int64_t &src, double &scale) {
+    if (a.mode == G_LIST) {
+        dst = (int64_t)(uint32_t)(a.mkey[j] & 0xffffffffu);
+        src = a.mval[j];
+        scale = ldexp(1.0, a.lev[dst]) / a.L0;       // 1 / side of the target box
+    } else {
+        const int64_t ch = a.base + 8 * j + a.oct;
+        if (a.mode == G_M2M) { src = ch; dst = a.parent[ch]; }
+        else { dst = ch; src = a.parent[ch]; }
+        scale = 1.0;
+    }
+}
+
+// 64 output rows x 64 pairs per workgroup; wave w owns rows 16w..16w+15 and
+// four 16x16 accumulator tiles (one per group of 16 pairs).
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
+    __shared__ double As[kKB][64 + 1];
+    __shared__ double Bs[kKB][64 + 1];
+    __shared__ int64_t ssrc[64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r0 = blockIdx.x * 64;
+    const int64_t j0 = (int64_t)blockIdx.y * 64;
+    if (threadIdx.x < 64) {
+        int64_t j = j0 + threadIdx.x, d, s;
+        double sc;
+        if (j < a.npairs) { pair_of(a, j, d, s, sc); ssrc[threadIdx.x] = s; }
+        else ssrc[threadIdx.x] = -1;
+    }
+    d4 acc[4];
+    for (int t = 0; t < 4; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < a.ncp; k0 += kKB) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < kKB * 64; e += 256) {
+            const int kk = e >> 6, rr = e & 63;
+            As[kk][rr] = (r0 + rr < a.ncp) ? a.opT[(int64_t)(k0 + kk) * a.ncp + r0 + rr] : 0.0;
+            const int cc = e / kKB, k2 = e % kKB;
+            const int64_t s = ssrc[cc];
+            Bs[k2][cc] = s >= 0 ? a.X[s * a.ncp + k0 + k2] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kKB; kk += 4) {
+            const double av = As[kk + (lane >> 4)][16 * w + (lane & 15)];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const double bv = Bs[kk + (lane >> 4)][16 * t + (lane & 15)];
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+            }
+        }
+    }
+    for (int t = 0; t < 4; ++t) {
+        const int64_t j = j0 + 16 * t + (lane & 15);
+        if (j >= a.npairs) continue;
+        int64_t d, s;
+        double sc;
+        pair_of(a, j, d, s, sc);
+        double *y = a.Y + d * a.ncp;
+        // v_mfma_f64_16x16x4f64 accumulator: register i of lane l holds row (l/16) + 4i, column l%16
+        for (int i = 0; i < 4; ++i) {
+            const int row = r0 + 16 * w + (lane >> 4) + 4 * i;
+            if (row < a.ncp) y[row] += sc * acc[t][i];
+        }
+    }
+}
+
+void gemm(Ctx &c, GemmArgs a) {
+    // split long pair lists so that grid.y stays within the launch limit
+    const int64_t chunk = (int64_t)32768 * 64;
+    for (int64_t j0 = 0; j0 < a.npairs; j0 += chunk) {
+        GemmArgs b = a;
+        b.npairs = a.npairs - j0 < chunk ? a.npairs - j0 : chunk;
+        if (a.mode == G_LIST) { b.mkey = a.mkey + j0; b.mval = a.mval + j0; }
+        else b.base = a.base + 8 * j0;
+        dim3 grid((unsigned)ceil_div(b.ncp, 64), (unsigned)ceil_div(b.npairs, 64));
+        hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, c.stream, b);
+        LSS_CHECK_LAUNCH("k_gemm");
+    }
+}
+
+// class index -> offset vector
+void class_vec(int cls, double v[3]) {
+    const int W = 2 * kR + 1;
+    v[0] = cls / (W * W) - kR;
+    v[1] = (cls / W) % W - kR;
+    v[2] = cls % W - kR;
+}
+
+void build_ops(Ctx &c, int kind, int nops, const std::vector<double> &vecs, int p, int ncp, double *dst) {
+    const int order = kind == 0 ? 2 * p : p;
+    const int stride = fmm::tri(order, order) + 1;
+    DBuf dv, tabs;
+    dv.ensure(sizeof(double) * 3 * nops);
+    tabs.ensure(sizeof(cd) * (size_t)stride * nops);
+    LSS_HIP(hipMemcpyAsync(dv.p, vecs.data(), sizeof(double) * 3 * nops, hipMemcpyHostToDevice, c.stream));
+    hipLaunchKernelGGL(k_op_tables, dim3(grid_for(nops, 64)), dim3(64), 0, c.stream, nops, dv.as<double>(), order,
+                       kind == 0 ? 1 : 0, stride, tabs.as<cd>());
+    LSS_CHECK_LAUNCH("k_op_tables");
+    const int64_t per = (int64_t)ncp * ncp;
+    hipLaunchKernelGGL(k_fill_op, dim3(grid_for(per), nops), dim3(kBlk), 0, c.stream, kind, p, ncp, nops,
+                       tabs.as<cd>(), stride, dst);
+    LSS_CHECK_LAUNCH("k_fill_op");
+    LSS_HIP(hipStreamSynchronize(c.stream));
+}
+
+}  // namespace
+
+void build_fmm(Ctx &c) {
+    build_tree(c);
+    Tree &t = c.tree;
+    const int p = c.opt.fmm_order > 0 ? c.opt.fmm_order : (c.opt.precision == LSS_MIXED ? 20 : 26);
+    const int ncp = (int)ceil_div(fmm::ncoef(p), kKB) * kKB;
+    const int64_t per = (int64_t)ncp * ncp;
+    // operators: M2M / L2L for the 8 octants, M2L for the classes in use
+    if (t.ops_p != p) {
+        std::vector<double> w(24);
+        for (int o = 0; o < 8; ++o) {
+            w[3 * o] = (o & 1) ? 0.5 : -0.5;
+            w[3 * o + 1] = ((o >> 1) & 1) ? 0.5 : -0.5;
+            w[3 * o + 2] = ((o >> 2) & 1) ? 0.5 : -0.5;
+        }
+        t.opM2M.ensure(sizeof(double) * 8 * per);
+        t.opL2L.ensure(sizeof(double) * 8 * per);
+        build_ops(c, 1, 8, w, p, ncp, t.opM2M.as<double>());
+        build_ops(c, 2, 8, w, p, ncp, t.opL2L.as<double>());
+        t.op_class_slot.assign(kNClass, -1);
+        t.opM2L.release();
+        t.ops_p = p;
+    }
+    {
+        std::vector<int> need;
+        for (int cls : t.class_used)
+            if (t.op_class_slot[cls] < 0) need.push_back(cls);
+        if (!need.empty()) {
+            int have = 0;
+            for (int s : t.op_class_slot) have += s >= 0;
+            t.opM2L.grow_copy(sizeof(double) * (size_t)(have + need.size()) * per, sizeof(double) * (size_t)have * per,
+                              c.stream);
+            std::vector<double> v(3 * need.size());
+            for (size_t i = 0; i < need.size(); ++i) class_vec(need[i], &v[3 * i]);
+            build_ops(c, 0, (int)need.size(), v, p, ncp, t.opM2L.as<double>() + (int64_t)have * per);
+            for (size_t i = 0; i < need.size(); ++i) t.op_class_slot[need[i]] = have + (int)i;
+        }
+    }
+    t.p = p;
+    t.ncp = ncp;
+    // expansions
+    t.M.ensure(sizeof(double) * t.nboxes * ncp);
+    t.L.ensure(sizeof(double) * t.nboxes * ncp);
+    LSS_HIP(hipMemsetAsync(t.M.p, 0, sizeof(double) * t.nboxes * ncp, c.stream));
+    LSS_HIP(hipMemsetAsync(t.L.p, 0, sizeof(double) * t.nboxes * ncp, c.stream));
+    Geo g{{t.origin[0], t.origin[1], t.origin[2]}, t.L0};
+    // P2M on the non-empty leaves
+    DBuf flag, ids, leaves, nleaf;
+    flag.ensure(4 * t.nboxes); ids.ensure(4 * t.nboxes); leaves.ensure(4 * t.nboxes); nleaf.ensure(16);
+    hipLaunchKernelGGL(k_leaf_flags, dim3(grid_for(t.nboxes)), dim3(kBlk), 0, c.stream, t.nboxes, t.child.as<int32_t>(),
+                       t.nb.as<int64_t>(), t.ne.as<int64_t>(), flag.as<int32_t>(), ids.as<int32_t>());
+    LSS_CHECK_LAUNCH("k_leaf_flags");
+    compact_flags(c, t.nboxes, nullptr, flag.as<int32_t>(), ids.as<int32_t>(), leaves.as<int32_t>(), nleaf.as<int32_t>());
+    int32_t nl = 0;
+    LSS_HIP(hipMemcpyAsync(&nl, nleaf.p, 4, hipMemcpyDeviceToHost, c.stream));
+    LSS_HIP(hipStreamSynchronize(c.stream));
+    c.stats.n_leaves = nl;
+    if (nl > 0) {
+        const int tstride = fmm::tri(p - 1, p - 1) + 1;
+        size_t shm = sizeof(double) * (2 * kG * tstride + 6 * kG);
+        hipLaunchKernelGGL(k_p2m, dim3(nl), dim3(kBlk), shm, c.stream, nleaf.as<int32_t>(), leaves.as<int32_t>(), p, ncp, g,
+                           t.level.as<int32_t>(), t.ijk.as<int32_t>(), t.nb.as<int64_t>(), t.ne.as<int64_t>(),
+                           t.src.as<Src>(), t.M.as<double>());
+        LSS_CHECK_LAUNCH("k_p2m");
+    }
+    // upward pass: M2M from level depth to 1 into their parents
+    for (int lvl = t.depth; lvl >= 1; --lvl) {
+        const int64_t base = t.level_begin[lvl], npar = (t.level_begin[lvl + 1] - base) / 8;
+        for (int o = 0; o < 8; ++o) {
+            GemmArgs a{G_M2M, ncp, npar, t.opM2M.as<double>() + o * per, t.M.as<double>(), t.M.as<double>(), nullptr,
+                       nullptr, base, o, t.parent.as<int32_t>(), t.level.as<int32_t>(), t.L0};
+            gemm(c, a);
+        }
+    }
+    // M2L, one launch per displacement class
+    for (int cls : t.class_used) {
+        const int64_t b0 = t.class_beg[cls], n = t.class_end[cls] - b0;
+        GemmArgs a{G_LIST, ncp, n, t.opM2L.as<double>() + (int64_t)t.op_class_slot[cls] * per, t.M.as<double>(),
+                   t.L.as<double>(), t.m2l_key2.as<uint64_t>() + b0, t.m2l_val2.as<int32_t>() + b0, 0, 0,
+                   t.parent.as<int32_t>(), t.level.as<int32_t>(), t.L0};
+        gemm(c, a);
+    }
+    // downward pass: L2L from level 0 to depth-1 into their children
+    for (int lvl = 1; lvl <= t.depth; ++lvl) {
+        const int64_t base = t.level_begin[lvl], npar = (t.level_begin[lvl + 1] - base) / 8;
+        for (int o = 0; o < 8; ++o) {
+            GemmArgs a{G_L2L, ncp, npar, t.opL2L.as<double>() + o * per, t.L.as<double>(), t.L.as<double>(), nullptr,
+                       nullptr, base, o, t.parent.as<int32_t>(), t.level.as<int32_t>(), t.L0};
+            gemm(c, a);
+        }
+    }
+    c.stats.fmm_order = p;
+}
+
+}  // namespace lss

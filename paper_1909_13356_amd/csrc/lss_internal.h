@@ -57,6 +57,20 @@ struct DBuf {
         p = nullptr;
         bytes = 0;
     }
+    // grow keeping the first `keep` bytes (stream-ordered copy)
+    void grow_copy(size_t nb, size_t keep, hipStream_t s) {
+        if (nb <= bytes) return;
+        void *q = nullptr;
+        size_t want = nb + nb / 2;
+        LSS_HIP(hipMalloc(&q, want));
+        if (p && keep) LSS_HIP(hipMemcpyAsync(q, p, keep, hipMemcpyDeviceToDevice, s));
+        if (p) {
+            LSS_HIP(hipStreamSynchronize(s));
+            (void)hipFree(p);
+        }
+        p = q;
+        bytes = want;
+    }
     template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
@@ -88,6 +102,36 @@ struct NewtonState {
     DBuf nact;           // int32[2] active count (device)
 };
 
+// Octree over the quadrature nodes and the FMM state (far_field = LSS_FAR_FMM).
+struct Tree {
+    double origin[3] = {0, 0, 0};   // root cube [origin, origin + L0]^3
+    double L0 = 1.0;
+    int depth = 0;                  // deepest level
+    int64_t nboxes = 0;
+    std::vector<int64_t> level_begin;   // box ids of level l: [level_begin[l], level_begin[l+1])
+    // boxes (BFS order; the 8 children of a box are consecutive)
+    DBuf level, ijk, nb, ne, child, parent;   // int32, int32x3, int64, int64, int32, int32
+    DBuf rmax;                                // double: largest near radius of the box's nodes
+    // nodes in Morton order
+    DBuf key, key2, perm, perm2, src;         // u64, u64, int32, int32, Src
+    // interaction lists
+    DBuf p2p_key, p2p_key2, p2p_val, p2p_val2;    // u64 (T<<32|S), int32
+    int64_t n_p2p = 0;
+    DBuf p2p_beg, p2p_end;                    // per box, int32 offsets into the sorted p2p list
+    DBuf m2l_key, m2l_key2, m2l_val, m2l_val2;    // u64 (class<<32|T), int32 S
+    int64_t n_m2l = 0;
+    std::vector<int64_t> class_beg, class_end;    // host: segments of the sorted m2l list per class
+    std::vector<int32_t> class_used;
+    // expansions and operators
+    int p = 0, ncp = 0, K = 4;
+    DBuf M, L;                                // nboxes * ncp doubles
+    DBuf opM2M, opL2L, opM2L;                 // 8, 8 and nclass_used operators (ncp*ncp, k-major)
+    std::vector<int32_t> op_class_slot;       // class -> slot in opM2L (-1 if not built)
+    int ops_p = -1, ops_R = -1;
+    // frontier scratch
+    DBuf fr, fr2, cnt;
+};
+
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -114,8 +158,11 @@ struct Ctx {
     DBuf vH;                  // vertex pseudonormals (nverts * 3)
     double bbox_lo[3] = {0, 0, 0}, bbox_hi[3] = {0, 0, 0};
 
+    Tree tree;
+
     // --- per-eval scratch
     DBuf tkey, tkey2, tperm, tperm2, tx, ty, tz, tmesh, sort_tmp;
+    DBuf tflag, tpos, tstart, ntiles;   // FMM eval: tile heads over the leaf-sorted targets
     DBuf pairs;               // double accumulator of executed pairs (stats)
     bool pairs_pending = false;   // counter not yet read back into stats.last_pairs
     NewtonState ns;
@@ -167,11 +214,31 @@ void launch_newton_update(Ctx &c, int64_t N, double tau, const double *phi, cons
 void launch_compact_active(Ctx &c, int64_t N);
 void launch_newton_output(Ctx &c, int64_t N, double *h, double *xout, int8_t *status, int8_t *iters);
 
+// octree, lists, FMM (lss_tree.hip, lss_fmm.hip)
+void build_tree(Ctx &c);
+void build_fmm(Ctx &c);
+void launch_locate_targets(Ctx &c, int64_t n_max, const int32_t *n_dev, const double *tx, const double *ty,
+                           const double *tz, uint64_t *keys, int32_t *idx);
+int64_t build_tiles(Ctx &c, int64_t n_max, const int32_t *n_dev, const uint64_t *sorted_keys, int tile,
+                    int32_t *tile_start, int32_t *ntiles_dev);
+int fmm_tile(const Ctx &c);
+void launch_eval_fmm(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const int32_t *tile_start,
+                     const int32_t *n_dev, int64_t n_max, const uint64_t *sorted_keys, const int32_t *sorted_idx,
+                     const double *tx, const double *ty, const double *tz, const int32_t *out_idx, double *phi,
+                     double *grad);
+void launch_soa(Ctx &c, const double *x, int64_t n, double *tx, double *ty, double *tz);
+
 // sorting and scans (lss_sort.hip)
 size_t sort_pairs_u64_tmp_bytes(int64_t n);
 void sort_pairs_u64(void *tmp, size_t tmp_bytes, const uint64_t *kin, uint64_t *kout,
                     const int32_t *vin, int32_t *vout, int64_t n, int begin_bit, int end_bit,
                     hipStream_t s);
+// sort (key, value) pairs with a context-owned temporary; keys/values end in kout/vout
+void sort_pairs(Ctx &c, const uint64_t *kin, uint64_t *kout, const int32_t *vin, int32_t *vout, int64_t n,
+                int end_bit = 64);
+// order-preserving compaction helpers (lss_kernels.hip)
+void compact_flags(Ctx &c, int64_t n_max, const int32_t *n_dev, const int32_t *flag, const int32_t *in,
+                   int32_t *out, int32_t *count_dev);
 
 // ------------------------------------------------------------ constants
 constexpr int kMaxIterDefault = 40;

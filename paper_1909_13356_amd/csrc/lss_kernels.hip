@@ -634,6 +634,26 @@ void launch_compact_active(Ctx &c, int64_t N) {
     LSS_CHECK_LAUNCH("compact");
 }
 
+// out <- in[i] for flag[i] != 0, i < n (n = *n_dev if given, else n_max); count -> *count_dev
+void compact_flags(Ctx &c, int64_t n_max, const int32_t *n_dev, const int32_t *flag, const int32_t *in,
+                   int32_t *out, int32_t *count_dev) {
+    DBuf &bs = c.ns.blocksum;
+    int32_t nb = (int32_t)ceil_div(n_max > 0 ? n_max : 1, kCompBlk);
+    bs.ensure(sizeof(int32_t) * (nb + 2));
+    const int32_t *nd = n_dev;
+    if (!nd) {
+        int32_t *tmp = bs.as<int32_t>() + nb;
+        int32_t v = (int32_t)n_max;
+        LSS_HIP(hipMemcpyAsync(tmp, &v, sizeof(int32_t), hipMemcpyHostToDevice, c.stream));
+        LSS_HIP(hipStreamSynchronize(c.stream));
+        nd = tmp;
+    }
+    hipLaunchKernelGGL(k_block_count, dim3(nb), dim3(kCompBlk), 0, c.stream, nd, flag, bs.as<int32_t>());
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kCompBlk), 0, c.stream, nb, bs.as<int32_t>(), count_dev);
+    hipLaunchKernelGGL(k_block_scatter, dim3(nb), dim3(kCompBlk), 0, c.stream, nd, flag, bs.as<int32_t>(), in, out);
+    LSS_CHECK_LAUNCH("compact_flags");
+}
+
 void launch_newton_output(Ctx &c, int64_t N, double *h, double *xout, int8_t *status, int8_t *iters) {
     NewtonState &s = c.ns;
     hipLaunchKernelGGL(k_newton_output, dim3(grid_for(N)), dim3(kBlk), 0, c.stream, N, s.orig.as<int32_t>(),

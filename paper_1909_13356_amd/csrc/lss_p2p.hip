@@ -23,6 +23,7 @@
 #include <cstring>
 #include <hip/hip_runtime.h>
 
+#include "fmm_math.h"
 #include "kfit_tables.h"
 #include "lss_internal.h"
 
@@ -273,6 +274,185 @@ __global__ __launch_bounds__(TILE) void k_p2p_direct_mixed(
     }
 }
 
+
+// ------------------------------------------------------------ FMM eval
+// One tile = up to TILE targets of one octree leaf.  Near field: the full
+// kernel over the node ranges of the leaf's direct list, streamed through
+// LDS; far field: the leaf's local expansion (L2P with its gradient).  The
+// grid is persistent: workgroups walk the tile list, whose length is read on
+// the device.
+struct FmmEvalArgs {
+    const int32_t *ntiles_dev, *tile_start;
+    int64_t n_max;
+    const int32_t *n_dev;
+    const uint64_t *skey;
+    const int32_t *sidx;
+    const double *tx, *ty, *tz;
+    const int32_t *out_idx;
+    double *phi, *grad;
+    const int32_t *p2p_beg, *p2p_end, *p2p_src;
+    const int64_t *nb, *ne;
+    const int32_t *lev, *ijk;
+    const Src *src;
+    int64_t nnodes;
+    int32_t nboxes;
+    const double *L;
+    int p, ncp;
+    double o0, o1, o2, L0;
+    double *pairs;
+};
+
+__device__ __forceinline__ void fmm_range(const FmmEvalArgs &a, int e, bool outside, int64_t &lo, int64_t &hi) {
+    if (outside) { lo = 0; hi = a.nnodes; }
+    else {
+        const int32_t S = a.p2p_src[e];
+        lo = a.nb[S];
+        hi = a.ne[S];
+    }
+}
+
+__device__ __forceinline__ void fmm_l2p(const FmmEvalArgs &a, int32_t B, double x, double y, double z, double &ph,
+                                        double g[3]) {
+    const double s = ldexp(a.L0, -a.lev[B]);
+    const double cx = a.o0 + (a.ijk[3 * B] + 0.5) * s, cy = a.o1 + (a.ijk[3 * B + 1] + 0.5) * s,
+                 cz = a.o2 + (a.ijk[3 * B + 2] + 0.5) * s;
+    const double inv = 1.0 / s;
+    fmm::l2p(a.L + (int64_t)B * a.ncp, (x - cx) * inv, (y - cy) * inv, (z - cz) * inv, inv, a.p, ph, g);
+}
+
+template <int TILE>
+__global__ __launch_bounds__(TILE) void k_eval_fmm_f64(FmmEvalArgs a) {
+    __shared__ Src sh[TILE];
+    const int ntiles = *a.ntiles_dev;
+    const int64_t n = a.n_dev ? (int64_t)*a.n_dev : a.n_max;
+    const int lane = threadIdx.x;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t s0 = a.tile_start[tile];
+        const uint64_t leafk = a.skey[s0];
+        const int64_t sp_ = s0 + lane;
+        const bool valid = sp_ < n && a.skey[sp_] == leafk;
+        const int64_t ti = a.sidx[valid ? sp_ : s0];
+        const double x = a.tx[ti], y = a.ty[ti], z = a.tz[ti];
+        const int32_t B = (int32_t)leafk;
+        const bool outside = B >= a.nboxes;
+        const int e0 = outside ? 0 : a.p2p_beg[B], e1 = outside ? 1 : a.p2p_end[B];
+        double sp = 0, ep = 0, sx = 0, ex = 0, sy = 0, ey = 0, sz = 0, ez = 0;
+        double npair = 0.0;
+        for (int e = e0; e < e1; ++e) {
+            int64_t lo, hi;
+            fmm_range(a, e, outside, lo, hi);
+            npair += (double)(hi - lo);
+            for (int64_t c0 = lo; c0 < hi; c0 += TILE) {
+                const int cnt = (int)(hi - c0 < TILE ? hi - c0 : TILE);
+                __syncthreads();
+                if (lane < cnt) sh[lane] = a.src[c0 + lane];
+                __syncthreads();
+                double p = 0, gx = 0, gy = 0, gz = 0;
+#pragma unroll 2
+                for (int j = 0; j < cnt; ++j) pair64(sh[j], x, y, z, p, gx, gy, gz);
+                two_sum(sp, ep, p);
+                two_sum(sx, ex, gx);
+                two_sum(sy, ey, gy);
+                two_sum(sz, ez, gz);
+            }
+        }
+        double ph = 0.0, g[3] = {0.0, 0.0, 0.0};
+        if (!outside) fmm_l2p(a, B, x, y, z, ph, g);
+        if (valid) {
+            const int64_t o = a.out_idx ? (int64_t)a.out_idx[ti] : ti;
+            a.phi[o] = (sp + ph) + ep;
+            if (a.grad) {
+                a.grad[3 * o] = (sx + g[0]) + ex;
+                a.grad[3 * o + 1] = (sy + g[1]) + ey;
+                a.grad[3 * o + 2] = (sz + g[2]) + ez;
+            }
+        }
+        if (a.pairs) {
+            double w = wave_sum(valid ? npair : 0.0);
+            if ((lane & 63) == 0) atomicAdd(a.pairs, w);
+        }
+    }
+}
+
+template <int TILE>
+__global__ __launch_bounds__(TILE) void k_eval_fmm_mixed(FmmEvalArgs a) {
+    __shared__ SrcF sh[TILE];
+    const int ntiles = *a.ntiles_dev;
+    const int64_t n = a.n_dev ? (int64_t)*a.n_dev : a.n_max;
+    const int lane = threadIdx.x;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t s0 = a.tile_start[tile];
+        const uint64_t leafk = a.skey[s0];
+        const int64_t sp_ = s0 + lane;
+        const bool valid = sp_ < n && a.skey[sp_] == leafk;
+        const int64_t ti = a.sidx[valid ? sp_ : s0];
+        const int64_t t0 = a.sidx[s0];
+        const double ox = a.tx[t0], oy = a.ty[t0], oz = a.tz[t0];
+        const double X = a.tx[ti], Y = a.ty[ti], Z = a.tz[ti];
+        const double dxo = X - ox, dyo = Y - oy, dzo = Z - oz;
+        const float x = (float)dxo, y = (float)dyo, z = (float)dzo;
+        const float xl = (float)(dxo - (double)x), yl = (float)(dyo - (double)y), zl = (float)(dzo - (double)z);
+        const int32_t B = (int32_t)leafk;
+        const bool outside = B >= a.nboxes;
+        const int e0 = outside ? 0 : a.p2p_beg[B], e1 = outside ? 1 : a.p2p_end[B];
+        float sp = 0, ep = 0, sx = 0, ex = 0, sy = 0, ey = 0, sz = 0, ez = 0;
+        double npair = 0.0;
+        for (int e = e0; e < e1; ++e) {
+            int64_t lo, hi;
+            fmm_range(a, e, outside, lo, hi);
+            npair += (double)(hi - lo);
+            for (int64_t c0 = lo; c0 < hi; c0 += TILE) {
+                const int cnt = (int)(hi - c0 < TILE ? hi - c0 : TILE);
+                __syncthreads();
+                if (lane < cnt) {
+                    const Src s = a.src[c0 + lane];
+                    SrcF f;
+                    const double qx = s.yx - ox, qy = s.yy - oy, qz = s.yz - oz;
+                    f.yx = (float)qx;
+                    f.yy = (float)qy;
+                    f.yz = (float)qz;
+                    f.lx = (float)(qx - (double)f.yx);
+                    f.ly = (float)(qy - (double)f.yy);
+                    f.lz = (float)(qz - (double)f.yz);
+                    f.s2 = (float)s.s2;
+                    f.ax = (float)s.ax;
+                    f.ay = (float)s.ay;
+                    f.az = (float)s.az;
+                    f.s2x2 = (float)s.s2x2;
+                    f.pad = 0.0f;
+                    sh[lane] = f;
+                }
+                __syncthreads();
+                for (int j0 = 0; j0 < cnt; j0 += 32) {
+                    float p = 0, gx = 0, gy = 0, gz = 0;
+                    const int j1 = j0 + 32 < cnt ? j0 + 32 : cnt;
+#pragma unroll 4
+                    for (int j = j0; j < j1; ++j) pair32(sh[j], x, y, z, xl, yl, zl, p, gx, gy, gz);
+                    two_sum_f(sp, ep, p);
+                    two_sum_f(sx, ex, gx);
+                    two_sum_f(sy, ey, gy);
+                    two_sum_f(sz, ez, gz);
+                }
+            }
+        }
+        double ph = 0.0, g[3] = {0.0, 0.0, 0.0};
+        if (!outside) fmm_l2p(a, B, X, Y, Z, ph, g);
+        if (valid) {
+            const int64_t o = a.out_idx ? (int64_t)a.out_idx[ti] : ti;
+            a.phi[o] = ((double)sp + (double)ep) + ph;
+            if (a.grad) {
+                a.grad[3 * o] = ((double)sx + (double)ex) + g[0];
+                a.grad[3 * o + 1] = ((double)sy + (double)ey) + g[1];
+                a.grad[3 * o + 2] = ((double)sz + (double)ez) + g[2];
+            }
+        }
+        if (a.pairs) {
+            double w = wave_sum(valid ? npair : 0.0);
+            if ((lane & 63) == 0) atomicAdd(a.pairs, w);
+        }
+    }
+}
+
 template <int TILE>
 void launch_tile(Ctx &c, int64_t n, const int32_t *n_dev, const double *tx, const double *ty, const double *tz,
                  const int32_t *tmesh, const int32_t *out_idx, double *phi, double *grad) {
@@ -287,7 +467,59 @@ void launch_tile(Ctx &c, int64_t n, const int32_t *n_dev, const double *tx, cons
     LSS_CHECK_LAUNCH("k_p2p_direct");
 }
 
+template <int TILE>
+void launch_fmm_tile(Ctx &c, unsigned grid, const FmmEvalArgs &a) {
+    if (c.opt.precision == LSS_MIXED)
+        hipLaunchKernelGGL(k_eval_fmm_mixed<TILE>, dim3(grid), dim3(TILE), 0, c.stream, a);
+    else
+        hipLaunchKernelGGL(k_eval_fmm_f64<TILE>, dim3(grid), dim3(TILE), 0, c.stream, a);
+    LSS_CHECK_LAUNCH("k_eval_fmm");
+}
+
 }  // namespace
+
+int fmm_tile(const Ctx &c) { return c.opt.tile == 64 ? 64 : (c.opt.tile == 128 ? 128 : 256); }
+
+void launch_eval_fmm(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const int32_t *tile_start,
+                     const int32_t *n_dev, int64_t n_max, const uint64_t *sorted_keys, const int32_t *sorted_idx,
+                     const double *tx, const double *ty, const double *tz, const int32_t *out_idx, double *phi,
+                     double *grad) {
+    const Tree &t = c.tree;
+    FmmEvalArgs a;
+    a.ntiles_dev = ntiles_dev;
+    a.tile_start = tile_start;
+    a.n_max = n_max;
+    a.n_dev = n_dev;
+    a.skey = sorted_keys;
+    a.sidx = sorted_idx;
+    a.tx = tx; a.ty = ty; a.tz = tz;
+    a.out_idx = out_idx;
+    a.phi = phi;
+    a.grad = grad;
+    a.p2p_beg = t.p2p_beg.as<int32_t>();
+    a.p2p_end = t.p2p_end.as<int32_t>();
+    a.p2p_src = t.p2p_val2.as<int32_t>();
+    a.nb = t.nb.as<int64_t>();
+    a.ne = t.ne.as<int64_t>();
+    a.lev = t.level.as<int32_t>();
+    a.ijk = t.ijk.as<int32_t>();
+    a.src = t.src.as<Src>();
+    a.nnodes = c.nnodes;
+    a.nboxes = (int32_t)t.nboxes;
+    a.L = t.L.as<double>();
+    a.p = t.p;
+    a.ncp = t.ncp;
+    a.o0 = t.origin[0]; a.o1 = t.origin[1]; a.o2 = t.origin[2];
+    a.L0 = t.L0;
+    a.pairs = c.pairs.as<double>();
+    int64_t g = max_tiles < 16384 ? max_tiles : 16384;
+    unsigned grid = (unsigned)(g > 0 ? g : 1);
+    switch (fmm_tile(c)) {
+        case 64: launch_fmm_tile<64>(c, grid, a); break;
+        case 128: launch_fmm_tile<128>(c, grid, a); break;
+        default: launch_fmm_tile<256>(c, grid, a); break;
+    }
+}
 
 void launch_p2p_direct(Ctx &c, int64_t n, const int32_t *n_dev, const double *tx, const double *ty,
                        const double *tz, const int32_t *tmesh, const int32_t *out_idx, double *phi,

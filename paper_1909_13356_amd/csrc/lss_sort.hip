@@ -24,4 +24,12 @@ void sort_pairs_u64(void *tmp, size_t tmp_bytes, const uint64_t *kin, uint64_t *
                                       (unsigned)end_bit, s));
 }
 
+void sort_pairs(Ctx &c, const uint64_t *kin, uint64_t *kout, const int32_t *vin, int32_t *vout, int64_t n,
+                int end_bit) {
+    if (n <= 0) return;
+    size_t tb = sort_pairs_u64_tmp_bytes(n);
+    c.sort_tmp.ensure(tb);
+    sort_pairs_u64(c.sort_tmp.p, tb, kin, kout, vin, vout, n, 0, end_bit, c.stream);
+}
+
 }  // namespace lss
