@@ -181,8 +181,13 @@ __global__ void k_dtt_count(int64_t n, const uint64_t *__restrict__ fr, DttArgs 
     int act = dtt_action(a, T, S, cls);
     if (act == A_M2L) atomicAdd(&cnt[1], 1ull);
     else if (act == A_P2P) atomicAdd(&cnt[2], 1ull);
-    else if (act == A_SPLIT_BOTH) atomicAdd(&cnt[0], 64ull);
-    else if (act == A_SPLIT_T) atomicAdd(&cnt[0], 8ull);
+    else if (act == A_SPLIT_BOTH) {
+        // only source children that hold nodes are paired
+        const int32_t s0 = a.child[S];
+        unsigned long long ns = 0;
+        for (int v = 0; v < 8; ++v) ns += a.ne[s0 + v] > a.nb[s0 + v] ? 1ull : 0ull;
+        atomicAdd(&cnt[0], 8ull * ns);
+    } else if (act == A_SPLIT_T) atomicAdd(&cnt[0], 8ull);
 }
 
 __global__ void k_dtt_emit(int64_t n, const uint64_t *__restrict__ fr, DttArgs a, unsigned long long *cnt,
@@ -202,10 +207,14 @@ __global__ void k_dtt_emit(int64_t n, const uint64_t *__restrict__ fr, DttArgs a
         p2p_key[q] = ((uint64_t)(uint32_t)T << 32) | (uint32_t)S;
         p2p_val[q] = S;
     } else if (act == A_SPLIT_BOTH) {
-        int64_t q = (int64_t)atomicAdd(&cnt[3], 64ull);
-        int32_t t0 = a.child[T], s0 = a.child[S];
+        const int32_t t0 = a.child[T], s0 = a.child[S];
+        int32_t sl[8];
+        int ns = 0;
+        for (int v = 0; v < 8; ++v)
+            if (a.ne[s0 + v] > a.nb[s0 + v]) sl[ns++] = s0 + v;
+        int64_t q = (int64_t)atomicAdd(&cnt[3], 8ull * (unsigned long long)ns);
         for (int u = 0; u < 8; ++u)
-            for (int v = 0; v < 8; ++v) next[q + 8 * u + v] = ((uint64_t)(uint32_t)(t0 + u) << 32) | (uint32_t)(s0 + v);
+            for (int v = 0; v < ns; ++v) next[q + ns * u + v] = ((uint64_t)(uint32_t)(t0 + u) << 32) | (uint32_t)sl[v];
     } else if (act == A_SPLIT_T) {
         int64_t q = (int64_t)atomicAdd(&cnt[3], 8ull);
         int32_t t0 = a.child[T];
