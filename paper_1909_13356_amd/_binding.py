@@ -37,7 +37,7 @@ class Options(ctypes.Structure):
                 ("fmm_order", ctypes.c_int32), ("leaf_capacity", ctypes.c_int32),
                 ("cut_factor", ctypes.c_double), ("newton_tau", ctypes.c_double),
                 ("newton_max_iter", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("leaf_shrink", ctypes.c_double), ("reserved", ctypes.c_int32 * 6)]
 
 
 class Stats(ctypes.Structure):
@@ -178,9 +178,9 @@ class Context:
         self._check(self._lib.lss_set_sigma(self._h, ps, len(sigma), fs))
 
     def set_options(self, precision=FP64, far_field=FAR_DIRECT, fmm_order=0, leaf_capacity=0,
-                    cut_factor=0.0, newton_tau=0.0, newton_max_iter=0, tile=0):
+                    cut_factor=0.0, newton_tau=0.0, newton_max_iter=0, tile=0, leaf_shrink=0.0):
         o = Options(precision, far_field, fmm_order, leaf_capacity, cut_factor, newton_tau,
-                    newton_max_iter, tile)
+                    newton_max_iter, tile, leaf_shrink)
         self._check(self._lib.lss_set_options(self._h, ctypes.byref(o)))
 
     def get_options(self):

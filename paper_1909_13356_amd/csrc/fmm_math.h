@@ -173,39 +173,43 @@ LSS_HD void p2m_dipole(double rx, double ry, double rz, double ax, double ay, do
 
 // L2P: Phi and grad Phi of a local expansion at scaled position (rx,ry,rz)
 // (in units of the box side s); grad is returned in physical units (divided by s).
+// L is the real layout (any memory; on the device the caller stages it in LDS).
+//   Phi          = sum_{j, m>=0} w_m Re(L_j^m U_j^m)                  (w_0 = 1, w_m = 2)
+//   dPhi/dz      = sum_{j, m>=0} w_m Re(L_{j+1}^m U_j^m)
+//   (dx + i dy)Phi = sum_{j, s} L_{j+1}^{s-1} U_j^s
+//                 = sum_{j, m>=0} L_{j+1}^{m-1} U_j^m - [m > 0] conj(L_{j+1}^{m+1} U_j^m)
 LSS_HD void l2p(const double *L, double rx, double ry, double rz, double inv_s, int p, double &phi, double g[3]) {
     const double r2 = rx * rx + ry * ry + rz * rz;
     double ph = 0.0, gz = 0.0, Are = 0.0, Aim = 0.0;
     cd diag = {1.0, 0.0};
-    auto Lget = [&](int n, int m) -> cd {
-        if (n > p || m > n || m < -n) return cd{0.0, 0.0};
-        int am = m < 0 ? -m : m;
-        cd v = {L[ire(n, am)], am == 0 ? 0.0 : L[iim(n, am)]};
-        if (m < 0) { v = cconj(v); if (am & 1) v = cscale(v, -1.0); }
-        return v;
-    };
     for (int m = 0; m <= p; ++m) {
-        if (m > 0) diag = cscale(cmul(diag, cd{rx, ry}), -1.0 / (2.0 * m));
+        if (m > 0) diag = cscale(cmul(diag, cd{rx, ry}), -0.5 / (double)m);
+        const double w = m == 0 ? 1.0 : 2.0;
         cd um2 = {0.0, 0.0}, u = diag;
         for (int j = m; j <= p; ++j) {
             if (j > m) {
-                const double inv = 1.0 / ((double)(j + m) * (double)(j - m));
+                const double den = (double)((j + m) * (j - m));
+                const double inv = 1.0 / den;
                 cd un = {((2 * j - 1) * rz * u.re - r2 * um2.re) * inv, ((2 * j - 1) * rz * u.im - r2 * um2.im) * inv};
                 um2 = u;
                 u = un;
             }
-            const double w = m == 0 ? 1.0 : 2.0;
-            cd Ljm = Lget(j, m);
-            ph += w * (Ljm.re * u.re - Ljm.im * u.im);
-            cd Lz = Lget(j + 1, m);
-            gz += w * (Lz.re * u.re - Lz.im * u.im);
-            cd a1 = cmul(Lget(j + 1, m - 1), u);     // s = m term of (dx + i dy)
-            Are += a1.re;
-            Aim += a1.im;
-            if (m > 0) {                              // s = -m term: -conj(L_{j+1}^{m+1} U_j^m)
-                cd a2 = cmul(Lget(j + 1, m + 1), u);
-                Are -= a2.re;
-                Aim += a2.im;
+            const double Lre = L[ire(j, m)], Lim = m ? L[iim(j, m)] : 0.0;
+            ph += w * (Lre * u.re - Lim * u.im);
+            if (j < p) {
+                const int j1 = j + 1;
+                const double zre = L[ire(j1, m)], zim = m ? L[iim(j1, m)] : 0.0;
+                gz += w * (zre * u.re - zim * u.im);
+                double are, aim;                       // L_{j+1}^{m-1}; L^{-1} = -conj(L^1)
+                if (m >= 1) { are = L[ire(j1, m - 1)]; aim = (m - 1) ? L[iim(j1, m - 1)] : 0.0; }
+                else { are = -L[ire(j1, 1)]; aim = L[iim(j1, 1)]; }
+                Are += are * u.re - aim * u.im;
+                Aim += are * u.im + aim * u.re;
+                if (m > 0) {                           // - conj(L_{j+1}^{m+1} U_j^m)
+                    const double bre = L[ire(j1, m + 1)], bim = L[iim(j1, m + 1)];
+                    Are -= bre * u.re - bim * u.im;
+                    Aim += bre * u.im + bim * u.re;
+                }
             }
         }
     }

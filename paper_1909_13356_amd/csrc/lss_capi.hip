@@ -71,7 +71,9 @@ void validate_options(const lss_options &o) {
     if (!(o.newton_tau >= 0.0) || !std::isfinite(o.newton_tau)) fail(LSS_EINVAL, "newton_tau must be >= 0");
     if (o.newton_max_iter < 0 || o.newton_max_iter > 120) fail(LSS_EINVAL, "newton_max_iter must be in [0, 120]");
     if (o.tile != 0 && o.tile != 64 && o.tile != 128 && o.tile != 256) fail(LSS_EINVAL, "tile must be 0, 64, 128 or 256");
-    for (int k = 0; k < 8; ++k)
+    if (!(o.leaf_shrink == 0.0 || (o.leaf_shrink >= 1.0 && o.leaf_shrink <= 3.0)))
+        fail(LSS_EINVAL, "leaf_shrink must be 0 (default) or in [1, 3]");
+    for (int k = 0; k < 6; ++k)
         if (o.reserved[k] != 0) fail(LSS_EINVAL, "reserved option fields must be zero");
 }
 
@@ -113,11 +115,13 @@ void eval_fmm_targets(Ctx &c, int64_t n, const int32_t *n_dev, double *phi, doub
                           c.tperm.as<int32_t>());
     sort_pairs(c, c.tkey.as<uint64_t>(), c.tkey2.as<uint64_t>(), c.tperm.as<int32_t>(), c.tperm2.as<int32_t>(), n, 64);
     c.tstart.ensure(sizeof(int32_t) * (n + 1));
+    c.tleaf.ensure(sizeof(int32_t) * (n + 1));
     c.ntiles.ensure(16);
-    build_tiles(c, n, n_dev, c.tkey2.as<uint64_t>(), fmm_tile(c), c.tstart.as<int32_t>(), c.ntiles.as<int32_t>());
+    build_tiles(c, n, n_dev, c.tkey2.as<uint64_t>(), fmm_tile(c), c.tleaf.as<int32_t>(), c.tstart.as<int32_t>(),
+                c.ntiles.as<int32_t>());
     if (reset_pairs) LSS_HIP(hipMemsetAsync(c.pairs.p, 0, sizeof(double), c.stream));
     c.ev_begin();
-    launch_eval_fmm(c, n, c.ntiles.as<int32_t>(), c.tstart.as<int32_t>(), n_dev, n, c.tkey2.as<uint64_t>(),
+    launch_eval_fmm(c, n, c.ntiles.as<int32_t>(), c.tstart.as<int32_t>(), n_dev, n, c.tleaf.as<int32_t>(),
                     c.tperm2.as<int32_t>(), c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(), nullptr, phi, grad);
     c.ev_end();
 }
@@ -310,6 +314,7 @@ void lss_destroy(lss_ctx *ctx) {
     (void)hipStreamSynchronize(c.stream);
     DBuf *bufs[] = {&c.verts, &c.tris, &c.tri_off, &c.node_off, &c.rule, &c.sigma, &c.src, &c.vH, &c.tkey,
                     &c.tkey2, &c.tperm, &c.tperm2, &c.tx, &c.ty, &c.tz, &c.tmesh, &c.sort_tmp, &c.pairs,
+                    &c.tflag, &c.tpos, &c.tstart, &c.ntiles, &c.tleaf,
                     &c.ns.T, &c.ns.H, &c.ns.h, &c.ns.lo, &c.ns.hi, &c.ns.sig, &c.ns.mesh, &c.ns.orig,
                     &c.ns.status, &c.ns.iters, &c.ns.active, &c.ns.active2, &c.ns.flag, &c.ns.blocksum,
                     &c.ns.nact};
@@ -429,7 +434,8 @@ int lss_set_options(lss_ctx *ctx, const lss_options *opt) {
         if (opt) o = *opt;
         lss::validate_options(o);
         if (o.precision != c.opt.precision || o.far_field != c.opt.far_field || o.fmm_order != c.opt.fmm_order ||
-            o.leaf_capacity != c.opt.leaf_capacity || o.cut_factor != c.opt.cut_factor)
+            o.leaf_capacity != c.opt.leaf_capacity || o.cut_factor != c.opt.cut_factor ||
+            o.leaf_shrink != c.opt.leaf_shrink)
             c.built = false;
         c.opt = o;
     });

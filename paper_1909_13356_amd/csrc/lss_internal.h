@@ -162,7 +162,7 @@ struct Ctx {
 
     // --- per-eval scratch
     DBuf tkey, tkey2, tperm, tperm2, tx, ty, tz, tmesh, sort_tmp;
-    DBuf tflag, tpos, tstart, ntiles;   // FMM eval: tile heads over the leaf-sorted targets
+    DBuf tflag, tpos, tstart, ntiles, tleaf;   // FMM eval: leaf of each sorted target, tile heads
     DBuf pairs;               // double accumulator of executed pairs (stats)
     bool pairs_pending = false;   // counter not yet read back into stats.last_pairs
     NewtonState ns;
@@ -220,10 +220,10 @@ void build_fmm(Ctx &c);
 void launch_locate_targets(Ctx &c, int64_t n_max, const int32_t *n_dev, const double *tx, const double *ty,
                            const double *tz, uint64_t *keys, int32_t *idx);
 int64_t build_tiles(Ctx &c, int64_t n_max, const int32_t *n_dev, const uint64_t *sorted_keys, int tile,
-                    int32_t *tile_start, int32_t *ntiles_dev);
+                    int32_t *sorted_leaf, int32_t *tile_start, int32_t *ntiles_dev);
 int fmm_tile(const Ctx &c);
 void launch_eval_fmm(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const int32_t *tile_start,
-                     const int32_t *n_dev, int64_t n_max, const uint64_t *sorted_keys, const int32_t *sorted_idx,
+                     const int32_t *n_dev, int64_t n_max, const int32_t *sorted_leaf, const int32_t *sorted_idx,
                      const double *tx, const double *ty, const double *tz, const int32_t *out_idx, double *phi,
                      double *grad);
 void launch_soa(Ctx &c, const double *x, int64_t n, double *tx, double *ty, double *tz);

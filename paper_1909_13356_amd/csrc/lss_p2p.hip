@@ -285,7 +285,7 @@ struct FmmEvalArgs {
     const int32_t *ntiles_dev, *tile_start;
     int64_t n_max;
     const int32_t *n_dev;
-    const uint64_t *skey;
+    const int32_t *sleaf;       // leaf of each sorted target (nboxes: outside the root)
     const int32_t *sidx;
     const double *tx, *ty, *tz;
     const int32_t *out_idx;
@@ -302,50 +302,104 @@ struct FmmEvalArgs {
     double *pairs;
 };
 
-__device__ __forceinline__ void fmm_range(const FmmEvalArgs &a, int e, bool outside, int64_t &lo, int64_t &hi) {
-    if (outside) { lo = 0; hi = a.nnodes; }
-    else {
-        const int32_t S = a.p2p_src[e];
-        lo = a.nb[S];
-        hi = a.ne[S];
+// The near list of a tile (its leaf's source boxes, or every node outside the
+// root cube) is streamed as one packed sequence: up to TILE ranges at a time
+// are prefix-summed in LDS and each chunk of TILE nodes is filled across range
+// boundaries, so no chunk is left partly empty at the end of a small box.
+template <int TILE>
+struct RangeBatch {
+    int64_t beg[TILE];
+    int64_t off[TILE + 1];
+};
+
+// load ranges [e, e + nr) of the leaf (or the single outside range) and
+// prefix-sum their lengths; returns the packed length (uniform)
+template <int TILE>
+__device__ __forceinline__ int64_t load_ranges(const FmmEvalArgs &a, RangeBatch<TILE> &rb, int e, int nr,
+                                               bool outside) {
+    const int t = threadIdx.x;
+    int64_t len = 0;
+    if (t < nr) {
+        int64_t lo, hi;
+        if (outside) { lo = 0; hi = a.nnodes; }
+        else {
+            const int32_t S = a.p2p_src[e + t];
+            lo = a.nb[S];
+            hi = a.ne[S];
+        }
+        rb.beg[t] = lo;
+        len = hi - lo;
     }
+    rb.off[t + 1] = len;
+    if (t == 0) rb.off[0] = 0;
+    __syncthreads();
+    for (int d = 1; d < TILE; d <<= 1) {      // inclusive scan of off[1..TILE]
+        int64_t v = (t >= d) ? rb.off[t + 1 - d] : 0;
+        __syncthreads();
+        rb.off[t + 1] += v;
+        __syncthreads();
+    }
+    return rb.off[nr];
 }
 
-__device__ __forceinline__ void fmm_l2p(const FmmEvalArgs &a, int32_t B, double x, double y, double z, double &ph,
-                                        double g[3]) {
+// node index of packed position v (v < total)
+template <int TILE>
+__device__ __forceinline__ int64_t packed_node(const RangeBatch<TILE> &rb, int nr, int64_t v) {
+    int lo = 0, hi = nr;                       // last r with off[r] <= v
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (rb.off[mid] <= v) lo = mid; else hi = mid;
+    }
+    return rb.beg[lo] + (v - rb.off[lo]);
+}
+
+// local expansion of leaf B staged in LDS by the whole workgroup (the caller
+// synchronises before use)
+__device__ __forceinline__ void stage_local(const FmmEvalArgs &a, int32_t B, double *Ls) {
+    const double *src = a.L + (int64_t)B * a.ncp;
+    for (int k = threadIdx.x; k < a.ncp; k += blockDim.x) Ls[k] = src[k];
+}
+
+__device__ __forceinline__ void fmm_l2p(const FmmEvalArgs &a, int32_t B, const double *Ls, double x, double y,
+                                        double z, double &ph, double g[3]) {
     const double s = ldexp(a.L0, -a.lev[B]);
     const double cx = a.o0 + (a.ijk[3 * B] + 0.5) * s, cy = a.o1 + (a.ijk[3 * B + 1] + 0.5) * s,
                  cz = a.o2 + (a.ijk[3 * B + 2] + 0.5) * s;
     const double inv = 1.0 / s;
-    fmm::l2p(a.L + (int64_t)B * a.ncp, (x - cx) * inv, (y - cy) * inv, (z - cz) * inv, inv, a.p, ph, g);
+    fmm::l2p(Ls, (x - cx) * inv, (y - cy) * inv, (z - cz) * inv, inv, a.p, ph, g);
 }
 
 template <int TILE>
 __global__ __launch_bounds__(TILE) void k_eval_fmm_f64(FmmEvalArgs a) {
     __shared__ Src sh[TILE];
+    __shared__ RangeBatch<TILE> rb;
+    extern __shared__ double Ls[];      // local expansion of the tile's leaf (ncp doubles)
     const int ntiles = *a.ntiles_dev;
     const int64_t n = a.n_dev ? (int64_t)*a.n_dev : a.n_max;
     const int lane = threadIdx.x;
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t s0 = a.tile_start[tile];
-        const uint64_t leafk = a.skey[s0];
+        const int32_t leafk = a.sleaf[s0];
         const int64_t sp_ = s0 + lane;
-        const bool valid = sp_ < n && a.skey[sp_] == leafk;
+        const bool valid = sp_ < n && a.sleaf[sp_] == leafk;
         const int64_t ti = a.sidx[valid ? sp_ : s0];
         const double x = a.tx[ti], y = a.ty[ti], z = a.tz[ti];
-        const int32_t B = (int32_t)leafk;
+        const int32_t B = leafk;
         const bool outside = B >= a.nboxes;
         const int e0 = outside ? 0 : a.p2p_beg[B], e1 = outside ? 1 : a.p2p_end[B];
+        __syncthreads();                    // previous tile is done with Ls
+        if (!outside) stage_local(a, B, Ls);
         double sp = 0, ep = 0, sx = 0, ex = 0, sy = 0, ey = 0, sz = 0, ez = 0;
         double npair = 0.0;
-        for (int e = e0; e < e1; ++e) {
-            int64_t lo, hi;
-            fmm_range(a, e, outside, lo, hi);
-            npair += (double)(hi - lo);
-            for (int64_t c0 = lo; c0 < hi; c0 += TILE) {
-                const int cnt = (int)(hi - c0 < TILE ? hi - c0 : TILE);
+        for (int eb = e0; eb < e1; eb += TILE) {
+            const int nr = e1 - eb < TILE ? e1 - eb : TILE;
+            __syncthreads();
+            const int64_t total = load_ranges<TILE>(a, rb, eb, nr, outside);
+            npair += (double)total;
+            for (int64_t c0 = 0; c0 < total; c0 += TILE) {
+                const int cnt = (int)(total - c0 < TILE ? total - c0 : TILE);
                 __syncthreads();
-                if (lane < cnt) sh[lane] = a.src[c0 + lane];
+                if (lane < cnt) sh[lane] = a.src[packed_node<TILE>(rb, nr, c0 + lane)];
                 __syncthreads();
                 double p = 0, gx = 0, gy = 0, gz = 0;
 #pragma unroll 2
@@ -357,7 +411,8 @@ __global__ __launch_bounds__(TILE) void k_eval_fmm_f64(FmmEvalArgs a) {
             }
         }
         double ph = 0.0, g[3] = {0.0, 0.0, 0.0};
-        if (!outside) fmm_l2p(a, B, x, y, z, ph, g);
+        __syncthreads();                    // Ls staged
+        if (!outside) fmm_l2p(a, B, Ls, x, y, z, ph, g);
         if (valid) {
             const int64_t o = a.out_idx ? (int64_t)a.out_idx[ti] : ti;
             a.phi[o] = (sp + ph) + ep;
@@ -377,14 +432,16 @@ __global__ __launch_bounds__(TILE) void k_eval_fmm_f64(FmmEvalArgs a) {
 template <int TILE>
 __global__ __launch_bounds__(TILE) void k_eval_fmm_mixed(FmmEvalArgs a) {
     __shared__ SrcF sh[TILE];
+    __shared__ RangeBatch<TILE> rb;
+    extern __shared__ double Ls[];      // local expansion of the tile's leaf (ncp doubles)
     const int ntiles = *a.ntiles_dev;
     const int64_t n = a.n_dev ? (int64_t)*a.n_dev : a.n_max;
     const int lane = threadIdx.x;
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t s0 = a.tile_start[tile];
-        const uint64_t leafk = a.skey[s0];
+        const int32_t leafk = a.sleaf[s0];
         const int64_t sp_ = s0 + lane;
-        const bool valid = sp_ < n && a.skey[sp_] == leafk;
+        const bool valid = sp_ < n && a.sleaf[sp_] == leafk;
         const int64_t ti = a.sidx[valid ? sp_ : s0];
         const int64_t t0 = a.sidx[s0];
         const double ox = a.tx[t0], oy = a.ty[t0], oz = a.tz[t0];
@@ -392,20 +449,23 @@ __global__ __launch_bounds__(TILE) void k_eval_fmm_mixed(FmmEvalArgs a) {
         const double dxo = X - ox, dyo = Y - oy, dzo = Z - oz;
         const float x = (float)dxo, y = (float)dyo, z = (float)dzo;
         const float xl = (float)(dxo - (double)x), yl = (float)(dyo - (double)y), zl = (float)(dzo - (double)z);
-        const int32_t B = (int32_t)leafk;
+        const int32_t B = leafk;
         const bool outside = B >= a.nboxes;
         const int e0 = outside ? 0 : a.p2p_beg[B], e1 = outside ? 1 : a.p2p_end[B];
+        __syncthreads();                    // previous tile is done with Ls
+        if (!outside) stage_local(a, B, Ls);
         float sp = 0, ep = 0, sx = 0, ex = 0, sy = 0, ey = 0, sz = 0, ez = 0;
         double npair = 0.0;
-        for (int e = e0; e < e1; ++e) {
-            int64_t lo, hi;
-            fmm_range(a, e, outside, lo, hi);
-            npair += (double)(hi - lo);
-            for (int64_t c0 = lo; c0 < hi; c0 += TILE) {
-                const int cnt = (int)(hi - c0 < TILE ? hi - c0 : TILE);
+        for (int eb = e0; eb < e1; eb += TILE) {
+            const int nr = e1 - eb < TILE ? e1 - eb : TILE;
+            __syncthreads();
+            const int64_t total = load_ranges<TILE>(a, rb, eb, nr, outside);
+            npair += (double)total;
+            for (int64_t c0 = 0; c0 < total; c0 += TILE) {
+                const int cnt = (int)(total - c0 < TILE ? total - c0 : TILE);
                 __syncthreads();
                 if (lane < cnt) {
-                    const Src s = a.src[c0 + lane];
+                    const Src s = a.src[packed_node<TILE>(rb, nr, c0 + lane)];
                     SrcF f;
                     const double qx = s.yx - ox, qy = s.yy - oy, qz = s.yz - oz;
                     f.yx = (float)qx;
@@ -436,7 +496,8 @@ __global__ __launch_bounds__(TILE) void k_eval_fmm_mixed(FmmEvalArgs a) {
             }
         }
         double ph = 0.0, g[3] = {0.0, 0.0, 0.0};
-        if (!outside) fmm_l2p(a, B, X, Y, Z, ph, g);
+        __syncthreads();                    // Ls staged
+        if (!outside) fmm_l2p(a, B, Ls, X, Y, Z, ph, g);
         if (valid) {
             const int64_t o = a.out_idx ? (int64_t)a.out_idx[ti] : ti;
             a.phi[o] = ((double)sp + (double)ep) + ph;
@@ -469,19 +530,24 @@ void launch_tile(Ctx &c, int64_t n, const int32_t *n_dev, const double *tx, cons
 
 template <int TILE>
 void launch_fmm_tile(Ctx &c, unsigned grid, const FmmEvalArgs &a) {
+    const size_t shm = sizeof(double) * (size_t)a.ncp;
     if (c.opt.precision == LSS_MIXED)
-        hipLaunchKernelGGL(k_eval_fmm_mixed<TILE>, dim3(grid), dim3(TILE), 0, c.stream, a);
+        hipLaunchKernelGGL(k_eval_fmm_mixed<TILE>, dim3(grid), dim3(TILE), shm, c.stream, a);
     else
-        hipLaunchKernelGGL(k_eval_fmm_f64<TILE>, dim3(grid), dim3(TILE), 0, c.stream, a);
+        hipLaunchKernelGGL(k_eval_fmm_f64<TILE>, dim3(grid), dim3(TILE), shm, c.stream, a);
     LSS_CHECK_LAUNCH("k_eval_fmm");
 }
 
 }  // namespace
 
-int fmm_tile(const Ctx &c) { return c.opt.tile == 64 ? 64 : (c.opt.tile == 128 ? 128 : 256); }
+// FMM tiles: 0 = default (64 FP64, 128 mixed: narrow tiles keep small leaves full)
+int fmm_tile(const Ctx &c) {
+    if (c.opt.tile == 64 || c.opt.tile == 128 || c.opt.tile == 256) return c.opt.tile;
+    return c.opt.precision == LSS_MIXED ? 128 : 64;
+}
 
 void launch_eval_fmm(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const int32_t *tile_start,
-                     const int32_t *n_dev, int64_t n_max, const uint64_t *sorted_keys, const int32_t *sorted_idx,
+                     const int32_t *n_dev, int64_t n_max, const int32_t *sorted_leaf, const int32_t *sorted_idx,
                      const double *tx, const double *ty, const double *tz, const int32_t *out_idx, double *phi,
                      double *grad) {
     const Tree &t = c.tree;
@@ -490,7 +556,7 @@ void launch_eval_fmm(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const
     a.tile_start = tile_start;
     a.n_max = n_max;
     a.n_dev = n_dev;
-    a.skey = sorted_keys;
+    a.sleaf = sorted_leaf;
     a.sidx = sorted_idx;
     a.tx = tx; a.ty = ty; a.tz = tz;
     a.out_idx = out_idx;

@@ -5,14 +5,13 @@
 //
 // Tree: the root cube holds every node (padded by 2 R_max); a box is split in
 // eight when it holds more than `leaf_capacity` nodes and its children would
-// still be at least as large as the largest near radius R_k of its nodes, so
-// every leaf is at least as wide as the near radius of its own nodes.  All
-// eight children are kept (empty ones too), so the leaves partition the root
-// cube and any target position has a leaf.
+// still be at least 1/shrink as wide as the largest near radius R_k of its
+// nodes.  All eight children are kept (empty ones too), so the leaves
+// partition the root cube and any target position has a leaf.
 //
 // Lists: one dual-tree traversal over (target box T, source box S) pairs:
-//   same level and admissible (|d|_inf >= 2 and |d|^2 >= K, d = integer
-//   offset of the boxes)  -> M2L(S -> T);  box separation >= side >= R_max(S)
+//   same level and admissible (|d|_inf >= 2, |d|^2 >= K, d = integer offset
+//   of the boxes, and box gap >= R_max(S))  -> M2L(S -> T)
 //   otherwise: T leaf -> direct pairs with all nodes of S;  else split the
 //   non-leaf box(es) and continue.
 // Every (target leaf, node) pair is covered exactly once, by a direct pair or
@@ -73,14 +72,21 @@ __global__ void k_permute_src(int64_t n, const Src *__restrict__ in, const int32
     if (k < n) out[k] = in[perm[k]];
 }
 
-// largest near radius cut * sigma_k over the nodes of each box of a level
+// largest near radius cut * sigma_k over the nodes of each box of a level:
+// block (i, g) reduces chunk g (kRmaxChunk nodes) of box lb + i and folds it
+// with an atomic max on the bits of the (positive) double
+constexpr int64_t kRmaxChunk = 8192;
+
 __global__ void k_box_rmax(int64_t lb, const int64_t *__restrict__ nb, const int64_t *__restrict__ ne,
-                           const Src *__restrict__ src, double cut, double *rmax) {
+                           const Src *__restrict__ src, double cut, unsigned long long *rmax_bits) {
     __shared__ double sh[kBlk];
-    int64_t b = lb + blockIdx.x;
+    const int64_t b = lb + blockIdx.x;
+    const int64_t k0 = nb[b] + (int64_t)blockIdx.y * kRmaxChunk;
+    const int64_t k1 = min(ne[b], k0 + kRmaxChunk);
+    if (k0 >= k1) return;
     double m = 0.0;
-    for (int64_t k = nb[b] + threadIdx.x; k < ne[b]; k += kBlk) {
-        double s2 = src[k].s2;                   // sigma = sqrt(1 / (2 s2))
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += kBlk) {
+        const double s2 = src[k].s2;                   // sigma = sqrt(1 / (2 s2))
         m = fmax(m, cut * sqrt(0.5 / s2));
     }
     sh[threadIdx.x] = m;
@@ -89,10 +95,10 @@ __global__ void k_box_rmax(int64_t lb, const int64_t *__restrict__ nb, const int
         if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) rmax[b] = sh[0];
+    if (threadIdx.x == 0) atomicMax(&rmax_bits[b], (unsigned long long)__double_as_longlong(sh[0]));
 }
 
-__global__ void k_split_flags(int64_t lb, int64_t nlev, int level, double L0, int64_t cap,
+__global__ void k_split_flags(int64_t lb, int64_t nlev, int level, double L0, int64_t cap, double shrink,
                               const int64_t *__restrict__ nb, const int64_t *__restrict__ ne,
                               const double *__restrict__ rmax, int32_t *flag, int32_t *ids) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -100,7 +106,7 @@ __global__ void k_split_flags(int64_t lb, int64_t nlev, int level, double L0, in
     int64_t b = lb + i;
     double half = ldexp(L0, -(level + 1));      // side of the children
     int64_t cnt = ne[b] - nb[b];
-    flag[i] = (cnt > cap && half >= rmax[b] && level < kMaxLevel) ? 1 : 0;
+    flag[i] = (cnt > cap && half * shrink >= rmax[b] && level < kMaxLevel) ? 1 : 0;
     ids[i] = (int32_t)b;
 }
 
@@ -114,7 +120,8 @@ __device__ inline int64_t lower_bound_key(const uint64_t *keys, int64_t lo, int6
 
 __global__ void k_make_children(const int32_t *__restrict__ nsplit_dev, const int32_t *__restrict__ split,
                                 int64_t child_base, int level, const uint64_t *__restrict__ keys, int32_t *lev,
-                                int32_t *ijk, int64_t *nb, int64_t *ne, int32_t *child, int32_t *parent) {
+                                int32_t *ijk, int64_t *nb, int64_t *ne, int32_t *child, int32_t *parent,
+                                unsigned long long *maxcnt) {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= *nsplit_dev) return;
     int32_t b = split[r];
@@ -137,6 +144,7 @@ __global__ void k_make_children(const int32_t *__restrict__ nsplit_dev, const in
         ne[q] = bound[c + 1];
         child[q] = -1;
         parent[q] = b;
+        atomicMax(maxcnt, (unsigned long long)(bound[c + 1] - bound[c]));
     }
 }
 
@@ -144,6 +152,8 @@ __global__ void k_make_children(const int32_t *__restrict__ nsplit_dev, const in
 struct DttArgs {
     const int32_t *lev, *ijk, *child;
     const int64_t *nb, *ne;
+    const double *rmax;
+    double L0;
     int K;
 };
 
@@ -160,7 +170,9 @@ __device__ inline int dtt_action(const DttArgs &a, int32_t T, int32_t S, int &cl
     if (lT == lS) {
         int dx = a.ijk[3 * T] - a.ijk[3 * S], dy = a.ijk[3 * T + 1] - a.ijk[3 * S + 1], dz = a.ijk[3 * T + 2] - a.ijk[3 * S + 2];
         int m = max(abs(dx), max(abs(dy), abs(dz)));
-        if (m >= 2 && dx * dx + dy * dy + dz * dz >= a.K && m <= kR) {
+        // admissible: K-criterion and a gap of at least the cut radius of S's nodes
+        if (m >= 2 && dx * dx + dy * dy + dz * dz >= a.K && m <= kR &&
+            (double)(m - 1) * ldexp(a.L0, -lT) >= a.rmax[S]) {
             cls = ((dx + kR) * (2 * kR + 1) + (dy + kR)) * (2 * kR + 1) + (dz + kR);
             return A_M2L;
         }
@@ -241,10 +253,14 @@ __global__ void k_class_ranges(int64_t n, const uint64_t *__restrict__ keys, int
 }
 
 // ----------------------------------------------------------- targets
-// leaf containing each target (sentinel nboxes outside the root cube)
+// Morton key of each target (bit 63 set outside the root cube); sorting by it
+// groups the targets of a leaf (a leaf is a Morton prefix range) and keeps
+// every wave of a tile spatially compact.
+constexpr uint64_t kOutside = 1ull << 63;
+
 __global__ void k_locate(int64_t n_max, const int32_t *__restrict__ n_dev, const double *__restrict__ tx,
                          const double *__restrict__ ty, const double *__restrict__ tz, Root r, double L0,
-                         const int32_t *__restrict__ child, int32_t nboxes, uint64_t *keys, int32_t *idx) {
+                         uint64_t *keys, int32_t *idx) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t n = n_dev ? (int64_t)*n_dev : n_max;
     if (i >= n_max) return;
@@ -254,37 +270,55 @@ __global__ void k_locate(int64_t n_max, const int32_t *__restrict__ n_dev, const
         return;
     }
     double q[3] = {(tx[i] - r.o[0]) / L0, (ty[i] - r.o[1]) / L0, (tz[i] - r.o[2]) / L0};
-    int32_t b = 0;
     bool inside = q[0] >= 0.0 && q[0] < 1.0 && q[1] >= 0.0 && q[1] < 1.0 && q[2] >= 0.0 && q[2] < 1.0;
-    if (!inside) b = nboxes;
-    else {
-        uint64_t k = key21(tx[i], ty[i], tz[i], r);
-        int lvl = 0;
-        while (child[b] >= 0) {
-            int oct = (int)((k >> (3 * (21 - (lvl + 1)))) & 7ull);
-            b = child[b] + oct;
-            ++lvl;
-        }
-    }
-    keys[i] = (uint64_t)(uint32_t)b;
+    keys[i] = inside ? key21(tx[i], ty[i], tz[i], r) : kOutside;
     idx[i] = (int32_t)i;
 }
 
-// tile heads: first target of a leaf segment and every TILE-th after it
-__global__ void k_tile_flags(int64_t n_max, const int32_t *__restrict__ n_dev, const uint64_t *__restrict__ keys,
-                             int tile, int32_t *flag, int32_t *pos) {
+// leaf of each sorted target (nboxes outside the root, -1 for unused slots)
+__global__ void k_sorted_leaf(int64_t n_max, const int32_t *__restrict__ n_dev, const uint64_t *__restrict__ keys,
+                              const int32_t *__restrict__ child, int32_t nboxes, int32_t *leaf) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t n = n_dev ? (int64_t)*n_dev : n_max;
     if (i >= n_max) return;
-    if (i >= n) { flag[i] = 0; pos[i] = (int32_t)i; return; }
-    uint64_t k = keys[i];
-    int64_t lo = 0, hi = i;           // first index with this key
+    if (i >= n) { leaf[i] = -1; return; }
+    const uint64_t k = keys[i];
+    if (k & kOutside) { leaf[i] = nboxes; return; }
+    int32_t b = 0;
+    int lvl = 0;
+    while (child[b] >= 0) {
+        int oct = (int)((k >> (3 * (21 - (lvl + 1)))) & 7ull);
+        b = child[b] + oct;
+        ++lvl;
+    }
+    leaf[i] = b;
+}
+
+// tile heads: first target of a leaf segment and every TILE-th after it.  The
+// segment of leaf b starts at the first key >= its Morton prefix.
+__global__ void k_tile_flags(int64_t n_max, const int32_t *__restrict__ n_dev, const uint64_t *__restrict__ keys,
+                             const int32_t *__restrict__ leaf, const int32_t *__restrict__ lev,
+                             const int32_t *__restrict__ ijk, int32_t nboxes, int tile, int32_t *flag, int32_t *pos) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t n = n_dev ? (int64_t)*n_dev : n_max;
+    if (i >= n_max) return;
+    pos[i] = (int32_t)i;
+    if (i >= n) { flag[i] = 0; return; }
+    const int32_t b = leaf[i];
+    uint64_t lo_key;
+    if (b >= nboxes) lo_key = kOutside;
+    else {
+        const int l = lev[b];
+        const uint64_t pre = spread21((uint64_t)ijk[3 * b]) | (spread21((uint64_t)ijk[3 * b + 1]) << 1) |
+                             (spread21((uint64_t)ijk[3 * b + 2]) << 2);
+        lo_key = pre << (3 * (21 - l));
+    }
+    int64_t lo = 0, hi = i;           // first index with key >= lo_key
     while (lo < hi) {
         int64_t mid = (lo + hi) >> 1;
-        if (keys[mid] < k) lo = mid + 1; else hi = mid;
+        if (keys[mid] < lo_key) lo = mid + 1; else hi = mid;
     }
     flag[i] = ((i - lo) % tile) == 0 ? 1 : 0;
-    pos[i] = (int32_t)i;
 }
 
 __global__ void k_soa(int64_t n, const double *__restrict__ x, double *tx, double *ty, double *tz) {
@@ -310,7 +344,8 @@ void build_tree(Ctx &c) {
     const int64_t n = c.nnodes;
     if (c.nmesh > 1) throw Error{LSS_EINVAL, "far_field = LSS_FAR_FMM supports one mesh per context"};
     const double cut = c.opt.cut_factor > 0 ? c.opt.cut_factor : (c.opt.precision == LSS_MIXED ? kCutMixed : kCutFP64);
-    const int64_t cap = c.opt.leaf_capacity > 0 ? c.opt.leaf_capacity : 256;
+    const int64_t cap = c.opt.leaf_capacity > 0 ? c.opt.leaf_capacity : (c.opt.precision == LSS_MIXED ? 256 : 128);
+    const double shrink = c.opt.leaf_shrink > 0 ? c.opt.leaf_shrink : (c.opt.precision == LSS_MIXED ? 1.0 : 2.0);
     t.K = c.opt.precision == LSS_MIXED ? 4 : 8;
     // root cube: node bounding box padded by 2 R_max on every side
     double rmax = cut * c.sigma_max, ext = 0.0;
@@ -360,13 +395,16 @@ void build_tree(Ctx &c) {
     }
     t.level_begin.assign({0, 1});
     DBuf flag, ids, split, nsplit;
+    int64_t maxcnt = n;                     // largest node count of a box of the current level
     for (int lvl = 0;; ++lvl) {
         int64_t lb = t.level_begin[lvl], le = t.level_begin[lvl + 1], nl = le - lb;
-        hipLaunchKernelGGL(k_box_rmax, dim3((unsigned)nl), dim3(kBlk), 0, c.stream, lb, t.nb.as<int64_t>(),
-                           t.ne.as<int64_t>(), t.src.as<Src>(), cut, t.rmax.as<double>());
+        LSS_HIP(hipMemsetAsync(t.rmax.as<double>() + lb, 0, sizeof(double) * nl, c.stream));
+        const unsigned gy = (unsigned)ceil_div(maxcnt > 0 ? maxcnt : 1, kRmaxChunk);
+        hipLaunchKernelGGL(k_box_rmax, dim3((unsigned)nl, gy), dim3(kBlk), 0, c.stream, lb, t.nb.as<int64_t>(),
+                           t.ne.as<int64_t>(), t.src.as<Src>(), cut, reinterpret_cast<unsigned long long *>(t.rmax.p));
         LSS_CHECK_LAUNCH("k_box_rmax");
         flag.ensure(4 * nl); ids.ensure(4 * nl); split.ensure(4 * nl); nsplit.ensure(16);
-        hipLaunchKernelGGL(k_split_flags, dim3(grid_for(nl)), dim3(kBlk), 0, c.stream, lb, nl, lvl, t.L0, cap,
+        hipLaunchKernelGGL(k_split_flags, dim3(grid_for(nl)), dim3(kBlk), 0, c.stream, lb, nl, lvl, t.L0, cap, shrink,
                            t.nb.as<int64_t>(), t.ne.as<int64_t>(), t.rmax.as<double>(), flag.as<int32_t>(),
                            ids.as<int32_t>());
         LSS_CHECK_LAUNCH("k_split_flags");
@@ -377,16 +415,22 @@ void build_tree(Ctx &c) {
         if (ns == 0) { t.depth = lvl; break; }
         int64_t child_base = le;
         grow(le + 8 * (int64_t)ns, le);
+        unsigned long long *mc = reinterpret_cast<unsigned long long *>(nsplit.as<int32_t>() + 2);
+        LSS_HIP(hipMemsetAsync(mc, 0, 8, c.stream));
         hipLaunchKernelGGL(k_make_children, dim3(grid_for(ns)), dim3(kBlk), 0, c.stream, nsplit.as<int32_t>(),
                            split.as<int32_t>(), child_base, lvl, keys, t.level.as<int32_t>(), t.ijk.as<int32_t>(),
-                           t.nb.as<int64_t>(), t.ne.as<int64_t>(), t.child.as<int32_t>(), t.parent.as<int32_t>());
+                           t.nb.as<int64_t>(), t.ne.as<int64_t>(), t.child.as<int32_t>(), t.parent.as<int32_t>(), mc);
         LSS_CHECK_LAUNCH("k_make_children");
+        unsigned long long hm = 0;
+        LSS_HIP(hipMemcpyAsync(&hm, mc, 8, hipMemcpyDeviceToHost, c.stream));
+        LSS_HIP(hipStreamSynchronize(c.stream));
+        maxcnt = (int64_t)hm;
         t.level_begin.push_back(le + 8 * (int64_t)ns);
     }
     t.nboxes = t.level_begin.back();
     // ---------------------------------------------------- dual traversal
     DttArgs a{t.level.as<int32_t>(), t.ijk.as<int32_t>(), t.child.as<int32_t>(), t.nb.as<int64_t>(),
-              t.ne.as<int64_t>(), t.K};
+              t.ne.as<int64_t>(), t.rmax.as<double>(), t.L0, t.K};
     t.cnt.ensure(8 * 8);
     int64_t nfr = 1;
     t.fr.ensure(8 * 64);
@@ -473,17 +517,23 @@ void launch_locate_targets(Ctx &c, int64_t n_max, const int32_t *n_dev, const do
                            const double *tz, uint64_t *keys, int32_t *idx) {
     Tree &t = c.tree;
     hipLaunchKernelGGL(k_locate, dim3(grid_for(n_max)), dim3(kBlk), 0, c.stream, n_max, n_dev, tx, ty, tz,
-                       make_root(t), t.L0, t.child.as<int32_t>(), (int32_t)t.nboxes, keys, idx);
+                       make_root(t), t.L0, keys, idx);
     LSS_CHECK_LAUNCH("k_locate");
 }
 
-// tile starts (positions in the leaf-sorted target list) and their count on the device
+// leaf of every sorted target, tile starts over the sorted list and their
+// count on the device
 int64_t build_tiles(Ctx &c, int64_t n_max, const int32_t *n_dev, const uint64_t *sorted_keys, int tile,
-                    int32_t *tile_start, int32_t *ntiles_dev) {
+                    int32_t *sorted_leaf, int32_t *tile_start, int32_t *ntiles_dev) {
+    Tree &t = c.tree;
     DBuf &fl = c.tflag, &pos = c.tpos;
     fl.ensure(4 * (n_max + 1));
     pos.ensure(4 * (n_max + 1));
-    hipLaunchKernelGGL(k_tile_flags, dim3(grid_for(n_max)), dim3(kBlk), 0, c.stream, n_max, n_dev, sorted_keys, tile,
+    hipLaunchKernelGGL(k_sorted_leaf, dim3(grid_for(n_max)), dim3(kBlk), 0, c.stream, n_max, n_dev, sorted_keys,
+                       t.child.as<int32_t>(), (int32_t)t.nboxes, sorted_leaf);
+    LSS_CHECK_LAUNCH("k_sorted_leaf");
+    hipLaunchKernelGGL(k_tile_flags, dim3(grid_for(n_max)), dim3(kBlk), 0, c.stream, n_max, n_dev, sorted_keys,
+                       sorted_leaf, t.level.as<int32_t>(), t.ijk.as<int32_t>(), (int32_t)t.nboxes, tile,
                        fl.as<int32_t>(), pos.as<int32_t>());
     LSS_CHECK_LAUNCH("k_tile_flags");
     compact_flags(c, n_max, nullptr, fl.as<int32_t>(), pos.as<int32_t>(), tile_start, ntiles_dev);
