@@ -129,10 +129,13 @@ typedef struct lss_stats {
                                  the iterations of the last lss_project */
     double  last_pairs;       /* pair-kernel evaluations of the last lss_eval / lss_project */
     int64_t n_degenerate;     /* zero-area triangles in the source set (they contribute nothing) */
-    double  pair_kernel_ms;   /* device time of the pair-kernel launches of the last lss_eval /
-                                 lss_project, from HIP events recorded around them on the
-                                 context stream (waits for those events) */
-    int32_t pair_kernel_launches;  /* number of pair-kernel launches timed in pair_kernel_ms */
+    double  pair_kernel_ms;   /* device time from HIP events recorded on the context stream
+                                 (reading it waits for them): for lss_eval, around the
+                                 pair-kernel launches; for lss_project, around the launches of
+                                 the captured Newton iterations (target update, evaluation,
+                                 Newton step and compaction together) */
+    int32_t pair_kernel_launches;  /* lss_eval: pair-kernel launches timed in pair_kernel_ms;
+                                      lss_project: graph launches (8 iterations each) */
     int32_t pad0;
 } lss_stats;
 
@@ -201,6 +204,19 @@ int lss_eval(lss_ctx *ctx, const double *x, const int32_t *x_mesh, int64_t n,
 int lss_project(lss_ctx *ctx, const double *chart_uv, int32_t np,
                 double *h, double *xout, int8_t *status, int8_t *iters,
                 unsigned flags);
+
+/* Autotuner: choose the tile width and, for LSS_FAR_FMM, the leaf capacity
+ * and leaf shrink for the current source set, sigma and precision by timing
+ * candidates on the caller's targets: cost = (build time) + eval_weight *
+ * (time to evaluate x), each from HIP events on the context stream.  Pass a
+ * spatially compact subset of the real targets and eval_weight = (all
+ * targets) / n to keep the local target density.  cache_path (may be NULL):
+ * a text file of one JSON object per line keyed by device, sizes and
+ * precision; a matching line is reused without timing, a new result is
+ * appended.  On return the best options are set on ctx and written to *out
+ * (may be NULL).  x: (n,3), host or device per flags; n >= 1. */
+int lss_autotune(lss_ctx *ctx, const double *x, int64_t n, unsigned flags, double eval_weight,
+                 const char *cache_path, lss_options *out);
 
 /* Counters of the context.  Waits for the events and counters of the last
  * lss_eval / lss_project (so it synchronises with those calls). */

@@ -21,7 +21,7 @@ PTR_DEVICE = 1
 # every entry point declared in include/lss.h
 EXPORTED_SYMBOLS = ["lss_create", "lss_destroy", "lss_last_error", "lss_synchronize",
                     "lss_set_sources", "lss_set_sigma", "lss_set_options", "lss_get_options",
-                    "lss_build", "lss_eval", "lss_project", "lss_get_stats"]
+                    "lss_build", "lss_eval", "lss_project", "lss_autotune", "lss_get_stats"]
 
 _CODES = {1: "LSS_EINVAL", 2: "LSS_ENOMEM", 3: "LSS_EHIP", 4: "LSS_ESTATE", 5: "LSS_EORIENT"}
 
@@ -90,6 +90,7 @@ def load_library():
     L.lss_eval.argtypes = [P, P, P, i64, P, P, u]
     L.lss_project.argtypes = [P, P, i32, P, P, P, P, u]
     L.lss_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
+    L.lss_autotune.argtypes = [P, P, i64, u, ctypes.c_double, ctypes.c_char_p, ctypes.POINTER(Options)]
     _lib = L
     return L
 
@@ -193,6 +194,15 @@ class Context:
 
     def synchronize(self):
         self._check(self._lib.lss_synchronize(self._h))
+
+    def autotune(self, x, eval_weight=1.0, cache_path=None):
+        """Pick tile / leaf parameters by timing candidates on targets x (see
+        lss_autotune); returns the chosen options."""
+        px, fx, kx = _ptr(x, np.float64)
+        o = Options()
+        cp = None if cache_path is None else str(cache_path).encode()
+        self._check(self._lib.lss_autotune(self._h, px, len(x), fx, float(eval_weight), cp, ctypes.byref(o)))
+        return {k: getattr(o, k) for k, _ in o._fields_ if k != "reserved"}
 
     def stats(self):
         s = Stats()

@@ -3,8 +3,13 @@
 #include <cstring>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <fstream>
 #include <new>
+#include <sstream>
 
 #include "lss_internal.h"
 
@@ -192,6 +197,54 @@ void eval(Ctx &c, const double *x, const int32_t *xm, int64_t n, double *phi, do
     c.pairs_pending = true;
 }
 
+// One Newton iteration over the active list, entirely on the device: no host
+// read, allocation, memset or sort, so a run of iterations can be captured.
+void newton_iteration(Ctx &c, int64_t N, double tau, double *phi, double *grad) {
+    NewtonState &s = c.ns;
+    const int32_t *nact = s.nact.as<int32_t>();
+    launch_iter_mark(c);
+    launch_newton_targets(c, N);
+    if (c.opt.far_field == LSS_FAR_FMM) {
+        build_tiles_unsorted(c, N, nact, fmm_tile(c));
+        launch_eval_fmm(c, N, c.ntiles.as<int32_t>(), c.tstart.as<int32_t>(), nact, N, c.tleaf.as<int32_t>(),
+                        nullptr, c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(), nullptr, phi, grad);
+    } else {
+        launch_p2p_direct(c, N, nact, c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(), c.tmesh.as<int32_t>(),
+                          nullptr, phi, grad, 3);
+    }
+    launch_newton_update(c, N, tau, phi, grad);
+    launch_compact_active(c, N);
+}
+
+// Capture `count` Newton iterations into an executable graph.  The capture
+// runs on a stream of the context's own (default priority); the graph is then
+// launched on the context stream.
+hipGraphExec_t capture_newton(Ctx &c, int64_t N, double tau, double *phi, double *grad, int count) {
+    if (!c.capture_stream) LSS_HIP(hipStreamCreateWithFlags(&c.capture_stream, hipStreamNonBlocking));
+    hipStream_t saved = c.stream;
+    c.stream = c.capture_stream;
+    hipGraph_t graph = nullptr;
+    LSS_HIP(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
+    try {
+        for (int k = 0; k < count; ++k) newton_iteration(c, N, tau, phi, grad);
+    } catch (...) {
+        (void)hipStreamEndCapture(c.stream, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        c.stream = saved;
+        throw;
+    }
+    hipError_t e = hipStreamEndCapture(c.stream, &graph);
+    c.stream = saved;
+    if (e != hipSuccess) fail(LSS_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) fail(LSS_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    return exec;
+}
+
+constexpr int kNewtonChunk = 8;   // iterations per graph launch between host checks
+
 void project(Ctx &c, const double *uv, int32_t np, double *h, double *xout, int8_t *st, int8_t *it, unsigned flags) {
     if (np <= 0) fail(LSS_EINVAL, "lss_project: np must be >= 1");
     if (!uv || !h) fail(LSS_EINVAL, "lss_project: chart_uv and h must be non-null");
@@ -205,33 +258,36 @@ void project(Ctx &c, const double *uv, int32_t np, double *h, double *xout, int8
     const int maxit = c.opt.newton_max_iter > 0 ? c.opt.newton_max_iter : kMaxIterDefault;
     launch_chart_init(c, duv.as<double>(), np, N);
     ensure_targets(c, N);
+    if (c.opt.far_field == LSS_FAR_FMM) ensure_tiles(c, N);
     NewtonState &s = c.ns;
     DBuf phi, grad;
     phi.ensure(sizeof(double) * N);
     grad.ensure(sizeof(double) * 3 * N);
     LSS_HIP(hipMemsetAsync(c.pairs.p, 0, sizeof(double), c.stream));
-    int64_t evals = 0;
-    int iters_run = 0;
+    // Iterations run in captured chunks; a node leaves the active list when it
+    // converges or reaches maxit, so iterations past the last active one are
+    // empty launches and the host only checks the count between chunks.
+    const int chunk = std::min(maxit, kNewtonChunk);
+    hipGraphExec_t exec = capture_newton(c, N, tau, phi.as<double>(), grad.as<double>(), chunk);
     c.ev_reset();
-    for (int k = 0; k < maxit; ++k) {
-        int32_t nact = 0;
-        LSS_HIP(hipMemcpyAsync(&nact, s.nact.p, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
-        LSS_HIP(hipStreamSynchronize(c.stream));
-        if (nact == 0) break;
-        evals += nact;
-        ++iters_run;
-        launch_newton_targets(c, N);
-        if (c.opt.far_field == LSS_FAR_FMM) {
-            eval_fmm_targets(c, N, s.nact.as<int32_t>(), phi.as<double>(), grad.as<double>(), false);
-        } else {
+    try {
+        for (int done = 0; done < maxit; done += chunk) {
             c.ev_begin();
-            launch_p2p_direct(c, N, s.nact.as<int32_t>(), c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(),
-                              c.tmesh.as<int32_t>(), nullptr, phi.as<double>(), grad.as<double>(), 3);
+            LSS_HIP(hipGraphLaunch(exec, c.stream));
             c.ev_end();
+            if (done + chunk >= maxit) break;
+            int32_t nact = 0;
+            LSS_HIP(hipMemcpyAsync(&nact, s.nact.p, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+            LSS_HIP(hipStreamSynchronize(c.stream));
+            if (nact == 0) break;
         }
-        launch_newton_update(c, N, tau, phi.as<double>(), grad.as<double>());
-        launch_compact_active(c, N);
+        LSS_HIP(hipStreamSynchronize(c.stream));
+    } catch (...) {
+        (void)hipStreamSynchronize(c.stream);
+        (void)hipGraphExecDestroy(exec);
+        throw;
     }
+    (void)hipGraphExecDestroy(exec);
     double *oh = h, *ox = xout;
     int8_t *ost = st, *oit = it;
     if (!dev) {
@@ -249,9 +305,130 @@ void project(Ctx &c, const double *uv, int32_t np, double *h, double *xout, int8
         if (st) LSS_HIP(hipMemcpyAsync(st, ost, N, hipMemcpyDeviceToHost, c.stream));
         if (it) LSS_HIP(hipMemcpyAsync(it, oit, N, hipMemcpyDeviceToHost, c.stream));
     }
+    int32_t cnt[4] = {0, 0, 0, 0};
+    std::vector<int32_t> hist(kHistCap, 0);
+    LSS_HIP(hipMemcpyAsync(cnt, s.nact.p, sizeof(cnt), hipMemcpyDeviceToHost, c.stream));
+    LSS_HIP(hipMemcpyAsync(hist.data(), s.hist.p, sizeof(int32_t) * kHistCap, hipMemcpyDeviceToHost, c.stream));
     LSS_HIP(hipStreamSynchronize(c.stream));
+    int64_t evals = 0;
+    for (int k = 0; k < cnt[3] && k < kHistCap; ++k) evals += hist[k];
     c.stats.last_targets = evals;
-    c.stats.newton_iters = iters_run;
+    c.stats.newton_iters = cnt[3];
+}
+
+
+// ------------------------------------------------------------- autotuner
+std::string tune_key(const Ctx &c) {
+    hipDeviceProp_t prop;
+    std::string dev = "gfx";
+    if (hipGetDeviceProperties(&prop, c.device) == hipSuccess) dev = prop.gcnArchName;
+    std::ostringstream k;
+    k << dev << "/tris=" << c.ntris << "/nq=" << c.nq << "/mesh=" << c.nmesh << "/prec=" << c.opt.precision
+      << "/far=" << c.opt.far_field << "/p=" << c.opt.fmm_order << "/cut=" << c.opt.cut_factor
+      << "/smin=" << c.sigma_min << "/smax=" << c.sigma_max;
+    return k.str();
+}
+
+bool tune_lookup(const char *path, const std::string &key, lss_options &o) {
+    if (!path) return false;
+    std::ifstream f(path);
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        const std::string tag = "\"key\": \"" + key + "\"";
+        if (line.find(tag) == std::string::npos) continue;
+        double shrink = 0;
+        int cap = 0, tile = 0;
+        const char *q = strstr(line.c_str(), "\"leaf_shrink\":");
+        if (q) shrink = atof(q + 14);
+        q = strstr(line.c_str(), "\"leaf_capacity\":");
+        if (q) cap = atoi(q + 16);
+        q = strstr(line.c_str(), "\"tile\":");
+        if (q) tile = atoi(q + 7);
+        o.leaf_shrink = shrink;
+        o.leaf_capacity = cap;
+        o.tile = tile;
+        found = true;               // the last matching line wins
+    }
+    return found;
+}
+
+void autotune(Ctx &c, const double *x, int64_t n, unsigned flags, double w, const char *path, lss_options *out) {
+    if (!c.have_sources || !c.have_sigma) fail(LSS_ESTATE, "lss_autotune: set sources and sigma first");
+    if (!x || n < 1) fail(LSS_EINVAL, "lss_autotune: need n >= 1 targets");
+    if (!(w > 0.0) || !std::isfinite(w)) fail(LSS_EINVAL, "lss_autotune: eval_weight must be positive");
+    const lss_options base = c.opt;
+    const std::string key = tune_key(c);
+    lss_options best = base;
+    if (tune_lookup(path, key, best)) {
+        validate_options(best);
+        c.opt = best;
+        c.built = false;
+        if (out) *out = best;
+        return;
+    }
+    DBuf dx, phi, grad;
+    upload(c, dx, x, sizeof(double) * 3 * n, flags);
+    phi.ensure(sizeof(double) * n);
+    grad.ensure(sizeof(double) * 3 * n);
+    struct Cand { double shrink; int cap, tile; };
+    std::vector<Cand> cands;
+    if (base.far_field == LSS_FAR_FMM) {
+        // candidate grids around the measured optimum of each precision
+        const bool mixed = base.precision == LSS_MIXED;
+        const std::vector<double> shr = mixed ? std::vector<double>{1.0, 1.5} : std::vector<double>{2.0, 3.0};
+        const std::vector<int> caps = mixed ? std::vector<int>{256, 512} : std::vector<int>{64, 128};
+        const std::vector<int> tiles = mixed ? std::vector<int>{64, 128, 256} : std::vector<int>{64, 128};
+        for (double sh : shr)
+            for (int cp : caps)
+                for (int tl : tiles) {
+                    if (tl == 256 && sh > 1.0) continue;
+                    cands.push_back({sh, cp, tl});
+                }
+    } else {
+        for (int tl : {64, 128, 256}) cands.push_back({0.0, 0, tl});
+    }
+    hipEvent_t e0, e1, e2;
+    LSS_HIP(hipEventCreate(&e0));
+    LSS_HIP(hipEventCreate(&e1));
+    LSS_HIP(hipEventCreate(&e2));
+    double best_cost = 1e300;
+    for (const Cand &k : cands) {
+        c.opt = base;
+        c.opt.leaf_shrink = k.shrink;
+        c.opt.leaf_capacity = k.cap;
+        c.opt.tile = k.tile;
+        c.built = false;
+        LSS_HIP(hipEventRecord(e0, c.stream));
+        build(c);
+        LSS_HIP(hipEventRecord(e1, c.stream));
+        eval(c, dx.as<double>(), nullptr, n, phi.as<double>(), grad.as<double>(), LSS_PTR_DEVICE);
+        LSS_HIP(hipEventRecord(e2, c.stream));
+        LSS_HIP(hipEventSynchronize(e2));
+        float tb = 0, te = 0;
+        LSS_HIP(hipEventElapsedTime(&tb, e0, e1));
+        LSS_HIP(hipEventElapsedTime(&te, e1, e2));
+        const double cost = tb + w * te;
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = c.opt;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(e2);
+    c.opt = best;
+    c.built = false;
+    if (path) {
+        std::ofstream f(path, std::ios::app);
+        if (f) {
+            char buf[256];
+            snprintf(buf, sizeof(buf), ", \"leaf_shrink\": %.3f, \"leaf_capacity\": %d, \"tile\": %d, \"cost_ms\": %.3f}",
+                     best.leaf_shrink, best.leaf_capacity, best.tile, best_cost);
+            f << "{\"key\": \"" << key << "\"" << buf << "\n";
+        }
+    }
+    if (out) *out = best;
 }
 
 template <class F> int guarded(lss_ctx *ctx, F &&f) {
@@ -317,8 +494,9 @@ void lss_destroy(lss_ctx *ctx) {
                     &c.tflag, &c.tpos, &c.tstart, &c.ntiles, &c.tleaf,
                     &c.ns.T, &c.ns.H, &c.ns.h, &c.ns.lo, &c.ns.hi, &c.ns.sig, &c.ns.mesh, &c.ns.orig,
                     &c.ns.status, &c.ns.iters, &c.ns.active, &c.ns.active2, &c.ns.flag, &c.ns.blocksum,
-                    &c.ns.nact};
+                    &c.ns.nact, &c.ns.hist};
     for (DBuf *b : bufs) b->release();
+    if (c.capture_stream) (void)hipStreamDestroy(c.capture_stream);
     for (hipEvent_t e : c.ev_start) (void)hipEventDestroy(e);
     for (hipEvent_t e : c.ev_stop) (void)hipEventDestroy(e);
     delete ctx;
@@ -459,6 +637,11 @@ int lss_eval(lss_ctx *ctx, const double *x, const int32_t *x_mesh, int64_t n, do
 int lss_project(lss_ctx *ctx, const double *chart_uv, int32_t np, double *h, double *xout, int8_t *status,
                 int8_t *iters, unsigned flags) {
     return lss::guarded(ctx, [&](Ctx &c) { lss::project(c, chart_uv, np, h, xout, status, iters, flags); });
+}
+
+int lss_autotune(lss_ctx *ctx, const double *x, int64_t n, unsigned flags, double eval_weight,
+                 const char *cache_path, lss_options *out) {
+    return lss::guarded(ctx, [&](Ctx &c) { lss::autotune(c, x, n, flags, eval_weight, cache_path, out); });
 }
 
 int lss_get_stats(const lss_ctx *ctx, lss_stats *out) {

@@ -90,6 +90,8 @@ struct alignas(16) SrcF {
 };
 
 // Per-chart-node Newton state, structure of arrays in sorted order.
+constexpr int kHistCap = 128;   // >= the largest newton_max_iter (120)
+
 struct NewtonState {
     DBuf T, H;           // 3 doubles each, AoS
     DBuf h, lo, hi;      // doubles
@@ -99,7 +101,8 @@ struct NewtonState {
     DBuf status, iters;  // int8
     DBuf active, active2, flag;   // int32 lists / flags
     DBuf blocksum;       // int32 per block counts
-    DBuf nact;           // int32[2] active count (device)
+    DBuf nact;           // int32[4]: active count, count at iteration start, N
+    DBuf hist;           // int32[kHistCap]: active count per iteration
 };
 
 // Octree over the quadrature nodes and the FMM state (far_field = LSS_FAR_FMM).
@@ -135,6 +138,7 @@ struct Tree {
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    hipStream_t capture_stream = nullptr;   // created on first use (default priority) for graph capture
     std::string err;
     lss_options opt{};
     lss_stats stats{};
@@ -212,6 +216,7 @@ void launch_chart_init(Ctx &c, const double *chart_uv, int32_t np, int64_t N);
 void launch_newton_targets(Ctx &c, int64_t N);
 void launch_newton_update(Ctx &c, int64_t N, double tau, const double *phi, const double *grad);
 void launch_compact_active(Ctx &c, int64_t N);
+void launch_iter_mark(Ctx &c);
 void launch_newton_output(Ctx &c, int64_t N, double *h, double *xout, int8_t *status, int8_t *iters);
 
 // octree, lists, FMM (lss_tree.hip, lss_fmm.hip)
@@ -227,6 +232,10 @@ void launch_eval_fmm(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const
                      const double *tx, const double *ty, const double *tz, const int32_t *out_idx, double *phi,
                      double *grad);
 void launch_soa(Ctx &c, const double *x, int64_t n, double *tx, double *ty, double *tz);
+// Newton targets in FMM mode: leaf of each target in its current order and
+// tile heads at leaf changes and every TILE-th position (no sort; capturable)
+void ensure_tiles(Ctx &c, int64_t n_max);
+void build_tiles_unsorted(Ctx &c, int64_t n_max, const int32_t *n_dev, int tile);
 
 // sorting and scans (lss_sort.hip)
 size_t sort_pairs_u64_tmp_bytes(int64_t n);

@@ -412,6 +412,25 @@ __global__ void k_block_scatter(const int32_t *__restrict__ n_dev, const int32_t
     if (f) out[pre] = in[i];
 }
 
+// start of a Newton iteration: the active count becomes the input count of
+// this iteration's compaction; a non-empty iteration is counted (nact[3]) and
+// its count recorded in hist (capacity cap)
+__global__ void k_iter_mark(int32_t *nact, int32_t *hist, int32_t cap) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const int32_t n = nact[0];
+        nact[1] = n;
+        if (n > 0 && nact[3] < cap) {
+            hist[nact[3]] = n;
+            nact[3] += 1;
+        }
+    }
+}
+
+__global__ void k_copy_active(const int32_t *__restrict__ n_dev, const int32_t *__restrict__ in, int32_t *out) {
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < *n_dev) out[a] = in[a];
+}
+
 __global__ void k_iota(int64_t n, int32_t *out) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = (int32_t)i;
@@ -571,8 +590,9 @@ void launch_chart_init(Ctx &c, const double *uv, int32_t np, int64_t N) {
     s.active.ensure(sizeof(int32_t) * N);
     s.active2.ensure(sizeof(int32_t) * N);
     s.flag.ensure(sizeof(int32_t) * N);
-    s.blocksum.ensure(sizeof(int32_t) * (ceil_div(N, kCompBlk) + 1));
+    s.blocksum.ensure(sizeof(int32_t) * (ceil_div(N, kCompBlk) + 4));
     s.nact.ensure(sizeof(int32_t) * 4);
+    s.hist.ensure(sizeof(int32_t) * kHistCap);
     hipLaunchKernelGGL(k_chart_init, dim3(grid_for(N)), dim3(kBlk), 0, c.stream, N, c.verts.as<double>(),
                        c.tris.as<int32_t>(), c.vH.as<double>(), uv, np, c.tri_off.as<int64_t>(), c.nmesh,
                        c.sigma.as<double>(), c.tperm2.as<int32_t>(), s.T.as<double>(), s.H.as<double>(),
@@ -583,8 +603,9 @@ void launch_chart_init(Ctx &c, const double *uv, int32_t np, int64_t N) {
     // initial active list: all non-degenerate nodes, in sorted order
     hipLaunchKernelGGL(k_iota, dim3(grid_for(N)), dim3(kBlk), 0, c.stream, N, s.active2.as<int32_t>());
     LSS_CHECK_LAUNCH("k_iota");
-    int32_t nN = (int32_t)N;
-    LSS_HIP(hipMemcpyAsync(s.nact.as<int32_t>() + 1, &nN, sizeof(int32_t), hipMemcpyHostToDevice, c.stream));
+    int32_t nN[3] = {(int32_t)N, (int32_t)N, 0};
+    LSS_HIP(hipMemcpyAsync(s.nact.as<int32_t>() + 1, nN, 3 * sizeof(int32_t), hipMemcpyHostToDevice, c.stream));
+    LSS_HIP(hipMemsetAsync(s.hist.p, 0, sizeof(int32_t) * kHistCap, c.stream));
     // compact active2[0..N) by flag into active, count into nact[0]
     int32_t nb = (int32_t)ceil_div(N, kCompBlk);
     hipLaunchKernelGGL(k_block_count, dim3(nb), dim3(kCompBlk), 0, c.stream, s.nact.as<int32_t>() + 1,
@@ -617,12 +638,22 @@ void launch_newton_update(Ctx &c, int64_t N, double tau, const double *phi, cons
     LSS_CHECK_LAUNCH("k_newton_update");
 }
 
-// active <- compact(active, flag); count n <- nact[0] (old count copied to nact[1] first)
+// Newton iteration bookkeeping, all on the device (capturable): nact[0] is
+// the active count, nact[1] the count at the start of the iteration, nact[2]
+// the total N, nact[3] the number of non-empty iterations; hist[k] records
+// the active count of iteration k.
+void launch_iter_mark(Ctx &c) {
+    NewtonState &s = c.ns;
+    hipLaunchKernelGGL(k_iter_mark, dim3(1), dim3(64), 0, c.stream, s.nact.as<int32_t>(), s.hist.as<int32_t>(),
+                       (int32_t)kHistCap);
+    LSS_CHECK_LAUNCH("k_iter_mark");
+}
+
+// active <- compact(active, flag) over the nact[1] entries of this iteration
 void launch_compact_active(Ctx &c, int64_t N) {
     NewtonState &s = c.ns;
-    LSS_HIP(hipMemcpyAsync(s.nact.as<int32_t>() + 1, s.nact.as<int32_t>(), sizeof(int32_t),
-                           hipMemcpyDeviceToDevice, c.stream));
-    LSS_HIP(hipMemcpyAsync(s.active2.p, s.active.p, sizeof(int32_t) * N, hipMemcpyDeviceToDevice, c.stream));
+    hipLaunchKernelGGL(k_copy_active, dim3(grid_for(N)), dim3(kBlk), 0, c.stream, s.nact.as<int32_t>() + 1,
+                       s.active.as<int32_t>(), s.active2.as<int32_t>());
     int32_t nb = (int32_t)ceil_div(N, kCompBlk);
     hipLaunchKernelGGL(k_block_count, dim3(nb), dim3(kCompBlk), 0, c.stream, s.nact.as<int32_t>() + 1,
                        s.flag.as<int32_t>(), s.blocksum.as<int32_t>());

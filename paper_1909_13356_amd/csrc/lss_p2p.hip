@@ -286,6 +286,8 @@ struct FmmEvalArgs {
     int64_t n_max;
     const int32_t *n_dev;
     const int32_t *sleaf;       // leaf of each sorted target (nboxes: outside the root)
+    // tiles [tile_start[k], tile_start[k+1]) (the last ends at the target count)
+    // hold at most TILE targets of one leaf
     const int32_t *sidx;
     const double *tx, *ty, *tz;
     const int32_t *out_idx;
@@ -380,9 +382,10 @@ __global__ __launch_bounds__(TILE) void k_eval_fmm_f64(FmmEvalArgs a) {
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t s0 = a.tile_start[tile];
         const int32_t leafk = a.sleaf[s0];
+        const int64_t s1 = tile + 1 < ntiles ? (int64_t)a.tile_start[tile + 1] : n;   // tile = [s0, s1)
         const int64_t sp_ = s0 + lane;
-        const bool valid = sp_ < n && a.sleaf[sp_] == leafk;
-        const int64_t ti = a.sidx[valid ? sp_ : s0];
+        const bool valid = sp_ < s1;
+        const int64_t ti = a.sidx ? (int64_t)a.sidx[valid ? sp_ : s0] : (valid ? sp_ : s0);
         const double x = a.tx[ti], y = a.ty[ti], z = a.tz[ti];
         const int32_t B = leafk;
         const bool outside = B >= a.nboxes;
@@ -440,10 +443,11 @@ __global__ __launch_bounds__(TILE) void k_eval_fmm_mixed(FmmEvalArgs a) {
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t s0 = a.tile_start[tile];
         const int32_t leafk = a.sleaf[s0];
+        const int64_t s1 = tile + 1 < ntiles ? (int64_t)a.tile_start[tile + 1] : n;   // tile = [s0, s1)
         const int64_t sp_ = s0 + lane;
-        const bool valid = sp_ < n && a.sleaf[sp_] == leafk;
-        const int64_t ti = a.sidx[valid ? sp_ : s0];
-        const int64_t t0 = a.sidx[s0];
+        const bool valid = sp_ < s1;
+        const int64_t ti = a.sidx ? (int64_t)a.sidx[valid ? sp_ : s0] : (valid ? sp_ : s0);
+        const int64_t t0 = a.sidx ? (int64_t)a.sidx[s0] : s0;
         const double ox = a.tx[t0], oy = a.ty[t0], oz = a.tz[t0];
         const double X = a.tx[ti], Y = a.ty[ti], Z = a.tz[ti];
         const double dxo = X - ox, dyo = Y - oy, dzo = Z - oz;

@@ -321,6 +321,36 @@ __global__ void k_tile_flags(int64_t n_max, const int32_t *__restrict__ n_dev, c
     flag[i] = ((i - lo) % tile) == 0 ? 1 : 0;
 }
 
+// leaf of each target in its current order (nboxes outside the root, -1 unused)
+__global__ void k_leaf_direct(int64_t n_max, const int32_t *__restrict__ n_dev, const double *__restrict__ tx,
+                              const double *__restrict__ ty, const double *__restrict__ tz, Root r, double L0,
+                              const int32_t *__restrict__ child, int32_t nboxes, int32_t *leaf) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t n = *n_dev;
+    if (i >= n_max) return;
+    if (i >= n) { leaf[i] = -1; return; }
+    double q[3] = {(tx[i] - r.o[0]) / L0, (ty[i] - r.o[1]) / L0, (tz[i] - r.o[2]) / L0};
+    bool inside = q[0] >= 0.0 && q[0] < 1.0 && q[1] >= 0.0 && q[1] < 1.0 && q[2] >= 0.0 && q[2] < 1.0;
+    if (!inside) { leaf[i] = nboxes; return; }
+    const uint64_t k = key21(tx[i], ty[i], tz[i], r);
+    int32_t b = 0;
+    int lvl = 0;
+    while (child[b] >= 0) {
+        b = child[b] + (int)((k >> (3 * (21 - (lvl + 1)))) & 7ull);
+        ++lvl;
+    }
+    leaf[i] = b;
+}
+
+__global__ void k_tile_flags_runs(int64_t n_max, const int32_t *__restrict__ n_dev, const int32_t *__restrict__ leaf,
+                                  int tile, int32_t *flag, int32_t *pos) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t n = *n_dev;
+    if (i >= n_max) return;
+    pos[i] = (int32_t)i;
+    flag[i] = (i < n && (i == 0 || leaf[i] != leaf[i - 1] || (i % tile) == 0)) ? 1 : 0;
+}
+
 __global__ void k_soa(int64_t n, const double *__restrict__ x, double *tx, double *ty, double *tz) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -538,6 +568,34 @@ int64_t build_tiles(Ctx &c, int64_t n_max, const int32_t *n_dev, const uint64_t 
     LSS_CHECK_LAUNCH("k_tile_flags");
     compact_flags(c, n_max, nullptr, fl.as<int32_t>(), pos.as<int32_t>(), tile_start, ntiles_dev);
     return n_max;
+}
+
+// Newton targets keep the order of their chart points (sorted once by Morton
+// key): each iteration finds the leaf of every active target in place and
+// starts a tile wherever the leaf changes or TILE targets have been taken.
+// No sort, no host synchronisation, no allocation: safe under stream capture
+// once the buffers have been sized by ensure_tiles.
+void ensure_tiles(Ctx &c, int64_t n_max) {
+    c.tflag.ensure(4 * (n_max + 1));
+    c.tpos.ensure(4 * (n_max + 1));
+    c.tstart.ensure(4 * (n_max + 1));
+    c.tleaf.ensure(4 * (n_max + 1));
+    c.ntiles.ensure(16);
+    c.ns.blocksum.ensure(sizeof(int32_t) * (ceil_div(n_max > 0 ? n_max : 1, 1024) + 4));
+}
+
+void build_tiles_unsorted(Ctx &c, int64_t n_max, const int32_t *n_dev, int tile) {
+    Tree &t = c.tree;
+    int32_t *leaf = c.tleaf.as<int32_t>();
+    hipLaunchKernelGGL(k_leaf_direct, dim3(grid_for(n_max)), dim3(kBlk), 0, c.stream, n_max, n_dev, c.tx.as<double>(),
+                       c.ty.as<double>(), c.tz.as<double>(), make_root(t), t.L0, t.child.as<int32_t>(),
+                       (int32_t)t.nboxes, leaf);
+    LSS_CHECK_LAUNCH("k_leaf_direct");
+    hipLaunchKernelGGL(k_tile_flags_runs, dim3(grid_for(n_max)), dim3(kBlk), 0, c.stream, n_max, n_dev, leaf, tile,
+                       c.tflag.as<int32_t>(), c.tpos.as<int32_t>());
+    LSS_CHECK_LAUNCH("k_tile_flags_runs");
+    compact_flags(c, n_max, n_dev, c.tflag.as<int32_t>(), c.tpos.as<int32_t>(), c.tstart.as<int32_t>(),
+                  c.ntiles.as<int32_t>());
 }
 
 }  // namespace lss

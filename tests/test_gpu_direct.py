@@ -225,3 +225,27 @@ def test_project_statuses():
     ho, xo, sto, ito = oracle.project(P, tt, [0.05], dunavant6(), chart_nodes(1), max_iter=1)
     assert np.array_equal(st, sto)
     assert np.max(np.abs(h - ho)) <= 1e-12
+
+
+@pytest.mark.parametrize("max_iter", [3, 20, 0])
+def test_project_repeated_graph_launches(max_iter):
+    """Newton iterations run as captured graphs launched in chunks; repeated
+    projections with other work in between, a smaller second call and an
+    iteration cap that is not a multiple of the chunk must all agree with the
+    oracle, and the statistics must match the per-node iteration counts."""
+    v, t = icosphere(3)
+    sigma = 0.1
+    say("case: repeated projections, max_iter", max_iter)
+    c = ctx_for(v, t, [sigma], lss.FP64, newton_max_iter=max_iter)
+    sel = np.arange(0, len(t), 41)
+    kw = dict(max_iter=max_iter) if max_iter else {}
+    for uv in (chart_nodes(2), chart_nodes(1), chart_nodes(2)):
+        h, x, st, it = c.project(uv)
+        stt = c.stats()
+        assert stt["newton_iters"] == it.max()
+        assert stt["last_targets"] == int(it.astype(np.int64).sum())
+        ho, xo, sto, ito = oracle.project(v, t, [sigma], dunavant6(), uv, sel=sel, **kw)
+        idx = (sel[:, None] * len(uv) + np.arange(len(uv))[None]).ravel()
+        assert np.array_equal(st[idx], sto)
+        assert np.max(np.abs(h[idx] - ho)) / sigma <= 1e-11
+        c.eval(np.array([[0.1, 0.2, 0.3]]))     # eager work between graph launches

@@ -119,3 +119,47 @@ def test_fmm_determinism_and_device_pointers(graded):
     assert torch.equal(p1, p2) and torch.equal(g1, g2)
     ph, gh = cf.eval(x)
     assert np.array_equal(p1.cpu().numpy(), ph)
+
+
+def test_autotune_and_cache(graded, tmp_path):
+    v, t, sig, x = graded
+    cache = tmp_path / "tune.jsonl"
+    for prec in (lss.MIXED, lss.FP64):
+        cf = ctx(v, t, sig, prec, lss.FAR_FMM)
+        o1 = cf.autotune(x[:20000], eval_weight=3.0, cache_path=cache)
+        say("case: autotune precision %d -> %s" % (prec, o1))
+        assert o1["tile"] in (64, 128, 256) and o1["leaf_capacity"] > 0 and o1["leaf_shrink"] >= 1.0
+        # the tuned options still meet the parity bar
+        pf, gf = cf.eval(x[:3000])
+        cd = ctx(v, t, sig, lss.FP64, lss.FAR_DIRECT)
+        pd, gd = cd.eval(x[:3000])
+        ep, eg = errs(pf, gf, pd, gd)
+        assert ep <= TOL[prec] and eg <= TOL[prec]
+        # a second context reads the cached choice without timing
+        c2 = ctx(v, t, sig, prec, lss.FAR_FMM)
+        o2 = c2.autotune(x[:20000], eval_weight=3.0, cache_path=cache)
+        assert o2 == o1
+    assert len(cache.read_text().strip().splitlines()) == 2
+
+
+def test_fmm_project_repeated(graded):
+    """FMM projection twice in a row (second call smaller) with an evaluation in
+    between: identical answers to a fresh context, and to the oracle."""
+    v, t, sig, _ = graded
+    sel = np.arange(0, len(t), 97)
+    for prec in (lss.MIXED, lss.FP64):
+        say("case: repeated FMM projections, precision %d" % prec)
+        cf = ctx(v, t, sig, prec, lss.FAR_FMM, newton_max_iter=12)
+        tau = 1e-12 if prec == lss.FP64 else 1e-6
+        for uv in (chart_nodes(2), chart_nodes(1)):
+            h, xs, st, it = cf.project(uv)
+            cf.eval(xs[:100])
+            fresh = ctx(v, t, sig, prec, lss.FAR_FMM, newton_max_iter=12)
+            h2, _, st2, it2 = fresh.project(uv)
+            assert np.array_equal(h, h2) and np.array_equal(st, st2) and np.array_equal(it, it2)
+            ho, xo, sto, ito = oracle.project(v, t, sig, dunavant6(), uv, tau=tau, sel=sel, max_iter=12)
+            idx = (sel[:, None] * len(uv) + np.arange(len(uv))[None]).ravel()
+            assert np.all(st[idx] == sto)
+            eh = np.max(np.abs(h[idx] - ho) / sig[sel].repeat(len(uv)))
+            say("  np %d e_h %.3e iters max %d" % (len(uv), eh, it.max()))
+            assert eh <= (1e-11 if prec == lss.FP64 else 2e-6)
