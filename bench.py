@@ -94,6 +94,57 @@ def time_variant(lss, torch, cfg, prec, far, steps, warmup):
                 pairs_per_s=pairs * steps / el, n_targets=n)
 
 
+def time_newton(lss, torch, cfg, prec, steps, warmup):
+    """Chart projection (Newton onto Phi = 1/2) of every chart node of the
+    graded surface with the FMM path; one step = build + all iterations."""
+    dev = torch.device("cuda")
+    v = torch.as_tensor(cfg["verts"], device=dev)
+    t = torch.as_tensor(cfg["tris"], device=dev)
+    r = torch.as_tensor(cfg["rule"], device=dev)
+    s = torch.as_tensor(np.asarray(cfg["sigma"], float), device=dev)
+    uv = torch.as_tensor(cfg["chart_uv"], device=dev)
+    c = lss.Context(0)
+    c.set_sources(v, t, r)
+    c.set_sigma(s)
+    c.set_options(precision=prec, far_field=lss.FAR_FMM)
+    n_nodes = len(cfg["tris"]) * len(cfg["chart_uv"])
+    for _ in range(warmup):
+        c.set_sigma(s)
+        c.project(uv, device=True)
+    torch.cuda.synchronize()
+    el, evals, iters, gms = 0.0, 0, 0, 0.0
+    for _ in range(steps):
+        c.set_sigma(s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h, x, st, it = c.project(uv, device=True)
+        torch.cuda.synchronize()
+        el += time.perf_counter() - t0
+        stt = c.stats()
+        evals += stt["last_targets"]
+        iters = max(iters, stt["newton_iters"])
+        gms += stt["pair_kernel_ms"]
+    conv = float((st == 0).sum().item()) / n_nodes
+    c.close()
+    return {"chart_nodes_per_s": n_nodes * steps / el, "target_evals_per_s": evals / el,
+            "ms_per_step": 1e3 * el / steps, "newton_graph_ms": gms / steps, "iterations": iters,
+            "evals_per_node": evals / steps / n_nodes, "converged_frac": conv}
+
+
+def cpu_newton(cfg, n_tris=4):
+    """The oracle's Newton projection (FP64 direct sum per evaluation) on the
+    chart nodes of a few seeded triangles: about 10 s of CPU work."""
+    import oracle
+    rng = np.random.default_rng(4321)
+    sel = np.sort(rng.choice(len(cfg["tris"]), n_tris, replace=False))
+    t0 = time.perf_counter()
+    oracle.project(cfg["verts"], cfg["tris"], cfg["sigma"], cfg["rule"], cfg["chart_uv"], sel=sel)
+    dt = time.perf_counter() - t0
+    nn = n_tris * len(cfg["chart_uv"])
+    return {"value": nn / dt, "unit": "chart nodes/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": "%d chart nodes of %d triangles (seeded), FP64 direct-sum Newton, %.1f s" % (nn, n_tris, dt)}
+
+
 def cpu_baseline(cfg, budget_s=15.0):
     import oracle
     x = cfg["targets"]
@@ -123,6 +174,7 @@ def main():
     ap.add_argument("--config", default="c5")
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-newton", action="store_true", help="skip the chart-projection measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the path is single-GPU; see DESIGN.md "
@@ -141,13 +193,14 @@ def main():
     mixed, f64 = res["mixed"], res["f64"]
 
     def roof(r, dt):
+        kname = ("k_eval_fmm_%s" if far else "k_p2p_direct_%s") % ("mixed" if dt == "f32" else "f64")
         if r["pair_kernel_launches"] <= 0 or r["pair_kernel_ms"] <= 0:
             return None
         per_launch = r["pair_kernel_ms"] / r["pair_kernel_launches"] * 1e-3
         ach = FLOP_PER_PAIR * r["pairs_per_step"] / r["pair_kernel_launches"] / per_launch / 1e12
         return {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK[dt], "unit": "TFLOP/s",
                 "frac": round(ach / PEAK[dt], 4), "traffic": None,
-                "kernel": "k_p2p_direct_%s" % ("mixed" if dt == "f32" else "f64"),
+                "kernel": kname,
                 "kernel_ms": round(per_launch * 1e3, 4)}
 
     out = {
@@ -164,6 +217,22 @@ def main():
     if not args.no_cpu:
         log("bench: timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(cfg)
+    if not args.no_newton:
+        from workloads import configs
+        del cfg
+        c3 = configs.config3()
+        nn = len(c3["tris"]) * len(c3["chart_uv"])
+        newton = {"workload": "graded bumpy surface (%d tri, %d nodes), sigma_j = D_j/2, %d chart nodes "
+                              "(45 per triangle), Newton onto Phi = 1/2, octree + FMM" % (
+                                  len(c3["tris"]), 12 * len(c3["tris"]), nn)}
+        for prec, name in ((lss.FP64, "f64"), (lss.MIXED, "mixed")):
+            log("bench: Newton", name)
+            newton[name] = time_newton(lss, torch, c3, prec, max(1, min(args.steps, 3)), 1)
+            log("bench: Newton", name, json.dumps(newton[name]))
+        if not args.no_cpu:
+            log("bench: timing the CPU oracle Newton on a sample")
+            newton["cpu_baseline"] = cpu_newton(c3)
+        out["newton"] = newton
     print(json.dumps(out), flush=True)
 
 
