@@ -116,8 +116,8 @@ void ensure_targets(Ctx &c, int64_t n) {
 // the device if given): leaf of each target, targets sorted by leaf, tiles,
 // near field + L2P.  Outputs at the target's index in tx/ty/tz.
 void eval_fmm_targets(Ctx &c, int64_t n, const int32_t *n_dev, double *phi, double *grad, bool reset_pairs = true) {
-    launch_locate_targets(c, n, n_dev, c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(), c.tkey.as<uint64_t>(),
-                          c.tperm.as<int32_t>());
+    launch_locate_targets(c, n, n_dev, c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(),
+                          c.tmesh.as<int32_t>(), c.tkey.as<uint64_t>(), c.tperm.as<int32_t>());
     sort_pairs(c, c.tkey.as<uint64_t>(), c.tkey2.as<uint64_t>(), c.tperm.as<int32_t>(), c.tperm2.as<int32_t>(), n, 64);
     c.tstart.ensure(sizeof(int32_t) * (n + 1));
     c.tleaf.ensure(sizeof(int32_t) * (n + 1));
@@ -157,7 +157,7 @@ void eval(Ctx &c, const double *x, const int32_t *xm, int64_t n, double *phi, do
             dgrad = hgrad.as<double>();
         }
     }
-    if (dxm && !dev) {
+    if (dxm) {      // mesh ids index per-mesh tables in every kernel: checked for device pointers too
         DBuf bad;
         bad.ensure(8);
         LSS_HIP(hipMemsetAsync(bad.p, 0, 8, c.stream));
@@ -172,6 +172,7 @@ void eval(Ctx &c, const double *x, const int32_t *xm, int64_t n, double *phi, do
     c.ev_reset();
     if (c.opt.far_field == LSS_FAR_FMM) {
         launch_soa(c, dx, n, c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>());
+        if (dxm) LSS_HIP(hipMemcpyAsync(c.tmesh.p, dxm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c.stream));
         eval_fmm_targets(c, n, nullptr, dphi, dgrad);
     } else {
     launch_target_keys(c, dx, dxm, n, c.tkey.as<uint64_t>(), c.tperm.as<int32_t>());

@@ -64,8 +64,8 @@ constexpr int kG = 4;          // nodes per pass
 constexpr int kNPT = 4;        // coefficients per thread (p <= 40)
 
 struct Geo {
-    double o[3];
-    double L0;
+    const double *root;         // per-mesh root cubes (corner xyz, side)
+    const int32_t *bmesh;
 };
 
 __global__ __launch_bounds__(kBlk) void k_p2m(const int32_t *__restrict__ nleaf_dev, const int32_t *__restrict__ leaves,
@@ -78,9 +78,10 @@ __global__ __launch_bounds__(kBlk) void k_p2m(const int32_t *__restrict__ nleaf_
     double *nd = smem + 2 * kG * tstride;                 // kG x (rx, ry, rz, ax, ay, az)
     if ((int)blockIdx.x >= *nleaf_dev) return;
     const int32_t b = leaves[blockIdx.x];
-    const double s = ldexp(g.L0, -lev[b]);
-    const double c0 = g.o[0] + (ijk[3 * b] + 0.5) * s, c1 = g.o[1] + (ijk[3 * b + 1] + 0.5) * s,
-                 c2 = g.o[2] + (ijk[3 * b + 2] + 0.5) * s;
+    const double s = box_side(g.root, g.bmesh, b, lev[b]);
+    const double *o = g.root + 4 * g.bmesh[b];
+    const double c0 = o[0] + (ijk[3 * b] + 0.5) * s, c1 = o[1] + (ijk[3 * b + 1] + 0.5) * s,
+                 c2 = o[2] + (ijk[3 * b + 2] + 0.5) * s;
     const double inv4pis = 1.0 / (4.0 * kPi * s);
     // coefficient slots of this thread: (n, m), n = 1..p, m = 0..n enumerated row by row
     int qn[kNPT], qm[kNPT];
@@ -183,14 +184,15 @@ struct GemmArgs {
     int64_t base;               // G_M2M / G_L2L: first child box of the level
     int oct;
     const int32_t *parent, *lev;
-    double L0;
+    const double *root;
+    const int32_t *bmesh;
 };
 
 __device__ inline void pair_of(const GemmArgs &a, int64_t j, int64_t &dst, int64_t &src, double &scale) {
     if (a.mode == G_LIST) {
         dst = (int64_t)(uint32_t)(a.mkey[j] & 0xffffffffu);
         src = a.mval[j];
-        scale = ldexp(1.0, a.lev[dst]) / a.L0;       // 1 / side of the target box
+        scale = 1.0 / box_side(a.root, a.bmesh, (int32_t)dst, a.lev[dst]);   // 1 / side of the target box
     } else {
         const int64_t ch = a.base + 8 * j + a.oct;
         if (a.mode == G_M2M) { src = ch; dst = a.parent[ch]; }
@@ -336,7 +338,7 @@ void build_fmm(Ctx &c) {
     t.L.ensure(sizeof(double) * t.nboxes * ncp);
     LSS_HIP(hipMemsetAsync(t.M.p, 0, sizeof(double) * t.nboxes * ncp, c.stream));
     LSS_HIP(hipMemsetAsync(t.L.p, 0, sizeof(double) * t.nboxes * ncp, c.stream));
-    Geo g{{t.origin[0], t.origin[1], t.origin[2]}, t.L0};
+    Geo g{t.root.as<double>(), t.bmesh.as<int32_t>()};
     // P2M on the non-empty leaves
     DBuf flag, ids, leaves, nleaf;
     flag.ensure(4 * t.nboxes); ids.ensure(4 * t.nboxes); leaves.ensure(4 * t.nboxes); nleaf.ensure(16);
@@ -361,7 +363,8 @@ void build_fmm(Ctx &c) {
         const int64_t base = t.level_begin[lvl], npar = (t.level_begin[lvl + 1] - base) / 8;
         for (int o = 0; o < 8; ++o) {
             GemmArgs a{G_M2M, ncp, npar, t.opM2M.as<double>() + o * per, t.M.as<double>(), t.M.as<double>(), nullptr,
-                       nullptr, base, o, t.parent.as<int32_t>(), t.level.as<int32_t>(), t.L0};
+                       nullptr, base, o, t.parent.as<int32_t>(), t.level.as<int32_t>(), t.root.as<double>(),
+                       t.bmesh.as<int32_t>()};
             gemm(c, a);
         }
     }
@@ -370,7 +373,8 @@ void build_fmm(Ctx &c) {
         const int64_t b0 = t.class_beg[cls], n = t.class_end[cls] - b0;
         GemmArgs a{G_LIST, ncp, n, t.opM2L.as<double>() + (int64_t)t.op_class_slot[cls] * per, t.M.as<double>(),
                    t.L.as<double>(), t.m2l_key2.as<uint64_t>() + b0, t.m2l_val2.as<int32_t>() + b0, 0, 0,
-                   t.parent.as<int32_t>(), t.level.as<int32_t>(), t.L0};
+                   t.parent.as<int32_t>(), t.level.as<int32_t>(), t.root.as<double>(),
+                       t.bmesh.as<int32_t>()};
         gemm(c, a);
     }
     // downward pass: L2L from level 0 to depth-1 into their children
@@ -378,7 +382,8 @@ void build_fmm(Ctx &c) {
         const int64_t base = t.level_begin[lvl], npar = (t.level_begin[lvl + 1] - base) / 8;
         for (int o = 0; o < 8; ++o) {
             GemmArgs a{G_L2L, ncp, npar, t.opL2L.as<double>() + o * per, t.L.as<double>(), t.L.as<double>(), nullptr,
-                       nullptr, base, o, t.parent.as<int32_t>(), t.level.as<int32_t>(), t.L0};
+                       nullptr, base, o, t.parent.as<int32_t>(), t.level.as<int32_t>(), t.root.as<double>(),
+                       t.bmesh.as<int32_t>()};
             gemm(c, a);
         }
     }

@@ -106,9 +106,18 @@ struct NewtonState {
 };
 
 // Octree over the quadrature nodes and the FMM state (far_field = LSS_FAR_FMM).
+// Octree forest: one root cube per mesh.  root[4m .. 4m+2] is the lower
+// corner and root[4m+3] the side of mesh m's cube; level-0 box m is that cube
+// and every box b belongs to the mesh bmesh[b].
+__host__ __device__ inline double box_side(const double *root, const int32_t *bmesh, int32_t b, int lev) {
+    return ldexp(root[4 * bmesh[b] + 3], -lev);
+}
+
 struct Tree {
-    double origin[3] = {0, 0, 0};   // root cube [origin, origin + L0]^3
-    double L0 = 1.0;
+    int nroot = 1;                  // meshes = level-0 boxes
+    int bits = 21;                  // Morton bits per dimension (mesh id above them)
+    std::vector<double> h_root;     // host copy of root (4 per mesh)
+    DBuf root, bmesh;               // double[4 * nroot], int32 per box
     int depth = 0;                  // deepest level
     int64_t nboxes = 0;
     std::vector<int64_t> level_begin;   // box ids of level l: [level_begin[l], level_begin[l+1])
@@ -223,7 +232,7 @@ void launch_newton_output(Ctx &c, int64_t N, double *h, double *xout, int8_t *st
 void build_tree(Ctx &c);
 void build_fmm(Ctx &c);
 void launch_locate_targets(Ctx &c, int64_t n_max, const int32_t *n_dev, const double *tx, const double *ty,
-                           const double *tz, uint64_t *keys, int32_t *idx);
+                           const double *tz, const int32_t *tmesh, uint64_t *keys, int32_t *idx);
 int64_t build_tiles(Ctx &c, int64_t n_max, const int32_t *n_dev, const uint64_t *sorted_keys, int tile,
                     int32_t *sorted_leaf, int32_t *tile_start, int32_t *ntiles_dev);
 int fmm_tile(const Ctx &c);

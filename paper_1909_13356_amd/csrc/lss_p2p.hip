@@ -285,7 +285,7 @@ struct FmmEvalArgs {
     const int32_t *ntiles_dev, *tile_start;
     int64_t n_max;
     const int32_t *n_dev;
-    const int32_t *sleaf;       // leaf of each sorted target (nboxes: outside the root)
+    const int32_t *sleaf;       // leaf of each sorted target (nboxes + m: outside mesh m's root)
     // tiles [tile_start[k], tile_start[k+1]) (the last ends at the target count)
     // hold at most TILE targets of one leaf
     const int32_t *sidx;
@@ -300,12 +300,14 @@ struct FmmEvalArgs {
     int32_t nboxes;
     const double *L;
     int p, ncp;
-    double o0, o1, o2, L0;
+    const double *root;         // per-mesh root cubes (corner xyz, side)
+    const int32_t *bmesh;
     double *pairs;
 };
 
-// The near list of a tile (its leaf's source boxes, or every node outside the
-// root cube) is streamed as one packed sequence: up to TILE ranges at a time
+// The near list of a tile (its leaf's source boxes, or every node of the mesh
+// for targets outside its root cube) is streamed as one packed sequence: up
+// to TILE ranges at a time
 // are prefix-summed in LDS and each chunk of TILE nodes is filled across range
 // boundaries, so no chunk is left partly empty at the end of a small box.
 template <int TILE>
@@ -314,16 +316,17 @@ struct RangeBatch {
     int64_t off[TILE + 1];
 };
 
-// load ranges [e, e + nr) of the leaf (or the single outside range) and
+// load ranges [e, e + nr) of the leaf (or, outside the root cube of mesh
+// `out_mesh` >= 0, that mesh's whole node range: its level-0 box) and
 // prefix-sum their lengths; returns the packed length (uniform)
 template <int TILE>
 __device__ __forceinline__ int64_t load_ranges(const FmmEvalArgs &a, RangeBatch<TILE> &rb, int e, int nr,
-                                               bool outside) {
+                                               int32_t out_mesh) {
     const int t = threadIdx.x;
     int64_t len = 0;
     if (t < nr) {
         int64_t lo, hi;
-        if (outside) { lo = 0; hi = a.nnodes; }
+        if (out_mesh >= 0) { lo = a.nb[out_mesh]; hi = a.ne[out_mesh]; }
         else {
             const int32_t S = a.p2p_src[e + t];
             lo = a.nb[S];
@@ -364,9 +367,10 @@ __device__ __forceinline__ void stage_local(const FmmEvalArgs &a, int32_t B, dou
 
 __device__ __forceinline__ void fmm_l2p(const FmmEvalArgs &a, int32_t B, const double *Ls, double x, double y,
                                         double z, double &ph, double g[3]) {
-    const double s = ldexp(a.L0, -a.lev[B]);
-    const double cx = a.o0 + (a.ijk[3 * B] + 0.5) * s, cy = a.o1 + (a.ijk[3 * B + 1] + 0.5) * s,
-                 cz = a.o2 + (a.ijk[3 * B + 2] + 0.5) * s;
+    const double s = box_side(a.root, a.bmesh, B, a.lev[B]);
+    const double *o = a.root + 4 * a.bmesh[B];
+    const double cx = o[0] + (a.ijk[3 * B] + 0.5) * s, cy = o[1] + (a.ijk[3 * B + 1] + 0.5) * s,
+                 cz = o[2] + (a.ijk[3 * B + 2] + 0.5) * s;
     const double inv = 1.0 / s;
     fmm::l2p(Ls, (x - cx) * inv, (y - cy) * inv, (z - cz) * inv, inv, a.p, ph, g);
 }
@@ -397,7 +401,7 @@ __global__ __launch_bounds__(TILE) void k_eval_fmm_f64(FmmEvalArgs a) {
         for (int eb = e0; eb < e1; eb += TILE) {
             const int nr = e1 - eb < TILE ? e1 - eb : TILE;
             __syncthreads();
-            const int64_t total = load_ranges<TILE>(a, rb, eb, nr, outside);
+            const int64_t total = load_ranges<TILE>(a, rb, eb, nr, outside ? B - a.nboxes : -1);
             npair += (double)total;
             for (int64_t c0 = 0; c0 < total; c0 += TILE) {
                 const int cnt = (int)(total - c0 < TILE ? total - c0 : TILE);
@@ -463,7 +467,7 @@ __global__ __launch_bounds__(TILE) void k_eval_fmm_mixed(FmmEvalArgs a) {
         for (int eb = e0; eb < e1; eb += TILE) {
             const int nr = e1 - eb < TILE ? e1 - eb : TILE;
             __syncthreads();
-            const int64_t total = load_ranges<TILE>(a, rb, eb, nr, outside);
+            const int64_t total = load_ranges<TILE>(a, rb, eb, nr, outside ? B - a.nboxes : -1);
             npair += (double)total;
             for (int64_t c0 = 0; c0 < total; c0 += TILE) {
                 const int cnt = (int)(total - c0 < TILE ? total - c0 : TILE);
@@ -579,8 +583,8 @@ void launch_eval_fmm(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const
     a.L = t.L.as<double>();
     a.p = t.p;
     a.ncp = t.ncp;
-    a.o0 = t.origin[0]; a.o1 = t.origin[1]; a.o2 = t.origin[2];
-    a.L0 = t.L0;
+    a.root = t.root.as<double>();
+    a.bmesh = t.bmesh.as<int32_t>();
     a.pairs = c.pairs.as<double>();
     int64_t g = max_tiles < 16384 ? max_tiles : 16384;
     unsigned grid = (unsigned)(g > 0 ? g : 1);

@@ -3,11 +3,13 @@
 // interactions beyond the cut radius R = cut * sigma use the Laplace double
 // layer, those inside it the full kernel).
 //
-// Tree: the root cube holds every node (padded by 2 R_max); a box is split in
-// eight when it holds more than `leaf_capacity` nodes and its children would
-// still be at least 1/shrink as wide as the largest near radius R_k of its
-// nodes.  All eight children are kept (empty ones too), so the leaves
-// partition the root cube and any target position has a leaf.
+// Tree: a forest with one root cube per mesh, holding that mesh's nodes
+// (padded by 2 R_max); a box is split in eight when it holds more than
+// `leaf_capacity` nodes and its children would still be at least 1/shrink as
+// wide as the largest near radius R_k of its nodes.  All eight children are
+// kept (empty ones too), so the leaves partition each root cube and any target
+// position has a leaf.  Node and target keys carry the mesh id above the
+// Morton bits, so a sort groups them by mesh first; meshes never interact.
 //
 // Lists: one dual-tree traversal over (target box T, source box S) pairs:
 //   same level and admissible (|d|_inf >= 2, |d|^2 >= K, d = integer offset
@@ -19,6 +21,7 @@
 #include <cstring>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "lss_internal.h"
@@ -28,7 +31,6 @@ namespace lss {
 namespace {
 
 constexpr int kBlk = 256;
-constexpr int kMaxLevel = 20;     // 21-bit Morton coordinates
 constexpr int kR = 7;             // class offsets in [-kR, kR]^3
 constexpr int kNClass = (2 * kR + 1) * (2 * kR + 1) * (2 * kR + 1);
 
@@ -44,27 +46,82 @@ __device__ inline uint64_t spread21(uint64_t x) {
     return x;
 }
 
-struct Root {
-    double o[3];
-    double inv;      // 2^21 / L0
-};
-
-__device__ inline uint64_t key21(double x, double y, double z, const Root &r) {
-    double q[3] = {(x - r.o[0]) * r.inv, (y - r.o[1]) * r.inv, (z - r.o[2]) * r.inv};
+// key of a point of mesh m: mesh id above the interleaved `bits`-bit cell
+// coordinates of the point in that mesh's root cube; `inside` tells whether
+// the point lies in the cube (NaN: outside)
+__device__ inline uint64_t point_key(double x, double y, double z, int32_t m, const double *__restrict__ root,
+                                     int bits, bool &inside) {
+    const double *r = root + 4 * m;
+    const double lim = ldexp(1.0, bits), scale = lim / r[3];
+    double q[3] = {(x - r[0]) * scale, (y - r[1]) * scale, (z - r[2]) * scale};
+    inside = q[0] >= 0.0 && q[0] < lim && q[1] >= 0.0 && q[1] < lim && q[2] >= 0.0 && q[2] < lim;
     uint64_t b[3];
     for (int c = 0; c < 3; ++c) {
         double t = q[c];
-        t = t != t ? 0.0 : fmin(fmax(t, 0.0), 2097151.0);
+        t = t != t ? 0.0 : fmin(fmax(t, 0.0), lim - 1.0);
         b[c] = (uint64_t)t;
     }
-    return spread21(b[0]) | (spread21(b[1]) << 1) | (spread21(b[2]) << 2);
+    return ((uint64_t)m << (3 * bits)) | spread21(b[0]) | (spread21(b[1]) << 1) | (spread21(b[2]) << 2);
 }
 
-__global__ void k_node_keys(int64_t n, const Src *__restrict__ src, Root r, uint64_t *keys, int32_t *idx) {
+__device__ inline int32_t mesh_of_node(int64_t k, const int64_t *__restrict__ node_off, int32_t nmesh) {
+    int32_t lo = 0, hi = nmesh;                 // last m with node_off[m] <= k
+    while (hi - lo > 1) {
+        int32_t mid = (lo + hi) >> 1;
+        if (node_off[mid] <= k) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_node_keys(int64_t n, const Src *__restrict__ src, const int64_t *__restrict__ node_off,
+                            int32_t nmesh, const double *__restrict__ root, int bits, uint64_t *keys, int32_t *idx) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    keys[k] = key21(src[k].yx, src[k].yy, src[k].yz, r);
+    bool inside;
+    keys[k] = point_key(src[k].yx, src[k].yy, src[k].yz, mesh_of_node(k, node_off, nmesh), root, bits, inside);
     idx[k] = (int32_t)k;
+}
+
+// per-mesh bounding boxes of the nodes: block (m, g) reduces chunk g of mesh
+// m; min / max fold through an order-preserving map of the doubles to u64
+constexpr int64_t kBoxChunk = 16384;
+
+__device__ inline unsigned long long ordered_bits(double d) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(d);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+
+__global__ void k_mesh_bbox(const int64_t *__restrict__ node_off, const Src *__restrict__ src,
+                            unsigned long long *lo, unsigned long long *hi) {
+    __shared__ unsigned long long sl[3][kBlk], sh[3][kBlk];
+    const int m = blockIdx.x;
+    const int64_t k0 = node_off[m] + (int64_t)blockIdx.y * kBoxChunk;
+    const int64_t k1 = min(node_off[m + 1], k0 + kBoxChunk);
+    if (k0 >= k1) return;
+    unsigned long long a[3] = {~0ull, ~0ull, ~0ull}, b[3] = {0, 0, 0};
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += kBlk) {
+        const double y[3] = {src[k].yx, src[k].yy, src[k].yz};
+        for (int c = 0; c < 3; ++c) {
+            const unsigned long long u = ordered_bits(y[c]);
+            a[c] = u < a[c] ? u : a[c];
+            b[c] = u > b[c] ? u : b[c];
+        }
+    }
+    for (int c = 0; c < 3; ++c) { sl[c][threadIdx.x] = a[c]; sh[c][threadIdx.x] = b[c]; }
+    __syncthreads();
+    for (int st = kBlk / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st)
+            for (int c = 0; c < 3; ++c) {
+                const unsigned long long u = sl[c][threadIdx.x + st], v = sh[c][threadIdx.x + st];
+                sl[c][threadIdx.x] = u < sl[c][threadIdx.x] ? u : sl[c][threadIdx.x];
+                sh[c][threadIdx.x] = v > sh[c][threadIdx.x] ? v : sh[c][threadIdx.x];
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) {
+        atomicMin(&lo[3 * m + threadIdx.x], sl[threadIdx.x][0]);
+        atomicMax(&hi[3 * m + threadIdx.x], sh[threadIdx.x][0]);
+    }
 }
 
 __global__ void k_permute_src(int64_t n, const Src *__restrict__ in, const int32_t *__restrict__ perm, Src *out) {
@@ -98,15 +155,16 @@ __global__ void k_box_rmax(int64_t lb, const int64_t *__restrict__ nb, const int
     if (threadIdx.x == 0) atomicMax(&rmax_bits[b], (unsigned long long)__double_as_longlong(sh[0]));
 }
 
-__global__ void k_split_flags(int64_t lb, int64_t nlev, int level, double L0, int64_t cap, double shrink,
+__global__ void k_split_flags(int64_t lb, int64_t nlev, int level, int max_level, const double *__restrict__ root,
+                              const int32_t *__restrict__ bmesh, int64_t cap, double shrink,
                               const int64_t *__restrict__ nb, const int64_t *__restrict__ ne,
                               const double *__restrict__ rmax, int32_t *flag, int32_t *ids) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nlev) return;
     int64_t b = lb + i;
-    double half = ldexp(L0, -(level + 1));      // side of the children
+    double half = box_side(root, bmesh, (int32_t)b, level + 1);      // side of the children
     int64_t cnt = ne[b] - nb[b];
-    flag[i] = (cnt > cap && half * shrink >= rmax[b] && level < kMaxLevel) ? 1 : 0;
+    flag[i] = (cnt > cap && half * shrink >= rmax[b] && level < max_level) ? 1 : 0;
     ids[i] = (int32_t)b;
 }
 
@@ -119,16 +177,18 @@ __device__ inline int64_t lower_bound_key(const uint64_t *keys, int64_t lo, int6
 }
 
 __global__ void k_make_children(const int32_t *__restrict__ nsplit_dev, const int32_t *__restrict__ split,
-                                int64_t child_base, int level, const uint64_t *__restrict__ keys, int32_t *lev,
-                                int32_t *ijk, int64_t *nb, int64_t *ne, int32_t *child, int32_t *parent,
-                                unsigned long long *maxcnt) {
+                                int64_t child_base, int level, int bits, const uint64_t *__restrict__ keys,
+                                int32_t *lev, int32_t *ijk, int64_t *nb, int64_t *ne, int32_t *child, int32_t *parent,
+                                int32_t *bmesh, unsigned long long *maxcnt) {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= *nsplit_dev) return;
     int32_t b = split[r];
     int64_t first = child_base + 8 * r;
     child[b] = (int32_t)first;
-    const int shift = 3 * (21 - (level + 1));
-    const uint64_t pre = (level == 0) ? 0 : (keys[nb[b]] >> (3 * (21 - level)));
+    // the box holds nodes (it is split), so its first key carries its prefix
+    // (mesh id and the cell bits of the levels above)
+    const int shift = 3 * (bits - (level + 1));
+    const uint64_t pre = keys[nb[b]] >> (3 * (bits - level));
     int64_t lo = nb[b], hi = ne[b];
     int64_t bound[9];
     bound[0] = lo;
@@ -144,6 +204,7 @@ __global__ void k_make_children(const int32_t *__restrict__ nsplit_dev, const in
         ne[q] = bound[c + 1];
         child[q] = -1;
         parent[q] = b;
+        bmesh[q] = bmesh[b];
         atomicMax(maxcnt, (unsigned long long)(bound[c + 1] - bound[c]));
     }
 }
@@ -153,7 +214,8 @@ struct DttArgs {
     const int32_t *lev, *ijk, *child;
     const int64_t *nb, *ne;
     const double *rmax;
-    double L0;
+    const double *root;
+    const int32_t *bmesh;
     int K;
 };
 
@@ -172,7 +234,7 @@ __device__ inline int dtt_action(const DttArgs &a, int32_t T, int32_t S, int &cl
         int m = max(abs(dx), max(abs(dy), abs(dz)));
         // admissible: K-criterion and a gap of at least the cut radius of S's nodes
         if (m >= 2 && dx * dx + dy * dy + dz * dz >= a.K && m <= kR &&
-            (double)(m - 1) * ldexp(a.L0, -lT) >= a.rmax[S]) {
+            (double)(m - 1) * box_side(a.root, a.bmesh, S, lT) >= a.rmax[S]) {
             cls = ((dx + kR) * (2 * kR + 1) + (dy + kR)) * (2 * kR + 1) + (dz + kR);
             return A_M2L;
         }
@@ -253,13 +315,25 @@ __global__ void k_class_ranges(int64_t n, const uint64_t *__restrict__ keys, int
 }
 
 // ----------------------------------------------------------- targets
-// Morton key of each target (bit 63 set outside the root cube); sorting by it
-// groups the targets of a leaf (a leaf is a Morton prefix range) and keeps
-// every wave of a tile spatially compact.
+// Key of each target: mesh id and Morton cell in that mesh's root cube, or
+// bit 63 plus the mesh id outside the cube; sorting by it groups the targets
+// of a leaf (a leaf is a key prefix range) and keeps every wave of a tile
+// spatially compact.  A target's leaf is nboxes + m outside mesh m's cube.
 constexpr uint64_t kOutside = 1ull << 63;
 
+__device__ inline int32_t descend(uint64_t k, int32_t m, int bits, const int32_t *__restrict__ child) {
+    int32_t b = m;
+    int lvl = 0;
+    while (child[b] >= 0) {
+        b = child[b] + (int)((k >> (3 * (bits - (lvl + 1)))) & 7ull);
+        ++lvl;
+    }
+    return b;
+}
+
 __global__ void k_locate(int64_t n_max, const int32_t *__restrict__ n_dev, const double *__restrict__ tx,
-                         const double *__restrict__ ty, const double *__restrict__ tz, Root r, double L0,
+                         const double *__restrict__ ty, const double *__restrict__ tz,
+                         const int32_t *__restrict__ tmesh, const double *__restrict__ root, int bits,
                          uint64_t *keys, int32_t *idx) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t n = n_dev ? (int64_t)*n_dev : n_max;
@@ -269,36 +343,31 @@ __global__ void k_locate(int64_t n_max, const int32_t *__restrict__ n_dev, const
         idx[i] = (int32_t)i;
         return;
     }
-    double q[3] = {(tx[i] - r.o[0]) / L0, (ty[i] - r.o[1]) / L0, (tz[i] - r.o[2]) / L0};
-    bool inside = q[0] >= 0.0 && q[0] < 1.0 && q[1] >= 0.0 && q[1] < 1.0 && q[2] >= 0.0 && q[2] < 1.0;
-    keys[i] = inside ? key21(tx[i], ty[i], tz[i], r) : kOutside;
+    const int32_t m = tmesh ? tmesh[i] : 0;
+    bool inside;
+    const uint64_t k = point_key(tx[i], ty[i], tz[i], m, root, bits, inside);
+    keys[i] = inside ? k : (kOutside | ((uint64_t)m << (3 * bits)));
     idx[i] = (int32_t)i;
 }
 
-// leaf of each sorted target (nboxes outside the root, -1 for unused slots)
+// leaf of each sorted target (nboxes + mesh outside the root, -1 for unused slots)
 __global__ void k_sorted_leaf(int64_t n_max, const int32_t *__restrict__ n_dev, const uint64_t *__restrict__ keys,
-                              const int32_t *__restrict__ child, int32_t nboxes, int32_t *leaf) {
+                              int bits, const int32_t *__restrict__ child, int32_t nboxes, int32_t *leaf) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t n = n_dev ? (int64_t)*n_dev : n_max;
     if (i >= n_max) return;
     if (i >= n) { leaf[i] = -1; return; }
     const uint64_t k = keys[i];
-    if (k & kOutside) { leaf[i] = nboxes; return; }
-    int32_t b = 0;
-    int lvl = 0;
-    while (child[b] >= 0) {
-        int oct = (int)((k >> (3 * (21 - (lvl + 1)))) & 7ull);
-        b = child[b] + oct;
-        ++lvl;
-    }
-    leaf[i] = b;
+    const int32_t m = (int32_t)((k & ~kOutside) >> (3 * bits));
+    leaf[i] = (k & kOutside) ? nboxes + m : descend(k, m, bits, child);
 }
 
 // tile heads: first target of a leaf segment and every TILE-th after it.  The
-// segment of leaf b starts at the first key >= its Morton prefix.
+// segment of leaf b starts at the first key >= its key prefix.
 __global__ void k_tile_flags(int64_t n_max, const int32_t *__restrict__ n_dev, const uint64_t *__restrict__ keys,
                              const int32_t *__restrict__ leaf, const int32_t *__restrict__ lev,
-                             const int32_t *__restrict__ ijk, int32_t nboxes, int tile, int32_t *flag, int32_t *pos) {
+                             const int32_t *__restrict__ ijk, const int32_t *__restrict__ bmesh, int bits,
+                             int32_t nboxes, int tile, int32_t *flag, int32_t *pos) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t n = n_dev ? (int64_t)*n_dev : n_max;
     if (i >= n_max) return;
@@ -306,12 +375,12 @@ __global__ void k_tile_flags(int64_t n_max, const int32_t *__restrict__ n_dev, c
     if (i >= n) { flag[i] = 0; return; }
     const int32_t b = leaf[i];
     uint64_t lo_key;
-    if (b >= nboxes) lo_key = kOutside;
+    if (b >= nboxes) lo_key = kOutside | ((uint64_t)(b - nboxes) << (3 * bits));
     else {
         const int l = lev[b];
         const uint64_t pre = spread21((uint64_t)ijk[3 * b]) | (spread21((uint64_t)ijk[3 * b + 1]) << 1) |
                              (spread21((uint64_t)ijk[3 * b + 2]) << 2);
-        lo_key = pre << (3 * (21 - l));
+        lo_key = ((uint64_t)bmesh[b] << (3 * bits)) | (pre << (3 * (bits - l)));
     }
     int64_t lo = 0, hi = i;           // first index with key >= lo_key
     while (lo < hi) {
@@ -321,25 +390,19 @@ __global__ void k_tile_flags(int64_t n_max, const int32_t *__restrict__ n_dev, c
     flag[i] = ((i - lo) % tile) == 0 ? 1 : 0;
 }
 
-// leaf of each target in its current order (nboxes outside the root, -1 unused)
+// leaf of each target in its current order (nboxes + mesh outside the root, -1 unused)
 __global__ void k_leaf_direct(int64_t n_max, const int32_t *__restrict__ n_dev, const double *__restrict__ tx,
-                              const double *__restrict__ ty, const double *__restrict__ tz, Root r, double L0,
+                              const double *__restrict__ ty, const double *__restrict__ tz,
+                              const int32_t *__restrict__ tmesh, const double *__restrict__ root, int bits,
                               const int32_t *__restrict__ child, int32_t nboxes, int32_t *leaf) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t n = *n_dev;
     if (i >= n_max) return;
     if (i >= n) { leaf[i] = -1; return; }
-    double q[3] = {(tx[i] - r.o[0]) / L0, (ty[i] - r.o[1]) / L0, (tz[i] - r.o[2]) / L0};
-    bool inside = q[0] >= 0.0 && q[0] < 1.0 && q[1] >= 0.0 && q[1] < 1.0 && q[2] >= 0.0 && q[2] < 1.0;
-    if (!inside) { leaf[i] = nboxes; return; }
-    const uint64_t k = key21(tx[i], ty[i], tz[i], r);
-    int32_t b = 0;
-    int lvl = 0;
-    while (child[b] >= 0) {
-        b = child[b] + (int)((k >> (3 * (21 - (lvl + 1)))) & 7ull);
-        ++lvl;
-    }
-    leaf[i] = b;
+    const int32_t m = tmesh ? tmesh[i] : 0;
+    bool inside;
+    const uint64_t k = point_key(tx[i], ty[i], tz[i], m, root, bits, inside);
+    leaf[i] = inside ? descend(k, m, bits, child) : nboxes + m;
 }
 
 __global__ void k_tile_flags_runs(int64_t n_max, const int32_t *__restrict__ n_dev, const int32_t *__restrict__ leaf,
@@ -359,11 +422,18 @@ __global__ void k_soa(int64_t n, const double *__restrict__ x, double *tx, doubl
     tz[i] = x[3 * i + 2];
 }
 
-Root make_root(const Tree &t) {
-    Root r;
-    for (int k = 0; k < 3; ++k) r.o[k] = t.origin[k];
-    r.inv = 2097152.0 / t.L0;
-    return r;
+__global__ void k_level0(int32_t nmesh, const int64_t *__restrict__ node_off, int32_t *lev, int32_t *ijk,
+                         int64_t *nb, int64_t *ne, int32_t *child, int32_t *parent, int32_t *bmesh, uint64_t *fr) {
+    int32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= nmesh) return;
+    lev[m] = 0;
+    ijk[3 * m] = ijk[3 * m + 1] = ijk[3 * m + 2] = 0;
+    nb[m] = node_off[m];
+    ne[m] = node_off[m + 1];
+    child[m] = -1;
+    parent[m] = -1;
+    bmesh[m] = m;
+    fr[m] = ((uint64_t)(uint32_t)m << 32) | (uint32_t)m;     // traversal starts at (root, root)
 }
 
 }  // namespace
@@ -372,22 +442,63 @@ Root make_root(const Tree &t) {
 void build_tree(Ctx &c) {
     Tree &t = c.tree;
     const int64_t n = c.nnodes;
-    if (c.nmesh > 1) throw Error{LSS_EINVAL, "far_field = LSS_FAR_FMM supports one mesh per context"};
+    const int32_t nm = c.nmesh;
     const double cut = c.opt.cut_factor > 0 ? c.opt.cut_factor : (c.opt.precision == LSS_MIXED ? kCutMixed : kCutFP64);
     const int64_t cap = c.opt.leaf_capacity > 0 ? c.opt.leaf_capacity : (c.opt.precision == LSS_MIXED ? 256 : 128);
     const double shrink = c.opt.leaf_shrink > 0 ? c.opt.leaf_shrink : (c.opt.precision == LSS_MIXED ? 1.0 : 2.0);
     t.K = c.opt.precision == LSS_MIXED ? 4 : 8;
-    // root cube: node bounding box padded by 2 R_max on every side
-    double rmax = cut * c.sigma_max, ext = 0.0;
-    for (int k = 0; k < 3; ++k) ext = fmax(ext, c.bbox_hi[k] - c.bbox_lo[k]);
-    t.L0 = ext + 4.0 * rmax;
-    t.L0 *= 1.0 + 1e-9;
-    for (int k = 0; k < 3; ++k) t.origin[k] = 0.5 * (c.bbox_lo[k] + c.bbox_hi[k]) - 0.5 * t.L0;
-    Root root = make_root(t);
-    // nodes in Morton order
+    // key layout: mesh id above `bits` Morton bits per dimension, bit 63 free
+    int mb = 0;
+    while ((int64_t(1) << mb) < nm) ++mb;
+    t.bits = std::min(21, (63 - mb) / 3);
+    t.nroot = nm;
+    // root cube per mesh: its nodes' bounding box padded by 2 R_max on every side
+    const double rmax = cut * c.sigma_max;
+    std::vector<double> lo(3 * nm), hi(3 * nm);
+    if (nm == 1) {
+        for (int k = 0; k < 3; ++k) { lo[k] = c.bbox_lo[k]; hi[k] = c.bbox_hi[k]; }
+    } else {
+        DBuf bb;
+        bb.ensure(sizeof(unsigned long long) * 6 * nm);
+        std::vector<unsigned long long> init(6 * nm);
+        for (int i = 0; i < 3 * nm; ++i) { init[i] = ~0ull; init[3 * nm + i] = 0ull; }
+        LSS_HIP(hipMemcpyAsync(bb.p, init.data(), 8 * init.size(), hipMemcpyHostToDevice, c.stream));
+        int64_t most = 0;
+        for (int m = 0; m < nm; ++m) most = std::max(most, (c.h_tri_off[m + 1] - c.h_tri_off[m]) * c.nq);
+        const unsigned gy = (unsigned)ceil_div(most > 0 ? most : 1, kBoxChunk);
+        unsigned long long *ulo = bb.as<unsigned long long>(), *uhi = ulo + 3 * nm;
+        hipLaunchKernelGGL(k_mesh_bbox, dim3((unsigned)nm, gy), dim3(kBlk), 0, c.stream, c.node_off.as<int64_t>(),
+                           c.src.as<Src>(), ulo, uhi);
+        LSS_CHECK_LAUNCH("k_mesh_bbox");
+        LSS_HIP(hipMemcpyAsync(init.data(), bb.p, 8 * init.size(), hipMemcpyDeviceToHost, c.stream));
+        LSS_HIP(hipStreamSynchronize(c.stream));
+        auto unmap = [](unsigned long long u) {
+            u = (u >> 63) ? (u & 0x7fffffffffffffffull) : ~u;
+            double d;
+            std::memcpy(&d, &u, 8);
+            return d;
+        };
+        for (int i = 0; i < 3 * nm; ++i) {
+            if (init[i] == ~0ull) { lo[i] = 0.0; hi[i] = 0.0; continue; }     // mesh without nodes
+            lo[i] = unmap(init[i]);
+            hi[i] = unmap(init[3 * nm + i]);
+        }
+    }
+    t.h_root.assign(4 * nm, 0.0);
+    for (int m = 0; m < nm; ++m) {
+        double ext = 0.0;
+        for (int k = 0; k < 3; ++k) ext = fmax(ext, hi[3 * m + k] - lo[3 * m + k]);
+        const double L0 = (ext + 4.0 * rmax) * (1.0 + 1e-9);
+        for (int k = 0; k < 3; ++k) t.h_root[4 * m + k] = 0.5 * (lo[3 * m + k] + hi[3 * m + k]) - 0.5 * L0;
+        t.h_root[4 * m + 3] = L0 > 0.0 ? L0 : 1.0;
+    }
+    t.root.ensure(sizeof(double) * 4 * nm);
+    LSS_HIP(hipMemcpyAsync(t.root.p, t.h_root.data(), sizeof(double) * 4 * nm, hipMemcpyHostToDevice, c.stream));
+    // nodes in key order (mesh, then Morton)
     t.key.ensure(8 * n); t.key2.ensure(8 * n); t.perm.ensure(4 * n); t.perm2.ensure(4 * n);
-    hipLaunchKernelGGL(k_node_keys, dim3(grid_for(n)), dim3(kBlk), 0, c.stream, n, c.src.as<Src>(), root,
-                       t.key.as<uint64_t>(), t.perm.as<int32_t>());
+    hipLaunchKernelGGL(k_node_keys, dim3(grid_for(n)), dim3(kBlk), 0, c.stream, n, c.src.as<Src>(),
+                       c.node_off.as<int64_t>(), nm, t.root.as<double>(), t.bits, t.key.as<uint64_t>(),
+                       t.perm.as<int32_t>());
     LSS_CHECK_LAUNCH("k_node_keys");
     sort_pairs(c, t.key.as<uint64_t>(), t.key2.as<uint64_t>(), t.perm.as<int32_t>(), t.perm2.as<int32_t>(), n, 63);
     t.src.ensure(sizeof(Src) * n);
@@ -395,8 +506,8 @@ void build_tree(Ctx &c) {
                        t.perm2.as<int32_t>(), t.src.as<Src>());
     LSS_CHECK_LAUNCH("k_permute_src");
     const uint64_t *keys = t.key2.as<uint64_t>();
-    // level 0
-    int64_t cap_boxes = 1024;
+    // level 0: one root box per mesh
+    int64_t cap_boxes = std::max<int64_t>(1024, 2 * (int64_t)nm);
     auto grow = [&](int64_t need, int64_t have) {
         if (need <= cap_boxes && t.level.p) return;
         int64_t nc = need > cap_boxes ? need + need / 2 : cap_boxes;
@@ -406,26 +517,22 @@ void build_tree(Ctx &c) {
         t.ne.grow_copy(8 * nc, 8 * have, c.stream);
         t.child.grow_copy(4 * nc, 4 * have, c.stream);
         t.parent.grow_copy(4 * nc, 4 * have, c.stream);
+        t.bmesh.grow_copy(4 * nc, 4 * have, c.stream);
         t.rmax.grow_copy(8 * nc, 8 * have, c.stream);
         cap_boxes = nc;
     };
     t.level.release(); t.ijk.release(); t.nb.release(); t.ne.release(); t.child.release(); t.parent.release();
-    t.rmax.release();
-    grow(1024, 0);
-    {
-        int32_t lv = 0, ij[3] = {0, 0, 0}, ch = -1, pa = -1;
-        int64_t b0 = 0, e0 = n;
-        LSS_HIP(hipMemcpyAsync(t.level.p, &lv, 4, hipMemcpyHostToDevice, c.stream));
-        LSS_HIP(hipMemcpyAsync(t.ijk.p, ij, 12, hipMemcpyHostToDevice, c.stream));
-        LSS_HIP(hipMemcpyAsync(t.nb.p, &b0, 8, hipMemcpyHostToDevice, c.stream));
-        LSS_HIP(hipMemcpyAsync(t.ne.p, &e0, 8, hipMemcpyHostToDevice, c.stream));
-        LSS_HIP(hipMemcpyAsync(t.child.p, &ch, 4, hipMemcpyHostToDevice, c.stream));
-        LSS_HIP(hipMemcpyAsync(t.parent.p, &pa, 4, hipMemcpyHostToDevice, c.stream));
-        LSS_HIP(hipStreamSynchronize(c.stream));
-    }
-    t.level_begin.assign({0, 1});
+    t.bmesh.release(); t.rmax.release();
+    grow(cap_boxes, 0);
+    t.fr.ensure(8 * std::max<int64_t>(64, nm));
+    hipLaunchKernelGGL(k_level0, dim3(grid_for(nm)), dim3(kBlk), 0, c.stream, nm, c.node_off.as<int64_t>(),
+                       t.level.as<int32_t>(), t.ijk.as<int32_t>(), t.nb.as<int64_t>(), t.ne.as<int64_t>(),
+                       t.child.as<int32_t>(), t.parent.as<int32_t>(), t.bmesh.as<int32_t>(), t.fr.as<uint64_t>());
+    LSS_CHECK_LAUNCH("k_level0");
+    t.level_begin.assign({0, (int64_t)nm});
     DBuf flag, ids, split, nsplit;
-    int64_t maxcnt = n;                     // largest node count of a box of the current level
+    int64_t maxcnt = 0;                     // largest node count of a box of the current level
+    for (int m = 0; m < nm; ++m) maxcnt = std::max(maxcnt, (c.h_tri_off[m + 1] - c.h_tri_off[m]) * c.nq);
     for (int lvl = 0;; ++lvl) {
         int64_t lb = t.level_begin[lvl], le = t.level_begin[lvl + 1], nl = le - lb;
         LSS_HIP(hipMemsetAsync(t.rmax.as<double>() + lb, 0, sizeof(double) * nl, c.stream));
@@ -434,9 +541,9 @@ void build_tree(Ctx &c) {
                            t.ne.as<int64_t>(), t.src.as<Src>(), cut, reinterpret_cast<unsigned long long *>(t.rmax.p));
         LSS_CHECK_LAUNCH("k_box_rmax");
         flag.ensure(4 * nl); ids.ensure(4 * nl); split.ensure(4 * nl); nsplit.ensure(16);
-        hipLaunchKernelGGL(k_split_flags, dim3(grid_for(nl)), dim3(kBlk), 0, c.stream, lb, nl, lvl, t.L0, cap, shrink,
-                           t.nb.as<int64_t>(), t.ne.as<int64_t>(), t.rmax.as<double>(), flag.as<int32_t>(),
-                           ids.as<int32_t>());
+        hipLaunchKernelGGL(k_split_flags, dim3(grid_for(nl)), dim3(kBlk), 0, c.stream, lb, nl, lvl, t.bits - 1,
+                           t.root.as<double>(), t.bmesh.as<int32_t>(), cap, shrink, t.nb.as<int64_t>(),
+                           t.ne.as<int64_t>(), t.rmax.as<double>(), flag.as<int32_t>(), ids.as<int32_t>());
         LSS_CHECK_LAUNCH("k_split_flags");
         compact_flags(c, nl, nullptr, flag.as<int32_t>(), ids.as<int32_t>(), split.as<int32_t>(), nsplit.as<int32_t>());
         int32_t ns = 0;
@@ -448,8 +555,9 @@ void build_tree(Ctx &c) {
         unsigned long long *mc = reinterpret_cast<unsigned long long *>(nsplit.as<int32_t>() + 2);
         LSS_HIP(hipMemsetAsync(mc, 0, 8, c.stream));
         hipLaunchKernelGGL(k_make_children, dim3(grid_for(ns)), dim3(kBlk), 0, c.stream, nsplit.as<int32_t>(),
-                           split.as<int32_t>(), child_base, lvl, keys, t.level.as<int32_t>(), t.ijk.as<int32_t>(),
-                           t.nb.as<int64_t>(), t.ne.as<int64_t>(), t.child.as<int32_t>(), t.parent.as<int32_t>(), mc);
+                           split.as<int32_t>(), child_base, lvl, t.bits, keys, t.level.as<int32_t>(),
+                           t.ijk.as<int32_t>(), t.nb.as<int64_t>(), t.ne.as<int64_t>(), t.child.as<int32_t>(),
+                           t.parent.as<int32_t>(), t.bmesh.as<int32_t>(), mc);
         LSS_CHECK_LAUNCH("k_make_children");
         unsigned long long hm = 0;
         LSS_HIP(hipMemcpyAsync(&hm, mc, 8, hipMemcpyDeviceToHost, c.stream));
@@ -460,14 +568,9 @@ void build_tree(Ctx &c) {
     t.nboxes = t.level_begin.back();
     // ---------------------------------------------------- dual traversal
     DttArgs a{t.level.as<int32_t>(), t.ijk.as<int32_t>(), t.child.as<int32_t>(), t.nb.as<int64_t>(),
-              t.ne.as<int64_t>(), t.rmax.as<double>(), t.L0, t.K};
+              t.ne.as<int64_t>(), t.rmax.as<double>(), t.root.as<double>(), t.bmesh.as<int32_t>(), t.K};
     t.cnt.ensure(8 * 8);
-    int64_t nfr = 1;
-    t.fr.ensure(8 * 64);
-    {
-        uint64_t rr = 0;
-        LSS_HIP(hipMemcpyAsync(t.fr.p, &rr, 8, hipMemcpyHostToDevice, c.stream));
-    }
+    int64_t nfr = nm;                       // (root m, root m) pairs written by k_level0
     t.n_m2l = 0;
     t.n_p2p = 0;
     int64_t cap_m2l = 0, cap_p2p = 0;
@@ -544,10 +647,10 @@ void launch_soa(Ctx &c, const double *x, int64_t n, double *tx, double *ty, doub
 }
 
 void launch_locate_targets(Ctx &c, int64_t n_max, const int32_t *n_dev, const double *tx, const double *ty,
-                           const double *tz, uint64_t *keys, int32_t *idx) {
+                           const double *tz, const int32_t *tmesh, uint64_t *keys, int32_t *idx) {
     Tree &t = c.tree;
     hipLaunchKernelGGL(k_locate, dim3(grid_for(n_max)), dim3(kBlk), 0, c.stream, n_max, n_dev, tx, ty, tz,
-                       make_root(t), t.L0, keys, idx);
+                       t.nroot > 1 ? tmesh : nullptr, t.root.as<double>(), t.bits, keys, idx);
     LSS_CHECK_LAUNCH("k_locate");
 }
 
@@ -560,11 +663,11 @@ int64_t build_tiles(Ctx &c, int64_t n_max, const int32_t *n_dev, const uint64_t 
     fl.ensure(4 * (n_max + 1));
     pos.ensure(4 * (n_max + 1));
     hipLaunchKernelGGL(k_sorted_leaf, dim3(grid_for(n_max)), dim3(kBlk), 0, c.stream, n_max, n_dev, sorted_keys,
-                       t.child.as<int32_t>(), (int32_t)t.nboxes, sorted_leaf);
+                       t.bits, t.child.as<int32_t>(), (int32_t)t.nboxes, sorted_leaf);
     LSS_CHECK_LAUNCH("k_sorted_leaf");
     hipLaunchKernelGGL(k_tile_flags, dim3(grid_for(n_max)), dim3(kBlk), 0, c.stream, n_max, n_dev, sorted_keys,
-                       sorted_leaf, t.level.as<int32_t>(), t.ijk.as<int32_t>(), (int32_t)t.nboxes, tile,
-                       fl.as<int32_t>(), pos.as<int32_t>());
+                       sorted_leaf, t.level.as<int32_t>(), t.ijk.as<int32_t>(), t.bmesh.as<int32_t>(), t.bits,
+                       (int32_t)t.nboxes, tile, fl.as<int32_t>(), pos.as<int32_t>());
     LSS_CHECK_LAUNCH("k_tile_flags");
     compact_flags(c, n_max, nullptr, fl.as<int32_t>(), pos.as<int32_t>(), tile_start, ntiles_dev);
     return n_max;
@@ -588,8 +691,8 @@ void build_tiles_unsorted(Ctx &c, int64_t n_max, const int32_t *n_dev, int tile)
     Tree &t = c.tree;
     int32_t *leaf = c.tleaf.as<int32_t>();
     hipLaunchKernelGGL(k_leaf_direct, dim3(grid_for(n_max)), dim3(kBlk), 0, c.stream, n_max, n_dev, c.tx.as<double>(),
-                       c.ty.as<double>(), c.tz.as<double>(), make_root(t), t.L0, t.child.as<int32_t>(),
-                       (int32_t)t.nboxes, leaf);
+                       c.ty.as<double>(), c.tz.as<double>(), t.nroot > 1 ? c.tmesh.as<int32_t>() : nullptr,
+                       t.root.as<double>(), t.bits, t.child.as<int32_t>(), (int32_t)t.nboxes, leaf);
     LSS_CHECK_LAUNCH("k_leaf_direct");
     hipLaunchKernelGGL(k_tile_flags_runs, dim3(grid_for(n_max)), dim3(kBlk), 0, c.stream, n_max, n_dev, leaf, tile,
                        c.tflag.as<int32_t>(), c.tpos.as<int32_t>());

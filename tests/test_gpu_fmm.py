@@ -163,3 +163,70 @@ def test_fmm_project_repeated(graded):
             eh = np.max(np.abs(h[idx] - ho) / sig[sel].repeat(len(uv)))
             say("  np %d e_h %.3e iters max %d" % (len(uv), eh, it.max()))
             assert eh <= (1e-11 if prec == lss.FP64 else 2e-6)
+
+
+@pytest.fixture(scope="module")
+def batch():
+    """Five star-shaped surfaces of uneven size that overlap in space (any
+    leak between meshes would show), per-triangle sigma, near-surface,
+    box and far targets per mesh."""
+    from workloads import configs, star_surface, bbox_targets
+    meshes = []
+    for i, (nu, shift) in enumerate([(12, 0.0), (4, 0.3), (20, 0.1), (2, 5.0), (9, -0.2)]):
+        v, tt = star_surface(nu, lmax=8, var0=0.1, seed=40 + i)
+        v = v + shift
+        sig = 0.5 * triangle_diameters(v, tt)
+        x = np.concatenate([surface_offset_targets(v, tt, sig, 1500, tmax=3.0, seed=60 + i),
+                            bbox_targets(v, 300, pad=0.25, seed=80 + i),
+                            shift + np.array([[12.0, 0.0, 0.0], [0.0, -9.0, 3.0]])])
+        meshes.append(dict(verts=v, tris=tt, sigma=sig, targets=x))
+    return configs.concat_batch(meshes)
+
+
+def bctx(b, prec, far, **kw):
+    c = lss.Context()
+    c.set_sources(b["verts"], b["tris"], dunavant6(), tri_offsets=b["tri_offsets"])
+    c.set_sigma(b["sigma"])
+    c.set_options(precision=prec, far_field=far, **kw)
+    return c
+
+
+@pytest.mark.parametrize("prec", [lss.FP64, lss.MIXED])
+def test_fmm_batch_vs_direct_and_oracle(batch, prec):
+    b = batch
+    say("case: FMM forest, batch of %d meshes, %d tri, %d targets, precision %d" % (
+        len(b["tri_offsets"]) - 1, len(b["tris"]), len(b["targets"]), prec))
+    cf = bctx(b, prec, lss.FAR_FMM)
+    pf, gf = cf.eval(b["targets"], x_mesh=b["target_mesh"])
+    cd = bctx(b, lss.FP64, lss.FAR_DIRECT)
+    pd, gd = cd.eval(b["targets"], x_mesh=b["target_mesh"])
+    ep, eg = errs(pf, gf, pd, gd)
+    say("  vs direct: e_phi %.3e e_grad %.3e" % (ep, eg))
+    assert ep <= TOL[prec] and eg <= TOL[prec]
+    sel = np.arange(0, len(b["targets"]), 23)
+    po, go = oracle.evaluate(b["verts"], b["tris"], b["sigma"], dunavant6(), b["targets"][sel],
+                             tri_offsets=b["tri_offsets"], x_mesh=b["target_mesh"][sel])
+    ep, eg = errs(pf[sel], gf[sel], po, go)
+    say("  vs oracle: e_phi %.3e e_grad %.3e" % (ep, eg))
+    assert ep <= TOL[prec] and eg <= TOL[prec]
+    st = cf.stats()
+    assert st["n_mesh"] == 5 and st["n_boxes"] >= 5
+
+
+def test_fmm_batch_project_vs_oracle(batch):
+    b = batch
+    uv = chart_nodes(2)
+    ntri = len(b["tris"])
+    sel = np.arange(0, ntri, 31)
+    idx = (sel[:, None] * len(uv) + np.arange(len(uv))[None]).ravel()
+    for prec in (lss.FP64, lss.MIXED):
+        say("case: FMM forest projection, precision %d" % prec)
+        cf = bctx(b, prec, lss.FAR_FMM)
+        h, xs, st, it = cf.project(uv)
+        tau = 1e-12 if prec == lss.FP64 else 1e-6
+        ho, xo, sto, ito = oracle.project(b["verts"], b["tris"], b["sigma"], dunavant6(), uv, tau=tau, sel=sel,
+                                          tri_offsets=b["tri_offsets"])
+        assert np.all(st[idx] == sto)
+        eh = np.max(np.abs(h[idx] - ho) / b["sigma"][sel].repeat(len(uv)))
+        say("  e_h %.3e iters max %d" % (eh, it.max()))
+        assert eh <= (1e-11 if prec == lss.FP64 else 2e-6)
