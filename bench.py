@@ -131,6 +131,65 @@ def time_newton(lss, torch, cfg, prec, steps, warmup):
             "evals_per_node": evals / steps / n_nodes, "converged_frac": conv}
 
 
+def time_batch(lss, torch, b, uv, prec, per_surface):
+    """One pass over the batch of surfaces: build, Phi / grad Phi at the
+    random targets of every surface, Newton projection of every chart node.
+    Batched: one context holds all surfaces (one build, one evaluation, one
+    projection).  Per surface: the same work surface by surface."""
+    dev = torch.device("cuda")
+    r = torch.as_tensor(b["rule"], device=dev)
+    uvd = torch.as_tensor(uv, device=dev)
+    off = b["tri_offsets"]
+    if per_surface:
+        parts = []
+        for m in range(len(off) - 1):
+            t0, t1 = off[m], off[m + 1]
+            tris = b["tris"][t0:t1]
+            v0 = tris.min()
+            sel = b["target_mesh"] == m
+            parts.append(dict(v=torch.as_tensor(b["verts"][v0:tris.max() + 1], device=dev),
+                              t=torch.as_tensor(tris - v0, device=dev),
+                              s=torch.as_tensor(b["sigma"][t0:t1], device=dev),
+                              x=torch.as_tensor(b["targets"][sel], device=dev)))
+    else:
+        parts = [dict(v=torch.as_tensor(b["verts"], device=dev), t=torch.as_tensor(b["tris"], device=dev),
+                      s=torch.as_tensor(b["sigma"], device=dev), x=torch.as_tensor(b["targets"], device=dev),
+                      xm=torch.as_tensor(b["target_mesh"], device=dev),
+                      off=torch.as_tensor(b["tri_offsets"], device=dev))]
+    ctxs = []
+    for q in parts:
+        c = lss.Context(0)
+        c.set_sources(q["v"], q["t"], r, tri_offsets=q.get("off"))
+        c.set_options(precision=prec, far_field=lss.FAR_FMM)
+        ctxs.append(c)
+
+    conv = [0, 0]
+
+    def step():
+        evals = 0
+        conv[0] = conv[1] = 0
+        for c, q in zip(ctxs, parts):
+            c.set_sigma(q["s"])
+            c.eval(q["x"], x_mesh=q.get("xm"))
+            h, x, st, it = c.project(uvd, device=True)
+            evals += q["x"].shape[0] + c.stats()["last_targets"]
+            conv[0] += int((st == 0).sum().item())
+            conv[1] += st.shape[0]
+        return evals
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evals = step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    for c in ctxs:
+        c.close()
+    n_nodes = len(b["tris"]) * len(uv)
+    return {"ms_per_step": 1e3 * el, "target_evals_per_s": evals / el, "chart_nodes_per_s": n_nodes / el,
+            "contexts": len(ctxs), "converged_frac": conv[0] / max(conv[1], 1)}
+
+
 def cpu_newton(cfg, n_tris=4):
     """The oracle's Newton projection (FP64 direct sum per evaluation) on the
     chart nodes of a few seeded triangles: about 10 s of CPU work."""
@@ -175,6 +234,7 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-newton", action="store_true", help="skip the chart-projection measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batch-of-surfaces measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the path is single-GPU; see DESIGN.md "
@@ -233,6 +293,25 @@ def main():
             log("bench: timing the CPU oracle Newton on a sample")
             newton["cpu_baseline"] = cpu_newton(c3)
         out["newton"] = newton
+    if not args.no_batch:
+        from workloads import configs
+        log("bench: building the batch of surfaces")
+        c4 = configs.config4()
+        b = configs.concat_batch(c4["meshes"])
+        b["rule"] = c4["rule"]
+        nt, nx = len(b["tris"]), len(b["targets"])
+        batch = {"workload": "%d star-shaped surfaces, %d..%d tri each (%d tri, %d nodes), sigma_j = D_j/2, "
+                             "%d random targets + %d chart nodes, octree forest + FMM" % (
+                                 len(c4["meshes"]), min(len(m["tris"]) for m in c4["meshes"]),
+                                 max(len(m["tris"]) for m in c4["meshes"]), nt, 12 * nt, nx, 45 * nt)}
+        for prec, name in ((lss.MIXED, "mixed"), (lss.FP64, "f64")):
+            log("bench: batch", name)
+            batch[name] = time_batch(lss, torch, b, c4["chart_uv"], prec, per_surface=False)
+            log("bench: batch", name, json.dumps(batch[name]))
+        log("bench: per-surface mixed")
+        batch["mixed_per_surface"] = time_batch(lss, torch, b, c4["chart_uv"], lss.MIXED, per_surface=True)
+        log("bench: per-surface mixed", json.dumps(batch["mixed_per_surface"]))
+        out["batch"] = batch
     print(json.dumps(out), flush=True)
 
 

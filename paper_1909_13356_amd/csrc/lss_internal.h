@@ -113,6 +113,35 @@ __host__ __device__ inline double box_side(const double *root, const int32_t *bm
     return ldexp(root[4 * bmesh[b] + 3], -lev);
 }
 
+__device__ inline uint64_t tree_spread21(uint64_t x) {     // 21 bits -> every third bit
+    x &= 0x1fffffull;
+    x = (x | (x << 32)) & 0x1f00000000ffffull;
+    x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+// tree key of a point of mesh m: mesh id above the interleaved `bits`-bit
+// cell coordinates of the point in that mesh's root cube; `inside` tells
+// whether the point lies in the cube (NaN: outside)
+__device__ inline uint64_t tree_point_key(double x, double y, double z, int32_t m, const double *__restrict__ root,
+                                          int bits, bool &inside) {
+    const double *r = root + 4 * m;
+    const double lim = ldexp(1.0, bits), scale = lim / r[3];
+    double q[3] = {(x - r[0]) * scale, (y - r[1]) * scale, (z - r[2]) * scale};
+    inside = q[0] >= 0.0 && q[0] < lim && q[1] >= 0.0 && q[1] < lim && q[2] >= 0.0 && q[2] < lim;
+    uint64_t b[3];
+    for (int c = 0; c < 3; ++c) {
+        double t = q[c];
+        t = t != t ? 0.0 : fmin(fmax(t, 0.0), lim - 1.0);
+        b[c] = (uint64_t)t;
+    }
+    return ((uint64_t)m << (3 * bits)) | tree_spread21(b[0]) | (tree_spread21(b[1]) << 1) |
+           (tree_spread21(b[2]) << 2);
+}
+
 struct Tree {
     int nroot = 1;                  // meshes = level-0 boxes
     int bits = 21;                  // Morton bits per dimension (mesh id above them)

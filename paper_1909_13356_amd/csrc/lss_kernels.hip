@@ -255,15 +255,20 @@ __device__ inline void chart_TH(const double *__restrict__ verts, const int32_t 
 
 __global__ void k_chart_keys(int64_t N, const double *__restrict__ verts, const int32_t *__restrict__ tris,
                              const double *__restrict__ vH, const double *__restrict__ uv, int32_t np,
-                             const int64_t *__restrict__ tri_off, int32_t nmesh, Box box, uint64_t *keys,
-                             int32_t *idx) {
+                             const int64_t *__restrict__ tri_off, int32_t nmesh, Box box,
+                             const double *__restrict__ troot, int tbits, uint64_t *keys, int32_t *idx) {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= N) return;
     double T[3], H[3];
     int64_t j;
     chart_TH(verts, tris, vH, uv, np, q, T, H, j);
     uint64_t m = nmesh > 1 ? (uint64_t)mesh_of_tri(tri_off, nmesh, j) : 0;
-    keys[q] = (m << 48) | morton_key(T[0], T[1], T[2], box.lo, box.inv);
+    if (troot) {        // octree order: the nodes of a leaf are contiguous
+        bool inside;
+        keys[q] = tree_point_key(T[0], T[1], T[2], (int32_t)m, troot, tbits, inside);
+    } else {
+        keys[q] = (m << 48) | morton_key(T[0], T[1], T[2], box.lo, box.inv);
+    }
     idx[q] = (int32_t)q;
 }
 
@@ -565,13 +570,15 @@ void launch_gather_targets(Ctx &c, const double *x, const int32_t *x_mesh, const
 
 void launch_chart_init(Ctx &c, const double *uv, int32_t np, int64_t N) {
     NewtonState &s = c.ns;
+    const bool fmm = c.opt.far_field == LSS_FAR_FMM && c.tree.root.p != nullptr;
     c.tkey.ensure(sizeof(uint64_t) * N);
     c.tkey2.ensure(sizeof(uint64_t) * N);
     c.tperm.ensure(sizeof(int32_t) * N);
     c.tperm2.ensure(sizeof(int32_t) * N);
     hipLaunchKernelGGL(k_chart_keys, dim3(grid_for(N)), dim3(kBlk), 0, c.stream, N, c.verts.as<double>(),
                        c.tris.as<int32_t>(), c.vH.as<double>(), uv, np, c.tri_off.as<int64_t>(), c.nmesh,
-                       make_box(c), c.tkey.as<uint64_t>(), c.tperm.as<int32_t>());
+                       make_box(c), fmm ? c.tree.root.as<double>() : nullptr, c.tree.bits, c.tkey.as<uint64_t>(),
+                       c.tperm.as<int32_t>());
     LSS_CHECK_LAUNCH("k_chart_keys");
     size_t tb = sort_pairs_u64_tmp_bytes(N);
     c.sort_tmp.ensure(tb);

@@ -36,32 +36,11 @@ constexpr int kNClass = (2 * kR + 1) * (2 * kR + 1) * (2 * kR + 1);
 
 inline unsigned grid_for(int64_t n, int blk = kBlk) { return (unsigned)ceil_div(n > 0 ? n : 1, blk); }
 
-__device__ inline uint64_t spread21(uint64_t x) {
-    x &= 0x1fffffull;
-    x = (x | (x << 32)) & 0x1f00000000ffffull;
-    x = (x | (x << 16)) & 0x1f0000ff0000ffull;
-    x = (x | (x << 8)) & 0x100f00f00f00f00full;
-    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
-    x = (x | (x << 2)) & 0x1249249249249249ull;
-    return x;
-}
+__device__ inline uint64_t spread21(uint64_t x) { return tree_spread21(x); }
 
-// key of a point of mesh m: mesh id above the interleaved `bits`-bit cell
-// coordinates of the point in that mesh's root cube; `inside` tells whether
-// the point lies in the cube (NaN: outside)
 __device__ inline uint64_t point_key(double x, double y, double z, int32_t m, const double *__restrict__ root,
                                      int bits, bool &inside) {
-    const double *r = root + 4 * m;
-    const double lim = ldexp(1.0, bits), scale = lim / r[3];
-    double q[3] = {(x - r[0]) * scale, (y - r[1]) * scale, (z - r[2]) * scale};
-    inside = q[0] >= 0.0 && q[0] < lim && q[1] >= 0.0 && q[1] < lim && q[2] >= 0.0 && q[2] < lim;
-    uint64_t b[3];
-    for (int c = 0; c < 3; ++c) {
-        double t = q[c];
-        t = t != t ? 0.0 : fmin(fmax(t, 0.0), lim - 1.0);
-        b[c] = (uint64_t)t;
-    }
-    return ((uint64_t)m << (3 * bits)) | spread21(b[0]) | (spread21(b[1]) << 1) | (spread21(b[2]) << 2);
+    return tree_point_key(x, y, z, m, root, bits, inside);
 }
 
 __device__ inline int32_t mesh_of_node(int64_t k, const int64_t *__restrict__ node_off, int32_t nmesh) {
