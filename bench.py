@@ -81,6 +81,8 @@ def time_variant(lss, torch, cfg, prec, far, steps, warmup):
     # pair-kernel duration from HIP events on the context stream (last step)
     st = c.stats()
     kms, launches, pairs = st["pair_kernel_ms"], st["pair_kernel_launches"], st["last_pairs"]
+    lane_use = st["last_pairs"] / st["lane_pairs"] if st["lane_pairs"] > 0 else None
+    tree = {k: st[k] for k in ("n_leaves", "n_boxes", "n_m2l", "tree_depth", "fmm_order")}
     # eval-only timing (built state reused)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -91,7 +93,7 @@ def time_variant(lss, torch, cfg, prec, far, steps, warmup):
     c.close()
     return dict(ms_per_step=1e3 * el / steps, value=n * steps / el, eval_only_per_s=n * steps / el_eval,
                 pair_kernel_ms=kms, pair_kernel_launches=launches, pairs_per_step=pairs,
-                pairs_per_s=pairs * steps / el, n_targets=n)
+                pairs_per_s=pairs * steps / el, n_targets=n, lane_use=lane_use, tree=tree)
 
 
 def time_newton(lss, torch, cfg, prec, steps, warmup):
@@ -260,7 +262,7 @@ def main():
         ach = FLOP_PER_PAIR * r["pairs_per_step"] / r["pair_kernel_launches"] / per_launch / 1e12
         return {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK[dt], "unit": "TFLOP/s",
                 "frac": round(ach / PEAK[dt], 4), "traffic": None,
-                "kernel": kname,
+                "kernel": kname, "lane_use": r["lane_use"],
                 "kernel_ms": round(per_launch * 1e3, 4)}
 
     out = {

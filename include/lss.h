@@ -99,8 +99,7 @@ typedef struct lss_options {
     int32_t precision;        /* LSS_FP64 (default) or LSS_MIXED */
     int32_t far_field;        /* LSS_FAR_DIRECT (default) or LSS_FAR_FMM */
     int32_t fmm_order;        /* multipole order p for LSS_FAR_FMM; 0 = default for the precision */
-    int32_t leaf_capacity;    /* octree: split a box holding more nodes than this; 0 = default
-                                 (128 FP64, 256 MIXED) */
+    int32_t leaf_capacity;    /* octree: split a box holding more nodes than this; 0 = default 64 */
     double  cut_factor;       /* near/far cut radius in units of the source sigma; the near list of
                                  a leaf covers every node within cut_factor * sigma_node;
                                  0 = default (8 for FP64, sqrt(40) for MIXED) */
@@ -108,10 +107,10 @@ typedef struct lss_options {
                                  0 = default (1e-12 FP64, 1e-6 MIXED) */
     int32_t newton_max_iter;  /* 0 = default 40 */
     int32_t tile;             /* targets per workgroup of the pair kernels: 64, 128 or 256; 0 = default
-                                 (direct sum 256; FMM 64 FP64, 128 MIXED) */
+                                 (direct sum 256; FMM 64) */
     double  leaf_shrink;      /* LSS_FAR_FMM: leaves may be as narrow as (cut radius of their nodes) /
                                  leaf_shrink; M2L then also needs a box gap >= the source's cut radius.
-                                 0 = default (2 for FP64, 1 for MIXED); otherwise in [1, 3] */
+                                 0 = default (2 for FP64, 1.5 for MIXED); otherwise in [1, 3] */
     int32_t reserved[6];      /* must be zero */
 } lss_options;
 
@@ -137,6 +136,8 @@ typedef struct lss_stats {
     int32_t pair_kernel_launches;  /* lss_eval: pair-kernel launches timed in pair_kernel_ms;
                                       lss_project: graph launches (8 iterations each) */
     int32_t pad0;
+    double  lane_pairs;       /* pair evaluations the pair kernels spent, idle lanes of partly
+                                 filled tiles included (last_pairs / lane_pairs = lane use) */
 } lss_stats;
 
 /* Create a context on HIP device `hip_device`, queuing work on `hip_stream`

@@ -46,7 +46,8 @@ class Stats(ctypes.Structure):
                 ("n_m2l", ctypes.c_int64), ("tree_depth", ctypes.c_int32), ("newton_iters", ctypes.c_int32),
                 ("last_targets", ctypes.c_int64), ("last_pairs", ctypes.c_double),
                 ("n_degenerate", ctypes.c_int64), ("pair_kernel_ms", ctypes.c_double),
-                ("pair_kernel_launches", ctypes.c_int32), ("pad0", ctypes.c_int32)]
+                ("pair_kernel_launches", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("lane_pairs", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -124,7 +124,7 @@ void eval_fmm_targets(Ctx &c, int64_t n, const int32_t *n_dev, double *phi, doub
     c.ntiles.ensure(16);
     build_tiles(c, n, n_dev, c.tkey2.as<uint64_t>(), fmm_tile(c), c.tleaf.as<int32_t>(), c.tstart.as<int32_t>(),
                 c.ntiles.as<int32_t>());
-    if (reset_pairs) LSS_HIP(hipMemsetAsync(c.pairs.p, 0, sizeof(double), c.stream));
+    if (reset_pairs) LSS_HIP(hipMemsetAsync(c.pairs.p, 0, 2 * sizeof(double), c.stream));
     c.ev_begin();
     launch_eval_fmm(c, n, c.ntiles.as<int32_t>(), c.tstart.as<int32_t>(), n_dev, n, c.tleaf.as<int32_t>(),
                     c.tperm2.as<int32_t>(), c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(), nullptr, phi, grad);
@@ -182,7 +182,7 @@ void eval(Ctx &c, const double *x, const int32_t *xm, int64_t n, double *phi, do
                    c.tperm2.as<int32_t>(), n, 0, 64, c.stream);
     launch_gather_targets(c, dx, dxm, c.tperm2.as<int32_t>(), n, c.tx.as<double>(), c.ty.as<double>(),
                           c.tz.as<double>(), c.tmesh.as<int32_t>());
-    LSS_HIP(hipMemsetAsync(c.pairs.p, 0, sizeof(double), c.stream));
+    LSS_HIP(hipMemsetAsync(c.pairs.p, 0, 2 * sizeof(double), c.stream));
     c.ev_begin();
     launch_p2p_direct(c, n, nullptr, c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(),
                       c.tmesh.as<int32_t>(), c.tperm2.as<int32_t>(), dphi, dgrad, 3);
@@ -264,7 +264,7 @@ void project(Ctx &c, const double *uv, int32_t np, double *h, double *xout, int8
     DBuf phi, grad;
     phi.ensure(sizeof(double) * N);
     grad.ensure(sizeof(double) * 3 * N);
-    LSS_HIP(hipMemsetAsync(c.pairs.p, 0, sizeof(double), c.stream));
+    LSS_HIP(hipMemsetAsync(c.pairs.p, 0, 2 * sizeof(double), c.stream));
     // Iterations run in captured chunks; a node leaves the active list when it
     // converges or reaches maxit, so iterations past the last active one are
     // empty launches and the host only checks the count between chunks.
@@ -377,15 +377,12 @@ void autotune(Ctx &c, const double *x, int64_t n, unsigned flags, double w, cons
     if (base.far_field == LSS_FAR_FMM) {
         // candidate grids around the measured optimum of each precision
         const bool mixed = base.precision == LSS_MIXED;
-        const std::vector<double> shr = mixed ? std::vector<double>{1.0, 1.5} : std::vector<double>{2.0, 3.0};
-        const std::vector<int> caps = mixed ? std::vector<int>{256, 512} : std::vector<int>{64, 128};
-        const std::vector<int> tiles = mixed ? std::vector<int>{64, 128, 256} : std::vector<int>{64, 128};
+        const std::vector<double> shr = mixed ? std::vector<double>{1.0, 1.5, 2.0} : std::vector<double>{1.5, 2.0, 3.0};
+        const std::vector<int> caps = {64, 256};
+        const std::vector<int> tiles = {64, 128};
         for (double sh : shr)
             for (int cp : caps)
-                for (int tl : tiles) {
-                    if (tl == 256 && sh > 1.0) continue;
-                    cands.push_back({sh, cp, tl});
-                }
+                for (int tl : tiles) cands.push_back({sh, cp, tl});
     } else {
         for (int tl : {64, 128, 256}) cands.push_back({0.0, 0, tl});
     }
@@ -665,14 +662,15 @@ int lss_get_stats(const lss_ctx *ctx, lss_stats *out) {
         c.ev_pending = false;
     }
     if (c.pairs_pending) {
-        double pr = 0.0;
+        double pr[2] = {0.0, 0.0};
         (void)hipSetDevice(c.device);
-        if (hipMemcpyAsync(&pr, c.pairs.p, sizeof(double), hipMemcpyDeviceToHost, c.stream) != hipSuccess ||
+        if (hipMemcpyAsync(pr, c.pairs.p, 2 * sizeof(double), hipMemcpyDeviceToHost, c.stream) != hipSuccess ||
             hipStreamSynchronize(c.stream) != hipSuccess) {
             c.err = "lss_get_stats: reading the pair counter failed";
             return LSS_EHIP;
         }
-        c.stats.last_pairs = pr;
+        c.stats.last_pairs = pr[0];
+        c.stats.lane_pairs = pr[1];
         c.pairs_pending = false;
     }
     *out = c.stats;

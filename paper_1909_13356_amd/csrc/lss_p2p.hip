@@ -184,9 +184,9 @@ __global__ __launch_bounds__(TILE) void k_p2p_direct_f64(
             grad[3 * o + 2] = sz + ez;
         }
     }
-    if (pairs) {
-        double w = wave_sum(valid ? (double)(e - b) : 0.0);
-        if ((lane & 63) == 0) atomicAdd(pairs, w);
+    if (pairs) {                            // [0] pairs of real targets, [1] lane slots spent
+        const double w = wave_sum(valid ? (double)(e - b) : 0.0), wl = wave_sum((double)(hi - lo));
+        if ((lane & 63) == 0) { atomicAdd(pairs, w); atomicAdd(pairs + 1, wl); }
     }
 }
 
@@ -268,9 +268,9 @@ __global__ __launch_bounds__(TILE) void k_p2p_direct_mixed(
             grad[3 * o + 2] = (double)sz + (double)ez;
         }
     }
-    if (pairs) {
-        double w = wave_sum(valid ? (double)(e - b) : 0.0);
-        if ((lane & 63) == 0) atomicAdd(pairs, w);
+    if (pairs) {                            // [0] pairs of real targets, [1] lane slots spent
+        const double w = wave_sum(valid ? (double)(e - b) : 0.0), wl = wave_sum((double)(hi - lo));
+        if ((lane & 63) == 0) { atomicAdd(pairs, w); atomicAdd(pairs + 1, wl); }
     }
 }
 
@@ -429,9 +429,9 @@ __global__ __launch_bounds__(TILE) void k_eval_fmm_f64(FmmEvalArgs a) {
                 a.grad[3 * o + 2] = (sz + g[2]) + ez;
             }
         }
-        if (a.pairs) {
-            double w = wave_sum(valid ? npair : 0.0);
-            if ((lane & 63) == 0) atomicAdd(a.pairs, w);
+        if (a.pairs) {                      // [0] pairs of real targets, [1] lane slots spent
+            const double w = wave_sum(valid ? npair : 0.0), wl = wave_sum(npair);
+            if ((lane & 63) == 0) { atomicAdd(a.pairs, w); atomicAdd(a.pairs + 1, wl); }
         }
     }
 }
@@ -515,9 +515,9 @@ __global__ __launch_bounds__(TILE) void k_eval_fmm_mixed(FmmEvalArgs a) {
                 a.grad[3 * o + 2] = ((double)sz + (double)ez) + g[2];
             }
         }
-        if (a.pairs) {
-            double w = wave_sum(valid ? npair : 0.0);
-            if ((lane & 63) == 0) atomicAdd(a.pairs, w);
+        if (a.pairs) {                      // [0] pairs of real targets, [1] lane slots spent
+            const double w = wave_sum(valid ? npair : 0.0), wl = wave_sum(npair);
+            if ((lane & 63) == 0) { atomicAdd(a.pairs, w); atomicAdd(a.pairs + 1, wl); }
         }
     }
 }
@@ -548,10 +548,10 @@ void launch_fmm_tile(Ctx &c, unsigned grid, const FmmEvalArgs &a) {
 
 }  // namespace
 
-// FMM tiles: 0 = default (64 FP64, 128 mixed: narrow tiles keep small leaves full)
+// FMM tiles: 0 = default 64 (narrow tiles keep the lanes of small leaves busy)
 int fmm_tile(const Ctx &c) {
     if (c.opt.tile == 64 || c.opt.tile == 128 || c.opt.tile == 256) return c.opt.tile;
-    return c.opt.precision == LSS_MIXED ? 128 : 64;
+    return 64;
 }
 
 void launch_eval_fmm(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const int32_t *tile_start,

@@ -65,6 +65,25 @@ __global__ void k_node_keys(int64_t n, const Src *__restrict__ src, const int64_
 // m; min / max fold through an order-preserving map of the doubles to u64
 constexpr int64_t kBoxChunk = 16384;
 
+// Leaves stop splitting at a side in [R, 2R) of their largest near radius
+// R, so the direct pairs per target grow with (side / R)^2.  Enlarging a
+// root cube by 2^phi (phi in [0, 1)) shifts every side; the histogram of
+// frac(log2(L0 / R_k)) per mesh lets the host pick the phi that brings the
+// sides closest to R.
+constexpr int kPhiBins = 64;
+
+__global__ void k_radius_hist(int64_t n, const Src *__restrict__ src, const int64_t *__restrict__ node_off,
+                              int32_t nmesh, const double *__restrict__ L0, double cut, unsigned int *hist) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int32_t m = mesh_of_node(k, node_off, nmesh);
+    const double R = cut * sqrt(0.5 / src[k].s2);
+    const double t = log2(L0[m] / R);
+    int b = (int)floor((t - floor(t)) * kPhiBins);
+    b = b < 0 ? 0 : (b >= kPhiBins ? kPhiBins - 1 : b);
+    atomicAdd(&hist[(int64_t)m * kPhiBins + b], 1u);
+}
+
 __device__ inline unsigned long long ordered_bits(double d) {
     const unsigned long long u = (unsigned long long)__double_as_longlong(d);
     return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
@@ -423,8 +442,8 @@ void build_tree(Ctx &c) {
     const int64_t n = c.nnodes;
     const int32_t nm = c.nmesh;
     const double cut = c.opt.cut_factor > 0 ? c.opt.cut_factor : (c.opt.precision == LSS_MIXED ? kCutMixed : kCutFP64);
-    const int64_t cap = c.opt.leaf_capacity > 0 ? c.opt.leaf_capacity : (c.opt.precision == LSS_MIXED ? 256 : 128);
-    const double shrink = c.opt.leaf_shrink > 0 ? c.opt.leaf_shrink : (c.opt.precision == LSS_MIXED ? 1.0 : 2.0);
+    const int64_t cap = c.opt.leaf_capacity > 0 ? c.opt.leaf_capacity : 64;
+    const double shrink = c.opt.leaf_shrink > 0 ? c.opt.leaf_shrink : (c.opt.precision == LSS_MIXED ? 1.5 : 2.0);
     t.K = c.opt.precision == LSS_MIXED ? 4 : 8;
     // key layout: mesh id above `bits` Morton bits per dimension, bit 63 free
     int mb = 0;
@@ -463,13 +482,47 @@ void build_tree(Ctx &c) {
             hi[i] = unmap(init[3 * nm + i]);
         }
     }
-    t.h_root.assign(4 * nm, 0.0);
+    std::vector<double> L0(nm);
     for (int m = 0; m < nm; ++m) {
         double ext = 0.0;
         for (int k = 0; k < 3; ++k) ext = fmax(ext, hi[3 * m + k] - lo[3 * m + k]);
-        const double L0 = (ext + 4.0 * rmax) * (1.0 + 1e-9);
-        for (int k = 0; k < 3; ++k) t.h_root[4 * m + k] = 0.5 * (lo[3 * m + k] + hi[3 * m + k]) - 0.5 * L0;
-        t.h_root[4 * m + 3] = L0 > 0.0 ? L0 : 1.0;
+        L0[m] = (ext + 4.0 * rmax) * (1.0 + 1e-9);
+        if (!(L0[m] > 0.0)) L0[m] = 1.0;
+    }
+    {   // enlarge each root by the 2^phi that brings the leaf sides closest to R
+        DBuf dL, dh;
+        dL.ensure(sizeof(double) * nm);
+        dh.ensure(sizeof(unsigned int) * kPhiBins * nm);
+        LSS_HIP(hipMemcpyAsync(dL.p, L0.data(), sizeof(double) * nm, hipMemcpyHostToDevice, c.stream));
+        LSS_HIP(hipMemsetAsync(dh.p, 0, sizeof(unsigned int) * kPhiBins * nm, c.stream));
+        hipLaunchKernelGGL(k_radius_hist, dim3(grid_for(n)), dim3(kBlk), 0, c.stream, n, c.src.as<Src>(),
+                           c.node_off.as<int64_t>(), nm, dL.as<double>(), cut, dh.as<unsigned int>());
+        LSS_CHECK_LAUNCH("k_radius_hist");
+        std::vector<unsigned int> hist((size_t)kPhiBins * nm);
+        LSS_HIP(hipMemcpyAsync(hist.data(), dh.p, sizeof(unsigned int) * hist.size(), hipMemcpyDeviceToHost,
+                               c.stream));
+        LSS_HIP(hipStreamSynchronize(c.stream));
+        for (int m = 0; m < nm; ++m) {
+            double best = -1.0;
+            int bj = 0;
+            for (int j = 0; j < kPhiBins; ++j) {          // phi = j / bins
+                double cost = 0.0;
+                for (int b = 0; b < kPhiBins; ++b) {
+                    const unsigned int h = hist[(size_t)m * kPhiBins + b];
+                    if (!h) continue;
+                    double f = (b + 0.5 + j) / kPhiBins;
+                    f -= std::floor(f);
+                    cost += h * std::exp2(2.0 * f);          // (side / R)^2
+                }
+                if (best < 0.0 || cost < best) { best = cost; bj = j; }
+            }
+            L0[m] *= std::exp2((double)bj / kPhiBins);
+        }
+    }
+    t.h_root.assign(4 * nm, 0.0);
+    for (int m = 0; m < nm; ++m) {
+        for (int k = 0; k < 3; ++k) t.h_root[4 * m + k] = 0.5 * (lo[3 * m + k] + hi[3 * m + k]) - 0.5 * L0[m];
+        t.h_root[4 * m + 3] = L0[m];
     }
     t.root.ensure(sizeof(double) * 4 * nm);
     LSS_HIP(hipMemcpyAsync(t.root.p, t.h_root.data(), sizeof(double) * 4 * nm, hipMemcpyHostToDevice, c.stream));
