@@ -107,7 +107,7 @@ typedef struct lss_options {
                                  0 = default (1e-12 FP64, 1e-6 MIXED) */
     int32_t newton_max_iter;  /* 0 = default 40 */
     int32_t tile;             /* targets per workgroup of the pair kernels: 64, 128 or 256; 0 = default
-                                 (direct sum 256; FMM 64) */
+                                 (direct sum 256; FMM 64; the mixed FMM kernel always uses 64) */
     double  leaf_shrink;      /* LSS_FAR_FMM: leaves may be as narrow as (cut radius of their nodes) /
                                  leaf_shrink; M2L then also needs a box gap >= the source's cut radius.
                                  0 = default (2 for FP64, 1.5 for MIXED); otherwise in [1, 3] */

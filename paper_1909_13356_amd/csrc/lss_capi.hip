@@ -92,6 +92,8 @@ void build(Ctx &c) {
     launch_bbox(c);
     launch_pseudonormals(c);
     c.pairs.ensure(sizeof(double) * 4);
+    c.tile_queue.ensure(sizeof(unsigned int) * 4);
+    LSS_HIP(hipMemsetAsync(c.tile_queue.p, 0, sizeof(unsigned int) * 4, c.stream));
     c.stats.n_boxes = c.stats.n_leaves = c.stats.n_m2l = 0;
     c.stats.tree_depth = c.stats.fmm_order = 0;
     if (c.opt.far_field == LSS_FAR_FMM) build_fmm(c);
@@ -379,7 +381,7 @@ void autotune(Ctx &c, const double *x, int64_t n, unsigned flags, double w, cons
         const bool mixed = base.precision == LSS_MIXED;
         const std::vector<double> shr = mixed ? std::vector<double>{1.0, 1.5, 2.0} : std::vector<double>{1.5, 2.0, 3.0};
         const std::vector<int> caps = {64, 256};
-        const std::vector<int> tiles = {64, 128};
+        const std::vector<int> tiles = mixed ? std::vector<int>{64} : std::vector<int>{64, 128};
         for (double sh : shr)
             for (int cp : caps)
                 for (int tl : tiles) cands.push_back({sh, cp, tl});
@@ -488,7 +490,7 @@ void lss_destroy(lss_ctx *ctx) {
     (void)hipSetDevice(c.device);
     (void)hipStreamSynchronize(c.stream);
     DBuf *bufs[] = {&c.verts, &c.tris, &c.tri_off, &c.node_off, &c.rule, &c.sigma, &c.src, &c.vH, &c.tkey,
-                    &c.tkey2, &c.tperm, &c.tperm2, &c.tx, &c.ty, &c.tz, &c.tmesh, &c.sort_tmp, &c.pairs,
+                    &c.tkey2, &c.tperm, &c.tperm2, &c.tx, &c.ty, &c.tz, &c.tmesh, &c.sort_tmp, &c.pairs, &c.tile_queue,
                     &c.tflag, &c.tpos, &c.tstart, &c.ntiles, &c.tleaf,
                     &c.ns.T, &c.ns.H, &c.ns.h, &c.ns.lo, &c.ns.hi, &c.ns.sig, &c.ns.mesh, &c.ns.orig,
                     &c.ns.status, &c.ns.iters, &c.ns.active, &c.ns.active2, &c.ns.flag, &c.ns.blocksum,

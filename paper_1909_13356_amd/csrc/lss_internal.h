@@ -206,6 +206,7 @@ struct Ctx {
     DBuf tkey, tkey2, tperm, tperm2, tx, ty, tz, tmesh, sort_tmp;
     DBuf tflag, tpos, tstart, ntiles, tleaf;   // FMM eval: leaf of each sorted target, tile heads
     DBuf pairs;               // double accumulator of executed pairs (stats)
+    DBuf tile_queue;          // uint32[2] work queue of the FMM evaluation (zero between launches)
     bool pairs_pending = false;   // counter not yet read back into stats.last_pairs
     NewtonState ns;
 

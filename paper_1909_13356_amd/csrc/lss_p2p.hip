@@ -51,13 +51,19 @@ __device__ __forceinline__ void two_sum_f(float &s, float &e, float v) {
 // S, T in FP64
 __device__ __forceinline__ void kfun64(double x, double &S, double &T) {
     if (x < KF64_X) {
+        // power basis with shared powers t^k: every step accumulates into
+        // its own sum (one FMA), where Horner's constant addend would cost a
+        // register copy per step in FP64; t in [0, 1) and the coefficients
+        // are of one sign but for a few small ones, so the sums stay well
+        // conditioned
         const double t = x * KF64_INV_X;
-        double ps = kf64_ps[KF64_PS_DEG], pt = kf64_pt[KF64_PT_DEG], q = kf64_q[KF64_Q_DEG];
+        double ps = kf64_ps[0], pt = kf64_pt[0], q = kf64_q[0], tk = 1.0;
 #pragma unroll
-        for (int k = KF64_Q_DEG - 1; k >= 0; --k) {
-            ps = fma(ps, t, kf64_ps[k]);
-            pt = fma(pt, t, kf64_pt[k]);
-            q = fma(q, t, kf64_q[k]);
+        for (int k = 1; k <= KF64_Q_DEG; ++k) {
+            tk *= t;
+            ps = fma(kf64_ps[k], tk, ps);
+            pt = fma(kf64_pt[k], tk, pt);
+            q = fma(kf64_q[k], tk, q);
         }
         double r = __builtin_amdgcn_rcp(q);
         r = fma(r, fma(-q, r, 1.0), r);
@@ -110,6 +116,64 @@ __device__ __forceinline__ void pair64(const Src &s, double x, double y, double 
     gy = fma(g, dy, fma(-s.ay, S, gy));
     gz = fma(g, dz, fma(-s.az, S, gz));
 }
+
+// K consecutive FP64 records against one target (see nodes32 below)
+template <int K>
+__device__ __forceinline__ void nodes64(const Src *sh, double x, double y, double z, double &p, double &gx,
+                                        double &gy, double &gz) {
+    double dx[K], dy[K], dz[K], u[K], ad[K], S[K], T[K];
+    bool nr[K], any = false;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const Src s = sh[k];
+        dx[k] = x - s.yx;
+        dy[k] = y - s.yy;
+        dz[k] = z - s.yz;
+        const double r2 = fma(dx[k], dx[k], fma(dy[k], dy[k], dz[k] * dz[k]));
+        ad[k] = fma(s.ax, dx[k], fma(s.ay, dy[k], s.az * dz[k]));
+        u[k] = r2 * s.s2;
+        nr[k] = u[k] < KF64_X;
+        any = any || nr[k];
+        const double ux = fmax(u[k], KF64_X);
+        double r = __builtin_amdgcn_rsq(ux);
+        const double hx = 0.5 * ux;
+        r = r * fma(-hx * r, r, 1.5);
+        r = r * fma(-hx * r, r, 1.5);
+        const double rr = r * r;
+        S[k] = kSqrtPiHalf * rr * r;
+        T[k] = 1.5 * S[k] * rr;
+    }
+    if (any) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double t = fmin(u[k], KF64_X) * KF64_INV_X;
+            double ps = kf64_ps[0], pt = kf64_pt[0], q = kf64_q[0], tk = 1.0;
+#pragma unroll
+            for (int i = 1; i <= KF64_Q_DEG; ++i) {
+                tk *= t;
+                ps = fma(kf64_ps[i], tk, ps);
+                pt = fma(kf64_pt[i], tk, pt);
+                q = fma(kf64_q[i], tk, q);
+            }
+            double r = __builtin_amdgcn_rcp(q);
+            r = fma(r, fma(-q, r, 1.0), r);
+            r = fma(r, fma(-q, r, 1.0), r);
+            S[k] = nr[k] ? ps * r : S[k];
+            T[k] = nr[k] ? pt * r : T[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const Src &s = sh[k];
+        p = fma(-ad[k], S[k], p);
+        const double g = ad[k] * T[k] * s.s2x2;
+        gx = fma(g, dx[k], fma(-s.ax, S[k], gx));
+        gy = fma(g, dy[k], fma(-s.ay, S[k], gy));
+        gz = fma(g, dz[k], fma(-s.az, S[k], gz));
+    }
+}
+
+constexpr int kNodeGroup64 = 4;
 
 __device__ __forceinline__ void pair32(const SrcF &s, float x, float y, float z, float xl, float yl, float zl,
                                        float &p, float &gx, float &gy, float &gz) {
@@ -303,7 +367,28 @@ struct FmmEvalArgs {
     const double *root;         // per-mesh root cubes (corner xyz, side)
     const int32_t *bmesh;
     double *pairs;
+    // tile queue: [0] next tile, [1] finished workgroups; zero between
+    // launches (the last workgroup to finish clears both)
+    unsigned int *queue;
 };
+
+// next tile for the workgroup (uniform); tiles are handed out in list order
+__device__ __forceinline__ int next_tile(const FmmEvalArgs &a, int *slot) {
+    __syncthreads();                    // everyone has read the previous slot value
+    if (threadIdx.x == 0) *slot = (int)atomicAdd(a.queue, 1u);
+    __syncthreads();
+    return *slot;
+}
+
+__device__ __forceinline__ void queue_done(const FmmEvalArgs &a) {
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(a.queue + 1, 1u) == gridDim.x - 1) {
+            atomicExch(a.queue, 0u);
+            atomicExch(a.queue + 1, 0u);
+        }
+    }
+}
 
 // The near list of a tile (its leaf's source boxes, or every node of the mesh
 // for targets outside its root cube) is streamed as one packed sequence: up
@@ -383,7 +468,8 @@ __global__ __launch_bounds__(TILE) void k_eval_fmm_f64(FmmEvalArgs a) {
     const int ntiles = *a.ntiles_dev;
     const int64_t n = a.n_dev ? (int64_t)*a.n_dev : a.n_max;
     const int lane = threadIdx.x;
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    __shared__ int slot;
+    for (int tile = next_tile(a, &slot); tile < ntiles; tile = next_tile(a, &slot)) {
         const int64_t s0 = a.tile_start[tile];
         const int32_t leafk = a.sleaf[s0];
         const int64_t s1 = tile + 1 < ntiles ? (int64_t)a.tile_start[tile + 1] : n;   // tile = [s0, s1)
@@ -407,10 +493,15 @@ __global__ __launch_bounds__(TILE) void k_eval_fmm_f64(FmmEvalArgs a) {
                 const int cnt = (int)(total - c0 < TILE ? total - c0 : TILE);
                 __syncthreads();
                 if (lane < cnt) sh[lane] = a.src[packed_node<TILE>(rb, nr, c0 + lane)];
+                else {                          // zero records pad the chunk to whole node groups
+                    Src f;
+                    f.yx = f.yy = f.yz = f.ax = f.ay = f.az = f.s2x2 = 0.0;
+                    f.s2 = 1.0e300;
+                    sh[lane] = f;
+                }
                 __syncthreads();
                 double p = 0, gx = 0, gy = 0, gz = 0;
-#pragma unroll 2
-                for (int j = 0; j < cnt; ++j) pair64(sh[j], x, y, z, p, gx, gy, gz);
+                for (int j = 0; j < cnt; j += kNodeGroup64) nodes64<kNodeGroup64>(sh + j, x, y, z, p, gx, gy, gz);
                 two_sum(sp, ep, p);
                 two_sum(sx, ex, gx);
                 two_sum(sy, ey, gy);
@@ -434,68 +525,126 @@ __global__ __launch_bounds__(TILE) void k_eval_fmm_f64(FmmEvalArgs a) {
             if ((lane & 63) == 0) { atomicAdd(a.pairs, w); atomicAdd(a.pairs + 1, wl); }
         }
     }
+    queue_done(a);
 }
 
-template <int TILE>
-__global__ __launch_bounds__(TILE) void k_eval_fmm_mixed(FmmEvalArgs a) {
-    __shared__ SrcF sh[TILE];
-    __shared__ RangeBatch<TILE> rb;
+
+constexpr int kNodeGroup = 4;
+
+template <int K>
+__device__ __forceinline__ void nodes32(const SrcF *sh, float x, float y, float z, float xl, float yl, float zl,
+                                        float &p, float &gx, float &gy, float &gz) {
+    float dx[K], dy[K], dz[K], u[K], ad[K], S[K], T[K];
+    bool nr[K], any = false;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const SrcF s = sh[k];
+        dx[k] = (x - s.yx) + (xl - s.lx);
+        dy[k] = (y - s.yy) + (yl - s.ly);
+        dz[k] = (z - s.yz) + (zl - s.lz);
+        const float r2 = fmaf(dx[k], dx[k], fmaf(dy[k], dy[k], dz[k] * dz[k]));
+        ad[k] = fmaf(s.ax, dx[k], fmaf(s.ay, dy[k], s.az * dz[k]));
+        u[k] = r2 * s.s2;
+        nr[k] = u[k] < (float)KF32_X;
+        any = any || nr[k];
+        const float r = __builtin_amdgcn_rsqf(fmaxf(u[k], (float)KF32_X));
+        const float rr = r * r;
+        S[k] = kSqrtPiHalfF * rr * r;
+        T[k] = 1.5f * S[k] * rr;
+    }
+    if (any) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const float t = fminf(u[k], (float)KF32_X) * (float)KF32_INV_X;
+            float ps = kf32_ps[KF32_PS_DEG], pt = kf32_pt[KF32_PT_DEG], q = kf32_q[KF32_Q_DEG];
+#pragma unroll
+            for (int i = KF32_Q_DEG - 1; i >= 0; --i) {
+                ps = fmaf(ps, t, kf32_ps[i]);
+                pt = fmaf(pt, t, kf32_pt[i]);
+                q = fmaf(q, t, kf32_q[i]);
+            }
+            const float rq = __builtin_amdgcn_rcpf(q);
+            S[k] = nr[k] ? ps * rq : S[k];
+            T[k] = nr[k] ? pt * rq : T[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const SrcF &s = sh[k];
+        const float g = ad[k] * T[k] * s.s2x2;
+        p = fmaf(-ad[k], S[k], p);
+        gx = fmaf(g, dx[k], fmaf(-s.ax, S[k], gx));
+        gy = fmaf(g, dy[k], fmaf(-s.ay, S[k], gy));
+        gz = fmaf(g, dz[k], fmaf(-s.az, S[k], gz));
+    }
+}
+
+// Mixed path: one wavefront per tile of 64 targets; each staged chunk of 64
+// node records is padded with zero records to whole groups of kNodeGroup.
+__global__ __launch_bounds__(64) void k_eval_fmm_mixed(FmmEvalArgs a) {
+    constexpr int W = 64;
+    __shared__ SrcF sh[W];
+    __shared__ RangeBatch<W> rb;
     extern __shared__ double Ls[];      // local expansion of the tile's leaf (ncp doubles)
     const int ntiles = *a.ntiles_dev;
     const int64_t n = a.n_dev ? (int64_t)*a.n_dev : a.n_max;
     const int lane = threadIdx.x;
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    __shared__ int slot;
+    for (int tile = next_tile(a, &slot); tile < ntiles; tile = next_tile(a, &slot)) {
         const int64_t s0 = a.tile_start[tile];
-        const int32_t leafk = a.sleaf[s0];
+        const int32_t B = a.sleaf[s0];
         const int64_t s1 = tile + 1 < ntiles ? (int64_t)a.tile_start[tile + 1] : n;   // tile = [s0, s1)
         const int64_t sp_ = s0 + lane;
         const bool valid = sp_ < s1;
         const int64_t ti = a.sidx ? (int64_t)a.sidx[valid ? sp_ : s0] : (valid ? sp_ : s0);
         const int64_t t0 = a.sidx ? (int64_t)a.sidx[s0] : s0;
-        const double ox = a.tx[t0], oy = a.ty[t0], oz = a.tz[t0];
+        const double ox = a.tx[t0], oy = a.ty[t0], oz = a.tz[t0];     // tile origin
         const double X = a.tx[ti], Y = a.ty[ti], Z = a.tz[ti];
         const double dxo = X - ox, dyo = Y - oy, dzo = Z - oz;
         const float x = (float)dxo, y = (float)dyo, z = (float)dzo;
         const float xl = (float)(dxo - (double)x), yl = (float)(dyo - (double)y), zl = (float)(dzo - (double)z);
-        const int32_t B = leafk;
         const bool outside = B >= a.nboxes;
         const int e0 = outside ? 0 : a.p2p_beg[B], e1 = outside ? 1 : a.p2p_end[B];
         __syncthreads();                    // previous tile is done with Ls
         if (!outside) stage_local(a, B, Ls);
         float sp = 0, ep = 0, sx = 0, ex = 0, sy = 0, ey = 0, sz = 0, ez = 0;
         double npair = 0.0;
-        for (int eb = e0; eb < e1; eb += TILE) {
-            const int nr = e1 - eb < TILE ? e1 - eb : TILE;
+        for (int eb = e0; eb < e1; eb += W) {
+            const int nr = e1 - eb < W ? e1 - eb : W;
             __syncthreads();
-            const int64_t total = load_ranges<TILE>(a, rb, eb, nr, outside ? B - a.nboxes : -1);
+            const int64_t total = load_ranges<W>(a, rb, eb, nr, outside ? B - a.nboxes : -1);
             npair += (double)total;
-            for (int64_t c0 = 0; c0 < total; c0 += TILE) {
-                const int cnt = (int)(total - c0 < TILE ? total - c0 : TILE);
+            for (int64_t c0 = 0; c0 < total; c0 += W) {
+                const int cnt = (int)(total - c0 < W ? total - c0 : W);
                 __syncthreads();
+                SrcF f;
                 if (lane < cnt) {
-                    const Src s = a.src[packed_node<TILE>(rb, nr, c0 + lane)];
-                    SrcF f;
-                    const double qx = s.yx - ox, qy = s.yy - oy, qz = s.yz - oz;
+                    const Src sr = a.src[packed_node<W>(rb, nr, c0 + lane)];
+                    const double qx = sr.yx - ox, qy = sr.yy - oy, qz = sr.yz - oz;
                     f.yx = (float)qx;
                     f.yy = (float)qy;
                     f.yz = (float)qz;
                     f.lx = (float)(qx - (double)f.yx);
                     f.ly = (float)(qy - (double)f.yy);
                     f.lz = (float)(qz - (double)f.yz);
-                    f.s2 = (float)s.s2;
-                    f.ax = (float)s.ax;
-                    f.ay = (float)s.ay;
-                    f.az = (float)s.az;
-                    f.s2x2 = (float)s.s2x2;
-                    f.pad = 0.0f;
-                    sh[lane] = f;
+                    f.s2 = (float)sr.s2;
+                    f.ax = (float)sr.ax;
+                    f.ay = (float)sr.ay;
+                    f.az = (float)sr.az;
+                    f.s2x2 = (float)sr.s2x2;
+                } else {                        // zero record: no contribution, far branch
+                    f.yx = f.yy = f.yz = f.lx = f.ly = f.lz = 0.0f;
+                    f.ax = f.ay = f.az = f.s2x2 = 0.0f;
+                    f.s2 = 1.0e30f;
                 }
+                f.pad = 0.0f;
+                sh[lane] = f;
                 __syncthreads();
                 for (int j0 = 0; j0 < cnt; j0 += 32) {
                     float p = 0, gx = 0, gy = 0, gz = 0;
                     const int j1 = j0 + 32 < cnt ? j0 + 32 : cnt;
-#pragma unroll 4
-                    for (int j = j0; j < j1; ++j) pair32(sh[j], x, y, z, xl, yl, zl, p, gx, gy, gz);
+                    for (int j = j0; j < j1; j += kNodeGroup)
+                        nodes32<kNodeGroup>(sh + j, x, y, z, xl, yl, zl, p, gx, gy, gz);
                     two_sum_f(sp, ep, p);
                     two_sum_f(sx, ex, gx);
                     two_sum_f(sy, ey, gy);
@@ -517,9 +666,10 @@ __global__ __launch_bounds__(TILE) void k_eval_fmm_mixed(FmmEvalArgs a) {
         }
         if (a.pairs) {                      // [0] pairs of real targets, [1] lane slots spent
             const double w = wave_sum(valid ? npair : 0.0), wl = wave_sum(npair);
-            if ((lane & 63) == 0) { atomicAdd(a.pairs, w); atomicAdd(a.pairs + 1, wl); }
+            if (lane == 0) { atomicAdd(a.pairs, w); atomicAdd(a.pairs + 1, wl); }
         }
     }
+    queue_done(a);
 }
 
 template <int TILE>
@@ -539,17 +689,16 @@ void launch_tile(Ctx &c, int64_t n, const int32_t *n_dev, const double *tx, cons
 template <int TILE>
 void launch_fmm_tile(Ctx &c, unsigned grid, const FmmEvalArgs &a) {
     const size_t shm = sizeof(double) * (size_t)a.ncp;
-    if (c.opt.precision == LSS_MIXED)
-        hipLaunchKernelGGL(k_eval_fmm_mixed<TILE>, dim3(grid), dim3(TILE), shm, c.stream, a);
-    else
-        hipLaunchKernelGGL(k_eval_fmm_f64<TILE>, dim3(grid), dim3(TILE), shm, c.stream, a);
+    hipLaunchKernelGGL(k_eval_fmm_f64<TILE>, dim3(grid), dim3(TILE), shm, c.stream, a);
     LSS_CHECK_LAUNCH("k_eval_fmm");
 }
 
 }  // namespace
 
-// FMM tiles: 0 = default 64 (narrow tiles keep the lanes of small leaves busy)
+// FMM tiles: 0 = default 64 (narrow tiles keep the lanes of small leaves
+// busy); the mixed kernel always takes 64-target tiles
 int fmm_tile(const Ctx &c) {
+    if (c.opt.precision == LSS_MIXED) return 64;
     if (c.opt.tile == 64 || c.opt.tile == 128 || c.opt.tile == 256) return c.opt.tile;
     return 64;
 }
@@ -586,8 +735,14 @@ void launch_eval_fmm(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const
     a.root = t.root.as<double>();
     a.bmesh = t.bmesh.as<int32_t>();
     a.pairs = c.pairs.as<double>();
+    a.queue = c.tile_queue.as<unsigned int>();
     int64_t g = max_tiles < 16384 ? max_tiles : 16384;
     unsigned grid = (unsigned)(g > 0 ? g : 1);
+    if (c.opt.precision == LSS_MIXED) {
+        hipLaunchKernelGGL(k_eval_fmm_mixed, dim3(grid), dim3(64), sizeof(double) * (size_t)a.ncp, c.stream, a);
+        LSS_CHECK_LAUNCH("k_eval_fmm_mixed");
+        return;
+    }
     switch (fmm_tile(c)) {
         case 64: launch_fmm_tile<64>(c, grid, a); break;
         case 128: launch_fmm_tile<128>(c, grid, a); break;
