@@ -74,14 +74,34 @@ constexpr int kPhiBins = 64;
 
 __global__ void k_radius_hist(int64_t n, const Src *__restrict__ src, const int64_t *__restrict__ node_off,
                               int32_t nmesh, const double *__restrict__ L0, double cut, unsigned int *hist) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const int32_t m = mesh_of_node(k, node_off, nmesh);
-    const double R = cut * sqrt(0.5 / src[k].s2);
-    const double t = log2(L0[m] / R);
-    int b = (int)floor((t - floor(t)) * kPhiBins);
-    b = b < 0 ? 0 : (b >= kPhiBins ? kPhiBins - 1 : b);
-    atomicAdd(&hist[(int64_t)m * kPhiBins + b], 1u);
+    // per-block histogram in LDS (the block's nodes are contiguous, so they
+    // belong to few meshes: a block folds one mesh at a time)
+    __shared__ unsigned int h[kPhiBins];
+    __shared__ int32_t mesh_lo, mesh_hi;
+    const int64_t k0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t k = k0 + threadIdx.x;
+    if (threadIdx.x == 0) {
+        mesh_lo = mesh_of_node(k0, node_off, nmesh);
+        mesh_hi = mesh_of_node(min(k0 + (int64_t)blockDim.x, n) - 1, node_off, nmesh);
+    }
+    __syncthreads();
+    const int32_t m = k < n ? mesh_of_node(k, node_off, nmesh) : -1;
+    int b = -1;
+    if (k < n) {
+        const double R = cut * sqrt(0.5 / src[k].s2);
+        const double t = log2(L0[m] / R);
+        b = (int)floor((t - floor(t)) * kPhiBins);
+        b = b < 0 ? 0 : (b >= kPhiBins ? kPhiBins - 1 : b);
+    }
+    for (int32_t mm = mesh_lo; mm <= mesh_hi; ++mm) {
+        for (int i = threadIdx.x; i < kPhiBins; i += blockDim.x) h[i] = 0u;
+        __syncthreads();
+        if (m == mm) atomicAdd(&h[b], 1u);
+        __syncthreads();
+        for (int i = threadIdx.x; i < kPhiBins; i += blockDim.x)
+            if (h[i]) atomicAdd(&hist[(int64_t)mm * kPhiBins + i], h[i]);
+        __syncthreads();
+    }
 }
 
 __device__ inline unsigned long long ordered_bits(double d) {
