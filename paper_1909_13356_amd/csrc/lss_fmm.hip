@@ -60,7 +60,7 @@ __global__ void k_fill_op(int kind, int p, int ncp, int nops, const cd *__restri
 }
 
 // ------------------------------------------------------------------ P2M
-constexpr int kG = 4;          // nodes per pass
+constexpr int kG = 8;          // nodes per pass
 constexpr int kNPT = 4;        // coefficients per thread (p <= 40)
 
 struct Geo {
@@ -68,6 +68,11 @@ struct Geo {
     const int32_t *bmesh;
 };
 
+// One workgroup per non-empty leaf.  Per pass of kG nodes: the regular
+// solid harmonics U_n^m (n < p) of every node are tabulated in LDS, one
+// column m per thread, by the order recurrence with a table of the
+// reciprocals 1/((n+m)(n-m)); then each thread adds the dipole terms of its
+// coefficients (n, m) for the kG nodes.
 __global__ __launch_bounds__(kBlk) void k_p2m(const int32_t *__restrict__ nleaf_dev, const int32_t *__restrict__ leaves,
                                                 int p, int ncp, Geo g, const int32_t *__restrict__ lev,
                                                 const int32_t *__restrict__ ijk, const int64_t *__restrict__ nb,
@@ -76,13 +81,21 @@ __global__ __launch_bounds__(kBlk) void k_p2m(const int32_t *__restrict__ nleaf_
     const int tstride = fmm::tri(p - 1, p - 1) + 1;
     cd *U = reinterpret_cast<cd *>(smem);                 // kG tables
     double *nd = smem + 2 * kG * tstride;                 // kG x (rx, ry, rz, ax, ay, az)
+    double *rinv = nd + 6 * kG;                           // 1/((n+m)(n-m)) at tri(n, m), n > m
     if ((int)blockIdx.x >= *nleaf_dev) return;
+    for (int i = threadIdx.x; i < tstride; i += kBlk) {
+        int n = 0;
+        while ((n + 1) * (n + 2) / 2 <= i) ++n;
+        const int m = i - n * (n + 1) / 2;
+        rinv[i] = n > m ? 1.0 / ((double)(n + m) * (double)(n - m)) : 0.0;
+    }
     const int32_t b = leaves[blockIdx.x];
     const double s = box_side(g.root, g.bmesh, b, lev[b]);
     const double *o = g.root + 4 * g.bmesh[b];
     const double c0 = o[0] + (ijk[3 * b] + 0.5) * s, c1 = o[1] + (ijk[3 * b + 1] + 0.5) * s,
                  c2 = o[2] + (ijk[3 * b + 2] + 0.5) * s;
     const double inv4pis = 1.0 / (4.0 * kPi * s);
+    const double invs = 1.0 / s;
     // coefficient slots of this thread: (n, m), n = 1..p, m = 0..n enumerated row by row
     int qn[kNPT], qm[kNPT];
     double are[kNPT], aim[kNPT];
@@ -105,30 +118,31 @@ __global__ __launch_bounds__(kBlk) void k_p2m(const int32_t *__restrict__ nleaf_
         if ((int)threadIdx.x < gn) {
             const Src sr = src[k0 + threadIdx.x];
             // unfold the dipole: a = a' / c(sigma), 1/c = 4 sqrt2 pi^1.5 sigma^3, sigma^2 = 1/(2 s2)
-            const double sig3 = pow(0.5 / sr.s2, 1.5);
-            const double f = 4.0 * 1.4142135623730951 * 5.568327996831708 * sig3;
+            const double sg2 = 0.5 / sr.s2;
+            const double f = 4.0 * 1.4142135623730951 * 5.568327996831708 * sg2 * sqrt(sg2);
             double *q = nd + 6 * threadIdx.x;
-            q[0] = (sr.yx - c0) / s;
-            q[1] = (sr.yy - c1) / s;
-            q[2] = (sr.yz - c2) / s;
+            q[0] = (sr.yx - c0) * invs;
+            q[1] = (sr.yy - c1) * invs;
+            q[2] = (sr.yz - c2) * invs;
             q[3] = sr.ax * f;
             q[4] = sr.ay * f;
             q[5] = sr.az * f;
         }
         __syncthreads();
-        {   // column m of U(r_g), orders m..p-1
-            const int gi = threadIdx.x / 64, m = threadIdx.x % 64;
+        for (int task = threadIdx.x; task < kG * 64; task += kBlk) {   // column m of U(r_gi), orders m..p-1
+            const int gi = task / 64, m = task % 64;
             if (gi < gn && m <= p - 1) {
                 const double *q = nd + 6 * gi;
                 const double x = q[0], y = q[1], z = q[2], r2 = x * x + y * y + z * z;
                 cd d = {1.0, 0.0};
-                for (int t = 1; t <= m; ++t) d = fmm::cscale(fmm::cmul(d, cd{x, y}), -1.0 / (2.0 * t));
+                for (int t = 1; t <= m; ++t) d = fmm::cscale(fmm::cmul(d, cd{x, y}), -0.5 / (double)t);
                 cd *Ug = U + gi * tstride;
                 Ug[fmm::tri(m, m)] = d;
                 cd um2 = {0.0, 0.0}, um1 = d;
                 for (int n = m + 1; n <= p - 1; ++n) {
-                    const double inv = 1.0 / ((double)(n + m) * (double)(n - m));
-                    cd un = {((2 * n - 1) * z * um1.re - r2 * um2.re) * inv, ((2 * n - 1) * z * um1.im - r2 * um2.im) * inv};
+                    const double inv = rinv[fmm::tri(n, m)];
+                    const double a2 = (double)(2 * n - 1) * z;
+                    cd un = {(a2 * um1.re - r2 * um2.re) * inv, (a2 * um1.im - r2 * um2.im) * inv};
                     Ug[fmm::tri(n, m)] = un;
                     um2 = um1;
                     um1 = un;
@@ -352,7 +366,7 @@ void build_fmm(Ctx &c) {
     c.stats.n_leaves = nl;
     if (nl > 0) {
         const int tstride = fmm::tri(p - 1, p - 1) + 1;
-        size_t shm = sizeof(double) * (2 * kG * tstride + 6 * kG);
+        size_t shm = sizeof(double) * (2 * kG * tstride + 6 * kG + tstride);
         hipLaunchKernelGGL(k_p2m, dim3(nl), dim3(kBlk), shm, c.stream, nleaf.as<int32_t>(), leaves.as<int32_t>(), p, ncp, g,
                            t.level.as<int32_t>(), t.ijk.as<int32_t>(), t.nb.as<int64_t>(), t.ne.as<int64_t>(),
                            t.src.as<Src>(), t.M.as<double>());
