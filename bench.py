@@ -33,6 +33,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_digest():
+    import hashlib
+    path = os.path.join(ROOT, "paper_1909_13356_amd", "csrc", "lss_p2p.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed counter
+    summary, or None when it was taken on other kernel source or workload."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    e = rec.get(kernel)
+    if not e or e.get("source_digest") != kernel_digest() or e.get("workload") != workload:
+        return None
+    return e.get("bytes_per_launch")
+
+
 def workload(name, scale):
     from workloads import configs
     if name == "c2":
@@ -256,12 +276,13 @@ def main():
 
     def roof(r, dt):
         kname = ("k_eval_fmm_%s" if far else "k_p2p_direct_%s") % ("mixed" if dt == "f32" else "f64")
+        traffic = measured_traffic(kname, desc)
         if r["pair_kernel_launches"] <= 0 or r["pair_kernel_ms"] <= 0:
             return None
         per_launch = r["pair_kernel_ms"] / r["pair_kernel_launches"] * 1e-3
         ach = FLOP_PER_PAIR * r["pairs_per_step"] / r["pair_kernel_launches"] / per_launch / 1e12
         return {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK[dt], "unit": "TFLOP/s",
-                "frac": round(ach / PEAK[dt], 4), "traffic": None,
+                "frac": round(ach / PEAK[dt], 4), "traffic": traffic,
                 "kernel": kname, "lane_use": r["lane_use"],
                 "kernel_ms": round(per_launch * 1e3, 4)}
 
