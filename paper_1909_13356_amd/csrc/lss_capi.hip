@@ -94,6 +94,8 @@ void build(Ctx &c) {
     c.pairs.ensure(sizeof(double) * 4);
     c.tile_queue.ensure(sizeof(unsigned int) * 4);
     LSS_HIP(hipMemsetAsync(c.tile_queue.p, 0, sizeof(unsigned int) * 4, c.stream));
+    c.tile_bucket.ensure(sizeof(int32_t) * 2 * kCostBuckets);
+    LSS_HIP(hipMemsetAsync(c.tile_bucket.p, 0, sizeof(int32_t) * 2 * kCostBuckets, c.stream));
     c.stats.n_boxes = c.stats.n_leaves = c.stats.n_m2l = 0;
     c.stats.tree_depth = c.stats.fmm_order = 0;
     if (c.opt.far_field == LSS_FAR_FMM) build_fmm(c);
@@ -126,6 +128,8 @@ void eval_fmm_targets(Ctx &c, int64_t n, const int32_t *n_dev, double *phi, doub
     c.ntiles.ensure(16);
     build_tiles(c, n, n_dev, c.tkey2.as<uint64_t>(), fmm_tile(c), c.tleaf.as<int32_t>(), c.tstart.as<int32_t>(),
                 c.ntiles.as<int32_t>());
+    c.tile_order.ensure(sizeof(int32_t) * (n + 1));
+    order_tiles(c, n, c.ntiles.as<int32_t>(), c.tstart.as<int32_t>(), c.tleaf.as<int32_t>());
     if (reset_pairs) LSS_HIP(hipMemsetAsync(c.pairs.p, 0, 2 * sizeof(double), c.stream));
     c.ev_begin();
     launch_eval_fmm(c, n, c.ntiles.as<int32_t>(), c.tstart.as<int32_t>(), n_dev, n, c.tleaf.as<int32_t>(),
@@ -209,6 +213,7 @@ void newton_iteration(Ctx &c, int64_t N, double tau, double *phi, double *grad) 
     launch_newton_targets(c, N);
     if (c.opt.far_field == LSS_FAR_FMM) {
         build_tiles_unsorted(c, N, nact, fmm_tile(c));
+        order_tiles(c, N, c.ntiles.as<int32_t>(), c.tstart.as<int32_t>(), c.tleaf.as<int32_t>());
         launch_eval_fmm(c, N, c.ntiles.as<int32_t>(), c.tstart.as<int32_t>(), nact, N, c.tleaf.as<int32_t>(),
                         nullptr, c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(), nullptr, phi, grad);
     } else {
@@ -490,7 +495,7 @@ void lss_destroy(lss_ctx *ctx) {
     (void)hipSetDevice(c.device);
     (void)hipStreamSynchronize(c.stream);
     DBuf *bufs[] = {&c.verts, &c.tris, &c.tri_off, &c.node_off, &c.rule, &c.sigma, &c.src, &c.vH, &c.tkey,
-                    &c.tkey2, &c.tperm, &c.tperm2, &c.tx, &c.ty, &c.tz, &c.tmesh, &c.sort_tmp, &c.pairs, &c.tile_queue,
+                    &c.tkey2, &c.tperm, &c.tperm2, &c.tx, &c.ty, &c.tz, &c.tmesh, &c.sort_tmp, &c.pairs, &c.tile_queue, &c.tile_order, &c.tile_bucket,
                     &c.tflag, &c.tpos, &c.tstart, &c.ntiles, &c.tleaf,
                     &c.ns.T, &c.ns.H, &c.ns.h, &c.ns.lo, &c.ns.hi, &c.ns.sig, &c.ns.mesh, &c.ns.orig,
                     &c.ns.status, &c.ns.iters, &c.ns.active, &c.ns.active2, &c.ns.flag, &c.ns.blocksum,

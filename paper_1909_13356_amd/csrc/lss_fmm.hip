@@ -183,7 +183,7 @@ __global__ void k_leaf_flags(int64_t n, const int32_t *__restrict__ child, const
 
 // --------------------------------------------------------- gathered GEMM
 typedef double d4 __attribute__((ext_vector_type(4)));
-constexpr int kKB = 32;
+constexpr int kKB = 16;
 
 enum { G_LIST = 0, G_M2M = 1, G_L2L = 2 };
 
@@ -215,67 +215,98 @@ __device__ inline void pair_of(const GemmArgs &a, int64_t j, int64_t &dst, int64
     }
 }
 
-// 64 output rows x 64 pairs per workgroup; wave w owns rows 16w..16w+15 and
-// four 16x16 accumulator tiles (one per group of 16 pairs).
+// 64 output rows x 128 pairs per workgroup; wave w owns pairs 32w..32w+31 of
+// the tile and eight 16x16 accumulator tiles (4 row groups x 2 pair groups).
+// The operator (k-major) and the gathered input columns go through LDS in
+// blocks of kKB coefficients; the next block is fetched into registers while
+// the MFMAs of the current one run.
+constexpr int kTR = 64, kTP = 128;
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
-    __shared__ double As[kKB][64 + 1];
-    __shared__ double Bs[kKB][64 + 1];
-    __shared__ int64_t ssrc[64];
+    __shared__ double As[kKB][kTR + 1];
+    __shared__ double Bs[kKB][kTP + 1];
+    __shared__ int64_t ssrc[kTP];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int r0 = blockIdx.x * 64;
-    const int64_t j0 = (int64_t)blockIdx.y * 64;
-    if (threadIdx.x < 64) {
+    const int r0 = blockIdx.x * kTR;
+    const int64_t j0 = (int64_t)blockIdx.y * kTP;
+    if (threadIdx.x < kTP) {
         int64_t j = j0 + threadIdx.x, d, s;
         double sc;
         if (j < a.npairs) { pair_of(a, j, d, s, sc); ssrc[threadIdx.x] = s; }
         else ssrc[threadIdx.x] = -1;
     }
-    d4 acc[4];
-    for (int t = 0; t < 4; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < a.ncp; k0 += kKB) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < kKB * 64; e += 256) {
-            const int kk = e >> 6, rr = e & 63;
-            As[kk][rr] = (r0 + rr < a.ncp) ? a.opT[(int64_t)(k0 + kk) * a.ncp + r0 + rr] : 0.0;
-            const int cc = e / kKB, k2 = e % kKB;
-            const int64_t s = ssrc[cc];
-            Bs[k2][cc] = s >= 0 ? a.X[s * a.ncp + k0 + k2] : 0.0;
+    __syncthreads();
+    // per thread: A elements (k, r) = (e / kTR, e % kTR) for e = tid + 256 i, i < 4;
+    // B elements (k, c) with c = tid / 2, k = 8 (tid & 1) + i, i < 8 (two threads per column)
+    constexpr int kNA = kKB * kTR / 256, kNB = kKB * kTP / 256;
+    const int bc = threadIdx.x >> 1, bk = (threadIdx.x & 1) * kNB;
+    const int64_t bsrc = ssrc[bc];
+    double ra[kNA], rb[kNB];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < kNA; ++i) {
+            const int e = threadIdx.x + 256 * i, kk = e / kTR, rr = e % kTR;
+            ra[i] = (r0 + rr < a.ncp) ? a.opT[(int64_t)(k0 + kk) * a.ncp + r0 + rr] : 0.0;
         }
+#pragma unroll
+        for (int i = 0; i < kNB; ++i) rb[i] = bsrc >= 0 ? a.X[bsrc * a.ncp + k0 + bk + i] : 0.0;
+    };
+    d4 acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        for (int t = 0; t < 2; ++t) acc[i][t] = d4{0.0, 0.0, 0.0, 0.0};
+    fetch(0);
+    for (int k0 = 0; k0 < a.ncp; k0 += kKB) {
+        __syncthreads();                                   // previous block's MFMAs are done with LDS
+#pragma unroll
+        for (int i = 0; i < kNA; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            As[e / kTR][e % kTR] = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < kNB; ++i) Bs[bk + i][bc] = rb[i];
         __syncthreads();
+        if (k0 + kKB < a.ncp) fetch(k0 + kKB);
 #pragma unroll
         for (int kk = 0; kk < kKB; kk += 4) {
-            const double av = As[kk + (lane >> 4)][16 * w + (lane & 15)];
+            double bv[2];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const double bv = Bs[kk + (lane >> 4)][16 * t + (lane & 15)];
-                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+            for (int t = 0; t < 2; ++t) bv[t] = Bs[kk + (lane >> 4)][32 * w + 16 * t + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const double av = As[kk + (lane >> 4)][16 * i + (lane & 15)];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) acc[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[t], acc[i][t], 0, 0, 0);
             }
         }
     }
-    for (int t = 0; t < 4; ++t) {
-        const int64_t j = j0 + 16 * t + (lane & 15);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int64_t j = j0 + 32 * w + 16 * t + (lane & 15);
         if (j >= a.npairs) continue;
         int64_t d, s;
         double sc;
         pair_of(a, j, d, s, sc);
         double *y = a.Y + d * a.ncp;
-        // v_mfma_f64_16x16x4f64 accumulator: register i of lane l holds row (l/16) + 4i, column l%16
-        for (int i = 0; i < 4; ++i) {
-            const int row = r0 + 16 * w + (lane >> 4) + 4 * i;
-            if (row < a.ncp) y[row] += sc * acc[t][i];
-        }
+        // v_mfma_f64_16x16x4f64 accumulator: register q of lane l holds row (l/16) + 4q, column l%16
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = r0 + 16 * i + (lane >> 4) + 4 * q;
+                if (row < a.ncp) y[row] += sc * acc[i][t][q];
+            }
     }
 }
 
 void gemm(Ctx &c, GemmArgs a) {
     // split long pair lists so that grid.y stays within the launch limit
-    const int64_t chunk = (int64_t)32768 * 64;
+    const int64_t chunk = (int64_t)32768 * kTP;
     for (int64_t j0 = 0; j0 < a.npairs; j0 += chunk) {
         GemmArgs b = a;
         b.npairs = a.npairs - j0 < chunk ? a.npairs - j0 : chunk;
         if (a.mode == G_LIST) { b.mkey = a.mkey + j0; b.mval = a.mval + j0; }
         else b.base = a.base + 8 * j0;
-        dim3 grid((unsigned)ceil_div(b.ncp, 64), (unsigned)ceil_div(b.npairs, 64));
+        dim3 grid((unsigned)ceil_div(b.ncp, kTR), (unsigned)ceil_div(b.npairs, kTP));
         hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, c.stream, b);
         LSS_CHECK_LAUNCH("k_gemm");
     }

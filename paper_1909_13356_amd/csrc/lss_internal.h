@@ -159,6 +159,7 @@ struct Tree {
     DBuf p2p_key, p2p_key2, p2p_val, p2p_val2;    // u64 (T<<32|S), int32
     int64_t n_p2p = 0;
     DBuf p2p_beg, p2p_end;                    // per box, int32 offsets into the sorted p2p list
+    DBuf near_cnt;                            // per box + per mesh (outside targets): direct-list node count
     DBuf m2l_key, m2l_key2, m2l_val, m2l_val2;    // u64 (class<<32|T), int32 S
     int64_t n_m2l = 0;
     std::vector<int64_t> class_beg, class_end;    // host: segments of the sorted m2l list per class
@@ -207,6 +208,8 @@ struct Ctx {
     DBuf tflag, tpos, tstart, ntiles, tleaf;   // FMM eval: leaf of each sorted target, tile heads
     DBuf pairs;               // double accumulator of executed pairs (stats)
     DBuf tile_queue;          // uint32[2] work queue of the FMM evaluation (zero between launches)
+    DBuf tile_order;          // FMM tiles, most expensive first (int32 per tile)
+    DBuf tile_bucket;         // int32[2 * kCostBuckets]: bucket counts (zero between uses), offsets
     bool pairs_pending = false;   // counter not yet read back into stats.last_pairs
     NewtonState ns;
 
@@ -274,6 +277,11 @@ void launch_soa(Ctx &c, const double *x, int64_t n, double *tx, double *ty, doub
 // Newton targets in FMM mode: leaf of each target in its current order and
 // tile heads at leaf changes and every TILE-th position (no sort; capturable)
 void ensure_tiles(Ctx &c, int64_t n_max);
+// tile order for the work queue: tiles bucketed by log2 of their direct-list
+// size, most expensive bucket first (kernels only: capturable)
+constexpr int kCostBuckets = 64;
+void order_tiles(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const int32_t *tile_start,
+                 const int32_t *leaf);
 void build_tiles_unsorted(Ctx &c, int64_t n_max, const int32_t *n_dev, int tile);
 
 // sorting and scans (lss_sort.hip)

@@ -370,6 +370,7 @@ struct FmmEvalArgs {
     // tile queue: [0] next tile, [1] finished workgroups; zero between
     // launches (the last workgroup to finish clears both)
     unsigned int *queue;
+    const int32_t *order;       // queue position -> tile (most expensive first)
 };
 
 // next tile for the workgroup (uniform); tiles are handed out in list order
@@ -469,7 +470,8 @@ __global__ __launch_bounds__(TILE) void k_eval_fmm_f64(FmmEvalArgs a) {
     const int64_t n = a.n_dev ? (int64_t)*a.n_dev : a.n_max;
     const int lane = threadIdx.x;
     __shared__ int slot;
-    for (int tile = next_tile(a, &slot); tile < ntiles; tile = next_tile(a, &slot)) {
+    for (int q = next_tile(a, &slot); q < ntiles; q = next_tile(a, &slot)) {
+        const int tile = a.order[q];
         const int64_t s0 = a.tile_start[tile];
         const int32_t leafk = a.sleaf[s0];
         const int64_t s1 = tile + 1 < ntiles ? (int64_t)a.tile_start[tile + 1] : n;   // tile = [s0, s1)
@@ -590,7 +592,8 @@ __global__ __launch_bounds__(64) void k_eval_fmm_mixed(FmmEvalArgs a) {
     const int64_t n = a.n_dev ? (int64_t)*a.n_dev : a.n_max;
     const int lane = threadIdx.x;
     __shared__ int slot;
-    for (int tile = next_tile(a, &slot); tile < ntiles; tile = next_tile(a, &slot)) {
+    for (int q = next_tile(a, &slot); q < ntiles; q = next_tile(a, &slot)) {
+        const int tile = a.order[q];
         const int64_t s0 = a.tile_start[tile];
         const int32_t B = a.sleaf[s0];
         const int64_t s1 = tile + 1 < ntiles ? (int64_t)a.tile_start[tile + 1] : n;   // tile = [s0, s1)
@@ -736,6 +739,7 @@ void launch_eval_fmm(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const
     a.bmesh = t.bmesh.as<int32_t>();
     a.pairs = c.pairs.as<double>();
     a.queue = c.tile_queue.as<unsigned int>();
+    a.order = c.tile_order.as<int32_t>();
     int64_t g = max_tiles < 16384 ? max_tiles : 16384;
     unsigned grid = (unsigned)(g > 0 ? g : 1);
     if (c.opt.precision == LSS_MIXED) {

@@ -432,6 +432,55 @@ __global__ void k_tile_flags_runs(int64_t n_max, const int32_t *__restrict__ n_d
     flag[i] = (i < n && (i == 0 || leaf[i] != leaf[i - 1] || (i % tile) == 0)) ? 1 : 0;
 }
 
+// nodes on the direct list of every box, and of every mesh's outside range
+__global__ void k_near_count(int64_t nboxes, int32_t nmesh, const int32_t *__restrict__ beg,
+                             const int32_t *__restrict__ end, const int32_t *__restrict__ src,
+                             const int64_t *__restrict__ nb, const int64_t *__restrict__ ne, int64_t *cnt) {
+    int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nboxes) {
+        int64_t s = 0;
+        for (int32_t e = beg[b]; e < end[b]; ++e) s += ne[src[e]] - nb[src[e]];
+        cnt[b] = s;
+    } else if (b < nboxes + nmesh) {
+        const int64_t m = b - nboxes;
+        cnt[b] = ne[m] - nb[m];
+    }
+}
+
+__device__ inline int cost_bucket(int64_t c) {           // 0 = most expensive
+    const int lg = c > 0 ? 63 - __clzll((unsigned long long)c) : 0;
+    return kCostBuckets - 1 - lg;
+}
+
+__global__ void k_tile_bucket_count(int64_t max_tiles, const int32_t *__restrict__ ntiles_dev,
+                                    const int32_t *__restrict__ tile_start, const int32_t *__restrict__ leaf,
+                                    const int64_t *__restrict__ cnt, int32_t *bucket) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= max_tiles || t >= *ntiles_dev) return;
+    atomicAdd(&bucket[cost_bucket(cnt[leaf[tile_start[t]]])], 1);
+}
+
+// single block: offsets from the counts, counts cleared for the next use
+__global__ void k_tile_bucket_scan(int32_t *bucket) {
+    if (threadIdx.x == 0) {
+        int32_t s = 0;
+        for (int i = 0; i < kCostBuckets; ++i) {
+            bucket[kCostBuckets + i] = s;
+            s += bucket[i];
+            bucket[i] = 0;
+        }
+    }
+}
+
+__global__ void k_tile_bucket_scatter(int64_t max_tiles, const int32_t *__restrict__ ntiles_dev,
+                                      const int32_t *__restrict__ tile_start, const int32_t *__restrict__ leaf,
+                                      const int64_t *__restrict__ cnt, int32_t *bucket, int32_t *order) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= max_tiles || t >= *ntiles_dev) return;
+    const int q = atomicAdd(&bucket[kCostBuckets + cost_bucket(cnt[leaf[tile_start[t]]])], 1);
+    order[q] = (int32_t)t;
+}
+
 __global__ void k_soa(int64_t n, const double *__restrict__ x, double *tx, double *ty, double *tz) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -668,6 +717,11 @@ void build_tree(Ctx &c) {
     if (t.n_p2p > 0)
         hipLaunchKernelGGL(k_p2p_ranges, dim3(grid_for(t.n_p2p)), dim3(kBlk), 0, c.stream, t.n_p2p,
                            t.p2p_key2.as<uint64_t>(), t.p2p_beg.as<int32_t>(), t.p2p_end.as<int32_t>());
+    t.near_cnt.ensure(8 * (t.nboxes + nm));
+    hipLaunchKernelGGL(k_near_count, dim3(grid_for(t.nboxes + nm)), dim3(kBlk), 0, c.stream, t.nboxes, nm,
+                       t.p2p_beg.as<int32_t>(), t.p2p_end.as<int32_t>(), t.p2p_val2.as<int32_t>(), t.nb.as<int64_t>(),
+                       t.ne.as<int64_t>(), t.near_cnt.as<int64_t>());
+    LSS_CHECK_LAUNCH("k_near_count");
     t.m2l_key2.ensure(8 * (t.n_m2l + 1)); t.m2l_val2.ensure(4 * (t.n_m2l + 1));
     sort_pairs(c, t.m2l_key.as<uint64_t>(), t.m2l_key2.as<uint64_t>(), t.m2l_val.as<int32_t>(),
                t.m2l_val2.as<int32_t>(), t.n_m2l);
@@ -730,7 +784,20 @@ int64_t build_tiles(Ctx &c, int64_t n_max, const int32_t *n_dev, const uint64_t 
 // starts a tile wherever the leaf changes or TILE targets have been taken.
 // No sort, no host synchronisation, no allocation: safe under stream capture
 // once the buffers have been sized by ensure_tiles.
+void order_tiles(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const int32_t *tile_start,
+                 const int32_t *leaf) {
+    Tree &t = c.tree;
+    const unsigned g = grid_for(max_tiles);
+    hipLaunchKernelGGL(k_tile_bucket_count, dim3(g), dim3(kBlk), 0, c.stream, max_tiles, ntiles_dev, tile_start, leaf,
+                       t.near_cnt.as<int64_t>(), c.tile_bucket.as<int32_t>());
+    hipLaunchKernelGGL(k_tile_bucket_scan, dim3(1), dim3(64), 0, c.stream, c.tile_bucket.as<int32_t>());
+    hipLaunchKernelGGL(k_tile_bucket_scatter, dim3(g), dim3(kBlk), 0, c.stream, max_tiles, ntiles_dev, tile_start,
+                       leaf, t.near_cnt.as<int64_t>(), c.tile_bucket.as<int32_t>(), c.tile_order.as<int32_t>());
+    LSS_CHECK_LAUNCH("order_tiles");
+}
+
 void ensure_tiles(Ctx &c, int64_t n_max) {
+    c.tile_order.ensure(4 * (n_max + 1));
     c.tflag.ensure(4 * (n_max + 1));
     c.tpos.ensure(4 * (n_max + 1));
     c.tstart.ensure(4 * (n_max + 1));
