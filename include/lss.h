@@ -89,7 +89,9 @@ enum {
 enum {
     LSS_NODE_CONVERGED = 0,
     LSS_NODE_MAXITER = 1,     /* not converged after max_iter iterations */
-    LSS_NODE_NOBRACKET = 2,   /* iterates driven past |h| > hmax/2 (hmax = 16 sigma_j/|H|): no root near */
+    LSS_NODE_NOBRACKET = 2,   /* no root near the skeleton: a bisection step went past |h| > 3/4 hmax
+                                 (hmax = 16 sigma_j/|H|) before Phi - 1/2 changed sign, or the
+                                 iteration cap was reached with |h| > hmax/2 */
     LSS_NODE_DEGENERATE_H = 3 /* |H| < 1e-3: no usable pseudonormal direction */
 };
 

@@ -298,7 +298,7 @@ void oracle_project(const double *verts, int64_t nverts, const int32_t *tris, in
         } else {
             const double hmax = 16.0 * sj / nH;
             double lo = -hmax, hi = hmax;
-            int done = 0;
+            int done = 0, seen = 0;     /* bit 1: g > 0 seen, bit 2: g < 0 seen */
             for (int k2 = 1; k2 <= max_iter; ++k2) {
                 double x[3], phi, g[3];
                 for (int c = 0; c < 3; ++c) x[c] = T[c] + h * H[c];
@@ -306,13 +306,17 @@ void oracle_project(const double *verts, int64_t nverts, const int32_t *tris, in
                 const double gv = phi - 0.5;
                 const double gp = H[0] * g[0] + H[1] * g[1] + H[2] * g[2];
                 it = k2;
-                if (gv > 0.0) lo = h;
-                else if (gv < 0.0) hi = h;
+                if (gv > 0.0) { lo = h; seen |= 1; }
+                else if (gv < 0.0) { hi = h; seen |= 2; }
                 else { st = ST_CONVERGED; done = 1; break; }
                 double hn = (gp < 0.0) ? h - gv / gp : NAN;
-                if (!(hn > lo && hn < hi)) hn = 0.5 * (lo + hi);
+                const int newton = hn > lo && hn < hi;
+                if (!newton) hn = 0.5 * (lo + hi);
                 const double dh = hn - h;
                 h = hn;
+                /* a bisection step into the outer quarter of the search range
+                 * without a sign change of g: no root near the skeleton */
+                if (!newton && seen != 3 && fabs(h) > 0.75 * hmax) { st = ST_NOBRACKET; done = 1; break; }
                 if (fabs(dh) <= tau * sj) { st = ST_CONVERGED; done = 1; break; }
             }
             /* not converged: NOBRACKET when the iterates were driven into the

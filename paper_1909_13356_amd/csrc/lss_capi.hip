@@ -498,7 +498,7 @@ void lss_destroy(lss_ctx *ctx) {
                     &c.tkey2, &c.tperm, &c.tperm2, &c.tx, &c.ty, &c.tz, &c.tmesh, &c.sort_tmp, &c.pairs, &c.tile_queue, &c.tile_order, &c.tile_bucket,
                     &c.tflag, &c.tpos, &c.tstart, &c.ntiles, &c.tleaf,
                     &c.ns.T, &c.ns.H, &c.ns.h, &c.ns.lo, &c.ns.hi, &c.ns.sig, &c.ns.mesh, &c.ns.orig,
-                    &c.ns.status, &c.ns.iters, &c.ns.active, &c.ns.active2, &c.ns.flag, &c.ns.blocksum,
+                    &c.ns.status, &c.ns.iters, &c.ns.seen, &c.ns.active, &c.ns.active2, &c.ns.flag, &c.ns.blocksum,
                     &c.ns.nact, &c.ns.hist};
     for (DBuf *b : bufs) b->release();
     if (c.capture_stream) (void)hipStreamDestroy(c.capture_stream);

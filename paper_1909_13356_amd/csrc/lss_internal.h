@@ -99,6 +99,7 @@ struct NewtonState {
     DBuf mesh;           // int32
     DBuf orig;           // int32 original output index
     DBuf status, iters;  // int8
+    DBuf seen;           // int8: bit 1 Phi > 1/2 seen, bit 2 Phi < 1/2 seen
     DBuf active, active2, flag;   // int32 lists / flags
     DBuf blocksum;       // int32 per block counts
     DBuf nact;           // int32[4]: active count, count at iteration start, N

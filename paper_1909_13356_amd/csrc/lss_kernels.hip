@@ -279,7 +279,8 @@ __global__ void k_chart_init(int64_t N, const double *__restrict__ verts, const 
                              const int64_t *__restrict__ tri_off, int32_t nmesh,
                              const double *__restrict__ sigma, const int32_t *__restrict__ perm,
                              double *Tout, double *Hout, double *h, double *lo, double *hi, double *sig,
-                             int32_t *mesh, int32_t *orig, int8_t *status, int8_t *iters, int32_t *flag) {
+                             int32_t *mesh, int32_t *orig, int8_t *status, int8_t *iters, int8_t *seen,
+                             int32_t *flag) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= N) return;
     int64_t q = perm[s];
@@ -297,6 +298,7 @@ __global__ void k_chart_init(int64_t N, const double *__restrict__ verts, const 
     mesh[s] = nmesh > 1 ? mesh_of_tri(tri_off, nmesh, j) : 0;
     orig[s] = (int32_t)q;
     iters[s] = 0;
+    seen[s] = 0;
     bool degenerate = !(nH >= 1e-3);
     status[s] = degenerate ? (int8_t)LSS_NODE_DEGENERATE_H : (int8_t)ST_ACTIVE;
     flag[s] = degenerate ? 0 : 1;
@@ -324,7 +326,7 @@ __global__ void k_newton_targets(const int32_t *__restrict__ nact, const int32_t
 __global__ void k_newton_update(const int32_t *__restrict__ nact, const int32_t *__restrict__ active,
                                 const double *__restrict__ phi, const double *__restrict__ grad,
                                 const double *__restrict__ H, double *h, double *lo, double *hi,
-                                const double *__restrict__ sig, int8_t *status, int8_t *iters,
+                                const double *__restrict__ sig, int8_t *status, int8_t *iters, int8_t *seen,
                                 int32_t *flag, double tau, int32_t max_iter) {
     int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= *nact) return;
@@ -333,25 +335,29 @@ __global__ void k_newton_update(const int32_t *__restrict__ nact, const int32_t 
     double g = phi[a] - 0.5;
     double gp = H[3 * s] * grad[3 * a] + H[3 * s + 1] * grad[3 * a + 1] + H[3 * s + 2] * grad[3 * a + 2];
     int it = iters[s] + 1;
+    int sn = seen[s];               // bit 1: g > 0 seen, bit 2: g < 0 seen
     int st = ST_ACTIVE;
-    if (g > 0.0) l = hs;
-    else if (g < 0.0) u = hs;
+    if (g > 0.0) { l = hs; sn |= 1; }
+    else if (g < 0.0) { u = hs; sn |= 2; }
     else st = LSS_NODE_CONVERGED;
     if (st == ST_ACTIVE) {
         double hn = gp < 0.0 ? hs - g / gp : (double)NAN;
-        if (!(hn > l && hn < u)) hn = 0.5 * (l + u);
+        const bool newton = hn > l && hn < u;
+        if (!newton) hn = 0.5 * (l + u);
         double dh = hn - hs;
         hs = hn;
-        if (fabs(dh) <= tau * sig[s]) st = LSS_NODE_CONVERGED;
-        else if (it >= max_iter) {
-            double hmax = 16.0 * sig[s] / sqrt(H[3 * s] * H[3 * s] + H[3 * s + 1] * H[3 * s + 1] + H[3 * s + 2] * H[3 * s + 2]);
-            st = fabs(hs) > 0.5 * hmax ? LSS_NODE_NOBRACKET : LSS_NODE_MAXITER;
-        }
+        const double hmax = 16.0 * sig[s] / sqrt(H[3 * s] * H[3 * s] + H[3 * s + 1] * H[3 * s + 1] + H[3 * s + 2] * H[3 * s + 2]);
+        // a bisection step into the outer quarter of the search range without
+        // a sign change of g: no root near the skeleton
+        if (!newton && sn != 3 && fabs(hs) > 0.75 * hmax) st = LSS_NODE_NOBRACKET;
+        else if (fabs(dh) <= tau * sig[s]) st = LSS_NODE_CONVERGED;
+        else if (it >= max_iter) st = fabs(hs) > 0.5 * hmax ? LSS_NODE_NOBRACKET : LSS_NODE_MAXITER;
     }
     h[s] = hs;
     lo[s] = l;
     hi[s] = u;
     iters[s] = (int8_t)it;
+    seen[s] = (int8_t)sn;
     status[s] = (int8_t)st;
     flag[a] = st == ST_ACTIVE ? 1 : 0;
 }
@@ -594,6 +600,7 @@ void launch_chart_init(Ctx &c, const double *uv, int32_t np, int64_t N) {
     s.orig.ensure(sizeof(int32_t) * N);
     s.status.ensure(N);
     s.iters.ensure(N);
+    s.seen.ensure(N);
     s.active.ensure(sizeof(int32_t) * N);
     s.active2.ensure(sizeof(int32_t) * N);
     s.flag.ensure(sizeof(int32_t) * N);
@@ -605,6 +612,7 @@ void launch_chart_init(Ctx &c, const double *uv, int32_t np, int64_t N) {
                        c.sigma.as<double>(), c.tperm2.as<int32_t>(), s.T.as<double>(), s.H.as<double>(),
                        s.h.as<double>(), s.lo.as<double>(), s.hi.as<double>(), s.sig.as<double>(),
                        s.mesh.as<int32_t>(), s.orig.as<int32_t>(), s.status.as<int8_t>(), s.iters.as<int8_t>(),
+                       s.seen.as<int8_t>(),
                        s.flag.as<int32_t>());
     LSS_CHECK_LAUNCH("k_chart_init");
     // initial active list: all non-degenerate nodes, in sorted order
@@ -641,6 +649,7 @@ void launch_newton_update(Ctx &c, int64_t N, double tau, const double *phi, cons
     hipLaunchKernelGGL(k_newton_update, dim3(grid_for(N)), dim3(kBlk), 0, c.stream, s.nact.as<int32_t>(),
                        s.active.as<int32_t>(), phi, grad, s.H.as<double>(), s.h.as<double>(), s.lo.as<double>(),
                        s.hi.as<double>(), s.sig.as<double>(), s.status.as<int8_t>(), s.iters.as<int8_t>(),
+                       s.seen.as<int8_t>(),
                        s.flag.as<int32_t>(), tau, maxit);
     LSS_CHECK_LAUNCH("k_newton_update");
 }

@@ -382,3 +382,23 @@ def test_newton_nobracket_and_degenerate():
     t2 = np.array([[0, 1, 2], [0, 2, 1]], np.int32)
     h, x, st, it = oracle.project(P, t2, [0.1], dunavant6(), chart_nodes(1))
     assert np.all(st == 3) and np.all(h == 0) and np.all(it == 0)
+
+
+def test_newton_no_root_is_never_converged():
+    """Where Phi - 1/2 keeps one sign on the whole search segment there is no
+    root: whatever the tolerance, the node ends NOBRACKET within a few
+    bisection steps instead of creeping to the end of the range."""
+    v, t = cube_mesh(1)
+    sigma = 5.0
+    uv = chart_nodes(1)
+    H = oracle.pseudonormals(v, t)
+    j = 0
+    T = v[t[j, 0]] + uv[0, 0] * (v[t[j, 1]] - v[t[j, 0]]) + uv[0, 1] * (v[t[j, 2]] - v[t[j, 0]])
+    Hj = H[t[j, 0]] + uv[0, 0] * (H[t[j, 1]] - H[t[j, 0]]) + uv[0, 1] * (H[t[j, 2]] - H[t[j, 0]])
+    hmax = 16 * sigma / np.linalg.norm(Hj)
+    hs = np.linspace(-hmax, hmax, 41)
+    phi, _ = oracle.evaluate(v, t, [sigma], dunavant6(), T[None, :] + hs[:, None] * Hj[None, :])
+    assert np.all(phi < 0.5)
+    for tau in (1e-6, 1e-12):
+        h, x, st, it = oracle.project(v, t, [sigma], dunavant6(), uv[:1], sel=[j], tau=tau)
+        assert st[0] == 2 and it[0] <= 6 and abs(h[0]) > 0.75 * hmax
