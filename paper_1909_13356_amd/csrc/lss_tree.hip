@@ -452,12 +452,13 @@ __device__ inline int cost_bucket(int64_t c) {           // 0 = most expensive
     return kCostBuckets - 1 - lg;
 }
 
+// grid-stride over the tiles (their count is on the device)
 __global__ void k_tile_bucket_count(int64_t max_tiles, const int32_t *__restrict__ ntiles_dev,
                                     const int32_t *__restrict__ tile_start, const int32_t *__restrict__ leaf,
                                     const int64_t *__restrict__ cnt, int32_t *bucket) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= max_tiles || t >= *ntiles_dev) return;
-    atomicAdd(&bucket[cost_bucket(cnt[leaf[tile_start[t]]])], 1);
+    const int64_t nt = min((int64_t)*ntiles_dev, max_tiles);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&bucket[cost_bucket(cnt[leaf[tile_start[t]]])], 1);
 }
 
 // single block: offsets from the counts, counts cleared for the next use
@@ -475,10 +476,11 @@ __global__ void k_tile_bucket_scan(int32_t *bucket) {
 __global__ void k_tile_bucket_scatter(int64_t max_tiles, const int32_t *__restrict__ ntiles_dev,
                                       const int32_t *__restrict__ tile_start, const int32_t *__restrict__ leaf,
                                       const int64_t *__restrict__ cnt, int32_t *bucket, int32_t *order) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= max_tiles || t >= *ntiles_dev) return;
-    const int q = atomicAdd(&bucket[kCostBuckets + cost_bucket(cnt[leaf[tile_start[t]]])], 1);
-    order[q] = (int32_t)t;
+    const int64_t nt = min((int64_t)*ntiles_dev, max_tiles);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x) {
+        const int q = atomicAdd(&bucket[kCostBuckets + cost_bucket(cnt[leaf[tile_start[t]]])], 1);
+        order[q] = (int32_t)t;
+    }
 }
 
 __global__ void k_soa(int64_t n, const double *__restrict__ x, double *tx, double *ty, double *tz) {
@@ -787,7 +789,7 @@ int64_t build_tiles(Ctx &c, int64_t n_max, const int32_t *n_dev, const uint64_t 
 void order_tiles(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const int32_t *tile_start,
                  const int32_t *leaf) {
     Tree &t = c.tree;
-    const unsigned g = grid_for(max_tiles);
+    const unsigned g = grid_for(max_tiles) < 2048u ? grid_for(max_tiles) : 2048u;
     hipLaunchKernelGGL(k_tile_bucket_count, dim3(g), dim3(kBlk), 0, c.stream, max_tiles, ntiles_dev, tile_start, leaf,
                        t.near_cnt.as<int64_t>(), c.tile_bucket.as<int32_t>());
     hipLaunchKernelGGL(k_tile_bucket_scan, dim3(1), dim3(64), 0, c.stream, c.tile_bucket.as<int32_t>());
