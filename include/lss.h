@@ -136,7 +136,10 @@ typedef struct lss_stats {
                                  the captured Newton iterations (target update, evaluation,
                                  Newton step and compaction together) */
     int32_t pair_kernel_launches;  /* lss_eval: pair-kernel launches timed in pair_kernel_ms;
-                                      lss_project: graph launches (8 iterations each) */
+                                      lss_project: timed launches of Newton iterations (graphs of
+                                      8 iterations; with LSS_FAR_FMM the first iteration runs on
+                                      its own, and the active list is re-ordered by leaf before
+                                      every graph launch) */
     int32_t pad0;
     double  lane_pairs;       /* pair evaluations the pair kernels spent, idle lanes of partly
                                  filled tiles included (last_pairs / lane_pairs = lane use) */

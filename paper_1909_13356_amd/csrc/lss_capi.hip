@@ -275,19 +275,27 @@ void project(Ctx &c, const double *uv, int32_t np, double *h, double *xout, int8
     // Iterations run in captured chunks; a node leaves the active list when it
     // converges or reaches maxit, so iterations past the last active one are
     // empty launches and the host only checks the count between chunks.
+    const bool fmm = c.opt.far_field == LSS_FAR_FMM;
     const int chunk = std::min(maxit, kNewtonChunk);
     hipGraphExec_t exec = capture_newton(c, N, tau, phi.as<double>(), grad.as<double>(), chunk);
     c.ev_reset();
     try {
-        for (int done = 0; done < maxit; done += chunk) {
+        int done = 0;
+        if (fmm && maxit > 1) {     // first step from the chart points, then re-bin by leaf
             c.ev_begin();
-            LSS_HIP(hipGraphLaunch(exec, c.stream));
+            newton_iteration(c, N, tau, phi.as<double>(), grad.as<double>());
             c.ev_end();
-            if (done + chunk >= maxit) break;
+            done = 1;
+        }
+        for (; done < maxit; done += chunk) {
             int32_t nact = 0;
             LSS_HIP(hipMemcpyAsync(&nact, s.nact.p, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
             LSS_HIP(hipStreamSynchronize(c.stream));
             if (nact == 0) break;
+            if (fmm && done > 0) rebin_active(c, N, nact);
+            c.ev_begin();
+            LSS_HIP(hipGraphLaunch(exec, c.stream));
+            c.ev_end();
         }
         LSS_HIP(hipStreamSynchronize(c.stream));
     } catch (...) {

@@ -284,6 +284,7 @@ constexpr int kCostBuckets = 64;
 void order_tiles(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const int32_t *tile_start,
                  const int32_t *leaf);
 void build_tiles_unsorted(Ctx &c, int64_t n_max, const int32_t *n_dev, int tile);
+void rebin_active(Ctx &c, int64_t N, int64_t nact);
 
 // sorting and scans (lss_sort.hip)
 size_t sort_pairs_u64_tmp_bytes(int64_t n);

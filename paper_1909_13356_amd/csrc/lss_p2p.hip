@@ -175,6 +175,57 @@ __device__ __forceinline__ void nodes64(const Src *sh, double x, double y, doubl
 
 constexpr int kNodeGroup64 = 4;
 
+constexpr int kNodeGroup = 4;
+
+template <int K>
+__device__ __forceinline__ void nodes32(const SrcF *sh, float x, float y, float z, float xl, float yl, float zl,
+                                        float &p, float &gx, float &gy, float &gz) {
+    float dx[K], dy[K], dz[K], u[K], ad[K], S[K], T[K];
+    bool nr[K], any = false;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const SrcF s = sh[k];
+        dx[k] = (x - s.yx) + (xl - s.lx);
+        dy[k] = (y - s.yy) + (yl - s.ly);
+        dz[k] = (z - s.yz) + (zl - s.lz);
+        const float r2 = fmaf(dx[k], dx[k], fmaf(dy[k], dy[k], dz[k] * dz[k]));
+        ad[k] = fmaf(s.ax, dx[k], fmaf(s.ay, dy[k], s.az * dz[k]));
+        u[k] = r2 * s.s2;
+        nr[k] = u[k] < (float)KF32_X;
+        any = any || nr[k];
+        const float r = __builtin_amdgcn_rsqf(fmaxf(u[k], (float)KF32_X));
+        const float rr = r * r;
+        S[k] = kSqrtPiHalfF * rr * r;
+        T[k] = 1.5f * S[k] * rr;
+    }
+    if (any) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const float t = fminf(u[k], (float)KF32_X) * (float)KF32_INV_X;
+            float ps = kf32_ps[KF32_PS_DEG], pt = kf32_pt[KF32_PT_DEG], q = kf32_q[KF32_Q_DEG];
+#pragma unroll
+            for (int i = KF32_Q_DEG - 1; i >= 0; --i) {
+                ps = fmaf(ps, t, kf32_ps[i]);
+                pt = fmaf(pt, t, kf32_pt[i]);
+                q = fmaf(q, t, kf32_q[i]);
+            }
+            const float rq = __builtin_amdgcn_rcpf(q);
+            S[k] = nr[k] ? ps * rq : S[k];
+            T[k] = nr[k] ? pt * rq : T[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const SrcF &s = sh[k];
+        const float g = ad[k] * T[k] * s.s2x2;
+        p = fmaf(-ad[k], S[k], p);
+        gx = fmaf(g, dx[k], fmaf(-s.ax, S[k], gx));
+        gy = fmaf(g, dy[k], fmaf(-s.ay, S[k], gy));
+        gz = fmaf(g, dz[k], fmaf(-s.az, S[k], gz));
+    }
+}
+
+
 __device__ __forceinline__ void pair32(const SrcF &s, float x, float y, float z, float xl, float yl, float zl,
                                        float &p, float &gx, float &gy, float &gz) {
     // d = (x_hi - y_hi) + (x_lo - y_lo): positions carried as float-float
@@ -223,12 +274,17 @@ __global__ __launch_bounds__(TILE) void k_p2p_direct_f64(
         const int cnt = (int)(hi - c0 < TILE ? hi - c0 : TILE);
         __syncthreads();
         if (lane < cnt) sh[lane] = src[c0 + lane];
+        else {                                  // zero records pad the chunk to whole node groups
+            Src f;
+            f.yx = f.yy = f.yz = f.ax = f.ay = f.az = f.s2x2 = 0.0;
+            f.s2 = 1.0e300;
+            sh[lane] = f;
+        }
         __syncthreads();
         double p = 0, gx = 0, gy = 0, gz = 0;
         const bool full = c0 >= b && c0 + cnt <= e;
         if (__all(full)) {
-#pragma unroll 2
-            for (int j = 0; j < cnt; ++j) pair64(sh[j], x, y, z, p, gx, gy, gz);
+            for (int j = 0; j < cnt; j += kNodeGroup64) nodes64<kNodeGroup64>(sh + j, x, y, z, p, gx, gy, gz);
         } else {
             const int jb = (int)(b - c0 > 0 ? (b - c0 < cnt ? b - c0 : cnt) : 0);
             const int je = (int)(e - c0 < cnt ? (e - c0 > 0 ? e - c0 : 0) : cnt);
@@ -283,22 +339,28 @@ __global__ __launch_bounds__(TILE) void k_p2p_direct_mixed(
     for (int64_t c0 = lo; c0 < hi; c0 += TILE) {
         const int cnt = (int)(hi - c0 < TILE ? hi - c0 : TILE);
         __syncthreads();
-        if (lane < cnt) {
-            const Src s = src[c0 + lane];
+        {
             SrcF f;
-            const double qx = s.yx - ox, qy = s.yy - oy, qz = s.yz - oz;
-            f.yx = (float)qx;
-            f.yy = (float)qy;
-            f.yz = (float)qz;
-            f.lx = (float)(qx - (double)f.yx);
-            f.ly = (float)(qy - (double)f.yy);
-            f.lz = (float)(qz - (double)f.yz);
+            if (lane < cnt) {
+                const Src s = src[c0 + lane];
+                const double qx = s.yx - ox, qy = s.yy - oy, qz = s.yz - oz;
+                f.yx = (float)qx;
+                f.yy = (float)qy;
+                f.yz = (float)qz;
+                f.lx = (float)(qx - (double)f.yx);
+                f.ly = (float)(qy - (double)f.yy);
+                f.lz = (float)(qz - (double)f.yz);
+                f.s2 = (float)s.s2;
+                f.ax = (float)s.ax;
+                f.ay = (float)s.ay;
+                f.az = (float)s.az;
+                f.s2x2 = (float)s.s2x2;
+            } else {                            // zero record: no contribution, far branch
+                f.yx = f.yy = f.yz = f.lx = f.ly = f.lz = 0.0f;
+                f.ax = f.ay = f.az = f.s2x2 = 0.0f;
+                f.s2 = 1.0e30f;
+            }
             f.pad = 0.0f;
-            f.s2 = (float)s.s2;
-            f.ax = (float)s.ax;
-            f.ay = (float)s.ay;
-            f.az = (float)s.az;
-            f.s2x2 = (float)s.s2x2;
             sh[lane] = f;
         }
         __syncthreads();
@@ -310,9 +372,8 @@ __global__ __launch_bounds__(TILE) void k_p2p_direct_mixed(
         for (int j0 = 0; j0 < cnt; j0 += 32) {
             float p = 0, gx = 0, gy = 0, gz = 0;
             const int j1 = j0 + 32 < cnt ? j0 + 32 : cnt;
-            if (wave_full) {
-#pragma unroll 4
-                for (int j = j0; j < j1; ++j) pair32(sh[j], x, y, z, xl, yl, zl, p, gx, gy, gz);
+            if (wave_full) {                // chunk padded with zero records to whole node groups
+                for (int j = j0; j < j1; j += kNodeGroup) nodes32<kNodeGroup>(sh + j, x, y, z, xl, yl, zl, p, gx, gy, gz);
             } else {
                 const int a0 = j0 > jb ? j0 : jb, a1 = j1 < je ? j1 : je;
                 for (int j = a0; j < a1; ++j) pair32(sh[j], x, y, z, xl, yl, zl, p, gx, gy, gz);
@@ -530,56 +591,6 @@ __global__ __launch_bounds__(TILE) void k_eval_fmm_f64(FmmEvalArgs a) {
     queue_done(a);
 }
 
-
-constexpr int kNodeGroup = 4;
-
-template <int K>
-__device__ __forceinline__ void nodes32(const SrcF *sh, float x, float y, float z, float xl, float yl, float zl,
-                                        float &p, float &gx, float &gy, float &gz) {
-    float dx[K], dy[K], dz[K], u[K], ad[K], S[K], T[K];
-    bool nr[K], any = false;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const SrcF s = sh[k];
-        dx[k] = (x - s.yx) + (xl - s.lx);
-        dy[k] = (y - s.yy) + (yl - s.ly);
-        dz[k] = (z - s.yz) + (zl - s.lz);
-        const float r2 = fmaf(dx[k], dx[k], fmaf(dy[k], dy[k], dz[k] * dz[k]));
-        ad[k] = fmaf(s.ax, dx[k], fmaf(s.ay, dy[k], s.az * dz[k]));
-        u[k] = r2 * s.s2;
-        nr[k] = u[k] < (float)KF32_X;
-        any = any || nr[k];
-        const float r = __builtin_amdgcn_rsqf(fmaxf(u[k], (float)KF32_X));
-        const float rr = r * r;
-        S[k] = kSqrtPiHalfF * rr * r;
-        T[k] = 1.5f * S[k] * rr;
-    }
-    if (any) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const float t = fminf(u[k], (float)KF32_X) * (float)KF32_INV_X;
-            float ps = kf32_ps[KF32_PS_DEG], pt = kf32_pt[KF32_PT_DEG], q = kf32_q[KF32_Q_DEG];
-#pragma unroll
-            for (int i = KF32_Q_DEG - 1; i >= 0; --i) {
-                ps = fmaf(ps, t, kf32_ps[i]);
-                pt = fmaf(pt, t, kf32_pt[i]);
-                q = fmaf(q, t, kf32_q[i]);
-            }
-            const float rq = __builtin_amdgcn_rcpf(q);
-            S[k] = nr[k] ? ps * rq : S[k];
-            T[k] = nr[k] ? pt * rq : T[k];
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const SrcF &s = sh[k];
-        const float g = ad[k] * T[k] * s.s2x2;
-        p = fmaf(-ad[k], S[k], p);
-        gx = fmaf(g, dx[k], fmaf(-s.ax, S[k], gx));
-        gy = fmaf(g, dy[k], fmaf(-s.ay, S[k], gy));
-        gz = fmaf(g, dz[k], fmaf(-s.az, S[k], gz));
-    }
-}
 
 // Mixed path: one wavefront per tile of 64 targets; each staged chunk of 64
 // node records is padded with zero records to whole groups of kNodeGroup.

@@ -483,6 +483,11 @@ __global__ void k_tile_bucket_scatter(int64_t max_tiles, const int32_t *__restri
     }
 }
 
+__global__ void k_leaf_keys(int64_t n, const int32_t *__restrict__ leaf, uint64_t *keys) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) keys[i] = (uint64_t)(uint32_t)leaf[i];
+}
+
 __global__ void k_soa(int64_t n, const double *__restrict__ x, double *tx, double *ty, double *tz) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -806,6 +811,28 @@ void ensure_tiles(Ctx &c, int64_t n_max) {
     c.tleaf.ensure(4 * (n_max + 1));
     c.ntiles.ensure(16);
     c.ns.blocksum.ensure(sizeof(int32_t) * (ceil_div(n_max > 0 ? n_max : 1, 1024) + 4));
+}
+
+// Newton targets drift off their chart points, so after a step the active
+// list is re-ordered by the leaf of each target's current position (stable:
+// chart order within a leaf); the captured iterations then tile full leaves.
+void rebin_active(Ctx &c, int64_t N, int64_t nact) {
+    if (nact <= 0) return;
+    NewtonState &s = c.ns;
+    Tree &t = c.tree;
+    launch_newton_targets(c, N);
+    hipLaunchKernelGGL(k_leaf_direct, dim3(grid_for(nact)), dim3(kBlk), 0, c.stream, nact, s.nact.as<int32_t>(),
+                       c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(),
+                       t.nroot > 1 ? c.tmesh.as<int32_t>() : nullptr, t.root.as<double>(), t.bits,
+                       t.child.as<int32_t>(), (int32_t)t.nboxes, c.tleaf.as<int32_t>());
+    hipLaunchKernelGGL(k_leaf_keys, dim3(grid_for(nact)), dim3(kBlk), 0, c.stream, nact, c.tleaf.as<int32_t>(),
+                       c.tkey.as<uint64_t>());
+    LSS_CHECK_LAUNCH("rebin_active");
+    int bits = 1;
+    while ((int64_t(1) << bits) <= t.nboxes + t.nroot) ++bits;
+    sort_pairs(c, c.tkey.as<uint64_t>(), c.tkey2.as<uint64_t>(), s.active.as<int32_t>(), s.active2.as<int32_t>(), nact,
+               bits);
+    LSS_HIP(hipMemcpyAsync(s.active.p, s.active2.p, sizeof(int32_t) * nact, hipMemcpyDeviceToDevice, c.stream));
 }
 
 void build_tiles_unsorted(Ctx &c, int64_t n_max, const int32_t *n_dev, int tile) {
