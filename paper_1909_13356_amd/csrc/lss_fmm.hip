@@ -60,35 +60,39 @@ __global__ void k_fill_op(int kind, int p, int ncp, int nops, const cd *__restri
 }
 
 // ------------------------------------------------------------------ P2M
-constexpr int kG = 8;          // nodes per pass
-constexpr int kNPT = 4;        // coefficients per thread (p <= 40)
-
 struct Geo {
     const double *root;         // per-mesh root cubes (corner xyz, side)
     const int32_t *bmesh;
 };
 
-// One workgroup per non-empty leaf.  Per pass of kG nodes: the regular
-// solid harmonics U_n^m (n < p) of every node are tabulated in LDS, one
-// column m per thread, by the order recurrence with a table of the
-// reciprocals 1/((n+m)(n-m)); then each thread adds the dipole terms of its
-// coefficients (n, m) for the kG nodes.
-__global__ __launch_bounds__(kBlk) void k_p2m(const int32_t *__restrict__ nleaf_dev, const int32_t *__restrict__ leaves,
-                                                int p, int ncp, Geo g, const int32_t *__restrict__ lev,
-                                                const int32_t *__restrict__ ijk, const int64_t *__restrict__ nb,
-                                                const int64_t *__restrict__ ne, const Src *__restrict__ src, double *M) {
+// P2M by columns: one wavefront per non-empty leaf; lane (g, m) owns column
+// m = 0..p of the regular solid harmonics of node g of a group of G = 64/(p+1)
+// nodes.  At step s every lane holds U_s^m (zero for m > s; the diagonal is
+// built up meanwhile), takes U_s^{m-1} and U_s^{m+1} from its neighbours and
+// adds the dipole term of M_{s+1}^m into an LDS accumulator of its node slot.
+// No division and no barrier inside the node loop.
+__global__ __launch_bounds__(64) void k_p2m_cols(const int32_t *__restrict__ nleaf_dev,
+                                                 const int32_t *__restrict__ leaves, int p, int ncp, Geo g,
+                                                 const int32_t *__restrict__ lev, const int32_t *__restrict__ ijk,
+                                                 const int64_t *__restrict__ nb, const int64_t *__restrict__ ne,
+                                                 const Src *__restrict__ src, double *M) {
     extern __shared__ double smem[];
-    const int tstride = fmm::tri(p - 1, p - 1) + 1;
-    cd *U = reinterpret_cast<cd *>(smem);                 // kG tables
-    double *nd = smem + 2 * kG * tstride;                 // kG x (rx, ry, rz, ax, ay, az)
-    double *rinv = nd + 6 * kG;                           // 1/((n+m)(n-m)) at tri(n, m), n > m
+    const int C = p + 1, G = 64 / C;
+    const int ntri = (p + 1) * (p + 2) / 2;
+    cd *acc = reinterpret_cast<cd *>(smem);               // G x ntri, at tri(n, m)
+    double *rinv = smem + 2 * G * ntri;                   // 1/((n+m)(n-m)) at tri(n, m), n > m
+    double *dfac = rinv + ntri;                           // -1/(2t), t = 1..p
     if ((int)blockIdx.x >= *nleaf_dev) return;
-    for (int i = threadIdx.x; i < tstride; i += kBlk) {
+    const int lane = threadIdx.x;
+    for (int i = lane; i < ntri; i += 64) {
         int n = 0;
         while ((n + 1) * (n + 2) / 2 <= i) ++n;
         const int m = i - n * (n + 1) / 2;
         rinv[i] = n > m ? 1.0 / ((double)(n + m) * (double)(n - m)) : 0.0;
     }
+    for (int t = lane; t <= p; t += 64) dfac[t] = t > 0 ? -0.5 / (double)t : 0.0;
+    for (int i = lane; i < G * ntri; i += 64) acc[i] = cd{0.0, 0.0};
+    __syncthreads();
     const int32_t b = leaves[blockIdx.x];
     const double s = box_side(g.root, g.bmesh, b, lev[b]);
     const double *o = g.root + 4 * g.bmesh[b];
@@ -96,82 +100,69 @@ __global__ __launch_bounds__(kBlk) void k_p2m(const int32_t *__restrict__ nleaf_
                  c2 = o[2] + (ijk[3 * b + 2] + 0.5) * s;
     const double inv4pis = 1.0 / (4.0 * kPi * s);
     const double invs = 1.0 / s;
-    // coefficient slots of this thread: (n, m), n = 1..p, m = 0..n enumerated row by row
-    int qn[kNPT], qm[kNPT];
-    double are[kNPT], aim[kNPT];
-    const int ncplx = (p + 1) * (p + 2) / 2 - 1;
-    for (int u = 0; u < kNPT; ++u) {
-        int q = threadIdx.x + u * kBlk;
-        qn[u] = -1;
-        are[u] = aim[u] = 0.0;
-        if (q < ncplx) {
-            int idx = q + 1, n = 0;                        // skip (0, 0)
-            while ((n + 1) * (n + 2) / 2 <= idx) ++n;
-            qn[u] = n;
-            qm[u] = idx - n * (n + 1) / 2;
-        }
-    }
+    const int gi = lane / C, m = lane % C;
+    const bool slot = gi < G;                             // lane holds a (node, column) slot
+    cd *accg = acc + (slot ? gi : 0) * ntri;
     const int64_t b0 = nb[b], b1 = ne[b];
-    for (int64_t k0 = b0; k0 < b1; k0 += kG) {
-        const int gn = (int)(b1 - k0 < kG ? b1 - k0 : kG);
-        __syncthreads();
-        if ((int)threadIdx.x < gn) {
-            const Src sr = src[k0 + threadIdx.x];
+    for (int64_t k0 = b0; k0 < b1; k0 += G) {
+        const int64_t k = k0 + gi;
+        const bool live = slot && k < b1;
+        double x = 0, y = 0, z = 0, ax = 0, ay = 0, az = 0;
+        if (live) {
+            const Src sr = src[k];
             // unfold the dipole: a = a' / c(sigma), 1/c = 4 sqrt2 pi^1.5 sigma^3, sigma^2 = 1/(2 s2)
             const double sg2 = 0.5 / sr.s2;
             const double f = 4.0 * 1.4142135623730951 * 5.568327996831708 * sg2 * sqrt(sg2);
-            double *q = nd + 6 * threadIdx.x;
-            q[0] = (sr.yx - c0) * invs;
-            q[1] = (sr.yy - c1) * invs;
-            q[2] = (sr.yz - c2) * invs;
-            q[3] = sr.ax * f;
-            q[4] = sr.ay * f;
-            q[5] = sr.az * f;
+            x = (sr.yx - c0) * invs;
+            y = (sr.yy - c1) * invs;
+            z = (sr.yz - c2) * invs;
+            ax = sr.ax * f;
+            ay = sr.ay * f;
+            az = sr.az * f;
         }
-        __syncthreads();
-        for (int task = threadIdx.x; task < kG * 64; task += kBlk) {   // column m of U(r_gi), orders m..p-1
-            const int gi = task / 64, m = task % 64;
-            if (gi < gn && m <= p - 1) {
-                const double *q = nd + 6 * gi;
-                const double x = q[0], y = q[1], z = q[2], r2 = x * x + y * y + z * z;
-                cd d = {1.0, 0.0};
-                for (int t = 1; t <= m; ++t) d = fmm::cscale(fmm::cmul(d, cd{x, y}), -0.5 / (double)t);
-                cd *Ug = U + gi * tstride;
-                Ug[fmm::tri(m, m)] = d;
-                cd um2 = {0.0, 0.0}, um1 = d;
-                for (int n = m + 1; n <= p - 1; ++n) {
-                    const double inv = rinv[fmm::tri(n, m)];
-                    const double a2 = (double)(2 * n - 1) * z;
-                    cd un = {(a2 * um1.re - r2 * um2.re) * inv, (a2 * um1.im - r2 * um2.im) * inv};
-                    Ug[fmm::tri(n, m)] = un;
-                    um2 = um1;
-                    um1 = un;
-                }
+        const double r2 = x * x + y * y + z * z;
+        cd d = {1.0, 0.0}, u1 = {0.0, 0.0}, u2 = {0.0, 0.0};
+        for (int st = 0; st < p; ++st) {
+            cd u = {0.0, 0.0};
+            if (st == m) {
+                u = d;
+            } else if (st > m) {
+                const double w = rinv[fmm::tri(st, m)];
+                const double a2 = (double)(2 * st - 1) * z;
+                u = cd{(a2 * u1.re - r2 * u2.re) * w, (a2 * u1.im - r2 * u2.im) * w};
+            } else {
+                d = fmm::cscale(fmm::cmul(d, cd{x, y}), dfac[st + 1]);
             }
-        }
-        __syncthreads();
-        for (int u = 0; u < kNPT; ++u) {
-            if (qn[u] < 0) continue;
-            const int n = qn[u], m = qm[u];
-            for (int gi = 0; gi < gn; ++gi) {
-                const cd *Ug = U + gi * tstride;
-                const double *q = nd + 6 * gi;
-                const double ax = q[3], ay = q[4], az = q[5];
-                cd up = fmm::tget(Ug, n - 1, m + 1), dn = fmm::tget(Ug, n - 1, m - 1), zz = fmm::tget(Ug, n - 1, m);
-                cd t = fmm::cadd(fmm::cadd(fmm::cmul(cd{0.5 * ax, -0.5 * ay}, up), fmm::cmul(cd{-0.5 * ax, -0.5 * ay}, dn)),
-                                 fmm::cscale(zz, az));
-                are[u] -= inv4pis * t.re;       // conj, times -1/(4 pi s)
-                aim[u] += inv4pis * t.im;
+            if (st >= m) { u2 = u1; u1 = u; }
+            // neighbours' columns at order st (same node slot; U^{-1} = -conj(U^1))
+            const double upre = __shfl(u.re, lane + 1), upim = __shfl(u.im, lane + 1);
+            const double dnre = __shfl(u.re, lane - 1), dnim = __shfl(u.im, lane - 1);
+            cd up = m + 1 < C ? cd{upre, upim} : cd{0.0, 0.0};
+            cd dn = m >= 1 ? cd{dnre, dnim} : cd{-upre, upim};
+            if (live && m <= st + 1) {
+                const cd t = fmm::cadd(fmm::cadd(fmm::cmul(cd{0.5 * ax, -0.5 * ay}, up),
+                                                 fmm::cmul(cd{-0.5 * ax, -0.5 * ay}, dn)),
+                                       fmm::cscale(u, az));
+                cd &A = accg[fmm::tri(st + 1, m)];
+                A.re -= inv4pis * t.re;         // conj, times -1/(4 pi s)
+                A.im += inv4pis * t.im;
             }
         }
     }
+    __syncthreads();
     double *Mb = M + (int64_t)b * ncp;
-    for (int u = 0; u < kNPT; ++u) {
-        if (qn[u] < 0) continue;
-        Mb[fmm::ire(qn[u], qm[u])] = are[u];
-        if (qm[u] > 0) Mb[fmm::iim(qn[u], qm[u])] = aim[u];
+    for (int i = lane; i < ntri; i += 64) {
+        int n = 0;
+        while ((n + 1) * (n + 2) / 2 <= i) ++n;
+        const int mm = i - n * (n + 1) / 2;
+        if (n == 0) continue;
+        double re = 0.0, im = 0.0;
+        for (int q = 0; q < G; ++q) { re += acc[q * ntri + i].re; im += acc[q * ntri + i].im; }
+        Mb[fmm::ire(n, mm)] = re;
+        if (mm > 0) Mb[fmm::iim(n, mm)] = im;
     }
 }
+
 
 __global__ void k_leaf_flags(int64_t n, const int32_t *__restrict__ child, const int64_t *__restrict__ nb,
                              const int64_t *__restrict__ ne, int32_t *flag, int32_t *ids) {
@@ -396,12 +387,12 @@ void build_fmm(Ctx &c) {
     LSS_HIP(hipStreamSynchronize(c.stream));
     c.stats.n_leaves = nl;
     if (nl > 0) {
-        const int tstride = fmm::tri(p - 1, p - 1) + 1;
-        size_t shm = sizeof(double) * (2 * kG * tstride + 6 * kG + tstride);
-        hipLaunchKernelGGL(k_p2m, dim3(nl), dim3(kBlk), shm, c.stream, nleaf.as<int32_t>(), leaves.as<int32_t>(), p, ncp, g,
-                           t.level.as<int32_t>(), t.ijk.as<int32_t>(), t.nb.as<int64_t>(), t.ne.as<int64_t>(),
+        const int ntri = (p + 1) * (p + 2) / 2, G = 64 / (p + 1);
+        size_t shm = sizeof(double) * (2 * G * ntri + ntri + p + 1);
+        hipLaunchKernelGGL(k_p2m_cols, dim3(nl), dim3(64), shm, c.stream, nleaf.as<int32_t>(), leaves.as<int32_t>(), p,
+                           ncp, g, t.level.as<int32_t>(), t.ijk.as<int32_t>(), t.nb.as<int64_t>(), t.ne.as<int64_t>(),
                            t.src.as<Src>(), t.M.as<double>());
-        LSS_CHECK_LAUNCH("k_p2m");
+        LSS_CHECK_LAUNCH("k_p2m_cols");
     }
     // upward pass: M2M from level depth to 1 into their parents
     for (int lvl = t.depth; lvl >= 1; --lvl) {

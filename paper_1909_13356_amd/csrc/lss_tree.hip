@@ -452,13 +452,20 @@ __device__ inline int cost_bucket(int64_t c) {           // 0 = most expensive
     return kCostBuckets - 1 - lg;
 }
 
-// grid-stride over the tiles (their count is on the device)
+// grid-stride over the tiles (their count is on the device); per-block LDS
+// histograms keep the global atomics at one per bucket per block
 __global__ void k_tile_bucket_count(int64_t max_tiles, const int32_t *__restrict__ ntiles_dev,
                                     const int32_t *__restrict__ tile_start, const int32_t *__restrict__ leaf,
                                     const int64_t *__restrict__ cnt, int32_t *bucket) {
+    __shared__ int32_t h[kCostBuckets];
+    for (int i = threadIdx.x; i < kCostBuckets; i += blockDim.x) h[i] = 0;
+    __syncthreads();
     const int64_t nt = min((int64_t)*ntiles_dev, max_tiles);
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(&bucket[cost_bucket(cnt[leaf[tile_start[t]]])], 1);
+        atomicAdd(&h[cost_bucket(cnt[leaf[tile_start[t]]])], 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kCostBuckets; i += blockDim.x)
+        if (h[i]) atomicAdd(&bucket[i], h[i]);
 }
 
 // single block: offsets from the counts, counts cleared for the next use
@@ -476,10 +483,23 @@ __global__ void k_tile_bucket_scan(int32_t *bucket) {
 __global__ void k_tile_bucket_scatter(int64_t max_tiles, const int32_t *__restrict__ ntiles_dev,
                                       const int32_t *__restrict__ tile_start, const int32_t *__restrict__ leaf,
                                       const int64_t *__restrict__ cnt, int32_t *bucket, int32_t *order) {
+    __shared__ int32_t h[kCostBuckets], base[kCostBuckets];
     const int64_t nt = min((int64_t)*ntiles_dev, max_tiles);
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x) {
-        const int q = atomicAdd(&bucket[kCostBuckets + cost_bucket(cnt[leaf[tile_start[t]]])], 1);
-        order[q] = (int32_t)t;
+    for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x; t0 < nt; t0 += (int64_t)gridDim.x * blockDim.x) {
+        for (int i = threadIdx.x; i < kCostBuckets; i += blockDim.x) h[i] = 0;
+        __syncthreads();
+        const int64_t t = t0 + threadIdx.x;
+        int bk = -1, r = 0;
+        if (t < nt) {
+            bk = cost_bucket(cnt[leaf[tile_start[t]]]);
+            r = atomicAdd(&h[bk], 1);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < kCostBuckets; i += blockDim.x)
+            base[i] = h[i] ? atomicAdd(&bucket[kCostBuckets + i], h[i]) : 0;
+        __syncthreads();
+        if (bk >= 0) order[base[bk] + r] = (int32_t)t;
+        __syncthreads();
     }
 }
 
