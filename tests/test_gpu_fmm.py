@@ -230,3 +230,17 @@ def test_fmm_batch_project_vs_oracle(batch):
         eh = np.max(np.abs(h[idx] - ho) / b["sigma"][sel].repeat(len(uv)))
         say("  e_h %.3e iters max %d" % (eh, it.max()))
         assert eh <= (1e-11 if prec == lss.FP64 else 2e-6)
+
+
+def test_fmm_mixed_eval_reproducible_and_counters(graded):
+    """The work queue hands tiles out in cost order, so workgroups meet the
+    tiles in a different order every run; the results must still be bitwise
+    identical between contexts, and the pair counters consistent."""
+    v, t, sig, x = graded
+    out = []
+    for _ in range(2):
+        cf = ctx(v, t, sig, lss.MIXED, lss.FAR_FMM)
+        out.append(cf.eval(x))
+        st = cf.stats()
+        assert 0 < st["last_pairs"] <= st["lane_pairs"] <= 64 * st["last_pairs"]
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
