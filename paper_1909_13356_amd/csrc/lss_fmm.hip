@@ -178,31 +178,42 @@ constexpr int kKB = 16;
 
 enum { G_LIST = 0, G_M2M = 1, G_L2L = 2 };
 
+// One launch of translations Y[dst] += scale * Op X[src] over a list of pairs.
+//   G_LIST: M2L pairs of one displacement class (dst = low 32 bits of mkey, src = mval).
+//   G_M2M:  pair j = the j-th parent of a level; its 8 children (consecutive boxes
+//           base + 8j ..) are one input column of 8 ncp coefficients and the 8 octant
+//           operators, stored one after the other in k-major order, are one
+//           ncp x 8 ncp operator, so each parent is written once per launch.
+//   G_L2L:  grid.z = octant o; pair j writes child base + 8j + o from its parent with
+//           operator o.  Children are distinct, so the 8 octants share the launch.
 struct GemmArgs {
-    int mode, ncp;
+    int mode, ncp, nk;          // nk: length of the contraction (ncp, or 8 ncp for G_M2M)
     int64_t npairs;
-    const double *opT;          // ncp x ncp, k-major
+    const double *opT;          // ncp rows, k-major (G_L2L: 8 such matrices)
     const double *X;
     double *Y;
-    const uint64_t *mkey;       // G_LIST: dst = low 32 bits
-    const int32_t *mval;        // G_LIST: src
+    const uint64_t *mkey;       // G_LIST
+    const int32_t *mval;        // G_LIST
     int64_t base;               // G_M2M / G_L2L: first child box of the level
-    int oct;
     const int32_t *parent, *lev;
     const double *root;
     const int32_t *bmesh;
 };
 
-__device__ inline void pair_of(const GemmArgs &a, int64_t j, int64_t &dst, int64_t &src, double &scale) {
+// destination box, first element of the input column and output scale of pair j
+__device__ inline void pair_of(const GemmArgs &a, int64_t j, int oct, int64_t &dst, int64_t &col, double &scale) {
+    scale = 1.0;
     if (a.mode == G_LIST) {
         dst = (int64_t)(uint32_t)(a.mkey[j] & 0xffffffffu);
-        src = a.mval[j];
+        col = (int64_t)a.mval[j] * a.ncp;
         scale = 1.0 / box_side(a.root, a.bmesh, (int32_t)dst, a.lev[dst]);   // 1 / side of the target box
+    } else if (a.mode == G_M2M) {
+        const int64_t ch = a.base + 8 * j;
+        dst = a.parent[ch];
+        col = ch * a.ncp;
     } else {
-        const int64_t ch = a.base + 8 * j + a.oct;
-        if (a.mode == G_M2M) { src = ch; dst = a.parent[ch]; }
-        else { dst = ch; src = a.parent[ch]; }
-        scale = 1.0;
+        dst = a.base + 8 * j + oct;
+        col = (int64_t)a.parent[dst] * a.ncp;
     }
 }
 
@@ -210,43 +221,48 @@ __device__ inline void pair_of(const GemmArgs &a, int64_t j, int64_t &dst, int64
 // the tile and eight 16x16 accumulator tiles (4 row groups x 2 pair groups).
 // The operator (k-major) and the gathered input columns go through LDS in
 // blocks of kKB coefficients; the next block is fetched into registers while
-// the MFMAs of the current one run.
+// the MFMAs of the current one run.  Asking for four waves per SIMD makes the
+// compiler keep the accumulators in ordinary VGPRs (126 in all, no AGPRs):
+// four workgroups share a CU instead of two, which hides the barrier and load
+// latency of one workgroup behind the MFMAs of the others.
 constexpr int kTR = 64, kTP = 128;
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_gemm(GemmArgs a) {
     __shared__ double As[kKB][kTR + 1];
     __shared__ double Bs[kKB][kTP + 1];
-    __shared__ int64_t ssrc[kTP];
+    __shared__ int64_t scol[kTP];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r0 = blockIdx.x * kTR;
     const int64_t j0 = (int64_t)blockIdx.y * kTP;
+    const int oct = blockIdx.z;
+    const double *__restrict__ op = a.opT + (int64_t)oct * a.ncp * a.ncp;
     if (threadIdx.x < kTP) {
-        int64_t j = j0 + threadIdx.x, d, s;
+        int64_t j = j0 + threadIdx.x, d, col;
         double sc;
-        if (j < a.npairs) { pair_of(a, j, d, s, sc); ssrc[threadIdx.x] = s; }
-        else ssrc[threadIdx.x] = -1;
+        if (j < a.npairs) { pair_of(a, j, oct, d, col, sc); scol[threadIdx.x] = col; }
+        else scol[threadIdx.x] = -1;
     }
     __syncthreads();
     // per thread: A elements (k, r) = (e / kTR, e % kTR) for e = tid + 256 i, i < 4;
     // B elements (k, c) with c = tid / 2, k = 8 (tid & 1) + i, i < 8 (two threads per column)
     constexpr int kNA = kKB * kTR / 256, kNB = kKB * kTP / 256;
     const int bc = threadIdx.x >> 1, bk = (threadIdx.x & 1) * kNB;
-    const int64_t bsrc = ssrc[bc];
+    const int64_t bcol = scol[bc];
     double ra[kNA], rb[kNB];
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < kNA; ++i) {
             const int e = threadIdx.x + 256 * i, kk = e / kTR, rr = e % kTR;
-            ra[i] = (r0 + rr < a.ncp) ? a.opT[(int64_t)(k0 + kk) * a.ncp + r0 + rr] : 0.0;
+            ra[i] = (r0 + rr < a.ncp) ? op[(int64_t)(k0 + kk) * a.ncp + r0 + rr] : 0.0;
         }
 #pragma unroll
-        for (int i = 0; i < kNB; ++i) rb[i] = bsrc >= 0 ? a.X[bsrc * a.ncp + k0 + bk + i] : 0.0;
+        for (int i = 0; i < kNB; ++i) rb[i] = bcol >= 0 ? a.X[bcol + k0 + bk + i] : 0.0;
     };
     d4 acc[4][2];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
         for (int t = 0; t < 2; ++t) acc[i][t] = d4{0.0, 0.0, 0.0, 0.0};
     fetch(0);
-    for (int k0 = 0; k0 < a.ncp; k0 += kKB) {
+    for (int k0 = 0; k0 < a.nk; k0 += kKB) {
         __syncthreads();                                   // previous block's MFMAs are done with LDS
 #pragma unroll
         for (int i = 0; i < kNA; ++i) {
@@ -256,7 +272,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
 #pragma unroll
         for (int i = 0; i < kNB; ++i) Bs[bk + i][bc] = rb[i];
         __syncthreads();
-        if (k0 + kKB < a.ncp) fetch(k0 + kKB);
+        if (k0 + kKB < a.nk) fetch(k0 + kKB);
 #pragma unroll
         for (int kk = 0; kk < kKB; kk += 4) {
             double bv[2];
@@ -274,9 +290,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
     for (int t = 0; t < 2; ++t) {
         const int64_t j = j0 + 32 * w + 16 * t + (lane & 15);
         if (j >= a.npairs) continue;
-        int64_t d, s;
+        int64_t d, col;
         double sc;
-        pair_of(a, j, d, s, sc);
+        pair_of(a, j, oct, d, col, sc);
         double *y = a.Y + d * a.ncp;
         // v_mfma_f64_16x16x4f64 accumulator: register q of lane l holds row (l/16) + 4q, column l%16
 #pragma unroll
@@ -297,7 +313,7 @@ void gemm(Ctx &c, GemmArgs a) {
         b.npairs = a.npairs - j0 < chunk ? a.npairs - j0 : chunk;
         if (a.mode == G_LIST) { b.mkey = a.mkey + j0; b.mval = a.mval + j0; }
         else b.base = a.base + 8 * j0;
-        dim3 grid((unsigned)ceil_div(b.ncp, kTR), (unsigned)ceil_div(b.npairs, kTP));
+        dim3 grid((unsigned)ceil_div(b.ncp, kTR), (unsigned)ceil_div(b.npairs, kTP), a.mode == G_L2L ? 8u : 1u);
         hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, c.stream, b);
         LSS_CHECK_LAUNCH("k_gemm");
     }
@@ -397,31 +413,25 @@ void build_fmm(Ctx &c) {
     // upward pass: M2M from level depth to 1 into their parents
     for (int lvl = t.depth; lvl >= 1; --lvl) {
         const int64_t base = t.level_begin[lvl], npar = (t.level_begin[lvl + 1] - base) / 8;
-        for (int o = 0; o < 8; ++o) {
-            GemmArgs a{G_M2M, ncp, npar, t.opM2M.as<double>() + o * per, t.M.as<double>(), t.M.as<double>(), nullptr,
-                       nullptr, base, o, t.parent.as<int32_t>(), t.level.as<int32_t>(), t.root.as<double>(),
-                       t.bmesh.as<int32_t>()};
-            gemm(c, a);
-        }
+        GemmArgs a{G_M2M, ncp, 8 * ncp, npar, t.opM2M.as<double>(), t.M.as<double>(), t.M.as<double>(), nullptr,
+                   nullptr, base, t.parent.as<int32_t>(), t.level.as<int32_t>(), t.root.as<double>(),
+                   t.bmesh.as<int32_t>()};
+        gemm(c, a);
     }
     // M2L, one launch per displacement class
     for (int cls : t.class_used) {
         const int64_t b0 = t.class_beg[cls], n = t.class_end[cls] - b0;
-        GemmArgs a{G_LIST, ncp, n, t.opM2L.as<double>() + (int64_t)t.op_class_slot[cls] * per, t.M.as<double>(),
-                   t.L.as<double>(), t.m2l_key2.as<uint64_t>() + b0, t.m2l_val2.as<int32_t>() + b0, 0, 0,
-                   t.parent.as<int32_t>(), t.level.as<int32_t>(), t.root.as<double>(),
-                       t.bmesh.as<int32_t>()};
+        GemmArgs a{G_LIST, ncp, ncp, n, t.opM2L.as<double>() + (int64_t)t.op_class_slot[cls] * per, t.M.as<double>(),
+                   t.L.as<double>(), t.m2l_key2.as<uint64_t>() + b0, t.m2l_val2.as<int32_t>() + b0, 0,
+                   t.parent.as<int32_t>(), t.level.as<int32_t>(), t.root.as<double>(), t.bmesh.as<int32_t>()};
         gemm(c, a);
     }
     // downward pass: L2L from level 0 to depth-1 into their children
     for (int lvl = 1; lvl <= t.depth; ++lvl) {
         const int64_t base = t.level_begin[lvl], npar = (t.level_begin[lvl + 1] - base) / 8;
-        for (int o = 0; o < 8; ++o) {
-            GemmArgs a{G_L2L, ncp, npar, t.opL2L.as<double>() + o * per, t.L.as<double>(), t.L.as<double>(), nullptr,
-                       nullptr, base, o, t.parent.as<int32_t>(), t.level.as<int32_t>(), t.root.as<double>(),
-                       t.bmesh.as<int32_t>()};
-            gemm(c, a);
-        }
+        GemmArgs a{G_L2L, ncp, ncp, npar, t.opL2L.as<double>(), t.L.as<double>(), t.L.as<double>(), nullptr, nullptr,
+                   base, t.parent.as<int32_t>(), t.level.as<int32_t>(), t.root.as<double>(), t.bmesh.as<int32_t>()};
+        gemm(c, a);
     }
     c.stats.fmm_order = p;
 }
