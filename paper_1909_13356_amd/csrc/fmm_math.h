@@ -219,5 +219,60 @@ LSS_HD void l2p(const double *L, double rx, double ry, double rz, double inv_s, 
     g[2] = gz * inv_s;
 }
 
+// M2P: Phi and grad Phi of a multipole expansion M~ (real layout) of a box of
+// side s, centre c, at the scaled position (rx,ry,rz) = (x - c)/s, outside the
+// sphere around the box.  It is the degree-0 and degree-1 part of the M2L of M~
+// to a box of side s centred at x (see M2L above), so
+//   Phi            = (1/s)   sum_{n,m} T_n^m(r) M~_n^m
+//   dPhi/dz        = -(1/s^2) sum_{n,m} T_{n+1}^m(r) M~_n^m
+//   (dx + i dy)Phi = -(1/s^2) conj(A),  A = sum_{n,m} T_{n+1}^{m-1}(r) M~_n^m.
+// The m < 0 halves fold as in l2p: T_{n+1}^{-m} M_n^{-m} = conj(T_{n+1}^m M_n^m),
+// and in A the terms of M_n^{m'} with m' <= 0 are -conj(T_{n+1}^{|m'|+1} M_n^{|m'|}).
+// T_j^m is generated column by column (m = 0..p+1, j = m..p+1) and consumed at
+// once, as T_j^m M_j^m, T_j^m M_{j-1}^m, T_j^m M_{j-1}^{m+1} and -conj(T_j^m M_{j-1}^{m-1}).
+LSS_HD void m2p(const double *M, double rx, double ry, double rz, double inv_s, int p, double &phi, double g[3]) {
+    const double r2 = rx * rx + ry * ry + rz * rz, ir2 = 1.0 / r2;
+    double s0 = 0.0, s1 = 0.0, Are = 0.0, Aim = 0.0;
+    cd diag = {sqrt(ir2), 0.0};
+    for (int m = 0; m <= p + 1; ++m) {
+        if (m > 0) diag = cscale(cmul(diag, cd{rx, ry}), -(2.0 * m - 1.0) * ir2);
+        const double w = m == 0 ? 1.0 : 2.0;
+        cd tm2 = {0.0, 0.0}, t = diag;
+        for (int j = m; j <= p + 1; ++j) {
+            if (j > m) {
+                const double a = (2 * j - 1) * rz, b = (double)(j - 1 + m) * (double)(j - 1 - m);
+                cd tn = {(a * t.re - b * tm2.re) * ir2, (a * t.im - b * tm2.im) * ir2};
+                tm2 = t;
+                t = tn;
+            }
+            if (j <= p) {                              // T_j^m M_j^m
+                const double mre = M[ire(j, m)], mim = m ? M[iim(j, m)] : 0.0;
+                s0 += w * (t.re * mre - t.im * mim);
+            }
+            if (j == 0) continue;
+            const int n = j - 1;
+            if (m <= n) {                              // T_{n+1}^m M_n^m
+                const double mre = M[ire(n, m)], mim = m ? M[iim(n, m)] : 0.0;
+                s1 += w * (t.re * mre - t.im * mim);
+            }
+            if (m + 1 <= n) {                          // T_{n+1}^m M_n^{m+1}
+                const double mre = M[ire(n, m + 1)], mim = M[iim(n, m + 1)];
+                Are += t.re * mre - t.im * mim;
+                Aim += t.re * mim + t.im * mre;
+            }
+            if (m >= 1) {                              // -conj(T_{n+1}^m M_n^{m-1})
+                const double mre = M[ire(n, m - 1)], mim = (m - 1) ? M[iim(n, m - 1)] : 0.0;
+                Are -= t.re * mre - t.im * mim;
+                Aim += t.re * mim + t.im * mre;
+            }
+        }
+    }
+    const double is2 = inv_s * inv_s;
+    phi = s0 * inv_s;
+    g[0] = -Are * is2;
+    g[1] = Aim * is2;
+    g[2] = -s1 * is2;
+}
+
 }  // namespace fmm
 }  // namespace lss

@@ -349,7 +349,7 @@ void build_ops(Ctx &c, int kind, int nops, const std::vector<double> &vecs, int 
 void build_fmm(Ctx &c) {
     build_tree(c);
     Tree &t = c.tree;
-    const int p = c.opt.fmm_order > 0 ? c.opt.fmm_order : (c.opt.precision == LSS_MIXED ? 20 : 26);
+    const int p = fmm_order_for(c);
     const int ncp = (int)ceil_div(fmm::ncoef(p), kKB) * kKB;
     const int64_t per = (int64_t)ncp * ncp;
     // operators: M2M / L2L for the 8 octants, M2L for the classes in use

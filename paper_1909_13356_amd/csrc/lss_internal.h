@@ -160,7 +160,10 @@ struct Tree {
     DBuf p2p_key, p2p_key2, p2p_val, p2p_val2;    // u64 (T<<32|S), int32
     int64_t n_p2p = 0;
     DBuf p2p_beg, p2p_end;                    // per box, int32 offsets into the sorted p2p list
-    DBuf near_cnt;                            // per box + per mesh (outside targets): direct-list node count
+    DBuf m2p_key, m2p_key2, m2p_val, m2p_val2;    // u64 (T<<32|S), int32 S: multipole of S at T's targets
+    int64_t n_m2p = 0;
+    DBuf m2p_beg, m2p_end;                    // per box, int32 offsets into the sorted m2p list
+    DBuf near_cnt;                            // per box + per mesh (outside targets): cost of a target in node pairs
     DBuf m2l_key, m2l_key2, m2l_val, m2l_val2;    // u64 (class<<32|T), int32 S
     int64_t n_m2l = 0;
     std::vector<int64_t> class_beg, class_end;    // host: segments of the sorted m2l list per class
@@ -263,6 +266,10 @@ void launch_iter_mark(Ctx &c);
 void launch_newton_output(Ctx &c, int64_t N, double *h, double *xout, int8_t *status, int8_t *iters);
 
 // octree, lists, FMM (lss_tree.hip, lss_fmm.hip)
+// expansion order of the far field: the caller's, else 20 (mixed) or 26 (FP64)
+inline int fmm_order_for(const Ctx &c) {
+    return c.opt.fmm_order > 0 ? c.opt.fmm_order : (c.opt.precision == LSS_MIXED ? 20 : 26);
+}
 void build_tree(Ctx &c);
 void build_fmm(Ctx &c);
 void launch_locate_targets(Ctx &c, int64_t n_max, const int32_t *n_dev, const double *tx, const double *ty,

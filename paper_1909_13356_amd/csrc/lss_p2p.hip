@@ -424,6 +424,8 @@ struct FmmEvalArgs {
     int64_t nnodes;
     int32_t nboxes;
     const double *L;
+    const double *M;            // multipole expansions (for the M2P lists)
+    const int32_t *m2p_beg, *m2p_end, *m2p_src;
     int p, ncp;
     const double *root;         // per-mesh root cubes (corner xyz, side)
     const int32_t *bmesh;
@@ -522,6 +524,36 @@ __device__ __forceinline__ void fmm_l2p(const FmmEvalArgs &a, int32_t B, const d
     fmm::l2p(Ls, (x - cx) * inv, (y - cy) * inv, (z - cz) * inv, inv, a.p, ph, g);
 }
 
+// M2P list of leaf B at this lane's target: the multipole expansion of each
+// listed box is staged in buf (ncp doubles) by the whole workgroup and
+// evaluated at (x, y, z) (section 4.4: the far kernel is the Laplace double
+// layer, so a box whose nodes are all beyond the cut of every target of B
+// contributes through its expansion).  Uniform over the workgroup; buf is free
+// again when it returns.
+__device__ __forceinline__ void fmm_m2p_list(const FmmEvalArgs &a, int32_t B, double *buf, double x, double y,
+                                             double z, double &ph, double g[3]) {
+    const int e0 = a.m2p_beg[B], e1 = a.m2p_end[B];
+    for (int e = e0; e < e1; ++e) {
+        const int32_t S = a.m2p_src[e];
+        __syncthreads();
+        const double *src = a.M + (int64_t)S * a.ncp;
+        for (int k = threadIdx.x; k < a.ncp; k += blockDim.x) buf[k] = src[k];
+        __syncthreads();
+        const double s = box_side(a.root, a.bmesh, S, a.lev[S]);
+        const double *o = a.root + 4 * a.bmesh[S];
+        const double cx = o[0] + (a.ijk[3 * S] + 0.5) * s, cy = o[1] + (a.ijk[3 * S + 1] + 0.5) * s,
+                     cz = o[2] + (a.ijk[3 * S + 2] + 0.5) * s;
+        const double inv = 1.0 / s;
+        double p1, g1[3];
+        fmm::m2p(buf, (x - cx) * inv, (y - cy) * inv, (z - cz) * inv, inv, a.p, p1, g1);
+        ph += p1;
+        g[0] += g1[0];
+        g[1] += g1[1];
+        g[2] += g1[2];
+    }
+    __syncthreads();
+}
+
 template <int TILE>
 __global__ __launch_bounds__(TILE) void k_eval_fmm_f64(FmmEvalArgs a) {
     __shared__ Src sh[TILE];
@@ -571,9 +603,17 @@ __global__ __launch_bounds__(TILE) void k_eval_fmm_f64(FmmEvalArgs a) {
                 two_sum(sz, ez, gz);
             }
         }
-        double ph = 0.0, g[3] = {0.0, 0.0, 0.0};
+        double ph = 0.0, g[3] = {0.0, 0.0, 0.0}, mph = 0.0, mg[3] = {0.0, 0.0, 0.0};
+        if (!outside && a.m2p_end[B] > a.m2p_beg[B]) {  // uniform: Ls is the M2P staging buffer, then L again
+            fmm_m2p_list(a, B, Ls, x, y, z, mph, mg);
+            stage_local(a, B, Ls);
+        }
         __syncthreads();                    // Ls staged
         if (!outside) fmm_l2p(a, B, Ls, x, y, z, ph, g);
+        ph += mph;
+        g[0] += mg[0];
+        g[1] += mg[1];
+        g[2] += mg[2];
         if (valid) {
             const int64_t o = a.out_idx ? (int64_t)a.out_idx[ti] : ti;
             a.phi[o] = (sp + ph) + ep;
@@ -666,9 +706,17 @@ __global__ __launch_bounds__(64) void k_eval_fmm_mixed(FmmEvalArgs a) {
                 }
             }
         }
-        double ph = 0.0, g[3] = {0.0, 0.0, 0.0};
+        double ph = 0.0, g[3] = {0.0, 0.0, 0.0}, mph = 0.0, mg[3] = {0.0, 0.0, 0.0};
+        if (!outside && a.m2p_end[B] > a.m2p_beg[B]) {  // uniform: Ls is the M2P staging buffer, then L again
+            fmm_m2p_list(a, B, Ls, X, Y, Z, mph, mg);
+            stage_local(a, B, Ls);
+        }
         __syncthreads();                    // Ls staged
         if (!outside) fmm_l2p(a, B, Ls, X, Y, Z, ph, g);
+        ph += mph;
+        g[0] += mg[0];
+        g[1] += mg[1];
+        g[2] += mg[2];
         if (valid) {
             const int64_t o = a.out_idx ? (int64_t)a.out_idx[ti] : ti;
             a.phi[o] = ((double)sp + (double)ep) + ph;
@@ -744,6 +792,10 @@ void launch_eval_fmm(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const
     a.nnodes = c.nnodes;
     a.nboxes = (int32_t)t.nboxes;
     a.L = t.L.as<double>();
+    a.M = t.M.as<double>();
+    a.m2p_beg = t.m2p_beg.as<int32_t>();
+    a.m2p_end = t.m2p_end.as<int32_t>();
+    a.m2p_src = t.m2p_val2.as<int32_t>();
     a.p = t.p;
     a.ncp = t.ncp;
     a.root = t.root.as<double>();

@@ -14,10 +14,15 @@
 // Lists: one dual-tree traversal over (target box T, source box S) pairs:
 //   same level and admissible (|d|_inf >= 2, |d|^2 >= K, d = integer offset
 //   of the boxes, and box gap >= R_max(S))  -> M2L(S -> T)
-//   otherwise: T leaf -> direct pairs with all nodes of S;  else split the
-//   non-leaf box(es) and continue.
-// Every (target leaf, node) pair is covered exactly once, by a direct pair or
-// by one M2L at some level.
+//   otherwise: T leaf -> direct pairs with all nodes of S, unless S is not a
+//   leaf and holds more than kDirectMax nodes: then S is split against the
+//   leaf T; a deeper S whose centre is at least sqrt(K) of its sides away from
+//   T's box and whose gap to it is at least R_max(S) is evaluated at T's
+//   targets from its multipole expansion (M2P);  else split the non-leaf
+//   box(es) and continue.
+// Every (target leaf, node) pair is covered exactly once, by a direct pair, by
+// one M2L at some level, or by one M2P.  Without the M2P descent a coarse leaf
+// (an empty box next to the surface, say) would sum millions of nodes directly.
 #include <cstring>
 #include <hip/hip_runtime.h>
 
@@ -240,7 +245,36 @@ struct DttArgs {
 __device__ inline bool is_empty(const DttArgs &a, int32_t S) { return a.ne[S] == a.nb[S]; }
 
 // action codes
-enum { A_DROP = 0, A_M2L = 1, A_P2P = 2, A_SPLIT_BOTH = 3, A_SPLIT_T = 4 };
+enum { A_DROP = 0, A_M2L = 1, A_P2P = 2, A_SPLIT_BOTH = 3, A_SPLIT_T = 4, A_SPLIT_S = 5, A_M2P = 6 };
+
+// a non-leaf source box with more nodes than this is split against a leaf target
+constexpr int64_t kDirectMax = 2048;
+
+__device__ inline void box_bounds(const DttArgs &a, int32_t b, double lo[3], double &side) {
+    side = box_side(a.root, a.bmesh, b, a.lev[b]);
+    const double *o = a.root + 4 * a.bmesh[b];
+    for (int d = 0; d < 3; ++d) lo[d] = o[d] + a.ijk[3 * b + d] * side;
+}
+
+// M2P of the (smaller) box S at the targets of box T: S's centre at least
+// sqrt(K) sides of S from T's box, and a gap of at least the cut radius of
+// S's nodes between the boxes
+__device__ inline bool m2p_ok(const DttArgs &a, int32_t T, int32_t S) {
+    double lt[3], ls[3], ht, hs;
+    box_bounds(a, T, lt, ht);
+    box_bounds(a, S, ls, hs);
+    double dc = 0.0, gap = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        const double c = ls[d] + 0.5 * hs;
+        const double e = fmax(fmax(lt[d] - c, c - (lt[d] + ht)), 0.0);     // centre of S to T's box
+        const double g = fmax(fmax(lt[d] - (ls[d] + hs), ls[d] - (lt[d] + ht)), 0.0);   // box to box
+        dc += e * e;
+        gap += g * g;
+    }
+    return dc >= (double)a.K * hs * hs && gap >= a.rmax[S] * a.rmax[S];
+}
+
+__device__ inline int64_t box_nodes(const DttArgs &a, int32_t b) { return a.ne[b] - a.nb[b]; }
 
 __device__ inline int dtt_action(const DttArgs &a, int32_t T, int32_t S, int &cls) {
     if (is_empty(a, S)) return A_DROP;
@@ -256,13 +290,22 @@ __device__ inline int dtt_action(const DttArgs &a, int32_t T, int32_t S, int &cl
             cls = ((dx + kR) * (2 * kR + 1) + (dy + kR)) * (2 * kR + 1) + (dz + kR);
             return A_M2L;
         }
-        if (leafT) return A_P2P;
+        if (leafT) return (leafS || box_nodes(a, S) <= kDirectMax) ? A_P2P : A_SPLIT_S;
         if (leafS) return A_SPLIT_T;
         return A_SPLIT_BOTH;
     }
-    // T deeper than S (S is a leaf by construction), or the reverse
-    if (leafT) return A_P2P;
-    return A_SPLIT_T;
+    if (lT > lS) return leafT ? A_P2P : A_SPLIT_T;     // T deeper than S (S is a leaf by construction)
+    // S deeper than the leaf T (reached by A_SPLIT_S only)
+    if (m2p_ok(a, T, S)) return A_M2P;
+    return (leafS || box_nodes(a, S) <= kDirectMax) ? A_P2P : A_SPLIT_S;
+}
+
+__device__ inline int nonempty_children(const DttArgs &a, int32_t S, int32_t sl[8]) {
+    const int32_t s0 = a.child[S];
+    int ns = 0;
+    for (int v = 0; v < 8; ++v)
+        if (a.ne[s0 + v] > a.nb[s0 + v]) sl[ns++] = s0 + v;
+    return ns;
 }
 
 __global__ void k_dtt_count(int64_t n, const uint64_t *__restrict__ fr, DttArgs a, unsigned long long *cnt) {
@@ -273,18 +316,19 @@ __global__ void k_dtt_count(int64_t n, const uint64_t *__restrict__ fr, DttArgs 
     int act = dtt_action(a, T, S, cls);
     if (act == A_M2L) atomicAdd(&cnt[1], 1ull);
     else if (act == A_P2P) atomicAdd(&cnt[2], 1ull);
-    else if (act == A_SPLIT_BOTH) {
+    else if (act == A_M2P) atomicAdd(&cnt[6], 1ull);
+    else if (act == A_SPLIT_BOTH || act == A_SPLIT_S) {
         // only source children that hold nodes are paired
-        const int32_t s0 = a.child[S];
-        unsigned long long ns = 0;
-        for (int v = 0; v < 8; ++v) ns += a.ne[s0 + v] > a.nb[s0 + v] ? 1ull : 0ull;
-        atomicAdd(&cnt[0], 8ull * ns);
+        int32_t sl[8];
+        const unsigned long long ns = (unsigned long long)nonempty_children(a, S, sl);
+        atomicAdd(&cnt[0], act == A_SPLIT_BOTH ? 8ull * ns : ns);
     } else if (act == A_SPLIT_T) atomicAdd(&cnt[0], 8ull);
 }
 
 __global__ void k_dtt_emit(int64_t n, const uint64_t *__restrict__ fr, DttArgs a, unsigned long long *cnt,
                            uint64_t *next, uint64_t *m2l_key, int32_t *m2l_val, int64_t m2l_base,
-                           uint64_t *p2p_key, int32_t *p2p_val, int64_t p2p_base) {
+                           uint64_t *p2p_key, int32_t *p2p_val, int64_t p2p_base, uint64_t *m2p_key,
+                           int32_t *m2p_val, int64_t m2p_base) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int32_t T = (int32_t)(fr[i] >> 32), S = (int32_t)(fr[i] & 0xffffffffu);
@@ -298,15 +342,22 @@ __global__ void k_dtt_emit(int64_t n, const uint64_t *__restrict__ fr, DttArgs a
         int64_t q = p2p_base + (int64_t)atomicAdd(&cnt[5], 1ull);
         p2p_key[q] = ((uint64_t)(uint32_t)T << 32) | (uint32_t)S;
         p2p_val[q] = S;
+    } else if (act == A_M2P) {
+        int64_t q = m2p_base + (int64_t)atomicAdd(&cnt[7], 1ull);
+        m2p_key[q] = ((uint64_t)(uint32_t)T << 32) | (uint32_t)S;
+        m2p_val[q] = S;
     } else if (act == A_SPLIT_BOTH) {
-        const int32_t t0 = a.child[T], s0 = a.child[S];
+        const int32_t t0 = a.child[T];
         int32_t sl[8];
-        int ns = 0;
-        for (int v = 0; v < 8; ++v)
-            if (a.ne[s0 + v] > a.nb[s0 + v]) sl[ns++] = s0 + v;
+        const int ns = nonempty_children(a, S, sl);
         int64_t q = (int64_t)atomicAdd(&cnt[3], 8ull * (unsigned long long)ns);
         for (int u = 0; u < 8; ++u)
             for (int v = 0; v < ns; ++v) next[q + ns * u + v] = ((uint64_t)(uint32_t)(t0 + u) << 32) | (uint32_t)sl[v];
+    } else if (act == A_SPLIT_S) {
+        int32_t sl[8];
+        const int ns = nonempty_children(a, S, sl);
+        int64_t q = (int64_t)atomicAdd(&cnt[3], (unsigned long long)ns);
+        for (int v = 0; v < ns; ++v) next[q + v] = ((uint64_t)(uint32_t)T << 32) | (uint32_t)sl[v];
     } else if (act == A_SPLIT_T) {
         int64_t q = (int64_t)atomicAdd(&cnt[3], 8ull);
         int32_t t0 = a.child[T];
@@ -432,15 +483,17 @@ __global__ void k_tile_flags_runs(int64_t n_max, const int32_t *__restrict__ n_d
     flag[i] = (i < n && (i == 0 || leaf[i] != leaf[i - 1] || (i % tile) == 0)) ? 1 : 0;
 }
 
-// nodes on the direct list of every box, and of every mesh's outside range
+// cost of a target of every box, in node pairs: the nodes on its direct list
+// plus m2p_weight per M2P box; and of every mesh's outside range
 __global__ void k_near_count(int64_t nboxes, int32_t nmesh, const int32_t *__restrict__ beg,
                              const int32_t *__restrict__ end, const int32_t *__restrict__ src,
+                             const int32_t *__restrict__ mbeg, const int32_t *__restrict__ mend, int64_t m2p_weight,
                              const int64_t *__restrict__ nb, const int64_t *__restrict__ ne, int64_t *cnt) {
     int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b < nboxes) {
         int64_t s = 0;
         for (int32_t e = beg[b]; e < end[b]; ++e) s += ne[src[e]] - nb[src[e]];
-        cnt[b] = s;
+        cnt[b] = s + m2p_weight * (int64_t)(mend[b] - mbeg[b]);
     } else if (b < nboxes + nmesh) {
         const int64_t m = b - nboxes;
         cnt[b] = ne[m] - nb[m];
@@ -701,16 +754,23 @@ void build_tree(Ctx &c) {
     int64_t nfr = nm;                       // (root m, root m) pairs written by k_level0
     t.n_m2l = 0;
     t.n_p2p = 0;
-    int64_t cap_m2l = 0, cap_p2p = 0;
+    t.n_m2p = 0;
+    int64_t cap_m2l = 0, cap_p2p = 0, cap_m2p = 0;
     while (nfr > 0) {
         LSS_HIP(hipMemsetAsync(t.cnt.p, 0, 8 * 8, c.stream));
         hipLaunchKernelGGL(k_dtt_count, dim3(grid_for(nfr)), dim3(kBlk), 0, c.stream, nfr, t.fr.as<uint64_t>(), a,
                            t.cnt.as<unsigned long long>());
         LSS_CHECK_LAUNCH("k_dtt_count");
-        unsigned long long h[3];
-        LSS_HIP(hipMemcpyAsync(h, t.cnt.p, 24, hipMemcpyDeviceToHost, c.stream));
+        unsigned long long h[8];
+        LSS_HIP(hipMemcpyAsync(h, t.cnt.p, 64, hipMemcpyDeviceToHost, c.stream));
         LSS_HIP(hipStreamSynchronize(c.stream));
-        const int64_t npush = (int64_t)h[0], nm = (int64_t)h[1], np2 = (int64_t)h[2];
+        const int64_t npush = (int64_t)h[0], nm = (int64_t)h[1], np2 = (int64_t)h[2], nmp = (int64_t)h[6];
+        if (t.n_m2p + nmp > cap_m2p) {
+            int64_t nc = (t.n_m2p + nmp) * 2 + 1024;
+            t.m2p_key.grow_copy(8 * nc, 8 * t.n_m2p, c.stream);
+            t.m2p_val.grow_copy(4 * nc, 4 * t.n_m2p, c.stream);
+            cap_m2p = nc;
+        }
         if (t.n_m2l + nm > cap_m2l) {
             int64_t nc = (t.n_m2l + nm) * 2 + 1024;
             t.m2l_key.grow_copy(8 * nc, 8 * t.n_m2l, c.stream);
@@ -726,10 +786,12 @@ void build_tree(Ctx &c) {
         t.fr2.ensure(8 * (npush > 0 ? npush : 1));
         hipLaunchKernelGGL(k_dtt_emit, dim3(grid_for(nfr)), dim3(kBlk), 0, c.stream, nfr, t.fr.as<uint64_t>(), a,
                            t.cnt.as<unsigned long long>(), t.fr2.as<uint64_t>(), t.m2l_key.as<uint64_t>(),
-                           t.m2l_val.as<int32_t>(), t.n_m2l, t.p2p_key.as<uint64_t>(), t.p2p_val.as<int32_t>(), t.n_p2p);
+                           t.m2l_val.as<int32_t>(), t.n_m2l, t.p2p_key.as<uint64_t>(), t.p2p_val.as<int32_t>(), t.n_p2p,
+                           t.m2p_key.as<uint64_t>(), t.m2p_val.as<int32_t>(), t.n_m2p);
         LSS_CHECK_LAUNCH("k_dtt_emit");
         t.n_m2l += nm;
         t.n_p2p += np2;
+        t.n_m2p += nmp;
         std::swap(t.fr.p, t.fr2.p);
         std::swap(t.fr.bytes, t.fr2.bytes);
         nfr = npush;
@@ -744,10 +806,22 @@ void build_tree(Ctx &c) {
     if (t.n_p2p > 0)
         hipLaunchKernelGGL(k_p2p_ranges, dim3(grid_for(t.n_p2p)), dim3(kBlk), 0, c.stream, t.n_p2p,
                            t.p2p_key2.as<uint64_t>(), t.p2p_beg.as<int32_t>(), t.p2p_end.as<int32_t>());
+    t.m2p_key2.ensure(8 * (t.n_m2p + 1)); t.m2p_val2.ensure(4 * (t.n_m2p + 1));
+    sort_pairs(c, t.m2p_key.as<uint64_t>(), t.m2p_key2.as<uint64_t>(), t.m2p_val.as<int32_t>(),
+               t.m2p_val2.as<int32_t>(), t.n_m2p);
+    t.m2p_beg.ensure(4 * (t.nboxes + 1)); t.m2p_end.ensure(4 * (t.nboxes + 1));
+    LSS_HIP(hipMemsetAsync(t.m2p_beg.p, 0, 4 * (t.nboxes + 1), c.stream));
+    LSS_HIP(hipMemsetAsync(t.m2p_end.p, 0, 4 * (t.nboxes + 1), c.stream));
+    if (t.n_m2p > 0)
+        hipLaunchKernelGGL(k_p2p_ranges, dim3(grid_for(t.n_m2p)), dim3(kBlk), 0, c.stream, t.n_m2p,
+                           t.m2p_key2.as<uint64_t>(), t.m2p_beg.as<int32_t>(), t.m2p_end.as<int32_t>());
+    // an M2P costs about as much as (p + 2)^2 / 4 direct pairs
+    const int p_est = fmm_order_for(c);
     t.near_cnt.ensure(8 * (t.nboxes + nm));
     hipLaunchKernelGGL(k_near_count, dim3(grid_for(t.nboxes + nm)), dim3(kBlk), 0, c.stream, t.nboxes, nm,
-                       t.p2p_beg.as<int32_t>(), t.p2p_end.as<int32_t>(), t.p2p_val2.as<int32_t>(), t.nb.as<int64_t>(),
-                       t.ne.as<int64_t>(), t.near_cnt.as<int64_t>());
+                       t.p2p_beg.as<int32_t>(), t.p2p_end.as<int32_t>(), t.p2p_val2.as<int32_t>(),
+                       t.m2p_beg.as<int32_t>(), t.m2p_end.as<int32_t>(), (int64_t)(p_est + 2) * (p_est + 2) / 4,
+                       t.nb.as<int64_t>(), t.ne.as<int64_t>(), t.near_cnt.as<int64_t>());
     LSS_CHECK_LAUNCH("k_near_count");
     t.m2l_key2.ensure(8 * (t.n_m2l + 1)); t.m2l_val2.ensure(4 * (t.n_m2l + 1));
     sort_pairs(c, t.m2l_key.as<uint64_t>(), t.m2l_key2.as<uint64_t>(), t.m2l_val.as<int32_t>(),
