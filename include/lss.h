@@ -143,6 +143,8 @@ typedef struct lss_stats {
     int32_t pad0;
     double  lane_pairs;       /* pair evaluations the pair kernels spent, idle lanes of partly
                                  filled tiles included (last_pairs / lane_pairs = lane use) */
+    int64_t n_m2p;            /* (leaf, box) pairs of the last build whose far field reaches the
+                                 leaf's targets straight from the box's multipole expansion */
 } lss_stats;
 
 /* Create a context on HIP device `hip_device`, queuing work on `hip_stream`

@@ -96,7 +96,7 @@ void build(Ctx &c) {
     LSS_HIP(hipMemsetAsync(c.tile_queue.p, 0, sizeof(unsigned int) * 4, c.stream));
     c.tile_bucket.ensure(sizeof(int32_t) * 2 * kCostBuckets);
     LSS_HIP(hipMemsetAsync(c.tile_bucket.p, 0, sizeof(int32_t) * 2 * kCostBuckets, c.stream));
-    c.stats.n_boxes = c.stats.n_leaves = c.stats.n_m2l = 0;
+    c.stats.n_boxes = c.stats.n_leaves = c.stats.n_m2l = c.stats.n_m2p = 0;
     c.stats.tree_depth = c.stats.fmm_order = 0;
     if (c.opt.far_field == LSS_FAR_FMM) build_fmm(c);
     c.built = true;

@@ -846,6 +846,7 @@ void build_tree(Ctx &c) {
     c.stats.n_leaves = 0;
     c.stats.tree_depth = t.depth;
     c.stats.n_m2l = t.n_m2l;
+    c.stats.n_m2p = t.n_m2p;
 }
 
 void launch_soa(Ctx &c, const double *x, int64_t n, double *tx, double *ty, double *tz) {

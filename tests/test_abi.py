@@ -33,7 +33,7 @@ def test_struct_layouts():
     from paper_1909_13356_amd._binding import Options, Stats
     # lss_options: 4 int32, 2 double, 2 int32, 1 double, 6 int32 reserved
     assert ctypes.sizeof(Options) == 4 * 4 + 2 * 8 + 2 * 4 + 8 + 6 * 4
-    assert ctypes.sizeof(Stats) == 8 * 2 + 4 * 2 + 8 * 3 + 4 * 2 + 8 + 8 + 8 + 8 + 4 + 4 + 8
+    assert ctypes.sizeof(Stats) == 8 * 2 + 4 * 2 + 8 * 3 + 4 * 2 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8
 
 
 def test_missing_library_fails_loudly(monkeypatch):

@@ -1,0 +1,83 @@
+"""Host-side check of the M2P evaluation of the far-field code (the
+header is host+device): the multipole series of point charges in a box,
+evaluated at points outside it, against the direct sum."""
+
+import os
+import subprocess
+import textwrap
+
+import pytest
+
+CSRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1909_13356_amd", "csrc")
+
+PROG = textwrap.dedent(r"""
+    #include <cmath>
+    #include <cstdio>
+    #include <cstdlib>
+    #include <vector>
+    #include "fmm_math.h"
+    using namespace lss::fmm;
+    // point charges q_k at y_k inside a box of side s (centre c): M~_n^m = sum q conj(U_n^m(y/s));
+    // the M2P series at |x - c| >= rmin s against sum q / |x - y| and its gradient
+    int main(int argc, char **argv) {
+        const int p = atoi(argv[1]);
+        const double rmin = atof(argv[2]);
+        srand(7);
+        auto rnd = [] { return rand() / (double)RAND_MAX - 0.5; };
+        double worst = 0.0;
+        for (int trial = 0; trial < 300; ++trial) {
+            const double s = 0.37, c[3] = {0.1, -0.2, 0.3};
+            std::vector<double> M(ncoef(p), 0.0);
+            std::vector<cd> U(tri(p, p) + 1);
+            double y[6][3], q[6], aq = 0.0;
+            for (int k = 0; k < 6; ++k) {
+                for (int d = 0; d < 3; ++d) y[k][d] = rnd() * s;
+                q[k] = rnd();
+                aq += fabs(q[k]);
+                regular_table(y[k][0] / s, y[k][1] / s, y[k][2] / s, p, U.data());
+                for (int n = 0; n <= p; ++n)
+                    for (int m = 0; m <= n; ++m) {
+                        M[ire(n, m)] += q[k] * U[tri(n, m)].re;
+                        if (m) M[iim(n, m)] -= q[k] * U[tri(n, m)].im;
+                    }
+            }
+            double dir[3] = {rnd(), rnd(), rnd()};
+            const double nd = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+            const double R = s * (rmin + 0.2 * (rnd() + 0.5));
+            double x[3], ph, g[3], eph = 0.0, eg[3] = {0.0, 0.0, 0.0};
+            for (int d = 0; d < 3; ++d) x[d] = c[d] + R * dir[d] / nd;
+            m2p(M.data(), (x[0] - c[0]) / s, (x[1] - c[1]) / s, (x[2] - c[2]) / s, 1.0 / s, p, ph, g);
+            for (int k = 0; k < 6; ++k) {
+                const double d0 = x[0] - c[0] - y[k][0], d1 = x[1] - c[1] - y[k][1], d2 = x[2] - c[2] - y[k][2];
+                const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2), r3 = r * r * r;
+                eph += q[k] / r;
+                eg[0] -= q[k] * d0 / r3; eg[1] -= q[k] * d1 / r3; eg[2] -= q[k] * d2 / r3;
+            }
+            worst = fmax(worst, fabs(ph - eph) / (aq / R));
+            for (int d = 0; d < 3; ++d) worst = fmax(worst, fabs(g[d] - eg[d]) / (aq / (R * R)));
+        }
+        printf("%.6e\n", worst);
+        return 0;
+    }
+""")
+
+
+@pytest.fixture(scope="module")
+def m2p_prog(tmp_path_factory):
+    d = tmp_path_factory.mktemp("m2p")
+    src = d / "m2p.cpp"
+    src.write_text(PROG)
+    exe = d / "m2p"
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-I", CSRC, str(src), "-o", str(exe)])
+    return str(exe)
+
+
+# (order, smallest distance in box sides, bound): the orders and separations of
+# the two precisions' M2P lists (K = 4 mixed at p = 20, K = 8 FP64 at p = 26)
+# and a low order that shows the series converging
+@pytest.mark.parametrize("p,rmin,bound", [(20, 2.0, 1e-7), (26, 2.83, 1e-13), (8, 2.0, 1e-2)])
+def test_m2p_series_matches_direct_sum(m2p_prog, p, rmin, bound):
+    err = float(subprocess.check_output([m2p_prog, str(p), str(rmin)]).decode())
+    assert err <= bound
+    if p == 8:
+        assert err > 1e-6                     # truncation visible: the high orders do matter

@@ -244,3 +244,38 @@ def test_fmm_mixed_eval_reproducible_and_counters(graded):
         st = cf.stats()
         assert 0 < st["last_pairs"] <= st["lane_pairs"] <= 64 * st["last_pairs"]
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.fixture(scope="module")
+def volume():
+    """Graded bumpy sphere with targets filling a cube around it: many sit in
+    coarse empty leaves inside and outside the surface, whose direct lists
+    would take whole subtrees without the M2P descent."""
+    v, t = bumpy_sphere(30, grade=4.0, lmax=10, nbumps=40, seed=11)
+    sig = 0.5 * triangle_diameters(v, t)
+    x = box_targets(30000, -1.3, 1.3, seed=12)
+    return v, t, sig, x
+
+
+@pytest.mark.parametrize("prec", [lss.FP64, lss.MIXED])
+def test_fmm_m2p_volume_targets(volume, prec):
+    v, t, sig, x = volume
+    say("case: volume targets, %d tri, %d targets, precision %d" % (len(t), len(x), prec))
+    cd = ctx(v, t, sig, lss.FP64, lss.FAR_DIRECT)
+    pd, gd = cd.eval(x)
+    cf = ctx(v, t, sig, prec, lss.FAR_FMM)
+    pf, gf = cf.eval(x)
+    st = cf.stats()
+    say("  boxes %d m2l %d m2p %d pairs/target %.0f (nodes %d)" % (
+        st["n_boxes"], st["n_m2l"], st["n_m2p"], st["last_pairs"] / len(x), st["n_nodes"]))
+    ep, eg = errs(pf, gf, pd, gd)
+    say("  vs direct: e_phi %.3e e_grad %.3e" % (ep, eg))
+    assert st["n_m2p"] > 0
+    assert st["last_pairs"] / len(x) < 0.25 * st["n_nodes"]
+    assert ep <= TOL[prec] and eg <= TOL[prec]
+    rng = np.random.default_rng(13)
+    sel = np.sort(rng.choice(len(x), 400, replace=False))
+    po, go = oracle.evaluate(v, t, sig, dunavant6(), x[sel])
+    ep, eg = errs(pf[sel], gf[sel], po, go)
+    say("  vs oracle (400 sampled): e_phi %.3e e_grad %.3e" % (ep, eg))
+    assert ep <= TOL[prec] and eg <= TOL[prec]
