@@ -82,7 +82,10 @@ struct alignas(64) Src {
 };
 
 // FP32 staging record of the mixed path: position relative to a tile origin
-// as an unevaluated float-float sum hi + lo (lo = the FP64 remainder).
+// as an unevaluated float-float sum hi + lo (lo = the FP64 remainder).  The
+// far-form constants are folded in: ax, ay, az hold sqrt(pi)/2 a' and s2x2
+// holds 1.5 * 2 s2, so that the pair kernels work with S / (sqrt(pi)/2) and
+// T / (1.5 sqrt(pi)/2), which beyond the cut are x^-3/2 and x^-5/2.
 struct alignas(16) SrcF {
     float yx, yy, yz, s2;
     float ax, ay, az, s2x2;

@@ -33,6 +33,10 @@ namespace {
 
 constexpr double kSqrtPiHalf = 0.88622692545275801365;
 constexpr float kSqrtPiHalfF = 0.88622692545275801365f;
+// SrcF scaling (see SrcF): a' times kFoldA, 2 s2 times kFoldT; the FP32 fits
+// are divided by the same factors after the division by their denominator
+constexpr double kFoldA = 0.88622692545275801365, kFoldT = 1.5;
+constexpr float kUnfoldS = (float)(1.0 / 0.88622692545275801365), kUnfoldT = (float)(1.0 / (1.5 * 0.88622692545275801365));
 
 __device__ __forceinline__ void two_sum(double &s, double &e, double v) {
     double t = s + v;
@@ -81,7 +85,7 @@ __device__ __forceinline__ void kfun64(double x, double &S, double &T) {
     }
 }
 
-// S, T in FP32
+// S / (sqrt(pi)/2) and T / (1.5 sqrt(pi)/2) in FP32, for SrcF records
 __device__ __forceinline__ void kfun32(float x, float &S, float &T) {
     if (x < (float)KF32_X) {
         const float t = x * (float)KF32_INV_X;
@@ -93,13 +97,13 @@ __device__ __forceinline__ void kfun32(float x, float &S, float &T) {
             q = fmaf(q, t, kf32_q[k]);
         }
         const float r = __builtin_amdgcn_rcpf(q);
-        S = ps * r;
-        T = pt * r;
+        S = ps * r * kUnfoldS;
+        T = pt * r * kUnfoldT;
     } else {
         const float r = __builtin_amdgcn_rsqf(x);
         const float r2 = r * r;
-        S = kSqrtPiHalfF * r2 * r;
-        T = 1.5f * S * r2;
+        S = r2 * r;
+        T = S * r2;
     }
 }
 
@@ -181,7 +185,7 @@ template <int K>
 __device__ __forceinline__ void nodes32(const SrcF *sh, float x, float y, float z, float xl, float yl, float zl,
                                         float &p, float &gx, float &gy, float &gz) {
     float dx[K], dy[K], dz[K], u[K], ad[K], S[K], T[K];
-    bool nr[K], any = false;
+    float umin = 3.0e38f;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const SrcF s = sh[k];
@@ -191,14 +195,13 @@ __device__ __forceinline__ void nodes32(const SrcF *sh, float x, float y, float 
         const float r2 = fmaf(dx[k], dx[k], fmaf(dy[k], dy[k], dz[k] * dz[k]));
         ad[k] = fmaf(s.ax, dx[k], fmaf(s.ay, dy[k], s.az * dz[k]));
         u[k] = r2 * s.s2;
-        nr[k] = u[k] < (float)KF32_X;
-        any = any || nr[k];
+        umin = fminf(umin, u[k]);
         const float r = __builtin_amdgcn_rsqf(fmaxf(u[k], (float)KF32_X));
         const float rr = r * r;
-        S[k] = kSqrtPiHalfF * rr * r;
-        T[k] = 1.5f * S[k] * rr;
+        S[k] = rr * r;                      // folded far form (see SrcF)
+        T[k] = S[k] * rr;
     }
-    if (any) {
+    if (umin < (float)KF32_X) {             // some pair of the group inside the cut
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const float t = fminf(u[k], (float)KF32_X) * (float)KF32_INV_X;
@@ -210,8 +213,9 @@ __device__ __forceinline__ void nodes32(const SrcF *sh, float x, float y, float 
                 q = fmaf(q, t, kf32_q[i]);
             }
             const float rq = __builtin_amdgcn_rcpf(q);
-            S[k] = nr[k] ? ps * rq : S[k];
-            T[k] = nr[k] ? pt * rq : T[k];
+            const bool nr = u[k] < (float)KF32_X;
+            S[k] = nr ? ps * rq * kUnfoldS : S[k];
+            T[k] = nr ? pt * rq * kUnfoldT : T[k];
         }
     }
 #pragma unroll
@@ -351,10 +355,10 @@ __global__ __launch_bounds__(TILE) void k_p2p_direct_mixed(
                 f.ly = (float)(qy - (double)f.yy);
                 f.lz = (float)(qz - (double)f.yz);
                 f.s2 = (float)s.s2;
-                f.ax = (float)s.ax;
-                f.ay = (float)s.ay;
-                f.az = (float)s.az;
-                f.s2x2 = (float)s.s2x2;
+                f.ax = (float)(kFoldA * s.ax);
+                f.ay = (float)(kFoldA * s.ay);
+                f.az = (float)(kFoldA * s.az);
+                f.s2x2 = (float)(kFoldT * s.s2x2);
             } else {                            // zero record: no contribution, far branch
                 f.yx = f.yy = f.yz = f.lx = f.ly = f.lz = 0.0f;
                 f.ax = f.ay = f.az = f.s2x2 = 0.0f;
@@ -682,10 +686,10 @@ __global__ __launch_bounds__(64) void k_eval_fmm_mixed(FmmEvalArgs a) {
                     f.ly = (float)(qy - (double)f.yy);
                     f.lz = (float)(qz - (double)f.yz);
                     f.s2 = (float)sr.s2;
-                    f.ax = (float)sr.ax;
-                    f.ay = (float)sr.ay;
-                    f.az = (float)sr.az;
-                    f.s2x2 = (float)sr.s2x2;
+                    f.ax = (float)(kFoldA * sr.ax);
+                    f.ay = (float)(kFoldA * sr.ay);
+                    f.az = (float)(kFoldA * sr.az);
+                    f.s2x2 = (float)(kFoldT * sr.s2x2);
                 } else {                        // zero record: no contribution, far branch
                     f.yx = f.yy = f.yz = f.lx = f.ly = f.lz = 0.0f;
                     f.ax = f.ay = f.az = f.s2x2 = 0.0f;
