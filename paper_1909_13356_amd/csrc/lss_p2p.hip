@@ -32,11 +32,23 @@ namespace lss {
 namespace {
 
 constexpr double kSqrtPiHalf = 0.88622692545275801365;
-constexpr float kSqrtPiHalfF = 0.88622692545275801365f;
-// SrcF scaling (see SrcF): a' times kFoldA, 2 s2 times kFoldT; the FP32 fits
-// are divided by the same factors after the division by their denominator
-constexpr double kFoldA = 0.88622692545275801365, kFoldT = 1.5;
-constexpr float kUnfoldS = (float)(1.0 / 0.88622692545275801365), kUnfoldT = (float)(1.0 / (1.5 * 0.88622692545275801365));
+// Staged node records carry the far-form constants: a' times kFoldA and 2 s2
+// times kFoldT (SrcF, fold_src), so that the pair kernels work with
+// S / (sqrt(pi)/2) and T / (1.5 sqrt(pi)/2); the fits below the cut are
+// divided by the same factors after the division by their denominator.
+constexpr double kFoldA = kSqrtPiHalf, kFoldT = 1.5;
+constexpr float kUnfoldS = (float)(1.0 / kSqrtPiHalf), kUnfoldT = (float)(1.0 / (1.5 * kSqrtPiHalf));
+constexpr double kUnfoldS64 = 1.0 / kSqrtPiHalf, kUnfoldT64 = 1.0 / (1.5 * kSqrtPiHalf);
+
+// FP64 node record as staged in LDS: the far-form constants folded in as in
+// SrcF (a' times sqrt(pi)/2, 2 s2 times 1.5)
+__device__ __forceinline__ Src fold_src(Src f) {
+    f.ax *= kFoldA;
+    f.ay *= kFoldA;
+    f.az *= kFoldA;
+    f.s2x2 *= kFoldT;
+    return f;
+}
 
 __device__ __forceinline__ void two_sum(double &s, double &e, double v) {
     double t = s + v;
@@ -52,7 +64,7 @@ __device__ __forceinline__ void two_sum_f(float &s, float &e, float v) {
     s = t;
 }
 
-// S, T in FP64
+// S / (sqrt(pi)/2) and T / (1.5 sqrt(pi)/2) in FP64, for folded records (fold_src)
 __device__ __forceinline__ void kfun64(double x, double &S, double &T) {
     if (x < KF64_X) {
         // power basis with shared powers t^k: every step accumulates into
@@ -72,16 +84,16 @@ __device__ __forceinline__ void kfun64(double x, double &S, double &T) {
         double r = __builtin_amdgcn_rcp(q);
         r = fma(r, fma(-q, r, 1.0), r);
         r = fma(r, fma(-q, r, 1.0), r);
-        S = ps * r;
-        T = pt * r;
+        S = ps * r * kUnfoldS64;
+        T = pt * r * kUnfoldT64;
     } else {
         double r = __builtin_amdgcn_rsq(x);
         const double hx = 0.5 * x;
         r = r * fma(-hx * r, r, 1.5);
         r = r * fma(-hx * r, r, 1.5);
         const double r2 = r * r;
-        S = kSqrtPiHalf * r2 * r;
-        T = 1.5 * S * r2;
+        S = r2 * r;
+        T = S * r2;
     }
 }
 
@@ -126,7 +138,7 @@ template <int K>
 __device__ __forceinline__ void nodes64(const Src *sh, double x, double y, double z, double &p, double &gx,
                                         double &gy, double &gz) {
     double dx[K], dy[K], dz[K], u[K], ad[K], S[K], T[K];
-    bool nr[K], any = false;
+    double umin = 1.0e300;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const Src s = sh[k];
@@ -136,18 +148,17 @@ __device__ __forceinline__ void nodes64(const Src *sh, double x, double y, doubl
         const double r2 = fma(dx[k], dx[k], fma(dy[k], dy[k], dz[k] * dz[k]));
         ad[k] = fma(s.ax, dx[k], fma(s.ay, dy[k], s.az * dz[k]));
         u[k] = r2 * s.s2;
-        nr[k] = u[k] < KF64_X;
-        any = any || nr[k];
+        umin = fmin(umin, u[k]);
         const double ux = fmax(u[k], KF64_X);
         double r = __builtin_amdgcn_rsq(ux);
         const double hx = 0.5 * ux;
         r = r * fma(-hx * r, r, 1.5);
         r = r * fma(-hx * r, r, 1.5);
         const double rr = r * r;
-        S[k] = kSqrtPiHalf * rr * r;
-        T[k] = 1.5 * S[k] * rr;
+        S[k] = rr * r;                      // folded far form (see fold_src)
+        T[k] = S[k] * rr;
     }
-    if (any) {
+    if (umin < KF64_X) {                    // some pair of the group inside the cut
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const double t = fmin(u[k], KF64_X) * KF64_INV_X;
@@ -162,8 +173,9 @@ __device__ __forceinline__ void nodes64(const Src *sh, double x, double y, doubl
             double r = __builtin_amdgcn_rcp(q);
             r = fma(r, fma(-q, r, 1.0), r);
             r = fma(r, fma(-q, r, 1.0), r);
-            S[k] = nr[k] ? ps * r : S[k];
-            T[k] = nr[k] ? pt * r : T[k];
+            const bool nr = u[k] < KF64_X;
+            S[k] = nr ? ps * r * kUnfoldS64 : S[k];
+            T[k] = nr ? pt * r * kUnfoldT64 : T[k];
         }
     }
 #pragma unroll
@@ -277,7 +289,7 @@ __global__ __launch_bounds__(TILE) void k_p2p_direct_f64(
     for (int64_t c0 = lo; c0 < hi; c0 += TILE) {
         const int cnt = (int)(hi - c0 < TILE ? hi - c0 : TILE);
         __syncthreads();
-        if (lane < cnt) sh[lane] = src[c0 + lane];
+        if (lane < cnt) sh[lane] = fold_src(src[c0 + lane]);
         else {                                  // zero records pad the chunk to whole node groups
             Src f;
             f.yx = f.yy = f.yz = f.ax = f.ay = f.az = f.s2x2 = 0.0;
@@ -591,7 +603,7 @@ __global__ __launch_bounds__(TILE) void k_eval_fmm_f64(FmmEvalArgs a) {
             for (int64_t c0 = 0; c0 < total; c0 += TILE) {
                 const int cnt = (int)(total - c0 < TILE ? total - c0 : TILE);
                 __syncthreads();
-                if (lane < cnt) sh[lane] = a.src[packed_node<TILE>(rb, nr, c0 + lane)];
+                if (lane < cnt) sh[lane] = fold_src(a.src[packed_node<TILE>(rb, nr, c0 + lane)]);
                 else {                          // zero records pad the chunk to whole node groups
                     Src f;
                     f.yx = f.yy = f.yz = f.ax = f.ay = f.az = f.s2x2 = 0.0;
