@@ -570,8 +570,10 @@ __device__ __forceinline__ void fmm_m2p_list(const FmmEvalArgs &a, int32_t B, do
     __syncthreads();
 }
 
+// Four waves per SIMD: the compiler fits the kernel in 128 VGPRs with a few
+// spills outside the chunk loop (1% faster on C5 than three waves at 139).
 template <int TILE>
-__global__ __launch_bounds__(TILE) void k_eval_fmm_f64(FmmEvalArgs a) {
+__global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_fmm_f64(FmmEvalArgs a) {
     __shared__ Src sh[TILE];
     __shared__ RangeBatch<TILE> rb;
     extern __shared__ double Ls[];      // local expansion of the tile's leaf (ncp doubles)
