@@ -1,0 +1,93 @@
+"""Parity at the full sizes of the benchmark workloads, in the configuration
+the benchmark times (inputs resident on the device, FMM far field, default
+options): every output checked finite, sampled outputs against the oracle
+(same error metric and bars as the other FMM tests).
+
+C5: graded bumpy sphere, 2M triangles, 2.4e7 nodes, 5e7 near-surface targets.
+C3: graded bumpy surface, 2e5 triangles, 9e6 chart nodes (Newton onto Phi = 1/2)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1909_13356_amd as lss
+from workloads import configs
+
+pytestmark = pytest.mark.gpu
+TOL = {lss.FP64: 1e-12, lss.MIXED: 1e-6}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def device_ctx(torch, cfg, prec):
+    dev = torch.device("cuda")
+    c = lss.Context(0)
+    c.set_sources(torch.as_tensor(cfg["verts"], device=dev), torch.as_tensor(cfg["tris"], device=dev),
+                  torch.as_tensor(cfg["rule"], device=dev))
+    c.set_sigma(torch.as_tensor(np.asarray(cfg["sigma"], float), device=dev))
+    c.set_options(precision=prec, far_field=lss.FAR_FMM)
+    return c
+
+
+@pytest.fixture(scope="module")
+def c5():
+    say("generating C5: 2M triangles, 5e7 targets (about a minute on the host)")
+    cfg = configs.config5()
+    rng = np.random.default_rng(55)
+    sel = np.sort(rng.choice(len(cfg["targets"]), 24, replace=False))
+    say("oracle at %d sampled targets (full direct sum over %d nodes each)" % (len(sel), 12 * len(cfg["tris"])))
+    po, go = oracle.evaluate(cfg["verts"], cfg["tris"], cfg["sigma"], cfg["rule"], cfg["targets"][sel])
+    return cfg, sel, po, go
+
+
+@pytest.mark.parametrize("prec", [lss.FP64, lss.MIXED])
+def test_config5_full_size_sampled(c5, prec):
+    import torch
+    cfg, sel, po, go = c5
+    say("case: C5 full size, precision %d" % prec)
+    c = device_ctx(torch, cfg, prec)
+    x = torch.as_tensor(cfg["targets"], device=torch.device("cuda"))
+    phi, grad = c.eval(x)
+    torch.cuda.synchronize()
+    st = c.stats()
+    say("  boxes %d m2l %d m2p %d pairs/target %.0f" % (st["n_boxes"], st["n_m2l"], st["n_m2p"],
+                                                       st["last_pairs"] / len(x)))
+    assert bool(torch.isfinite(phi).all()) and bool(torch.isfinite(grad).all())
+    si = torch.as_tensor(sel, device=x.device)
+    pf, gf = phi[si].cpu().numpy(), grad[si].cpu().numpy()
+    ep = np.max(np.abs(pf - po)) / np.max(np.abs(po))
+    eg = np.max(np.linalg.norm(gf - go, axis=1)) / np.max(np.linalg.norm(go, axis=1))
+    say("  vs oracle (%d sampled): e_phi %.3e e_grad %.3e" % (len(sel), ep, eg))
+    c.close()
+    assert ep <= TOL[prec] and eg <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [lss.FP64, lss.MIXED])
+def test_config3_full_size_project_sampled(prec):
+    import torch
+    cfg = configs.config3()
+    uv = cfg["chart_uv"]
+    ntri, npc = len(cfg["tris"]), len(uv)
+    say("case: C3 full size projection, %d triangles x %d chart nodes, precision %d" % (ntri, npc, prec))
+    c = device_ctx(torch, cfg, prec)
+    h, xs, status, iters = c.project(torch.as_tensor(uv, device=torch.device("cuda")), device=True)
+    torch.cuda.synchronize()
+    conv = status == lss.NODE_CONVERGED
+    say("  converged %d of %d, iterations max %d" % (int(conv.sum()), ntri * npc, int(iters.max())))
+    assert bool(torch.isfinite(h[conv]).all()) and bool(torch.isfinite(xs[conv]).all())
+    sel = np.array([7, 49_999, 100_003, 199_991])
+    idx = (sel[:, None] * npc + np.arange(npc)[None]).ravel()
+    tau = 1e-12 if prec == lss.FP64 else 1e-6
+    ho, xo, sto, ito = oracle.project(cfg["verts"], cfg["tris"], cfg["sigma"], cfg["rule"], uv, tau=tau, sel=sel)
+    ii = torch.as_tensor(idx, device=h.device)
+    hg, stg = h[ii].cpu().numpy(), status[ii].cpu().numpy()
+    sig = np.asarray(cfg["sigma"], float)
+    eh = np.max(np.abs(hg - ho) / sig[sel].repeat(npc))
+    say("  sampled %d nodes: e_h %.3e" % (len(idx), eh))
+    c.close()
+    assert np.all(stg == sto)
+    assert eh <= (1e-11 if prec == lss.FP64 else 2e-6)
