@@ -20,8 +20,14 @@ cut (section 4.4, the 8 sigma bounds), so the kernels switch to
 S = (sqrt(pi)/2) x^(-3/2), T = 1.5 S / x there.
 
 Two fits are produced:
-  * FP64: X = 32 (cut at 8 sigma), degree (15, 15);
+  * FP64: X = 32 (cut at 8 sigma), degree (13, 13) (fit error 7e-15; degree
+    12 reaches only 1.7e-13, degree 15 7e-18);
   * FP32: X = 20 (cut at sqrt(40) sigma = 6.32 sigma), degree (7, 7).
+
+The pair kernels stage node records with the far-form constants folded in
+(dipole vector times sqrt(pi)/2, 2 s2 times 1.5), so they need S / (sqrt(pi)/2)
+and T / (1.5 sqrt(pi)/2); the numerators are emitted divided by those factors
+(one rounding of the exact quotient).
 
 Run:  python gen_kfit.py   (takes a few minutes; rewrites kfit_tables.h)
 """
@@ -82,9 +88,17 @@ def fit_common(fs, X, n, m, K=300, iters=40):
     return best
 
 
+FOLD = (mp.sqrt(mp.pi) / 2, mp.mpf(3) / 2 * mp.sqrt(mp.pi) / 2)   # S and T divisors
+
+
+def fold(P):
+    return [[c / FOLD[fi] for c in p] for fi, p in enumerate(P)]
+
+
 def check(P, q, X, dt):
-    """Max relative error of the rounded coefficients evaluated in dtype dt
-    (FMA-free Horner, a pessimistic stand-in for the device evaluation)."""
+    """Max relative error of the rounded (folded) coefficients evaluated in
+    dtype dt against S / FOLD[0] and T / FOLD[1] (FMA-free Horner, a
+    pessimistic stand-in for the device evaluation)."""
     Pc = [np.array([float(c) for c in p], dtype=dt) for p in P]
     qc = np.array([float(c) for c in q], dtype=dt)
     xs = np.linspace(0.0, X, 4001)
@@ -99,7 +113,7 @@ def check(P, q, X, dt):
     out = []
     for fi, f in enumerate((S, T)):
         v = horner(Pc[fi]) * r
-        out.append(max(abs(float(v[i]) / float(f(xs[i])) - 1) for i in range(len(xs))))
+        out.append(max(abs(float(v[i]) / float(f(xs[i]) / FOLD[fi]) - 1) for i in range(len(xs))))
     return out
 
 
@@ -118,16 +132,18 @@ def emit(f, name, ctype, P, q, X, fit_err, eval_err):
 
 
 def main():
-    specs = [("kf64", 32.0, 15, 15, np.float64, "double"),
+    specs = [("kf64", 32.0, 13, 13, np.float64, "double"),
              ("kf32", 20.0, 7, 7, np.float32, "float")]
     out = os.path.join(HERE, "kfit_tables.h")
     with open(out + ".tmp", "w") as f:
         f.write("// Generated by gen_kfit.py -- do not edit.\n"
-                "// Rational fits S ~ P_S(t)/Q(t), T ~ P_T(t)/Q(t), t = x/X, of\n"
+                "// Rational fits S' ~ P_S(t)/Q(t), T' ~ P_T(t)/Q(t), t = x/X, of\n"
+                "// S' = S / (sqrt(pi)/2), T' = T / (1.5 sqrt(pi)/2) with\n"
                 "// S(x) = gamma(3/2,x)/x^(3/2) and T(x) = gamma(5/2,x)/x^(5/2).\n"
                 "#pragma once\n\n")
         for name, X, n, m, dt, ctype in specs:
             fe, P, q = fit_common([S, T], mp.mpf(X), n, m)
+            P = fold(P)
             ee = check(P, q, X, dt)
             print(name, "fit", mp.nstr(fe, 3), "eval", ee, file=sys.stderr)
             emit(f, name, ctype, P, q, X, float(fe), ee)

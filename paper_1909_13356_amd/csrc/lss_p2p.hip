@@ -34,11 +34,9 @@ namespace {
 constexpr double kSqrtPiHalf = 0.88622692545275801365;
 // Staged node records carry the far-form constants: a' times kFoldA and 2 s2
 // times kFoldT (SrcF, fold_src), so that the pair kernels work with
-// S / (sqrt(pi)/2) and T / (1.5 sqrt(pi)/2); the fits below the cut are
-// divided by the same factors after the division by their denominator.
+// S / (sqrt(pi)/2) and T / (1.5 sqrt(pi)/2); the fits below the cut
+// (kfit_tables.h) are generated for these quotients.
 constexpr double kFoldA = kSqrtPiHalf, kFoldT = 1.5;
-constexpr float kUnfoldS = (float)(1.0 / kSqrtPiHalf), kUnfoldT = (float)(1.0 / (1.5 * kSqrtPiHalf));
-constexpr double kUnfoldS64 = 1.0 / kSqrtPiHalf, kUnfoldT64 = 1.0 / (1.5 * kSqrtPiHalf);
 
 // FP64 node record as staged in LDS: the far-form constants folded in as in
 // SrcF (a' times sqrt(pi)/2, 2 s2 times 1.5)
@@ -84,8 +82,8 @@ __device__ __forceinline__ void kfun64(double x, double &S, double &T) {
         double r = __builtin_amdgcn_rcp(q);
         r = fma(r, fma(-q, r, 1.0), r);
         r = fma(r, fma(-q, r, 1.0), r);
-        S = ps * r * kUnfoldS64;
-        T = pt * r * kUnfoldT64;
+        S = ps * r;
+        T = pt * r;
     } else {
         double r = __builtin_amdgcn_rsq(x);
         const double hx = 0.5 * x;
@@ -109,8 +107,8 @@ __device__ __forceinline__ void kfun32(float x, float &S, float &T) {
             q = fmaf(q, t, kf32_q[k]);
         }
         const float r = __builtin_amdgcn_rcpf(q);
-        S = ps * r * kUnfoldS;
-        T = pt * r * kUnfoldT;
+        S = ps * r;
+        T = pt * r;
     } else {
         const float r = __builtin_amdgcn_rsqf(x);
         const float r2 = r * r;
@@ -174,8 +172,8 @@ __device__ __forceinline__ void nodes64(const Src *sh, double x, double y, doubl
             r = fma(r, fma(-q, r, 1.0), r);
             r = fma(r, fma(-q, r, 1.0), r);
             const bool nr = u[k] < KF64_X;
-            S[k] = nr ? ps * r * kUnfoldS64 : S[k];
-            T[k] = nr ? pt * r * kUnfoldT64 : T[k];
+            S[k] = nr ? ps * r : S[k];
+            T[k] = nr ? pt * r : T[k];
         }
     }
 #pragma unroll
@@ -226,8 +224,8 @@ __device__ __forceinline__ void nodes32(const SrcF *sh, float x, float y, float 
             }
             const float rq = __builtin_amdgcn_rcpf(q);
             const bool nr = u[k] < (float)KF32_X;
-            S[k] = nr ? ps * rq * kUnfoldS : S[k];
-            T[k] = nr ? pt * rq * kUnfoldT : T[k];
+            S[k] = nr ? ps * rq : S[k];
+            T[k] = nr ? pt * rq : T[k];
         }
     }
 #pragma unroll
