@@ -197,9 +197,11 @@ int lss_build(lss_ctx *ctx);
 /* Phi and grad Phi at n targets x (n,3).  x_mesh (n) gives, for a batch
  * with nmesh > 1, the mesh whose nodes are summed for each target (NULL is
  * allowed only for nmesh == 1); values outside [0, nmesh) give LSS_EINVAL
- * (checked only for host pointers; device-side out-of-range ids are clamped).
+ * (device arrays too: a check kernel runs and the call waits for it).
  * phi (n), grad (n,3) receive the results; grad may be NULL.  n == 0 is a
- * no-op.  Non-finite targets give NaN outputs. */
+ * no-op.  Non-finite targets give NaN outputs.  With LSS_FAR_FMM a target
+ * outside its mesh's root cube (the node bounding box padded by twice the
+ * largest cut radius) is summed directly over all nodes of its mesh. */
 int lss_eval(lss_ctx *ctx, const double *x, const int32_t *x_mesh, int64_t n,
              double *phi, double *grad, unsigned flags);
 
