@@ -440,6 +440,9 @@ struct FmmEvalArgs {
     const double *L;
     const double *M;            // multipole expansions (for the M2P lists)
     const int32_t *m2p_beg, *m2p_end, *m2p_src;
+    const int32_t *child, *parent;
+    const double *rmax;         // largest cut radius of each box's nodes
+    int K;                      // separation criterion of the M2P lists
     int p, ncp;
     const double *root;         // per-mesh root cubes (corner xyz, side)
     const int32_t *bmesh;
@@ -468,35 +471,26 @@ __device__ __forceinline__ void queue_done(const FmmEvalArgs &a) {
     }
 }
 
-// The near list of a tile (its leaf's source boxes, or every node of the mesh
-// for targets outside its root cube) is streamed as one packed sequence: up
-// to TILE ranges at a time
-// are prefix-summed in LDS and each chunk of TILE nodes is filled across range
-// boundaries, so no chunk is left partly empty at the end of a small box.
+// The near list of a tile (its leaf's source boxes) is streamed as one packed
+// sequence: up to TILE ranges at a time are prefix-summed in LDS and each
+// chunk of TILE nodes is filled across range boundaries, so no chunk is left
+// partly empty at the end of a small box.
 template <int TILE>
 struct RangeBatch {
     int64_t beg[TILE];
     int64_t off[TILE + 1];
 };
 
-// load ranges [e, e + nr) of the leaf (or, outside the root cube of mesh
-// `out_mesh` >= 0, that mesh's whole node range: its level-0 box) and
-// prefix-sum their lengths; returns the packed length (uniform)
+// load ranges [e, e + nr) of the leaf's direct list and prefix-sum their
+// lengths; returns the packed length (uniform)
 template <int TILE>
-__device__ __forceinline__ int64_t load_ranges(const FmmEvalArgs &a, RangeBatch<TILE> &rb, int e, int nr,
-                                               int32_t out_mesh) {
+__device__ __forceinline__ int64_t load_ranges(const FmmEvalArgs &a, RangeBatch<TILE> &rb, int e, int nr) {
     const int t = threadIdx.x;
     int64_t len = 0;
     if (t < nr) {
-        int64_t lo, hi;
-        if (out_mesh >= 0) { lo = a.nb[out_mesh]; hi = a.ne[out_mesh]; }
-        else {
-            const int32_t S = a.p2p_src[e + t];
-            lo = a.nb[S];
-            hi = a.ne[S];
-        }
-        rb.beg[t] = lo;
-        len = hi - lo;
+        const int32_t S = a.p2p_src[e + t];
+        rb.beg[t] = a.nb[S];
+        len = a.ne[S] - a.nb[S];
     }
     rb.off[t + 1] = len;
     if (t == 0) rb.off[0] = 0;
@@ -568,6 +562,91 @@ __device__ __forceinline__ void fmm_m2p_list(const FmmEvalArgs &a, int32_t B, do
     __syncthreads();
 }
 
+// Far field at a target outside its mesh's root cube (every node is then
+// beyond the cut, the root cube being padded by twice the largest cut
+// radius): one lane walks mesh m's tree depth first without a stack (the
+// eight children of a box are consecutive, so the next box after a subtree is
+// the next sibling of the first ancestor that is not an eighth child).  A box
+// that passes the M2P test of the lists for this point is evaluated from its
+// multipole expansion, a leaf that does not is summed directly, any other box
+// is opened.  Returns the direct pairs spent.
+__device__ __forceinline__ double fmm_outside(const FmmEvalArgs &a, int32_t m, double x, double y, double z, double &ph,
+                              double g[3]) {
+    double npair = 0.0, p = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    int32_t b = m;                                  // level-0 box of mesh m
+    while (b >= 0) {
+        bool open = false;
+        const int64_t n0 = a.nb[b], n1 = a.ne[b];
+        if (n1 > n0) {
+            const double s = box_side(a.root, a.bmesh, b, a.lev[b]);
+            const double *o = a.root + 4 * a.bmesh[b];
+            const double lo[3] = {o[0] + a.ijk[3 * b] * s, o[1] + a.ijk[3 * b + 1] * s, o[2] + a.ijk[3 * b + 2] * s};
+            const double pt[3] = {x, y, z};
+            double dc = 0.0, gap = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                const double c = lo[d] + 0.5 * s, e = pt[d] - c;
+                const double gd = fmax(fmax(lo[d] - pt[d], pt[d] - (lo[d] + s)), 0.0);
+                dc += e * e;
+                gap += gd * gd;
+            }
+            if (dc >= (double)a.K * s * s && gap >= a.rmax[b] * a.rmax[b]) {
+                double p1, g1[3];
+                const double inv = 1.0 / s;
+                fmm::m2p(a.M + (int64_t)b * a.ncp, (x - lo[0]) * inv - 0.5, (y - lo[1]) * inv - 0.5,
+                         (z - lo[2]) * inv - 0.5, inv, a.p, p1, g1);
+                p += p1;
+                gx += g1[0];
+                gy += g1[1];
+                gz += g1[2];
+            } else if (a.child[b] < 0) {
+                for (int64_t k = n0; k < n1; ++k) pair64(fold_src(a.src[k]), x, y, z, p, gx, gy, gz);
+                npair += (double)(n1 - n0);
+            } else {
+                open = true;
+            }
+        }
+        if (open) {
+            b = a.child[b];
+        } else {
+            while (b != m && b == a.child[a.parent[b]] + 7) b = a.parent[b];
+            b = b == m ? -1 : b + 1;
+        }
+    }
+    ph = p;
+    g[0] = gx;
+    g[1] = gy;
+    g[2] = gz;
+    return npair;
+}
+
+// Targets outside their mesh's root cube (their tiles are skipped by the
+// tile kernels): one thread per target over the sorted targets, both
+// precisions in FP64.
+__global__ __launch_bounds__(256) void k_eval_outside(FmmEvalArgs a) {
+    const int64_t n = a.n_dev ? (int64_t)*a.n_dev : a.n_max;
+    double npair = 0.0, lanes = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t B = a.sleaf[i];
+        if (B < a.nboxes) continue;
+        const int64_t ti = a.sidx ? (int64_t)a.sidx[i] : i;
+        double ph, g[3];
+        const double np = fmm_outside(a, B - a.nboxes, a.tx[ti], a.ty[ti], a.tz[ti], ph, g);
+        npair += np;
+        lanes += np;
+        const int64_t o = a.out_idx ? (int64_t)a.out_idx[ti] : ti;
+        a.phi[o] = ph;
+        if (a.grad) {
+            a.grad[3 * o] = g[0];
+            a.grad[3 * o + 1] = g[1];
+            a.grad[3 * o + 2] = g[2];
+        }
+    }
+    if (a.pairs && npair > 0.0) {           // [0] pairs of real targets, [1] lane slots spent
+        atomicAdd(a.pairs, npair);
+        atomicAdd(a.pairs + 1, lanes);
+    }
+}
+
 // Four waves per SIMD: the compiler fits the kernel in 128 VGPRs with a few
 // spills outside the chunk loop (1% faster on C5 than three waves at 139).
 template <int TILE>
@@ -589,16 +668,16 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(4))) void 
         const int64_t ti = a.sidx ? (int64_t)a.sidx[valid ? sp_ : s0] : (valid ? sp_ : s0);
         const double x = a.tx[ti], y = a.ty[ti], z = a.tz[ti];
         const int32_t B = leafk;
-        const bool outside = B >= a.nboxes;
-        const int e0 = outside ? 0 : a.p2p_beg[B], e1 = outside ? 1 : a.p2p_end[B];
+        if (B >= a.nboxes) continue;        // outside the root cube: k_eval_outside
+        const int e0 = a.p2p_beg[B], e1 = a.p2p_end[B];
         __syncthreads();                    // previous tile is done with Ls
-        if (!outside) stage_local(a, B, Ls);
+        stage_local(a, B, Ls);
         double sp = 0, ep = 0, sx = 0, ex = 0, sy = 0, ey = 0, sz = 0, ez = 0;
         double npair = 0.0;
         for (int eb = e0; eb < e1; eb += TILE) {
             const int nr = e1 - eb < TILE ? e1 - eb : TILE;
             __syncthreads();
-            const int64_t total = load_ranges<TILE>(a, rb, eb, nr, outside ? B - a.nboxes : -1);
+            const int64_t total = load_ranges<TILE>(a, rb, eb, nr);
             npair += (double)total;
             for (int64_t c0 = 0; c0 < total; c0 += TILE) {
                 const int cnt = (int)(total - c0 < TILE ? total - c0 : TILE);
@@ -620,12 +699,12 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(4))) void 
             }
         }
         double ph = 0.0, g[3] = {0.0, 0.0, 0.0}, mph = 0.0, mg[3] = {0.0, 0.0, 0.0};
-        if (!outside && a.m2p_end[B] > a.m2p_beg[B]) {  // uniform: Ls is the M2P staging buffer, then L again
+        if (a.m2p_end[B] > a.m2p_beg[B]) {  // uniform: Ls is the M2P staging buffer, then L again
             fmm_m2p_list(a, B, Ls, x, y, z, mph, mg);
             stage_local(a, B, Ls);
         }
         __syncthreads();                    // Ls staged
-        if (!outside) fmm_l2p(a, B, Ls, x, y, z, ph, g);
+        fmm_l2p(a, B, Ls, x, y, z, ph, g);
         ph += mph;
         g[0] += mg[0];
         g[1] += mg[1];
@@ -663,6 +742,7 @@ __global__ __launch_bounds__(64) void k_eval_fmm_mixed(FmmEvalArgs a) {
         const int tile = a.order[q];
         const int64_t s0 = a.tile_start[tile];
         const int32_t B = a.sleaf[s0];
+        if (B >= a.nboxes) continue;        // outside the root cube: k_eval_outside
         const int64_t s1 = tile + 1 < ntiles ? (int64_t)a.tile_start[tile + 1] : n;   // tile = [s0, s1)
         const int64_t sp_ = s0 + lane;
         const bool valid = sp_ < s1;
@@ -673,16 +753,15 @@ __global__ __launch_bounds__(64) void k_eval_fmm_mixed(FmmEvalArgs a) {
         const double dxo = X - ox, dyo = Y - oy, dzo = Z - oz;
         const float x = (float)dxo, y = (float)dyo, z = (float)dzo;
         const float xl = (float)(dxo - (double)x), yl = (float)(dyo - (double)y), zl = (float)(dzo - (double)z);
-        const bool outside = B >= a.nboxes;
-        const int e0 = outside ? 0 : a.p2p_beg[B], e1 = outside ? 1 : a.p2p_end[B];
+        const int e0 = a.p2p_beg[B], e1 = a.p2p_end[B];
         __syncthreads();                    // previous tile is done with Ls
-        if (!outside) stage_local(a, B, Ls);
+        stage_local(a, B, Ls);
         float sp = 0, ep = 0, sx = 0, ex = 0, sy = 0, ey = 0, sz = 0, ez = 0;
         double npair = 0.0;
         for (int eb = e0; eb < e1; eb += W) {
             const int nr = e1 - eb < W ? e1 - eb : W;
             __syncthreads();
-            const int64_t total = load_ranges<W>(a, rb, eb, nr, outside ? B - a.nboxes : -1);
+            const int64_t total = load_ranges<W>(a, rb, eb, nr);
             npair += (double)total;
             for (int64_t c0 = 0; c0 < total; c0 += W) {
                 const int cnt = (int)(total - c0 < W ? total - c0 : W);
@@ -723,12 +802,12 @@ __global__ __launch_bounds__(64) void k_eval_fmm_mixed(FmmEvalArgs a) {
             }
         }
         double ph = 0.0, g[3] = {0.0, 0.0, 0.0}, mph = 0.0, mg[3] = {0.0, 0.0, 0.0};
-        if (!outside && a.m2p_end[B] > a.m2p_beg[B]) {  // uniform: Ls is the M2P staging buffer, then L again
+        if (a.m2p_end[B] > a.m2p_beg[B]) {  // uniform: Ls is the M2P staging buffer, then L again
             fmm_m2p_list(a, B, Ls, X, Y, Z, mph, mg);
             stage_local(a, B, Ls);
         }
         __syncthreads();                    // Ls staged
-        if (!outside) fmm_l2p(a, B, Ls, X, Y, Z, ph, g);
+        fmm_l2p(a, B, Ls, X, Y, Z, ph, g);
         ph += mph;
         g[0] += mg[0];
         g[1] += mg[1];
@@ -819,18 +898,25 @@ void launch_eval_fmm(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const
     a.pairs = c.pairs.as<double>();
     a.queue = c.tile_queue.as<unsigned int>();
     a.order = c.tile_order.as<int32_t>();
+    a.child = t.child.as<int32_t>();
+    a.parent = t.parent.as<int32_t>();
+    a.rmax = t.rmax.as<double>();
+    a.K = t.K;
     int64_t g = max_tiles < 16384 ? max_tiles : 16384;
     unsigned grid = (unsigned)(g > 0 ? g : 1);
     if (c.opt.precision == LSS_MIXED) {
         hipLaunchKernelGGL(k_eval_fmm_mixed, dim3(grid), dim3(64), sizeof(double) * (size_t)a.ncp, c.stream, a);
         LSS_CHECK_LAUNCH("k_eval_fmm_mixed");
-        return;
+    } else {
+        switch (fmm_tile(c)) {
+            case 64: launch_fmm_tile<64>(c, grid, a); break;
+            case 128: launch_fmm_tile<128>(c, grid, a); break;
+            default: launch_fmm_tile<256>(c, grid, a); break;
+        }
     }
-    switch (fmm_tile(c)) {
-        case 64: launch_fmm_tile<64>(c, grid, a); break;
-        case 128: launch_fmm_tile<128>(c, grid, a); break;
-        default: launch_fmm_tile<256>(c, grid, a); break;
-    }
+    const int64_t go = ceil_div(n_max > 0 ? n_max : 1, 256);
+    hipLaunchKernelGGL(k_eval_outside, dim3((unsigned)(go < 1024 ? go : 1024)), dim3(256), 0, c.stream, a);
+    LSS_CHECK_LAUNCH("k_eval_outside");
 }
 
 void launch_p2p_direct(Ctx &c, int64_t n, const int32_t *n_dev, const double *tx, const double *ty,

@@ -279,3 +279,26 @@ def test_fmm_m2p_volume_targets(volume, prec):
     ep, eg = errs(pf[sel], gf[sel], po, go)
     say("  vs oracle (400 sampled): e_phi %.3e e_grad %.3e" % (ep, eg))
     assert ep <= TOL[prec] and eg <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [lss.FP64, lss.MIXED])
+def test_fmm_targets_outside_root_cube(prec):
+    """Targets outside the padded root cube take the far field from a
+    stackless walk of the tree (multipoles where the M2P test passes, direct
+    sums of the leaves where it does not), not a direct sum over the mesh."""
+    v, t = icosphere(4)
+    sig = 0.05
+    xo = shell_targets(3000, 7.0, 12.0, seed=21)         # outside the root cube (half side <= 3.6)
+    x = np.concatenate([xo, box_targets(1000, -1.6, 1.6, seed=22)])
+    cd = ctx(v, t, sig, lss.FP64, lss.FAR_DIRECT)
+    pd, gd = cd.eval(x)
+    cf = ctx(v, t, sig, prec, lss.FAR_FMM)
+    cf.eval(xo)
+    st = cf.stats()
+    say("case: outside targets, precision %d: direct pairs/target %.0f of %d nodes" % (
+        prec, st["last_pairs"] / len(xo), st["n_nodes"]))
+    assert st["last_pairs"] / len(xo) < 0.05 * st["n_nodes"]
+    pf, gf = cf.eval(x)
+    ep, eg = errs(pf, gf, pd, gd)
+    say("  with 1000 volume targets: e_phi %.3e e_grad %.3e" % (ep, eg))
+    assert ep <= TOL[prec] and eg <= TOL[prec]
