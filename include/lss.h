@@ -201,7 +201,9 @@ int lss_build(lss_ctx *ctx);
  * phi (n), grad (n,3) receive the results; grad may be NULL.  n == 0 is a
  * no-op.  Non-finite targets give NaN outputs.  With LSS_FAR_FMM a target
  * outside its mesh's root cube (the node bounding box padded by twice the
- * largest cut radius) is summed directly over all nodes of its mesh. */
+ * largest cut radius) gets its field from a walk of that mesh's tree:
+ * multipole expansions of the boxes far enough from it, direct sums of the
+ * leaves that are not. */
 int lss_eval(lss_ctx *ctx, const double *x, const int32_t *x_mesh, int64_t n,
              double *phi, double *grad, unsigned flags);
 
