@@ -225,8 +225,12 @@ __device__ inline void pair_of(const GemmArgs &a, int64_t j, int oct, int64_t &d
 // compiler keep the accumulators in ordinary VGPRs (126 in all, no AGPRs):
 // four workgroups share a CU instead of two, which hides the barrier and load
 // latency of one workgroup behind the MFMAs of the others.
-constexpr int kTR = 64, kTP = 128;
+// TP = 128 pairs per workgroup for long pair lists, 64 for short ones (twice
+// the workgroups for the same work where one launch would not fill the chip).
+constexpr int kTR = 64;
+template <int TP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_gemm(GemmArgs a) {
+    constexpr int kTP = TP, NT = TP / 64, TPC = 256 / TP;   // 16-pair groups per wave, threads per column
     __shared__ double As[kKB][kTR + 1];
     __shared__ double Bs[kKB][kTP + 1];
     __shared__ int64_t scol[kTP];
@@ -243,9 +247,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     }
     __syncthreads();
     // per thread: A elements (k, r) = (e / kTR, e % kTR) for e = tid + 256 i, i < 4;
-    // B elements (k, c) with c = tid / 2, k = 8 (tid & 1) + i, i < 8 (two threads per column)
+    // B elements (k, c) with c = tid / TPC, k = kNB (tid % TPC) + i, i < kNB (TPC threads per column)
     constexpr int kNA = kKB * kTR / 256, kNB = kKB * kTP / 256;
-    const int bc = threadIdx.x >> 1, bk = (threadIdx.x & 1) * kNB;
+    const int bc = threadIdx.x / TPC, bk = (threadIdx.x % TPC) * kNB;
     const int64_t bcol = scol[bc];
     double ra[kNA], rb[kNB];
     auto fetch = [&](int k0) {
@@ -257,10 +261,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
         for (int i = 0; i < kNB; ++i) rb[i] = bcol >= 0 ? a.X[bcol + k0 + bk + i] : 0.0;
     };
-    d4 acc[4][2];
+    d4 acc[4][NT];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-        for (int t = 0; t < 2; ++t) acc[i][t] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t < NT; ++t) acc[i][t] = d4{0.0, 0.0, 0.0, 0.0};
     fetch(0);
     for (int k0 = 0; k0 < a.nk; k0 += kKB) {
         __syncthreads();                                   // previous block's MFMAs are done with LDS
@@ -275,20 +279,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         if (k0 + kKB < a.nk) fetch(k0 + kKB);
 #pragma unroll
         for (int kk = 0; kk < kKB; kk += 4) {
-            double bv[2];
+            double bv[NT];
 #pragma unroll
-            for (int t = 0; t < 2; ++t) bv[t] = Bs[kk + (lane >> 4)][32 * w + 16 * t + (lane & 15)];
+            for (int t = 0; t < NT; ++t) bv[t] = Bs[kk + (lane >> 4)][16 * NT * w + 16 * t + (lane & 15)];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const double av = As[kk + (lane >> 4)][16 * i + (lane & 15)];
 #pragma unroll
-                for (int t = 0; t < 2; ++t) acc[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[t], acc[i][t], 0, 0, 0);
+                for (int t = 0; t < NT; ++t) acc[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[t], acc[i][t], 0, 0, 0);
             }
         }
     }
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        const int64_t j = j0 + 32 * w + 16 * t + (lane & 15);
+    for (int t = 0; t < NT; ++t) {
+        const int64_t j = j0 + 16 * NT * w + 16 * t + (lane & 15);
         if (j >= a.npairs) continue;
         int64_t d, col;
         double sc;
@@ -306,15 +310,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 }
 
 void gemm(Ctx &c, GemmArgs a) {
+    // short lists (fewer than two 128-pair workgroups per CU) take 64-pair workgroups
+    const bool small = a.npairs * (a.mode == G_L2L ? 8 : 1) * ceil_div(a.ncp, kTR) < 2 * 256 * 128;
+    const int tp = small ? 64 : 128;
     // split long pair lists so that grid.y stays within the launch limit
-    const int64_t chunk = (int64_t)32768 * kTP;
+    const int64_t chunk = (int64_t)32768 * tp;
     for (int64_t j0 = 0; j0 < a.npairs; j0 += chunk) {
         GemmArgs b = a;
         b.npairs = a.npairs - j0 < chunk ? a.npairs - j0 : chunk;
         if (a.mode == G_LIST) { b.mkey = a.mkey + j0; b.mval = a.mval + j0; }
         else b.base = a.base + 8 * j0;
-        dim3 grid((unsigned)ceil_div(b.ncp, kTR), (unsigned)ceil_div(b.npairs, kTP), a.mode == G_L2L ? 8u : 1u);
-        hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, c.stream, b);
+        dim3 grid((unsigned)ceil_div(b.ncp, kTR), (unsigned)ceil_div(b.npairs, tp), a.mode == G_L2L ? 8u : 1u);
+        if (small) hipLaunchKernelGGL(k_gemm<64>, grid, dim3(256), 0, c.stream, b);
+        else hipLaunchKernelGGL(k_gemm<128>, grid, dim3(256), 0, c.stream, b);
         LSS_CHECK_LAUNCH("k_gemm");
     }
 }
