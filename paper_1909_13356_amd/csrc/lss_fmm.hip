@@ -310,8 +310,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 }
 
 void gemm(Ctx &c, GemmArgs a) {
-    // short lists (fewer than two 128-pair workgroups per CU) take 64-pair workgroups
-    const bool small = a.npairs * (a.mode == G_L2L ? 8 : 1) * ceil_div(a.ncp, kTR) < 2 * 256 * 128;
+    // short lists (fewer than four 128-pair workgroups per CU) take 64-pair workgroups
+    const bool small = a.npairs * (a.mode == G_L2L ? 8 : 1) * ceil_div(a.ncp, kTR) < 4 * 256 * 128;
     const int tp = small ? 64 : 128;
     // split long pair lists so that grid.y stays within the launch limit
     const int64_t chunk = (int64_t)32768 * tp;
