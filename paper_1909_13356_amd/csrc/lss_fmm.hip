@@ -164,6 +164,105 @@ __global__ __launch_bounds__(64) void k_p2m_cols(const int32_t *__restrict__ nle
 }
 
 
+// The same P2M for the default orders (P known at compile time): lane (g, m)
+// keeps its column's contributions to M_n^m, n = 1..P, in registers across
+// all the leaf's nodes (the step loop is unrolled), instead of a read-modify-
+// write in LDS per step; the G node slots are summed by shuffles at the end,
+// in the order the LDS version sums them.
+template <int P>
+__global__ __launch_bounds__(64) void k_p2m_reg(const int32_t *__restrict__ nleaf_dev,
+                                                const int32_t *__restrict__ leaves, int ncp, Geo g,
+                                                const int32_t *__restrict__ lev, const int32_t *__restrict__ ijk,
+                                                const int64_t *__restrict__ nb, const int64_t *__restrict__ ne,
+                                                const Src *__restrict__ src, double *M) {
+    constexpr int C = P + 1, G = 64 / C, ntri = (P + 1) * (P + 2) / 2;
+    __shared__ double rinv[ntri];                         // 1/((n+m)(n-m)) at tri(n, m), n > m
+    __shared__ double dfac[P + 1];                        // -1/(2t), t = 1..P
+    if ((int)blockIdx.x >= *nleaf_dev) return;
+    const int lane = threadIdx.x;
+    for (int i = lane; i < ntri; i += 64) {
+        int n = 0;
+        while ((n + 1) * (n + 2) / 2 <= i) ++n;
+        const int m = i - n * (n + 1) / 2;
+        rinv[i] = n > m ? 1.0 / ((double)(n + m) * (double)(n - m)) : 0.0;
+    }
+    for (int t = lane; t <= P; t += 64) dfac[t] = t > 0 ? -0.5 / (double)t : 0.0;
+    __syncthreads();
+    const int32_t b = leaves[blockIdx.x];
+    const double s = box_side(g.root, g.bmesh, b, lev[b]);
+    const double *o = g.root + 4 * g.bmesh[b];
+    const double c0 = o[0] + (ijk[3 * b] + 0.5) * s, c1 = o[1] + (ijk[3 * b + 1] + 0.5) * s,
+                 c2 = o[2] + (ijk[3 * b + 2] + 0.5) * s;
+    const double inv4pis = 1.0 / (4.0 * kPi * s);
+    const double invs = 1.0 / s;
+    const int gi = lane / C, m = lane % C;
+    const bool slot = gi < G;
+    double are[P], aim[P];                                // contributions to M_{st+1}^m
+#pragma unroll
+    for (int st = 0; st < P; ++st) are[st] = aim[st] = 0.0;
+    const int64_t b0 = nb[b], b1 = ne[b];
+    for (int64_t k0 = b0; k0 < b1; k0 += G) {
+        const int64_t k = k0 + gi;
+        const bool live = slot && k < b1;
+        double x = 0, y = 0, z = 0, ax = 0, ay = 0, az = 0;
+        if (live) {
+            const Src sr = src[k];
+            // unfold the dipole: a = a' / c(sigma), 1/c = 4 sqrt2 pi^1.5 sigma^3, sigma^2 = 1/(2 s2)
+            const double sg2 = 0.5 / sr.s2;
+            const double f = 4.0 * 1.4142135623730951 * 5.568327996831708 * sg2 * sqrt(sg2);
+            x = (sr.yx - c0) * invs;
+            y = (sr.yy - c1) * invs;
+            z = (sr.yz - c2) * invs;
+            ax = sr.ax * f;
+            ay = sr.ay * f;
+            az = sr.az * f;
+        }
+        const double r2 = x * x + y * y + z * z;
+        cd d = {1.0, 0.0}, u1 = {0.0, 0.0}, u2 = {0.0, 0.0};
+#pragma unroll
+        for (int st = 0; st < P; ++st) {
+            cd u = {0.0, 0.0};
+            if (st == m) {
+                u = d;
+            } else if (st > m) {
+                const double w = rinv[fmm::tri(st, m)];
+                const double a2 = (double)(2 * st - 1) * z;
+                u = cd{(a2 * u1.re - r2 * u2.re) * w, (a2 * u1.im - r2 * u2.im) * w};
+            } else {
+                d = fmm::cscale(fmm::cmul(d, cd{x, y}), dfac[st + 1]);
+            }
+            if (st >= m) { u2 = u1; u1 = u; }
+            const double upre = __shfl(u.re, lane + 1), upim = __shfl(u.im, lane + 1);
+            const double dnre = __shfl(u.re, lane - 1), dnim = __shfl(u.im, lane - 1);
+            cd up = m + 1 < C ? cd{upre, upim} : cd{0.0, 0.0};
+            cd dn = m >= 1 ? cd{dnre, dnim} : cd{-upre, upim};
+            if (live && m <= st + 1) {
+                const cd t = fmm::cadd(fmm::cadd(fmm::cmul(cd{0.5 * ax, -0.5 * ay}, up),
+                                                 fmm::cmul(cd{-0.5 * ax, -0.5 * ay}, dn)),
+                                       fmm::cscale(u, az));
+                are[st] -= inv4pis * t.re;      // conj, times -1/(4 pi s)
+                aim[st] += inv4pis * t.im;
+            }
+        }
+    }
+    // sum the node slots into lanes (0, m) and write M~_n^m, n = 1..P
+    double *Mb = M + (int64_t)b * ncp;
+#pragma unroll
+    for (int st = 0; st < P; ++st) {
+        double re = 0.0 + are[st], im = 0.0 + aim[st];
+#pragma unroll
+        for (int q = 1; q < G; ++q) {
+            re += __shfl(are[st], lane + q * C);
+            im += __shfl(aim[st], lane + q * C);
+        }
+        const int n = st + 1;
+        if (gi == 0 && m <= n) {
+            Mb[fmm::ire(n, m)] = re;
+            if (m > 0) Mb[fmm::iim(n, m)] = im;
+        }
+    }
+}
+
 __global__ void k_leaf_flags(int64_t n, const int32_t *__restrict__ child, const int64_t *__restrict__ nb,
                              const int64_t *__restrict__ ne, int32_t *flag, int32_t *ids) {
     int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -411,12 +510,20 @@ void build_fmm(Ctx &c) {
     LSS_HIP(hipStreamSynchronize(c.stream));
     c.stats.n_leaves = nl;
     if (nl > 0) {
-        const int ntri = (p + 1) * (p + 2) / 2, G = 64 / (p + 1);
-        size_t shm = sizeof(double) * (2 * G * ntri + ntri + p + 1);
-        hipLaunchKernelGGL(k_p2m_cols, dim3(nl), dim3(64), shm, c.stream, nleaf.as<int32_t>(), leaves.as<int32_t>(), p,
-                           ncp, g, t.level.as<int32_t>(), t.ijk.as<int32_t>(), t.nb.as<int64_t>(), t.ne.as<int64_t>(),
-                           t.src.as<Src>(), t.M.as<double>());
-        LSS_CHECK_LAUNCH("k_p2m_cols");
+        if (p == 20 || p == 26) {
+            auto k = p == 20 ? k_p2m_reg<20> : k_p2m_reg<26>;
+            hipLaunchKernelGGL(k, dim3(nl), dim3(64), 0, c.stream, nleaf.as<int32_t>(), leaves.as<int32_t>(), ncp, g,
+                               t.level.as<int32_t>(), t.ijk.as<int32_t>(), t.nb.as<int64_t>(), t.ne.as<int64_t>(),
+                               t.src.as<Src>(), t.M.as<double>());
+            LSS_CHECK_LAUNCH("k_p2m_reg");
+        } else {
+            const int ntri = (p + 1) * (p + 2) / 2, G = 64 / (p + 1);
+            size_t shm = sizeof(double) * (2 * G * ntri + ntri + p + 1);
+            hipLaunchKernelGGL(k_p2m_cols, dim3(nl), dim3(64), shm, c.stream, nleaf.as<int32_t>(), leaves.as<int32_t>(),
+                               p, ncp, g, t.level.as<int32_t>(), t.ijk.as<int32_t>(), t.nb.as<int64_t>(),
+                               t.ne.as<int64_t>(), t.src.as<Src>(), t.M.as<double>());
+            LSS_CHECK_LAUNCH("k_p2m_cols");
+        }
     }
     // upward pass: M2M from level depth to 1 into their parents
     for (int lvl = t.depth; lvl >= 1; --lvl) {
