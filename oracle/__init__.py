@@ -126,3 +126,43 @@ def project(verts, tris, sigma, rule, chart_uv, tau=1e-12, max_iter=40, sel=None
                            _p(s), nsel, float(tau), int(max_iter), _p(h), _p(xo),
                            _p(st), _p(it), int(nthreads))
     return h, xo, st, it
+
+
+def chart_geometry(verts, tris, sigma, rule, chart_uv, h, sel=None, tri_offsets=None, nthreads=0):
+    """Tangents x_u, x_v, area element |x_u x x_v| and outward unit normal of
+    the charts x = T + h H (section 3.1, eq. chart, u_vector, U_vector_2,
+    v_vector, v_vector_2, eq. da) at the chart nodes of the triangles ``sel``
+    (all if None), for the given h (index k * np + i over sel).  T and H are
+    the linear maps of eq. tparam and mkpseudovec (vertex pseudonormals of eq.
+    mkvertexpn); grad Phi comes from ``evaluate``; the normal is
+    -grad Phi / |grad Phi|, outward because Phi grows inward."""
+    verts = _f64(verts)
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    uv = _f64(chart_uv).reshape(-1, 2)
+    s = np.arange(len(tris)) if sel is None else np.asarray(sel, dtype=np.int64)
+    npn = len(uv)
+    Hv = pseudonormals(verts, tris)
+    t = tris[s]
+    P1, P2, P3 = verts[t[:, 0]][:, None], verts[t[:, 1]][:, None], verts[t[:, 2]][:, None]
+    H1, H2, H3 = Hv[t[:, 0]][:, None], Hv[t[:, 1]][:, None], Hv[t[:, 2]][:, None]
+    u, v = uv[None, :, 0:1], uv[None, :, 1:2]
+    T = P1 + u * (P2 - P1) + v * (P3 - P1)
+    H = H1 + u * (H2 - H1) + v * (H3 - H1)
+    hh = _f64(h).reshape(len(s), npn, 1)
+    x = T + hh * H
+    xm = None
+    if tri_offsets is not None:
+        mesh = np.searchsorted(np.asarray(tri_offsets), s, side="right") - 1
+        xm = np.repeat(mesh, npn).astype(np.int32)
+    _, g = evaluate(verts, tris, sigma, rule, x.reshape(-1, 3), tri_offsets=tri_offsets, x_mesh=xm,
+                    nthreads=nthreads)
+    g = g.reshape(len(s), npn, 3)
+    Tu, Tv, Hu, Hvv = P2 - P1, P3 - P1, H2 - H1, H3 - H1
+    den = np.sum(H * g, axis=-1, keepdims=True)
+    au, av = Tu + hh * Hu, Tv + hh * Hvv
+    hu = -np.sum(au * g, axis=-1, keepdims=True) / den
+    hv = -np.sum(av * g, axis=-1, keepdims=True) / den
+    xu, xv = au + hu * H, av + hv * H
+    da = np.linalg.norm(np.cross(xu, xv), axis=-1)
+    nrm = -g / np.linalg.norm(g, axis=-1, keepdims=True)
+    return xu.reshape(-1, 3), xv.reshape(-1, 3), da.reshape(-1), nrm.reshape(-1, 3)

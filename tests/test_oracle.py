@@ -402,3 +402,64 @@ def test_newton_no_root_is_never_converged():
     for tau in (1e-6, 1e-12):
         h, x, st, it = oracle.project(v, t, [sigma], dunavant6(), uv[:1], sel=[j], tau=tau)
         assert st[0] == 2 and it[0] <= 6 and abs(h[0]) > 0.75 * hmax
+
+
+# ------------------------------------------------------------- chart geometry
+def test_chart_geometry_tangents_match_finite_differences():
+    """x_u and x_v of eq. u_vector / v_vector against central differences of
+    the oracle's own Newton solution x(u +- d, v), x(u, v +- d): a dropped
+    term (h H_u), a sign or the dh/du quotient of eq. U_vector_2 would show."""
+    v, t = star_surface(6, lmax=6, var0=0.1, seed=3)
+    sig = 0.5 * triangle_diameters(v, t)
+    uv = np.array([[0.2, 0.3], [0.55, 0.15], [0.1, 0.7]])
+    sel = np.array([3, 40, 111])
+    h, x, st, _ = oracle.project(v, t, sig, dunavant6(), uv, tau=1e-14, sel=sel)
+    assert np.all(st == 0)
+    xu, xv, da, nrm = oracle.chart_geometry(v, t, sig, dunavant6(), uv, h, sel=sel)
+    d = 1e-4
+    for k, (du, dv) in enumerate(((d, 0.0), (0.0, d))):
+        up = oracle.project(v, t, sig, dunavant6(), uv + [du, dv], tau=1e-14, sel=sel)[1]
+        dn = oracle.project(v, t, sig, dunavant6(), uv - [du, dv], tau=1e-14, sel=sel)[1]
+        fd = (up - dn) / (2 * d)
+        an = xu if k == 0 else xv
+        err = np.linalg.norm(fd - an, axis=1) / np.linalg.norm(an, axis=1)
+        assert err.max() < 1e-6, err
+    # tangency, the normal's orientation and the area element's definition
+    assert np.abs(np.sum(xu * nrm, axis=1)).max() < 1e-10 * np.linalg.norm(xu, axis=1).max()
+    assert np.abs(np.sum(xv * nrm, axis=1)).max() < 1e-10 * np.linalg.norm(xv, axis=1).max()
+    assert np.allclose(np.linalg.norm(nrm, axis=1), 1.0)
+    c = v.mean(axis=0)
+    assert np.all(np.sum((x - c) * nrm, axis=1) > 0)             # outward on a star-shaped surface
+    assert np.allclose(da, np.linalg.norm(np.cross(xu, xv), axis=1))
+
+
+def test_chart_geometry_sphere_normals_and_area():
+    """On a fine icosphere the 1/2 level set is nearly a sphere: the normals
+    are nearly radial and the charts' areas (interpolatory weights of the
+    chart nodes times da) add up to nearly 4 pi r^2."""
+    v, t = icosphere(3)
+    sigma = 0.1
+    uv = chart_nodes(4)
+    h, x, st, _ = oracle.project(v, t, [sigma], dunavant6(), uv)
+    assert np.all(st == 0)
+    xu, xv, da, nrm = oracle.chart_geometry(v, t, [sigma], dunavant6(), uv, h)
+    r = np.linalg.norm(x, axis=1)
+    cosang = np.sum(x * nrm, axis=1) / r
+    assert cosang.min() > 0.999
+    w = simplex_weights(uv, 4)
+    area = np.sum(da.reshape(len(t), -1) * w[None, :])
+    rm = r.mean()
+    assert abs(area / (4 * np.pi * rm ** 2) - 1) < 5e-3
+
+
+def simplex_weights(uv, deg):
+    """Interpolatory quadrature weights of the nodes uv on the standard
+    simplex: exact for every monomial u^a v^b with a + b <= deg (moments
+    a! b! / (a + b + 2)!)."""
+    from math import factorial
+    rows, mom = [], []
+    for a in range(deg + 1):
+        for b in range(deg + 1 - a):
+            rows.append(uv[:, 0] ** a * uv[:, 1] ** b)
+            mom.append(factorial(a) * factorial(b) / factorial(a + b + 2))
+    return np.linalg.solve(np.array(rows), np.array(mom))
