@@ -217,6 +217,22 @@ int lss_project(lss_ctx *ctx, const double *chart_uv, int32_t np,
                 double *h, double *xout, int8_t *status, int8_t *iters,
                 unsigned flags);
 
+/* Chart geometry at the chart nodes of every triangle (section 3.1: eq. chart,
+ * u_vector, U_vector_2, v_vector, v_vector_2, eq. da), for distances h from
+ * lss_project (index j * np + i, the same chart_uv).  With x = T + h H the
+ * function evaluates grad Phi at x (as lss_eval, with the context's options)
+ * and writes per node:
+ *   xu, xv (N,3): x_u = T_u + h H_u + (dh/du) H with dh/du = -(T_u + h H_u) . grad Phi
+ *                 / (H . grad Phi), and likewise in v (T and H are linear on the
+ *                 triangle, so T_u = P2 - P1, H_u = H2 - H1, T_v = P3 - P1, H_v = H3 - H1);
+ *   da (N):       |x_u x x_v|, the area element per du dv of the standard simplex;
+ *   normal (N,3): the outward unit normal -grad Phi / |grad Phi| (Phi grows inward).
+ * N = ntris * np.  Any output may be NULL.  Nodes with H . grad Phi = 0 or a
+ * zero gradient get non-finite values.  Host or device arrays as for lss_project;
+ * the call returns when the outputs are written. */
+int lss_chart_geometry(lss_ctx *ctx, const double *chart_uv, int32_t np, const double *h, double *xu, double *xv,
+                       double *da, double *normal, unsigned flags);
+
 /* Autotuner: choose the tile width and, for LSS_FAR_FMM, the leaf capacity
  * and leaf shrink for the current source set, sigma and precision by timing
  * candidates on the caller's targets: cost = (build time) + eval_weight *

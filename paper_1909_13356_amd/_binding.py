@@ -21,7 +21,7 @@ PTR_DEVICE = 1
 # every entry point declared in include/lss.h
 EXPORTED_SYMBOLS = ["lss_create", "lss_destroy", "lss_last_error", "lss_synchronize",
                     "lss_set_sources", "lss_set_sigma", "lss_set_options", "lss_get_options",
-                    "lss_build", "lss_eval", "lss_project", "lss_autotune", "lss_get_stats"]
+                    "lss_build", "lss_eval", "lss_project", "lss_chart_geometry", "lss_autotune", "lss_get_stats"]
 
 _CODES = {1: "LSS_EINVAL", 2: "LSS_ENOMEM", 3: "LSS_EHIP", 4: "LSS_ESTATE", 5: "LSS_EORIENT"}
 
@@ -90,6 +90,7 @@ def load_library():
     L.lss_build.argtypes = [P]
     L.lss_eval.argtypes = [P, P, P, i64, P, P, u]
     L.lss_project.argtypes = [P, P, i32, P, P, P, P, u]
+    L.lss_chart_geometry.argtypes = [P, P, i32, P, P, P, P, P, u]
     L.lss_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
     L.lss_autotune.argtypes = [P, P, i64, u, ctypes.c_double, ctypes.c_char_p, ctypes.POINTER(Options)]
     _lib = L
@@ -266,3 +267,32 @@ class Context:
         pi, fi, ki = _ptr(it, np.int8)
         self._check(self._lib.lss_project(self._h, pu, npn, ph, px, ps, pi, fu))
         return h, x, st, it
+
+    def chart_geometry(self, chart_uv, h):
+        """Tangents x_u, x_v (N,3), area element da (N) and outward unit normal
+        (N,3) of the charts x = T + h H at the chart nodes (index j * np + i),
+        for distances h from project().  Device tensors in, device tensors out."""
+        npn = len(chart_uv)
+        N = self.ntris * npn
+        if _is_torch(h) and h.device.type == "cuda":
+            import torch
+            dev = h.device
+            uv = chart_uv if _is_torch(chart_uv) else torch.as_tensor(np.ascontiguousarray(chart_uv, np.float64), device=dev)
+            xu, xv = torch.empty((N, 3), dtype=torch.float64, device=dev), torch.empty((N, 3), dtype=torch.float64, device=dev)
+            da, nr = torch.empty(N, dtype=torch.float64, device=dev), torch.empty((N, 3), dtype=torch.float64, device=dev)
+        else:
+            uv = np.ascontiguousarray(chart_uv, np.float64)
+            h = np.ascontiguousarray(h, np.float64)
+            xu, xv, da, nr = np.empty((N, 3)), np.empty((N, 3)), np.empty(N), np.empty((N, 3))
+        if len(h) != N:
+            raise ValueError("h must have ntris * len(chart_uv) entries")
+        pu, fu, ku = _ptr(uv, np.float64)
+        ph, fh, kh = _ptr(h, np.float64)
+        if fu != fh:
+            raise ValueError("chart_uv and h must both be host arrays or both device tensors")
+        pxu, _, k1 = _ptr(xu, np.float64)
+        pxv, _, k2 = _ptr(xv, np.float64)
+        pda, _, k3 = _ptr(da, np.float64)
+        pnr, _, k4 = _ptr(nr, np.float64)
+        self._check(self._lib.lss_chart_geometry(self._h, pu, npn, ph, pxu, pxv, pda, pnr, fh))
+        return xu, xv, da, nr

@@ -332,6 +332,50 @@ void project(Ctx &c, const double *uv, int32_t np, double *h, double *xout, int8
     c.stats.newton_iters = cnt[3];
 }
 
+// Chart geometry at given chart distances (section 3.1, eq. u_vector to eq. da):
+// the chart points x = T + h H, one evaluation of grad Phi there, then the
+// tangents, area element and outward unit normal per node.
+void chart_geometry(Ctx &c, const double *uv, int32_t np, const double *h, double *xu, double *xv, double *da,
+                    double *nrm, unsigned flags) {
+    if (np <= 0) fail(LSS_EINVAL, "lss_chart_geometry: np must be >= 1");
+    if (!uv || !h) fail(LSS_EINVAL, "lss_chart_geometry: chart_uv and h must be non-null");
+    build(c);
+    const int64_t N = c.ntris * (int64_t)np;
+    if (N > (int64_t)INT32_MAX) fail(LSS_EINVAL, "lss_chart_geometry: ntris * np exceeds 2^31-1");
+    if (N == 0) return;
+    const bool dev = flags & LSS_PTR_DEVICE;
+    DBuf duv, dh, x, xm, phi, grad, oxu, oxv, oda, onr;
+    upload(c, duv, uv, sizeof(double) * 2 * np, flags);
+    const double *ph = h;
+    if (!dev) {
+        upload(c, dh, h, sizeof(double) * N, 0);
+        ph = dh.as<double>();
+    }
+    x.ensure(sizeof(double) * 3 * N);
+    if (c.nmesh > 1) xm.ensure(sizeof(int32_t) * N);
+    launch_chart_points(c, duv.as<double>(), np, N, ph, x.as<double>(), c.nmesh > 1 ? xm.as<int32_t>() : nullptr);
+    phi.ensure(sizeof(double) * N);
+    grad.ensure(sizeof(double) * 3 * N);
+    eval(c, x.as<double>(), c.nmesh > 1 ? xm.as<int32_t>() : nullptr, N, phi.as<double>(), grad.as<double>(),
+         LSS_PTR_DEVICE);
+    double *qxu = xu, *qxv = xv, *qda = da, *qnr = nrm;
+    if (!dev) {
+        if (xu) { oxu.ensure(sizeof(double) * 3 * N); qxu = oxu.as<double>(); }
+        if (xv) { oxv.ensure(sizeof(double) * 3 * N); qxv = oxv.as<double>(); }
+        if (da) { oda.ensure(sizeof(double) * N); qda = oda.as<double>(); }
+        if (nrm) { onr.ensure(sizeof(double) * 3 * N); qnr = onr.as<double>(); }
+    }
+    launch_chart_geometry(c, duv.as<double>(), np, N, ph, grad.as<double>(), qxu, qxv, qda, qnr);
+    if (!dev) {
+        if (xu) LSS_HIP(hipMemcpyAsync(xu, qxu, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, c.stream));
+        if (xv) LSS_HIP(hipMemcpyAsync(xv, qxv, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, c.stream));
+        if (da) LSS_HIP(hipMemcpyAsync(da, qda, sizeof(double) * N, hipMemcpyDeviceToHost, c.stream));
+        if (nrm) LSS_HIP(hipMemcpyAsync(nrm, qnr, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, c.stream));
+    }
+    // the temporaries are freed on return: wait for the kernels that use them
+    LSS_HIP(hipStreamSynchronize(c.stream));
+}
+
 
 // ------------------------------------------------------------- autotuner
 std::string tune_key(const Ctx &c) {
@@ -650,6 +694,11 @@ int lss_eval(lss_ctx *ctx, const double *x, const int32_t *x_mesh, int64_t n, do
 int lss_project(lss_ctx *ctx, const double *chart_uv, int32_t np, double *h, double *xout, int8_t *status,
                 int8_t *iters, unsigned flags) {
     return lss::guarded(ctx, [&](Ctx &c) { lss::project(c, chart_uv, np, h, xout, status, iters, flags); });
+}
+
+int lss_chart_geometry(lss_ctx *ctx, const double *chart_uv, int32_t np, const double *h, double *xu, double *xv,
+                       double *da, double *normal, unsigned flags) {
+    return lss::guarded(ctx, [&](Ctx &c) { lss::chart_geometry(c, chart_uv, np, h, xu, xv, da, normal, flags); });
 }
 
 int lss_autotune(lss_ctx *ctx, const double *x, int64_t n, unsigned flags, double eval_weight,

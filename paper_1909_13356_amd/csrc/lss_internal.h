@@ -262,6 +262,10 @@ void launch_p2p_direct(Ctx &c, int64_t n, const int32_t *n_dev, const double *tx
 
 // Newton (lss_kernels.hip)
 void launch_chart_init(Ctx &c, const double *chart_uv, int32_t np, int64_t N);
+void launch_chart_points(Ctx &c, const double *uv, int32_t np, int64_t N, const double *h, double *x,
+                         int32_t *xmesh);
+void launch_chart_geometry(Ctx &c, const double *uv, int32_t np, int64_t N, const double *h, const double *grad,
+                           double *xu, double *xv, double *da, double *nrm);
 void launch_newton_targets(Ctx &c, int64_t N);
 void launch_newton_update(Ctx &c, int64_t N, double tau, const double *phi, const double *grad);
 void launch_compact_active(Ctx &c, int64_t N);

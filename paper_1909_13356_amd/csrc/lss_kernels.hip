@@ -710,3 +710,95 @@ void launch_newton_output(Ctx &c, int64_t N, double *h, double *xout, int8_t *st
 }
 
 }  // namespace lss
+
+// ------------------------------------------------------- chart geometry
+namespace lss {
+namespace {
+
+// chart point x = T + h H of node q (eq. chart) and its mesh (batches)
+__global__ void k_chart_points(int64_t N, const double *__restrict__ verts, const int32_t *__restrict__ tris,
+                               const double *__restrict__ vH, const double *__restrict__ uv, int32_t np,
+                               const int64_t *__restrict__ tri_off, int32_t nmesh, const double *__restrict__ h,
+                               double *x, int32_t *xmesh) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N) return;
+    double T[3], H[3];
+    int64_t j;
+    chart_TH(verts, tris, vH, uv, np, q, T, H, j);
+    const double hq = h[q];
+    for (int c = 0; c < 3; ++c) x[3 * q + c] = T[c] + hq * H[c];
+    if (xmesh) xmesh[q] = mesh_of_tri(tri_off, nmesh, j);
+}
+
+// Tangents, area element and unit normal of the chart x = T + h H at node q
+// (section 3.1, eq. u_vector, U_vector_2, v_vector, v_vector_2, eq. da):
+// T and H are linear in (u, v) on the triangle (eq. tparam, mkpseudovec), so
+// T_u = P2 - P1, H_u = H2 - H1 (likewise in v); dh/du follows from x_u being
+// tangent to the level set, i.e. orthogonal to grad Phi; the outward unit
+// normal is -grad Phi / |grad Phi| (Phi grows inward).  Any output may be null.
+__global__ void k_chart_geometry(int64_t N, const double *__restrict__ verts, const int32_t *__restrict__ tris,
+                                 const double *__restrict__ vH, const double *__restrict__ uv, int32_t np,
+                                 const double *__restrict__ h, const double *__restrict__ grad, double *xu,
+                                 double *xv, double *da, double *nrm) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N) return;
+    double T[3], H[3];
+    int64_t j;
+    chart_TH(verts, tris, vH, uv, np, q, T, H, j);
+    const int32_t *t = tris + 3 * j;
+    double Tu[3], Tv[3], Hu[3], Hv[3], g[3];
+    for (int c = 0; c < 3; ++c) {
+        const double p1 = verts[3 * (int64_t)t[0] + c];
+        const double h1 = vH[3 * (int64_t)t[0] + c];
+        Tu[c] = verts[3 * (int64_t)t[1] + c] - p1;
+        Tv[c] = verts[3 * (int64_t)t[2] + c] - p1;
+        Hu[c] = vH[3 * (int64_t)t[1] + c] - h1;
+        Hv[c] = vH[3 * (int64_t)t[2] + c] - h1;
+        g[c] = grad[3 * q + c];
+    }
+    const double hq = h[q];
+    double au[3], av[3];                      // T_u + h H_u, T_v + h H_v
+    for (int c = 0; c < 3; ++c) {
+        au[c] = Tu[c] + hq * Hu[c];
+        av[c] = Tv[c] + hq * Hv[c];
+    }
+    const double den = H[0] * g[0] + H[1] * g[1] + H[2] * g[2];
+    const double hu = -(au[0] * g[0] + au[1] * g[1] + au[2] * g[2]) / den;
+    const double hv = -(av[0] * g[0] + av[1] * g[1] + av[2] * g[2]) / den;
+    double a[3], b[3];
+    for (int c = 0; c < 3; ++c) {
+        a[c] = au[c] + hu * H[c];
+        b[c] = av[c] + hv * H[c];
+    }
+    if (xu)
+        for (int c = 0; c < 3; ++c) xu[3 * q + c] = a[c];
+    if (xv)
+        for (int c = 0; c < 3; ++c) xv[3 * q + c] = b[c];
+    if (da) {
+        const double cx = a[1] * b[2] - a[2] * b[1], cy = a[2] * b[0] - a[0] * b[2], cz = a[0] * b[1] - a[1] * b[0];
+        da[q] = sqrt(cx * cx + cy * cy + cz * cz);
+    }
+    if (nrm) {
+        const double ig = -1.0 / sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+        for (int c = 0; c < 3; ++c) nrm[3 * q + c] = g[c] * ig;
+    }
+}
+
+}  // namespace
+
+void launch_chart_points(Ctx &c, const double *uv, int32_t np, int64_t N, const double *h, double *x,
+                         int32_t *xmesh) {
+    hipLaunchKernelGGL(k_chart_points, dim3(grid_for(N)), dim3(kBlk), 0, c.stream, N, c.verts.as<double>(),
+                       c.tris.as<int32_t>(), c.vH.as<double>(), uv, np, c.tri_off.as<int64_t>(), c.nmesh, h, x,
+                       xmesh);
+    LSS_CHECK_LAUNCH("k_chart_points");
+}
+
+void launch_chart_geometry(Ctx &c, const double *uv, int32_t np, int64_t N, const double *h, const double *grad,
+                           double *xu, double *xv, double *da, double *nrm) {
+    hipLaunchKernelGGL(k_chart_geometry, dim3(grid_for(N)), dim3(kBlk), 0, c.stream, N, c.verts.as<double>(),
+                       c.tris.as<int32_t>(), c.vH.as<double>(), uv, np, h, grad, xu, xv, da, nrm);
+    LSS_CHECK_LAUNCH("k_chart_geometry");
+}
+
+}  // namespace lss

@@ -1,0 +1,111 @@
+"""GPU parity of the chart geometry (section 3.1: tangents x_u, x_v of eq.
+u_vector / v_vector, area element of eq. da, outward unit normal) against
+the CPU oracle, through the C ABI, at the distances h of the GPU projection;
+plus the paper's quality metrics on a near-sphere: Gauss-flux
+water-tightness eps_0 (Gauss's law) and the radius statistics of the chart
+nodes."""
+import sys
+from math import factorial
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1909_13356_amd as lss
+from workloads import dunavant6, chart_nodes, icosphere, star_surface, triangle_diameters
+
+pytestmark = pytest.mark.gpu
+TOL = {lss.FP64: 1e-11, lss.MIXED: 1e-6}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def ctx(v, t, sigma, prec, far):
+    c = lss.Context()
+    c.set_sources(v, t, dunavant6())
+    c.set_sigma(np.atleast_1d(np.asarray(sigma, float)))
+    c.set_options(precision=prec, far_field=far)
+    return c
+
+
+def rel(a, b):
+    return np.max(np.linalg.norm(np.atleast_2d((a - b).T).T, axis=-1) if a.ndim > 1 else np.abs(a - b)) / \
+        np.max(np.linalg.norm(b, axis=-1) if b.ndim > 1 else np.abs(b))
+
+
+def simplex_weights(uv, deg):
+    """Interpolatory weights of the nodes uv on the standard simplex (exact for
+    u^a v^b, a + b <= deg)."""
+    rows, mom = [], []
+    for a in range(deg + 1):
+        for b in range(deg + 1 - a):
+            rows.append(uv[:, 0] ** a * uv[:, 1] ** b)
+            mom.append(factorial(a) * factorial(b) / factorial(a + b + 2))
+    return np.linalg.solve(np.array(rows), np.array(mom))
+
+
+@pytest.mark.parametrize("far", [lss.FAR_DIRECT, lss.FAR_FMM])
+@pytest.mark.parametrize("prec", [lss.FP64, lss.MIXED])
+def test_chart_geometry_vs_oracle(prec, far):
+    v, t = star_surface(10, lmax=8, var0=0.1, seed=9)
+    sig = 0.5 * triangle_diameters(v, t)
+    uv = chart_nodes(3)
+    say("case: chart geometry, %d tri x %d nodes, precision %d, far field %d" % (len(t), len(uv), prec, far))
+    c = ctx(v, t, sig, prec, far)
+    h, x, st, it = c.project(uv)
+    assert np.all(st == lss.NODE_CONVERGED)
+    xu, xv, da, nr = c.chart_geometry(uv, h)
+    sel = np.arange(0, len(t), 37)
+    idx = (sel[:, None] * len(uv) + np.arange(len(uv))[None]).ravel()
+    oxu, oxv, oda, onr = oracle.chart_geometry(v, t, sig, dunavant6(), uv, h[idx], sel=sel)
+    e = [rel(xu[idx], oxu), rel(xv[idx], oxv), rel(da[idx], oda), rel(nr[idx], onr)]
+    say("  x_u %.2e x_v %.2e da %.2e n %.2e" % tuple(e))
+    assert max(e) <= TOL[prec]
+    assert np.all(np.isfinite(xu)) and np.all(np.isfinite(da)) and np.all(np.isfinite(nr))
+
+
+def test_chart_geometry_device_tensors_match_host():
+    import torch
+    v, t = star_surface(8, lmax=6, var0=0.1, seed=4)
+    sig = 0.5 * triangle_diameters(v, t)
+    uv = chart_nodes(2)
+    c = ctx(v, t, sig, lss.FP64, lss.FAR_FMM)
+    h, x, st, it = c.project(uv, device=True)
+    dxu, dxv, dda, dnr = c.chart_geometry(torch.as_tensor(uv, device="cuda"), h)
+    torch.cuda.synchronize()
+    hxu, hxv, hda, hnr = c.chart_geometry(uv, h.cpu().numpy())
+    assert np.array_equal(dxu.cpu().numpy(), hxu) and np.array_equal(dda.cpu().numpy(), hda)
+    assert np.array_equal(dxv.cpu().numpy(), hxv) and np.array_equal(dnr.cpu().numpy(), hnr)
+
+
+@pytest.mark.parametrize("prec", [lss.FP64, lss.MIXED])
+def test_gauss_flux_and_sphere_statistics(prec):
+    """Quality metrics of the paper's experiments on a near-sphere: eps_0 =
+    1 + integral over the charts of n . grad_x 1/(4 pi |x0 - x|) with x0 at
+    the centre (0 for a closed surface by Gauss's law), and mean / std of the
+    chart nodes' radii; the GPU's numbers against the oracle's."""
+    v, t = icosphere(3)
+    sigma = 0.1
+    uv = chart_nodes(4)
+    w = simplex_weights(uv, 4)
+    c = ctx(v, t, [sigma], prec, lss.FAR_FMM)
+    h, x, st, it = c.project(uv)
+    assert np.all(st == lss.NODE_CONVERGED)
+    xu, xv, da, nr = c.chart_geometry(uv, h)
+    oxu, oxv, oda, onr = oracle.chart_geometry(v, t, [sigma], dunavant6(), uv, h)
+
+    def eps0(x, da, nr):
+        d = -x                                           # x0 - x, x0 = 0
+        r = np.linalg.norm(d, axis=1)
+        f = np.sum(nr * d, axis=1) / (4 * np.pi * r ** 3)
+        return 1.0 + np.sum((f * da).reshape(len(t), -1) * w[None, :])
+
+    eg, eo = eps0(x, da, nr), eps0(x, oda, onr)
+    r = np.linalg.norm(x, axis=1)
+    say("case: sphere metrics, precision %d: eps0 GPU %.3e oracle %.3e, <|x|> %.6f std %.2e" % (
+        prec, eg, eo, r.mean(), r.std()))
+    assert abs(eg - eo) <= (1e-9 if prec == lss.FP64 else 1e-5)
+    assert abs(eg) < 1e-3
