@@ -147,10 +147,20 @@ def time_newton(lss, torch, cfg, prec, steps, warmup):
         iters = max(iters, stt["newton_iters"])
         gms += stt["pair_kernel_ms"]
     conv = float((st == 0).sum().item()) / n_nodes
+    # chart geometry (tangents, area element, normal) at the converged charts:
+    # one evaluation of grad Phi at x = T + h H plus the per-node kernel
+    c.chart_geometry(uv, h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        c.chart_geometry(uv, h)
+    torch.cuda.synchronize()
+    eg = time.perf_counter() - t0
     c.close()
     return {"chart_nodes_per_s": n_nodes * steps / el, "target_evals_per_s": evals / el,
             "ms_per_step": 1e3 * el / steps, "newton_graph_ms": gms / steps, "iterations": iters,
-            "evals_per_node": evals / steps / n_nodes, "converged_frac": conv}
+            "evals_per_node": evals / steps / n_nodes, "converged_frac": conv,
+            "geometry_nodes_per_s": n_nodes * steps / eg, "geometry_ms": 1e3 * eg / steps}
 
 
 def time_batch(lss, torch, b, uv, prec, per_surface):
