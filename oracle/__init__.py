@@ -166,3 +166,41 @@ def chart_geometry(verts, tris, sigma, rule, chart_uv, h, sel=None, tri_offsets=
     da = np.linalg.norm(np.cross(xu, xv), axis=-1)
     nrm = -g / np.linalg.norm(g, axis=-1, keepdims=True)
     return xu.reshape(-1, 3), xv.reshape(-1, 3), da.reshape(-1), nrm.reshape(-1, 3)
+
+
+def koornwinder(uv, p):
+    """Koornwinder (Dubiner) orthogonal basis of the polynomials of total
+    degree <= p on the standard simplex (section 3.3), at points uv (n, 2):
+    (n, (p+1)(p+2)/2), columns ordered by (m, n), m + n <= p, with
+    K_mn(u, v) = P_m((2u + v - 1)/(1 - v)) (1 - v)^m P_n^(2m+1, 0)(2v - 1)
+    (Legendre P_m, Jacobi P_n^(a, b); points with v < 1)."""
+    from scipy.special import eval_jacobi, eval_legendre
+    uv = _f64(uv).reshape(-1, 2)
+    u, v = uv[:, 0], uv[:, 1]
+    t = 1.0 - v
+    cols = []
+    for m in range(p + 1):
+        lm = eval_legendre(m, (2 * u + v - 1) / t) * t ** m
+        for n in range(p + 1 - m):
+            cols.append(lm * eval_jacobi(n, 2 * m + 1, 0, 2 * v - 1))
+    return np.stack(cols, axis=1)
+
+
+def chart_interp(chart_uv, f, eval_uv):
+    """Values at eval_uv of every triangle's degree-p polynomial interpolant
+    of the node data f ((ntris * np,) or (ntris * np, ncomp), index j * np + i)
+    given at chart_uv, np = (p+1)(p+2)/2 (section 3.3): Koornwinder
+    coefficients c = V^-1 f per triangle, values E c."""
+    uv = _f64(chart_uv).reshape(-1, 2)
+    npn = len(uv)
+    p = 0
+    while (p + 1) * (p + 2) // 2 < npn:
+        p += 1
+    assert (p + 1) * (p + 2) // 2 == npn
+    f = _f64(f)
+    flat = f.ndim == 1
+    F = f.reshape(-1, npn, 1 if flat else f.shape[1])
+    ntris, ncomp = F.shape[0], F.shape[2]
+    coef = np.linalg.solve(koornwinder(uv, p), F.transpose(1, 0, 2).reshape(npn, -1))
+    out = (koornwinder(eval_uv, p) @ coef).reshape(-1, ntris, ncomp).transpose(1, 0, 2)
+    return out.reshape(-1) if flat else out.reshape(-1, ncomp)

@@ -463,3 +463,49 @@ def simplex_weights(uv, deg):
             rows.append(uv[:, 0] ** a * uv[:, 1] ** b)
             mom.append(factorial(a) * factorial(b) / factorial(a + b + 2))
     return np.linalg.solve(np.array(rows), np.array(mom))
+
+
+# --------------------------------------------------- Koornwinder interpolation
+def test_koornwinder_basis_is_orthogonal_on_the_simplex():
+    """Gram matrix of the basis by a collapsed Gauss-Legendre rule exact to
+    degree 2p: diagonal only (a wrong Jacobi parameter or homogenisation
+    would couple the columns)."""
+    p = 6
+    g, w = np.polynomial.legendre.leggauss(p + 2)
+    a, b = (g + 1) / 2, (g + 1) / 2
+    A, B = np.meshgrid(a, b, indexing="ij")
+    WA, WB = np.meshgrid(w / 2, w / 2, indexing="ij")
+    v = B.ravel()
+    u = A.ravel() * (1 - v)
+    wt = (WA * WB).ravel() * (1 - v)                          # du dv = (1 - v) da db
+    K = oracle.koornwinder(np.stack([u, v], 1), p)
+    G = K.T @ (wt[:, None] * K)
+    off = G - np.diag(np.diag(G))
+    assert np.abs(off).max() < 1e-13 * np.abs(np.diag(G)).max()
+    assert np.isclose(G[0, 0], 0.5)                           # K_00 = 1: the simplex area
+
+
+@pytest.mark.parametrize("p", [2, 4, 8])
+def test_chart_interp_reproduces_polynomials(p):
+    rng = np.random.default_rng(p)
+    uv = chart_nodes(p)
+    ev = rng.dirichlet([1, 1, 1], 50)[:, :2]
+    mons = [(a, b) for a in range(p + 1) for b in range(p + 1 - a)]
+    ntris = 3
+    co = rng.standard_normal((ntris, len(mons), 2))
+    q = lambda pts, j, c: sum(co[j, k, c] * pts[:, 0] ** a * pts[:, 1] ** b for k, (a, b) in enumerate(mons))
+    f = np.stack([np.stack([q(uv, j, c) for c in range(2)], 1) for j in range(ntris)]).reshape(-1, 2)
+    want = np.stack([np.stack([q(ev, j, c) for c in range(2)], 1) for j in range(ntris)]).reshape(-1, 2)
+    got = oracle.chart_interp(uv, f, ev)
+    assert np.abs(got - want).max() < 1e-11 * np.abs(want).max()
+
+
+def test_chart_interp_converges_on_a_smooth_function():
+    rng = np.random.default_rng(1)
+    ev = rng.dirichlet([1, 1, 1], 200)[:, :2]
+    exact = np.exp(ev[:, 0] + 2 * ev[:, 1])
+    errs = []
+    for p in (2, 4, 8):
+        uv = chart_nodes(p)
+        errs.append(np.abs(oracle.chart_interp(uv, np.exp(uv[:, 0] + 2 * uv[:, 1]), ev) - exact).max())
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-5
