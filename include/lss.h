@@ -233,6 +233,21 @@ int lss_project(lss_ctx *ctx, const double *chart_uv, int32_t np,
 int lss_chart_geometry(lss_ctx *ctx, const double *chart_uv, int32_t np, const double *h, double *xu, double *xv,
                        double *da, double *normal, unsigned flags);
 
+/* Interpolation of chart data between the chart nodes (section 3.3: a chart
+ * is a polynomial of total degree p on the standard simplex, represented in
+ * the orthogonal Koornwinder basis through its values at the p-th order
+ * nodes).  chart_uv (np,2) are the nodes, np = (p+1)(p+2)/2, unisolvent for
+ * degree p (else LSS_EINVAL); f (ntris*np, ncomp) the data at the nodes of
+ * every triangle (index j * np + i, e.g. x or h from lss_project); eval_uv
+ * (ne,2) points of the simplex; out (ntris*ne, ncomp) receives the value of
+ * every triangle's degree-p interpolant at them (index j * ne + e).  The
+ * interpolation matrix (ne x np) is formed on the host in FP64 by LU with
+ * partial pivoting; one kernel applies it to all triangles.  Needs sources
+ * (LSS_ESTATE otherwise), not sigma.  Host or device arrays as for
+ * lss_project; returns when out is written. */
+int lss_chart_interp(lss_ctx *ctx, const double *chart_uv, int32_t np, const double *f, int32_t ncomp,
+                     const double *eval_uv, int32_t ne, double *out, unsigned flags);
+
 /* Autotuner: choose the tile width and, for LSS_FAR_FMM, the leaf capacity
  * and leaf shrink for the current source set, sigma and precision by timing
  * candidates on the caller's targets: cost = (build time) + eval_weight *

@@ -21,7 +21,8 @@ PTR_DEVICE = 1
 # every entry point declared in include/lss.h
 EXPORTED_SYMBOLS = ["lss_create", "lss_destroy", "lss_last_error", "lss_synchronize",
                     "lss_set_sources", "lss_set_sigma", "lss_set_options", "lss_get_options",
-                    "lss_build", "lss_eval", "lss_project", "lss_chart_geometry", "lss_autotune", "lss_get_stats"]
+                    "lss_build", "lss_eval", "lss_project", "lss_chart_geometry", "lss_chart_interp",
+                    "lss_autotune", "lss_get_stats"]
 
 _CODES = {1: "LSS_EINVAL", 2: "LSS_ENOMEM", 3: "LSS_EHIP", 4: "LSS_ESTATE", 5: "LSS_EORIENT"}
 
@@ -91,6 +92,7 @@ def load_library():
     L.lss_eval.argtypes = [P, P, P, i64, P, P, u]
     L.lss_project.argtypes = [P, P, i32, P, P, P, P, u]
     L.lss_chart_geometry.argtypes = [P, P, i32, P, P, P, P, P, u]
+    L.lss_chart_interp.argtypes = [P, P, i32, P, i32, P, i32, P, u]
     L.lss_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
     L.lss_autotune.argtypes = [P, P, i64, u, ctypes.c_double, ctypes.c_char_p, ctypes.POINTER(Options)]
     _lib = L
@@ -296,3 +298,31 @@ class Context:
         pnr, _, k4 = _ptr(nr, np.float64)
         self._check(self._lib.lss_chart_geometry(self._h, pu, npn, ph, pxu, pxv, pda, pnr, fh))
         return xu, xv, da, nr
+
+    def chart_interp(self, chart_uv, f, eval_uv):
+        """Values at eval_uv (ne,2) of every triangle's polynomial interpolant
+        of the node data f (ntris*np,) or (ntris*np, ncomp) given at chart_uv
+        (np,2): returns (ntris*ne,) or (ntris*ne, ncomp), index j * ne + e.
+        Device tensors in (all three), device tensor out."""
+        npn, ne = len(chart_uv), len(eval_uv)
+        flat = (f.ndim == 1)
+        ncomp = 1 if flat else f.shape[1]
+        if len(f) != self.ntris * npn:
+            raise ValueError("f must have ntris * len(chart_uv) rows")
+        shape = (self.ntris * ne,) if flat else (self.ntris * ne, ncomp)
+        if _is_torch(f) and f.device.type == "cuda":
+            import torch
+            out = torch.empty(shape, dtype=torch.float64, device=f.device)
+        else:
+            f = np.ascontiguousarray(f, np.float64)
+            chart_uv = np.ascontiguousarray(chart_uv, np.float64)
+            eval_uv = np.ascontiguousarray(eval_uv, np.float64)
+            out = np.empty(shape)
+        pu, fu, k1 = _ptr(chart_uv, np.float64)
+        pe, fe, k2 = _ptr(eval_uv, np.float64)
+        pf, ff, k3 = _ptr(f, np.float64)
+        po, fo, k4 = _ptr(out, np.float64)
+        if not (fu == fe == ff == fo):
+            raise ValueError("chart_uv, f and eval_uv must all be host arrays or all device tensors")
+        self._check(self._lib.lss_chart_interp(self._h, pu, npn, pf, ncomp, pe, ne, po, ff))
+        return out

@@ -701,6 +701,11 @@ int lss_chart_geometry(lss_ctx *ctx, const double *chart_uv, int32_t np, const d
     return lss::guarded(ctx, [&](Ctx &c) { lss::chart_geometry(c, chart_uv, np, h, xu, xv, da, normal, flags); });
 }
 
+int lss_chart_interp(lss_ctx *ctx, const double *chart_uv, int32_t np, const double *f, int32_t ncomp,
+                     const double *eval_uv, int32_t ne, double *out, unsigned flags) {
+    return lss::guarded(ctx, [&](Ctx &c) { lss::chart_interp(c, chart_uv, np, f, ncomp, eval_uv, ne, out, flags); });
+}
+
 int lss_autotune(lss_ctx *ctx, const double *x, int64_t n, unsigned flags, double eval_weight,
                  const char *cache_path, lss_options *out) {
     return lss::guarded(ctx, [&](Ctx &c) { lss::autotune(c, x, n, flags, eval_weight, cache_path, out); });

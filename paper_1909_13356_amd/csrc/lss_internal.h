@@ -266,6 +266,8 @@ void launch_chart_points(Ctx &c, const double *uv, int32_t np, int64_t N, const 
                          int32_t *xmesh);
 void launch_chart_geometry(Ctx &c, const double *uv, int32_t np, int64_t N, const double *h, const double *grad,
                            double *xu, double *xv, double *da, double *nrm);
+void chart_interp(Ctx &c, const double *chart_uv, int32_t np, const double *f, int32_t ncomp, const double *eval_uv,
+                  int32_t ne, double *out, unsigned flags);
 void launch_newton_targets(Ctx &c, int64_t N);
 void launch_newton_update(Ctx &c, int64_t N, double tau, const double *phi, const double *grad);
 void launch_compact_active(Ctx &c, int64_t N);

@@ -109,3 +109,43 @@ def test_gauss_flux_and_sphere_statistics(prec):
         prec, eg, eo, r.mean(), r.std()))
     assert abs(eg - eo) <= (1e-9 if prec == lss.FP64 else 1e-5)
     assert abs(eg) < 1e-3
+
+
+@pytest.mark.parametrize("p", [4, 8])
+def test_chart_interp_vs_oracle_and_newton(p):
+    """Degree-p interpolation of the projected chart points (section 3.3):
+    against the oracle's interpolation of the same node values, and against
+    direct Newton projections at the evaluation points (the high-order
+    approximation of the surface)."""
+    v, t = star_surface(8, lmax=6, var0=0.1, seed=4)
+    sig = 0.5 * triangle_diameters(v, t)
+    uv = chart_nodes(p)
+    rng = np.random.default_rng(3)
+    ev = rng.dirichlet([2, 2, 2], 12)[:, :2]
+    c = ctx(v, t, sig, lss.FP64, lss.FAR_FMM)
+    h, x, st, it = c.project(uv)
+    xi = c.chart_interp(uv, x, ev)
+    hi = c.chart_interp(uv, h, ev)
+    e1 = np.abs(xi - oracle.chart_interp(uv, x, ev)).max() / np.abs(x).max()
+    e2 = np.abs(hi - oracle.chart_interp(uv, h, ev)).max() / np.abs(h).max()
+    sel = np.arange(0, len(t), 97)
+    _, xn, stn, _ = oracle.project(v, t, sig, dunavant6(), ev, sel=sel)
+    idx = (sel[:, None] * len(ev) + np.arange(len(ev))[None]).ravel()
+    gap = np.max(np.linalg.norm(xi[idx] - xn, axis=1) / np.repeat(sig[sel], len(ev)))
+    say("case: chart interpolation p %d: vs oracle x %.2e h %.2e; |interpolant - Newton| / sigma max %.2e" % (
+        p, e1, e2, gap))
+    assert e1 < 1e-11 and e2 < 1e-11
+    assert np.all(stn == lss.NODE_CONVERGED)
+    assert gap < (1e-3 if p == 4 else 1e-6)
+
+
+def test_chart_interp_errors():
+    v, t = star_surface(4, lmax=4, var0=0.1, seed=2)
+    c = lss.Context()
+    c.set_sources(v, t, dunavant6())
+    uv = chart_nodes(2)
+    with pytest.raises(lss.LssError):
+        c.chart_interp(uv[:5], np.zeros(len(t) * 5), uv)          # 5 is not (p+1)(p+2)/2
+    bad = np.array([[0.1, 0.1], [0.2, 0.2], [0.3, 0.3], [0.4, 0.4], [0.5, 0.4], [0.1, 0.2]])
+    with pytest.raises(lss.LssError):
+        c.chart_interp(bad, np.zeros(len(t) * 6), uv)             # four nodes on one line: not unisolvent
