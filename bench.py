@@ -156,11 +156,23 @@ def time_newton(lss, torch, cfg, prec, steps, warmup):
         c.chart_geometry(uv, h)
     torch.cuda.synchronize()
     eg = time.perf_counter() - t0
+    # degree-8 interpolation of the chart points to 66 new points per triangle
+    # (the order-10 lattice), section 3.3
+    from workloads import chart_nodes
+    ev = torch.as_tensor(chart_nodes(10), device=dev)
+    c.chart_interp(uv, x, ev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        c.chart_interp(uv, x, ev)
+    torch.cuda.synchronize()
+    ei = time.perf_counter() - t0
     c.close()
     return {"chart_nodes_per_s": n_nodes * steps / el, "target_evals_per_s": evals / el,
             "ms_per_step": 1e3 * el / steps, "newton_graph_ms": gms / steps, "iterations": iters,
             "evals_per_node": evals / steps / n_nodes, "converged_frac": conv,
-            "geometry_nodes_per_s": n_nodes * steps / eg, "geometry_ms": 1e3 * eg / steps}
+            "geometry_nodes_per_s": n_nodes * steps / eg, "geometry_ms": 1e3 * eg / steps,
+            "interp_points_per_s": len(cfg["tris"]) * 66 * steps / ei, "interp_ms": 1e3 * ei / steps}
 
 
 def time_batch(lss, torch, b, uv, prec, per_surface):

@@ -45,18 +45,56 @@ void koornwinder(double u, double v, int p, double *out) {
     }
 }
 
-__global__ void k_chart_interp(int64_t ntris, int32_t np, int32_t ne, int32_t ncomp, const double *__restrict__ I,
+// one thread per (triangle j, point e); IT is the interpolation matrix
+// stored node-major (IT[i * ne + e]), so the threads of a wave, which hold
+// consecutive points, read consecutive entries
+__global__ void k_chart_interp(int64_t ntris, int32_t np, int32_t ne, int32_t ncomp, const double *__restrict__ IT,
                                const double *__restrict__ f, double *out) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= ntris * ne) return;
     const int64_t j = q / ne;
     const int32_t e = (int32_t)(q - j * ne);
-    const double *row = I + (int64_t)e * np;
     const double *fj = f + j * np * ncomp;
     for (int32_t c = 0; c < ncomp; ++c) {
         double acc = 0.0;
-        for (int32_t i = 0; i < np; ++i) acc = fma(row[i], fj[(int64_t)i * ncomp + c], acc);
+        for (int32_t i = 0; i < np; ++i) acc = fma(IT[(int64_t)i * ne + e], fj[(int64_t)i * ncomp + c], acc);
         out[q * ncomp + c] = acc;
+    }
+}
+
+// Same product with the interpolation matrix staged once per workgroup in
+// LDS (when it fits) and a grid-stride loop over (triangle, point), three
+// independent sums for three-component data.
+__global__ __launch_bounds__(256) void k_chart_interp_lds(int64_t ntris, int32_t np, int32_t ne, int32_t ncomp,
+                                                          const double *__restrict__ IT, const double *__restrict__ f,
+                                                          double *out) {
+    extern __shared__ double sIT[];
+    for (int k = threadIdx.x; k < np * ne; k += blockDim.x) sIT[k] = IT[k];
+    __syncthreads();
+    const int64_t n = ntris * ne;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = q / ne;
+        const int32_t e = (int32_t)(q - j * ne);
+        const double *fj = f + j * np * ncomp;
+        if (ncomp == 3) {
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll 5
+            for (int32_t i = 0; i < np; ++i) {
+                const double w = sIT[i * ne + e];
+                a0 = fma(w, fj[3 * i], a0);
+                a1 = fma(w, fj[3 * i + 1], a1);
+                a2 = fma(w, fj[3 * i + 2], a2);
+            }
+            out[3 * q] = a0;
+            out[3 * q + 1] = a1;
+            out[3 * q + 2] = a2;
+        } else {
+            for (int32_t c = 0; c < ncomp; ++c) {
+                double acc = 0.0;
+                for (int32_t i = 0; i < np; ++i) acc = fma(sIT[i * ne + e], fj[(int64_t)i * ncomp + c], acc);
+                out[q * ncomp + c] = acc;
+            }
+        }
     }
 }
 
@@ -104,12 +142,12 @@ void chart_interp(Ctx &c, const double *chart_uv, int32_t np, const double *f, i
             for (int e = 0; e < ne; ++e) B[(size_t)r * ne + e] -= m * B[(size_t)col * ne + e];
         }
     }
-    std::vector<double> I((size_t)ne * np);                                    // I[e][i] = X[i][e]
+    std::vector<double> I((size_t)np * ne);                                    // I^T, node-major: I[i][e]
     for (int e = 0; e < ne; ++e)
         for (int r = np - 1; r >= 0; --r) {
             double s = B[(size_t)r * ne + e];
-            for (int k = r + 1; k < np; ++k) s -= A[(size_t)r * np + k] * I[(size_t)e * np + k];
-            I[(size_t)e * np + r] = s / A[(size_t)r * np + r];
+            for (int k = r + 1; k < np; ++k) s -= A[(size_t)r * np + k] * I[(size_t)k * ne + e];
+            I[(size_t)r * ne + e] = s / A[(size_t)r * np + r];
         }
     const int64_t nin = c.ntris * (int64_t)np * ncomp, nout = c.ntris * (int64_t)ne * ncomp;
     DBuf dI, df, dout;
@@ -125,7 +163,13 @@ void chart_interp(Ctx &c, const double *chart_uv, int32_t np, const double *f, i
         po = dout.as<double>();
     }
     const int64_t nthr = c.ntris * (int64_t)ne;
-    if (nthr > 0) {
+    const size_t lds = sizeof(double) * I.size();
+    if (nthr > 0 && lds <= 48 * 1024) {
+        const int64_t blocks = ceil_div(nthr, 256);
+        hipLaunchKernelGGL(k_chart_interp_lds, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), lds,
+                           c.stream, c.ntris, np, ne, ncomp, dI.as<double>(), pf, po);
+        LSS_CHECK_LAUNCH("k_chart_interp_lds");
+    } else if (nthr > 0) {
         hipLaunchKernelGGL(k_chart_interp, dim3((unsigned)ceil_div(nthr, 256)), dim3(256), 0, c.stream, c.ntris, np, ne,
                            ncomp, dI.as<double>(), pf, po);
         LSS_CHECK_LAUNCH("k_chart_interp");
