@@ -91,3 +91,62 @@ def test_config3_full_size_project_sampled(prec):
     c.close()
     assert np.all(stg == sto)
     assert eh <= (1e-11 if prec == lss.FP64 else 2e-6)
+
+
+@pytest.fixture(scope="module")
+def c4():
+    c4 = configs.config4()
+    b = configs.concat_batch(c4["meshes"])
+    b["chart_uv"] = c4["chart_uv"]
+    b["rule"] = c4["rule"]
+    return b
+
+
+@pytest.mark.parametrize("prec", [lss.FP64, lss.MIXED])
+def test_config4_full_size_batch_sampled(c4, prec):
+    """C4 at full size: 64 star-shaped surfaces (832120 triangles) in one
+    context, the 640000 random targets evaluated and all 37.4M chart nodes
+    projected in one call each; samples against the oracle."""
+    import torch
+    b = c4
+    dev = torch.device("cuda")
+    say("case: C4 full size, %d surfaces, %d triangles, precision %d" % (len(b["tri_offsets"]) - 1, len(b["tris"]), prec))
+    c = lss.Context(0)
+    c.set_sources(torch.as_tensor(b["verts"], device=dev), torch.as_tensor(b["tris"], device=dev),
+                  torch.as_tensor(b["rule"], device=dev), tri_offsets=torch.as_tensor(b["tri_offsets"], device=dev))
+    c.set_sigma(torch.as_tensor(b["sigma"], device=dev))
+    c.set_options(precision=prec, far_field=lss.FAR_FMM)
+    x = torch.as_tensor(b["targets"], device=dev)
+    phi, grad = c.eval(x, x_mesh=torch.as_tensor(b["target_mesh"], device=dev))
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(phi).all()) and bool(torch.isfinite(grad).all())
+    rng = np.random.default_rng(44)
+    sel = np.sort(rng.choice(len(b["targets"]), 300, replace=False))
+    po, go = oracle.evaluate(b["verts"], b["tris"], b["sigma"], b["rule"], b["targets"][sel],
+                             tri_offsets=b["tri_offsets"], x_mesh=b["target_mesh"][sel])
+    si = torch.as_tensor(sel, device=dev)
+    pf, gf = phi[si].cpu().numpy(), grad[si].cpu().numpy()
+    ep = np.max(np.abs(pf - po)) / np.max(np.abs(po))
+    eg = np.max(np.linalg.norm(gf - go, axis=1)) / np.max(np.linalg.norm(go, axis=1))
+    say("  random targets vs oracle (300 sampled): e_phi %.3e e_grad %.3e" % (ep, eg))
+    assert ep <= TOL[prec] and eg <= TOL[prec]
+    uv = b["chart_uv"]
+    npc = len(uv)
+    h, xs, status, iters = c.project(torch.as_tensor(uv, device=dev), device=True)
+    torch.cuda.synchronize()
+    conv = float((status == lss.NODE_CONVERGED).sum().item()) / len(status)
+    say("  %d chart nodes: converged fraction %.6f, iterations max %d" % (len(status), conv, int(iters.max())))
+    assert conv > 0.999
+    tsel = np.array([5, 123_457, 400_001, 600_000, 832_119])
+    idx = (tsel[:, None] * npc + np.arange(npc)[None]).ravel()
+    tau = 1e-12 if prec == lss.FP64 else 1e-6
+    ho, xo, sto, ito = oracle.project(b["verts"], b["tris"], b["sigma"], b["rule"], uv, tau=tau, sel=tsel,
+                                      tri_offsets=b["tri_offsets"])
+    ii = torch.as_tensor(idx, device=dev)
+    hg, stg = h[ii].cpu().numpy(), status[ii].cpu().numpy()
+    ok = sto == lss.NODE_CONVERGED
+    eh = np.max(np.abs(hg[ok] - ho[ok]) / b["sigma"][tsel].repeat(npc)[ok])
+    say("  sampled %d nodes: statuses equal %s, e_h %.3e" % (len(idx), bool(np.all(stg == sto)), eh))
+    c.close()
+    assert np.all(stg == sto)
+    assert eh <= (1e-11 if prec == lss.FP64 else 2e-6)
