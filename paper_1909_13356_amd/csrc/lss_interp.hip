@@ -63,19 +63,29 @@ __global__ void k_chart_interp(int64_t ntris, int32_t np, int32_t ne, int32_t nc
 }
 
 // Same product with the interpolation matrix staged once per workgroup in
-// LDS (when it fits) and a grid-stride loop over (triangle, point), three
-// independent sums for three-component data.
+// LDS, and with the node values of the (at most tpb) triangles that a
+// workgroup's 256 consecutive outputs touch staged in LDS per pass of the
+// grid-stride loop (when both fit); three independent sums for
+// three-component data.
 __global__ __launch_bounds__(256) void k_chart_interp_lds(int64_t ntris, int32_t np, int32_t ne, int32_t ncomp,
-                                                          const double *__restrict__ IT, const double *__restrict__ f,
-                                                          double *out) {
-    extern __shared__ double sIT[];
+                                                          int32_t tpb, const double *__restrict__ IT,
+                                                          const double *__restrict__ f, double *out) {
+    extern __shared__ double sm[];
+    double *sIT = sm, *sF = sm + (int64_t)np * ne;
     for (int k = threadIdx.x; k < np * ne; k += blockDim.x) sIT[k] = IT[k];
-    __syncthreads();
-    const int64_t n = ntris * ne;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t n = ntris * ne, per = (int64_t)np * ncomp;
+    for (int64_t qb = (int64_t)blockIdx.x * blockDim.x; qb < n; qb += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t jb = qb / ne;                           // first triangle of this pass
+        const int64_t je = ((qb + blockDim.x < n ? qb + blockDim.x : n) - 1) / ne;   // last one
+        __syncthreads();                                      // previous pass is done with sF
+        const int64_t cnt = (je - jb + 1) * per;              // <= tpb * per by the host's choice of tpb
+        for (int64_t k = threadIdx.x; k < cnt; k += blockDim.x) sF[k] = f[jb * per + k];
+        __syncthreads();
+        const int64_t q = qb + threadIdx.x;
+        if (q >= n) continue;
         const int64_t j = q / ne;
         const int32_t e = (int32_t)(q - j * ne);
-        const double *fj = f + j * np * ncomp;
+        const double *fj = sF + (j - jb) * per;
         if (ncomp == 3) {
             double a0 = 0.0, a1 = 0.0, a2 = 0.0;
 #pragma unroll 5
@@ -163,11 +173,12 @@ void chart_interp(Ctx &c, const double *chart_uv, int32_t np, const double *f, i
         po = dout.as<double>();
     }
     const int64_t nthr = c.ntris * (int64_t)ne;
-    const size_t lds = sizeof(double) * I.size();
-    if (nthr > 0 && lds <= 48 * 1024) {
+    const int32_t tpb = 256 / ne + 2;                         // triangles touched by 256 consecutive outputs
+    const size_t lds = sizeof(double) * (I.size() + (size_t)tpb * np * ncomp);
+    if (nthr > 0 && lds <= 60 * 1024) {
         const int64_t blocks = ceil_div(nthr, 256);
-        hipLaunchKernelGGL(k_chart_interp_lds, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), lds,
-                           c.stream, c.ntris, np, ne, ncomp, dI.as<double>(), pf, po);
+        hipLaunchKernelGGL(k_chart_interp_lds, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(256), lds,
+                           c.stream, c.ntris, np, ne, ncomp, tpb, dI.as<double>(), pf, po);
         LSS_CHECK_LAUNCH("k_chart_interp_lds");
     } else if (nthr > 0) {
         hipLaunchKernelGGL(k_chart_interp, dim3((unsigned)ceil_div(nthr, 256)), dim3(256), 0, c.stream, c.ntris, np, ne,
