@@ -1,0 +1,84 @@
+"""Refinement study of the kind of the paper's rounded-cube tables (section
+5): a rounded-cube skeleton (a cube grid pushed onto the superellipsoid
+|x|^6 + |y|^6 + |z|^6 = 1) is split 1 -> 4 twice (sigma_j = D_j/2 halves
+with every level; the skeleton itself is unchanged), each level is smoothed
+and projected with the FMM path, and the water-tightness eps_0 = 1 +
+integral of n . grad_x 1/(4 pi |x0 - x|) over the charts (x0 inside; 0 for a
+closed surface) is formed from the chart geometry with interpolatory weights
+of the chart nodes.  eps_0 must fall with the level and with the chart order
+p, no chart may fold (n . x_u x x_v > 0), and the Newton residual
+|Phi - 1/2| stays at the tolerance.  Level 0 is checked against the oracle.
+(On a sharp cube with sigma = D/2 about 1% of the charts near the corners
+fold over, and eps_0 stalls near 1e-3.)"""
+import sys
+from math import factorial
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1909_13356_amd as lss
+from workloads import dunavant6, chart_nodes, cube_mesh, refine_1to4, triangle_diameters
+
+pytestmark = pytest.mark.gpu
+X0 = np.array([0.1, -0.2, 0.15])
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def simplex_weights(uv, deg):
+    rows, mom = [], []
+    for a in range(deg + 1):
+        for b in range(deg + 1 - a):
+            rows.append(uv[:, 0] ** a * uv[:, 1] ** b)
+            mom.append(factorial(a) * factorial(b) / factorial(a + b + 2))
+    return np.linalg.solve(np.array(rows), np.array(mom))
+
+
+def eps0(x, da, nr, w, ntri):
+    d = X0[None] - x
+    r = np.linalg.norm(d, axis=1)
+    f = np.sum(nr * d, axis=1) / (4 * np.pi * r ** 3)
+    return 1.0 + np.sum((f * da).reshape(ntri, -1) * w[None, :])
+
+
+def test_refinement_study_water_tightness():
+    v, t = cube_mesh(6, -1.0, 1.0)
+    v = v / (np.sum(np.abs(v) ** 6, axis=1) ** (1.0 / 6))[:, None]
+    rows = {}
+    for level in range(3):
+        sig = 0.5 * triangle_diameters(v, t)
+        for p in (4, 8):
+            uv = chart_nodes(p)
+            w = simplex_weights(uv, p)
+            c = lss.Context()
+            c.set_sources(v, t, dunavant6())
+            c.set_sigma(sig)
+            c.set_options(precision=lss.FP64, far_field=lss.FAR_FMM)
+            h, x, st, it = c.project(uv)
+            assert np.all(st == lss.NODE_CONVERGED)
+            phi, _ = c.eval(x)
+            xu, xv, da, nr = c.chart_geometry(uv, h)
+            assert np.all(np.sum(nr * np.cross(xu, xv), axis=1) > 0)
+            e0 = eps0(x, da, nr, w, len(t))
+            eN = np.abs(phi - 0.5).max()
+            rows[(level, p)] = (len(t), e0, eN, int(it.max()))
+            say("M %6d  p %d  n_p %2d  M n_p %7d  k %d  eps_N %.1e  eps_0 %.2e" % (
+                len(t), p, len(uv), len(t) * len(uv), int(it.max()), eN, e0))
+            if level == 0 and p == 4:
+                ho, xo, sto, ito = oracle.project(v, t, sig, dunavant6(), uv)
+                oxu, oxv, oda, onr = oracle.chart_geometry(v, t, sig, dunavant6(), uv, ho)
+                eo = eps0(xo, oda, onr, w, len(t))
+                say("  oracle: eps_0 %.2e, max |h - h_oracle| / sigma %.1e" % (
+                    eo, np.max(np.abs(h - ho) / np.repeat(sig, len(uv)))))
+                assert abs(e0 - eo) < 1e-12
+            c.close()
+        v, t = refine_1to4(v, t)
+    assert all(r[2] < 1e-11 for r in rows.values())
+    for p in (4, 8):
+        assert abs(rows[(1, p)][1]) < abs(rows[(0, p)][1])
+    for level in range(3):
+        assert abs(rows[(level, 8)][1]) < abs(rows[(level, 4)][1])
