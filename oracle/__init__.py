@@ -37,10 +37,10 @@ def _load():
         P = ctypes.c_void_p
         i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         L.oracle_radial.argtypes = [P, i64, f64, P, P]
-        L.oracle_nodes.argtypes = [P, P, i64, P, i32, P, P]
-        L.oracle_eval.argtypes = [P, P, i64, P, P, i64, P, i32, P, P, i64, P, P, P, P, ctypes.c_int]
+        L.oracle_nodes.argtypes = [P, P, i32, i64, P, i32, P, P]
+        L.oracle_eval.argtypes = [P, P, i32, i64, P, P, i64, P, i32, P, P, i64, P, P, P, P, ctypes.c_int]
         L.oracle_pseudonormals.argtypes = [P, i64, P, i64, P]
-        L.oracle_project.argtypes = [P, i64, P, i64, P, i32, P, i64, P, i32, P, i32, P, i64,
+        L.oracle_project.argtypes = [P, i64, P, i32, i64, P, i32, P, i64, P, i32, P, i32, P, i64,
                                      f64, i32, P, P, P, P, ctypes.c_int]
         L.oracle_threads.restype = ctypes.c_int
         _lib = L
@@ -67,13 +67,22 @@ def radial(rho, sigma):
     return K, F
 
 
+def _tris(tris):
+    """Triangle index array and its width: (ntris, 3) flat, (ntris, 6)
+    quadratic (corners P1 P2 P3, then the edge points of P1P2, P2P3, P3P1)."""
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    if tris.ndim != 2 or tris.shape[1] not in (3, 6):
+        raise ValueError("tris must be (ntris, 3) or (ntris, 6)")
+    return tris, tris.shape[1]
+
+
 def nodes(verts, tris, rule):
     """Quadrature nodes y (N, 3) and weighted area normals a = w J (N, 3)."""
     verts, rule = _f64(verts), _f64(rule)
-    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    tris, nvt = _tris(tris)
     n = len(tris) * len(rule)
     y, a = np.empty((n, 3)), np.empty((n, 3))
-    _load().oracle_nodes(_p(verts), _p(tris), len(tris), _p(rule), len(rule), _p(y), _p(a))
+    _load().oracle_nodes(_p(verts), _p(tris), nvt, len(tris), _p(rule), len(rule), _p(y), _p(a))
     return y, a
 
 
@@ -82,14 +91,14 @@ def evaluate(verts, tris, sigma, rule, x, tri_offsets=None, x_mesh=None,
     """Phi (n,) and grad Phi (n, 3) by the direct FP64 sum over all nodes."""
     verts, rule, x = _f64(verts), _f64(rule), _f64(x).reshape(-1, 3)
     sigma = _f64(np.atleast_1d(sigma))
-    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    tris, nvt = _tris(tris)
     off = None if tri_offsets is None else np.ascontiguousarray(tri_offsets, dtype=np.int64)
     xm = None if x_mesh is None else np.ascontiguousarray(x_mesh, dtype=np.int32)
     n = len(x)
     phi, grad = np.empty(n), np.empty((n, 3))
     aphi = np.empty(n) if with_abs else None
     agrad = np.empty(n) if with_abs else None
-    _load().oracle_eval(_p(verts), _p(tris), len(tris), _p(off), _p(sigma), sigma.size,
+    _load().oracle_eval(_p(verts), _p(tris), nvt, len(tris), _p(off), _p(sigma), sigma.size,
                         _p(rule), len(rule), _p(x), _p(xm), n, _p(phi), _p(grad),
                         _p(aphi), _p(agrad), int(nthreads))
     if with_abs:
@@ -112,7 +121,7 @@ def project(verts, tris, sigma, rule, chart_uv, tau=1e-12, max_iter=40, sel=None
     index k * np + i."""
     verts, rule, uv = _f64(verts), _f64(rule), _f64(chart_uv).reshape(-1, 2)
     sigma = _f64(np.atleast_1d(sigma))
-    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    tris, nvt = _tris(tris)
     off = None if tri_offsets is None else np.ascontiguousarray(tri_offsets, dtype=np.int64)
     nmesh = 0 if off is None else len(off) - 1
     s = None if sel is None else np.ascontiguousarray(sel, dtype=np.int64)
@@ -121,7 +130,7 @@ def project(verts, tris, sigma, rule, chart_uv, tau=1e-12, max_iter=40, sel=None
     tot = nsel * npn
     h, xo = np.empty(tot), np.empty((tot, 3))
     st, it = np.empty(tot, np.int8), np.empty(tot, np.int8)
-    _load().oracle_project(_p(verts), len(verts), _p(tris), len(tris), _p(off), nmesh,
+    _load().oracle_project(_p(verts), len(verts), _p(tris), nvt, len(tris), _p(off), nmesh,
                            _p(sigma), sigma.size, _p(rule), len(rule), _p(uv), npn,
                            _p(s), nsel, float(tau), int(max_iter), _p(h), _p(xo),
                            _p(st), _p(it), int(nthreads))
@@ -134,15 +143,17 @@ def chart_geometry(verts, tris, sigma, rule, chart_uv, h, sel=None, tri_offsets=
     v_vector, v_vector_2, eq. da) at the chart nodes of the triangles ``sel``
     (all if None), for the given h (index k * np + i over sel).  T and H are
     the linear maps of eq. tparam and mkpseudovec (vertex pseudonormals of eq.
-    mkvertexpn); grad Phi comes from ``evaluate``; the normal is
-    -grad Phi / |grad Phi|, outward because Phi grows inward."""
+    mkvertexpn), on the corner triangles when ``tris`` is quadratic; grad Phi
+    comes from ``evaluate``; the normal is -grad Phi / |grad Phi|, outward
+    because Phi grows inward."""
     verts = _f64(verts)
-    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    tris, _ = _tris(tris)
+    corner = np.ascontiguousarray(tris[:, :3])
     uv = _f64(chart_uv).reshape(-1, 2)
     s = np.arange(len(tris)) if sel is None else np.asarray(sel, dtype=np.int64)
     npn = len(uv)
-    Hv = pseudonormals(verts, tris)
-    t = tris[s]
+    Hv = pseudonormals(verts, corner)
+    t = corner[s]
     P1, P2, P3 = verts[t[:, 0]][:, None], verts[t[:, 1]][:, None], verts[t[:, 2]][:, None]
     H1, H2, H3 = Hv[t[:, 0]][:, None], Hv[t[:, 1]][:, None], Hv[t[:, 2]][:, None]
     u, v = uv[None, :, 0:1], uv[None, :, 1:2]

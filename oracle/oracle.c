@@ -13,6 +13,13 @@
  *    sum eq. discrete_int):  y = P1 + u (P2-P1) + v (P3-P1), with the
  *    area-weighted outward normal  J = (P2-P1) x (P3-P1)  so that
  *    N_hat da = J du dv;
+ *  - on a quadratic (second-order curvilinear) skeleton triangle (section
+ *    on quadratic skeletons) given by six points, the corners P1, P2, P3 and
+ *    the edge points P4 (edge P1P2), P5 (P2P3), P6 (P3P1):
+ *    y = sum_k N_k(u, v) P_k with the quadratic Lagrange shape functions of
+ *    the six points, and J = y_u x y_v at the node (the paper names the
+ *    element but not its node order or shape functions: these are the
+ *    standard ones);
  *  - the level-set function as the direct discrete sum (eq. surf, kerpsi,
  *    discrete_int)  Phi(x) = sum_nodes w psi_sigma(x, y)  with
  *        psi da = -(J . d) K(rho) w du dv,   d = x - y,  rho = |d|,
@@ -128,19 +135,58 @@ static void tri_node(const double *verts, const int32_t *tri, const double *uvw,
     a[2] = uvw[2] * (tu[0] * tv[1] - tu[1] * tv[0]);
 }
 
+/* Quadratic triangle: barycentrics l1 = 1-u-v, l2 = u, l3 = v;
+ *   N1 = l1(2 l1 - 1), N2 = l2(2 l2 - 1), N3 = l3(2 l3 - 1),
+ *   N4 = 4 l1 l2,      N5 = 4 l2 l3,      N6 = 4 l3 l1,
+ * derivatives by the chain rule with dl/du = (-1, 1, 0), dl/dv = (-1, 0, 1). */
+static void quad_node(const double *verts, const int32_t *tri, const double *uvw,
+                      double y[3], double a[3])
+{
+    const double u = uvw[0], v = uvw[1];
+    const double l1 = 1.0 - u - v, l2 = u, l3 = v;
+    const double N[6] = {l1 * (2.0 * l1 - 1.0), l2 * (2.0 * l2 - 1.0), l3 * (2.0 * l3 - 1.0),
+                         4.0 * l1 * l2, 4.0 * l2 * l3, 4.0 * l3 * l1};
+    const double Nu[6] = {-(4.0 * l1 - 1.0), 4.0 * l2 - 1.0, 0.0,
+                          4.0 * (l1 - l2), 4.0 * l3, -4.0 * l3};
+    const double Nv[6] = {-(4.0 * l1 - 1.0), 0.0, 4.0 * l3 - 1.0,
+                          -4.0 * l2, 4.0 * l2, 4.0 * (l1 - l3)};
+    double yu[3] = {0, 0, 0}, yv[3] = {0, 0, 0};
+    for (int c = 0; c < 3; ++c) y[c] = 0.0;
+    for (int k = 0; k < 6; ++k) {
+        const double *P = verts + 3 * (int64_t)tri[k];
+        for (int c = 0; c < 3; ++c) {
+            y[c] += N[k] * P[c];
+            yu[c] += Nu[k] * P[c];
+            yv[c] += Nv[k] * P[c];
+        }
+    }
+    a[0] = uvw[2] * (yu[1] * yv[2] - yu[2] * yv[1]);
+    a[1] = uvw[2] * (yu[2] * yv[0] - yu[0] * yv[2]);
+    a[2] = uvw[2] * (yu[0] * yv[1] - yu[1] * yv[0]);
+}
+
+/* node m of triangle j; nvt = 3 (flat) or 6 (quadratic) indices per triangle */
+static void src_node(const double *verts, const int32_t *tris, int32_t nvt, int64_t j,
+                     const double *uvw, double y[3], double a[3])
+{
+    if (nvt == 6) quad_node(verts, tris + 6 * j, uvw, y, a);
+    else tri_node(verts, tris + 3 * j, uvw, y, a);
+}
+
 /* all nodes y and weighted normals a = w J, node index = tri * nq + m */
-void oracle_nodes(const double *verts, const int32_t *tris, int64_t ntris,
+void oracle_nodes(const double *verts, const int32_t *tris, int32_t nvt, int64_t ntris,
                   const double *rule, int32_t nq, double *y, double *a)
 {
     for (int64_t j = 0; j < ntris; ++j)
         for (int m = 0; m < nq; ++m)
-            tri_node(verts, tris + 3 * j, rule + 3 * m, y + 3 * (j * nq + m), a + 3 * (j * nq + m));
+            src_node(verts, tris, nvt, j, rule + 3 * m, y + 3 * (j * nq + m), a + 3 * (j * nq + m));
 }
 
 /* ------------------------------------------------------------ evaluation */
 typedef struct {
     const double *verts;
     const int32_t *tris;
+    int32_t nvt;              /* indices per triangle: 3 flat, 6 quadratic */
     const int64_t *tri_off;   /* nmesh+1 or NULL */
     int64_t ntris;
     const double *sigma;      /* length 1 or ntris */
@@ -159,7 +205,7 @@ static void eval_point(const srcset *S, const double x[3], int32_t mesh,
         const double sigma = S->nsigma == 1 ? S->sigma[0] : S->sigma[j];
         for (int m = 0; m < S->nq; ++m) {
             double y[3], a[3], d[3];
-            tri_node(S->verts, S->tris + 3 * j, S->rule + 3 * m, y, a);
+            src_node(S->verts, S->tris, S->nvt, j, S->rule + 3 * m, y, a);
             d[0] = x[0] - y[0]; d[1] = x[1] - y[1]; d[2] = x[2] - y[2];
             const double rho = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
             double K, F;
@@ -201,13 +247,13 @@ int oracle_threads(void)
 /* Phi and grad Phi at n targets.  x_mesh (may be NULL) selects, per target,
  * the mesh (CSR range of tri_off) whose triangles are summed. aphi / agrad
  * (may be NULL) receive sum |term| and sum ||grad term||. */
-void oracle_eval(const double *verts, const int32_t *tris, int64_t ntris,
+void oracle_eval(const double *verts, const int32_t *tris, int32_t nvt, int64_t ntris,
                  const int64_t *tri_off, const double *sigma, int64_t nsigma,
                  const double *rule, int32_t nq,
                  const double *x, const int32_t *x_mesh, int64_t n,
                  double *phi, double *grad, double *aphi, double *agrad, int nthreads)
 {
-    srcset S = {verts, tris, tri_off, ntris, sigma, nsigma, rule, nq};
+    srcset S = {verts, tris, nvt, tri_off, ntris, sigma, nsigma, rule, nq};
     set_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t i = 0; i < n; ++i)
@@ -255,8 +301,11 @@ void oracle_pseudonormals(const double *verts, int64_t nverts, const int32_t *tr
 /* ---------------------------------------------------------- Newton projection */
 /* For each selected triangle j (sel[k], or k if sel is NULL) and each chart
  * node (u_i, v_i): T, H from eq. tparam / mkpseudovec, then the safeguarded
- * Newton iteration described in the header.  Output index k * np + i. */
-void oracle_project(const double *verts, int64_t nverts, const int32_t *tris, int64_t ntris,
+ * Newton iteration described in the header.  Output index k * np + i.
+ * With quadratic sources (nvt = 6) Phi sums the curved triangles while the
+ * chart base T and the pseudonormal field H come from their corner
+ * triangles P1 P2 P3. */
+void oracle_project(const double *verts, int64_t nverts, const int32_t *tris, int32_t nvt, int64_t ntris,
                     const int64_t *tri_off, int32_t nmesh,
                     const double *sigma, int64_t nsigma, const double *rule, int32_t nq,
                     const double *chart_uv, int32_t np, const int64_t *sel, int64_t nsel,
@@ -264,9 +313,12 @@ void oracle_project(const double *verts, int64_t nverts, const int32_t *tris, in
                     double *h_out, double *x_out, int8_t *status, int8_t *iters,
                     int nthreads)
 {
-    srcset S = {verts, tris, tri_off, ntris, sigma, nsigma, rule, nq};
+    srcset S = {verts, tris, nvt, tri_off, ntris, sigma, nsigma, rule, nq};
+    int32_t *corner = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)ntris);
+    for (int64_t j = 0; j < ntris; ++j)
+        for (int k = 0; k < 3; ++k) corner[3 * j + k] = tris[nvt * j + k];
     double *Hv = (double *)malloc(sizeof(double) * 3 * (size_t)nverts);
-    oracle_pseudonormals(verts, nverts, tris, ntris, Hv);
+    oracle_pseudonormals(verts, nverts, corner, ntris, Hv);
     set_threads(nthreads);
     const int64_t total = nsel * (int64_t)np;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -281,7 +333,7 @@ void oracle_project(const double *verts, int64_t nverts, const int32_t *tris, in
             mesh = lo;
         }
         const double u = chart_uv[2 * i], v = chart_uv[2 * i + 1];
-        const int32_t *t = tris + 3 * j;
+        const int32_t *t = corner + 3 * j;
         double T[3], H[3];
         for (int c = 0; c < 3; ++c) {
             const double p1 = verts[3 * (int64_t)t[0] + c], p2 = verts[3 * (int64_t)t[1] + c], p3 = verts[3 * (int64_t)t[2] + c];
@@ -330,4 +382,5 @@ void oracle_project(const double *verts, int64_t nverts, const int32_t *tris, in
         iters[idx] = (int8_t)it;
     }
     free(Hv);
+    free(corner);
 }

@@ -16,7 +16,7 @@ from scipy.special import erf
 from scipy.integrate import quad
 
 import oracle
-from workloads import (dunavant6, chart_nodes, cube_mesh, icosphere, star_surface,
+from workloads import (dunavant6, chart_nodes, cube_mesh, icosphere, star_surface, torus_mesh, quadratic_from_flat,
                        triangle_diameters, box_targets, shell_targets, configs)
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden", "paper_constants.txt")
@@ -509,3 +509,114 @@ def test_chart_interp_converges_on_a_smooth_function():
         uv = chart_nodes(p)
         errs.append(np.abs(oracle.chart_interp(uv, np.exp(uv[:, 0] + 2 * uv[:, 1]), ev) - exact).max())
     assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-5
+
+
+# ------------------------------------------------ quadratic skeleton triangles
+def _unit_sphere(p):
+    return p / np.linalg.norm(p, axis=1, keepdims=True)
+
+
+def test_quadratic_nodes_sit_on_their_six_points():
+    """The rule points (0,0), (1,0), (0,1), (1/2,0), (1/2,1/2), (0,1/2) of T0
+    land on P1..P6 (node order: corners, then the edges P1P2, P2P3, P3P1)."""
+    rng = np.random.default_rng(3)
+    verts = rng.normal(size=(6, 3))
+    uvw = np.array([[0, 0, 1], [1, 0, 1], [0, 1, 1], [.5, 0, 1], [.5, .5, 1], [0, .5, 1]], float)
+    y, _ = oracle.nodes(verts, np.arange(6, dtype=np.int32)[None], uvw)
+    assert np.array_equal(y, verts)
+
+
+def test_quadratic_with_midpoint_edges_is_the_flat_triangle():
+    v, t = icosphere(1)
+    v6, t6 = quadratic_from_flat(v, t)
+    rule = dunavant6()
+    y3, a3 = oracle.nodes(v, t, rule)
+    y6, a6 = oracle.nodes(v6, t6, rule)
+    assert np.max(np.abs(y6 - y3)) < 1e-15
+    assert np.max(np.abs(a6 - a3)) < 1e-15
+
+
+def test_quadratic_patch_vector_area_is_the_boundary_integral():
+    """Stokes: the vector area of a surface patch, int n dA, equals half the
+    boundary integral of y x dy.  The boundary of a quadratic triangle is
+    three parabolic arcs through a corner, the edge point and the next corner,
+    and c x c' is a cubic in the arc parameter, so 3-point Gauss-Legendre
+    integrates it exactly; the 12-point rule is exact for the degree-2
+    integrand y_u x y_v."""
+    rng = np.random.default_rng(11)
+    for _ in range(5):
+        P = rng.normal(size=(6, 3))
+        _, a = oracle.nodes(P, np.arange(6, dtype=np.int32)[None], dunavant6())
+        g, gw = np.polynomial.legendre.leggauss(3)
+        t, gw = 0.5 * (g + 1.0), 0.5 * gw
+        ref = np.zeros(3)
+        for A, M, B in ((P[0], P[3], P[1]), (P[1], P[4], P[2]), (P[2], P[5], P[0])):
+            c = (np.outer((1 - t) * (1 - 2 * t), A) + np.outer(4 * t * (1 - t), M)
+                 + np.outer(t * (2 * t - 1), B))
+            dc = np.outer(4 * t - 3, A) + np.outer(4 - 8 * t, M) + np.outer(4 * t - 1, B)
+            ref += 0.5 * np.sum(gw[:, None] * np.cross(c, dc), axis=0)
+        assert np.max(np.abs(a.sum(0) - ref)) < 1e-13 * (1 + np.abs(ref).max())
+
+
+def test_quadratic_paraboloid_patch_fluxes():
+    """A quadratic triangle whose six points lie on z = f(x, y) = x^2 +
+    0.5 x y - 0.3 y^2 over the unit right triangle (edge points above the
+    edge midpoints) is exactly that graph, with y_u x y_v = (-f_x, -f_y, 1).
+    Closed forms over the triangle: int x^2 = int y^2 = 1/12, int xy = 1/24,
+    int x = int y = 1/6."""
+    xy = np.array([[0, 0], [1, 0], [0, 1], [.5, 0], [.5, .5], [0, .5]], float)
+    f = xy[:, 0] ** 2 + 0.5 * xy[:, 0] * xy[:, 1] - 0.3 * xy[:, 1] ** 2
+    P = np.column_stack([xy, f])
+    y, a = oracle.nodes(P, np.arange(6, dtype=np.int32)[None], dunavant6())
+    assert abs(a[:, 2].sum() - 0.5) < 1e-15
+    assert abs(a[:, 0].sum() + (2 / 6 + 0.5 / 6)) < 1e-15
+    assert abs(a[:, 1].sum() + (0.5 / 6 - 0.6 / 6)) < 1e-15
+    assert abs(np.sum(y[:, 2] * a[:, 2]) - (1 / 12 + 0.5 / 24 - 0.3 / 12)) < 1e-15
+    fx = 2 * y[:, 0] + 0.5 * y[:, 1]
+    assert np.max(np.abs(y[:, 2] - (y[:, 0] ** 2 + 0.5 * y[:, 0] * y[:, 1] - 0.3 * y[:, 1] ** 2))) < 1e-15
+    w = dunavant6()[:, 2]
+    assert np.max(np.abs(a[:, 0] + w * fx)) < 1e-15
+
+
+def test_quadratic_sphere_closed_and_volume_converges_at_fourth_order():
+    """Edge points lifted onto the unit sphere: sum a = 0 (closed surface),
+    and the divergence-theorem volume (1/3) sum y . a tends to 4 pi / 3 with
+    error O(h^4) (the flat skeleton's is O(h^2))."""
+    rule = dunavant6()
+    eq, ef = [], []
+    for lev in (1, 2, 3):
+        v, t = icosphere(lev)
+        v6, t6 = quadratic_from_flat(v, t, lift=_unit_sphere)
+        y6, a6 = oracle.nodes(v6, t6, rule)
+        y3, a3 = oracle.nodes(v, t, rule)
+        assert np.max(np.abs(a6.sum(0))) < 1e-13
+        eq.append(abs(np.sum(y6 * a6) / 3 - 4 * PI / 3))
+        ef.append(abs(np.sum(y3 * a3) / 3 - 4 * PI / 3))
+    for k in (0, 1):
+        assert 12.0 < eq[k] / eq[k + 1] < 20.0, eq
+        assert 3.0 < ef[k] / ef[k + 1] < 5.0, ef
+    assert eq[-1] < 1e-2 * ef[-1]
+
+
+def test_quadratic_torus_level_set_closer_to_the_surface():
+    """With every skeleton point on a torus, Phi at points of the torus is
+    closer to 1/2 for the quadratic skeleton than for the flat one with the
+    same corners; deep inside Phi is 1 and far outside 0 in both."""
+    rule = dunavant6()
+    v3, t3 = torus_mesh(24, 12)
+    v6, t6 = torus_mesh(24, 12, quadratic=True)
+    s = 0.05
+    rng = np.random.default_rng(2)
+    th, ph = rng.uniform(0, 2 * PI, 40), rng.uniform(0, 2 * PI, 40)
+    xs = np.column_stack([(1 + 0.4 * np.cos(ph)) * np.cos(th), (1 + 0.4 * np.cos(ph)) * np.sin(th),
+                          0.4 * np.sin(ph)])
+    p3, _ = oracle.evaluate(v3, t3, s, rule, xs)
+    p6, _ = oracle.evaluate(v6, t6, s, rule, xs)
+    e3, e6 = np.abs(p3 - 0.5).max(), np.abs(p6 - 0.5).max()
+    assert e6 < 0.2 * e3 and e6 < 0.05, (e3, e6)
+    core = np.array([[1.0, 0, 0], [0, -1.0, 0]])
+    far = np.array([[0, 0, 0.0], [3.0, 0, 0]])
+    for v, t in ((v3, t3), (v6, t6)):
+        pc, _ = oracle.evaluate(v, t, s, rule, core)
+        pf, _ = oracle.evaluate(v, t, s, rule, far)
+        assert np.max(np.abs(pc - 1)) < 1e-3 and np.max(np.abs(pf)) < 1e-3

@@ -3,6 +3,9 @@ skeleton is a conforming, positively oriented triangle mesh).
 
 All generators return ``(verts, tris)`` with ``verts`` (nv, 3) float64 and
 ``tris`` (nt, 3) int32, vertex order counter-clockwise seen from outside.
+Quadratic (second-order curvilinear) skeletons have ``tris`` (nt, 6): the
+corners P1 P2 P3 as above, then the edge points of P1P2, P2P3 and P3P1, each
+shared by the two triangles of its edge.
 """
 import numpy as np
 
@@ -258,6 +261,54 @@ def bumpy_sphere(nu, grade=10.0, lmax=64, amp=0.05, nbumps=2000, seed=5,
                 d2 = np.sum((base[idx] - c[b]) ** 2, axis=1)
                 r[idx] += sgn[b] * h[b] * np.exp(-d2 / (2.0 * w[b] ** 2))
     return base * r[:, None], tris
+
+
+# ----------------------------------------------------------------- torus
+def torus_mesh(nu, nv, R=1.0, r=0.4, quadratic=False):
+    """Torus ((R + r cos p) cos t, (R + r cos p) sin t, r sin p) on an nu x nv
+    grid of (t, p), each cell split along its diagonal into two triangles
+    (counter-clockwise in (t, p), which is outward).  With ``quadratic`` the
+    edge points are the surface points at the parameter midpoints, so every
+    one of the six points lies on the torus."""
+    k = 2 if quadratic else 1
+    gi, gj = np.meshgrid(np.arange(k * nu), np.arange(k * nv), indexing="ij")
+    t = 2.0 * np.pi * gi.ravel() / (k * nu)
+    p = 2.0 * np.pi * gj.ravel() / (k * nv)
+    verts = np.stack([(R + r * np.cos(p)) * np.cos(t), (R + r * np.cos(p)) * np.sin(t),
+                      r * np.sin(p)], axis=1)
+
+    def vid(i, j):  # vertex at half-step grid point (i, j) of the k-refined grid
+        return (i % (k * nu)) * (k * nv) + (j % (k * nv))
+
+    i, j = np.meshgrid(np.arange(nu), np.arange(nv), indexing="ij")
+    i, j = k * i.ravel(), k * j.ravel()
+    a, b, c, d = vid(i, j), vid(i + k, j), vid(i + k, j + k), vid(i, j + k)
+    if not quadratic:
+        tris = np.concatenate([np.stack([a, b, c], 1), np.stack([a, c, d], 1)])
+        return verts, tris.astype(np.int32)
+    ab, bc, ac = vid(i + 1, j), vid(i + 2, j + 1), vid(i + 1, j + 1)
+    cd, da = vid(i + 1, j + 2), vid(i, j + 1)
+    tris = np.concatenate([np.stack([a, b, c, ab, bc, ac], 1), np.stack([a, c, d, ac, cd, da], 1)])
+    used = np.unique(tris)
+    remap = np.full(len(verts), -1, np.int64)
+    remap[used] = np.arange(len(used))
+    return verts[used], remap[tris].astype(np.int32)
+
+
+def quadratic_from_flat(verts, tris, lift=None):
+    """Quadratic skeleton from a flat one: one edge point per edge at the
+    edge midpoint, mapped through ``lift`` (points (n, 3) -> (n, 3)) when
+    given, e.g. onto the surface the flat mesh approximates.  Returns
+    (verts, tris6); the corner vertices keep their indices."""
+    nv, nt = len(verts), len(tris)
+    e = np.concatenate([tris[:, [0, 1]], tris[:, [1, 2]], tris[:, [2, 0]]])
+    uk, inv = np.unique(np.sort(e, axis=1), axis=0, return_inverse=True)
+    mid = 0.5 * (verts[uk[:, 0]] + verts[uk[:, 1]])
+    if lift is not None:
+        mid = lift(mid)
+    inv = inv.reshape(-1)
+    t6 = np.concatenate([tris, np.stack([nv + inv[:nt], nv + inv[nt:2 * nt], nv + inv[2 * nt:]], 1)], 1)
+    return np.concatenate([verts, mid]), t6.astype(np.int32)
 
 
 # ----------------------------------------------------------- utilities
