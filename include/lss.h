@@ -96,6 +96,8 @@ enum {
 };
 
 #define LSS_PTR_DEVICE 1u
+/* lss_set_sources: tris holds six indices per triangle (quadratic skeleton) */
+#define LSS_TRI6 2u
 
 typedef struct lss_options {
     int32_t precision;        /* LSS_FP64 (default) or LSS_MIXED */
@@ -171,7 +173,15 @@ int lss_synchronize(lss_ctx *ctx);
  *   rule_uvw (nq,3): nodes (u_m, v_m) on T0 and weights w_m (sum 1/2), nq >= 1.
  * Indices outside [0, nverts) give LSS_EINVAL.  A mesh with signed volume
  * <= 0 gives LSS_EORIENT.  Invalidates sigma-dependent state: lss_set_sigma
- * must follow before lss_build / lss_eval / lss_project. */
+ * must follow before lss_build / lss_eval / lss_project.
+ * With LSS_TRI6 in flags the skeleton is quadratic (section on quadratic
+ * skeletons: second-order curvilinear triangles): tris is (ntris,6), the
+ * corners P1 P2 P3 in the order above, then the edge points P4 (edge P1P2),
+ * P5 (P2P3), P6 (P3P1), shared by the two triangles of an edge.  The patch is
+ * y(u,v) = sum_k N_k(u,v) P_k with the quadratic Lagrange shape functions
+ * and each node carries w (y_u x y_v).  The orientation check, the vertex
+ * pseudonormals and the chart bases of lss_project / lss_chart_geometry use
+ * the corner triangles P1 P2 P3; Phi sums the curved triangles. */
 int lss_set_sources(lss_ctx *ctx,
                     const double *verts, int64_t nverts,
                     const int32_t *tris, int64_t ntris,

@@ -17,6 +17,7 @@ FP64, MIXED = 0, 1
 FAR_DIRECT, FAR_FMM = 0, 1
 NODE_CONVERGED, NODE_MAXITER, NODE_NOBRACKET, NODE_DEGENERATE_H = 0, 1, 2, 3
 PTR_DEVICE = 1
+TRI6 = 2
 
 # every entry point declared in include/lss.h
 EXPORTED_SYMBOLS = ["lss_create", "lss_destroy", "lss_last_error", "lss_synchronize",
@@ -164,11 +165,14 @@ class Context:
 
     # ------------------------------------------------------------ setters
     def set_sources(self, verts, tris, rule, tri_offsets=None):
+        """tris (ntris, 3) flat or (ntris, 6) quadratic triangles (LSS_TRI6)."""
+        if len(tris.shape) != 2 or tris.shape[1] not in (3, 6):
+            raise ValueError("tris must be (ntris, 3) or (ntris, 6)")
         pv, fv, kv = _ptr(verts, np.float64)
         pt, ft, kt = _ptr(tris, np.int32)
         pr, fr, kr = _ptr(rule, np.float64)
         po, fo, ko = _ptr(tri_offsets, np.int64)
-        flags = fv | ft | fr | fo
+        flags = fv | ft | fr | fo | (TRI6 if tris.shape[1] == 6 else 0)
         if len({f for f in (fv, ft, fr, fo if tri_offsets is not None else fv)}) != 1:
             raise ValueError("all arrays of one call must live in the same memory (host or device)")
         nverts, ntris = len(verts), len(tris)

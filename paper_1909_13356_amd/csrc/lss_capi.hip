@@ -28,6 +28,13 @@ __global__ void k_check_tris(int64_t n3, const int32_t *__restrict__ tris, int64
     }
 }
 
+// corner triangles P1 P2 P3 of a quadratic skeleton
+__global__ void k_corners(int64_t ntris, const int32_t *__restrict__ t6, int32_t *__restrict__ t3) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < ntris)
+        for (int k = 0; k < 3; ++k) t3[3 * j + k] = t6[6 * j + k];
+}
+
 __global__ void k_check_verts(int64_t n3, const double *__restrict__ v, unsigned long long *bad) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n3 && !isfinite(v[i])) atomicAdd(bad, 1ull);
@@ -546,7 +553,7 @@ void lss_destroy(lss_ctx *ctx) {
     Ctx &c = ctx->c;
     (void)hipSetDevice(c.device);
     (void)hipStreamSynchronize(c.stream);
-    DBuf *bufs[] = {&c.verts, &c.tris, &c.tri_off, &c.node_off, &c.rule, &c.sigma, &c.src, &c.vH, &c.tkey,
+    DBuf *bufs[] = {&c.verts, &c.tris, &c.tris6, &c.tri_off, &c.node_off, &c.rule, &c.sigma, &c.src, &c.vH, &c.tkey,
                     &c.tkey2, &c.tperm, &c.tperm2, &c.tx, &c.ty, &c.tz, &c.tmesh, &c.sort_tmp, &c.pairs, &c.tile_queue, &c.tile_order, &c.tile_bucket,
                     &c.tflag, &c.tpos, &c.tstart, &c.ntiles, &c.tleaf,
                     &c.ns.T, &c.ns.H, &c.ns.h, &c.ns.lo, &c.ns.hi, &c.ns.sig, &c.ns.mesh, &c.ns.orig,
@@ -576,6 +583,8 @@ int lss_set_sources(lss_ctx *ctx, const double *verts, int64_t nverts, const int
         if (mesh_tri_offsets == nullptr && nmesh > 1) fail(LSS_EINVAL, "lss_set_sources: nmesh > 1 needs offsets");
         if (nmesh < 0) fail(LSS_EINVAL, "lss_set_sources: nmesh < 0");
         const bool dev = flags & LSS_PTR_DEVICE;
+        const bool quad = flags & LSS_TRI6;
+        const int nvt = quad ? 6 : 3;
         c.have_sources = false;
         c.have_sigma = false;
         c.built = false;
@@ -598,7 +607,16 @@ int lss_set_sources(lss_ctx *ctx, const double *verts, int64_t nverts, const int
             if (!std::isfinite(hrule[3 * m]) || !std::isfinite(hrule[3 * m + 1]) || !std::isfinite(hrule[3 * m + 2]))
                 fail(LSS_EINVAL, "lss_set_sources: rule entries must be finite");
         upload(c, c.verts, verts, sizeof(double) * 3 * nverts, flags);
-        upload(c, c.tris, tris, sizeof(int32_t) * 3 * ntris, flags);
+        if (quad) {
+            upload(c, c.tris6, tris, sizeof(int32_t) * 6 * ntris, flags);
+            c.tris.ensure(sizeof(int32_t) * 3 * ntris);
+            hipLaunchKernelGGL(lss::k_corners, dim3(lss::grid_for(ntris)), dim3(256), 0, c.stream, ntris,
+                               c.tris6.as<int32_t>(), c.tris.as<int32_t>());
+            LSS_CHECK_LAUNCH("k_corners");
+        } else {
+            upload(c, c.tris, tris, sizeof(int32_t) * 3 * ntris, flags);
+            c.tris6.release();
+        }
         upload(c, c.rule, hrule.data(), sizeof(double) * 3 * nq, 0);
         c.tri_off.ensure(sizeof(int64_t) * (nm + 1));
         LSS_HIP(hipMemcpyAsync(c.tri_off.p, off.data(), sizeof(int64_t) * (nm + 1), hipMemcpyHostToDevice, c.stream));
@@ -610,8 +628,8 @@ int lss_set_sources(lss_ctx *ctx, const double *verts, int64_t nverts, const int
         DBuf bad;
         bad.ensure(16);
         LSS_HIP(hipMemsetAsync(bad.p, 0, 16, c.stream));
-        hipLaunchKernelGGL(lss::k_check_tris, dim3(lss::grid_for(3 * ntris)), dim3(256), 0, c.stream, 3 * ntris,
-                           c.tris.as<int32_t>(), nverts, bad.as<unsigned long long>());
+        hipLaunchKernelGGL(lss::k_check_tris, dim3(lss::grid_for(nvt * ntris)), dim3(256), 0, c.stream, nvt * ntris,
+                           (quad ? c.tris6 : c.tris).as<int32_t>(), nverts, bad.as<unsigned long long>());
         hipLaunchKernelGGL(lss::k_check_verts, dim3(lss::grid_for(3 * nverts)), dim3(256), 0, c.stream, 3 * nverts,
                            c.verts.as<double>(), bad.as<unsigned long long>() + 1);
         unsigned long long nb[2] = {0, 0};
@@ -623,6 +641,7 @@ int lss_set_sources(lss_ctx *ctx, const double *verts, int64_t nverts, const int
         c.ntris = ntris;
         c.nmesh = nm;
         c.nq = nq;
+        c.quadratic = quad;
         c.h_tri_off = off;
         std::vector<double> vol;
         int64_t ndeg = 0;

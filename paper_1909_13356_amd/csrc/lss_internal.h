@@ -194,6 +194,8 @@ struct Ctx {
     int32_t nmesh = 0, nq = 0;
     std::vector<int64_t> h_tri_off;   // nmesh + 1
     DBuf verts, tris, tri_off, node_off, rule;
+    DBuf tris6;               // quadratic skeleton: 6 indices per triangle (tris then holds the corners)
+    bool quadratic = false;
     bool have_sources = false;
 
     // --- sigma

@@ -25,28 +25,59 @@ __device__ inline void cross3(const double *a, const double *b, double *o) {
 // area-weighted normal J = (P2-P1) x (P3-P1) carries N_hat da; the dipole
 // vector is folded with the kernel normalisation c = 1/(4 sqrt2 pi^1.5 sigma^3)
 // so that the pair kernel needs only S(x), T(x) of x = rho^2/(2 sigma^2).
+// Quadrature node k = j * nq + m.  Flat triangle (eq. tparam): y = P1 + u tu
+// + v tv, J = tu x tv.  Quadratic triangle (tris6 != nullptr; corners, then
+// the edge points of P1P2, P2P3, P3P1): the Lagrange interpolant through the
+// six points written in monomials about P1,
+//   y = P1 + u (A + u C + v E) + v (B + v D),
+//   A = 4 P4 - 3 P1 - P2,  B = 4 P6 - 3 P1 - P3,  C = 2 (P1 + P2 - 2 P4),
+//   D = 2 (P1 + P3 - 2 P6),  E = 4 (P1 - P4 + P5 - P6),
+// and J = y_u x y_v with y_u = A + 2u C + v E, y_v = B + 2v D + u E.
 __global__ void k_prep_sources(int64_t nnodes, int32_t nq, const double *__restrict__ verts,
-                               const int32_t *__restrict__ tris, const double *__restrict__ rule,
-                               const double *__restrict__ sigma, Src *__restrict__ out) {
+                               const int32_t *__restrict__ tris, const int32_t *__restrict__ tris6,
+                               const double *__restrict__ rule, const double *__restrict__ sigma,
+                               Src *__restrict__ out) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nnodes) return;
     int64_t j = k / nq;
     int m = (int)(k - j * nq);
-    const int32_t *t = tris + 3 * j;
-    double P1[3], tu[3], tv[3], J[3];
-    for (int c = 0; c < 3; ++c) {
-        P1[c] = verts[3 * (int64_t)t[0] + c];
-        tu[c] = verts[3 * (int64_t)t[1] + c] - P1[c];
-        tv[c] = verts[3 * (int64_t)t[2] + c] - P1[c];
-    }
-    cross3(tu, tv, J);
     const double u = rule[3 * m], v = rule[3 * m + 1], w = rule[3 * m + 2];
+    double P1[3], y[3], J[3];
+    if (tris6) {
+        const int32_t *t = tris6 + 6 * j;
+        double yu[3], yv[3];
+        for (int c = 0; c < 3; ++c) {
+            P1[c] = verts[3 * (int64_t)t[0] + c];
+            const double d2 = verts[3 * (int64_t)t[1] + c] - P1[c];
+            const double d3 = verts[3 * (int64_t)t[2] + c] - P1[c];
+            const double d4 = verts[3 * (int64_t)t[3] + c] - P1[c];
+            const double d5 = verts[3 * (int64_t)t[4] + c] - P1[c];
+            const double d6 = verts[3 * (int64_t)t[5] + c] - P1[c];
+            const double A = 4.0 * d4 - d2, B = 4.0 * d6 - d3;
+            const double C = 2.0 * (d2 - 2.0 * d4), D = 2.0 * (d3 - 2.0 * d6);
+            const double E = 4.0 * (d5 - d4 - d6);
+            y[c] = P1[c] + (u * (A + u * C + v * E) + v * (B + v * D));
+            yu[c] = A + 2.0 * u * C + v * E;
+            yv[c] = B + 2.0 * v * D + u * E;
+        }
+        cross3(yu, yv, J);
+    } else {
+        const int32_t *t = tris + 3 * j;
+        double tu[3], tv[3];
+        for (int c = 0; c < 3; ++c) {
+            P1[c] = verts[3 * (int64_t)t[0] + c];
+            tu[c] = verts[3 * (int64_t)t[1] + c] - P1[c];
+            tv[c] = verts[3 * (int64_t)t[2] + c] - P1[c];
+            y[c] = P1[c] + u * tu[c] + v * tv[c];
+        }
+        cross3(tu, tv, J);
+    }
     const double s = sigma[j];
     const double cnorm = 1.0 / (4.0 * 1.4142135623730951 * 5.568327996831708 * s * s * s);  // pi^1.5
     Src r;
-    r.yx = P1[0] + u * tu[0] + v * tv[0];
-    r.yy = P1[1] + u * tu[1] + v * tv[1];
-    r.yz = P1[2] + u * tu[2] + v * tv[2];
+    r.yx = y[0];
+    r.yy = y[1];
+    r.yz = y[2];
     r.s2 = 0.5 / (s * s);
     r.ax = cnorm * w * J[0];
     r.ay = cnorm * w * J[1];
@@ -480,8 +511,8 @@ Box make_box(const Ctx &c) {
 // ============================================================== wrappers
 void launch_prep_sources(Ctx &c) {
     hipLaunchKernelGGL(k_prep_sources, dim3(grid_for(c.nnodes)), dim3(kBlk), 0, c.stream, c.nnodes, c.nq,
-                       c.verts.as<double>(), c.tris.as<int32_t>(), c.rule.as<double>(), c.sigma.as<double>(),
-                       c.src.as<Src>());
+                       c.verts.as<double>(), c.tris.as<int32_t>(), c.quadratic ? c.tris6.as<int32_t>() : nullptr,
+                       c.rule.as<double>(), c.sigma.as<double>(), c.src.as<Src>());
     LSS_CHECK_LAUNCH("k_prep_sources");
 }
 
