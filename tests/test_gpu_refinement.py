@@ -18,7 +18,7 @@ import pytest
 
 import oracle
 import paper_1909_13356_amd as lss
-from workloads import dunavant6, chart_nodes, cube_mesh, refine_1to4, triangle_diameters
+from workloads import dunavant6, chart_nodes, cube_mesh, refine_1to4, torus_mesh, triangle_diameters
 
 pytestmark = pytest.mark.gpu
 X0 = np.array([0.1, -0.2, 0.15])
@@ -82,3 +82,56 @@ def test_refinement_study_water_tightness():
         assert abs(rows[(1, p)][1]) < abs(rows[(0, p)][1])
     for level in range(3):
         assert abs(rows[(level, 8)][1]) < abs(rows[(level, 4)][1])
+
+
+def torus_distance(x, R=1.0, r=0.4):
+    return np.abs(np.hypot(np.hypot(x[:, 0], x[:, 1]) - R, x[:, 2]) - r)
+
+
+def test_quadratic_torus_study():
+    """The quadratic-skeleton comparison of the paper's torus example, made
+    quantitative: a torus (R 1, r 0.4) skeleton of flat triangles and one of
+    quadratic triangles with the same corners (edge points on the torus),
+    sigma_j = D_j / lambda with lambda = 10 as in that example, projected with
+    p = 4 charts at three resolutions.  The curved skeleton's charts lie
+    several times closer to the torus and are more water-tight (eps_0 about
+    x0 = (1, 0.05, 0.1), inside the tube); both distances fall with
+    refinement.  The coarsest quadratic level is checked against the oracle."""
+    x0 = np.array([1.0, 0.05, 0.1])
+    uv = chart_nodes(4)
+    w = simplex_weights(uv, 4)
+    rows = {}
+    for lev, (nu, nv) in enumerate(((24, 12), (48, 24), (96, 48))):
+        for quad in (False, True):
+            v, t = torus_mesh(nu, nv, quadratic=quad)
+            corner = np.ascontiguousarray(t[:, :3])
+            sig = triangle_diameters(v, corner) / 10.0
+            c = lss.Context()
+            c.set_sources(v, t, dunavant6())
+            c.set_sigma(sig)
+            c.set_options(precision=lss.FP64, far_field=lss.FAR_FMM)
+            h, x, st, it = c.project(uv)
+            assert np.all(st == lss.NODE_CONVERGED)
+            xu, xv, da, nr = c.chart_geometry(uv, h)
+            assert np.all(np.sum(nr * np.cross(xu, xv), axis=1) > 0)
+            d = x0[None] - x
+            r = np.linalg.norm(d, axis=1)
+            f = np.sum(nr * d, axis=1) / (4 * np.pi * r ** 3)
+            e0 = 1.0 + np.sum((f * da).reshape(len(t), -1) * w[None, :])
+            dist = torus_distance(x)
+            rows[(lev, quad)] = (dist.max(), e0)
+            say("torus %3d x %2d  %-9s  M %5d  max dist %.2e  mean dist %.2e  eps_0 %+.2e  k %d" % (
+                nu, nv, "quadratic" if quad else "flat", len(t), dist.max(), dist.mean(), e0, int(it.max())))
+            if lev == 0 and quad:
+                sel = np.arange(0, len(t), 11)
+                ho, xo, sto, ito = oracle.project(v, t, sig, dunavant6(), uv, sel=sel)
+                idx = (sel[:, None] * len(uv) + np.arange(len(uv))[None]).ravel()
+                eh = np.max(np.abs(h[idx] - ho) / np.repeat(sig[sel], len(uv)))
+                say("  oracle: max |h - h_oracle| / sigma %.1e" % eh)
+                assert np.all(sto == 0) and eh < 1e-11
+            c.close()
+    for lev in range(3):
+        assert rows[(lev, True)][0] < 0.2 * rows[(lev, False)][0]
+        assert abs(rows[(lev, True)][1]) < abs(rows[(lev, False)][1])
+    for quad in (False, True):
+        assert rows[(2, quad)][0] < rows[(1, quad)][0] < rows[(0, quad)][0]
