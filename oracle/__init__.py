@@ -40,6 +40,8 @@ def _load():
         L.oracle_nodes.argtypes = [P, P, i32, i64, P, i32, P, P]
         L.oracle_eval.argtypes = [P, P, i32, i64, P, P, i64, P, i32, P, P, i64, P, P, P, P, ctypes.c_int]
         L.oracle_pseudonormals.argtypes = [P, i64, P, i64, P]
+        L.oracle_radial_G.argtypes = [P, i64, f64, P]
+        L.oracle_hessian.argtypes = [P, P, i32, i64, P, P, i64, P, i32, P, P, i64, P, ctypes.c_int]
         L.oracle_project.argtypes = [P, i64, P, i32, i64, P, i32, P, i64, P, i32, P, i32, P, i64,
                                      f64, i32, P, P, P, P, ctypes.c_int]
         L.oracle_threads.restype = ctypes.c_int
@@ -76,6 +78,14 @@ def _tris(tris):
     return tris, tris.shape[1]
 
 
+def radial_G(rho, sigma):
+    """G(rho) = F'(rho)/rho, the Hessian's third radial function (see oracle.c)."""
+    rho = _f64(rho).ravel()
+    G = np.empty_like(rho)
+    _load().oracle_radial_G(_p(rho), rho.size, float(sigma), _p(G))
+    return G
+
+
 def nodes(verts, tris, rule):
     """Quadrature nodes y (N, 3) and weighted area normals a = w J (N, 3)."""
     verts, rule = _f64(verts), _f64(rule)
@@ -104,6 +114,27 @@ def evaluate(verts, tris, sigma, rule, x, tri_offsets=None, x_mesh=None,
     if with_abs:
         return phi, grad, aphi, agrad
     return phi, grad
+
+
+def hessian(verts, tris, sigma, rule, x, tri_offsets=None, x_mesh=None, nthreads=0):
+    """Hessian of Phi at x (n, 3) by the direct FP64 sum: (n, 6) as xx, xy,
+    xz, yy, yz, zz."""
+    verts, rule, x = _f64(verts), _f64(rule), _f64(x).reshape(-1, 3)
+    sigma = _f64(np.atleast_1d(sigma))
+    tris, nvt = _tris(tris)
+    off = None if tri_offsets is None else np.ascontiguousarray(tri_offsets, dtype=np.int64)
+    xm = None if x_mesh is None else np.ascontiguousarray(x_mesh, dtype=np.int32)
+    out = np.empty((len(x), 6))
+    _load().oracle_hessian(_p(verts), _p(tris), nvt, len(tris), _p(off), _p(sigma), sigma.size,
+                           _p(rule), len(rule), _p(x), _p(xm), len(x), _p(out), int(nthreads))
+    return out
+
+
+def sym3(h6):
+    """(n, 6) xx, xy, xz, yy, yz, zz -> (n, 3, 3)."""
+    h6 = np.asarray(h6)
+    i = np.array([[0, 1, 2], [1, 3, 4], [2, 4, 5]])
+    return h6[:, i]
 
 
 def pseudonormals(verts, tris):
@@ -177,6 +208,71 @@ def chart_geometry(verts, tris, sigma, rule, chart_uv, h, sel=None, tri_offsets=
     da = np.linalg.norm(np.cross(xu, xv), axis=-1)
     nrm = -g / np.linalg.norm(g, axis=-1, keepdims=True)
     return xu.reshape(-1, 3), xv.reshape(-1, 3), da.reshape(-1), nrm.reshape(-1, 3)
+
+
+def chart_curvature(verts, tris, sigma, rule, chart_uv, h, sel=None, tri_offsets=None, nthreads=0):
+    """Second derivatives of the charts x = T + h H and the curvatures of the
+    surface at the chart nodes (section 3.1, eq. uu_vector, uu_vector_aux1,
+    uu_vector_aux2 and the analogous uv, vv expressions).  T and H are linear
+    on the (corner) triangle, so T_uu = H_uu = 0 and, with w_u = x_u,
+    w_v = x_v, g = grad Phi, B = grad grad Phi, D = g . H:
+        h_uu = -(w_u B w_u + 2 h_u g.H_u) / D,   x_uu = 2 h_u H_u + h_uu H,
+        h_uv = -(w_u B w_v + g.(h_u H_v + h_v H_u)) / D,
+                                                 x_uv = h_u H_v + h_v H_u + h_uv H,
+        h_vv = -(w_v B w_v + 2 h_v g.H_v) / D,   x_vv = 2 h_v H_v + h_vv H.
+    (The printed eq. uu_vector groups its last terms as 2 h_u + h_uu H_u; the
+    derivative of eq. u_vector, and eq. uu_vector_aux1 itself, give
+    2 h_u H_u + h_uu H.)  With the outward normal n = -g/|g| and the first and
+    second fundamental forms E, F, G and L = x_uu.n, M = x_uv.n, N = x_vv.n:
+    Gaussian curvature (LN - M^2)/(EG - F^2), mean curvature
+    -(EN - 2FM + GL)/(2(EG - F^2)) (1/R on a sphere of radius R).
+    Returns xuu, xuv, xvv (N, 3), gauss (N), mean (N)."""
+    verts = _f64(verts)
+    tris, _ = _tris(tris)
+    corner = np.ascontiguousarray(tris[:, :3])
+    uv = _f64(chart_uv).reshape(-1, 2)
+    s = np.arange(len(tris)) if sel is None else np.asarray(sel, dtype=np.int64)
+    npn = len(uv)
+    Hv = pseudonormals(verts, corner)
+    t = corner[s]
+    P1, P2, P3 = verts[t[:, 0]][:, None], verts[t[:, 1]][:, None], verts[t[:, 2]][:, None]
+    H1, H2, H3 = Hv[t[:, 0]][:, None], Hv[t[:, 1]][:, None], Hv[t[:, 2]][:, None]
+    u, v = uv[None, :, 0:1], uv[None, :, 1:2]
+    T = P1 + u * (P2 - P1) + v * (P3 - P1)
+    H = H1 + u * (H2 - H1) + v * (H3 - H1)
+    hh = _f64(h).reshape(len(s), npn, 1)
+    x = (T + hh * H).reshape(-1, 3)
+    xm = None
+    if tri_offsets is not None:
+        mesh = np.searchsorted(np.asarray(tri_offsets), s, side="right") - 1
+        xm = np.repeat(mesh, npn).astype(np.int32)
+    _, g = evaluate(verts, tris, sigma, rule, x, tri_offsets=tri_offsets, x_mesh=xm, nthreads=nthreads)
+    B = sym3(hessian(verts, tris, sigma, rule, x, tri_offsets=tri_offsets, x_mesh=xm, nthreads=nthreads))
+    g = g.reshape(len(s), npn, 3)
+    B = B.reshape(len(s), npn, 3, 3)
+    Tu, Tv, Hu, Hw = P2 - P1, P3 - P1, H2 - H1, H3 - H1
+    Hu, Hw = np.broadcast_to(Hu, g.shape), np.broadcast_to(Hw, g.shape)
+    dot = lambda a, b: np.sum(a * b, axis=-1, keepdims=True)
+    D = dot(H, g)
+    hu = -dot(Tu + hh * Hu, g) / D
+    hv = -dot(Tv + hh * Hw, g) / D
+    xu = Tu + hu * H + hh * Hu
+    xv = Tv + hv * H + hh * Hw
+    quad = lambda a, b: np.einsum("...i,...ij,...j->...", a, B, b)[..., None]
+    huu = -(quad(xu, xu) + 2 * hu * dot(g, Hu)) / D
+    huv = -(quad(xu, xv) + dot(g, hu * Hw + hv * Hu)) / D
+    hvv = -(quad(xv, xv) + 2 * hv * dot(g, Hw)) / D
+    xuu = 2 * hu * Hu + huu * H
+    xuv = hu * Hw + hv * Hu + huv * H
+    xvv = 2 * hv * Hw + hvv * H
+    n = -g / np.linalg.norm(g, axis=-1, keepdims=True)
+    E, F, G = dot(xu, xu), dot(xu, xv), dot(xv, xv)
+    L, M, N = dot(xuu, n), dot(xuv, n), dot(xvv, n)
+    det = E * G - F * F
+    gauss = (L * N - M * M) / det
+    mean = -(E * N - 2 * F * M + G * L) / (2 * det)
+    return (xuu.reshape(-1, 3), xuv.reshape(-1, 3), xvv.reshape(-1, 3), gauss.reshape(-1),
+            mean.reshape(-1))
 
 
 def koornwinder(uv, p):

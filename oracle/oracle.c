@@ -38,6 +38,10 @@
  *    derivative is used here, and F also gets its own series for u < 1.)
  *    No cut-off and no far-field approximation: every pair uses the full
  *    kernel, accumulated with Neumaier compensation;
+ *  - the Hessian of the same sum (for the charts' second derivatives,
+ *    section 3.1 eq. uu_vector_aux1/aux2), with the third radial function
+ *    G = F'(rho)/rho:
+ *        grad grad psi da = [ -F (J d^T + d J^T) - (J.d) F I - (J.d) G d d^T ] w;
  *  - vertex pseudonormals (eq. mkvertexpn) and the linear pseudonormal field
  *    on each triangle (eq. mkpseudovec);
  *  - the chart projection: for chart node (u_i, v_i) of triangle j, the root
@@ -111,10 +115,44 @@ static void radial_KF(double rho, double sigma, double *K, double *F)
     }
 }
 
+/* G(rho) = F'(rho)/rho, the third radial function of the Hessian.  With
+ * K = P(3/2, u^2)/(4 pi rho^3) (P the regularised lower incomplete gamma
+ * function), d/drho [P(s, u^2)/rho^(2s)] = -2s P(s+1, u^2)/rho^(2s+1), so
+ * F = -3 P(5/2, u^2)/(4 pi rho^5) and G = 15 P(7/2, u^2)/(4 pi rho^7), where
+ * P(s+1, t) = P(s, t) - t^s e^-t / Gamma(s+1) takes P(3/2, t) = erf(u) -
+ * 2 u e^-t / sqrt(pi) up to s = 7/2.  For u < 1.5 the same function by the
+ * term-wise derivative of the F series:
+ *   G = [sum_k 2 (-1)^k u^2k / (k! (2k+7))] / (4 sqrt(2 pi^3) sigma^7). */
+static double radial_G(double rho, double sigma)
+{
+    const double u = rho / (sqrt(2.0) * sigma);
+    if (u < 1.5) {
+        const double u2 = u * u;
+        double p = 1.0, s = 0.0;
+        for (int k = 0; k < 60; ++k) {
+            const double t = 2.0 * p / (2.0 * k + 7.0);
+            s += t;
+            if (fabs(t) < 1e-18 * fabs(s)) break;
+            p *= -u2 / (double)(k + 1);
+        }
+        return s / (4.0 * sqrt(2.0 * ORC_PI * ORC_PI * ORC_PI) * pow(sigma, 7.0));
+    }
+    const double t = u * u, e = exp(-t);
+    const double P32 = erf(u) - 2.0 * u * e / sqrt(ORC_PI);
+    const double P52 = P32 - pow(t, 1.5) * e / (0.75 * sqrt(ORC_PI));          /* Gamma(5/2) */
+    const double P72 = P52 - pow(t, 2.5) * e / (1.875 * sqrt(ORC_PI));         /* Gamma(7/2) */
+    return 15.0 * P72 / (4.0 * ORC_PI * pow(rho, 7.0));
+}
+
 /* exported for the kernel-function checks: K, F at rho for one sigma */
 void oracle_radial(const double *rho, int64_t n, double sigma, double *K, double *F)
 {
     for (int64_t i = 0; i < n; ++i) radial_KF(rho[i], sigma, &K[i], &F[i]);
+}
+
+void oracle_radial_G(const double *rho, int64_t n, double sigma, double *G)
+{
+    for (int64_t i = 0; i < n; ++i) G[i] = radial_G(rho[i], sigma);
 }
 
 /* --------------------------------------------------------- quadrature nodes */
@@ -259,6 +297,48 @@ void oracle_eval(const double *verts, const int32_t *tris, int32_t nvt, int64_t 
     for (int64_t i = 0; i < n; ++i)
         eval_point(&S, x + 3 * i, x_mesh ? x_mesh[i] : 0, &phi[i], grad + 3 * i,
                    aphi ? &aphi[i] : NULL, agrad ? &agrad[i] : NULL);
+}
+
+/* Hessian of Phi at n targets (the second x-derivative of the same discrete
+ * sum, needed for the second derivatives of the charts, section 3.1 eq.
+ * uu_vector_aux1/aux2).  Per node, with a = w J, d = x - y:
+ *   d2 psi / dx_i dx_j = -F (a_i d_j + a_j d_i) - (a.d) F delta_ij - (a.d) G d_i d_j.
+ * Output hess (n, 6): xx, xy, xz, yy, yz, zz.  Full kernel for every pair. */
+void oracle_hessian(const double *verts, const int32_t *tris, int32_t nvt, int64_t ntris,
+                    const int64_t *tri_off, const double *sigma, int64_t nsigma,
+                    const double *rule, int32_t nq,
+                    const double *x, const int32_t *x_mesh, int64_t n, double *hess, int nthreads)
+{
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t mesh = x_mesh ? x_mesh[i] : 0;
+        int64_t j0 = 0, j1 = ntris;
+        if (tri_off) { j0 = tri_off[mesh]; j1 = tri_off[mesh + 1]; }
+        nsum S[3][3];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) S[r][c].s = S[r][c].c = 0.0;
+        for (int64_t j = j0; j < j1; ++j) {
+            const double sg = nsigma == 1 ? sigma[0] : sigma[j];
+            for (int m = 0; m < nq; ++m) {
+                double y[3], a[3], d[3];
+                src_node(verts, tris, nvt, j, rule + 3 * m, y, a);
+                for (int c = 0; c < 3; ++c) d[c] = x[3 * i + c] - y[c];
+                const double rho = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                double K, F;
+                radial_KF(rho, sg, &K, &F);
+                const double G = radial_G(rho, sg);
+                const double ad = a[0] * d[0] + a[1] * d[1] + a[2] * d[2];
+                for (int r = 0; r < 3; ++r)
+                    for (int c = r; c < 3; ++c)
+                        nsum_add(&S[r][c], -F * (a[r] * d[c] + a[c] * d[r]) - (r == c ? ad * F : 0.0)
+                                               - ad * G * d[r] * d[c]);
+            }
+        }
+        double *o = hess + 6 * i;
+        o[0] = nsum_get(&S[0][0]); o[1] = nsum_get(&S[0][1]); o[2] = nsum_get(&S[0][2]);
+        o[3] = nsum_get(&S[1][1]); o[4] = nsum_get(&S[1][2]); o[5] = nsum_get(&S[2][2]);
+    }
 }
 
 /* ----------------------------------------------------------- pseudonormals */

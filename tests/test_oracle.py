@@ -620,3 +620,124 @@ def test_quadratic_torus_level_set_closer_to_the_surface():
         pc, _ = oracle.evaluate(v, t, s, rule, core)
         pf, _ = oracle.evaluate(v, t, s, rule, far)
         assert np.max(np.abs(pc - 1)) < 1e-3 and np.max(np.abs(pf)) < 1e-3
+
+
+# ------------------------------------------------ Hessian and chart curvature
+def box_hessian(x, s, lo=0.0, hi=1.0):
+    """Hessian of the Gaussian convolution of the box indicator (n, 3, 3):
+    products of the 1-D factor f and its first two derivatives."""
+    el, eh = np.exp(-(x - lo) ** 2 / (2 * s * s)), np.exp(-(hi - x) ** 2 / (2 * s * s))
+    f = 0.5 * (erf((hi - x) / (RT2 * s)) + erf((x - lo) / (RT2 * s)))
+    f1 = (el - eh) / (np.sqrt(2 * PI) * s)
+    f2 = (-(x - lo) * el - (hi - x) * eh) / (np.sqrt(2 * PI) * s ** 3)
+    out = np.empty((len(x), 3, 3))
+    for i in range(3):
+        for j in range(3):
+            d = [f[:, k] for k in range(3)]
+            if i == j:
+                d[i] = f2[:, i]
+            else:
+                d[i], d[j] = f1[:, i], f1[:, j]
+            out[:, i, j] = d[0] * d[1] * d[2]
+    return out
+
+
+def test_radial_G_vs_incomplete_gamma_and_derivative():
+    """G = F'/rho = 15 P(7/2, u^2) / (4 pi rho^7) against mpmath at 40 digits
+    across the u = 1.5 switch, and against central differences of F."""
+    mp.mp.dps = 40
+    for sigma in (0.05, 1.0):
+        us = np.concatenate([np.linspace(1e-4, 4, 81), [1.4999999, 1.5, 1.5000001, 5.66, 8, 12]])
+        rho = us * RT2 * sigma
+        G = oracle.radial_G(rho, sigma)
+        for i, u in enumerate(us):
+            r = mp.mpf(rho[i])
+            Gx = 15 * mp.gammainc(3.5, 0, mp.mpf(u) ** 2, regularized=True) / (4 * mp.pi * r ** 7)
+            assert abs(G[i] - float(Gx)) <= 1e-14 * abs(float(Gx)), (sigma, u)
+        r = np.linspace(0.3, 6.0, 40) * sigma
+        d = 1e-5 * sigma
+        fd = (oracle.radial(r + d, sigma)[1] - oracle.radial(r - d, sigma)[1]) / (2 * d) / r
+        assert np.max(np.abs(fd - oracle.radial_G(r, sigma)) / np.abs(oracle.radial_G(r, sigma))) < 1e-6
+
+
+def test_hessian_box_closed_form():
+    v, t = cube_mesh(32)
+    x = box_targets(48, seed=12)
+    B = oracle.sym3(oracle.hessian(v, t, [0.1], dunavant6(), x))
+    ref = box_hessian(x, 0.1)
+    assert np.abs(B - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+def test_hessian_is_the_derivative_of_the_gradient_and_harmonic_far_away():
+    v, t = star_surface(6, lmax=6, var0=0.1, seed=3)
+    sig = 0.5 * triangle_diameters(v, t)
+    rng = np.random.default_rng(4)
+    x = rng.normal(size=(12, 3)) * 0.6
+    B = oracle.sym3(oracle.hessian(v, t, sig, dunavant6(), x))
+    d = 1e-4
+    for c in range(3):
+        e = np.zeros(3)
+        e[c] = d
+        gp = oracle.evaluate(v, t, sig, dunavant6(), x + e)[1]
+        gm = oracle.evaluate(v, t, sig, dunavant6(), x - e)[1]
+        gp2 = oracle.evaluate(v, t, sig, dunavant6(), x + 2 * e)[1]
+        gm2 = oracle.evaluate(v, t, sig, dunavant6(), x - 2 * e)[1]
+        fd = (8 * (gp - gm) - (gp2 - gm2)) / (12 * d)              # fourth-order central difference
+        assert np.abs(fd - B[:, :, c]).max() < 1e-7 * np.abs(B).max()
+    # an open patch (on a closed surface the far field cancels to rounding):
+    # beyond 8 sigma its field is the Laplace double layer, so trace B = 0
+    far = np.array([[4.0, 0.5, -1.0], [0.2, -5.0, 0.3]])           # > 8 sigma_max from every node
+    Bf = oracle.sym3(oracle.hessian(v, t[:60], sig[:60], dunavant6(), far))
+    tr = np.trace(Bf, axis1=1, axis2=2)
+    assert np.all(np.abs(tr) < 1e-11 * np.abs(Bf).reshape(2, -1).max(axis=1))
+
+
+def test_chart_curvature_matches_implicit_surface_and_finite_differences():
+    """x_uu, x_uv, x_vv against central differences of the oracle's x_u, x_v
+    at shifted chart nodes; the Gaussian and mean curvature from the charts
+    equal those of the level set computed from grad Phi and the Hessian alone
+    (Goldman's formulas: K = -det [[B, g], [g^T, 0]] / |g|^4, mean =
+    (g^T B g - |g|^2 tr B) / (2 |g|^3) for the outward normal -g/|g|)."""
+    v, t = star_surface(6, lmax=6, var0=0.1, seed=3)
+    sig = 0.5 * triangle_diameters(v, t)
+    uv = np.array([[0.2, 0.3], [0.55, 0.15], [0.1, 0.7]])
+    sel = np.array([3, 40, 111])
+    rule = dunavant6()
+    h, x, st, _ = oracle.project(v, t, sig, rule, uv, tau=1e-14, sel=sel)
+    assert np.all(st == 0)
+    xuu, xuv, xvv, K, Hm = oracle.chart_curvature(v, t, sig, rule, uv, h, sel=sel)
+    d = 1e-4
+    for k, (du, dv) in enumerate(((d, 0.0), (0.0, d))):
+        hp = oracle.project(v, t, sig, rule, uv + [du, dv], tau=1e-14, sel=sel)[0]
+        hm = oracle.project(v, t, sig, rule, uv - [du, dv], tau=1e-14, sel=sel)[0]
+        up = oracle.chart_geometry(v, t, sig, rule, uv + [du, dv], hp, sel=sel)
+        dn = oracle.chart_geometry(v, t, sig, rule, uv - [du, dv], hm, sel=sel)
+        fdu, fdv = (up[0] - dn[0]) / (2 * d), (up[1] - dn[1]) / (2 * d)
+        an_u, an_v = (xuu, xuv) if k == 0 else (xuv, xvv)
+        scale = max(np.abs(xuu).max(), np.abs(xvv).max())
+        assert np.abs(fdu - an_u).max() < 1e-5 * scale
+        assert np.abs(fdv - an_v).max() < 1e-5 * scale
+    _, g = oracle.evaluate(v, t, sig, rule, x)
+    B = oracle.sym3(oracle.hessian(v, t, sig, rule, x))
+    gn = np.linalg.norm(g, axis=1)
+    bord = np.zeros((len(x), 4, 4))
+    bord[:, :3, :3], bord[:, :3, 3], bord[:, 3, :3] = B, g, g
+    Ki = -np.linalg.det(bord) / gn ** 4
+    Hi = (np.einsum("ni,nij,nj->n", g, B, g) - gn ** 2 * np.trace(B, axis1=1, axis2=2)) / (2 * gn ** 3)
+    assert np.abs(K - Ki).max() < 1e-9 * np.abs(Ki).max()
+    assert np.abs(Hm - Hi).max() < 1e-9 * np.abs(Hi).max()
+
+
+def test_chart_curvature_sphere():
+    """On a fine sphere skeleton with a narrow sigma the level set is a
+    sphere of radius |x|: Gaussian curvature 1/|x|^2, mean curvature 1/|x|."""
+    v, t = icosphere(4)
+    uv = chart_nodes(2)
+    sel = np.arange(0, len(t), 97)
+    rule = dunavant6()
+    h, x, st, _ = oracle.project(v, t, [0.05], rule, uv, sel=sel)
+    assert np.all(st == 0)
+    _, _, _, K, Hm = oracle.chart_curvature(v, t, [0.05], rule, uv, h, sel=sel)
+    R = np.linalg.norm(x, axis=1)
+    assert np.abs(K * R ** 2 - 1).max() < 5e-2
+    assert np.abs(Hm * R - 1).max() < 2.5e-2
