@@ -243,6 +243,37 @@ int lss_project(lss_ctx *ctx, const double *chart_uv, int32_t np,
 int lss_chart_geometry(lss_ctx *ctx, const double *chart_uv, int32_t np, const double *h, double *xu, double *xv,
                        double *da, double *normal, unsigned flags);
 
+/* Hessian of Phi (section 3.1: needed for the charts' second derivatives,
+ * eq. uu_vector_aux1/aux2), with Phi and grad Phi from the same pass, at n
+ * targets x (n,3); x_mesh as for lss_eval.  hess (n,6) receives the
+ * symmetric matrix as xx, xy, xz, yy, yz, zz; phi (n) and grad (n,3) may be
+ * NULL.  Every (target, node) pair of the target's mesh is summed with the
+ * full kernel and its third radial function G = F'(rho)/rho, in FP64,
+ * whatever the precision and far-field options: the cost is n times the
+ * mesh's node count, meant for the chart nodes of moderate meshes.  Host or
+ * device arrays per flags; returns when the outputs are written. */
+int lss_eval_hessian(lss_ctx *ctx, const double *x, const int32_t *x_mesh, int64_t n, double *phi, double *grad,
+                     double *hess, unsigned flags);
+
+/* Second derivatives and curvatures of the charts x = T + h H at the chart
+ * nodes (section 3.1, eq. uu_vector, uu_vector_aux1, uu_vector_aux2 and the
+ * analogous uv, vv expressions), for distances h (ntris*np) from
+ * lss_project.  T and H are linear on the (corner) triangle, so with
+ * B = grad grad Phi (from lss_eval_hessian's sum), g = grad Phi, D = g.H and
+ * x_u, x_v, h_u, h_v as in lss_chart_geometry:
+ *   xuu (N,3) = 2 h_u H_u + h_uu H,  h_uu = -(x_u.B x_u + 2 h_u g.H_u)/D;
+ *   xuv (N,3) = h_u H_v + h_v H_u + h_uv H,
+ *               h_uv = -(x_u.B x_v + g.(h_u H_v + h_v H_u))/D;
+ *   xvv (N,3) = 2 h_v H_v + h_vv H,  h_vv = -(x_v.B x_v + 2 h_v g.H_v)/D;
+ *   gauss (N) = (LN - M^2)/(EG - F^2), mean (N) = -(EN - 2FM + GL)/(2(EG - F^2))
+ *   (first and second fundamental forms with the outward normal -g/|g|, so
+ *   a sphere of radius R has mean curvature 1/R).
+ * N = ntris * np.  Any output may be NULL.  The cost is that of
+ * lss_eval_hessian at the N chart points.  Host or device arrays as for
+ * lss_project; returns when the outputs are written. */
+int lss_chart_curvature(lss_ctx *ctx, const double *chart_uv, int32_t np, const double *h, double *xuu,
+                        double *xuv, double *xvv, double *gauss, double *mean, unsigned flags);
+
 /* Interpolation of chart data between the chart nodes (section 3.3: a chart
  * is a polynomial of total degree p on the standard simplex, represented in
  * the orthogonal Koornwinder basis through its values at the p-th order

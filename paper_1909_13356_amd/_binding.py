@@ -23,6 +23,7 @@ TRI6 = 2
 EXPORTED_SYMBOLS = ["lss_create", "lss_destroy", "lss_last_error", "lss_synchronize",
                     "lss_set_sources", "lss_set_sigma", "lss_set_options", "lss_get_options",
                     "lss_build", "lss_eval", "lss_project", "lss_chart_geometry", "lss_chart_interp",
+                    "lss_eval_hessian", "lss_chart_curvature",
                     "lss_autotune", "lss_get_stats"]
 
 _CODES = {1: "LSS_EINVAL", 2: "LSS_ENOMEM", 3: "LSS_EHIP", 4: "LSS_ESTATE", 5: "LSS_EORIENT"}
@@ -94,6 +95,8 @@ def load_library():
     L.lss_project.argtypes = [P, P, i32, P, P, P, P, u]
     L.lss_chart_geometry.argtypes = [P, P, i32, P, P, P, P, P, u]
     L.lss_chart_interp.argtypes = [P, P, i32, P, i32, P, i32, P, u]
+    L.lss_eval_hessian.argtypes = [P, P, P, i64, P, P, P, u]
+    L.lss_chart_curvature.argtypes = [P, P, i32, P, P, P, P, P, P, u]
     L.lss_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
     L.lss_autotune.argtypes = [P, P, i64, u, ctypes.c_double, ctypes.c_char_p, ctypes.POINTER(Options)]
     _lib = L
@@ -302,6 +305,53 @@ class Context:
         pnr, _, k4 = _ptr(nr, np.float64)
         self._check(self._lib.lss_chart_geometry(self._h, pu, npn, ph, pxu, pxv, pda, pnr, fh))
         return xu, xv, da, nr
+
+    def eval_hessian(self, x, x_mesh=None):
+        """Phi (n,), grad Phi (n, 3) and the Hessian (n, 6: xx, xy, xz, yy,
+        yz, zz) at targets x (n, 3) by the direct FP64 sum.  Device tensors
+        in, device tensors out."""
+        n = len(x)
+        if _is_torch(x) and x.device.type == "cuda":
+            import torch
+            mk = lambda *s: torch.empty(s, dtype=torch.float64, device=x.device)
+        else:
+            mk = lambda *s: np.empty(s)
+        phi, grad, hess = mk(n), mk(n, 3), mk(n, 6)
+        px, fx, kx = _ptr(x, np.float64)
+        pm, fm, km = _ptr(x_mesh, np.int32)
+        if x_mesh is not None and fm != fx:
+            raise ValueError("x and x_mesh must both be host arrays or both device tensors")
+        pp, _, k1 = _ptr(phi, np.float64)
+        pg, _, k2 = _ptr(grad, np.float64)
+        ph, _, k3 = _ptr(hess, np.float64)
+        self._check(self._lib.lss_eval_hessian(self._h, px, pm, n, pp, pg, ph, fx))
+        return phi, grad, hess
+
+    def chart_curvature(self, chart_uv, h):
+        """Second derivatives x_uu, x_uv, x_vv (N,3) and the Gaussian and mean
+        curvature (N) of the charts at the chart nodes (index j * np + i), for
+        distances h from project().  Device tensors in, device tensors out."""
+        npn = len(chart_uv)
+        N = self.ntris * npn
+        if _is_torch(h) and h.device.type == "cuda":
+            import torch
+            dev = h.device
+            uv = chart_uv if _is_torch(chart_uv) else torch.as_tensor(np.ascontiguousarray(chart_uv, np.float64), device=dev)
+            mk = lambda *s: torch.empty(s, dtype=torch.float64, device=dev)
+        else:
+            uv = np.ascontiguousarray(chart_uv, np.float64)
+            h = np.ascontiguousarray(h, np.float64)
+            mk = lambda *s: np.empty(s)
+        if len(h) != N:
+            raise ValueError("h must have ntris * len(chart_uv) entries")
+        out = [mk(N, 3), mk(N, 3), mk(N, 3), mk(N), mk(N)]
+        pu, fu, ku = _ptr(uv, np.float64)
+        ph, fh, kh = _ptr(h, np.float64)
+        if fu != fh:
+            raise ValueError("chart_uv and h must both be host arrays or both device tensors")
+        ptrs = [_ptr(o, np.float64)[0] for o in out]
+        self._check(self._lib.lss_chart_curvature(self._h, pu, npn, ph, *ptrs, fh))
+        return tuple(out)
 
     def chart_interp(self, chart_uv, f, eval_uv):
         """Values at eval_uv (ne,2) of every triangle's polynomial interpolant

@@ -383,6 +383,94 @@ void chart_geometry(Ctx &c, const double *uv, int32_t np, const double *h, doubl
     LSS_HIP(hipStreamSynchronize(c.stream));
 }
 
+// Hessian (and Phi, grad Phi) by the direct sum over the target's mesh
+void eval_hessian(Ctx &c, const double *x, const int32_t *xm, int64_t n, double *phi, double *grad, double *hess,
+                  unsigned flags) {
+    if (n < 0) fail(LSS_EINVAL, "lss_eval_hessian: n < 0");
+    if (n == 0) return;
+    if (n > (int64_t)INT32_MAX) fail(LSS_EINVAL, "lss_eval_hessian: n exceeds 2^31-1");
+    if (!x || !hess) fail(LSS_EINVAL, "lss_eval_hessian: x and hess must be non-null");
+    if (c.nmesh > 1 && !xm) fail(LSS_EINVAL, "lss_eval_hessian: x_mesh is required for a batch of meshes");
+    build(c);
+    const bool dev = flags & LSS_PTR_DEVICE;
+    DBuf hx, hxm, hphi, hgrad, hhess;
+    const double *dx = x;
+    const int32_t *dxm = c.nmesh > 1 ? xm : nullptr;
+    double *dphi = phi, *dgrad = grad, *dhess = hess;
+    if (!dev) {
+        upload(c, hx, x, sizeof(double) * 3 * n, 0);
+        dx = hx.as<double>();
+        if (dxm) {
+            upload(c, hxm, xm, sizeof(int32_t) * n, 0);
+            dxm = hxm.as<int32_t>();
+        }
+        if (phi) { hphi.ensure(sizeof(double) * n); dphi = hphi.as<double>(); }
+        if (grad) { hgrad.ensure(sizeof(double) * 3 * n); dgrad = hgrad.as<double>(); }
+        hhess.ensure(sizeof(double) * 6 * n);
+        dhess = hhess.as<double>();
+    }
+    if (dxm) {
+        DBuf bad;
+        bad.ensure(8);
+        LSS_HIP(hipMemsetAsync(bad.p, 0, 8, c.stream));
+        hipLaunchKernelGGL(k_check_mesh_ids, dim3(grid_for(n)), dim3(256), 0, c.stream, n, dxm, c.nmesh,
+                           bad.as<unsigned long long>());
+        unsigned long long nb = 0;
+        LSS_HIP(hipMemcpyAsync(&nb, bad.p, 8, hipMemcpyDeviceToHost, c.stream));
+        LSS_HIP(hipStreamSynchronize(c.stream));
+        if (nb) fail(LSS_EINVAL, "lss_eval_hessian: x_mesh values outside [0, nmesh)");
+    }
+    launch_hessian_direct(c, n, dx, dxm, dphi, dgrad, dhess);
+    if (!dev) {
+        if (phi) LSS_HIP(hipMemcpyAsync(phi, dphi, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
+        if (grad) LSS_HIP(hipMemcpyAsync(grad, dgrad, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, c.stream));
+        LSS_HIP(hipMemcpyAsync(hess, dhess, sizeof(double) * 6 * n, hipMemcpyDeviceToHost, c.stream));
+    }
+    LSS_HIP(hipStreamSynchronize(c.stream));
+}
+
+void chart_curvature(Ctx &c, const double *uv, int32_t np, const double *h, double *xuu, double *xuv, double *xvv,
+                     double *gauss, double *mean, unsigned flags) {
+    if (np <= 0) fail(LSS_EINVAL, "lss_chart_curvature: np must be >= 1");
+    if (!uv || !h) fail(LSS_EINVAL, "lss_chart_curvature: chart_uv and h must be non-null");
+    build(c);
+    const int64_t N = c.ntris * (int64_t)np;
+    if (N > (int64_t)INT32_MAX) fail(LSS_EINVAL, "lss_chart_curvature: ntris * np exceeds 2^31-1");
+    if (N == 0) return;
+    const bool dev = flags & LSS_PTR_DEVICE;
+    DBuf duv, dh, x, xm, grad, hess, o[5];
+    upload(c, duv, uv, sizeof(double) * 2 * np, flags);
+    const double *ph = h;
+    if (!dev) {
+        upload(c, dh, h, sizeof(double) * N, 0);
+        ph = dh.as<double>();
+    }
+    x.ensure(sizeof(double) * 3 * N);
+    if (c.nmesh > 1) xm.ensure(sizeof(int32_t) * N);
+    launch_chart_points(c, duv.as<double>(), np, N, ph, x.as<double>(), c.nmesh > 1 ? xm.as<int32_t>() : nullptr);
+    grad.ensure(sizeof(double) * 3 * N);
+    hess.ensure(sizeof(double) * 6 * N);
+    launch_hessian_direct(c, N, x.as<double>(), c.nmesh > 1 ? xm.as<int32_t>() : nullptr, nullptr,
+                          grad.as<double>(), hess.as<double>());
+    double *out[5] = {xuu, xuv, xvv, gauss, mean};
+    const int width[5] = {3, 3, 3, 1, 1};
+    double *q[5];
+    for (int k = 0; k < 5; ++k) {
+        q[k] = out[k];
+        if (!dev && out[k]) {
+            o[k].ensure(sizeof(double) * width[k] * N);
+            q[k] = o[k].as<double>();
+        }
+    }
+    launch_chart_curvature(c, duv.as<double>(), np, N, ph, grad.as<double>(), hess.as<double>(), q[0], q[1], q[2],
+                           q[3], q[4]);
+    if (!dev)
+        for (int k = 0; k < 5; ++k)
+            if (out[k])
+                LSS_HIP(hipMemcpyAsync(out[k], q[k], sizeof(double) * width[k] * N, hipMemcpyDeviceToHost,
+                                       c.stream));
+    LSS_HIP(hipStreamSynchronize(c.stream));
+}
 
 // ------------------------------------------------------------- autotuner
 std::string tune_key(const Ctx &c) {
@@ -713,6 +801,18 @@ int lss_eval(lss_ctx *ctx, const double *x, const int32_t *x_mesh, int64_t n, do
 int lss_project(lss_ctx *ctx, const double *chart_uv, int32_t np, double *h, double *xout, int8_t *status,
                 int8_t *iters, unsigned flags) {
     return lss::guarded(ctx, [&](Ctx &c) { lss::project(c, chart_uv, np, h, xout, status, iters, flags); });
+}
+
+int lss_eval_hessian(lss_ctx *ctx, const double *x, const int32_t *x_mesh, int64_t n, double *phi, double *grad,
+                     double *hess, unsigned flags) {
+    return lss::guarded(ctx, [&](Ctx &c) { lss::eval_hessian(c, x, x_mesh, n, phi, grad, hess, flags); });
+}
+
+int lss_chart_curvature(lss_ctx *ctx, const double *chart_uv, int32_t np, const double *h, double *xuu,
+                        double *xuv, double *xvv, double *gauss, double *mean, unsigned flags) {
+    return lss::guarded(ctx, [&](Ctx &c) {
+        lss::chart_curvature(c, chart_uv, np, h, xuu, xuv, xvv, gauss, mean, flags);
+    });
 }
 
 int lss_chart_geometry(lss_ctx *ctx, const double *chart_uv, int32_t np, const double *h, double *xu, double *xv,

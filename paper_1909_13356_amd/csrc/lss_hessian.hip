@@ -1,0 +1,213 @@
+// Hessian of the smoothed indicator and the second derivatives of the charts
+// (section 3.1, eq. uu_vector, uu_vector_aux1, uu_vector_aux2 and their uv,
+// vv analogues), on the device.
+//
+// Per source node (y, a' = c w J, s2 = 1/(2 sigma^2), c = 1/(4 sqrt2 pi^1.5
+// sigma^3)) and target x, d = x - y, t = |d|^2 s2 = u^2, the three radial
+// functions of the kernel in units of the folded amplitude, K c = k1,
+// F c = k2, G c = k3 (F = K'/rho, G = F'/rho), are
+//   t < 9/4:   k1 = S(3), k2 = -2 s2 S(5), k3 = 4 s2^2 S(7),
+//              S(m) = sum_k 2 (-t)^k / (k! (2k + m))      (term-wise series)
+//   t >= 9/4:  with q = 2/sqrt(pi), e = exp(-t):
+//              P3 = erf(u) - q u e,  P5 = P3 - q (2/3) u^3 e,  P7 = P5 - q (4/15) u^5 e
+//              (the regularised incomplete gamma functions P(3/2|5/2|7/2, t)),
+//              k1 = (sqrt(pi)/2) P3 / u^3, k2 = -(3 sqrt(pi)/2) s2 P5 / u^5,
+//              k3 = (15 sqrt(pi)/2) s2^2 P7 / u^7,  and P3 = P5 = P7 = 1 for
+//              t >= 50, where the dropped terms are below 1e-18.
+// Then Phi -= (a'.d) k1, grad Phi += -a' k1 - (a'.d) k2 d, and
+//   Hess += -k2 (a' d^T + d a'^T) - (a'.d) k2 I - (a'.d) k3 d d^T.
+// Every pair uses the full kernel (no cut, no far-field expansion).
+#include "lss_internal.h"
+
+namespace lss {
+namespace {
+
+constexpr double kSqrtPi = 1.7724538509055160273;
+
+inline unsigned blocks256(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+__device__ inline void radial3(double t, double s2, double &k1, double &k2, double &k3) {
+    if (t < 2.25) {
+        double p = 1.0, a3 = 0.0, a5 = 0.0, a7 = 0.0;
+#pragma unroll
+        for (int k = 0; k < 30; ++k) {
+            a3 += p * (2.0 / (2 * k + 3));
+            a5 += p * (2.0 / (2 * k + 5));
+            a7 += p * (2.0 / (2 * k + 7));
+            p *= -t * (1.0 / (k + 1));
+        }
+        k1 = a3;
+        k2 = -2.0 * s2 * a5;
+        k3 = 4.0 * s2 * s2 * a7;
+        return;
+    }
+    const double u = sqrt(t);
+    double P3 = 1.0, P5 = 1.0, P7 = 1.0;
+    if (t < 50.0) {
+        const double qe = (2.0 / kSqrtPi) * exp(-t);
+        const double u3 = u * t;
+        P3 = erf(u) - qe * u;
+        P5 = P3 - qe * (2.0 / 3.0) * u3;
+        P7 = P5 - qe * (4.0 / 15.0) * u3 * t;
+    }
+    const double iu = 1.0 / u, iu2 = iu * iu;
+    const double iu3 = iu * iu2, iu5 = iu3 * iu2, iu7 = iu5 * iu2;
+    k1 = (0.5 * kSqrtPi) * P3 * iu3;
+    k2 = -(1.5 * kSqrtPi) * s2 * P5 * iu5;
+    k3 = (7.5 * kSqrtPi) * s2 * s2 * P7 * iu7;
+}
+
+// one thread per target; the nodes of the target's mesh are read in order,
+// so a wave whose targets share a mesh reads each record once (broadcast)
+__global__ void __launch_bounds__(256) k_hessian_direct(int64_t n, const double *__restrict__ x,
+                                                        const int32_t *__restrict__ xm,
+                                                        const int64_t *__restrict__ node_off,
+                                                        const Src *__restrict__ src, double *phi, double *grad,
+                                                        double *hess) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t m = xm ? xm[i] : 0;
+    const int64_t j0 = node_off[m], j1 = node_off[m + 1];
+    const double px = x[3 * i], py = x[3 * i + 1], pz = x[3 * i + 2];
+    double f = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    double hxx = 0.0, hxy = 0.0, hxz = 0.0, hyy = 0.0, hyz = 0.0, hzz = 0.0;
+    for (int64_t j = j0; j < j1; ++j) {
+        const Src s = src[j];
+        const double dx = px - s.yx, dy = py - s.yy, dz = pz - s.yz;
+        const double t = (dx * dx + dy * dy + dz * dz) * s.s2;
+        double k1, k2, k3;
+        radial3(t, s.s2, k1, k2, k3);
+        const double ad = s.ax * dx + s.ay * dy + s.az * dz;
+        f -= ad * k1;
+        const double adk2 = ad * k2, adk3 = ad * k3;
+        gx -= s.ax * k1 + adk2 * dx;
+        gy -= s.ay * k1 + adk2 * dy;
+        gz -= s.az * k1 + adk2 * dz;
+        const double ex = adk3 * dx, ey = adk3 * dy, ez = adk3 * dz;
+        hxx -= 2.0 * k2 * s.ax * dx + adk2 + ex * dx;
+        hyy -= 2.0 * k2 * s.ay * dy + adk2 + ey * dy;
+        hzz -= 2.0 * k2 * s.az * dz + adk2 + ez * dz;
+        hxy -= k2 * (s.ax * dy + s.ay * dx) + ex * dy;
+        hxz -= k2 * (s.ax * dz + s.az * dx) + ex * dz;
+        hyz -= k2 * (s.ay * dz + s.az * dy) + ey * dz;
+    }
+    if (phi) phi[i] = f;
+    if (grad) {
+        grad[3 * i] = gx;
+        grad[3 * i + 1] = gy;
+        grad[3 * i + 2] = gz;
+    }
+    double *o = hess + 6 * i;
+    o[0] = hxx;
+    o[1] = hxy;
+    o[2] = hxz;
+    o[3] = hyy;
+    o[4] = hyz;
+    o[5] = hzz;
+}
+
+// Second derivatives and curvatures of chart j at node i (index q = j np + i).
+// T and H are linear on the corner triangle (T_uu = H_uu = 0); with w_u = x_u,
+// w_v = x_v, g = grad Phi, B = the Hessian, D = g . H:
+//   h_uu = -(w_u B w_u + 2 h_u g.H_u) / D,             x_uu = 2 h_u H_u + h_uu H
+//   h_uv = -(w_u B w_v + g.(h_u H_v + h_v H_u)) / D,   x_uv = h_u H_v + h_v H_u + h_uv H
+//   h_vv = -(w_v B w_v + 2 h_v g.H_v) / D,             x_vv = 2 h_v H_v + h_vv H
+// Curvatures from the fundamental forms with the outward normal n = -g/|g|:
+//   Gaussian (LN - M^2)/(EG - F^2), mean -(EN - 2FM + GL)/(2(EG - F^2)).
+__global__ void k_chart_curvature(int64_t N, const double *__restrict__ verts, const int32_t *__restrict__ tris,
+                                  const double *__restrict__ vH, const double *__restrict__ uv, int32_t np,
+                                  const double *__restrict__ h, const double *__restrict__ grad,
+                                  const double *__restrict__ hess, double *xuu, double *xuv, double *xvv,
+                                  double *gauss, double *mean) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N) return;
+    const int64_t j = q / np;
+    const int i = (int)(q - j * np);
+    const double u = uv[2 * i], v = uv[2 * i + 1];
+    const int32_t *t = tris + 3 * j;
+    double H[3], Tu[3], Tv[3], Hu[3], Hv[3], g[3];
+    for (int c = 0; c < 3; ++c) {
+        const double h1 = vH[3 * (int64_t)t[0] + c], h2 = vH[3 * (int64_t)t[1] + c], h3 = vH[3 * (int64_t)t[2] + c];
+        const double p1 = verts[3 * (int64_t)t[0] + c];
+        Tu[c] = verts[3 * (int64_t)t[1] + c] - p1;
+        Tv[c] = verts[3 * (int64_t)t[2] + c] - p1;
+        Hu[c] = h2 - h1;
+        Hv[c] = h3 - h1;
+        H[c] = h1 + u * Hu[c] + v * Hv[c];
+        g[c] = grad[3 * q + c];
+    }
+    const double *b = hess + 6 * q;
+    const double B[3][3] = {{b[0], b[1], b[2]}, {b[1], b[3], b[4]}, {b[2], b[4], b[5]}};
+    const double hq = h[q];
+    const double D = H[0] * g[0] + H[1] * g[1] + H[2] * g[2];
+    double au[3], av[3];
+    for (int c = 0; c < 3; ++c) {
+        au[c] = Tu[c] + hq * Hu[c];
+        av[c] = Tv[c] + hq * Hv[c];
+    }
+    const double hu = -(au[0] * g[0] + au[1] * g[1] + au[2] * g[2]) / D;
+    const double hv = -(av[0] * g[0] + av[1] * g[1] + av[2] * g[2]) / D;
+    double wu[3], wv[3], Bwu[3], Bwv[3];
+    for (int c = 0; c < 3; ++c) {
+        wu[c] = au[c] + hu * H[c];
+        wv[c] = av[c] + hv * H[c];
+    }
+    for (int r = 0; r < 3; ++r) {
+        Bwu[r] = B[r][0] * wu[0] + B[r][1] * wu[1] + B[r][2] * wu[2];
+        Bwv[r] = B[r][0] * wv[0] + B[r][1] * wv[1] + B[r][2] * wv[2];
+    }
+    const double uBu = wu[0] * Bwu[0] + wu[1] * Bwu[1] + wu[2] * Bwu[2];
+    const double uBv = wu[0] * Bwv[0] + wu[1] * Bwv[1] + wu[2] * Bwv[2];
+    const double vBv = wv[0] * Bwv[0] + wv[1] * Bwv[1] + wv[2] * Bwv[2];
+    const double gHu = g[0] * Hu[0] + g[1] * Hu[1] + g[2] * Hu[2];
+    const double gHv = g[0] * Hv[0] + g[1] * Hv[1] + g[2] * Hv[2];
+    const double huu = -(uBu + 2.0 * hu * gHu) / D;
+    const double huv = -(uBv + hu * gHv + hv * gHu) / D;
+    const double hvv = -(vBv + 2.0 * hv * gHv) / D;
+    double a[3], m[3], e[3];
+    for (int c = 0; c < 3; ++c) {
+        a[c] = 2.0 * hu * Hu[c] + huu * H[c];
+        m[c] = hu * Hv[c] + hv * Hu[c] + huv * H[c];
+        e[c] = 2.0 * hv * Hv[c] + hvv * H[c];
+    }
+    if (xuu)
+        for (int c = 0; c < 3; ++c) xuu[3 * q + c] = a[c];
+    if (xuv)
+        for (int c = 0; c < 3; ++c) xuv[3 * q + c] = m[c];
+    if (xvv)
+        for (int c = 0; c < 3; ++c) xvv[3 * q + c] = e[c];
+    if (gauss || mean) {
+        const double ig = -1.0 / sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+        double nn[3];
+        for (int c = 0; c < 3; ++c) nn[c] = g[c] * ig;
+        const double E = wu[0] * wu[0] + wu[1] * wu[1] + wu[2] * wu[2];
+        const double F = wu[0] * wv[0] + wu[1] * wv[1] + wu[2] * wv[2];
+        const double G = wv[0] * wv[0] + wv[1] * wv[1] + wv[2] * wv[2];
+        const double L = a[0] * nn[0] + a[1] * nn[1] + a[2] * nn[2];
+        const double M = m[0] * nn[0] + m[1] * nn[1] + m[2] * nn[2];
+        const double Nn = e[0] * nn[0] + e[1] * nn[1] + e[2] * nn[2];
+        const double det = E * G - F * F;
+        if (gauss) gauss[q] = (L * Nn - M * M) / det;
+        if (mean) mean[q] = -(E * Nn - 2.0 * F * M + G * L) / (2.0 * det);
+    }
+}
+
+}  // namespace
+
+void launch_hessian_direct(Ctx &c, int64_t n, const double *x, const int32_t *xm, double *phi, double *grad,
+                           double *hess) {
+    hipLaunchKernelGGL(k_hessian_direct, dim3(blocks256(n)), dim3(256), 0, c.stream, n, x, xm,
+                       c.node_off.as<int64_t>(), c.src.as<Src>(), phi, grad, hess);
+    LSS_CHECK_LAUNCH("k_hessian_direct");
+}
+
+void launch_chart_curvature(Ctx &c, const double *uv, int32_t np, int64_t N, const double *h, const double *grad,
+                            const double *hess, double *xuu, double *xuv, double *xvv, double *gauss,
+                            double *mean) {
+    hipLaunchKernelGGL(k_chart_curvature, dim3(blocks256(N)), dim3(256), 0, c.stream, N, c.verts.as<double>(),
+                       c.tris.as<int32_t>(), c.vH.as<double>(), uv, np, h, grad, hess, xuu, xuv, xvv, gauss,
+                       mean);
+    LSS_CHECK_LAUNCH("k_chart_curvature");
+}
+
+}  // namespace lss

@@ -268,6 +268,11 @@ void launch_chart_points(Ctx &c, const double *uv, int32_t np, int64_t N, const 
                          int32_t *xmesh);
 void launch_chart_geometry(Ctx &c, const double *uv, int32_t np, int64_t N, const double *h, const double *grad,
                            double *xu, double *xv, double *da, double *nrm);
+void launch_hessian_direct(Ctx &c, int64_t n, const double *x, const int32_t *xm, double *phi, double *grad,
+                           double *hess);
+void launch_chart_curvature(Ctx &c, const double *uv, int32_t np, int64_t N, const double *h, const double *grad,
+                            const double *hess, double *xuu, double *xuv, double *xvv, double *gauss,
+                            double *mean);
 void chart_interp(Ctx &c, const double *chart_uv, int32_t np, const double *f, int32_t ncomp, const double *eval_uv,
                   int32_t ne, double *out, unsigned flags);
 void launch_newton_targets(Ctx &c, int64_t N);
