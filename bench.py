@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 METRIC = ("Φ+∇Φ target evals/sec, mixed vs FP64 at 1e-6 / 1e-12, 2M-triangle mesh, 1 GPU")
 PEAK = {"f64": 78.6, "f32": 157.3}          # TFLOP/s, MI355X published dense vector peaks
 FLOP_PER_PAIR = 40.0                        # algorithmic FLOPs per (target, node) pair
+HESS_FLOP_PER_PAIR = 87.0                   # Phi, grad and Hessian of one pair, far form
 
 
 def log(*a):
@@ -175,6 +176,47 @@ def time_newton(lss, torch, cfg, prec, steps, warmup):
             "interp_points_per_s": len(cfg["tris"]) * 66 * steps / ei, "interp_ms": 1e3 * ei / steps}
 
 
+def time_hessian(lss, torch, steps):
+    """Hessian and chart curvature on the 20,480-triangle sphere (sigma 0.05):
+    the p = 2 chart nodes (6 per triangle) are projected once, then one step
+    is lss_chart_curvature (the direct FP64 Hessian sum at every chart node
+    plus the per-node second derivatives); lss_eval_hessian at the same points
+    is timed alone for the pair rate."""
+    from workloads import configs, chart_nodes
+    c2 = configs.config2(n_targets=1)
+    dev = torch.device("cuda")
+    uv = torch.as_tensor(chart_nodes(2), device=dev)
+    c = lss.Context(0)
+    c.set_sources(torch.as_tensor(c2["verts"], device=dev), torch.as_tensor(c2["tris"], device=dev),
+                  torch.as_tensor(c2["rule"], device=dev))
+    c.set_sigma(np.asarray(c2["sigma"], float))
+    c.set_options(precision=lss.FP64, far_field=lss.FAR_FMM)
+    h, x, st, it = c.project(uv, device=True)
+    n = len(x)
+    pairs = n * 12 * len(c2["tris"])
+    c.eval_hessian(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        c.eval_hessian(x)
+    torch.cuda.synchronize()
+    eh = (time.perf_counter() - t0) / steps
+    c.chart_curvature(uv, h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        c.chart_curvature(uv, h)
+    torch.cuda.synchronize()
+    ec = (time.perf_counter() - t0) / steps
+    c.close()
+    ach = HESS_FLOP_PER_PAIR * pairs / eh / 1e12
+    return {"workload": "icosphere, %d tri, %d nodes, sigma 0.05, %d chart nodes (p = 2), direct FP64 Hessian"
+                        % (len(c2["tris"]), 12 * len(c2["tris"]), n),
+            "hessian_ms": 1e3 * eh, "hessian_pairs_per_s": pairs / eh, "hessian_points_per_s": n / eh,
+            "hessian_tflops": round(ach, 3), "hessian_frac_f64": round(ach / PEAK["f64"], 4),
+            "curvature_ms": 1e3 * ec, "curvature_nodes_per_s": n / ec}
+
+
 def time_batch(lss, torch, b, uv, prec, per_surface):
     """One pass over the batch of surfaces: build, Phi / grad Phi at the
     random targets of every surface, Newton projection of every chart node.
@@ -279,6 +321,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-newton", action="store_true", help="skip the chart-projection measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch-of-surfaces measurement")
+    ap.add_argument("--no-hessian", action="store_true", help="skip the Hessian / curvature measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the path is single-GPU; see DESIGN.md "
@@ -357,6 +400,10 @@ def main():
         batch["mixed_per_surface"] = time_batch(lss, torch, b, c4["chart_uv"], lss.MIXED, per_surface=True)
         log("bench: per-surface mixed", json.dumps(batch["mixed_per_surface"]))
         out["batch"] = batch
+    if not args.no_hessian:
+        log("bench: Hessian and chart curvature")
+        out["hessian"] = time_hessian(lss, torch, max(1, min(args.steps, 3)))
+        log("bench: Hessian", json.dumps(out["hessian"]))
     print(json.dumps(out), flush=True)
 
 

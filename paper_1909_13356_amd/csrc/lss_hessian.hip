@@ -17,6 +17,8 @@
 // Then Phi -= (a'.d) k1, grad Phi += -a' k1 - (a'.d) k2 d, and
 //   Hess += -k2 (a' d^T + d a'^T) - (a'.d) k2 I - (a'.d) k3 d d^T.
 // Every pair uses the full kernel (no cut, no far-field expansion).
+#include <climits>
+
 #include "lss_internal.h"
 
 namespace lss {
@@ -41,56 +43,92 @@ __device__ inline void radial3(double t, double s2, double &k1, double &k2, doub
         k3 = 4.0 * s2 * s2 * a7;
         return;
     }
-    const double u = sqrt(t);
+    // 1/u = t^-1/2: hardware estimate and two Newton steps (to rounding)
+    double iu = __builtin_amdgcn_rsq(t);
+    const double ht = 0.5 * t;
+    iu = iu * fma(-ht * iu, iu, 1.5);
+    iu = iu * fma(-ht * iu, iu, 1.5);
     double P3 = 1.0, P5 = 1.0, P7 = 1.0;
     if (t < 50.0) {
+        const double u = t * iu;
         const double qe = (2.0 / kSqrtPi) * exp(-t);
         const double u3 = u * t;
         P3 = erf(u) - qe * u;
         P5 = P3 - qe * (2.0 / 3.0) * u3;
         P7 = P5 - qe * (4.0 / 15.0) * u3 * t;
     }
-    const double iu = 1.0 / u, iu2 = iu * iu;
+    const double iu2 = iu * iu;
     const double iu3 = iu * iu2, iu5 = iu3 * iu2, iu7 = iu5 * iu2;
     k1 = (0.5 * kSqrtPi) * P3 * iu3;
     k2 = -(1.5 * kSqrtPi) * s2 * P5 * iu5;
     k3 = (7.5 * kSqrtPi) * s2 * s2 * P7 * iu7;
 }
 
-// one thread per target; the nodes of the target's mesh are read in order,
-// so a wave whose targets share a mesh reads each record once (broadcast)
+// One thread per target.  The block walks the union of its targets' node
+// ranges in tiles of 256 records staged in LDS (every lane then reads the
+// same record: a broadcast); each thread sums the part of a tile that lies
+// in its own mesh's range.  Targets grouped by mesh keep the union to one
+// mesh (two at a boundary block).
 __global__ void __launch_bounds__(256) k_hessian_direct(int64_t n, const double *__restrict__ x,
                                                         const int32_t *__restrict__ xm,
                                                         const int64_t *__restrict__ node_off,
                                                         const Src *__restrict__ src, double *phi, double *grad,
                                                         double *hess) {
+    __shared__ Src tile[256];
+    __shared__ long long blo, bhi;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int32_t m = xm ? xm[i] : 0;
-    const int64_t j0 = node_off[m], j1 = node_off[m + 1];
-    const double px = x[3 * i], py = x[3 * i + 1], pz = x[3 * i + 2];
+    const bool act = i < n;
+    int64_t j0 = 0, j1 = 0;
+    double px = 0.0, py = 0.0, pz = 0.0;
+    if (act) {
+        const int32_t m = xm ? xm[i] : 0;
+        j0 = node_off[m];
+        j1 = node_off[m + 1];
+        px = x[3 * i];
+        py = x[3 * i + 1];
+        pz = x[3 * i + 2];
+    }
+    if (threadIdx.x == 0) {
+        blo = LLONG_MAX;
+        bhi = 0;
+    }
+    __syncthreads();
+    if (act && j1 > j0) {
+        atomicMin(&blo, (long long)j0);
+        atomicMax(&bhi, (long long)j1);
+    }
+    __syncthreads();
+    const int64_t lo = blo, hi = bhi;
     double f = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
     double hxx = 0.0, hxy = 0.0, hxz = 0.0, hyy = 0.0, hyz = 0.0, hzz = 0.0;
-    for (int64_t j = j0; j < j1; ++j) {
-        const Src s = src[j];
-        const double dx = px - s.yx, dy = py - s.yy, dz = pz - s.yz;
-        const double t = (dx * dx + dy * dy + dz * dz) * s.s2;
-        double k1, k2, k3;
-        radial3(t, s.s2, k1, k2, k3);
-        const double ad = s.ax * dx + s.ay * dy + s.az * dz;
-        f -= ad * k1;
-        const double adk2 = ad * k2, adk3 = ad * k3;
-        gx -= s.ax * k1 + adk2 * dx;
-        gy -= s.ay * k1 + adk2 * dy;
-        gz -= s.az * k1 + adk2 * dz;
-        const double ex = adk3 * dx, ey = adk3 * dy, ez = adk3 * dz;
-        hxx -= 2.0 * k2 * s.ax * dx + adk2 + ex * dx;
-        hyy -= 2.0 * k2 * s.ay * dy + adk2 + ey * dy;
-        hzz -= 2.0 * k2 * s.az * dz + adk2 + ez * dz;
-        hxy -= k2 * (s.ax * dy + s.ay * dx) + ex * dy;
-        hxz -= k2 * (s.ax * dz + s.az * dx) + ex * dz;
-        hyz -= k2 * (s.ay * dz + s.az * dy) + ey * dz;
+    for (int64_t base = lo; base < hi; base += 256) {
+        __syncthreads();
+        if (base + threadIdx.x < hi) tile[threadIdx.x] = src[base + threadIdx.x];
+        __syncthreads();
+        const int64_t k0 = j0 > base ? j0 - base : 0;
+        const int64_t k1 = (j1 - base < 256) ? j1 - base : 256;
+        for (int64_t k = k0; k < k1; ++k) {
+            const Src s = tile[k];
+            const double dx = px - s.yx, dy = py - s.yy, dz = pz - s.yz;
+            const double t = (dx * dx + dy * dy + dz * dz) * s.s2;
+            double k1r, k2, k3;
+            radial3(t, s.s2, k1r, k2, k3);
+            const double ad = s.ax * dx + s.ay * dy + s.az * dz;
+            f -= ad * k1r;
+            const double adk2 = ad * k2, adk3 = ad * k3;
+            gx -= s.ax * k1r + adk2 * dx;
+            gy -= s.ay * k1r + adk2 * dy;
+            gz -= s.az * k1r + adk2 * dz;
+            const double ex = adk3 * dx, ey = adk3 * dy, ez = adk3 * dz;
+            hxx -= 2.0 * k2 * s.ax * dx + adk2 + ex * dx;
+            hyy -= 2.0 * k2 * s.ay * dy + adk2 + ey * dy;
+            hzz -= 2.0 * k2 * s.az * dz + adk2 + ez * dz;
+            hxy -= k2 * (s.ax * dy + s.ay * dx) + ex * dy;
+            hxz -= k2 * (s.ax * dz + s.az * dx) + ex * dz;
+            hyz -= k2 * (s.ay * dz + s.az * dy) + ey * dz;
+        }
     }
+    if (!act) return;
     if (phi) phi[i] = f;
     if (grad) {
         grad[3 * i] = gx;
