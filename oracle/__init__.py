@@ -42,6 +42,8 @@ def _load():
         L.oracle_pseudonormals.argtypes = [P, i64, P, i64, P]
         L.oracle_radial_G.argtypes = [P, i64, f64, P]
         L.oracle_hessian.argtypes = [P, P, i32, i64, P, P, i64, P, i32, P, P, i64, P, ctypes.c_int]
+        L.oracle_sigma_field.argtypes = [P, P, i32, i64, P, i32, f64, f64, P, P, i64, P, P, P, P]
+        L.oracle_eval_multiscale.argtypes = [P, P, i32, i64, P, P, i32, P, P, i64, P, P, P, P, ctypes.c_int]
         L.oracle_project.argtypes = [P, i64, P, i32, i64, P, i32, P, i64, P, i32, P, i32, P, i64,
                                      f64, i32, P, P, P, P, ctypes.c_int]
         L.oracle_threads.restype = ctypes.c_int
@@ -128,6 +130,37 @@ def hessian(verts, tris, sigma, rule, x, tri_offsets=None, x_mesh=None, nthreads
     _load().oracle_hessian(_p(verts), _p(tris), nvt, len(tris), _p(off), _p(sigma), sigma.size,
                            _p(rule), len(rule), _p(x), _p(xm), len(x), _p(out), int(nthreads))
     return out
+
+
+def sigma_field(verts, tris, x, lam=2.5, sigma0=0.0, tri_offsets=None, x_mesh=None):
+    """Multiscale width of eq. sigma2 at x (n, 3): returns sigma(x) (n,),
+    grad sigma (n, 3), sigma_j = D_j / lambda (ntris,) and sigma0 per mesh
+    (sqrt(5) max_j D_j of the mesh when sigma0 <= 0)."""
+    verts, x = _f64(verts), _f64(x).reshape(-1, 3)
+    tris, nvt = _tris(tris)
+    off = None if tri_offsets is None else np.ascontiguousarray(tri_offsets, dtype=np.int64)
+    nmesh = 1 if off is None else len(off) - 1
+    xm = None if x_mesh is None else np.ascontiguousarray(x_mesh, dtype=np.int32)
+    s, g = np.empty(len(x)), np.empty((len(x), 3))
+    sj, s0 = np.empty(len(tris)), np.empty(nmesh)
+    _load().oracle_sigma_field(_p(verts), _p(tris), nvt, len(tris), _p(off), nmesh, float(lam),
+                               float(sigma0), _p(x), _p(xm), len(x), _p(s), _p(g), _p(sj), _p(s0))
+    return s, g, sj, s0
+
+
+def evaluate_multiscale(verts, tris, rule, x, lam=2.5, sigma0=0.0, tri_offsets=None, x_mesh=None,
+                        nthreads=0):
+    """Phi (n,), grad Phi (n, 3) and sigma(x) (n,) with the target-attached
+    width of eq. basemodelk / sigma2, by the direct FP64 sum."""
+    verts, rule, x = _f64(verts), _f64(rule), _f64(x).reshape(-1, 3)
+    tris, nvt = _tris(tris)
+    off = None if tri_offsets is None else np.ascontiguousarray(tri_offsets, dtype=np.int64)
+    xm = None if x_mesh is None else np.ascontiguousarray(x_mesh, dtype=np.int32)
+    s, g, _, _ = sigma_field(verts, tris, x, lam, sigma0, tri_offsets, x_mesh)
+    phi, grad = np.empty(len(x)), np.empty((len(x), 3))
+    _load().oracle_eval_multiscale(_p(verts), _p(tris), nvt, len(tris), _p(off), _p(rule), len(rule),
+                                   _p(x), _p(xm), len(x), _p(s), _p(g), _p(phi), _p(grad), int(nthreads))
+    return phi, grad, s
 
 
 def sym3(h6):

@@ -42,6 +42,12 @@
  *    section 3.1 eq. uu_vector_aux1/aux2), with the third radial function
  *    G = F'(rho)/rho:
  *        grad grad psi da = [ -F (J d^T + d J^T) - (J.d) F I - (J.d) G d d^T ] w;
+ *  - the paper's target-attached width (section 2, eq. basemodelk,
+ *    convkernel, sigma2): sigma(x) = sum_j sigma_j w_j / sum_j w_j over the
+ *    triangle centroids c_j, w_j = exp(-|x - c_j|^2 / (2 sigma0^2)),
+ *    sigma_j = D_j / lambda (D_j the diameter of the smallest enclosing
+ *    ball), and Phi, grad Phi with K(rho; sigma(x)) plus the chain-rule term
+ *    (dPhi/dsigma) grad sigma;
  *  - vertex pseudonormals (eq. mkvertexpn) and the linear pseudonormal field
  *    on each triangle (eq. mkpseudovec);
  *  - the chart projection: for chart node (u_i, v_i) of triangle j, the root
@@ -338,6 +344,143 @@ void oracle_hessian(const double *verts, const int32_t *tris, int32_t nvt, int64
         double *o = hess + 6 * i;
         o[0] = nsum_get(&S[0][0]); o[1] = nsum_get(&S[0][1]); o[2] = nsum_get(&S[0][2]);
         o[3] = nsum_get(&S[1][1]); o[4] = nsum_get(&S[1][2]); o[5] = nsum_get(&S[2][2]);
+    }
+}
+
+/* ------------------------------------------- multiscale sigma(x) (section 2) */
+/* D_j: diameter of the smallest ball enclosing the triangle: the longest
+ * edge when the triangle is right or obtuse (the ball on that edge holds the
+ * third vertex), else twice the circumradius abc / (4 area). */
+static double tri_diameter(const double *A, const double *B, const double *C)
+{
+    double a2 = 0, b2 = 0, c2 = 0, e1[3], e2[3], cr[3];
+    for (int k = 0; k < 3; ++k) {
+        a2 += (B[k] - C[k]) * (B[k] - C[k]);
+        b2 += (C[k] - A[k]) * (C[k] - A[k]);
+        c2 += (A[k] - B[k]) * (A[k] - B[k]);
+        e1[k] = B[k] - A[k];
+        e2[k] = C[k] - A[k];
+    }
+    double m = a2 > b2 ? a2 : b2;
+    m = m > c2 ? m : c2;
+    if (2.0 * m >= a2 + b2 + c2) return sqrt(m);          /* largest angle >= 90 degrees */
+    cr[0] = e1[1] * e2[2] - e1[2] * e2[1];
+    cr[1] = e1[2] * e2[0] - e1[0] * e2[2];
+    cr[2] = e1[0] * e2[1] - e1[1] * e2[0];
+    const double area2 = sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);   /* twice the area */
+    return sqrt(a2 * b2 * c2) / area2;                    /* 2 R = abc / (2 area) */
+}
+
+/* Centroids c_j and D_j of triangles j0..j1-1 (corners P1 P2 P3). */
+static void tri_centroids(const double *verts, const int32_t *tris, int32_t nvt, int64_t j0, int64_t j1,
+                          double *cen, double *D)
+{
+    for (int64_t j = j0; j < j1; ++j) {
+        const int32_t *t = tris + nvt * j;
+        const double *A = verts + 3 * (int64_t)t[0], *B = verts + 3 * (int64_t)t[1], *C = verts + 3 * (int64_t)t[2];
+        for (int k = 0; k < 3; ++k) cen[3 * j + k] = (A[k] + B[k] + C[k]) / 3.0;
+        D[j] = tri_diameter(A, B, C);
+    }
+}
+
+/* sigma(x) of eq. sigma2 and its gradient
+ *   grad sigma = -sum_j (sigma_j - sigma) w_j (x - c_j) / (sigma0^2 sum_j w_j),
+ * w_j = exp(-|x - c_j|^2 / (2 sigma0^2)), all weights taken relative to the
+ * largest one (the nearest centroid) so that none underflows to 0/0. */
+static void sigma_blend(const double *cen, const double *sj, int64_t j0, int64_t j1, double s0,
+                        const double x[3], double *sig, double g[3])
+{
+    double dmin = INFINITY;
+    for (int64_t j = j0; j < j1; ++j) {
+        const double dx = x[0] - cen[3 * j], dy = x[1] - cen[3 * j + 1], dz = x[2] - cen[3 * j + 2];
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        if (d2 < dmin) dmin = d2;
+    }
+    nsum num = {0, 0}, den = {0, 0};
+    for (int64_t j = j0; j < j1; ++j) {
+        const double dx = x[0] - cen[3 * j], dy = x[1] - cen[3 * j + 1], dz = x[2] - cen[3 * j + 2];
+        const double w = exp(-(dx * dx + dy * dy + dz * dz - dmin) / (2.0 * s0 * s0));
+        nsum_add(&num, sj[j] * w);
+        nsum_add(&den, w);
+    }
+    const double s = nsum_get(&num) / nsum_get(&den);
+    nsum gs[3] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int64_t j = j0; j < j1; ++j) {
+        const double d[3] = {x[0] - cen[3 * j], x[1] - cen[3 * j + 1], x[2] - cen[3 * j + 2]};
+        const double w = exp(-(d[0] * d[0] + d[1] * d[1] + d[2] * d[2] - dmin) / (2.0 * s0 * s0));
+        for (int k = 0; k < 3; ++k) nsum_add(&gs[k], -(sj[j] - s) * w * d[k]);
+    }
+    *sig = s;
+    for (int k = 0; k < 3; ++k) g[k] = nsum_get(&gs[k]) / (s0 * s0 * nsum_get(&den));
+}
+
+/* sigma(x) (n), grad sigma (n,3), sigma_j (ntris) and the sigma0 used per
+ * mesh, from the triangles' centroids and diameters: sigma_j = D_j / lambda,
+ * sigma0 as given, or sqrt(5) max_j D_j over the target's mesh when
+ * sigma0 <= 0. */
+void oracle_sigma_field(const double *verts, const int32_t *tris, int32_t nvt, int64_t ntris,
+                        const int64_t *tri_off, int32_t nmesh, double lambda, double sigma0,
+                        const double *x, const int32_t *x_mesh, int64_t n, double *sig, double *gsig,
+                        double *sj_out, double *s0_out)
+{
+    const int32_t nm = tri_off ? nmesh : 1;
+    double *cen = (double *)malloc(sizeof(double) * 3 * (size_t)ntris);
+    double *D = (double *)malloc(sizeof(double) * (size_t)ntris);
+    tri_centroids(verts, tris, nvt, 0, ntris, cen, D);
+    for (int64_t j = 0; j < ntris; ++j) sj_out[j] = D[j] / lambda;
+    for (int32_t m = 0; m < nm; ++m) {
+        const int64_t j0 = tri_off ? tri_off[m] : 0, j1 = tri_off ? tri_off[m + 1] : ntris;
+        double dmax = 0.0;
+        for (int64_t j = j0; j < j1; ++j) dmax = D[j] > dmax ? D[j] : dmax;
+        s0_out[m] = sigma0 > 0.0 ? sigma0 : sqrt(5.0) * dmax;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t m = x_mesh ? x_mesh[i] : 0;
+        const int64_t j0 = tri_off ? tri_off[m] : 0, j1 = tri_off ? tri_off[m + 1] : ntris;
+        sigma_blend(cen, sj_out, j0, j1, s0_out[m], x + 3 * i, &sig[i], gsig + 3 * i);
+    }
+    free(cen);
+    free(D);
+}
+
+/* Phi and grad Phi with the target-attached width sigma(x) of eq. basemodelk,
+ * convkernel and sigma2: every node of the target's mesh with K(rho; sigma(x))
+ * and F(rho; sigma(x)), and the chain-rule term (dPhi/dsigma) grad sigma with
+ *   dK/dsigma = -exp(-rho^2 / (2 sigma^2)) / (2 sqrt(2) pi^1.5 sigma^4),
+ *   dPhi/dsigma = sum (a.d) exp(-rho^2 / (2 sigma^2)) / (2 sqrt(2) pi^1.5 sigma^4).
+ * (The printed eq. gradPhi has the opposite sign on this term, as on its
+ * second one; the exact derivative is used.)  sig / gsig from
+ * oracle_sigma_field. */
+void oracle_eval_multiscale(const double *verts, const int32_t *tris, int32_t nvt, int64_t ntris,
+                            const int64_t *tri_off, const double *rule, int32_t nq,
+                            const double *x, const int32_t *x_mesh, int64_t n,
+                            const double *sig, const double *gsig, double *phi, double *grad, int nthreads)
+{
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t mesh = x_mesh ? x_mesh[i] : 0;
+        int64_t j0 = 0, j1 = ntris;
+        if (tri_off) { j0 = tri_off[mesh]; j1 = tri_off[mesh + 1]; }
+        const double s = sig[i];
+        const double cs = 1.0 / (2.0 * sqrt(2.0) * pow(ORC_PI, 1.5) * s * s * s * s);
+        nsum sp = {0, 0}, sg[3] = {{0, 0}, {0, 0}, {0, 0}}, ss = {0, 0};
+        for (int64_t j = j0; j < j1; ++j)
+            for (int m = 0; m < nq; ++m) {
+                double y[3], a[3], d[3];
+                src_node(verts, tris, nvt, j, rule + 3 * m, y, a);
+                for (int c = 0; c < 3; ++c) d[c] = x[3 * i + c] - y[c];
+                const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                double K, F;
+                radial_KF(sqrt(r2), s, &K, &F);
+                const double ad = a[0] * d[0] + a[1] * d[1] + a[2] * d[2];
+                nsum_add(&sp, -ad * K);
+                for (int c = 0; c < 3; ++c) nsum_add(&sg[c], -a[c] * K - ad * F * d[c]);
+                nsum_add(&ss, ad * exp(-r2 / (2.0 * s * s)) * cs);
+            }
+        phi[i] = nsum_get(&sp);
+        const double dps = nsum_get(&ss);
+        for (int c = 0; c < 3; ++c) grad[3 * i + c] = nsum_get(&sg[c]) + dps * gsig[3 * i + c];
     }
 }
 

@@ -741,3 +741,82 @@ def test_chart_curvature_sphere():
     R = np.linalg.norm(x, axis=1)
     assert np.abs(K * R ** 2 - 1).max() < 5e-2
     assert np.abs(Hm * R - 1).max() < 2.5e-2
+
+
+# ------------------------------------------------ multiscale sigma(x) (eq. sigma2)
+def graded_cube(n, power=1.6):
+    """Unit cube with each coordinate warped by s -> s^power: the faces stay
+    planar, the grid is graded (triangle diameters vary about 4x)."""
+    v, t = cube_mesh(n)
+    return v ** power, t
+
+
+def test_triangle_diameter_is_the_smallest_enclosing_ball():
+    from scipy.optimize import minimize
+    rng = np.random.default_rng(8)
+    P = rng.normal(size=(12, 3, 3))
+    P[::3, 2] = 0.5 * (P[::3, 0] + P[::3, 1]) + 0.05 * rng.normal(size=(4, 3))   # obtuse ones
+    v = P.reshape(-1, 3)
+    t = np.arange(len(v), dtype=np.int32).reshape(-1, 3)
+    _, _, sj, _ = oracle.sigma_field(v, t, np.zeros((1, 3)), lam=1.0)
+    for k in range(len(t)):
+        A, B, C = P[k]
+        f = lambda c: max(np.linalg.norm(c - A), np.linalg.norm(c - B), np.linalg.norm(c - C))
+        best = min(minimize(f, x0, method="Nelder-Mead", options=dict(xatol=1e-12, fatol=1e-13, maxiter=20000)).fun
+                   for x0 in (P[k].mean(0), A, 0.5 * (A + B)))
+        assert abs(sj[k] - 2 * best) < 1e-8 * sj[k]
+
+
+def test_sigma_field_constant_and_bounds_and_gradient():
+    v, t = cube_mesh(6)                        # congruent triangles: sigma(x) = D/lambda
+    x = box_targets(50, seed=3)
+    s, g, sj, s0 = oracle.sigma_field(v, t, x, lam=2.5)
+    D = np.sqrt(2) / 6
+    assert np.allclose(sj, D / 2.5, rtol=1e-14) and np.allclose(s, D / 2.5, rtol=1e-13)
+    assert np.abs(g).max() < 1e-12 and abs(s0[0] - np.sqrt(5) * D) < 1e-14
+    p1, g1, _ = oracle.evaluate_multiscale(v, t, dunavant6(), x, lam=2.5)
+    p0, g0 = oracle.evaluate(v, t, [D / 2.5], dunavant6(), x)
+    assert np.abs(p1 - p0).max() < 1e-14 and np.abs(g1 - g0).max() < 1e-12
+    vg, tg = graded_cube(8)
+    xg = np.concatenate([box_targets(40, seed=4), box_targets(10, -3.0, 4.0, seed=5) * 30])   # some far away
+    s, g, sj, s0 = oracle.sigma_field(vg, tg, xg, lam=2.5, sigma0=0.1)
+    assert np.all(s >= sj.min() * (1 - 1e-14)) and np.all(s <= sj.max() * (1 + 1e-14))
+    d = 1e-6
+    for c in range(3):
+        e = np.zeros(3)
+        e[c] = d
+        fd = (oracle.sigma_field(vg, tg, xg + e, 2.5, 0.1)[0] - oracle.sigma_field(vg, tg, xg - e, 2.5, 0.1)[0]) / (2 * d)
+        assert np.abs(fd - g[:, c]).max() < 1e-7 * max(1.0, np.abs(g).max())
+
+
+def test_multiscale_phi_is_the_box_convolution_at_sigma_x():
+    """For each x, Phi(x) is the Gaussian convolution of the indicator with
+    width sigma(x), evaluated at x: the box closed form at sigma(x)."""
+    v, t = graded_cube(24)
+    x = box_targets(48, seed=13)
+    phi, g, s = oracle.evaluate_multiscale(v, t, dunavant6(), x, lam=0.5, sigma0=0.2)
+    P, _ = box_closed(x, s[:, None])
+    assert np.abs(phi - P).max() < 1e-9
+
+
+def test_multiscale_gradient_includes_the_sigma_term():
+    """grad Phi against differences of Phi with sigma(x) re-evaluated at the
+    shifted points; without the (dPhi/dsigma) grad sigma term (or with its
+    sign flipped) the difference is far above the bar."""
+    v, t = graded_cube(8)
+    rng = np.random.default_rng(9)
+    x = rng.uniform(-0.2, 1.2, size=(20, 3))
+    rule = dunavant6()
+    p, g, s = oracle.evaluate_multiscale(v, t, rule, x, lam=2.5, sigma0=0.15)
+    d = 1e-5
+    fd = np.empty_like(g)
+    for c in range(3):
+        e = np.zeros(3)
+        e[c] = d
+        fd[:, c] = (oracle.evaluate_multiscale(v, t, rule, x + e, 2.5, 0.15)[0]
+                    - oracle.evaluate_multiscale(v, t, rule, x - e, 2.5, 0.15)[0]) / (2 * d)
+    err = np.abs(fd - g).max() / np.abs(g).max()
+    assert err < 1e-7, err
+    # the same sums at the fixed width sigma(x_i): the gradient without the term
+    g_fixed = np.concatenate([oracle.evaluate(v, t, [s[i]], rule, x[i:i + 1])[1] for i in range(len(x))])
+    assert np.abs(fd - g_fixed).max() / np.abs(g).max() > 1e-4
