@@ -255,6 +255,24 @@ int lss_chart_geometry(lss_ctx *ctx, const double *chart_uv, int32_t np, const d
 int lss_eval_hessian(lss_ctx *ctx, const double *x, const int32_t *x_mesh, int64_t n, double *phi, double *grad,
                      double *hess, unsigned flags);
 
+/* Phi and grad Phi with the target-attached width of section 2 (eq.
+ * basemodelk, convkernel, sigma2) instead of the per-triangle sigma of
+ * lss_set_sigma: for a target x of mesh m,
+ *   sigma(x) = sum_j sigma_j w_j / sum_j w_j,  w_j = exp(-|x - c_j|^2 / (2 sigma0^2)),
+ * over the triangles j of mesh m, c_j the centroid and sigma_j = D_j / lambda
+ * with D_j the diameter of the smallest ball enclosing the (corner) triangle;
+ * sigma0 > 0 as given, or sigma0 == 0 for sqrt(5) max_j D_j of the mesh (the
+ * paper's suggestion, with lambda about 2.5).  Phi sums every node of the
+ * mesh with width sigma(x); grad Phi is the exact x-derivative, including
+ * (dPhi/dsigma) grad sigma.  x (n,3), x_mesh as for lss_eval; phi (n); grad
+ * (n,3) and sigma_x (n, receives sigma(x)) may be NULL.  FP64 direct sum over
+ * the centroids and the nodes of the target's mesh, whatever the precision
+ * and far-field options; needs sources, not sigma (LSS_ESTATE otherwise).
+ * lambda <= 0, sigma0 < 0 or non-finite give LSS_EINVAL.  Host or device
+ * arrays per flags; returns when the outputs are written. */
+int lss_eval_multiscale(lss_ctx *ctx, double lambda, double sigma0, const double *x, const int32_t *x_mesh,
+                        int64_t n, double *phi, double *grad, double *sigma_x, unsigned flags);
+
 /* Second derivatives and curvatures of the charts x = T + h H at the chart
  * nodes (section 3.1, eq. uu_vector, uu_vector_aux1, uu_vector_aux2 and the
  * analogous uv, vv expressions), for distances h (ntris*np) from

@@ -462,6 +462,11 @@ void oracle_eval_multiscale(const double *verts, const int32_t *tris, int32_t nv
         const int32_t mesh = x_mesh ? x_mesh[i] : 0;
         int64_t j0 = 0, j1 = ntris;
         if (tri_off) { j0 = tri_off[mesh]; j1 = tri_off[mesh + 1]; }
+        if (j0 == j1) {             /* no triangles: an empty sum */
+            phi[i] = 0.0;
+            for (int c = 0; c < 3; ++c) grad[3 * i + c] = 0.0;
+            continue;
+        }
         const double s = sig[i];
         const double cs = 1.0 / (2.0 * sqrt(2.0) * pow(ORC_PI, 1.5) * s * s * s * s);
         nsum sp = {0, 0}, sg[3] = {{0, 0}, {0, 0}, {0, 0}}, ss = {0, 0};

@@ -23,7 +23,7 @@ TRI6 = 2
 EXPORTED_SYMBOLS = ["lss_create", "lss_destroy", "lss_last_error", "lss_synchronize",
                     "lss_set_sources", "lss_set_sigma", "lss_set_options", "lss_get_options",
                     "lss_build", "lss_eval", "lss_project", "lss_chart_geometry", "lss_chart_interp",
-                    "lss_eval_hessian", "lss_chart_curvature",
+                    "lss_eval_hessian", "lss_chart_curvature", "lss_eval_multiscale",
                     "lss_autotune", "lss_get_stats"]
 
 _CODES = {1: "LSS_EINVAL", 2: "LSS_ENOMEM", 3: "LSS_EHIP", 4: "LSS_ESTATE", 5: "LSS_EORIENT"}
@@ -97,6 +97,7 @@ def load_library():
     L.lss_chart_interp.argtypes = [P, P, i32, P, i32, P, i32, P, u]
     L.lss_eval_hessian.argtypes = [P, P, P, i64, P, P, P, u]
     L.lss_chart_curvature.argtypes = [P, P, i32, P, P, P, P, P, P, u]
+    L.lss_eval_multiscale.argtypes = [P, ctypes.c_double, ctypes.c_double, P, P, i64, P, P, P, u]
     L.lss_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
     L.lss_autotune.argtypes = [P, P, i64, u, ctypes.c_double, ctypes.c_char_p, ctypes.POINTER(Options)]
     _lib = L
@@ -326,6 +327,27 @@ class Context:
         ph, _, k3 = _ptr(hess, np.float64)
         self._check(self._lib.lss_eval_hessian(self._h, px, pm, n, pp, pg, ph, fx))
         return phi, grad, hess
+
+    def eval_multiscale(self, x, lam=2.5, sigma0=0.0, x_mesh=None):
+        """Phi (n,), grad Phi (n, 3) and sigma(x) (n,) with the target-attached
+        width sigma(x) of section 2 (sigma_j = D_j / lam, blend width sigma0;
+        0 = sqrt(5) max D_j).  Device tensors in, device tensors out."""
+        n = len(x)
+        if _is_torch(x) and x.device.type == "cuda":
+            import torch
+            mk = lambda *s: torch.empty(s, dtype=torch.float64, device=x.device)
+        else:
+            mk = lambda *s: np.empty(s)
+        phi, grad, sig = mk(n), mk(n, 3), mk(n)
+        px, fx, kx = _ptr(x, np.float64)
+        pm, fm, km = _ptr(x_mesh, np.int32)
+        if x_mesh is not None and fm != fx:
+            raise ValueError("x and x_mesh must both be host arrays or both device tensors")
+        pp, _, k1 = _ptr(phi, np.float64)
+        pg, _, k2 = _ptr(grad, np.float64)
+        ps, _, k3 = _ptr(sig, np.float64)
+        self._check(self._lib.lss_eval_multiscale(self._h, float(lam), float(sigma0), px, pm, n, pp, pg, ps, fx))
+        return phi, grad, sig
 
     def chart_curvature(self, chart_uv, h):
         """Second derivatives x_uu, x_uv, x_vv (N,3) and the Gaussian and mean

@@ -429,6 +429,72 @@ void eval_hessian(Ctx &c, const double *x, const int32_t *xm, int64_t n, double 
     LSS_HIP(hipStreamSynchronize(c.stream));
 }
 
+// Phi, grad Phi with the target-attached width sigma(x), direct sum
+void eval_multiscale(Ctx &c, double lambda, double sigma0, const double *x, const int32_t *xm, int64_t n, double *phi,
+                     double *grad, double *sig, unsigned flags) {
+    if (!c.have_sources) fail(LSS_ESTATE, "lss_eval_multiscale: no sources (call lss_set_sources)");
+    if (!(lambda > 0.0) || !std::isfinite(lambda)) fail(LSS_EINVAL, "lss_eval_multiscale: lambda must be positive");
+    if (!(sigma0 >= 0.0) || !std::isfinite(sigma0)) fail(LSS_EINVAL, "lss_eval_multiscale: sigma0 must be >= 0");
+    if (n < 0) fail(LSS_EINVAL, "lss_eval_multiscale: n < 0");
+    if (n == 0) return;
+    if (n > (int64_t)INT32_MAX) fail(LSS_EINVAL, "lss_eval_multiscale: n exceeds 2^31-1");
+    if (!x || !phi) fail(LSS_EINVAL, "lss_eval_multiscale: x and phi must be non-null");
+    if (c.nmesh > 1 && !xm) fail(LSS_EINVAL, "lss_eval_multiscale: x_mesh is required for a batch of meshes");
+    const bool dev = flags & LSS_PTR_DEVICE;
+    // centroids, sigma_j and sigma0 per mesh (sqrt(5) max_j D_j when sigma0 == 0)
+    DBuf cen, D, s0, raw;
+    cen.ensure(sizeof(Cen) * c.ntris);
+    D.ensure(sizeof(double) * c.ntris);
+    launch_centroids(c, lambda, cen.as<Cen>(), D.as<double>());
+    std::vector<double> hD(c.ntris), hs0(c.nmesh);
+    LSS_HIP(hipMemcpyAsync(hD.data(), D.p, sizeof(double) * c.ntris, hipMemcpyDeviceToHost, c.stream));
+    LSS_HIP(hipStreamSynchronize(c.stream));
+    for (int32_t m = 0; m < c.nmesh; ++m) {
+        double dmax = 0.0;
+        for (int64_t j = c.h_tri_off[m]; j < c.h_tri_off[m + 1]; ++j) dmax = std::max(dmax, hD[j]);
+        hs0[m] = sigma0 > 0.0 ? sigma0 : std::sqrt(5.0) * dmax;
+        if (c.h_tri_off[m + 1] > c.h_tri_off[m] && !(hs0[m] > 0.0) )
+            fail(LSS_EINVAL, "lss_eval_multiscale: a mesh has only zero-size triangles");
+    }
+    upload(c, s0, hs0.data(), sizeof(double) * c.nmesh, 0);
+    raw.ensure(sizeof(RawNode) * c.ntris * c.nq);
+    launch_prep_raw(c, raw.as<RawNode>());
+    DBuf hx, hxm, hphi, hgrad, hsig;
+    const double *dx = x;
+    const int32_t *dxm = c.nmesh > 1 ? xm : nullptr;
+    double *dphi = phi, *dgrad = grad, *dsig = sig;
+    if (!dev) {
+        upload(c, hx, x, sizeof(double) * 3 * n, 0);
+        dx = hx.as<double>();
+        if (dxm) {
+            upload(c, hxm, xm, sizeof(int32_t) * n, 0);
+            dxm = hxm.as<int32_t>();
+        }
+        hphi.ensure(sizeof(double) * n);
+        dphi = hphi.as<double>();
+        if (grad) { hgrad.ensure(sizeof(double) * 3 * n); dgrad = hgrad.as<double>(); }
+        if (sig) { hsig.ensure(sizeof(double) * n); dsig = hsig.as<double>(); }
+    }
+    if (dxm) {
+        DBuf bad;
+        bad.ensure(8);
+        LSS_HIP(hipMemsetAsync(bad.p, 0, 8, c.stream));
+        hipLaunchKernelGGL(k_check_mesh_ids, dim3(grid_for(n)), dim3(256), 0, c.stream, n, dxm, c.nmesh,
+                           bad.as<unsigned long long>());
+        unsigned long long nb = 0;
+        LSS_HIP(hipMemcpyAsync(&nb, bad.p, 8, hipMemcpyDeviceToHost, c.stream));
+        LSS_HIP(hipStreamSynchronize(c.stream));
+        if (nb) fail(LSS_EINVAL, "lss_eval_multiscale: x_mesh values outside [0, nmesh)");
+    }
+    launch_eval_multiscale(c, n, dx, dxm, cen.as<Cen>(), raw.as<RawNode>(), s0.as<double>(), dphi, dgrad, dsig);
+    if (!dev) {
+        LSS_HIP(hipMemcpyAsync(phi, dphi, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
+        if (grad) LSS_HIP(hipMemcpyAsync(grad, dgrad, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, c.stream));
+        if (sig) LSS_HIP(hipMemcpyAsync(sig, dsig, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
+    }
+    LSS_HIP(hipStreamSynchronize(c.stream));
+}
+
 void chart_curvature(Ctx &c, const double *uv, int32_t np, const double *h, double *xuu, double *xuv, double *xvv,
                      double *gauss, double *mean, unsigned flags) {
     if (np <= 0) fail(LSS_EINVAL, "lss_chart_curvature: np must be >= 1");
@@ -806,6 +872,13 @@ int lss_project(lss_ctx *ctx, const double *chart_uv, int32_t np, double *h, dou
 int lss_eval_hessian(lss_ctx *ctx, const double *x, const int32_t *x_mesh, int64_t n, double *phi, double *grad,
                      double *hess, unsigned flags) {
     return lss::guarded(ctx, [&](Ctx &c) { lss::eval_hessian(c, x, x_mesh, n, phi, grad, hess, flags); });
+}
+
+int lss_eval_multiscale(lss_ctx *ctx, double lambda, double sigma0, const double *x, const int32_t *x_mesh,
+                        int64_t n, double *phi, double *grad, double *sigma_x, unsigned flags) {
+    return lss::guarded(ctx, [&](Ctx &c) {
+        lss::eval_multiscale(c, lambda, sigma0, x, x_mesh, n, phi, grad, sigma_x, flags);
+    });
 }
 
 int lss_chart_curvature(lss_ctx *ctx, const double *chart_uv, int32_t np, const double *h, double *xuu,

@@ -1,6 +1,8 @@
+// Direct-sum kernels beyond Phi / grad Phi with per-source widths: the
 // Hessian of the smoothed indicator and the second derivatives of the charts
 // (section 3.1, eq. uu_vector, uu_vector_aux1, uu_vector_aux2 and their uv,
-// vv analogues), on the device.
+// vv analogues), and Phi / grad Phi with the target-attached width sigma(x)
+// (section 2, eq. basemodelk, convkernel, sigma2).
 //
 // Per source node (y, a' = c w J, s2 = 1/(2 sigma^2), c = 1/(4 sqrt2 pi^1.5
 // sigma^3)) and target x, d = x - y, t = |d|^2 s2 = u^2, the three radial
@@ -28,11 +30,13 @@ constexpr double kSqrtPi = 1.7724538509055160273;
 
 inline unsigned blocks256(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-__device__ inline void radial3(double t, double s2, double &k1, double &k2, double &k3) {
+// e receives exp(-t) (0 for t >= 50), which the target-attached width needs
+__device__ inline void radial3(double t, double s2, double &k1, double &k2, double &k3, double &e) {
     if (t < 2.25) {
-        double p = 1.0, a3 = 0.0, a5 = 0.0, a7 = 0.0;
+        double p = 1.0, a0 = 0.0, a3 = 0.0, a5 = 0.0, a7 = 0.0;
 #pragma unroll
         for (int k = 0; k < 30; ++k) {
+            a0 += p;
             a3 += p * (2.0 / (2 * k + 3));
             a5 += p * (2.0 / (2 * k + 5));
             a7 += p * (2.0 / (2 * k + 7));
@@ -41,6 +45,7 @@ __device__ inline void radial3(double t, double s2, double &k1, double &k2, doub
         k1 = a3;
         k2 = -2.0 * s2 * a5;
         k3 = 4.0 * s2 * s2 * a7;
+        e = a0;
         return;
     }
     // 1/u = t^-1/2: hardware estimate and two Newton steps (to rounding)
@@ -49,9 +54,11 @@ __device__ inline void radial3(double t, double s2, double &k1, double &k2, doub
     iu = iu * fma(-ht * iu, iu, 1.5);
     iu = iu * fma(-ht * iu, iu, 1.5);
     double P3 = 1.0, P5 = 1.0, P7 = 1.0;
+    e = 0.0;
     if (t < 50.0) {
         const double u = t * iu;
-        const double qe = (2.0 / kSqrtPi) * exp(-t);
+        e = exp(-t);
+        const double qe = (2.0 / kSqrtPi) * e;
         const double u3 = u * t;
         P3 = erf(u) - qe * u;
         P5 = P3 - qe * (2.0 / 3.0) * u3;
@@ -111,8 +118,8 @@ __global__ void __launch_bounds__(256) k_hessian_direct(int64_t n, const double 
             const Src s = tile[k];
             const double dx = px - s.yx, dy = py - s.yy, dz = pz - s.yz;
             const double t = (dx * dx + dy * dy + dz * dz) * s.s2;
-            double k1r, k2, k3;
-            radial3(t, s.s2, k1r, k2, k3);
+            double k1r, k2, k3, et;
+            radial3(t, s.s2, k1r, k2, k3, et);
             const double ad = s.ax * dx + s.ay * dy + s.az * dz;
             f -= ad * k1r;
             const double adk2 = ad * k2, adk3 = ad * k3;
@@ -142,6 +149,150 @@ __global__ void __launch_bounds__(256) k_hessian_direct(int64_t n, const double 
     o[3] = hyy;
     o[4] = hyz;
     o[5] = hzz;
+}
+
+// Target-attached width (section 2, eq. basemodelk, convkernel, sigma2).
+// Phase 1: sigma(x) = sum_j sigma_j w_j / sum_j w_j over the centroids of the
+// target's mesh, w_j = exp(-|x - c_j|^2 / (2 sigma0^2)), accumulated relative
+// to the nearest centroid seen so far (the sums are rescaled when it
+// changes), and grad sigma = -(V1 - sigma V0) / (sigma0^2 S0) with
+// S0 = sum w_j, V0 = sum w_j (x - c_j), V1 = sum sigma_j w_j (x - c_j).
+// Phase 2: every node of the mesh with the raw normal a = w J and the
+// target's width, c = 1/(4 sqrt2 pi^1.5 sigma^3), s2 = 1/(2 sigma^2):
+//   Phi = -c sum (a.d) k1,  grad Phi = -c sum (a k1 + (a.d) k2 d)
+//         + (dPhi/dsigma) grad sigma,  dPhi/dsigma = (2c/sigma) sum (a.d) exp(-t),
+// k1, k2 as in radial3 (K = c k1, F = c k2).  A target whose mesh has no
+// triangles gets sigma = NaN and Phi = grad Phi = 0.
+__global__ void __launch_bounds__(256) k_eval_multiscale(int64_t n, const double *__restrict__ x,
+                                                         const int32_t *__restrict__ xm,
+                                                         const int64_t *__restrict__ tri_off,
+                                                         const int64_t *__restrict__ node_off,
+                                                         const Cen *__restrict__ cen,
+                                                         const RawNode *__restrict__ nodes,
+                                                         const double *__restrict__ sigma0, double *phi,
+                                                         double *grad, double *sig_out) {
+    __shared__ RawNode tile[256];
+    __shared__ long long blo, bhi;
+    Cen *ctile = reinterpret_cast<Cen *>(tile);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool act = i < n;
+    int32_t m = 0;
+    double px = 0.0, py = 0.0, pz = 0.0;
+    if (act) {
+        m = xm ? xm[i] : 0;
+        px = x[3 * i];
+        py = x[3 * i + 1];
+        pz = x[3 * i + 2];
+    }
+    // ---- phase 1: sigma(x) and its gradient
+    int64_t j0 = act ? tri_off[m] : 0, j1 = act ? tri_off[m + 1] : 0;
+    if (threadIdx.x == 0) {
+        blo = LLONG_MAX;
+        bhi = 0;
+    }
+    __syncthreads();
+    if (j1 > j0) {
+        atomicMin(&blo, (long long)j0);
+        atomicMax(&bhi, (long long)j1);
+    }
+    __syncthreads();
+    int64_t lo = blo, hi = bhi;
+    const double s0 = act ? sigma0[m] : 1.0;
+    const double inv2s0 = 0.5 / (s0 * s0);
+    double dmin = INFINITY, S0 = 0.0, S1 = 0.0, V0x = 0.0, V0y = 0.0, V0z = 0.0, V1x = 0.0, V1y = 0.0, V1z = 0.0;
+    for (int64_t base = lo; base < hi; base += 256) {
+        __syncthreads();
+        if (base + threadIdx.x < hi) ctile[threadIdx.x] = cen[base + threadIdx.x];
+        __syncthreads();
+        const int64_t k0 = j0 > base ? j0 - base : 0;
+        const int64_t k1 = (j1 - base < 256) ? j1 - base : 256;
+        for (int64_t k = k0; k < k1; ++k) {
+            const Cen c = ctile[k];
+            const double dx = px - c.cx, dy = py - c.cy, dz = pz - c.cz;
+            const double d2 = dx * dx + dy * dy + dz * dz;
+            if (d2 < dmin) {          // new nearest centroid: rescale the sums to it
+                const double f = exp((d2 - dmin) * inv2s0);
+                S0 *= f;
+                S1 *= f;
+                V0x *= f;
+                V0y *= f;
+                V0z *= f;
+                V1x *= f;
+                V1y *= f;
+                V1z *= f;
+                dmin = d2;
+            }
+            const double w = exp((dmin - d2) * inv2s0);
+            const double sw = c.sj * w;
+            S0 += w;
+            S1 += sw;
+            V0x += w * dx;
+            V0y += w * dy;
+            V0z += w * dz;
+            V1x += sw * dx;
+            V1y += sw * dy;
+            V1z += sw * dz;
+        }
+    }
+    const bool have = S0 > 0.0;
+    const double sg = have ? S1 / S0 : 0.5;
+    const double gsc = have ? -1.0 / (s0 * s0 * S0) : 0.0;
+    const double gsx = gsc * (V1x - sg * V0x), gsy = gsc * (V1y - sg * V0y), gsz = gsc * (V1z - sg * V0z);
+    // ---- phase 2: Phi, grad Phi with width sigma(x)
+    j0 = act ? node_off[m] : 0;
+    j1 = act ? node_off[m + 1] : 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        blo = LLONG_MAX;
+        bhi = 0;
+    }
+    __syncthreads();
+    if (j1 > j0) {
+        atomicMin(&blo, (long long)j0);
+        atomicMax(&bhi, (long long)j1);
+    }
+    __syncthreads();
+    lo = blo;
+    hi = bhi;
+    const double s2 = 0.5 / (sg * sg);
+    double P = 0.0, Gx = 0.0, Gy = 0.0, Gz = 0.0, E = 0.0;
+    for (int64_t base = lo; base < hi; base += 256) {
+        __syncthreads();
+        if (base + threadIdx.x < hi) tile[threadIdx.x] = nodes[base + threadIdx.x];
+        __syncthreads();
+        const int64_t k0 = j0 > base ? j0 - base : 0;
+        const int64_t k1 = (j1 - base < 256) ? j1 - base : 256;
+        for (int64_t k = k0; k < k1; ++k) {
+            const RawNode s = tile[k];
+            const double dx = px - s.yx, dy = py - s.yy, dz = pz - s.yz;
+            const double t = (dx * dx + dy * dy + dz * dz) * s2;
+            double r1, r2, r3, et;
+            radial3(t, s2, r1, r2, r3, et);
+            const double ad = s.ax * dx + s.ay * dy + s.az * dz;
+            P += ad * r1;
+            const double adr2 = ad * r2;
+            Gx += s.ax * r1 + adr2 * dx;
+            Gy += s.ay * r1 + adr2 * dy;
+            Gz += s.az * r1 + adr2 * dz;
+            E += ad * et;
+        }
+    }
+    if (!act) return;
+    if (!have) {
+        phi[i] = 0.0;
+        if (grad) grad[3 * i] = grad[3 * i + 1] = grad[3 * i + 2] = 0.0;
+        if (sig_out) sig_out[i] = NAN;
+        return;
+    }
+    const double c = 1.0 / (4.0 * 1.4142135623730951 * 5.568327996831708 * sg * sg * sg);   // pi^1.5
+    const double dps = 2.0 * c / sg * E;
+    phi[i] = -c * P;
+    if (grad) {
+        grad[3 * i] = -c * Gx + dps * gsx;
+        grad[3 * i + 1] = -c * Gy + dps * gsy;
+        grad[3 * i + 2] = -c * Gz + dps * gsz;
+    }
+    if (sig_out) sig_out[i] = sg;
 }
 
 // Second derivatives and curvatures of chart j at node i (index q = j np + i).
@@ -237,6 +388,13 @@ void launch_hessian_direct(Ctx &c, int64_t n, const double *x, const int32_t *xm
     hipLaunchKernelGGL(k_hessian_direct, dim3(blocks256(n)), dim3(256), 0, c.stream, n, x, xm,
                        c.node_off.as<int64_t>(), c.src.as<Src>(), phi, grad, hess);
     LSS_CHECK_LAUNCH("k_hessian_direct");
+}
+
+void launch_eval_multiscale(Ctx &c, int64_t n, const double *x, const int32_t *xm, const Cen *cen,
+                            const RawNode *nodes, const double *sigma0, double *phi, double *grad, double *sig) {
+    hipLaunchKernelGGL(k_eval_multiscale, dim3(blocks256(n)), dim3(256), 0, c.stream, n, x, xm,
+                       c.tri_off.as<int64_t>(), c.node_off.as<int64_t>(), cen, nodes, sigma0, phi, grad, sig);
+    LSS_CHECK_LAUNCH("k_eval_multiscale");
 }
 
 void launch_chart_curvature(Ctx &c, const double *uv, int32_t np, int64_t N, const double *h, const double *grad,

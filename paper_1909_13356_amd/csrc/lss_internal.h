@@ -81,6 +81,16 @@ struct alignas(64) Src {
     double ax, ay, az, s2x2;
 };
 
+// Node without a width (target-attached sigma): position and a = w J.
+struct RawNode {
+    double yx, yy, yz, ax, ay, az;
+};
+
+// Triangle centroid and sigma_j = D_j / lambda (multiscale width, section 2).
+struct Cen {
+    double cx, cy, cz, sj;
+};
+
 // FP32 staging record of the mixed path: position relative to a tile origin
 // as an unevaluated float-float sum hi + lo (lo = the FP64 remainder).  The
 // far-form constants are folded in: ax, ay, az hold sqrt(pi)/2 a' and s2x2
@@ -247,6 +257,10 @@ struct Ctx {
 // ------------------------------------------------------- launch wrappers
 // prep (lss_kernels.hip)
 void launch_prep_sources(Ctx &c);
+void launch_prep_raw(Ctx &c, RawNode *out);
+void launch_centroids(Ctx &c, double lambda, Cen *out, double *D);
+void launch_eval_multiscale(Ctx &c, int64_t n, const double *x, const int32_t *xm, const Cen *cen,
+                            const RawNode *nodes, const double *sigma0, double *phi, double *grad, double *sig);
 void launch_pseudonormals(Ctx &c);
 void launch_bbox(Ctx &c);
 double launch_check_orientation(Ctx &c, std::vector<double> &vol_per_mesh, int64_t &ndegenerate);

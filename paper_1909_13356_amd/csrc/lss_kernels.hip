@@ -33,16 +33,14 @@ __device__ inline void cross3(const double *a, const double *b, double *o) {
 //   A = 4 P4 - 3 P1 - P2,  B = 4 P6 - 3 P1 - P3,  C = 2 (P1 + P2 - 2 P4),
 //   D = 2 (P1 + P3 - 2 P6),  E = 4 (P1 - P4 + P5 - P6),
 // and J = y_u x y_v with y_u = A + 2u C + v E, y_v = B + 2v D + u E.
-__global__ void k_prep_sources(int64_t nnodes, int32_t nq, const double *__restrict__ verts,
-                               const int32_t *__restrict__ tris, const int32_t *__restrict__ tris6,
-                               const double *__restrict__ rule, const double *__restrict__ sigma,
-                               Src *__restrict__ out) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nnodes) return;
-    int64_t j = k / nq;
-    int m = (int)(k - j * nq);
-    const double u = rule[3 * m], v = rule[3 * m + 1], w = rule[3 * m + 2];
-    double P1[3], y[3], J[3];
+__device__ inline void node_yJ(const double *__restrict__ verts, const int32_t *__restrict__ tris,
+                               const int32_t *__restrict__ tris6, const double *__restrict__ rule, int32_t nq,
+                               int64_t k, int64_t &j, double y[3], double J[3], double &w) {
+    j = k / nq;
+    const int m = (int)(k - j * nq);
+    const double u = rule[3 * m], v = rule[3 * m + 1];
+    w = rule[3 * m + 2];
+    double P1[3];
     if (tris6) {
         const int32_t *t = tris6 + 6 * j;
         double yu[3], yv[3];
@@ -72,6 +70,17 @@ __global__ void k_prep_sources(int64_t nnodes, int32_t nq, const double *__restr
         }
         cross3(tu, tv, J);
     }
+}
+
+__global__ void k_prep_sources(int64_t nnodes, int32_t nq, const double *__restrict__ verts,
+                               const int32_t *__restrict__ tris, const int32_t *__restrict__ tris6,
+                               const double *__restrict__ rule, const double *__restrict__ sigma,
+                               Src *__restrict__ out) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nnodes) return;
+    int64_t j;
+    double y[3], J[3], w;
+    node_yJ(verts, tris, tris6, rule, nq, k, j, y, J, w);
     const double s = sigma[j];
     const double cnorm = 1.0 / (4.0 * 1.4142135623730951 * 5.568327996831708 * s * s * s);  // pi^1.5
     Src r;
@@ -84,6 +93,50 @@ __global__ void k_prep_sources(int64_t nnodes, int32_t nq, const double *__restr
     r.az = cnorm * w * J[2];
     r.s2x2 = 2.0 * r.s2;
     out[k] = r;
+}
+
+// the same nodes without a width: y and a = w J (for a target-attached sigma)
+__global__ void k_prep_raw(int64_t nnodes, int32_t nq, const double *__restrict__ verts,
+                           const int32_t *__restrict__ tris, const int32_t *__restrict__ tris6,
+                           const double *__restrict__ rule, RawNode *__restrict__ out) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nnodes) return;
+    int64_t j;
+    double y[3], J[3], w;
+    node_yJ(verts, tris, tris6, rule, nq, k, j, y, J, w);
+    out[k] = RawNode{y[0], y[1], y[2], w * J[0], w * J[1], w * J[2]};
+}
+
+// Centroid c_j of corner triangle j and D_j, the diameter of its smallest
+// enclosing ball (section 2): the longest edge if the largest angle is at
+// least 90 degrees, else the circumdiameter |AB| |BC| |CA| / |AB x AC|.
+// Writes {c_j, D_j / lambda} and D_j.
+__global__ void k_centroids(int64_t ntris, const double *__restrict__ verts, const int32_t *__restrict__ tris,
+                            double lambda, Cen *__restrict__ out, double *__restrict__ D) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ntris) return;
+    const int32_t *t = tris + 3 * j;
+    double P[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) P[a][c] = verts[3 * (int64_t)t[a] + c];
+    double e[3][3], l2[3];
+    for (int a = 0; a < 3; ++a) {
+        const int b = a == 2 ? 0 : a + 1;
+        for (int c = 0; c < 3; ++c) e[a][c] = P[b][c] - P[a][c];
+        l2[a] = e[a][0] * e[a][0] + e[a][1] * e[a][1] + e[a][2] * e[a][2];
+    }
+    const double mx = fmax(l2[0], fmax(l2[1], l2[2]));
+    double d;
+    if (2.0 * mx >= l2[0] + l2[1] + l2[2]) {
+        d = sqrt(mx);
+    } else {
+        double n[3];
+        cross3(e[0], e[2], n);
+        d = sqrt(l2[0] * l2[1] * l2[2]) / sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    }
+    D[j] = d;
+    out[j] = Cen{(P[0][0] + P[1][0] + P[2][0]) / 3.0, (P[0][1] + P[1][1] + P[2][1]) / 3.0,
+                 (P[0][2] + P[1][2] + P[2][2]) / 3.0, d / lambda};
 }
 
 // signed volume per mesh (sum P1 . (P2 x P3) / 6) and zero-area count
@@ -514,6 +567,20 @@ void launch_prep_sources(Ctx &c) {
                        c.verts.as<double>(), c.tris.as<int32_t>(), c.quadratic ? c.tris6.as<int32_t>() : nullptr,
                        c.rule.as<double>(), c.sigma.as<double>(), c.src.as<Src>());
     LSS_CHECK_LAUNCH("k_prep_sources");
+}
+
+void launch_prep_raw(Ctx &c, RawNode *out) {
+    const int64_t nn = c.ntris * (int64_t)c.nq;
+    hipLaunchKernelGGL(k_prep_raw, dim3(grid_for(nn)), dim3(kBlk), 0, c.stream, nn, c.nq,
+                       c.verts.as<double>(), c.tris.as<int32_t>(), c.quadratic ? c.tris6.as<int32_t>() : nullptr,
+                       c.rule.as<double>(), out);
+    LSS_CHECK_LAUNCH("k_prep_raw");
+}
+
+void launch_centroids(Ctx &c, double lambda, Cen *out, double *D) {
+    hipLaunchKernelGGL(k_centroids, dim3(grid_for(c.ntris)), dim3(kBlk), 0, c.stream, c.ntris,
+                       c.verts.as<double>(), c.tris.as<int32_t>(), lambda, out, D);
+    LSS_CHECK_LAUNCH("k_centroids");
 }
 
 double launch_check_orientation(Ctx &c, std::vector<double> &vol, int64_t &ndegen) {

@@ -1,0 +1,94 @@
+"""GPU parity of Phi / grad Phi with the paper's target-attached width
+sigma(x) (section 2, eq. sigma2: the Gaussian blend of sigma_j = D_j/lambda
+over the triangle centroids), direct FP64 sum, against the oracle: Phi,
+grad Phi (with the (dPhi/dsigma) grad sigma term) and sigma(x) within 1e-12
+(max error relative to the largest oracle value)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1909_13356_amd as lss
+from workloads import (dunavant6, cube_mesh, star_surface, torus_mesh, triangle_diameters,
+                       surface_offset_targets, box_targets)
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return np.max(np.abs(np.asarray(a) - b)) / np.max(np.abs(b))
+
+
+def ctx(v, t, offsets=None):
+    c = lss.Context()
+    c.set_sources(v, t, dunavant6(), tri_offsets=offsets)
+    return c
+
+
+@pytest.mark.parametrize("lam,sigma0", [(2.5, 0.0), (2.5, 0.15), (1.0, 0.05)])
+def test_multiscale_vs_oracle(lam, sigma0):
+    v, t = star_surface(8, lmax=8, var0=0.1, seed=6)
+    sig = 0.5 * triangle_diameters(v, t)
+    x = np.concatenate([surface_offset_targets(v, t, sig, 2000, tmax=3.0, seed=7),
+                        box_targets(200, -2.0, 2.0, seed=8)])
+    say("case: multiscale sigma(x), star surface %d tri, lambda %g sigma0 %g, %d targets" % (len(t), lam, sigma0, len(x)))
+    p, g, s = ctx(v, t).eval_multiscale(x, lam, sigma0)
+    po, go, so = oracle.evaluate_multiscale(v, t, dunavant6(), x, lam, sigma0)
+    e = rel(p, po), rel(g, go), rel(s, so)
+    say("  e_phi %.2e e_grad %.2e e_sigma %.2e" % e)
+    assert max(e) <= 1e-12
+
+
+def test_multiscale_batch_of_a_quadratic_torus_and_a_cube():
+    vt, tt = torus_mesh(16, 8, quadratic=True)
+    vc, tc = cube_mesh(4, 2.0, 3.0)
+    # the cube as quadratic triangles with their own (unshared) edge midpoints
+    mids = 0.5 * (vc[tc[:, [0, 1, 2]]] + vc[tc[:, [1, 2, 0]]]).reshape(-1, 3)
+    v = np.concatenate([vt, vc, mids])
+    tcq = np.column_stack([tc + len(vt), len(vt) + len(vc) + np.arange(3 * len(tc)).reshape(-1, 3)])
+    t6 = np.concatenate([tt, tcq]).astype(np.int32)
+    off = np.array([0, len(tt), len(t6)], np.int64)
+    x = np.concatenate([box_targets(300, -1.5, 1.5, seed=1), box_targets(300, 1.8, 3.2, seed=3)])
+    xm = np.repeat(np.array([0, 1], np.int32), [300, 300])
+    say("case: multiscale, batch of a quadratic torus and a cube")
+    c = ctx(v, t6, offsets=off)
+    p, g, s = c.eval_multiscale(x, 2.5, 0.0, x_mesh=xm)
+    po, go, so = oracle.evaluate_multiscale(v, t6, dunavant6(), x, 2.5, 0.0, tri_offsets=off, x_mesh=xm)
+    e = rel(p, po), rel(g, go), rel(s, so)
+    say("  e_phi %.2e e_grad %.2e e_sigma %.2e" % e)
+    assert max(e) <= 1e-12
+    bad = xm.copy()
+    bad[3] = 2
+    with pytest.raises(lss.LssError) as err:
+        c.eval_multiscale(x, 2.5, 0.0, x_mesh=bad)
+    assert err.value.code == 1
+
+
+def test_multiscale_constant_diameter_is_the_constant_sigma_sum_and_device_tensors():
+    import torch
+    v, t = cube_mesh(6)
+    D = np.sqrt(2) / 6
+    x = box_targets(1500, -0.5, 1.5, seed=4)
+    say("case: multiscale on congruent triangles vs constant sigma; device tensors; errors")
+    c = ctx(v, t)
+    with pytest.raises(lss.LssError) as err:
+        c.eval_multiscale(x, 0.0)
+    assert err.value.code == 1
+    p, g, s = c.eval_multiscale(x, 2.5)
+    assert np.allclose(s, D / 2.5, rtol=1e-13, atol=0)
+    c.set_sigma(np.array([D / 2.5]))
+    c.set_options(precision=lss.FP64, far_field=lss.FAR_DIRECT)
+    p0, g0 = c.eval(x)
+    assert rel(p, p0) <= 1e-12 and rel(g, g0) <= 1e-12
+    pd, gd, sd = c.eval_multiscale(torch.as_tensor(x, device="cuda"), 2.5)
+    torch.cuda.synchronize()
+    assert np.array_equal(pd.cpu().numpy(), p) and np.array_equal(gd.cpu().numpy(), g)
+    with pytest.raises(lss.LssError) as err:
+        lss.Context().eval_multiscale(x, 2.5)
+    assert err.value.code == 4
