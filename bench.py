@@ -181,7 +181,8 @@ def time_hessian(lss, torch, steps):
     the p = 2 chart nodes (6 per triangle) are projected once, then one step
     is lss_chart_curvature (the direct FP64 Hessian sum at every chart node
     plus the per-node second derivatives); lss_eval_hessian at the same points
-    is timed alone for the pair rate."""
+    is timed alone for the pair rate, and lss_eval_multiscale (target-attached
+    sigma(x)) at the same points as well (pairs counted as centroids + nodes)."""
     from workloads import configs, chart_nodes
     c2 = configs.config2(n_targets=1)
     dev = torch.device("cuda")
@@ -208,13 +209,24 @@ def time_hessian(lss, torch, steps):
         c.chart_curvature(uv, h)
     torch.cuda.synchronize()
     ec = (time.perf_counter() - t0) / steps
+    # the paper's target-attached width sigma(x) (lambda 2.5, sigma0 = sqrt(5) max D)
+    # at the same points: a pass over the centroids, then one over the nodes
+    c.eval_multiscale(x, 2.5, 0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        c.eval_multiscale(x, 2.5, 0.0)
+    torch.cuda.synchronize()
+    em = (time.perf_counter() - t0) / steps
     c.close()
     ach = HESS_FLOP_PER_PAIR * pairs / eh / 1e12
     return {"workload": "icosphere, %d tri, %d nodes, sigma 0.05, %d chart nodes (p = 2), direct FP64 Hessian"
                         % (len(c2["tris"]), 12 * len(c2["tris"]), n),
             "hessian_ms": 1e3 * eh, "hessian_pairs_per_s": pairs / eh, "hessian_points_per_s": n / eh,
             "hessian_tflops": round(ach, 3), "hessian_frac_f64": round(ach / PEAK["f64"], 4),
-            "curvature_ms": 1e3 * ec, "curvature_nodes_per_s": n / ec}
+            "curvature_ms": 1e3 * ec, "curvature_nodes_per_s": n / ec,
+            "multiscale_ms": 1e3 * em, "multiscale_points_per_s": n / em,
+            "multiscale_pairs_per_s": n * 13 * len(c2["tris"]) / em}
 
 
 def time_batch(lss, torch, b, uv, prec, per_surface):
