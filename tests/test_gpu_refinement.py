@@ -135,3 +135,38 @@ def test_quadratic_torus_study():
         assert abs(rows[(lev, True)][1]) < abs(rows[(lev, False)][1])
     for quad in (False, True):
         assert rows[(2, quad)][0] < rows[(1, quad)][0] < rows[(0, quad)][0]
+
+
+def test_refinement_of_quadratic_skeletons():
+    """1 -> 4 refinement keeps a skeleton's surface and shrinks sigma_j = D_j
+    / 10 with the triangles, so the level set approaches the skeleton: a flat
+    torus skeleton (12 x 6 cells) stays at its faceting error, the quadratic
+    one with the same corners goes on approaching the torus."""
+    from workloads import refine_1to4_quadratic
+    uv = chart_nodes(4)
+    v3, t3 = torus_mesh(12, 6)
+    v6, t6 = torus_mesh(12, 6, quadratic=True)
+    rows = {}
+    for lev in range(3):
+        for name, (v, t) in (("flat", (v3, t3)), ("quadratic", (v6, t6))):
+            corner = np.ascontiguousarray(t[:, :3])
+            sig = triangle_diameters(v, corner) / 10.0
+            c = lss.Context()
+            c.set_sources(v, t, dunavant6())
+            c.set_sigma(sig)
+            c.set_options(precision=lss.FP64, far_field=lss.FAR_FMM)
+            h, x, st, it = c.project(uv)
+            assert np.all(st == lss.NODE_CONVERGED)
+            d = torus_distance(x)
+            rows[(lev, name)] = (d.max(), d.mean())
+            say("level %d %-9s M %5d  max dist %.2e  mean dist %.2e" % (lev, name, len(t), d.max(), d.mean()))
+            c.close()
+        v3, t3 = refine_1to4(v3, t3)
+        v6, t6 = refine_1to4_quadratic(v6, t6)
+    for lev in range(3):
+        assert rows[(lev, "quadratic")][0] < 0.2 * rows[(lev, "flat")][0]
+    # the quadratic skeleton's charts keep approaching the torus (the maximum
+    # levels off at the coarse patches' own interpolation error, about 3e-3)
+    q = [rows[(lev, "quadratic")] for lev in range(3)]
+    assert q[2][0] < q[1][0] < q[0][0] and q[2][1] < 0.6 * q[1][1] < 0.36 * q[0][1]
+    assert rows[(2, "flat")][0] > 0.8 * rows[(0, "flat")][0]

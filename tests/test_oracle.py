@@ -820,3 +820,20 @@ def test_multiscale_gradient_includes_the_sigma_term():
     # the same sums at the fixed width sigma(x_i): the gradient without the term
     g_fixed = np.concatenate([oracle.evaluate(v, t, [s[i]], rule, x[i:i + 1])[1] for i in range(len(x))])
     assert np.abs(fd - g_fixed).max() / np.abs(g).max() > 1e-4
+
+
+def test_quadratic_refinement_keeps_the_surface():
+    """refine_1to4_quadratic: the refined skeleton is closed, shares its edge
+    points, and encloses exactly the parent's volume with the same (zero)
+    vector area: its patches are pieces of the parent patches."""
+    from workloads import refine_1to4_quadratic, mesh_check
+    v, t = torus_mesh(12, 6, quadratic=True)
+    rule = dunavant6()
+    y, a = oracle.nodes(v, t, rule)
+    vol0 = np.sum(y * a) / 3
+    for _ in range(2):
+        v, t = refine_1to4_quadratic(v, t)
+        closed, _ = mesh_check(v, np.ascontiguousarray(t[:, :3]))
+        assert closed and len(np.unique(t)) == len(v)
+        y, a = oracle.nodes(v, t, rule)
+        assert abs(np.sum(y * a) / 3 - vol0) < 1e-13 and np.abs(a.sum(0)).max() < 1e-13

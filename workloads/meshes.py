@@ -327,6 +327,70 @@ def refine_1to4(verts, tris):
     return np.concatenate([verts, mid]), new.astype(np.int32)
 
 
+def refine_1to4_quadratic(verts, tris6):
+    """Split every quadratic triangle into four (section 4.5 applied to the
+    curved skeleton): the new corners are the old corners and edge points,
+    the new edge points are points of the old patch, so the refined skeleton
+    describes the same surface.  On a patch with parameters (u, v) on T0 the
+    sub-triangles are (0,0)(1/2,0)(0,1/2), (1/2,0)(1,0)(1/2,1/2),
+    (0,1/2)(1/2,1/2)(0,1), (1/2,0)(1/2,1/2)(0,1/2); edge points on an old edge
+    are its quadratic curve at t = 1/4 and 3/4 (computed once per edge, so
+    neighbours share them), interior ones the patch at (1/4,1/4), (1/2,1/4),
+    (1/4,1/2)."""
+    verts = np.asarray(verts, dtype=np.float64)
+    t = np.asarray(tris6, dtype=np.int64)
+    nt = len(t)
+    P = verts[t]                                        # (nt, 6, 3)
+
+    def patch(u, v):                                    # quadratic Lagrange patch at (u, v)
+        l1, l2, l3 = 1.0 - u - v, u, v
+        N = np.array([l1 * (2 * l1 - 1), l2 * (2 * l2 - 1), l3 * (2 * l3 - 1), 4 * l1 * l2, 4 * l2 * l3, 4 * l3 * l1])
+        return np.einsum("k,nkc->nc", N, P)
+
+    # old edges (corner a, edge point m, corner b) as P1P2, P2P3, P3P1
+    ea = np.concatenate([t[:, 0], t[:, 1], t[:, 2]])
+    eb = np.concatenate([t[:, 1], t[:, 2], t[:, 0]])
+    em = np.concatenate([t[:, 3], t[:, 4], t[:, 5]])
+    lo, hi = np.minimum(ea, eb), np.maximum(ea, eb)
+    key = lo * (len(verts) + 1) + hi
+    uk, first, inv = np.unique(key, return_index=True, return_inverse=True)
+    inv = inv.reshape(-1)
+    A, B, M = verts[lo[first]], verts[hi[first]], verts[em[first]]
+
+    def curve(s):                                       # the edge's quadratic, s = 0 at the lower-index corner
+        return (1 - s) * (1 - 2 * s) * A + 4 * s * (1 - s) * M + s * (2 * s - 1) * B
+
+    nv = len(verts)
+    q_lo = curve(0.25)                                  # quarter point next to the lower-index corner
+    q_hi = curve(0.75)
+    ne = len(uk)
+    new = [verts, q_lo, q_hi]
+    base_lo, base_hi = nv, nv + ne
+    ins = [patch(0.25, 0.25), patch(0.5, 0.25), patch(0.25, 0.5)]
+    base_in = nv + 2 * ne
+    new += ins
+
+    def quarter(e_slot, near):
+        """index of the quarter point of old edge slot e_slot (0: P1P2, 1: P2P3,
+        2: P3P1 of every triangle) next to corner array `near`"""
+        e = inv[e_slot * nt:(e_slot + 1) * nt]
+        lo_e = lo[e_slot * nt:(e_slot + 1) * nt]
+        return np.where(near == lo_e, base_lo + e, base_hi + e)
+    c1, c2, c3, m12, m23, m31 = (t[:, k] for k in range(6))
+    q12a, q12b = quarter(0, c1), quarter(0, c2)         # (1/4,0) and (3/4,0)
+    q23a, q23b = quarter(1, c2), quarter(1, c3)         # (3/4,1/4) and (1/4,3/4)
+    q31a, q31b = quarter(2, c3), quarter(2, c1)         # (0,3/4) and (0,1/4)
+    i11 = base_in + np.arange(nt)                       # (1/4,1/4)
+    i21 = base_in + nt + np.arange(nt)                  # (1/2,1/4)
+    i12 = base_in + 2 * nt + np.arange(nt)              # (1/4,1/2)
+    out = np.concatenate([
+        np.stack([c1, m12, m31, q12a, i11, q31b], 1),
+        np.stack([m12, c2, m23, q12b, q23a, i21], 1),
+        np.stack([m31, m23, c3, i12, q23b, q31a], 1),
+        np.stack([m12, m23, m31, i21, i12, i11], 1)])
+    return np.concatenate(new), out.astype(np.int32)
+
+
 def mesh_check(verts, tris):
     """Return (closed, signed_volume): closed is True when every directed edge
     appears exactly once and its reverse exactly once (water-tight, consistently
