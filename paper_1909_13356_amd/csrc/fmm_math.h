@@ -274,5 +274,108 @@ LSS_HD void m2p(const double *M, double rx, double ry, double rz, double inv_s, 
     g[2] = -s1 * is2;
 }
 
+// Real-layout coefficient (n, m) as a complex number for any m in [-n, n]
+// (0 outside), by the symmetry of a real potential C_n^{-m} = (-1)^m conj(C_n^m).
+LSS_HD cd coef(const double *C, int n, int m) {
+    if (n < 0 || m > n || m < -n) return cd{0.0, 0.0};
+    const int a = m < 0 ? -m : m;
+    cd v = {C[ire(n, a)], a ? C[iim(n, a)] : 0.0};
+    if (m < 0) {
+        v = cconj(v);
+        if (a & 1) v = cscale(v, -1.0);
+    }
+    return v;
+}
+
+// Hessian H = (xx, xy, xz, yy, yz, zz) of a harmonic field from three
+// complex second derivatives: Z = d2/dz2, W = dz (dx + i dy), P = (dx + i dy)^2
+// (P = Hxx - Hyy + 2i Hxy, W = Hxz + i Hyz, Hxx + Hyy = -Hzz).
+LSS_HD void hess_from(double Z, cd W, cd P, double H[6]) {
+    H[5] = Z;
+    H[2] = W.re;
+    H[4] = W.im;
+    H[1] = 0.5 * P.im;
+    H[0] = 0.5 * (P.re - Z);
+    H[3] = 0.5 * (-P.re - Z);
+}
+
+// L2P Hessian: second derivatives of the local expansion (scaled L~, box side
+// s) at the scaled position r.  From dz U_n^m = U_{n-1}^m and (dx + i dy) U_n^m
+// = U_{n-1}^{m+1}:
+//   d2/dz2 Phi        = s^-2 sum_{j,s} L~_{j+2}^s     U_j^s(r)
+//   dz (dx + i dy)Phi = s^-2 sum_{j,s} L~_{j+2}^{s-1} U_j^s(r)
+//   (dx + i dy)^2 Phi = s^-2 sum_{j,s} L~_{j+2}^{s-2} U_j^s(r)
+// with U_j^s generated column by column (s >= 0) and U_j^{-s} = (-1)^s conj(U_j^s).
+LSS_HD void l2p_hess(const double *L, double rx, double ry, double rz, double inv_s, int p, double H[6]) {
+    const double r2 = rx * rx + ry * ry + rz * rz;
+    cd Z = {0.0, 0.0}, W = {0.0, 0.0}, P = {0.0, 0.0};
+    cd diag = {1.0, 0.0};
+    for (int m = 0; m + 2 <= p; ++m) {
+        if (m > 0) diag = cscale(cmul(diag, cd{rx, ry}), -0.5 / (double)m);
+        cd um2 = {0.0, 0.0}, u = diag;
+        for (int j = m; j + 2 <= p; ++j) {
+            if (j > m) {
+                const double inv = 1.0 / ((double)(j + m) * (double)(j - m));
+                cd un = {((2 * j - 1) * rz * u.re - r2 * um2.re) * inv, ((2 * j - 1) * rz * u.im - r2 * um2.im) * inv};
+                um2 = u;
+                u = un;
+            }
+            Z = cadd(Z, cmul(coef(L, j + 2, m), u));
+            W = cadd(W, cmul(coef(L, j + 2, m - 1), u));
+            P = cadd(P, cmul(coef(L, j + 2, m - 2), u));
+            if (m > 0) {
+                cd un = cconj(u);
+                if (m & 1) un = cscale(un, -1.0);           // U_j^{-m}
+                Z = cadd(Z, cmul(coef(L, j + 2, -m), un));
+                W = cadd(W, cmul(coef(L, j + 2, -m - 1), un));
+                P = cadd(P, cmul(coef(L, j + 2, -m - 2), un));
+            }
+        }
+    }
+    const double is2 = inv_s * inv_s;
+    hess_from(Z.re * is2, cscale(W, is2), cscale(P, is2), H);
+}
+
+// M2P Hessian: second derivatives of a multipole expansion (scaled M~, box
+// side s) at the scaled position r outside the box's sphere.  From
+// dz T_n^m = -T_{n+1}^m and (dx - i dy) T_n^m = -T_{n+1}^{m-1} (unit side):
+//   d2/dz2 Phi        = s^-3 sum_{n,m} T_{n+2}^m     M~_n^m
+//   dz (dx - i dy)Phi = s^-3 sum_{n,m} T_{n+2}^{m-1} M~_n^m
+//   (dx - i dy)^2 Phi = s^-3 sum_{n,m} T_{n+2}^{m-2} M~_n^m
+// and, Phi being real, the (dx + i dy) forms are their conjugates.  T_j^mu is
+// generated column by column (mu >= 0, j = mu..p+2) with T_j^{-mu} =
+// (-1)^mu conj(T_j^mu); the term T_j^mu pairs with M~_{j-2}^{mu+q}, q = 0, 1, 2.
+LSS_HD void m2p_hess(const double *M, double rx, double ry, double rz, double inv_s, int p, double H[6]) {
+    const double r2 = rx * rx + ry * ry + rz * rz, ir2 = 1.0 / r2;
+    cd Z = {0.0, 0.0}, W = {0.0, 0.0}, P = {0.0, 0.0};
+    cd diag = {sqrt(ir2), 0.0};
+    for (int mu = 0; mu <= p + 2; ++mu) {
+        if (mu > 0) diag = cscale(cmul(diag, cd{rx, ry}), -(2.0 * mu - 1.0) * ir2);
+        cd tm2 = {0.0, 0.0}, t = diag;
+        for (int j = mu; j <= p + 2; ++j) {
+            if (j > mu) {
+                const double a = (2 * j - 1) * rz, b = (double)(j - 1 + mu) * (double)(j - 1 - mu);
+                cd tn = {(a * t.re - b * tm2.re) * ir2, (a * t.im - b * tm2.im) * ir2};
+                tm2 = t;
+                t = tn;
+            }
+            if (j < 2) continue;
+            const int n = j - 2;
+            Z = cadd(Z, cmul(t, coef(M, n, mu)));
+            W = cadd(W, cmul(t, coef(M, n, mu + 1)));
+            P = cadd(P, cmul(t, coef(M, n, mu + 2)));
+            if (mu > 0) {
+                cd tn = cconj(t);
+                if (mu & 1) tn = cscale(tn, -1.0);          // T_j^{-mu}
+                Z = cadd(Z, cmul(tn, coef(M, n, -mu)));
+                W = cadd(W, cmul(tn, coef(M, n, -mu + 1)));
+                P = cadd(P, cmul(tn, coef(M, n, -mu + 2)));
+            }
+        }
+    }
+    const double is3 = inv_s * inv_s * inv_s;
+    hess_from(Z.re * is3, cconj(cscale(W, is3)), cconj(cscale(P, is3)), H);
+}
+
 }  // namespace fmm
 }  // namespace lss

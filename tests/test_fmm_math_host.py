@@ -81,3 +81,105 @@ def test_m2p_series_matches_direct_sum(m2p_prog, p, rmin, bound):
     assert err <= bound
     if p == 8:
         assert err > 1e-6                     # truncation visible: the high orders do matter
+
+
+HESS_PROG = textwrap.dedent(r"""
+    #include <cmath>
+    #include <cstdio>
+    #include <cstdlib>
+    #include <vector>
+    #include "fmm_math.h"
+    using namespace lss::fmm;
+    // Hessians of the M2P and L2P series of point charges against the direct
+    // Hessian of sum q / |x - y|: d2/dxi dxj 1/|d| = (3 d_i d_j - delta_ij |d|^2) / |d|^5.
+    static void direct(const double x[3], double y[][3], const double *q, int nq, double H[6]) {
+        const int I[6] = {0, 0, 0, 1, 1, 2}, J[6] = {0, 1, 2, 1, 2, 2};
+        for (int k = 0; k < 6; ++k) H[k] = 0.0;
+        for (int e = 0; e < nq; ++e) {
+            const double d[3] = {x[0] - y[e][0], x[1] - y[e][1], x[2] - y[e][2]};
+            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2], r5 = r2 * r2 * sqrt(r2);
+            for (int k = 0; k < 6; ++k) H[k] += q[e] * (3 * d[I[k]] * d[J[k]] - (I[k] == J[k] ? r2 : 0.0)) / r5;
+        }
+    }
+    int main(int argc, char **argv) {
+        const int p = atoi(argv[1]);
+        const double rmin = atof(argv[2]);
+        srand(11);
+        auto rnd = [] { return rand() / (double)RAND_MAX - 0.5; };
+        double worst_m = 0.0, worst_l = 0.0;
+        for (int trial = 0; trial < 200; ++trial) {
+            const double s = 0.37, c[3] = {0.1, -0.2, 0.3};
+            double y[6][3], q[6], aq = 0.0;
+            for (int k = 0; k < 6; ++k) q[k] = rnd(), aq += fabs(q[k]);
+            double dir[3] = {rnd(), rnd(), rnd()};
+            const double nd = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+            const double R = s * (rmin + 0.2 * (rnd() + 0.5));
+            // M2P: charges in the box, target at distance R
+            {
+                std::vector<double> M(ncoef(p), 0.0);
+                std::vector<cd> U(tri(p, p) + 1);
+                for (int k = 0; k < 6; ++k) {
+                    for (int d = 0; d < 3; ++d) y[k][d] = c[d] + rnd() * s;
+                    regular_table((y[k][0] - c[0]) / s, (y[k][1] - c[1]) / s, (y[k][2] - c[2]) / s, p, U.data());
+                    for (int n = 0; n <= p; ++n)
+                        for (int m = 0; m <= n; ++m) {
+                            M[ire(n, m)] += q[k] * U[tri(n, m)].re;
+                            if (m) M[iim(n, m)] -= q[k] * U[tri(n, m)].im;
+                        }
+                }
+                double x[3], H[6], E[6];
+                for (int d = 0; d < 3; ++d) x[d] = c[d] + R * dir[d] / nd;
+                m2p_hess(M.data(), (x[0] - c[0]) / s, (x[1] - c[1]) / s, (x[2] - c[2]) / s, 1.0 / s, p, H);
+                direct(x, y, q, 6, E);
+                for (int k = 0; k < 6; ++k) worst_m = fmax(worst_m, fabs(H[k] - E[k]) / (aq / (R * R * R)));
+            }
+            // L2P: charges at distance R, target in the box; L~_n^m = s^n sum q conj(T_n^m(y - c))
+            {
+                std::vector<double> L(ncoef(p), 0.0);
+                std::vector<cd> T(tri(p, p) + 1);
+                for (int k = 0; k < 6; ++k) {
+                    const double R2 = s * (rmin + 0.2 * (rnd() + 0.5));
+                    double e[3] = {rnd(), rnd(), rnd()};
+                    const double ne = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+                    for (int d = 0; d < 3; ++d) y[k][d] = c[d] + R2 * e[d] / ne;
+                    irregular_table(y[k][0] - c[0], y[k][1] - c[1], y[k][2] - c[2], p, T.data());
+                    double sn = 1.0;
+                    for (int n = 0; n <= p; ++n, sn *= s)
+                        for (int m = 0; m <= n; ++m) {
+                            L[ire(n, m)] += q[k] * sn * T[tri(n, m)].re;
+                            if (m) L[iim(n, m)] -= q[k] * sn * T[tri(n, m)].im;
+                        }
+                }
+                double x[3], H[6], E[6];
+                for (int d = 0; d < 3; ++d) x[d] = c[d] + 0.5 * s * rnd();
+                l2p_hess(L.data(), (x[0] - c[0]) / s, (x[1] - c[1]) / s, (x[2] - c[2]) / s, 1.0 / s, p, H);
+                direct(x, y, q, 6, E);
+                const double Rmin = s * rmin;
+                for (int k = 0; k < 6; ++k) worst_l = fmax(worst_l, fabs(H[k] - E[k]) / (aq / (Rmin * Rmin * Rmin)));
+            }
+        }
+        printf("%.6e %.6e\n", worst_m, worst_l);
+        return 0;
+    }
+""")
+
+
+@pytest.fixture(scope="module")
+def hess_prog(tmp_path_factory):
+    d = tmp_path_factory.mktemp("hess")
+    src = d / "hess.cpp"
+    src.write_text(HESS_PROG)
+    exe = d / "hess"
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-I", CSRC, str(src), "-o", str(exe)])
+    return str(exe)
+
+
+# M2P and L2P Hessians against the direct Hessian of the charges (relative to
+# sum |q| / R^3) at the separations of the two precisions' lists, and at a low
+# order where the truncation shows
+@pytest.mark.parametrize("p,rmin,bound", [(20, 2.0, 3e-6), (26, 2.83, 2e-12), (8, 2.0, 1.0)])
+def test_m2p_l2p_hessian_match_direct_sum(hess_prog, p, rmin, bound):
+    em, el = (float(v) for v in subprocess.check_output([hess_prog, str(p), str(rmin)]).decode().split())
+    assert em <= bound and el <= bound
+    if p == 8:
+        assert max(em, el) > 1e-6
