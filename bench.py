@@ -168,8 +168,18 @@ def time_newton(lss, torch, cfg, prec, steps, warmup):
         c.chart_interp(uv, x, ev)
     torch.cuda.synchronize()
     ei = time.perf_counter() - t0
+    # second derivatives and curvatures of every chart: the Hessian through
+    # the octree at x = T + h H plus the per-node kernel (section 3.1)
+    c.chart_curvature(uv, h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        c.chart_curvature(uv, h)
+    torch.cuda.synchronize()
+    ek = time.perf_counter() - t0
     c.close()
     return {"chart_nodes_per_s": n_nodes * steps / el, "target_evals_per_s": evals / el,
+            "curvature_nodes_per_s": n_nodes * steps / ek, "curvature_ms": 1e3 * ek / steps,
             "ms_per_step": 1e3 * el / steps, "newton_graph_ms": gms / steps, "iterations": iters,
             "evals_per_node": evals / steps / n_nodes, "converged_frac": conv,
             "geometry_nodes_per_s": n_nodes * steps / eg, "geometry_ms": 1e3 * eg / steps,
@@ -178,11 +188,12 @@ def time_newton(lss, torch, cfg, prec, steps, warmup):
 
 def time_hessian(lss, torch, steps):
     """Hessian and chart curvature on the 20,480-triangle sphere (sigma 0.05):
-    the p = 2 chart nodes (6 per triangle) are projected once, then one step
-    is lss_chart_curvature (the direct FP64 Hessian sum at every chart node
-    plus the per-node second derivatives); lss_eval_hessian at the same points
-    is timed alone for the pair rate, and lss_eval_multiscale (target-attached
-    sigma(x)) at the same points as well (pairs counted as centroids + nodes)."""
+    the p = 2 chart nodes (6 per triangle) are projected once; then
+    lss_eval_hessian at those points through the octree (FP64 settings) and
+    by the direct sum over every pair (the pair rate), lss_chart_curvature
+    (octree Hessian plus the per-node second derivatives), and
+    lss_eval_multiscale (target-attached sigma(x), direct; pairs counted as
+    centroids + nodes)."""
     from workloads import configs, chart_nodes
     c2 = configs.config2(n_targets=1)
     dev = torch.device("cuda")
@@ -195,13 +206,22 @@ def time_hessian(lss, torch, steps):
     h, x, st, it = c.project(uv, device=True)
     n = len(x)
     pairs = n * 12 * len(c2["tris"])
-    c.eval_hessian(x)
+    c.eval_hessian(x)                      # through the octree (near lists + expansions)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        c.eval_hessian(x)
+    torch.cuda.synchronize()
+    ef = (time.perf_counter() - t0) / steps
+    c.set_options(precision=lss.FP64, far_field=lss.FAR_DIRECT)
+    c.eval_hessian(x)                      # every pair
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         c.eval_hessian(x)
     torch.cuda.synchronize()
     eh = (time.perf_counter() - t0) / steps
+    c.set_options(precision=lss.FP64, far_field=lss.FAR_FMM)
     c.chart_curvature(uv, h)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -220,8 +240,9 @@ def time_hessian(lss, torch, steps):
     em = (time.perf_counter() - t0) / steps
     c.close()
     ach = HESS_FLOP_PER_PAIR * pairs / eh / 1e12
-    return {"workload": "icosphere, %d tri, %d nodes, sigma 0.05, %d chart nodes (p = 2), direct FP64 Hessian"
+    return {"workload": "icosphere, %d tri, %d nodes, sigma 0.05, %d chart nodes (p = 2), FP64 Hessian"
                         % (len(c2["tris"]), 12 * len(c2["tris"]), n),
+            "hessian_fmm_ms": 1e3 * ef, "hessian_fmm_points_per_s": n / ef,
             "hessian_ms": 1e3 * eh, "hessian_pairs_per_s": pairs / eh, "hessian_points_per_s": n / eh,
             "hessian_tflops": round(ach, 3), "hessian_frac_f64": round(ach / PEAK["f64"], 4),
             "curvature_ms": 1e3 * ec, "curvature_nodes_per_s": n / ec,

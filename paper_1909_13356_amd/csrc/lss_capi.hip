@@ -126,7 +126,8 @@ void ensure_targets(Ctx &c, int64_t n) {
 // FMM evaluation of the targets already in c.tx/ty/tz[0..n) (count *n_dev on
 // the device if given): leaf of each target, targets sorted by leaf, tiles,
 // near field + L2P.  Outputs at the target's index in tx/ty/tz.
-void eval_fmm_targets(Ctx &c, int64_t n, const int32_t *n_dev, double *phi, double *grad, bool reset_pairs = true) {
+void eval_fmm_targets(Ctx &c, int64_t n, const int32_t *n_dev, double *phi, double *grad, bool reset_pairs = true,
+                      double *hess = nullptr) {
     launch_locate_targets(c, n, n_dev, c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(),
                           c.tmesh.as<int32_t>(), c.tkey.as<uint64_t>(), c.tperm.as<int32_t>());
     sort_pairs(c, c.tkey.as<uint64_t>(), c.tkey2.as<uint64_t>(), c.tperm.as<int32_t>(), c.tperm2.as<int32_t>(), n, 64);
@@ -140,7 +141,8 @@ void eval_fmm_targets(Ctx &c, int64_t n, const int32_t *n_dev, double *phi, doub
     if (reset_pairs) LSS_HIP(hipMemsetAsync(c.pairs.p, 0, 2 * sizeof(double), c.stream));
     c.ev_begin();
     launch_eval_fmm(c, n, c.ntiles.as<int32_t>(), c.tstart.as<int32_t>(), n_dev, n, c.tleaf.as<int32_t>(),
-                    c.tperm2.as<int32_t>(), c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(), nullptr, phi, grad);
+                    c.tperm2.as<int32_t>(), c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(), nullptr, phi, grad,
+                    hess);
     c.ev_end();
 }
 
@@ -420,7 +422,15 @@ void eval_hessian(Ctx &c, const double *x, const int32_t *xm, int64_t n, double 
         LSS_HIP(hipStreamSynchronize(c.stream));
         if (nb) fail(LSS_EINVAL, "lss_eval_hessian: x_mesh values outside [0, nmesh)");
     }
-    launch_hessian_direct(c, n, dx, dxm, dphi, dgrad, dhess);
+    if (c.opt.far_field == LSS_FAR_FMM) {       // near lists + expansions of the context's tree
+        ensure_targets(c, n);
+        c.ev_reset();
+        launch_soa(c, dx, n, c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>());
+        if (dxm) LSS_HIP(hipMemcpyAsync(c.tmesh.p, dxm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c.stream));
+        eval_fmm_targets(c, n, nullptr, dphi, dgrad, true, dhess);
+    } else {
+        launch_hessian_direct(c, n, dx, dxm, dphi, dgrad, dhess);
+    }
     if (!dev) {
         if (phi) LSS_HIP(hipMemcpyAsync(phi, dphi, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
         if (grad) LSS_HIP(hipMemcpyAsync(grad, dgrad, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, c.stream));
@@ -516,8 +526,8 @@ void chart_curvature(Ctx &c, const double *uv, int32_t np, const double *h, doub
     launch_chart_points(c, duv.as<double>(), np, N, ph, x.as<double>(), c.nmesh > 1 ? xm.as<int32_t>() : nullptr);
     grad.ensure(sizeof(double) * 3 * N);
     hess.ensure(sizeof(double) * 6 * N);
-    launch_hessian_direct(c, N, x.as<double>(), c.nmesh > 1 ? xm.as<int32_t>() : nullptr, nullptr,
-                          grad.as<double>(), hess.as<double>());
+    eval_hessian(c, x.as<double>(), c.nmesh > 1 ? xm.as<int32_t>() : nullptr, N, nullptr, grad.as<double>(),
+                 hess.as<double>(), LSS_PTR_DEVICE);
     double *out[5] = {xuu, xuv, xvv, gauss, mean};
     const int width[5] = {3, 3, 3, 1, 1};
     double *q[5];

@@ -5,71 +5,19 @@
 // (section 2, eq. basemodelk, convkernel, sigma2).
 //
 // Per source node (y, a' = c w J, s2 = 1/(2 sigma^2), c = 1/(4 sqrt2 pi^1.5
-// sigma^3)) and target x, d = x - y, t = |d|^2 s2 = u^2, the three radial
-// functions of the kernel in units of the folded amplitude, K c = k1,
-// F c = k2, G c = k3 (F = K'/rho, G = F'/rho), are
-//   t < 9/4:   k1 = S(3), k2 = -2 s2 S(5), k3 = 4 s2^2 S(7),
-//              S(m) = sum_k 2 (-t)^k / (k! (2k + m))      (term-wise series)
-//   t >= 9/4:  with q = 2/sqrt(pi), e = exp(-t):
-//              P3 = erf(u) - q u e,  P5 = P3 - q (2/3) u^3 e,  P7 = P5 - q (4/15) u^5 e
-//              (the regularised incomplete gamma functions P(3/2|5/2|7/2, t)),
-//              k1 = (sqrt(pi)/2) P3 / u^3, k2 = -(3 sqrt(pi)/2) s2 P5 / u^5,
-//              k3 = (15 sqrt(pi)/2) s2^2 P7 / u^7,  and P3 = P5 = P7 = 1 for
-//              t >= 50, where the dropped terms are below 1e-18.
-// Then Phi -= (a'.d) k1, grad Phi += -a' k1 - (a'.d) k2 d, and
-//   Hess += -k2 (a' d^T + d a'^T) - (a'.d) k2 I - (a'.d) k3 d d^T.
+// sigma^3)) and target x, d = x - y, t = |d|^2 s2, the radial functions
+// k1 = K/c, k2 = F/c, k3 = G/c come from radial3 (radial_exact.h).
+// Each pair is accumulated by pair_hess (radial_exact.h).
 // Every pair uses the full kernel (no cut, no far-field expansion).
 #include <climits>
 
 #include "lss_internal.h"
+#include "radial_exact.h"
 
 namespace lss {
 namespace {
 
-constexpr double kSqrtPi = 1.7724538509055160273;
-
 inline unsigned blocks256(int64_t n) { return (unsigned)((n + 255) / 256); }
-
-// e receives exp(-t) (0 for t >= 50), which the target-attached width needs
-__device__ inline void radial3(double t, double s2, double &k1, double &k2, double &k3, double &e) {
-    if (t < 2.25) {
-        double p = 1.0, a0 = 0.0, a3 = 0.0, a5 = 0.0, a7 = 0.0;
-#pragma unroll
-        for (int k = 0; k < 30; ++k) {
-            a0 += p;
-            a3 += p * (2.0 / (2 * k + 3));
-            a5 += p * (2.0 / (2 * k + 5));
-            a7 += p * (2.0 / (2 * k + 7));
-            p *= -t * (1.0 / (k + 1));
-        }
-        k1 = a3;
-        k2 = -2.0 * s2 * a5;
-        k3 = 4.0 * s2 * s2 * a7;
-        e = a0;
-        return;
-    }
-    // 1/u = t^-1/2: hardware estimate and two Newton steps (to rounding)
-    double iu = __builtin_amdgcn_rsq(t);
-    const double ht = 0.5 * t;
-    iu = iu * fma(-ht * iu, iu, 1.5);
-    iu = iu * fma(-ht * iu, iu, 1.5);
-    double P3 = 1.0, P5 = 1.0, P7 = 1.0;
-    e = 0.0;
-    if (t < 50.0) {
-        const double u = t * iu;
-        e = exp(-t);
-        const double qe = (2.0 / kSqrtPi) * e;
-        const double u3 = u * t;
-        P3 = erf(u) - qe * u;
-        P5 = P3 - qe * (2.0 / 3.0) * u3;
-        P7 = P5 - qe * (4.0 / 15.0) * u3 * t;
-    }
-    const double iu2 = iu * iu;
-    const double iu3 = iu * iu2, iu5 = iu3 * iu2, iu7 = iu5 * iu2;
-    k1 = (0.5 * kSqrtPi) * P3 * iu3;
-    k2 = -(1.5 * kSqrtPi) * s2 * P5 * iu5;
-    k3 = (7.5 * kSqrtPi) * s2 * s2 * P7 * iu7;
-}
 
 // One thread per target.  The block walks the union of its targets' node
 // ranges in tiles of 256 records staged in LDS (every lane then reads the
@@ -106,49 +54,29 @@ __global__ void __launch_bounds__(256) k_hessian_direct(int64_t n, const double 
     }
     __syncthreads();
     const int64_t lo = blo, hi = bhi;
-    double f = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
-    double hxx = 0.0, hxy = 0.0, hxz = 0.0, hyy = 0.0, hyz = 0.0, hzz = 0.0;
+    HessAcc A;
     for (int64_t base = lo; base < hi; base += 256) {
         __syncthreads();
         if (base + threadIdx.x < hi) tile[threadIdx.x] = src[base + threadIdx.x];
         __syncthreads();
         const int64_t k0 = j0 > base ? j0 - base : 0;
         const int64_t k1 = (j1 - base < 256) ? j1 - base : 256;
-        for (int64_t k = k0; k < k1; ++k) {
-            const Src s = tile[k];
-            const double dx = px - s.yx, dy = py - s.yy, dz = pz - s.yz;
-            const double t = (dx * dx + dy * dy + dz * dz) * s.s2;
-            double k1r, k2, k3, et;
-            radial3(t, s.s2, k1r, k2, k3, et);
-            const double ad = s.ax * dx + s.ay * dy + s.az * dz;
-            f -= ad * k1r;
-            const double adk2 = ad * k2, adk3 = ad * k3;
-            gx -= s.ax * k1r + adk2 * dx;
-            gy -= s.ay * k1r + adk2 * dy;
-            gz -= s.az * k1r + adk2 * dz;
-            const double ex = adk3 * dx, ey = adk3 * dy, ez = adk3 * dz;
-            hxx -= 2.0 * k2 * s.ax * dx + adk2 + ex * dx;
-            hyy -= 2.0 * k2 * s.ay * dy + adk2 + ey * dy;
-            hzz -= 2.0 * k2 * s.az * dz + adk2 + ez * dz;
-            hxy -= k2 * (s.ax * dy + s.ay * dx) + ex * dy;
-            hxz -= k2 * (s.ax * dz + s.az * dx) + ex * dz;
-            hyz -= k2 * (s.ay * dz + s.az * dy) + ey * dz;
-        }
+        for (int64_t k = k0; k < k1; ++k) pair_hess(tile[k], px, py, pz, A);
     }
     if (!act) return;
-    if (phi) phi[i] = f;
+    if (phi) phi[i] = A.f;
     if (grad) {
-        grad[3 * i] = gx;
-        grad[3 * i + 1] = gy;
-        grad[3 * i + 2] = gz;
+        grad[3 * i] = A.gx;
+        grad[3 * i + 1] = A.gy;
+        grad[3 * i + 2] = A.gz;
     }
     double *o = hess + 6 * i;
-    o[0] = hxx;
-    o[1] = hxy;
-    o[2] = hxz;
-    o[3] = hyy;
-    o[4] = hyz;
-    o[5] = hzz;
+    o[0] = A.hxx;
+    o[1] = A.hxy;
+    o[2] = A.hxz;
+    o[3] = A.hyy;
+    o[4] = A.hyz;
+    o[5] = A.hzz;
 }
 
 // Target-attached width (section 2, eq. basemodelk, convkernel, sigma2).

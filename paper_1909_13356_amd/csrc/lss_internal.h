@@ -310,7 +310,7 @@ int fmm_tile(const Ctx &c);
 void launch_eval_fmm(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const int32_t *tile_start,
                      const int32_t *n_dev, int64_t n_max, const int32_t *sorted_leaf, const int32_t *sorted_idx,
                      const double *tx, const double *ty, const double *tz, const int32_t *out_idx, double *phi,
-                     double *grad);
+                     double *grad, double *hess = nullptr);
 void launch_soa(Ctx &c, const double *x, int64_t n, double *tx, double *ty, double *tz);
 // Newton targets in FMM mode: leaf of each target in its current order and
 // tile heads at leaf changes and every TILE-th position (no sort; capturable)

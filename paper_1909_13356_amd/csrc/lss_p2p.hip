@@ -26,6 +26,7 @@
 #include "fmm_math.h"
 #include "kfit_tables.h"
 #include "lss_internal.h"
+#include "radial_exact.h"
 
 namespace lss {
 
@@ -647,6 +648,142 @@ __global__ __launch_bounds__(256) void k_eval_outside(FmmEvalArgs a) {
     }
 }
 
+// ---------------------------------------------------------------- Hessian
+// Phi, grad Phi and the Hessian through the same tree and lists (section
+// 3.1 needs the Hessian for the charts' second derivatives): the near list
+// with the full kernel and its third radial function (pair_hess), the M2P
+// list and the leaf's local expansion with their second derivatives
+// (fmm::m2p_hess, fmm::l2p_hess).  Beyond the cut the kernel is the Laplace
+// double layer to the truncation of the cut (8 sigma: P(7/2, 32) differs from
+// 1 by 2e-11 relative, so the Hessian bar is looser than the field's).  FP64
+// in either precision setting; the context's cut and order set the accuracy.
+__device__ __forceinline__ void fmm_m2p_list_hess(const FmmEvalArgs &a, int32_t B, double *buf, double x, double y,
+                                                  double z, double &ph, double g[3], double H[6]) {
+    const int e0 = a.m2p_beg[B], e1 = a.m2p_end[B];
+    for (int e = e0; e < e1; ++e) {
+        const int32_t S = a.m2p_src[e];
+        __syncthreads();
+        const double *src = a.M + (int64_t)S * a.ncp;
+        for (int k = threadIdx.x; k < a.ncp; k += blockDim.x) buf[k] = src[k];
+        __syncthreads();
+        const double s = box_side(a.root, a.bmesh, S, a.lev[S]);
+        const double *o = a.root + 4 * a.bmesh[S];
+        const double inv = 1.0 / s;
+        const double rx = (x - (o[0] + (a.ijk[3 * S] + 0.5) * s)) * inv;
+        const double ry = (y - (o[1] + (a.ijk[3 * S + 1] + 0.5) * s)) * inv;
+        const double rz = (z - (o[2] + (a.ijk[3 * S + 2] + 0.5) * s)) * inv;
+        double p1, g1[3], h1[6];
+        fmm::m2p(buf, rx, ry, rz, inv, a.p, p1, g1);
+        fmm::m2p_hess(buf, rx, ry, rz, inv, a.p, h1);
+        ph += p1;
+        for (int d = 0; d < 3; ++d) g[d] += g1[d];
+        for (int d = 0; d < 6; ++d) H[d] += h1[d];
+    }
+    __syncthreads();
+}
+
+// one workgroup of TILE lanes per tile (the tiles of the evaluation, at most
+// TILE targets of one leaf), tiles taken in a grid-stride loop
+template <int TILE>
+__global__ __launch_bounds__(TILE) void k_hess_fmm(FmmEvalArgs a, double *hess) {
+    __shared__ Src sh[TILE];
+    __shared__ RangeBatch<TILE> rb;
+    extern __shared__ double Ls[];      // local expansion of the tile's leaf (ncp doubles)
+    const int ntiles = *a.ntiles_dev;
+    const int64_t n = a.n_dev ? (int64_t)*a.n_dev : a.n_max;
+    const int lane = threadIdx.x;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t s0 = a.tile_start[tile];
+        const int32_t B = a.sleaf[s0];
+        const int64_t s1 = tile + 1 < ntiles ? (int64_t)a.tile_start[tile + 1] : n;
+        if (B >= a.nboxes) continue;        // outside the root cube: k_hess_outside
+        const int64_t sp_ = s0 + lane;
+        const bool valid = sp_ < s1;
+        const int64_t ti = a.sidx ? (int64_t)a.sidx[valid ? sp_ : s0] : (valid ? sp_ : s0);
+        const double x = a.tx[ti], y = a.ty[ti], z = a.tz[ti];
+        const int e0 = a.p2p_beg[B], e1 = a.p2p_end[B];
+        HessAcc A;
+        for (int eb = e0; eb < e1; eb += TILE) {
+            const int nr = e1 - eb < TILE ? e1 - eb : TILE;
+            __syncthreads();
+            const int64_t total = load_ranges<TILE>(a, rb, eb, nr);
+            for (int64_t c0 = 0; c0 < total; c0 += TILE) {
+                const int cnt = (int)(total - c0 < TILE ? total - c0 : TILE);
+                __syncthreads();
+                if (lane < cnt) sh[lane] = a.src[packed_node<TILE>(rb, nr, c0 + lane)];
+                __syncthreads();
+                for (int j = 0; j < cnt; ++j) pair_hess(sh[j], x, y, z, A);
+            }
+        }
+        double ph = 0.0, g[3] = {0.0, 0.0, 0.0}, H[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        fmm_m2p_list_hess(a, B, Ls, x, y, z, ph, g, H);
+        stage_local(a, B, Ls);
+        __syncthreads();
+        {
+            double lp, lg[3];                // fmm_l2p writes (does not add) its outputs
+            fmm_l2p(a, B, Ls, x, y, z, lp, lg);
+            ph += lp;
+            for (int d = 0; d < 3; ++d) g[d] += lg[d];
+        }
+        {
+            const double s = box_side(a.root, a.bmesh, B, a.lev[B]);
+            const double *o = a.root + 4 * a.bmesh[B];
+            const double inv = 1.0 / s;
+            double h1[6];
+            fmm::l2p_hess(Ls, (x - (o[0] + (a.ijk[3 * B] + 0.5) * s)) * inv,
+                          (y - (o[1] + (a.ijk[3 * B + 1] + 0.5) * s)) * inv,
+                          (z - (o[2] + (a.ijk[3 * B + 2] + 0.5) * s)) * inv, inv, a.p, h1);
+            for (int d = 0; d < 6; ++d) H[d] += h1[d];
+        }
+        __syncthreads();                    // everyone is done with Ls before the next tile
+        if (valid) {
+            const int64_t o = a.out_idx ? (int64_t)a.out_idx[ti] : ti;
+            if (a.phi) a.phi[o] = A.f + ph;
+            if (a.grad) {
+                a.grad[3 * o] = A.gx + g[0];
+                a.grad[3 * o + 1] = A.gy + g[1];
+                a.grad[3 * o + 2] = A.gz + g[2];
+            }
+            double *q = hess + 6 * o;
+            q[0] = A.hxx + H[0];
+            q[1] = A.hxy + H[1];
+            q[2] = A.hxz + H[2];
+            q[3] = A.hyy + H[3];
+            q[4] = A.hyz + H[4];
+            q[5] = A.hzz + H[5];
+        }
+    }
+}
+
+// targets outside their mesh's root cube: the direct sum over the mesh's
+// nodes (the level-0 box m holds them all), one thread per target
+__global__ __launch_bounds__(256) void k_hess_outside(FmmEvalArgs a, double *hess) {
+    const int64_t n = a.n_dev ? (int64_t)*a.n_dev : a.n_max;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t B = a.sleaf[i];
+        if (B < a.nboxes) continue;
+        const int32_t m = B - a.nboxes;
+        const int64_t ti = a.sidx ? (int64_t)a.sidx[i] : i;
+        const double x = a.tx[ti], y = a.ty[ti], z = a.tz[ti];
+        HessAcc A;
+        for (int64_t k = a.nb[m]; k < a.ne[m]; ++k) pair_hess(a.src[k], x, y, z, A);
+        const int64_t o = a.out_idx ? (int64_t)a.out_idx[ti] : ti;
+        if (a.phi) a.phi[o] = A.f;
+        if (a.grad) {
+            a.grad[3 * o] = A.gx;
+            a.grad[3 * o + 1] = A.gy;
+            a.grad[3 * o + 2] = A.gz;
+        }
+        double *q = hess + 6 * o;
+        q[0] = A.hxx;
+        q[1] = A.hxy;
+        q[2] = A.hxz;
+        q[3] = A.hyy;
+        q[4] = A.hyz;
+        q[5] = A.hzz;
+    }
+}
+
 // Four waves per SIMD: the compiler fits the kernel in 128 VGPRs with a few
 // spills outside the chunk loop (1% faster on C5 than three waves at 139).
 template <int TILE>
@@ -844,6 +981,13 @@ void launch_tile(Ctx &c, int64_t n, const int32_t *n_dev, const double *tx, cons
 }
 
 template <int TILE>
+void launch_hess_tile(Ctx &c, unsigned grid, const FmmEvalArgs &a, double *hess) {
+    const size_t shm = sizeof(double) * (size_t)a.ncp;
+    hipLaunchKernelGGL(k_hess_fmm<TILE>, dim3(grid), dim3(TILE), shm, c.stream, a, hess);
+    LSS_CHECK_LAUNCH("k_hess_fmm");
+}
+
+template <int TILE>
 void launch_fmm_tile(Ctx &c, unsigned grid, const FmmEvalArgs &a) {
     const size_t shm = sizeof(double) * (size_t)a.ncp;
     hipLaunchKernelGGL(k_eval_fmm_f64<TILE>, dim3(grid), dim3(TILE), shm, c.stream, a);
@@ -863,7 +1007,7 @@ int fmm_tile(const Ctx &c) {
 void launch_eval_fmm(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const int32_t *tile_start,
                      const int32_t *n_dev, int64_t n_max, const int32_t *sorted_leaf, const int32_t *sorted_idx,
                      const double *tx, const double *ty, const double *tz, const int32_t *out_idx, double *phi,
-                     double *grad) {
+                     double *grad, double *hess) {
     const Tree &t = c.tree;
     FmmEvalArgs a;
     a.ntiles_dev = ntiles_dev;
@@ -904,6 +1048,17 @@ void launch_eval_fmm(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const
     a.K = t.K;
     int64_t g = max_tiles < 16384 ? max_tiles : 16384;
     unsigned grid = (unsigned)(g > 0 ? g : 1);
+    if (hess) {                             // Phi, grad Phi and the Hessian (FP64)
+        switch (fmm_tile(c)) {
+            case 64: launch_hess_tile<64>(c, grid, a, hess); break;
+            case 128: launch_hess_tile<128>(c, grid, a, hess); break;
+            default: launch_hess_tile<256>(c, grid, a, hess); break;
+        }
+        const int64_t go = ceil_div(n_max > 0 ? n_max : 1, 256);
+        hipLaunchKernelGGL(k_hess_outside, dim3((unsigned)(go < 1024 ? go : 1024)), dim3(256), 0, c.stream, a, hess);
+        LSS_CHECK_LAUNCH("k_hess_outside");
+        return;
+    }
     if (c.opt.precision == LSS_MIXED) {
         hipLaunchKernelGGL(k_eval_fmm_mixed, dim3(grid), dim3(64), sizeof(double) * (size_t)a.ncp, c.stream, a);
         LSS_CHECK_LAUNCH("k_eval_fmm_mixed");

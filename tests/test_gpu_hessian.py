@@ -44,8 +44,8 @@ def test_hessian_vs_oracle(star):
     v, t, sig = star
     x = np.concatenate([surface_offset_targets(v, t, sig, 2500, tmax=3.0, seed=7),
                         box_targets(300, -2.0, 2.0, seed=8)])
-    say("case: Hessian, star surface %d tri, %d targets" % (len(t), len(x)))
-    c = ctx(v, t, sig)
+    say("case: Hessian by the direct sum, star surface %d tri, %d targets" % (len(t), len(x)))
+    c = ctx(v, t, sig, far=lss.FAR_DIRECT)
     phi, g, hs = c.eval_hessian(x)
     ho = oracle.hessian(v, t, sig, dunavant6(), x)
     po, go = oracle.evaluate(v, t, sig, dunavant6(), x)
@@ -120,3 +120,45 @@ def test_chart_curvature_sphere_and_device_tensors():
     p, g, hs = c.eval_hessian(x[:500])
     torch.cuda.synchronize()
     assert np.array_equal(hsd.cpu().numpy(), hs) and np.array_equal(pd.cpu().numpy(), p)
+
+
+@pytest.mark.parametrize("prec", [lss.FP64, lss.MIXED])
+def test_hessian_fmm_vs_oracle_and_direct(star, prec):
+    """The Hessian through the octree: near lists with the full kernel, M2P
+    lists and local expansions with their second derivatives.  Bars: Phi and
+    grad as for lss_eval; the Hessian 1e-10 (FP64 settings: the kernel at the
+    8 sigma cut differs from the Laplace double layer by 2e-11 in its third
+    radial function) and 1e-5 (mixed settings: cut sqrt(40) sigma, p = 20)."""
+    v, t, sig = star
+    x = np.concatenate([surface_offset_targets(v, t, sig, 4000, tmax=3.0, seed=17),
+                        box_targets(400, -2.0, 2.0, seed=18),
+                        np.array([[6.0, 0.5, -0.3], [0.2, -7.0, 1.0]])])      # outside the root cube
+    say("case: Hessian through the FMM, star surface %d tri, %d targets, precision %d" % (len(t), len(x), prec))
+    c = ctx(v, t, sig, far=lss.FAR_FMM)
+    c.set_options(precision=prec, far_field=lss.FAR_FMM)
+    phi, g, hs = c.eval_hessian(x)
+    st = c.stats()
+    assert st["n_m2l"] > 0
+    cd = ctx(v, t, sig, far=lss.FAR_DIRECT)
+    pd, gd, hd = cd.eval_hessian(x)
+    ho = oracle.hessian(v, t, sig, dunavant6(), x[::7])
+    bar_f = 1e-12 if prec == lss.FP64 else 1e-6
+    bar_h = 1e-10 if prec == lss.FP64 else 1e-5
+    e = rel(hs, hd), rel(phi, pd), rel(g, gd), rel(hs[::7], ho)
+    say("  vs direct: e_hess %.2e e_phi %.2e e_grad %.2e; vs oracle: e_hess %.2e" % e)
+    assert e[0] <= bar_h and e[3] <= bar_h and e[1] <= bar_f and e[2] <= bar_f
+
+
+def test_chart_curvature_through_the_fmm(star):
+    v, t, sig = star
+    uv = chart_nodes(4)
+    say("case: chart curvature through the FMM, star surface %d tri" % len(t))
+    c = ctx(v, t, sig, far=lss.FAR_FMM)
+    h, x, st, it = c.project(uv)
+    assert np.all(st == 0)
+    out = c.chart_curvature(uv, h)
+    cd = ctx(v, t, sig, far=lss.FAR_DIRECT)
+    ref = cd.chart_curvature(uv, h)
+    errs = [rel(a, b) for a, b in zip(out, ref)]
+    say("  vs direct: e_xuu %.2e e_xuv %.2e e_xvv %.2e e_gauss %.2e e_mean %.2e" % tuple(errs))
+    assert max(errs) <= 1e-9
