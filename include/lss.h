@@ -247,11 +247,16 @@ int lss_chart_geometry(lss_ctx *ctx, const double *chart_uv, int32_t np, const d
  * eq. uu_vector_aux1/aux2), with Phi and grad Phi from the same pass, at n
  * targets x (n,3); x_mesh as for lss_eval.  hess (n,6) receives the
  * symmetric matrix as xx, xy, xz, yy, yz, zz; phi (n) and grad (n,3) may be
- * NULL.  Every (target, node) pair of the target's mesh is summed with the
- * full kernel and its third radial function G = F'(rho)/rho, in FP64,
- * whatever the precision and far-field options: the cost is n times the
- * mesh's node count, meant for the chart nodes of moderate meshes.  Host or
- * device arrays per flags; returns when the outputs are written. */
+ * NULL.  Pairs are summed in FP64 with the full kernel and its third radial
+ * function G = F'(rho)/rho.  LSS_FAR_DIRECT: every (target, node) pair of the
+ * target's mesh (cost n times the mesh's node count).  LSS_FAR_FMM: the
+ * context's octree: the near lists with the full kernel, the M2P lists and
+ * the leaf's local expansion with their second derivatives (targets outside
+ * the root cube: every node of their mesh).  The accuracy follows the
+ * context's cut and order: about 1e-13 relative with the FP64 settings,
+ * 1e-7 with the mixed ones (whose cut and order are smaller); the
+ * precision option does not change the pair arithmetic.  Host or device
+ * arrays per flags; returns when the outputs are written. */
 int lss_eval_hessian(lss_ctx *ctx, const double *x, const int32_t *x_mesh, int64_t n, double *phi, double *grad,
                      double *hess, unsigned flags);
 
@@ -287,7 +292,7 @@ int lss_eval_multiscale(lss_ctx *ctx, double lambda, double sigma0, const double
  *   (first and second fundamental forms with the outward normal -g/|g|, so
  *   a sphere of radius R has mean curvature 1/R).
  * N = ntris * np.  Any output may be NULL.  The cost is that of
- * lss_eval_hessian at the N chart points.  Host or device arrays as for
+ * lss_eval_hessian (with the context's far-field option) at the N chart points.  Host or device arrays as for
  * lss_project; returns when the outputs are written. */
 int lss_chart_curvature(lss_ctx *ctx, const double *chart_uv, int32_t np, const double *h, double *xuu,
                         double *xuv, double *xvv, double *gauss, double *mean, unsigned flags);
