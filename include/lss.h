@@ -270,9 +270,15 @@ int lss_eval_hessian(lss_ctx *ctx, const double *x, const int32_t *x_mesh, int64
  * paper's suggestion, with lambda about 2.5).  Phi sums every node of the
  * mesh with width sigma(x); grad Phi is the exact x-derivative, including
  * (dPhi/dsigma) grad sigma.  x (n,3), x_mesh as for lss_eval; phi (n); grad
- * (n,3) and sigma_x (n, receives sigma(x)) may be NULL.  FP64 direct sum over
- * the centroids and the nodes of the target's mesh, whatever the precision
- * and far-field options; needs sources, not sigma (LSS_ESTATE otherwise).
+ * (n,3) and sigma_x (n, receives sigma(x)) may be NULL.  sigma(x) is a direct
+ * FP64 sum over the centroids of the target's mesh.  LSS_FAR_DIRECT: Phi is
+ * a direct FP64 sum over the mesh's nodes.  LSS_FAR_FMM: an octree is built
+ * with cut widths equal to each mesh's largest sigma_j (an upper bound of
+ * sigma(x)), the near lists are summed at the target's width and the far
+ * field comes from the expansions (accuracy as for lss_eval with the same
+ * options); the context's own sigma is left as it was, and its built state
+ * is rebuilt on the next call that needs it.  Needs sources, not sigma
+ * (LSS_ESTATE otherwise).
  * lambda <= 0, sigma0 < 0 or non-finite give LSS_EINVAL.  Host or device
  * arrays per flags; returns when the outputs are written. */
 int lss_eval_multiscale(lss_ctx *ctx, double lambda, double sigma0, const double *x, const int32_t *x_mesh,

@@ -127,7 +127,7 @@ void ensure_targets(Ctx &c, int64_t n) {
 // the device if given): leaf of each target, targets sorted by leaf, tiles,
 // near field + L2P.  Outputs at the target's index in tx/ty/tz.
 void eval_fmm_targets(Ctx &c, int64_t n, const int32_t *n_dev, double *phi, double *grad, bool reset_pairs = true,
-                      double *hess = nullptr) {
+                      double *hess = nullptr, const MsArgs *ms = nullptr) {
     launch_locate_targets(c, n, n_dev, c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(),
                           c.tmesh.as<int32_t>(), c.tkey.as<uint64_t>(), c.tperm.as<int32_t>());
     sort_pairs(c, c.tkey.as<uint64_t>(), c.tkey2.as<uint64_t>(), c.tperm.as<int32_t>(), c.tperm2.as<int32_t>(), n, 64);
@@ -142,7 +142,7 @@ void eval_fmm_targets(Ctx &c, int64_t n, const int32_t *n_dev, double *phi, doub
     c.ev_begin();
     launch_eval_fmm(c, n, c.ntiles.as<int32_t>(), c.tstart.as<int32_t>(), n_dev, n, c.tleaf.as<int32_t>(),
                     c.tperm2.as<int32_t>(), c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(), nullptr, phi, grad,
-                    hess);
+                    hess, ms);
     c.ev_end();
 }
 
@@ -467,8 +467,6 @@ void eval_multiscale(Ctx &c, double lambda, double sigma0, const double *x, cons
             fail(LSS_EINVAL, "lss_eval_multiscale: a mesh has only zero-size triangles");
     }
     upload(c, s0, hs0.data(), sizeof(double) * c.nmesh, 0);
-    raw.ensure(sizeof(RawNode) * c.ntris * c.nq);
-    launch_prep_raw(c, raw.as<RawNode>());
     DBuf hx, hxm, hphi, hgrad, hsig;
     const double *dx = x;
     const int32_t *dxm = c.nmesh > 1 ? xm : nullptr;
@@ -496,7 +494,63 @@ void eval_multiscale(Ctx &c, double lambda, double sigma0, const double *x, cons
         LSS_HIP(hipStreamSynchronize(c.stream));
         if (nb) fail(LSS_EINVAL, "lss_eval_multiscale: x_mesh values outside [0, nmesh)");
     }
-    launch_eval_multiscale(c, n, dx, dxm, cen.as<Cen>(), raw.as<RawNode>(), s0.as<double>(), dphi, dgrad, dsig);
+    if (c.opt.far_field == LSS_FAR_FMM) {
+        // sigma(x) and grad sigma, then the tree of the cut widths sigma_cut =
+        // the mesh's largest sigma_j (>= sigma(x) everywhere: a convex
+        // combination), built in place of the caller's sigma, which is put
+        // back afterwards (the built state is then stale and rebuilt on use)
+        DBuf tsig, tgs, dscut, saved;
+        tsig.ensure(sizeof(double) * n);
+        tgs.ensure(sizeof(double) * 3 * n);
+        launch_sigma_field(c, n, dx, dxm, cen.as<Cen>(), s0.as<double>(), tsig.as<double>(), tgs.as<double>());
+        std::vector<double> smax(c.nmesh, 0.0), scut(c.ntris);
+        for (int32_t m = 0; m < c.nmesh; ++m)
+            for (int64_t j = c.h_tri_off[m]; j < c.h_tri_off[m + 1]; ++j) smax[m] = std::max(smax[m], hD[j] / lambda);
+        for (int32_t m = 0; m < c.nmesh; ++m)
+            for (int64_t j = c.h_tri_off[m]; j < c.h_tri_off[m + 1]; ++j) scut[j] = smax[m];
+        struct Restore {
+            Ctx &c;
+            DBuf &saved;
+            bool had;
+            double lo, hi;
+            ~Restore() {
+                if (had) (void)hipMemcpyAsync(c.sigma.p, saved.p, sizeof(double) * c.ntris, hipMemcpyDeviceToDevice,
+                                              c.stream);
+                (void)hipStreamSynchronize(c.stream);
+                c.have_sigma = had;
+                c.sigma_min = lo;
+                c.sigma_max = hi;
+                c.built = false;
+            }
+        } restore{c, saved, c.have_sigma, c.sigma_min, c.sigma_max};
+        if (c.have_sigma) {
+            saved.ensure(sizeof(double) * c.ntris);
+            LSS_HIP(hipMemcpyAsync(saved.p, c.sigma.p, sizeof(double) * c.ntris, hipMemcpyDeviceToDevice, c.stream));
+        }
+        upload(c, c.sigma, scut.data(), sizeof(double) * c.ntris, 0);
+        double mn = INFINITY, mx = 0.0;
+        for (int32_t m = 0; m < c.nmesh; ++m)
+            if (c.h_tri_off[m + 1] > c.h_tri_off[m]) { mn = std::min(mn, smax[m]); mx = std::max(mx, smax[m]); }
+        c.have_sigma = true;
+        c.sigma_min = mn;
+        c.sigma_max = mx;
+        c.built = false;
+        build(c);
+        upload(c, dscut, smax.data(), sizeof(double) * c.nmesh, 0);
+        ensure_targets(c, n);
+        c.ev_reset();
+        launch_soa(c, dx, n, c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>());
+        if (dxm) LSS_HIP(hipMemcpyAsync(c.tmesh.p, dxm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c.stream));
+        const MsArgs ms{tsig.as<double>(), tgs.as<double>(), dscut.as<double>()};
+        eval_fmm_targets(c, n, nullptr, dphi, dgrad, true, nullptr, &ms);
+        if (dsig) LSS_HIP(hipMemcpyAsync(dsig, tsig.p, sizeof(double) * n, hipMemcpyDeviceToDevice, c.stream));
+        LSS_HIP(hipStreamSynchronize(c.stream));
+    } else {
+        raw.ensure(sizeof(RawNode) * c.ntris * c.nq);
+        launch_prep_raw(c, raw.as<RawNode>());
+        launch_eval_multiscale(c, n, dx, dxm, cen.as<Cen>(), raw.as<RawNode>(), s0.as<double>(), dphi, dgrad,
+                               dsig);
+    }
     if (!dev) {
         LSS_HIP(hipMemcpyAsync(phi, dphi, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
         if (grad) LSS_HIP(hipMemcpyAsync(grad, dgrad, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, c.stream));

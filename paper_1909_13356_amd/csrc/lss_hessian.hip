@@ -79,53 +79,23 @@ __global__ void __launch_bounds__(256) k_hessian_direct(int64_t n, const double 
     o[5] = A.hzz;
 }
 
-// Target-attached width (section 2, eq. basemodelk, convkernel, sigma2).
-// Phase 1: sigma(x) = sum_j sigma_j w_j / sum_j w_j over the centroids of the
-// target's mesh, w_j = exp(-|x - c_j|^2 / (2 sigma0^2)), accumulated relative
-// to the nearest centroid seen so far (the sums are rescaled when it
-// changes), and grad sigma = -(V1 - sigma V0) / (sigma0^2 S0) with
-// S0 = sum w_j, V0 = sum w_j (x - c_j), V1 = sum sigma_j w_j (x - c_j).
-// Phase 2: every node of the mesh with the raw normal a = w J and the
-// target's width, c = 1/(4 sqrt2 pi^1.5 sigma^3), s2 = 1/(2 sigma^2):
-//   Phi = -c sum (a.d) k1,  grad Phi = -c sum (a k1 + (a.d) k2 d)
-//         + (dPhi/dsigma) grad sigma,  dPhi/dsigma = (2c/sigma) sum (a.d) exp(-t),
-// k1, k2 as in radial3 (K = c k1, F = c k2).  A target whose mesh has no
-// triangles gets sigma = NaN and Phi = grad Phi = 0.
-__global__ void __launch_bounds__(256) k_eval_multiscale(int64_t n, const double *__restrict__ x,
-                                                         const int32_t *__restrict__ xm,
-                                                         const int64_t *__restrict__ tri_off,
-                                                         const int64_t *__restrict__ node_off,
-                                                         const Cen *__restrict__ cen,
-                                                         const RawNode *__restrict__ nodes,
-                                                         const double *__restrict__ sigma0, double *phi,
-                                                         double *grad, double *sig_out) {
-    __shared__ RawNode tile[256];
-    __shared__ long long blo, bhi;
-    Cen *ctile = reinterpret_cast<Cen *>(tile);
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool act = i < n;
-    int32_t m = 0;
-    double px = 0.0, py = 0.0, pz = 0.0;
-    if (act) {
-        m = xm ? xm[i] : 0;
-        px = x[3 * i];
-        py = x[3 * i + 1];
-        pz = x[3 * i + 2];
-    }
-    // ---- phase 1: sigma(x) and its gradient
-    int64_t j0 = act ? tri_off[m] : 0, j1 = act ? tri_off[m + 1] : 0;
+// sigma(x) and grad sigma of one target (phase 1 of the multiscale sums):
+// the workgroup walks the union of its targets' centroid ranges [j0, j1) in
+// LDS tiles; returns false (and sigma = 0.5, grad = 0) for an empty range.
+// Every thread of the workgroup must call it.
+__device__ bool sigma_phase(const Cen *__restrict__ cen, Cen *ctile, long long *blo, long long *bhi, int64_t j0,
+                            int64_t j1, double px, double py, double pz, double s0, double &sg, double gs[3]) {
     if (threadIdx.x == 0) {
-        blo = LLONG_MAX;
-        bhi = 0;
+        *blo = LLONG_MAX;
+        *bhi = 0;
     }
     __syncthreads();
     if (j1 > j0) {
-        atomicMin(&blo, (long long)j0);
-        atomicMax(&bhi, (long long)j1);
+        atomicMin(blo, (long long)j0);
+        atomicMax(bhi, (long long)j1);
     }
     __syncthreads();
-    int64_t lo = blo, hi = bhi;
-    const double s0 = act ? sigma0[m] : 1.0;
+    const int64_t lo = *blo, hi = *bhi;
     const double inv2s0 = 0.5 / (s0 * s0);
     double dmin = INFINITY, S0 = 0.0, S1 = 0.0, V0x = 0.0, V0y = 0.0, V0z = 0.0, V1x = 0.0, V1y = 0.0, V1z = 0.0;
     for (int64_t base = lo; base < hi; base += 256) {
@@ -162,10 +132,84 @@ __global__ void __launch_bounds__(256) k_eval_multiscale(int64_t n, const double
             V1z += sw * dz;
         }
     }
+    __syncthreads();                  // the caller may reuse the tile
     const bool have = S0 > 0.0;
-    const double sg = have ? S1 / S0 : 0.5;
+    sg = have ? S1 / S0 : 0.5;
     const double gsc = have ? -1.0 / (s0 * s0 * S0) : 0.0;
-    const double gsx = gsc * (V1x - sg * V0x), gsy = gsc * (V1y - sg * V0y), gsz = gsc * (V1z - sg * V0z);
+    gs[0] = gsc * (V1x - sg * V0x);
+    gs[1] = gsc * (V1y - sg * V0y);
+    gs[2] = gsc * (V1z - sg * V0z);
+    return have;
+}
+
+// sigma(x) and grad sigma alone (the octree path of the multiscale sums)
+__global__ void __launch_bounds__(256) k_sigma_field(int64_t n, const double *__restrict__ x,
+                                                     const int32_t *__restrict__ xm,
+                                                     const int64_t *__restrict__ tri_off,
+                                                     const Cen *__restrict__ cen,
+                                                     const double *__restrict__ sigma0, double *sig,
+                                                     double *gsig) {
+    __shared__ Cen ctile[256];
+    __shared__ long long blo, bhi;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool act = i < n;
+    int32_t m = 0;
+    double px = 0.0, py = 0.0, pz = 0.0;
+    if (act) {
+        m = xm ? xm[i] : 0;
+        px = x[3 * i];
+        py = x[3 * i + 1];
+        pz = x[3 * i + 2];
+    }
+    const int64_t j0 = act ? tri_off[m] : 0, j1 = act ? tri_off[m + 1] : 0;
+    double sg, gs[3];
+    const bool have = sigma_phase(cen, ctile, &blo, &bhi, j0, j1, px, py, pz, act ? sigma0[m] : 1.0, sg, gs);
+    if (!act) return;
+    sig[i] = have ? sg : NAN;
+    gsig[3 * i] = gs[0];
+    gsig[3 * i + 1] = gs[1];
+    gsig[3 * i + 2] = gs[2];
+}
+
+// Target-attached width (section 2, eq. basemodelk, convkernel, sigma2).
+// Phase 1: sigma(x) = sum_j sigma_j w_j / sum_j w_j over the centroids of the
+// target's mesh, w_j = exp(-|x - c_j|^2 / (2 sigma0^2)), accumulated relative
+// to the nearest centroid seen so far (the sums are rescaled when it
+// changes), and grad sigma = -(V1 - sigma V0) / (sigma0^2 S0) with
+// S0 = sum w_j, V0 = sum w_j (x - c_j), V1 = sum sigma_j w_j (x - c_j).
+// Phase 2: every node of the mesh with the raw normal a = w J and the
+// target's width, c = 1/(4 sqrt2 pi^1.5 sigma^3), s2 = 1/(2 sigma^2):
+//   Phi = -c sum (a.d) k1,  grad Phi = -c sum (a k1 + (a.d) k2 d)
+//         + (dPhi/dsigma) grad sigma,  dPhi/dsigma = (2c/sigma) sum (a.d) exp(-t),
+// k1, k2 as in radial3 (K = c k1, F = c k2).  A target whose mesh has no
+// triangles gets sigma = NaN and Phi = grad Phi = 0.
+__global__ void __launch_bounds__(256) k_eval_multiscale(int64_t n, const double *__restrict__ x,
+                                                         const int32_t *__restrict__ xm,
+                                                         const int64_t *__restrict__ tri_off,
+                                                         const int64_t *__restrict__ node_off,
+                                                         const Cen *__restrict__ cen,
+                                                         const RawNode *__restrict__ nodes,
+                                                         const double *__restrict__ sigma0, double *phi,
+                                                         double *grad, double *sig_out) {
+    __shared__ RawNode tile[256];
+    __shared__ long long blo, bhi;
+    Cen *ctile = reinterpret_cast<Cen *>(tile);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool act = i < n;
+    int32_t m = 0;
+    double px = 0.0, py = 0.0, pz = 0.0;
+    if (act) {
+        m = xm ? xm[i] : 0;
+        px = x[3 * i];
+        py = x[3 * i + 1];
+        pz = x[3 * i + 2];
+    }
+    // ---- phase 1: sigma(x) and its gradient
+    int64_t j0 = act ? tri_off[m] : 0, j1 = act ? tri_off[m + 1] : 0;
+    double sg, gs[3];
+    const bool have = sigma_phase(cen, ctile, &blo, &bhi, j0, j1, px, py, pz, act ? sigma0[m] : 1.0, sg, gs);
+    const double gsx = gs[0], gsy = gs[1], gsz = gs[2];
+    int64_t lo, hi;
     // ---- phase 2: Phi, grad Phi with width sigma(x)
     j0 = act ? node_off[m] : 0;
     j1 = act ? node_off[m + 1] : 0;
@@ -316,6 +360,13 @@ void launch_hessian_direct(Ctx &c, int64_t n, const double *x, const int32_t *xm
     hipLaunchKernelGGL(k_hessian_direct, dim3(blocks256(n)), dim3(256), 0, c.stream, n, x, xm,
                        c.node_off.as<int64_t>(), c.src.as<Src>(), phi, grad, hess);
     LSS_CHECK_LAUNCH("k_hessian_direct");
+}
+
+void launch_sigma_field(Ctx &c, int64_t n, const double *x, const int32_t *xm, const Cen *cen, const double *sigma0,
+                        double *sig, double *gsig) {
+    hipLaunchKernelGGL(k_sigma_field, dim3(blocks256(n)), dim3(256), 0, c.stream, n, x, xm, c.tri_off.as<int64_t>(),
+                       cen, sigma0, sig, gsig);
+    LSS_CHECK_LAUNCH("k_sigma_field");
 }
 
 void launch_eval_multiscale(Ctx &c, int64_t n, const double *x, const int32_t *xm, const Cen *cen,

@@ -91,6 +91,13 @@ struct Cen {
     double cx, cy, cz, sj;
 };
 
+// Target-attached width through the tree: sigma(x) and grad sigma per target
+// (original order) and the cut width of each mesh's tree.
+struct MsArgs {
+    const double *sig, *gsig;
+    const double *scut;
+};
+
 // FP32 staging record of the mixed path: position relative to a tile origin
 // as an unevaluated float-float sum hi + lo (lo = the FP64 remainder).  The
 // far-form constants are folded in: ax, ay, az hold sqrt(pi)/2 a' and s2x2
@@ -259,6 +266,8 @@ struct Ctx {
 void launch_prep_sources(Ctx &c);
 void launch_prep_raw(Ctx &c, RawNode *out);
 void launch_centroids(Ctx &c, double lambda, Cen *out, double *D);
+void launch_sigma_field(Ctx &c, int64_t n, const double *x, const int32_t *xm, const Cen *cen, const double *sigma0,
+                        double *sig, double *gsig);
 void launch_eval_multiscale(Ctx &c, int64_t n, const double *x, const int32_t *xm, const Cen *cen,
                             const RawNode *nodes, const double *sigma0, double *phi, double *grad, double *sig);
 void launch_pseudonormals(Ctx &c);
@@ -310,7 +319,7 @@ int fmm_tile(const Ctx &c);
 void launch_eval_fmm(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const int32_t *tile_start,
                      const int32_t *n_dev, int64_t n_max, const int32_t *sorted_leaf, const int32_t *sorted_idx,
                      const double *tx, const double *ty, const double *tz, const int32_t *out_idx, double *phi,
-                     double *grad, double *hess = nullptr);
+                     double *grad, double *hess = nullptr, const MsArgs *ms = nullptr);
 void launch_soa(Ctx &c, const double *x, int64_t n, double *tx, double *ty, double *tz);
 // Newton targets in FMM mode: leaf of each target in its current order and
 // tile heads at leaf changes and every TILE-th position (no sort; capturable)

@@ -784,6 +784,109 @@ __global__ __launch_bounds__(256) void k_hess_outside(FmmEvalArgs a, double *hes
     }
 }
 
+// ------------------------------------------------ target-attached width
+// Phi and grad Phi with sigma(x) (section 2, eq. basemodelk, sigma2) through
+// a tree whose cut radii come from the mesh's largest sigma_j, which bounds
+// sigma(x) everywhere (a convex combination of the sigma_j): every pair within
+// the cut of sigma(x) is in a near list.  Near pairs use the target's width
+// (pair_ms) and are scaled by c(sigma(x)) / c(sigma_cut) = (sigma_cut /
+// sigma(x))^3; the far field (Laplace double layer) does not depend on the
+// width.  grad Phi gains (dPhi/dsigma) grad sigma, dPhi/dsigma = (2 c(x) /
+// sigma(x)) sum (a.d) exp(-t) over the near pairs (beyond the cut exp(-t) is
+// below the cut's truncation).  FP64.
+__device__ __forceinline__ void ms_finish(double sx, double sc, const MsAcc &A, const double *gs, double &ph,
+                                          double g[3]) {
+    // with a = a'/c(cut) and f = c(x)/c(cut) = (sigma_cut/sigma(x))^3:
+    // Phi = -f sum (a'.d) k1, grad = -f sum (a' k1 + (a'.d) k2 d),
+    // dPhi/dsigma = (2 c(x)/sigma(x)) sum (a.d) e^-t = (2 f/sigma(x)) sum (a'.d) e^-t
+    const double r = sc / sx, f = r * r * r;
+    const double dps = 2.0 * f * A.e / sx;
+    ph -= f * A.f;
+    g[0] += -f * A.gx + dps * gs[0];
+    g[1] += -f * A.gy + dps * gs[1];
+    g[2] += -f * A.gz + dps * gs[2];
+}
+
+template <int TILE>
+__global__ __launch_bounds__(TILE) void k_multiscale_fmm(FmmEvalArgs a, MsArgs ms) {
+    __shared__ Src sh[TILE];
+    __shared__ RangeBatch<TILE> rb;
+    extern __shared__ double Ls[];
+    const int ntiles = *a.ntiles_dev;
+    const int64_t n = a.n_dev ? (int64_t)*a.n_dev : a.n_max;
+    const int lane = threadIdx.x;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t s0 = a.tile_start[tile];
+        const int32_t B = a.sleaf[s0];
+        const int64_t s1 = tile + 1 < ntiles ? (int64_t)a.tile_start[tile + 1] : n;
+        if (B >= a.nboxes) continue;        // outside the root cube: k_multiscale_outside
+        const int64_t sp_ = s0 + lane;
+        const bool valid = sp_ < s1;
+        const int64_t ti = a.sidx ? (int64_t)a.sidx[valid ? sp_ : s0] : (valid ? sp_ : s0);
+        const double x = a.tx[ti], y = a.ty[ti], z = a.tz[ti];
+        const double sx = ms.sig[ti], s2x = 0.5 / (sx * sx);
+        const int e0 = a.p2p_beg[B], e1 = a.p2p_end[B];
+        MsAcc A;
+        for (int eb = e0; eb < e1; eb += TILE) {
+            const int nr = e1 - eb < TILE ? e1 - eb : TILE;
+            __syncthreads();
+            const int64_t total = load_ranges<TILE>(a, rb, eb, nr);
+            for (int64_t c0 = 0; c0 < total; c0 += TILE) {
+                const int cnt = (int)(total - c0 < TILE ? total - c0 : TILE);
+                __syncthreads();
+                if (lane < cnt) sh[lane] = a.src[packed_node<TILE>(rb, nr, c0 + lane)];
+                __syncthreads();
+                for (int j = 0; j < cnt; ++j) pair_ms(sh[j], x, y, z, s2x, A);
+            }
+        }
+        double ph = 0.0, g[3] = {0.0, 0.0, 0.0};
+        if (a.m2p_end[B] > a.m2p_beg[B]) fmm_m2p_list(a, B, Ls, x, y, z, ph, g);
+        stage_local(a, B, Ls);
+        __syncthreads();
+        {
+            double lp, lg[3];
+            fmm_l2p(a, B, Ls, x, y, z, lp, lg);
+            ph += lp;
+            for (int d = 0; d < 3; ++d) g[d] += lg[d];
+        }
+        __syncthreads();
+        if (valid) {
+            ms_finish(sx, ms.scut[a.bmesh[B]], A, ms.gsig + 3 * ti, ph, g);
+            const int64_t o = a.out_idx ? (int64_t)a.out_idx[ti] : ti;
+            a.phi[o] = ph;
+            if (a.grad) {
+                a.grad[3 * o] = g[0];
+                a.grad[3 * o + 1] = g[1];
+                a.grad[3 * o + 2] = g[2];
+            }
+        }
+    }
+}
+
+// targets outside their mesh's root cube: every node of the mesh
+__global__ __launch_bounds__(256) void k_multiscale_outside(FmmEvalArgs a, MsArgs ms) {
+    const int64_t n = a.n_dev ? (int64_t)*a.n_dev : a.n_max;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t B = a.sleaf[i];
+        if (B < a.nboxes) continue;
+        const int32_t m = B - a.nboxes;
+        const int64_t ti = a.sidx ? (int64_t)a.sidx[i] : i;
+        const double x = a.tx[ti], y = a.ty[ti], z = a.tz[ti];
+        const double sx = ms.sig[ti], s2x = 0.5 / (sx * sx);
+        MsAcc A;
+        for (int64_t k = a.nb[m]; k < a.ne[m]; ++k) pair_ms(a.src[k], x, y, z, s2x, A);
+        double ph = 0.0, g[3] = {0.0, 0.0, 0.0};
+        ms_finish(sx, ms.scut[m], A, ms.gsig + 3 * ti, ph, g);
+        const int64_t o = a.out_idx ? (int64_t)a.out_idx[ti] : ti;
+        a.phi[o] = ph;
+        if (a.grad) {
+            a.grad[3 * o] = g[0];
+            a.grad[3 * o + 1] = g[1];
+            a.grad[3 * o + 2] = g[2];
+        }
+    }
+}
+
 // Four waves per SIMD: the compiler fits the kernel in 128 VGPRs with a few
 // spills outside the chunk loop (1% faster on C5 than three waves at 139).
 template <int TILE>
@@ -1007,7 +1110,7 @@ int fmm_tile(const Ctx &c) {
 void launch_eval_fmm(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const int32_t *tile_start,
                      const int32_t *n_dev, int64_t n_max, const int32_t *sorted_leaf, const int32_t *sorted_idx,
                      const double *tx, const double *ty, const double *tz, const int32_t *out_idx, double *phi,
-                     double *grad, double *hess) {
+                     double *grad, double *hess, const MsArgs *ms) {
     const Tree &t = c.tree;
     FmmEvalArgs a;
     a.ntiles_dev = ntiles_dev;
@@ -1048,6 +1151,20 @@ void launch_eval_fmm(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const
     a.K = t.K;
     int64_t g = max_tiles < 16384 ? max_tiles : 16384;
     unsigned grid = (unsigned)(g > 0 ? g : 1);
+    if (ms) {                               // target-attached width (FP64)
+        const size_t shm = sizeof(double) * (size_t)a.ncp;
+        switch (fmm_tile(c)) {
+            case 64: hipLaunchKernelGGL(k_multiscale_fmm<64>, dim3(grid), dim3(64), shm, c.stream, a, *ms); break;
+            case 128: hipLaunchKernelGGL(k_multiscale_fmm<128>, dim3(grid), dim3(128), shm, c.stream, a, *ms); break;
+            default: hipLaunchKernelGGL(k_multiscale_fmm<256>, dim3(grid), dim3(256), shm, c.stream, a, *ms); break;
+        }
+        LSS_CHECK_LAUNCH("k_multiscale_fmm");
+        const int64_t go = ceil_div(n_max > 0 ? n_max : 1, 256);
+        hipLaunchKernelGGL(k_multiscale_outside, dim3((unsigned)(go < 1024 ? go : 1024)), dim3(256), 0, c.stream, a,
+                           *ms);
+        LSS_CHECK_LAUNCH("k_multiscale_outside");
+        return;
+    }
     if (hess) {                             // Phi, grad Phi and the Hessian (FP64)
         switch (fmm_tile(c)) {
             case 64: launch_hess_tile<64>(c, grid, a, hess); break;

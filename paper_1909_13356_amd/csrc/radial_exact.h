@@ -92,4 +92,25 @@ __device__ inline void pair_hess(const Src &s, double px, double py, double pz, 
     A.hyz -= k2 * (s.ay * dz + s.az * dy) + ey * dz;
 }
 
+// Phi, grad Phi and dPhi/dsigma-sum with a target-attached width: the node
+// record's a' carries the normalisation of its own (cut) width, the target's
+// s2x = 1/(2 sigma(x)^2) sets the kernel; the caller scales by c(x)/c(node).
+struct MsAcc {
+    double f = 0.0, gx = 0.0, gy = 0.0, gz = 0.0, e = 0.0;
+};
+
+__device__ inline void pair_ms(const Src &s, double px, double py, double pz, double s2x, MsAcc &A) {
+    const double dx = px - s.yx, dy = py - s.yy, dz = pz - s.yz;
+    const double t = (dx * dx + dy * dy + dz * dz) * s2x;
+    double k1, k2, k3, et;
+    radial3(t, s2x, k1, k2, k3, et);
+    const double ad = s.ax * dx + s.ay * dy + s.az * dz;
+    A.f += ad * k1;
+    const double adk2 = ad * k2;
+    A.gx += s.ax * k1 + adk2 * dx;
+    A.gy += s.ay * k1 + adk2 * dy;
+    A.gz += s.az * k1 + adk2 * dz;
+    A.e += ad * et;
+}
+
 }  // namespace lss

@@ -92,3 +92,35 @@ def test_multiscale_constant_diameter_is_the_constant_sigma_sum_and_device_tenso
     with pytest.raises(lss.LssError) as err:
         lss.Context().eval_multiscale(x, 2.5)
     assert err.value.code == 4
+
+
+@pytest.mark.parametrize("prec", [lss.FP64, lss.MIXED])
+def test_multiscale_through_the_octree(prec):
+    """sigma(x) through the tree: cut radii from the mesh's largest sigma_j,
+    near pairs at the target's width, far field from the expansions.  Bars
+    1e-12 (FP64 settings) and 1e-6 (mixed settings: cut sqrt(40) sigma_cut,
+    p = 20).  The context's own sigma and results are unchanged afterwards."""
+    v, t = star_surface(10, lmax=8, var0=0.1, seed=9)
+    sig = 0.5 * triangle_diameters(v, t)
+    x = np.concatenate([surface_offset_targets(v, t, sig, 6000, tmax=3.0, seed=10),
+                        box_targets(500, -2.0, 2.0, seed=11),
+                        np.array([[9.0, 0.1, 0.2], [-0.3, 8.0, -1.0]])])        # outside the root cube
+    say("case: multiscale sigma(x) through the octree, star surface %d tri, %d targets, precision %d"
+        % (len(t), len(x), prec))
+    c = ctx(v, t)
+    c.set_sigma(sig)
+    c.set_options(precision=prec, far_field=lss.FAR_FMM)
+    p0, g0 = c.eval(x)
+    p, g, s = c.eval_multiscale(x, 2.5, 0.0)
+    st = c.stats()
+    assert st["n_m2l"] > 0
+    po, go, so = oracle.evaluate_multiscale(v, t, dunavant6(), x[::5], 2.5, 0.0)
+    bar = 1e-12 if prec == lss.FP64 else 1e-6
+    e = rel(p[::5], po), rel(g[::5], go), rel(s[::5], so)
+    say("  vs oracle: e_phi %.2e e_grad %.2e e_sigma %.2e" % e)
+    assert max(e) <= bar
+    cd = ctx(v, t)
+    pd, gd, sd = cd.eval_multiscale(x, 2.5, 0.0)               # the direct path on every target
+    assert rel(p, pd) <= bar and rel(g, gd) <= bar
+    p1, g1 = c.eval(x)
+    assert np.array_equal(p1, p0) and np.array_equal(g1, g0)
