@@ -177,8 +177,17 @@ def time_newton(lss, torch, cfg, prec, steps, warmup):
         c.chart_curvature(uv, h)
     torch.cuda.synchronize()
     ek = time.perf_counter() - t0
+    # the paper's target-attached width sigma(x) (lambda 2.5, sigma0 = sqrt(5)
+    # max D) at the converged chart points, through the octree: one call
+    c.eval_multiscale(x, 2.5, 0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c.eval_multiscale(x, 2.5, 0.0)
+    torch.cuda.synchronize()
+    em = time.perf_counter() - t0
     c.close()
     return {"chart_nodes_per_s": n_nodes * steps / el, "target_evals_per_s": evals / el,
+            "multiscale_ms": 1e3 * em, "multiscale_points_per_s": n_nodes / em,
             "curvature_nodes_per_s": n_nodes * steps / ek, "curvature_ms": 1e3 * ek / steps,
             "ms_per_step": 1e3 * el / steps, "newton_graph_ms": gms / steps, "iterations": iters,
             "evals_per_node": evals / steps / n_nodes, "converged_frac": conv,
