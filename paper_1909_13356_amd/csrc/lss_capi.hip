@@ -439,7 +439,7 @@ void eval_hessian(Ctx &c, const double *x, const int32_t *xm, int64_t n, double 
     LSS_HIP(hipStreamSynchronize(c.stream));
 }
 
-// Phi, grad Phi with the target-attached width sigma(x), direct sum
+// Phi, grad Phi with the target-attached width sigma(x)
 void eval_multiscale(Ctx &c, double lambda, double sigma0, const double *x, const int32_t *xm, int64_t n, double *phi,
                      double *grad, double *sig, unsigned flags) {
     if (!c.have_sources) fail(LSS_ESTATE, "lss_eval_multiscale: no sources (call lss_set_sources)");
@@ -452,10 +452,12 @@ void eval_multiscale(Ctx &c, double lambda, double sigma0, const double *x, cons
     if (c.nmesh > 1 && !xm) fail(LSS_EINVAL, "lss_eval_multiscale: x_mesh is required for a batch of meshes");
     const bool dev = flags & LSS_PTR_DEVICE;
     // centroids, sigma_j and sigma0 per mesh (sqrt(5) max_j D_j when sigma0 == 0)
-    DBuf cen, D, s0, raw;
+    DBuf cen, D, s0, raw, cbox;
     cen.ensure(sizeof(Cen) * c.ntris);
     D.ensure(sizeof(double) * c.ntris);
     launch_centroids(c, lambda, cen.as<Cen>(), D.as<double>());
+    cbox.ensure(sizeof(double) * 6 * ((c.ntris + 255) / 256));
+    launch_cen_boxes(c, cen.as<Cen>(), cbox.as<double>());
     std::vector<double> hD(c.ntris), hs0(c.nmesh);
     LSS_HIP(hipMemcpyAsync(hD.data(), D.p, sizeof(double) * c.ntris, hipMemcpyDeviceToHost, c.stream));
     LSS_HIP(hipStreamSynchronize(c.stream));
@@ -502,7 +504,8 @@ void eval_multiscale(Ctx &c, double lambda, double sigma0, const double *x, cons
         DBuf tsig, tgs, dscut, saved;
         tsig.ensure(sizeof(double) * n);
         tgs.ensure(sizeof(double) * 3 * n);
-        launch_sigma_field(c, n, dx, dxm, cen.as<Cen>(), s0.as<double>(), tsig.as<double>(), tgs.as<double>());
+        launch_sigma_field(c, n, dx, dxm, cen.as<Cen>(), cbox.as<double>(), s0.as<double>(), tsig.as<double>(),
+                           tgs.as<double>());
         std::vector<double> smax(c.nmesh, 0.0), scut(c.ntris);
         for (int32_t m = 0; m < c.nmesh; ++m)
             for (int64_t j = c.h_tri_off[m]; j < c.h_tri_off[m + 1]; ++j) smax[m] = std::max(smax[m], hD[j] / lambda);
@@ -548,8 +551,8 @@ void eval_multiscale(Ctx &c, double lambda, double sigma0, const double *x, cons
     } else {
         raw.ensure(sizeof(RawNode) * c.ntris * c.nq);
         launch_prep_raw(c, raw.as<RawNode>());
-        launch_eval_multiscale(c, n, dx, dxm, cen.as<Cen>(), raw.as<RawNode>(), s0.as<double>(), dphi, dgrad,
-                               dsig);
+        launch_eval_multiscale(c, n, dx, dxm, cen.as<Cen>(), cbox.as<double>(), raw.as<RawNode>(), s0.as<double>(),
+                               dphi, dgrad, dsig);
     }
     if (!dev) {
         LSS_HIP(hipMemcpyAsync(phi, dphi, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));

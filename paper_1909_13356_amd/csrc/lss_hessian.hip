@@ -79,12 +79,38 @@ __global__ void __launch_bounds__(256) k_hessian_direct(int64_t n, const double 
     o[5] = A.hzz;
 }
 
-// sigma(x) and grad sigma of one target (phase 1 of the multiscale sums):
-// the workgroup walks the union of its targets' centroid ranges [j0, j1) in
-// LDS tiles; returns false (and sigma = 0.5, grad = 0) for an empty range.
-// Every thread of the workgroup must call it.
-__device__ bool sigma_phase(const Cen *__restrict__ cen, Cen *ctile, long long *blo, long long *bhi, int64_t j0,
-                            int64_t j1, double px, double py, double pz, double s0, double &sg, double gs[3]) {
+// Bounding box (lo xyz, hi xyz) of every run of 256 consecutive centroids.
+__global__ void k_cen_boxes(int64_t ntris, const Cen *__restrict__ cen, double *__restrict__ box) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t * 256 >= ntris) return;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    const int64_t e = (t + 1) * 256 < ntris ? (t + 1) * 256 : ntris;
+    for (int64_t j = t * 256; j < e; ++j) {
+        const double p[3] = {cen[j].cx, cen[j].cy, cen[j].cz};
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = fmin(lo[d], p[d]);
+            hi[d] = fmax(hi[d], p[d]);
+        }
+    }
+    for (int d = 0; d < 3; ++d) {
+        box[6 * t + d] = lo[d];
+        box[6 * t + 3 + d] = hi[d];
+    }
+}
+
+// sigma(x) and grad sigma of one target (phase 1 of the multiscale sums).
+// The centroids come in runs of 256 (run r = [256 r, 256 r + 256)) with
+// bounding boxes.  A first pass bounds the nearest centroid's squared
+// distance from above by the farthest corner distance of each run that
+// meets the target's range [j0, j1); a run whose nearest box distance exceeds
+// that bound by 100 sigma0^2 carries weights below e^-50 of the largest and
+// is skipped.  The workgroup stages a run in LDS when any of its targets
+// needs it; the sums are taken relative to the nearest centroid seen so far
+// (rescaled when it changes).  Returns false (sigma = 0.5, grad = 0) for an
+// empty range.  Every thread of the workgroup must call it.
+__device__ bool sigma_phase(const Cen *__restrict__ cen, const double *__restrict__ box, Cen *ctile, long long *blo,
+                            long long *bhi, int64_t j0, int64_t j1, double px, double py, double pz, double s0,
+                            double &sg, double gs[3]) {
     if (threadIdx.x == 0) {
         *blo = LLONG_MAX;
         *bhi = 0;
@@ -97,42 +123,67 @@ __device__ bool sigma_phase(const Cen *__restrict__ cen, Cen *ctile, long long *
     __syncthreads();
     const int64_t lo = *blo, hi = *bhi;
     const double inv2s0 = 0.5 / (s0 * s0);
-    double dmin = INFINITY, S0 = 0.0, S1 = 0.0, V0x = 0.0, V0y = 0.0, V0z = 0.0, V1x = 0.0, V1y = 0.0, V1z = 0.0;
-    for (int64_t base = lo; base < hi; base += 256) {
-        __syncthreads();
-        if (base + threadIdx.x < hi) ctile[threadIdx.x] = cen[base + threadIdx.x];
-        __syncthreads();
-        const int64_t k0 = j0 > base ? j0 - base : 0;
-        const int64_t k1 = (j1 - base < 256) ? j1 - base : 256;
-        for (int64_t k = k0; k < k1; ++k) {
-            const Cen c = ctile[k];
-            const double dx = px - c.cx, dy = py - c.cy, dz = pz - c.cz;
-            const double d2 = dx * dx + dy * dy + dz * dz;
-            if (d2 < dmin) {          // new nearest centroid: rescale the sums to it
-                const double f = exp((d2 - dmin) * inv2s0);
-                S0 *= f;
-                S1 *= f;
-                V0x *= f;
-                V0y *= f;
-                V0z *= f;
-                V1x *= f;
-                V1y *= f;
-                V1z *= f;
-                dmin = d2;
-            }
-            const double w = exp((dmin - d2) * inv2s0);
-            const double sw = c.sj * w;
-            S0 += w;
-            S1 += sw;
-            V0x += w * dx;
-            V0y += w * dy;
-            V0z += w * dz;
-            V1x += sw * dx;
-            V1y += sw * dy;
-            V1z += sw * dz;
+    const double p[3] = {px, py, pz};
+    const int64_t r0 = lo / 256, r1 = hi > lo ? (hi + 255) / 256 : r0;
+    double dref = INFINITY;                       // >= squared distance of the nearest centroid
+    for (int64_t r = r0; r < r1; ++r) {
+        if (!(j0 < (r + 1) * 256 && j1 > r * 256)) continue;
+        double far2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            const double a = fmax(fabs(p[d] - box[6 * r + d]), fabs(p[d] - box[6 * r + 3 + d]));
+            far2 += a * a;
         }
+        dref = fmin(dref, far2);
     }
-    __syncthreads();                  // the caller may reuse the tile
+    double dmin = INFINITY, S0 = 0.0, S1 = 0.0, V0x = 0.0, V0y = 0.0, V0z = 0.0, V1x = 0.0, V1y = 0.0, V1z = 0.0;
+    for (int64_t r = r0; r < r1; ++r) {
+        bool need = j0 < (r + 1) * 256 && j1 > r * 256;
+        if (need) {
+            double near2 = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                const double a = fmax(fmax(box[6 * r + d] - p[d], p[d] - box[6 * r + 3 + d]), 0.0);
+                near2 += a * a;
+            }
+            need = (near2 - dref) * inv2s0 <= 50.0;
+        }
+        if (!__syncthreads_or(need)) continue;      // uniform: no target of the workgroup needs the run
+        const int64_t b = r * 256;
+        const int64_t j = b + threadIdx.x;
+        if (j >= lo && j < hi) ctile[threadIdx.x] = cen[j];
+        __syncthreads();
+        if (need) {
+            const int64_t k0 = j0 > b ? j0 - b : 0;
+            const int64_t k1 = (j1 - b < 256) ? j1 - b : 256;
+            for (int64_t k = k0; k < k1; ++k) {
+                const Cen c = ctile[k];
+                const double dx = px - c.cx, dy = py - c.cy, dz = pz - c.cz;
+                const double d2 = dx * dx + dy * dy + dz * dz;
+                if (d2 < dmin) {          // new nearest centroid: rescale the sums to it
+                    const double f = exp((d2 - dmin) * inv2s0);
+                    S0 *= f;
+                    S1 *= f;
+                    V0x *= f;
+                    V0y *= f;
+                    V0z *= f;
+                    V1x *= f;
+                    V1y *= f;
+                    V1z *= f;
+                    dmin = d2;
+                }
+                const double w = exp((dmin - d2) * inv2s0);
+                const double sw = c.sj * w;
+                S0 += w;
+                S1 += sw;
+                V0x += w * dx;
+                V0y += w * dy;
+                V0z += w * dz;
+                V1x += sw * dx;
+                V1y += sw * dy;
+                V1z += sw * dz;
+            }
+        }
+        __syncthreads();                  // the run's LDS copy is consumed
+    }
     const bool have = S0 > 0.0;
     sg = have ? S1 / S0 : 0.5;
     const double gsc = have ? -1.0 / (s0 * s0 * S0) : 0.0;
@@ -147,6 +198,7 @@ __global__ void __launch_bounds__(256) k_sigma_field(int64_t n, const double *__
                                                      const int32_t *__restrict__ xm,
                                                      const int64_t *__restrict__ tri_off,
                                                      const Cen *__restrict__ cen,
+                                                     const double *__restrict__ cbox,
                                                      const double *__restrict__ sigma0, double *sig,
                                                      double *gsig) {
     __shared__ Cen ctile[256];
@@ -163,7 +215,7 @@ __global__ void __launch_bounds__(256) k_sigma_field(int64_t n, const double *__
     }
     const int64_t j0 = act ? tri_off[m] : 0, j1 = act ? tri_off[m + 1] : 0;
     double sg, gs[3];
-    const bool have = sigma_phase(cen, ctile, &blo, &bhi, j0, j1, px, py, pz, act ? sigma0[m] : 1.0, sg, gs);
+    const bool have = sigma_phase(cen, cbox, ctile, &blo, &bhi, j0, j1, px, py, pz, act ? sigma0[m] : 1.0, sg, gs);
     if (!act) return;
     sig[i] = have ? sg : NAN;
     gsig[3 * i] = gs[0];
@@ -188,6 +240,7 @@ __global__ void __launch_bounds__(256) k_eval_multiscale(int64_t n, const double
                                                          const int64_t *__restrict__ tri_off,
                                                          const int64_t *__restrict__ node_off,
                                                          const Cen *__restrict__ cen,
+                                                         const double *__restrict__ cbox,
                                                          const RawNode *__restrict__ nodes,
                                                          const double *__restrict__ sigma0, double *phi,
                                                          double *grad, double *sig_out) {
@@ -207,7 +260,7 @@ __global__ void __launch_bounds__(256) k_eval_multiscale(int64_t n, const double
     // ---- phase 1: sigma(x) and its gradient
     int64_t j0 = act ? tri_off[m] : 0, j1 = act ? tri_off[m + 1] : 0;
     double sg, gs[3];
-    const bool have = sigma_phase(cen, ctile, &blo, &bhi, j0, j1, px, py, pz, act ? sigma0[m] : 1.0, sg, gs);
+    const bool have = sigma_phase(cen, cbox, ctile, &blo, &bhi, j0, j1, px, py, pz, act ? sigma0[m] : 1.0, sg, gs);
     const double gsx = gs[0], gsy = gs[1], gsz = gs[2];
     int64_t lo, hi;
     // ---- phase 2: Phi, grad Phi with width sigma(x)
@@ -362,17 +415,24 @@ void launch_hessian_direct(Ctx &c, int64_t n, const double *x, const int32_t *xm
     LSS_CHECK_LAUNCH("k_hessian_direct");
 }
 
-void launch_sigma_field(Ctx &c, int64_t n, const double *x, const int32_t *xm, const Cen *cen, const double *sigma0,
-                        double *sig, double *gsig) {
+void launch_cen_boxes(Ctx &c, const Cen *cen, double *box) {
+    const int64_t runs = (c.ntris + 255) / 256;
+    hipLaunchKernelGGL(k_cen_boxes, dim3(blocks256(runs)), dim3(256), 0, c.stream, c.ntris, cen, box);
+    LSS_CHECK_LAUNCH("k_cen_boxes");
+}
+
+void launch_sigma_field(Ctx &c, int64_t n, const double *x, const int32_t *xm, const Cen *cen, const double *cbox,
+                        const double *sigma0, double *sig, double *gsig) {
     hipLaunchKernelGGL(k_sigma_field, dim3(blocks256(n)), dim3(256), 0, c.stream, n, x, xm, c.tri_off.as<int64_t>(),
-                       cen, sigma0, sig, gsig);
+                       cen, cbox, sigma0, sig, gsig);
     LSS_CHECK_LAUNCH("k_sigma_field");
 }
 
 void launch_eval_multiscale(Ctx &c, int64_t n, const double *x, const int32_t *xm, const Cen *cen,
-                            const RawNode *nodes, const double *sigma0, double *phi, double *grad, double *sig) {
+                            const double *cbox, const RawNode *nodes, const double *sigma0, double *phi,
+                            double *grad, double *sig) {
     hipLaunchKernelGGL(k_eval_multiscale, dim3(blocks256(n)), dim3(256), 0, c.stream, n, x, xm,
-                       c.tri_off.as<int64_t>(), c.node_off.as<int64_t>(), cen, nodes, sigma0, phi, grad, sig);
+                       c.tri_off.as<int64_t>(), c.node_off.as<int64_t>(), cen, cbox, nodes, sigma0, phi, grad, sig);
     LSS_CHECK_LAUNCH("k_eval_multiscale");
 }
 

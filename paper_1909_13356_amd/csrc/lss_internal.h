@@ -266,10 +266,12 @@ struct Ctx {
 void launch_prep_sources(Ctx &c);
 void launch_prep_raw(Ctx &c, RawNode *out);
 void launch_centroids(Ctx &c, double lambda, Cen *out, double *D);
-void launch_sigma_field(Ctx &c, int64_t n, const double *x, const int32_t *xm, const Cen *cen, const double *sigma0,
-                        double *sig, double *gsig);
+void launch_cen_boxes(Ctx &c, const Cen *cen, double *box);
+void launch_sigma_field(Ctx &c, int64_t n, const double *x, const int32_t *xm, const Cen *cen, const double *cbox,
+                        const double *sigma0, double *sig, double *gsig);
 void launch_eval_multiscale(Ctx &c, int64_t n, const double *x, const int32_t *xm, const Cen *cen,
-                            const RawNode *nodes, const double *sigma0, double *phi, double *grad, double *sig);
+                            const double *cbox, const RawNode *nodes, const double *sigma0, double *phi,
+                            double *grad, double *sig);
 void launch_pseudonormals(Ctx &c);
 void launch_bbox(Ctx &c);
 double launch_check_orientation(Ctx &c, std::vector<double> &vol_per_mesh, int64_t &ndegenerate);
