@@ -129,3 +129,24 @@ def test_batch_concat():
     assert list(b["tri_offsets"]) == [0, 12, 60]
     assert b["tris"].max() == len(b["verts"]) - 1
     assert list(np.bincount(b["target_mesh"])) == [5, 5]
+
+
+def test_torus_and_quadratic_generators():
+    from workloads import torus_mesh, quadratic_from_flat, mesh_check
+    v, t = torus_mesh(24, 12, R=1.0, r=0.4)
+    closed, vol = mesh_check(v, t)
+    assert closed and 0.9 * 2 * np.pi ** 2 * 0.16 < vol < 2 * np.pi ** 2 * 0.16
+    v6, t6 = torus_mesh(24, 12, R=1.0, r=0.4, quadratic=True)
+    assert t6.shape == (len(t), 6) and len(np.unique(t6)) == len(v6)
+    assert np.abs(np.hypot(np.hypot(v6[:, 0], v6[:, 1]) - 1.0, v6[:, 2]) - 0.4).max() < 1e-14
+    closed, _ = mesh_check(v6, np.ascontiguousarray(t6[:, :3]))
+    assert closed
+    # every edge point is shared by the two triangles of its edge
+    e = np.concatenate([t6[:, [0, 1, 3]], t6[:, [1, 2, 4]], t6[:, [2, 0, 5]]])
+    key = {}
+    for a, b, m in e:
+        key.setdefault((min(a, b), max(a, b)), set()).add(m)
+    assert all(len(s) == 1 for s in key.values())
+    vs, ts = icosphere(1)
+    vq, tq = quadratic_from_flat(vs, ts, lift=lambda p: p / np.linalg.norm(p, axis=1, keepdims=True))
+    assert np.allclose(np.linalg.norm(vq, axis=1), 1.0) and np.array_equal(tq[:, :3], ts)
