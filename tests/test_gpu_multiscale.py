@@ -45,7 +45,8 @@ def test_multiscale_vs_oracle(lam, sigma0):
     assert max(e) <= 1e-12
 
 
-def test_multiscale_batch_of_a_quadratic_torus_and_a_cube():
+@pytest.mark.parametrize("far", [lss.FAR_DIRECT, lss.FAR_FMM])
+def test_multiscale_batch_of_a_quadratic_torus_and_a_cube(far):
     vt, tt = torus_mesh(16, 8, quadratic=True)
     vc, tc = cube_mesh(4, 2.0, 3.0)
     # the cube as quadratic triangles with their own (unshared) edge midpoints
@@ -56,8 +57,9 @@ def test_multiscale_batch_of_a_quadratic_torus_and_a_cube():
     off = np.array([0, len(tt), len(t6)], np.int64)
     x = np.concatenate([box_targets(300, -1.5, 1.5, seed=1), box_targets(300, 1.8, 3.2, seed=3)])
     xm = np.repeat(np.array([0, 1], np.int32), [300, 300])
-    say("case: multiscale, batch of a quadratic torus and a cube")
+    say("case: multiscale, batch of a quadratic torus and a cube, far field %d" % far)
     c = ctx(v, t6, offsets=off)
+    c.set_options(precision=lss.FP64, far_field=far)
     p, g, s = c.eval_multiscale(x, 2.5, 0.0, x_mesh=xm)
     po, go, so = oracle.evaluate_multiscale(v, t6, dunavant6(), x, 2.5, 0.0, tri_offsets=off, x_mesh=xm)
     e = rel(p, po), rel(g, go), rel(s, so)
