@@ -162,3 +162,21 @@ def test_chart_curvature_through_the_fmm(star):
     errs = [rel(a, b) for a, b in zip(out, ref)]
     say("  vs direct: e_xuu %.2e e_xuv %.2e e_xvv %.2e e_gauss %.2e e_mean %.2e" % tuple(errs))
     assert max(errs) <= 1e-9
+
+
+@pytest.mark.parametrize("tile", [128, 256])
+def test_hessian_and_sigma_x_fmm_wide_tiles(star, tile):
+    """The octree Hessian and sigma(x) kernels at the wider FP64 tiles."""
+    v, t, sig = star
+    x = surface_offset_targets(v, t, sig, 3000, tmax=3.0, seed=23)
+    say("case: Hessian and sigma(x) through the FMM with tile %d" % tile)
+    c = ctx(v, t, sig, far=lss.FAR_FMM)
+    c.set_options(precision=lss.FP64, far_field=lss.FAR_FMM, tile=tile)
+    _, _, hs = c.eval_hessian(x)
+    p, g, s = c.eval_multiscale(x, 2.5, 0.0)
+    cd = ctx(v, t, sig, far=lss.FAR_DIRECT)
+    _, _, hd = cd.eval_hessian(x)
+    pd, gd, sd = cd.eval_multiscale(x, 2.5, 0.0)
+    e = rel(hs, hd), rel(p, pd), rel(g, gd)
+    say("  e_hess %.2e e_phi %.2e e_grad %.2e" % e)
+    assert e[0] <= 1e-10 and e[1] <= 1e-12 and e[2] <= 1e-12
