@@ -180,3 +180,26 @@ def test_hessian_and_sigma_x_fmm_wide_tiles(star, tile):
     e = rel(hs, hd), rel(p, pd), rel(g, gd)
     say("  e_hess %.2e e_phi %.2e e_grad %.2e" % e)
     assert e[0] <= 1e-10 and e[1] <= 1e-12 and e[2] <= 1e-12
+
+
+def test_chart_curvature_batch_vs_oracle():
+    """Two surfaces in one context: every chart's curvature from its own mesh."""
+    v1, t1 = star_surface(5, lmax=6, var0=0.1, seed=31)
+    v2, t2 = icosphere(2)
+    v2 = 0.5 * v2 + np.array([3.0, 0.0, 0.0])
+    v = np.concatenate([v1, v2])
+    t = np.concatenate([t1, t2 + len(v1)]).astype(np.int32)
+    off = np.array([0, len(t1), len(t)], np.int64)
+    sig = 0.5 * triangle_diameters(v, t)
+    uv = chart_nodes(2)
+    say("case: chart curvature on a batch of two surfaces, %d tri" % len(t))
+    c = ctx(v, t, sig, offsets=off)
+    h, x, st, it = c.project(uv)
+    assert np.all(st == 0)
+    out = c.chart_curvature(uv, h)
+    sel = np.arange(0, len(t), 9)
+    idx = (sel[:, None] * len(uv) + np.arange(len(uv))[None]).ravel()
+    o = oracle.chart_curvature(v, t, sig, dunavant6(), uv, h[idx], sel=sel, tri_offsets=off)
+    errs = [rel(a[idx], b) for a, b in zip(out, o)]
+    say("  e_xuu %.2e e_xuv %.2e e_xvv %.2e e_gauss %.2e e_mean %.2e" % tuple(errs))
+    assert max(errs) <= 1e-9
