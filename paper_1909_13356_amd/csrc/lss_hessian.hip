@@ -104,7 +104,7 @@ __global__ void k_cen_boxes(int64_t ntris, const Cen *__restrict__ cen, double *
 // distance from above by the farthest corner distance of each run that
 // meets the target's range [j0, j1); a run whose nearest box distance exceeds
 // that bound by 100 sigma0^2 carries weights below e^-50 of the largest and
-// is skipped.  The workgroup stages a run in LDS when any of its targets
+// is skipped, and so is any single centroid that far.  The workgroup stages a run in LDS when any of its targets
 // needs it; the sums are taken relative to the nearest centroid seen so far
 // (rescaled when it changes).  Returns false (sigma = 0.5, grad = 0) for an
 // empty range.  Every thread of the workgroup must call it.
@@ -158,6 +158,7 @@ __device__ bool sigma_phase(const Cen *__restrict__ cen, const double *__restric
                 const Cen c = ctile[k];
                 const double dx = px - c.cx, dy = py - c.cy, dz = pz - c.cz;
                 const double d2 = dx * dx + dy * dy + dz * dz;
+                if ((d2 - dref) * inv2s0 > 50.0) continue;   // weight below e^-50 of the nearest
                 if (d2 < dmin) {          // new nearest centroid: rescale the sums to it
                     const double f = exp((d2 - dmin) * inv2s0);
                     S0 *= f;
