@@ -837,3 +837,75 @@ def test_quadratic_refinement_keeps_the_surface():
         assert closed and len(np.unique(t)) == len(v)
         y, a = oracle.nodes(v, t, rule)
         assert abs(np.sum(y * a) / 3 - vol0) < 1e-13 and np.abs(a.sum(0)).max() < 1e-13
+
+
+def _two_obtuse_triangles():
+    """Two obtuse triangles with exact centroids and diameters: for an obtuse
+    triangle the smallest enclosing ball has the longest edge as diameter.
+    T1: base 0.4 along x, apex 0.03 above its midpoint -> c1 = (0, 0.01, 0),
+    D1 = 0.4; T2: base 0.8, apex 0.06 above -> c2 = (0.9, 0.32, 0.2), D2 = 0.8."""
+    v = np.array([[-0.2, 0.0, 0.0], [0.2, 0.0, 0.0], [0.0, 0.03, 0.0],
+                  [0.5, 0.3, 0.2], [1.3, 0.3, 0.2], [0.9, 0.36, 0.2]])
+    t = np.array([[0, 1, 2], [3, 4, 5]], dtype=np.int32)
+    c = np.array([[0.0, 0.01, 0.0], [0.9, 0.32, 0.2]])
+    return v, t, c, np.array([0.4, 0.8])
+
+
+def test_sigma_blend_exact_weights_three_to_one():
+    """eq. sigma2 with two centroids: the weights are exp(-|x - c_j|^2 /
+    (2 sigma0^2)), so where |x - c2|^2 - |x - c1|^2 = 2 sigma0^2 ln 3 they are
+    exactly 3 : 1 and sigma(x) = (3 sigma_1 + sigma_2) / 4, whatever the offset
+    of x across the line c1 c2.  A width sigma0^2 in place of 2 sigma0^2 gives
+    9 : 1 (sigma = 0.22 here instead of 0.25), and a weight centred on the
+    midpoint of the longest edge (the enclosing-ball centre) or on the
+    circumcentre instead of the centroid moves the ratio away from 3."""
+    v, t, c, D = _two_obtuse_triangles()
+    lam, s0 = 2.0, 0.5
+    s1, s2 = D / lam
+    e = c[1] - c[0]
+    L2 = e @ e
+    s = 0.5 * (1.0 - 2.0 * s0 * s0 * np.log(3.0) / L2)      # x = c1 + s e on the line
+    perp = np.cross(e, [0.0, 0.0, 1.0])
+    perp2 = np.cross(e, perp)
+    x = np.array([c[0] + s * e + a * perp + b * perp2 for a, b in ((0, 0), (0.3, 0), (-0.2, 0.5), (1.1, -0.7))])
+    sig, _, sj, s0_used = oracle.sigma_field(v, t, x, lam=lam, sigma0=s0)
+    assert np.allclose(sj, [s1, s2], rtol=1e-15, atol=0) and s0_used[0] == s0
+    assert np.abs(sig - (3 * s1 + s2) / 4).max() < 1e-14
+    # the pin separates the readings: 9 : 1 with the narrower width, and another
+    # ratio with the enclosing-ball centres (midpoints of the longest edges)
+    assert abs((9 * s1 + s2) / 10 - (3 * s1 + s2) / 4) > 1e-2
+    m = np.array([[0.0, 0.0, 0.0], [0.9, 0.3, 0.2]])
+    r = np.exp(-(((x - m[0]) ** 2).sum(1) - ((x - m[1]) ** 2).sum(1)) / (2 * s0 * s0))
+    assert np.abs((r * s1 + s2) / (r + 1) - (3 * s1 + s2) / 4).min() > 1e-4
+
+
+def test_sigma_blend_midpoint_value_and_gradient():
+    """At any point equidistant from the two centroids the weights are equal:
+    sigma = (sigma_1 + sigma_2) / 2, and differentiating eq. sigma2 there gives
+    grad sigma = (sigma_2 - sigma_1) (c2 - c1) / (4 sigma0^2) (the components
+    across c1 c2 cancel).  With the width sigma0^2 the gradient doubles."""
+    v, t, c, D = _two_obtuse_triangles()
+    lam, s0 = 2.0, 0.45
+    s1, s2 = D / lam
+    e = c[1] - c[0]
+    perp = np.cross(e, [0.0, 1.0, 0.0])
+    perp2 = np.cross(e, perp)
+    mid = 0.5 * (c[0] + c[1])
+    x = np.array([mid + a * perp + b * perp2 for a, b in ((0, 0), (0.4, 0), (0, -0.3), (-0.5, 0.25))])
+    sig, g, _, _ = oracle.sigma_field(v, t, x, lam=lam, sigma0=s0)
+    assert np.abs(sig - 0.5 * (s1 + s2)).max() < 1e-15
+    want = (s2 - s1) * e / (4 * s0 * s0)
+    assert np.abs(g - want).max() < 1e-14 * np.abs(want).max()
+
+
+def test_sigma_blend_nearest_centroid_dominates_far_away():
+    """Far from both centroids along c1 -> c2 the weight ratio exp(-(|x-c1|^2 -
+    |x-c2|^2) / (2 sigma0^2)) underflows in FP64: sigma(x) must then be the
+    nearest triangle's sigma_j (the weights are taken relative to the largest,
+    so there is no 0/0), with zero gradient."""
+    v, t, c, D = _two_obtuse_triangles()
+    e = (c[1] - c[0]) / np.linalg.norm(c[1] - c[0])
+    x = np.array([c[1] + 40.0 * e, c[0] - 40.0 * e])
+    sig, g, sj, _ = oracle.sigma_field(v, t, x, lam=2.0, sigma0=0.2)
+    assert sig[0] == sj[1] and sig[1] == sj[0]
+    assert np.abs(g).max() == 0.0
