@@ -170,7 +170,10 @@ int lss_synchronize(lss_ctx *ctx);
  *   mesh_tri_offsets: CSR of length nmesh+1 splitting the triangles into
  *     independent meshes (a ragged batch); offsets[0] = 0, non-decreasing,
  *     offsets[nmesh] = ntris.  NULL (with nmesh 0 or 1) = one mesh.
- *   rule_uvw (nq,3): nodes (u_m, v_m) on T0 and weights w_m (sum 1/2), nq >= 1.
+ *   rule_uvw (nq,3): nodes (u_m, v_m) on T0 and weights w_m (sum 1/2), nq >= 1;
+ *     NULL selects the default rule of lss_default_rule (Dunavant's 12-node
+ *     degree-6 rule, standing in for the paper's Vioreanu-Rokhlin rules of
+ *     section 4.3); nq must then be 0 or 12.
  * Indices outside [0, nverts) give LSS_EINVAL.  A mesh with signed volume
  * <= 0 gives LSS_EORIENT.  Invalidates sigma-dependent state: lss_set_sigma
  * must follow before lss_build / lss_eval / lss_project.
@@ -188,6 +191,14 @@ int lss_set_sources(lss_ctx *ctx,
                     const int64_t *mesh_tri_offsets, int32_t nmesh,
                     const double *rule_uvw, int32_t nq,
                     unsigned flags);
+
+/* The default source quadrature rule (section 4.3 asks for a high-order rule
+ * for smooth functions on each triangle): the 12-node symmetric degree-6 rule
+ * of Dunavant on T0, as rows (u_m, v_m, w_m) with sum w_m = 1/2, exact for
+ * polynomials of total degree <= 6.  Writes min(cap, 12) rows to out (host
+ * memory; NULL or cap <= 0 writes nothing) and returns 12.  Needs no device
+ * and no context. */
+int32_t lss_default_rule(double *out, int32_t cap);
 
 /* Set the smoothing width (section 2: sigma_j attached to triangle j).
  *   n == 1: one constant sigma; n == ntris: one sigma per triangle.

@@ -24,7 +24,7 @@ EXPORTED_SYMBOLS = ["lss_create", "lss_destroy", "lss_last_error", "lss_synchron
                     "lss_set_sources", "lss_set_sigma", "lss_set_options", "lss_get_options",
                     "lss_build", "lss_eval", "lss_project", "lss_chart_geometry", "lss_chart_interp",
                     "lss_eval_hessian", "lss_chart_curvature", "lss_eval_multiscale",
-                    "lss_autotune", "lss_get_stats"]
+                    "lss_autotune", "lss_get_stats", "lss_default_rule"]
 
 _CODES = {1: "LSS_EINVAL", 2: "LSS_ENOMEM", 3: "LSS_EHIP", 4: "LSS_ESTATE", 5: "LSS_EORIENT"}
 
@@ -100,8 +100,18 @@ def load_library():
     L.lss_eval_multiscale.argtypes = [P, ctypes.c_double, ctypes.c_double, P, P, i64, P, P, P, u]
     L.lss_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
     L.lss_autotune.argtypes = [P, P, i64, u, ctypes.c_double, ctypes.c_char_p, ctypes.POINTER(Options)]
+    L.lss_default_rule.argtypes = [P, i32]
+    L.lss_default_rule.restype = i32
     _lib = L
     return L
+
+
+def default_rule():
+    """The library's default source rule (lss_default_rule): (12, 3) rows (u, v, w)."""
+    L = load_library()
+    out = np.empty((12, 3))
+    n = L.lss_default_rule(out.ctypes.data_as(ctypes.c_void_p), 12)
+    return out[:n]
 
 
 def _is_torch(a):
@@ -168,8 +178,9 @@ class Context:
         self.close()
 
     # ------------------------------------------------------------ setters
-    def set_sources(self, verts, tris, rule, tri_offsets=None):
-        """tris (ntris, 3) flat or (ntris, 6) quadratic triangles (LSS_TRI6)."""
+    def set_sources(self, verts, tris, rule=None, tri_offsets=None):
+        """tris (ntris, 3) flat or (ntris, 6) quadratic triangles (LSS_TRI6);
+        rule (nq, 3) or None for the library's default rule."""
         if len(tris.shape) != 2 or tris.shape[1] not in (3, 6):
             raise ValueError("tris must be (ntris, 3) or (ntris, 6)")
         pv, fv, kv = _ptr(verts, np.float64)
@@ -177,11 +188,12 @@ class Context:
         pr, fr, kr = _ptr(rule, np.float64)
         po, fo, ko = _ptr(tri_offsets, np.int64)
         flags = fv | ft | fr | fo | (TRI6 if tris.shape[1] == 6 else 0)
-        if len({f for f in (fv, ft, fr, fo if tri_offsets is not None else fv)}) != 1:
+        if len({f for f in (fv, ft, fr if rule is not None else fv, fo if tri_offsets is not None else fv)}) != 1:
             raise ValueError("all arrays of one call must live in the same memory (host or device)")
         nverts, ntris = len(verts), len(tris)
         nmesh = 0 if tri_offsets is None else len(tri_offsets) - 1
-        self._check(self._lib.lss_set_sources(self._h, pv, nverts, pt, ntris, po, nmesh, pr, len(rule), flags))
+        nq = 0 if rule is None else len(rule)
+        self._check(self._lib.lss_set_sources(self._h, pv, nverts, pt, ntris, po, nmesh, pr, nq, flags))
         self.ntris = ntris
 
     def set_sigma(self, sigma):

@@ -64,6 +64,39 @@ __global__ void k_check_mesh_ids(int64_t n, const int32_t *__restrict__ xm, int3
 
 inline unsigned grid_for(int64_t n, int blk = 256) { return (unsigned)ceil_div(n > 0 ? n : 1, blk); }
 
+// The default source rule: Dunavant's 12-point symmetric rule of degree 6 on
+// T0 (two three-point orbits (a, a, 1 - 2a) and one six-point orbit (b, c,
+// 1 - b - c) in barycentric coordinates; weights normalised to 1 over the
+// triangle, then halved for the area of T0).  The orbit parameters are the
+// published ones carried to full double precision (exact on the 28 moment
+// equations of degree <= 6 to rounding).  Rows are (u, v, w) = (l2, l3, w/2).
+constexpr int kDefaultRuleNodes = 12;
+
+void default_rule(double *r) {
+    const double s21[2][2] = {{0.2492867451709104212916386, 0.1167862757263793660252896},
+                              {0.0630890144915022283403316, 0.05084490637020681692093681}};
+    const double s111[3] = {0.05314504984481694735324967, 0.3103524510337844054166077,
+                            0.08285107561837357519355346};
+    int k = 0;
+    for (int o = 0; o < 2; ++o) {
+        const double a = s21[o][0], w = s21[o][1], b = 1.0 - 2.0 * a;
+        const double l23[3][2] = {{a, b}, {b, a}, {a, a}};     // (l2, l3) of (a,a,b), (a,b,a), (b,a,a)
+        for (int q = 0; q < 3; ++q, ++k) {
+            r[3 * k] = l23[q][0];
+            r[3 * k + 1] = l23[q][1];
+            r[3 * k + 2] = 0.5 * w;
+        }
+    }
+    const double b = s111[0], c = s111[1], w = s111[2], d = 1.0 - b - c;
+    // (l2, l3) of the six permutations (b,c,d), (b,d,c), (c,b,d), (c,d,b), (d,b,c), (d,c,b)
+    const double l23[6][2] = {{c, d}, {d, c}, {b, d}, {d, b}, {b, c}, {c, b}};
+    for (int q = 0; q < 6; ++q, ++k) {
+        r[3 * k] = l23[q][0];
+        r[3 * k + 1] = l23[q][1];
+        r[3 * k + 2] = 0.5 * w;
+    }
+}
+
 void fail(int code, const std::string &m) { throw Error{code, m}; }
 
 // copy n bytes of caller data (host or device) into a context buffer
@@ -749,6 +782,13 @@ thread_local std::string g_create_err;   // message of the last failed lss_creat
 
 extern "C" {
 
+int32_t lss_default_rule(double *out, int32_t cap) {
+    double r[3 * lss::kDefaultRuleNodes];
+    lss::default_rule(r);
+    if (out && cap > 0) std::memcpy(out, r, sizeof(double) * 3 * (size_t)std::min<int32_t>(cap, lss::kDefaultRuleNodes));
+    return lss::kDefaultRuleNodes;
+}
+
 int lss_create(lss_ctx **out, int hip_device, void *hip_stream) {
     g_create_err.clear();
     if (!out) { g_create_err = "lss_create: out is null"; return LSS_EINVAL; }
@@ -797,7 +837,10 @@ int lss_set_sources(lss_ctx *ctx, const double *verts, int64_t nverts, const int
                     const int64_t *mesh_tri_offsets, int32_t nmesh, const double *rule_uvw, int32_t nq,
                     unsigned flags) {
     return lss::guarded(ctx, [&](Ctx &c) {
-        if (!verts || !tris || !rule_uvw) fail(LSS_EINVAL, "lss_set_sources: null pointer");
+        if (!verts || !tris) fail(LSS_EINVAL, "lss_set_sources: null pointer");
+        if (!rule_uvw && nq != 0 && nq != lss::kDefaultRuleNodes)
+            fail(LSS_EINVAL, "lss_set_sources: rule_uvw == NULL (default rule) needs nq 0 or 12");
+        if (!rule_uvw) nq = lss::kDefaultRuleNodes;
         if (nverts < 3 || ntris < 1 || nq < 1) fail(LSS_EINVAL, "lss_set_sources: need nverts >= 3, ntris >= 1, nq >= 1");
         if (nverts > (int64_t)INT32_MAX || ntris * (int64_t)nq > ((int64_t)1 << 40))
             fail(LSS_EINVAL, "lss_set_sources: mesh too large");
@@ -823,7 +866,11 @@ int lss_set_sources(lss_ctx *ctx, const double *verts, int64_t nverts, const int
         for (int32_t m = 0; m < nm; ++m)
             if (off[m + 1] < off[m]) fail(LSS_EINVAL, "lss_set_sources: offsets must be non-decreasing");
         std::vector<double> hrule(3 * (size_t)nq);
-        LSS_HIP(hipMemcpy(hrule.data(), rule_uvw, sizeof(double) * 3 * nq, dev ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+        if (rule_uvw)
+            LSS_HIP(hipMemcpy(hrule.data(), rule_uvw, sizeof(double) * 3 * nq,
+                              dev ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+        else
+            lss::default_rule(hrule.data());
         for (int m = 0; m < nq; ++m)
             if (!std::isfinite(hrule[3 * m]) || !std::isfinite(hrule[3 * m + 1]) || !std::isfinite(hrule[3 * m + 2]))
                 fail(LSS_EINVAL, "lss_set_sources: rule entries must be finite");

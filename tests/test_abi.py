@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 import paper_1909_13356_amd as lss
@@ -42,3 +43,25 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(b, "_LIBPATH", "/nonexistent/liblss.so")
     with pytest.raises(ImportError):
         b.load_library()
+
+
+def test_default_rule_is_dunavant6():
+    """lss_default_rule (the rule that rule_uvw == NULL selects): host-only, no
+    device.  The same 12 rows as the rule the tests pass explicitly, bit for
+    bit (both are built from the published orbit parameters), and exact on
+    every monomial u^i v^j of degree <= 6 over T0 (integral i! j! / (i+j+2)!)."""
+    if not os.path.exists(lss.library_path()):
+        pytest.skip("liblss.so not built")
+    from math import factorial
+    from workloads import dunavant6
+    r = lss.default_rule()
+    assert r.shape == (12, 3)
+    assert np.array_equal(r, dunavant6())
+    u, v, w = r.T
+    for i in range(7):
+        for j in range(7 - i):
+            exact = factorial(i) * factorial(j) / factorial(i + j + 2)
+            assert abs(np.sum(w * u ** i * v ** j) - exact) < 2e-16, (i, j)
+    assert np.all(u > 0) and np.all(v > 0) and np.all(u + v < 1)
+    L = lss.load_library()
+    assert L.lss_default_rule(None, 0) == 12

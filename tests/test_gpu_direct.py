@@ -188,6 +188,31 @@ def test_error_codes():
     assert phi[0] > 0.5
 
 
+def test_default_rule_when_rule_is_null(c1):
+    """rule_uvw == NULL selects the library's Dunavant-6 rule: the sums are
+    bitwise those with the same rule passed explicitly (direct and FMM), and
+    a NULL rule with nq other than 0 or 12 is rejected."""
+    import ctypes
+    cfg, po, go = c1
+    say("case: NULL rule vs explicit Dunavant-6, cube 3072 tri")
+    for far in (lss.FAR_DIRECT, lss.FAR_FMM):
+        ca = lss.Context()
+        ca.set_sources(cfg["verts"], cfg["tris"], None)
+        cb = ctx_for(cfg["verts"], cfg["tris"], cfg["sigma"])
+        for c in (ca, cb):
+            c.set_sigma(cfg["sigma"])
+            c.set_options(precision=lss.FP64, far_field=far)
+        pa, ga = ca.eval(cfg["targets"])
+        pb, gb = cb.eval(cfg["targets"])
+        assert np.array_equal(pa, pb) and np.array_equal(ga, gb), far
+        assert ca.stats()["n_nodes"] == 12 * len(cfg["tris"])
+    v = np.ascontiguousarray(cfg["verts"])
+    t = np.ascontiguousarray(cfg["tris"], dtype=np.int32)
+    rc = ca._lib.lss_set_sources(ca._h, v.ctypes.data_as(ctypes.c_void_p), len(v), t.ctypes.data_as(ctypes.c_void_p),
+                                 len(t), None, 0, None, 7, 0)
+    assert rc == 1                                             # EINVAL: NULL rule with nq = 7
+
+
 # ------------------------------------------------------------------ Newton
 @pytest.mark.parametrize("prec", [lss.FP64, lss.MIXED])
 def test_project_sphere_vs_oracle(prec):
