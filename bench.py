@@ -27,6 +27,12 @@ sys.path.insert(0, ROOT)
 METRIC = ("Φ+∇Φ target evals/sec, mixed vs FP64 at 1e-6 / 1e-12, 2M-triangle mesh, 1 GPU")
 PEAK = {"f64": 78.6, "f32": 157.3}          # TFLOP/s, MI355X published dense vector peaks
 FLOP_PER_PAIR = 40.0                        # algorithmic FLOPs per (target, node) pair
+
+
+def L2P_FLOP(p):
+    """Algorithmic FLOPs of a local-expansion evaluation with its gradient at
+    one target, order p: about 8 per coefficient."""
+    return 8.0 * (p + 1) ** 2
 HESS_FLOP_PER_PAIR = 87.0                   # Phi, grad and Hessian of one pair, far form
 
 
@@ -111,10 +117,16 @@ def time_variant(lss, torch, cfg, prec, far, steps, warmup):
         c.eval(x, phi=phi, grad=grad)
     torch.cuda.synchronize()
     el_eval = time.perf_counter() - t1
+    # one more evaluation, untimed, whose kernels also count the pairs inside
+    # the cut (the method's own near-field work); results are unchanged
+    c.set_options(precision=prec, far_field=far, count_useful=1)
+    c.eval(x, phi=phi, grad=grad)
+    useful = c.stats()["useful_pairs"]
     c.close()
     return dict(ms_per_step=1e3 * el / steps, value=n * steps / el, eval_only_per_s=n * steps / el_eval,
                 pair_kernel_ms=kms, pair_kernel_launches=launches, pairs_per_step=pairs,
-                pairs_per_s=pairs * steps / el, n_targets=n, lane_use=lane_use, tree=tree)
+                pairs_per_s=pairs * steps / el, useful_pairs_per_step=useful, useful_pairs_per_s=useful * steps / el,
+                n_targets=n, lane_use=lane_use, tree=tree, phi=phi, grad=grad)
 
 
 def time_newton(lss, torch, cfg, prec, steps, warmup):
@@ -338,7 +350,12 @@ def cpu_newton(cfg, n_tris=4):
             "sample": "%d chart nodes of %d triangles (seeded), FP64 direct-sum Newton, %.1f s" % (nn, n_tris, dt)}
 
 
-def cpu_baseline(cfg, budget_s=15.0):
+def cpu_baseline(cfg, budget_s=15.0, budget1_s=8.0):
+    """The oracle (plain FP64 direct sum, no cut, no FMM) on a seeded target
+    sample sized to about budget_s of work on every host thread, then on a
+    smaller sample on one thread.  Returns the report and, for the error
+    report, the sample's indices with the oracle's Phi, grad Phi and the
+    condition sums A_Phi = sum |term|."""
     import oracle
     x = cfg["targets"]
     rng = np.random.default_rng(1234)
@@ -349,14 +366,47 @@ def cpu_baseline(cfg, budget_s=15.0):
     oracle.evaluate(cfg["verts"], cfg["tris"], cfg["sigma"], cfg["rule"], x[idx])
     dt = time.perf_counter() - t0
     m2 = int(min(len(x), max(m, m * budget_s / max(dt, 1e-3))))
-    idx = rng.choice(len(x), m2, replace=False)
+    idx = np.sort(rng.choice(len(x), m2, replace=False))
     t0 = time.perf_counter()
-    oracle.evaluate(cfg["verts"], cfg["tris"], cfg["sigma"], cfg["rule"], x[idx])
+    po, go, ao, _ = oracle.evaluate(cfg["verts"], cfg["tris"], cfg["sigma"], cfg["rule"], x[idx], with_abs=True)
     dt = time.perf_counter() - t0
-    return {"value": m2 / dt, "unit": "target evals/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": "%d of %d targets (seeded), full direct FP64 sum over all %d nodes, %.1f s" % (
-                m2, len(x), nsrc, dt),
-            "pairs_per_s": m2 * nsrc / dt}
+    nt = oracle.threads()
+    m1 = int(max(1, min(m2, m2 / dt / max(nt, 1) * budget1_s)))
+    t0 = time.perf_counter()
+    oracle.evaluate(cfg["verts"], cfg["tris"], cfg["sigma"], cfg["rule"], x[idx[:m1]], nthreads=1)
+    dt1 = time.perf_counter() - t0
+    rep = {"value": m2 / dt, "unit": "target evals/s", "cores": nt, "kind": "oracle",
+           "sample": "%d of %d targets (seeded), full direct FP64 sum over all %d nodes, %.1f s" % (
+               m2, len(x), nsrc, dt),
+           "pairs_per_s": m2 * nsrc / dt,
+           "single_thread": {"value": m1 / dt1, "unit": "target evals/s", "cores": 1,
+                             "pairs_per_s": m1 * nsrc / dt1,
+                             "sample": "the first %d targets of the same sample, %.1f s" % (m1, dt1)}}
+    return rep, (idx, po, go, ao)
+
+
+def error_report(phi, grad, ref):
+    """Errors of the GPU results at the oracle's sample (SURVEY c12 reading):
+    e_phi = max |dPhi| / max |Phi_oracle|, e_grad likewise with norms;
+    pointwise |dPhi| / |Phi_oracle| over targets with |Phi_oracle| >= 1e-3,
+    and |dPhi| / A_Phi (A_Phi = sum of |terms|), at median, p99 and max."""
+    idx, po, go, ao = ref
+    import torch
+    ii = torch.as_tensor(idx, device=phi.device)
+    p = phi.index_select(0, ii).cpu().numpy()
+    g = grad.index_select(0, ii).cpu().numpy()
+    dp = np.abs(p - po)
+    dg = np.linalg.norm(g - go, axis=1)
+    big = np.abs(po) >= 1e-3
+    pw = dp[big] / np.abs(po[big])
+    ca = dp / ao
+
+    def q(a):
+        return {"median": float(np.median(a)), "p99": float(np.quantile(a, 0.99)), "max": float(a.max())} \
+            if len(a) else None
+    return {"targets": int(len(idx)), "e_phi": float(dp.max() / np.abs(po).max()),
+            "e_grad": float(dg.max() / np.linalg.norm(go, axis=1).max()),
+            "pointwise_rel_phi": q(pw), "dphi_over_Aphi": q(ca)}
 
 
 def main():
@@ -384,20 +434,33 @@ def main():
     for prec, name in ((lss.FP64, "f64"), (lss.MIXED, "mixed")):
         log("bench: timing", name)
         res[name] = time_variant(lss, torch, cfg, prec, far, args.steps, args.warmup)
-        log("bench:", name, json.dumps(res[name]))
+        log("bench:", name, json.dumps({k: v for k, v in res[name].items() if k not in ("phi", "grad")}))
     mixed, f64 = res["mixed"], res["f64"]
 
     def roof(r, dt):
+        """Algorithmic FLOPs of one evaluation launch over its duration: 40 per
+        pair inside the cut (the near field the method asks for) plus the
+        local-expansion evaluation, 8 (p+1)^2 per target; pairs evaluated
+        beyond the cut (whole leaves of the near lists) are not counted."""
         kname = ("k_eval_fmm_%s" if far else "k_p2p_direct_%s") % ("mixed" if dt == "f32" else "f64")
         traffic = measured_traffic(kname, desc)
         if r["pair_kernel_launches"] <= 0 or r["pair_kernel_ms"] <= 0:
             return None
         per_launch = r["pair_kernel_ms"] / r["pair_kernel_launches"] * 1e-3
-        ach = FLOP_PER_PAIR * r["pairs_per_step"] / r["pair_kernel_launches"] / per_launch / 1e12
+        p = r["tree"]["fmm_order"]
+        l2p = L2P_FLOP(p) * r["n_targets"] if far else 0.0
+        useful = r["useful_pairs_per_step"] / r["pair_kernel_launches"]
+        ach = (FLOP_PER_PAIR * useful + l2p) / per_launch / 1e12
         return {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK[dt], "unit": "TFLOP/s",
                 "frac": round(ach / PEAK[dt], 4), "traffic": traffic,
-                "kernel": kname, "lane_use": r["lane_use"],
-                "kernel_ms": round(per_launch * 1e3, 4)}
+                "kernel": kname, "kernel_ms": round(per_launch * 1e3, 4),
+                "useful_pairs_per_launch": useful, "flop_per_useful_pair": FLOP_PER_PAIR,
+                "l2p_flop_per_target": L2P_FLOP(p) if far else 0.0,
+                "executed_pairs_per_launch": r["pairs_per_step"] / r["pair_kernel_launches"],
+                "executed_over_useful": round(r["pairs_per_step"] / max(r["useful_pairs_per_step"], 1.0), 3),
+                "lane_use": r["lane_use"],
+                "executed_tflops": round(FLOP_PER_PAIR * r["pairs_per_step"] / r["pair_kernel_launches"]
+                                         / per_launch / 1e12, 3)}
 
     out = {
         "metric": METRIC, "value": mixed["value"], "unit": "target evals/s", "n_gpus": 1,
@@ -407,12 +470,19 @@ def main():
         "config": {"workload": desc},
         "roofline": roof(mixed, "f32"),
         "fp64": {"value": f64["value"], "ms_per_step": f64["ms_per_step"], "roofline": roof(f64, "f64"),
-                 "eval_only_per_s": f64["eval_only_per_s"], "pairs_per_s": f64["pairs_per_s"]},
-        "mixed": {"eval_only_per_s": mixed["eval_only_per_s"], "pairs_per_s": mixed["pairs_per_s"]},
+                 "eval_only_per_s": f64["eval_only_per_s"], "pairs_per_s": f64["pairs_per_s"],
+                 "useful_pairs_per_s": f64["useful_pairs_per_s"]},
+        "mixed": {"eval_only_per_s": mixed["eval_only_per_s"], "pairs_per_s": mixed["pairs_per_s"],
+                  "useful_pairs_per_s": mixed["useful_pairs_per_s"]},
     }
     if not args.no_cpu:
         log("bench: timing the CPU oracle on a sample")
-        out["cpu_baseline"] = cpu_baseline(cfg)
+        out["cpu_baseline"], ref = cpu_baseline(cfg)
+        out["errors"] = {"mixed": error_report(mixed["phi"], mixed["grad"], ref),
+                         "f64": error_report(f64["phi"], f64["grad"], ref)}
+        log("bench: errors", json.dumps(out["errors"]))
+    for r in res.values():
+        del r["phi"], r["grad"]
     if not args.no_newton:
         from workloads import configs
         del cfg

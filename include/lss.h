@@ -115,7 +115,10 @@ typedef struct lss_options {
     double  leaf_shrink;      /* LSS_FAR_FMM: leaves may be as narrow as (cut radius of their nodes) /
                                  leaf_shrink; M2L then also needs a box gap >= the source's cut radius.
                                  0 = default (2 for FP64, 1.5 for MIXED); otherwise in [1, 3] */
-    int32_t reserved[6];      /* must be zero */
+    int32_t count_useful;     /* LSS_FAR_FMM: nonzero makes the evaluation kernels also count the
+                                 pairs inside the cut (lss_stats.useful_pairs), at a small cost in
+                                 speed; 0 = off (useful_pairs stays 0 for the FMM path) */
+    int32_t reserved[5];      /* must be zero */
 } lss_options;
 
 typedef struct lss_stats {
@@ -147,6 +150,13 @@ typedef struct lss_stats {
                                  filled tiles included (last_pairs / lane_pairs = lane use) */
     int64_t n_m2p;            /* (leaf, box) pairs of the last build whose far field reaches the
                                  leaf's targets straight from the box's multipole expansion */
+    double  useful_pairs;     /* pairs of the last lss_eval / lss_project whose distance is inside
+                                 the cut of their node (rho < cut_factor * sigma): the work the
+                                 method itself asks for (section 4.4: the near field is the ball of
+                                 radius cut around the target).  LSS_FAR_DIRECT: every pair (the
+                                 exact sum has no cut).  LSS_FAR_FMM: counted only with
+                                 lss_options.count_useful, else 0.  last_pairs / useful_pairs is
+                                 the overhead of evaluating whole leaves of the near lists. */
 } lss_stats;
 
 /* Create a context on HIP device `hip_device`, queuing work on `hip_stream`

@@ -40,7 +40,8 @@ class Options(ctypes.Structure):
                 ("fmm_order", ctypes.c_int32), ("leaf_capacity", ctypes.c_int32),
                 ("cut_factor", ctypes.c_double), ("newton_tau", ctypes.c_double),
                 ("newton_max_iter", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("leaf_shrink", ctypes.c_double), ("reserved", ctypes.c_int32 * 6)]
+                ("leaf_shrink", ctypes.c_double), ("count_useful", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class Stats(ctypes.Structure):
@@ -50,7 +51,8 @@ class Stats(ctypes.Structure):
                 ("last_targets", ctypes.c_int64), ("last_pairs", ctypes.c_double),
                 ("n_degenerate", ctypes.c_int64), ("pair_kernel_ms", ctypes.c_double),
                 ("pair_kernel_launches", ctypes.c_int32), ("pad0", ctypes.c_int32),
-                ("lane_pairs", ctypes.c_double), ("n_m2p", ctypes.c_int64)]
+                ("lane_pairs", ctypes.c_double), ("n_m2p", ctypes.c_int64),
+                ("useful_pairs", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -203,9 +205,10 @@ class Context:
         self._check(self._lib.lss_set_sigma(self._h, ps, len(sigma), fs))
 
     def set_options(self, precision=FP64, far_field=FAR_DIRECT, fmm_order=0, leaf_capacity=0,
-                    cut_factor=0.0, newton_tau=0.0, newton_max_iter=0, tile=0, leaf_shrink=0.0):
+                    cut_factor=0.0, newton_tau=0.0, newton_max_iter=0, tile=0, leaf_shrink=0.0,
+                    count_useful=0):
         o = Options(precision, far_field, fmm_order, leaf_capacity, cut_factor, newton_tau,
-                    newton_max_iter, tile, leaf_shrink)
+                    newton_max_iter, tile, leaf_shrink, int(bool(count_useful)))
         self._check(self._lib.lss_set_options(self._h, ctypes.byref(o)))
 
     def get_options(self):

@@ -118,7 +118,8 @@ void validate_options(const lss_options &o) {
     if (o.tile != 0 && o.tile != 64 && o.tile != 128 && o.tile != 256) fail(LSS_EINVAL, "tile must be 0, 64, 128 or 256");
     if (!(o.leaf_shrink == 0.0 || (o.leaf_shrink >= 1.0 && o.leaf_shrink <= 3.0)))
         fail(LSS_EINVAL, "leaf_shrink must be 0 (default) or in [1, 3]");
-    for (int k = 0; k < 6; ++k)
+    if (o.count_useful != 0 && o.count_useful != 1) fail(LSS_EINVAL, "count_useful must be 0 or 1");
+    for (int k = 0; k < 5; ++k)
         if (o.reserved[k] != 0) fail(LSS_EINVAL, "reserved option fields must be zero");
 }
 
@@ -171,7 +172,7 @@ void eval_fmm_targets(Ctx &c, int64_t n, const int32_t *n_dev, double *phi, doub
                 c.ntiles.as<int32_t>());
     c.tile_order.ensure(sizeof(int32_t) * (n + 1));
     order_tiles(c, n, c.ntiles.as<int32_t>(), c.tstart.as<int32_t>(), c.tleaf.as<int32_t>());
-    if (reset_pairs) LSS_HIP(hipMemsetAsync(c.pairs.p, 0, 2 * sizeof(double), c.stream));
+    if (reset_pairs) LSS_HIP(hipMemsetAsync(c.pairs.p, 0, 3 * sizeof(double), c.stream));
     c.ev_begin();
     launch_eval_fmm(c, n, c.ntiles.as<int32_t>(), c.tstart.as<int32_t>(), n_dev, n, c.tleaf.as<int32_t>(),
                     c.tperm2.as<int32_t>(), c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(), nullptr, phi, grad,
@@ -230,7 +231,7 @@ void eval(Ctx &c, const double *x, const int32_t *xm, int64_t n, double *phi, do
                    c.tperm2.as<int32_t>(), n, 0, 64, c.stream);
     launch_gather_targets(c, dx, dxm, c.tperm2.as<int32_t>(), n, c.tx.as<double>(), c.ty.as<double>(),
                           c.tz.as<double>(), c.tmesh.as<int32_t>());
-    LSS_HIP(hipMemsetAsync(c.pairs.p, 0, 2 * sizeof(double), c.stream));
+    LSS_HIP(hipMemsetAsync(c.pairs.p, 0, 3 * sizeof(double), c.stream));
     c.ev_begin();
     launch_p2p_direct(c, n, nullptr, c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(),
                       c.tmesh.as<int32_t>(), c.tperm2.as<int32_t>(), dphi, dgrad, 3);
@@ -313,7 +314,7 @@ void project(Ctx &c, const double *uv, int32_t np, double *h, double *xout, int8
     DBuf phi, grad;
     phi.ensure(sizeof(double) * N);
     grad.ensure(sizeof(double) * 3 * N);
-    LSS_HIP(hipMemsetAsync(c.pairs.p, 0, 2 * sizeof(double), c.stream));
+    LSS_HIP(hipMemsetAsync(c.pairs.p, 0, 3 * sizeof(double), c.stream));
     // Iterations run in captured chunks; a node leaves the active list when it
     // converges or reaches maxit, so iterations past the last active one are
     // empty launches and the host only checks the count between chunks.
@@ -1037,15 +1038,16 @@ int lss_get_stats(const lss_ctx *ctx, lss_stats *out) {
         c.ev_pending = false;
     }
     if (c.pairs_pending) {
-        double pr[2] = {0.0, 0.0};
+        double pr[3] = {0.0, 0.0, 0.0};
         (void)hipSetDevice(c.device);
-        if (hipMemcpyAsync(pr, c.pairs.p, 2 * sizeof(double), hipMemcpyDeviceToHost, c.stream) != hipSuccess ||
+        if (hipMemcpyAsync(pr, c.pairs.p, 3 * sizeof(double), hipMemcpyDeviceToHost, c.stream) != hipSuccess ||
             hipStreamSynchronize(c.stream) != hipSuccess) {
             c.err = "lss_get_stats: reading the pair counter failed";
             return LSS_EHIP;
         }
         c.stats.last_pairs = pr[0];
         c.stats.lane_pairs = pr[1];
+        c.stats.useful_pairs = c.opt.far_field == LSS_FAR_FMM ? pr[2] : pr[0];
         c.pairs_pending = false;
     }
     *out = c.stats;

@@ -49,6 +49,28 @@ __device__ __forceinline__ Src fold_src(Src f) {
     return f;
 }
 
+// Padding records (chunks are filled to whole node groups): zero dipole
+// vector, placed so far away that every target sees them beyond the cut
+// (the dipole branch, whose terms underflow to zero), so they neither
+// contribute nor pull a node group into the near-branch evaluation.
+__device__ __forceinline__ Src pad_src() {
+    Src f;
+    f.yx = f.yy = f.yz = 1.0e150;
+    f.ax = f.ay = f.az = f.s2x2 = 0.0;
+    f.s2 = 1.0;
+    return f;
+}
+
+__device__ __forceinline__ SrcF pad_srcf() {
+    SrcF f;
+    f.yx = f.yy = f.yz = 1.0e18f;
+    f.lx = f.ly = f.lz = 0.0f;
+    f.ax = f.ay = f.az = f.s2x2 = 0.0f;
+    f.s2 = 1.0f;
+    f.pad = 0.0f;
+    return f;
+}
+
 __device__ __forceinline__ void two_sum(double &s, double &e, double v) {
     double t = s + v;
     double bp = t - s;
@@ -132,10 +154,11 @@ __device__ __forceinline__ void pair64(const Src &s, double x, double y, double 
     gz = fma(g, dz, fma(-s.az, S, gz));
 }
 
-// K consecutive FP64 records against one target (see nodes32 below)
-template <int K>
+// K consecutive FP64 records against one target (see nodes32 below); with
+// COUNT the pairs inside the cut are added to *cnt
+template <int K, bool COUNT = false>
 __device__ __forceinline__ void nodes64(const Src *sh, double x, double y, double z, double &p, double &gx,
-                                        double &gy, double &gz) {
+                                        double &gy, double &gz, uint32_t *cnt = nullptr) {
     double dx[K], dy[K], dz[K], u[K], ad[K], S[K], T[K];
     double umin = 1.0e300;
 #pragma unroll
@@ -175,6 +198,7 @@ __device__ __forceinline__ void nodes64(const Src *sh, double x, double y, doubl
             const bool nr = u[k] < KF64_X;
             S[k] = nr ? ps * r : S[k];
             T[k] = nr ? pt * r : T[k];
+            if (COUNT) *cnt += nr ? 1u : 0u;
         }
     }
 #pragma unroll
@@ -192,9 +216,9 @@ constexpr int kNodeGroup64 = 4;
 
 constexpr int kNodeGroup = 4;
 
-template <int K>
+template <int K, bool COUNT = false>
 __device__ __forceinline__ void nodes32(const SrcF *sh, float x, float y, float z, float xl, float yl, float zl,
-                                        float &p, float &gx, float &gy, float &gz) {
+                                        float &p, float &gx, float &gy, float &gz, uint32_t *cnt = nullptr) {
     float dx[K], dy[K], dz[K], u[K], ad[K], S[K], T[K];
     float umin = 3.0e38f;
 #pragma unroll
@@ -227,6 +251,7 @@ __device__ __forceinline__ void nodes32(const SrcF *sh, float x, float y, float 
             const bool nr = u[k] < (float)KF32_X;
             S[k] = nr ? ps * rq : S[k];
             T[k] = nr ? pt * rq : T[k];
+            if (COUNT) *cnt += nr ? 1u : 0u;
         }
     }
 #pragma unroll
@@ -289,12 +314,7 @@ __global__ __launch_bounds__(TILE) void k_p2p_direct_f64(
         const int cnt = (int)(hi - c0 < TILE ? hi - c0 : TILE);
         __syncthreads();
         if (lane < cnt) sh[lane] = fold_src(src[c0 + lane]);
-        else {                                  // zero records pad the chunk to whole node groups
-            Src f;
-            f.yx = f.yy = f.yz = f.ax = f.ay = f.az = f.s2x2 = 0.0;
-            f.s2 = 1.0e300;
-            sh[lane] = f;
-        }
+        else sh[lane] = pad_src();              // pad the chunk to whole node groups
         __syncthreads();
         double p = 0, gx = 0, gy = 0, gz = 0;
         const bool full = c0 >= b && c0 + cnt <= e;
@@ -370,10 +390,8 @@ __global__ __launch_bounds__(TILE) void k_p2p_direct_mixed(
                 f.ay = (float)(kFoldA * s.ay);
                 f.az = (float)(kFoldA * s.az);
                 f.s2x2 = (float)(kFoldT * s.s2x2);
-            } else {                            // zero record: no contribution, far branch
-                f.yx = f.yy = f.yz = f.lx = f.ly = f.lz = 0.0f;
-                f.ax = f.ay = f.az = f.s2x2 = 0.0f;
-                f.s2 = 1.0e30f;
+            } else {
+                f = pad_srcf();
             }
             f.pad = 0.0f;
             sh[lane] = f;
@@ -889,7 +907,8 @@ __global__ __launch_bounds__(256) void k_multiscale_outside(FmmEvalArgs a, MsArg
 
 // Four waves per SIMD: the compiler fits the kernel in 128 VGPRs with a few
 // spills outside the chunk loop (1% faster on C5 than three waves at 139).
-template <int TILE>
+// COUNT: also count the pairs inside the cut (pairs[2]), for the statistics
+template <int TILE, bool COUNT>
 __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_fmm_f64(FmmEvalArgs a) {
     __shared__ Src sh[TILE];
     __shared__ RangeBatch<TILE> rb;
@@ -914,6 +933,7 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(4))) void 
         stage_local(a, B, Ls);
         double sp = 0, ep = 0, sx = 0, ex = 0, sy = 0, ey = 0, sz = 0, ez = 0;
         double npair = 0.0;
+        uint32_t nuse = 0;
         for (int eb = e0; eb < e1; eb += TILE) {
             const int nr = e1 - eb < TILE ? e1 - eb : TILE;
             __syncthreads();
@@ -923,15 +943,11 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(4))) void 
                 const int cnt = (int)(total - c0 < TILE ? total - c0 : TILE);
                 __syncthreads();
                 if (lane < cnt) sh[lane] = fold_src(a.src[packed_node<TILE>(rb, nr, c0 + lane)]);
-                else {                          // zero records pad the chunk to whole node groups
-                    Src f;
-                    f.yx = f.yy = f.yz = f.ax = f.ay = f.az = f.s2x2 = 0.0;
-                    f.s2 = 1.0e300;
-                    sh[lane] = f;
-                }
+                else sh[lane] = pad_src();      // pad the chunk to whole node groups
                 __syncthreads();
                 double p = 0, gx = 0, gy = 0, gz = 0;
-                for (int j = 0; j < cnt; j += kNodeGroup64) nodes64<kNodeGroup64>(sh + j, x, y, z, p, gx, gy, gz);
+                for (int j = 0; j < cnt; j += kNodeGroup64)
+                    nodes64<kNodeGroup64, COUNT>(sh + j, x, y, z, p, gx, gy, gz, &nuse);
                 two_sum(sp, ep, p);
                 two_sum(sx, ex, gx);
                 two_sum(sy, ey, gy);
@@ -958,9 +974,14 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(4))) void 
                 a.grad[3 * o + 2] = (sz + g[2]) + ez;
             }
         }
-        if (a.pairs) {                      // [0] pairs of real targets, [1] lane slots spent
+        if (a.pairs) {                      // [0] pairs of real targets, [1] lane slots spent, [2] inside the cut
             const double w = wave_sum(valid ? npair : 0.0), wl = wave_sum(npair);
-            if ((lane & 63) == 0) { atomicAdd(a.pairs, w); atomicAdd(a.pairs + 1, wl); }
+            const double wu = COUNT ? wave_sum(valid ? (double)nuse : 0.0) : 0.0;
+            if ((lane & 63) == 0) {
+                atomicAdd(a.pairs, w);
+                atomicAdd(a.pairs + 1, wl);
+                if (COUNT) atomicAdd(a.pairs + 2, wu);
+            }
         }
     }
     queue_done(a);
@@ -969,6 +990,7 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(4))) void 
 
 // Mixed path: one wavefront per tile of 64 targets; each staged chunk of 64
 // node records is padded with zero records to whole groups of kNodeGroup.
+template <bool COUNT>
 __global__ __launch_bounds__(64) void k_eval_fmm_mixed(FmmEvalArgs a) {
     constexpr int W = 64;
     __shared__ SrcF sh[W];
@@ -998,6 +1020,7 @@ __global__ __launch_bounds__(64) void k_eval_fmm_mixed(FmmEvalArgs a) {
         stage_local(a, B, Ls);
         float sp = 0, ep = 0, sx = 0, ex = 0, sy = 0, ey = 0, sz = 0, ez = 0;
         double npair = 0.0;
+        uint32_t nuse = 0;
         for (int eb = e0; eb < e1; eb += W) {
             const int nr = e1 - eb < W ? e1 - eb : W;
             __syncthreads();
@@ -1021,10 +1044,8 @@ __global__ __launch_bounds__(64) void k_eval_fmm_mixed(FmmEvalArgs a) {
                     f.ay = (float)(kFoldA * sr.ay);
                     f.az = (float)(kFoldA * sr.az);
                     f.s2x2 = (float)(kFoldT * sr.s2x2);
-                } else {                        // zero record: no contribution, far branch
-                    f.yx = f.yy = f.yz = f.lx = f.ly = f.lz = 0.0f;
-                    f.ax = f.ay = f.az = f.s2x2 = 0.0f;
-                    f.s2 = 1.0e30f;
+                } else {
+                    f = pad_srcf();
                 }
                 f.pad = 0.0f;
                 sh[lane] = f;
@@ -1033,7 +1054,7 @@ __global__ __launch_bounds__(64) void k_eval_fmm_mixed(FmmEvalArgs a) {
                     float p = 0, gx = 0, gy = 0, gz = 0;
                     const int j1 = j0 + 32 < cnt ? j0 + 32 : cnt;
                     for (int j = j0; j < j1; j += kNodeGroup)
-                        nodes32<kNodeGroup>(sh + j, x, y, z, xl, yl, zl, p, gx, gy, gz);
+                        nodes32<kNodeGroup, COUNT>(sh + j, x, y, z, xl, yl, zl, p, gx, gy, gz, &nuse);
                     two_sum_f(sp, ep, p);
                     two_sum_f(sx, ex, gx);
                     two_sum_f(sy, ey, gy);
@@ -1061,9 +1082,14 @@ __global__ __launch_bounds__(64) void k_eval_fmm_mixed(FmmEvalArgs a) {
                 a.grad[3 * o + 2] = ((double)sz + (double)ez) + g[2];
             }
         }
-        if (a.pairs) {                      // [0] pairs of real targets, [1] lane slots spent
+        if (a.pairs) {                      // [0] pairs of real targets, [1] lane slots spent, [2] inside the cut
             const double w = wave_sum(valid ? npair : 0.0), wl = wave_sum(npair);
-            if (lane == 0) { atomicAdd(a.pairs, w); atomicAdd(a.pairs + 1, wl); }
+            const double wu = COUNT ? wave_sum(valid ? (double)nuse : 0.0) : 0.0;
+            if (lane == 0) {
+                atomicAdd(a.pairs, w);
+                atomicAdd(a.pairs + 1, wl);
+                if (COUNT) atomicAdd(a.pairs + 2, wu);
+            }
         }
     }
     queue_done(a);
@@ -1093,7 +1119,10 @@ void launch_hess_tile(Ctx &c, unsigned grid, const FmmEvalArgs &a, double *hess)
 template <int TILE>
 void launch_fmm_tile(Ctx &c, unsigned grid, const FmmEvalArgs &a) {
     const size_t shm = sizeof(double) * (size_t)a.ncp;
-    hipLaunchKernelGGL(k_eval_fmm_f64<TILE>, dim3(grid), dim3(TILE), shm, c.stream, a);
+    if (c.opt.count_useful)
+        hipLaunchKernelGGL((k_eval_fmm_f64<TILE, true>), dim3(grid), dim3(TILE), shm, c.stream, a);
+    else
+        hipLaunchKernelGGL((k_eval_fmm_f64<TILE, false>), dim3(grid), dim3(TILE), shm, c.stream, a);
     LSS_CHECK_LAUNCH("k_eval_fmm");
 }
 
@@ -1177,7 +1206,12 @@ void launch_eval_fmm(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const
         return;
     }
     if (c.opt.precision == LSS_MIXED) {
-        hipLaunchKernelGGL(k_eval_fmm_mixed, dim3(grid), dim3(64), sizeof(double) * (size_t)a.ncp, c.stream, a);
+        if (c.opt.count_useful)
+            hipLaunchKernelGGL(k_eval_fmm_mixed<true>, dim3(grid), dim3(64), sizeof(double) * (size_t)a.ncp, c.stream,
+                               a);
+        else
+            hipLaunchKernelGGL(k_eval_fmm_mixed<false>, dim3(grid), dim3(64), sizeof(double) * (size_t)a.ncp, c.stream,
+                               a);
         LSS_CHECK_LAUNCH("k_eval_fmm_mixed");
     } else {
         switch (fmm_tile(c)) {

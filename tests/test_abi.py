@@ -32,9 +32,37 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts():
     from paper_1909_13356_amd._binding import Options, Stats
-    # lss_options: 4 int32, 2 double, 2 int32, 1 double, 6 int32 reserved
-    assert ctypes.sizeof(Options) == 4 * 4 + 2 * 8 + 2 * 4 + 8 + 6 * 4
-    assert ctypes.sizeof(Stats) == 8 * 2 + 4 * 2 + 8 * 3 + 4 * 2 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8
+    # lss_options: 4 int32, 2 double, 2 int32, 1 double, count_useful, 5 int32 reserved
+    assert ctypes.sizeof(Options) == 4 * 4 + 2 * 8 + 2 * 4 + 8 + 4 + 5 * 4
+    assert ctypes.sizeof(Stats) == 8 * 2 + 4 * 2 + 8 * 3 + 4 * 2 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8 + 8
+
+
+def test_struct_offsets_match_the_c_header(tmp_path):
+    """Every field offset of the ctypes structures equals offsetof() in a C
+    program compiled against include/lss.h."""
+    import shutil
+    import subprocess
+    from paper_1909_13356_amd._binding import Options, Stats
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lss.h"', 'int main(void) {']
+    for cname, S in (("lss_options", Options), ("lss_stats", Stats)):
+        lines.append('printf("%%s sizeof %%zu\\n", "%s", sizeof(%s));' % (cname, cname))
+        for f, _ in S._fields_:
+            lines.append('printf("%%s %%s %%zu\\n", "%s", "%s", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append("return 0; }")
+    src = tmp_path / "off.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "off"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)]).decode().splitlines():
+        a, b, v = line.split()
+        got[(a, b)] = int(v)
+    for cname, S in (("lss_options", Options), ("lss_stats", Stats)):
+        assert got[(cname, "sizeof")] == ctypes.sizeof(S), cname
+        for f, _ in S._fields_:
+            assert got[(cname, f)] == getattr(S, f).offset, (cname, f)
 
 
 def test_missing_library_fails_loudly(monkeypatch):

@@ -246,6 +246,51 @@ def test_fmm_mixed_eval_reproducible_and_counters(graded):
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
+def useful_pairs_brute(v, t, sig, x, cut):
+    """Pairs (target, node) with |x - y_k| < cut * sigma_k, by a k-d tree over
+    the nodes (every node within cut * max sigma, then each node's own radius)."""
+    from scipy.spatial import cKDTree
+    y, _ = oracle.nodes(v, t, dunavant6())
+    sk = np.repeat(np.asarray(sig, float), len(dunavant6()))
+    tree = cKDTree(y)
+    n = 0
+    for i, cand in enumerate(tree.query_ball_point(x, cut * sk.max(), workers=-1)):
+        cand = np.asarray(cand, dtype=np.int64)
+        d2 = ((y[cand] - x[i]) ** 2).sum(1)
+        n += int(np.count_nonzero(d2 < (cut * sk[cand]) ** 2))
+    return n
+
+
+@pytest.mark.parametrize("prec", [lss.FP64, lss.MIXED])
+def test_useful_pair_count(graded, prec):
+    """With count_useful the evaluation kernels count the pairs inside their
+    node's cut radius (section 4.4: the near field is the ball of radius cut
+    around the target).  Every such pair lies on a near list, so the count
+    equals a brute-force count by distance; the decision u < cut^2 / 2 is taken
+    in the kernel's precision, so pairs within rounding of the cut may differ
+    (none expected at this size).  Results do not depend on the option."""
+    v, t, sig, x = graded
+    rng = np.random.default_rng(11)
+    xs = x[np.sort(rng.choice(len(x), 2000, replace=False))]
+    cut = 8.0 if prec == lss.FP64 else np.sqrt(40.0)
+    want = useful_pairs_brute(v, t, sig, xs, cut)
+    cf = ctx(v, t, sig, prec, lss.FAR_FMM)
+    p0, g0 = cf.eval(xs)
+    assert cf.stats()["useful_pairs"] == 0.0
+    cf.set_options(precision=prec, far_field=lss.FAR_FMM, count_useful=1)
+    p1, g1 = cf.eval(xs)
+    st = cf.stats()
+    say("  precision %d useful pairs %.0f (brute force %d), executed %.0f (%.2fx)" % (
+        prec, st["useful_pairs"], want, st["last_pairs"], st["last_pairs"] / max(st["useful_pairs"], 1)))
+    assert abs(st["useful_pairs"] - want) <= 2 + 1e-7 * want
+    assert st["useful_pairs"] <= st["last_pairs"]
+    assert np.array_equal(p0, p1) and np.array_equal(g0, g1)
+    cd = ctx(v, t, sig, prec, lss.FAR_DIRECT)
+    cd.eval(xs[:100])
+    sd = cd.stats()
+    assert sd["useful_pairs"] == sd["last_pairs"] == 100 * 12 * len(t)
+
+
 @pytest.fixture(scope="module")
 def volume():
     """Graded bumpy sphere with targets filling a cube around it: many sit in
