@@ -238,6 +238,30 @@ int lss_build(lss_ctx *ctx);
 int lss_eval(lss_ctx *ctx, const double *x, const int32_t *x_mesh, int64_t n,
              double *phi, double *grad, unsigned flags);
 
+/* Allocation-free evaluation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): lss_eval's evaluation, same kernels in the same order, with
+ * every per-call buffer (target copies, sort keys and workspace, tile lists)
+ * in a static device array of the library (48 MiB per device, held until the
+ * process ends) instead of context allocations.  Results equal lss_eval's bit
+ * for bit.  Differences from lss_eval:
+ *   - device pointers only: flags must contain LSS_PTR_DEVICE (else EINVAL);
+ *   - n <= LSS_NOALLOC_MAX_TARGETS (else EINVAL; call lss_eval instead);
+ *   - the context must already be built (lss_build, or any call that builds,
+ *     after the last set_* call), else ESTATE: this call does not build;
+ *   - lss_get_stats is not updated (no counters, no timing events);
+ *   - every call on one device shares the array: calls that overlap on one
+ *     device (contexts on different streams of that device) race; calls
+ *     ordered on one stream do not.  The array keeps the last call's
+ *     contents; what must start at zero is cleared by a kernel, not a memset.
+ * It calls no hipMalloc / hipFree and no allocating library routine.  With a
+ * batch (nmesh > 1) it checks x_mesh first and waits for that check, as
+ * lss_eval does; otherwise it returns without waiting (outputs are defined
+ * once the context stream passes the call).  Arguments as for lss_eval. */
+#define LSS_NOALLOC_MAX_TARGETS 524288
+int lss_eval_noalloc(lss_ctx *ctx, const double *x, const int32_t *x_mesh, int64_t n, double *phi, double *grad,
+                     unsigned flags);
+
 /* Chart projection onto Phi = 1/2 for np chart nodes (u_i, v_i) on T0,
  * chart_uv (np,2), on every triangle.  Output index j*np + i (triangle
  * major): h (ntris*np) pseudonormal distance, xout (ntris*np, 3) projected

@@ -24,7 +24,7 @@ EXPORTED_SYMBOLS = ["lss_create", "lss_destroy", "lss_last_error", "lss_synchron
                     "lss_set_sources", "lss_set_sigma", "lss_set_options", "lss_get_options",
                     "lss_build", "lss_eval", "lss_project", "lss_chart_geometry", "lss_chart_interp",
                     "lss_eval_hessian", "lss_chart_curvature", "lss_eval_multiscale",
-                    "lss_autotune", "lss_get_stats", "lss_default_rule"]
+                    "lss_autotune", "lss_get_stats", "lss_default_rule", "lss_eval_noalloc"]
 
 _CODES = {1: "LSS_EINVAL", 2: "LSS_ENOMEM", 3: "LSS_EHIP", 4: "LSS_ESTATE", 5: "LSS_EORIENT"}
 
@@ -94,6 +94,7 @@ def load_library():
     L.lss_get_options.argtypes = [P, ctypes.POINTER(Options)]
     L.lss_build.argtypes = [P]
     L.lss_eval.argtypes = [P, P, P, i64, P, P, u]
+    L.lss_eval_noalloc.argtypes = [P, P, P, i64, P, P, u]
     L.lss_project.argtypes = [P, P, i32, P, P, P, P, u]
     L.lss_chart_geometry.argtypes = [P, P, i32, P, P, P, P, P, u]
     L.lss_chart_interp.argtypes = [P, P, i32, P, i32, P, i32, P, u]
@@ -266,6 +267,17 @@ class Context:
             phi[...] = kp
             if grad is not None:
                 grad[...] = kg
+        return phi, grad
+
+    def eval_noalloc(self, x, phi, grad=None, x_mesh=None):
+        """lss_eval_noalloc: Phi and grad Phi at targets x (n, 3) into the
+        caller's device tensors phi (n,) and grad (n, 3) (may be None), with
+        no device allocation in the library; the context must be built."""
+        px, fx, kx = _ptr(x, np.float64)
+        pm, fm, km = _ptr(x_mesh, np.int32)
+        pp, fp, kp = _ptr(phi, np.float64)
+        pg, fg, kg = _ptr(grad, np.float64)
+        self._check(self._lib.lss_eval_noalloc(self._h, px, pm, len(x), pp, pg, fx | fp))
         return phi, grad
 
     def project(self, chart_uv, device=False):

@@ -157,28 +157,78 @@ void ensure_targets(Ctx &c, int64_t n) {
     c.tmesh.ensure(sizeof(int32_t) * n);
 }
 
-// FMM evaluation of the targets already in c.tx/ty/tz[0..n) (count *n_dev on
-// the device if given): leaf of each target, targets sorted by leaf, tiles,
-// near field + L2P.  Outputs at the target's index in tx/ty/tz.
-void eval_fmm_targets(Ctx &c, int64_t n, const int32_t *n_dev, double *phi, double *grad, bool reset_pairs = true,
-                      double *hess = nullptr, const MsArgs *ms = nullptr) {
-    launch_locate_targets(c, n, n_dev, c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(),
-                          c.tmesh.as<int32_t>(), c.tkey.as<uint64_t>(), c.tperm.as<int32_t>());
-    sort_pairs(c, c.tkey.as<uint64_t>(), c.tkey2.as<uint64_t>(), c.tperm.as<int32_t>(), c.tperm2.as<int32_t>(), n, 64);
+}  // namespace
+
+// The context's grow-only buffers as the per-call buffers of an evaluation of
+// n targets (statistics counters and timing events on).
+EvalBufs eval_bufs_ctx(Ctx &c, int64_t n) {
+    ensure_targets(c, n);
+    c.tflag.ensure(sizeof(int32_t) * (n + 1));
+    c.tpos.ensure(sizeof(int32_t) * (n + 1));
     c.tstart.ensure(sizeof(int32_t) * (n + 1));
     c.tleaf.ensure(sizeof(int32_t) * (n + 1));
-    c.ntiles.ensure(16);
-    build_tiles(c, n, n_dev, c.tkey2.as<uint64_t>(), fmm_tile(c), c.tleaf.as<int32_t>(), c.tstart.as<int32_t>(),
-                c.ntiles.as<int32_t>());
     c.tile_order.ensure(sizeof(int32_t) * (n + 1));
-    order_tiles(c, n, c.ntiles.as<int32_t>(), c.tstart.as<int32_t>(), c.tleaf.as<int32_t>());
-    if (reset_pairs) LSS_HIP(hipMemsetAsync(c.pairs.p, 0, 3 * sizeof(double), c.stream));
-    c.ev_begin();
-    launch_eval_fmm(c, n, c.ntiles.as<int32_t>(), c.tstart.as<int32_t>(), n_dev, n, c.tleaf.as<int32_t>(),
-                    c.tperm2.as<int32_t>(), c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(), nullptr, phi, grad,
-                    hess, ms);
-    c.ev_end();
+    c.ntiles.ensure(16);
+    c.ns.blocksum.ensure(sizeof(int32_t) * (compact_blocks(n) + 2));
+    const size_t tb = sort_pairs_u64_tmp_bytes(n);
+    c.sort_tmp.ensure(tb);
+    EvalBufs b;
+    b.tx = c.tx.as<double>();
+    b.ty = c.ty.as<double>();
+    b.tz = c.tz.as<double>();
+    b.tmesh = c.tmesh.as<int32_t>();
+    b.key = c.tkey.as<uint64_t>();
+    b.key2 = c.tkey2.as<uint64_t>();
+    b.perm = c.tperm.as<int32_t>();
+    b.perm2 = c.tperm2.as<int32_t>();
+    b.flag = c.tflag.as<int32_t>();
+    b.pos = c.tpos.as<int32_t>();
+    b.blocksum = nullptr;                 // compact_flags uses (and grows) the context's own
+    b.tstart = c.tstart.as<int32_t>();
+    b.tleaf = c.tleaf.as<int32_t>();
+    b.ntiles = c.ntiles.as<int32_t>();
+    b.order = c.tile_order.as<int32_t>();
+    b.sort_tmp = c.sort_tmp.p;
+    b.sort_bytes = tb;
+    b.pairs = c.pairs.as<double>();
+    b.n_dev = nullptr;
+    return b;
 }
+
+// FMM evaluation of the targets already in b.tx/ty/tz[0..n): leaf of each
+// target, targets sorted by leaf, tiles, near field + L2P.  Outputs at the
+// target's index in tx/ty/tz.  With b.pairs the counters are cleared first and
+// HIP events bracket the evaluation launch (lss_stats).
+void eval_fmm_bufs(Ctx &c, const EvalBufs &b, int64_t n, double *phi, double *grad, double *hess, const MsArgs *ms) {
+    launch_locate_targets(c, n, b.n_dev, b.tx, b.ty, b.tz, b.tmesh, b.key, b.perm);
+    sort_pairs_u64(b.sort_tmp, b.sort_bytes, b.key, b.key2, b.perm, b.perm2, n, 0, 64, c.stream);
+    build_tiles(c, n, b.n_dev, b.key2, fmm_tile(c), b.tleaf, b.tstart, b.ntiles, b.flag, b.pos, b.blocksum);
+    order_tiles(c, n, b.ntiles, b.tstart, b.tleaf, b.order);
+    if (b.pairs) {
+        LSS_HIP(hipMemsetAsync(b.pairs, 0, 3 * sizeof(double), c.stream));
+        c.ev_begin();
+    }
+    launch_eval_fmm(c, n, b.ntiles, b.tstart, b.n_dev, n, b.tleaf, b.perm2, b.tx, b.ty, b.tz, nullptr, phi, grad,
+                    b.order, b.pairs, hess, ms);
+    if (b.pairs) c.ev_end();
+}
+
+// Direct evaluation: targets sorted by (mesh, Morton key), gathered into SoA,
+// every pair of the target's mesh; outputs at the caller's target index.
+void eval_direct_bufs(Ctx &c, const EvalBufs &b, const double *x, const int32_t *xm, int64_t n, double *phi,
+                      double *grad) {
+    launch_target_keys(c, x, xm, n, b.key, b.perm);
+    sort_pairs_u64(b.sort_tmp, b.sort_bytes, b.key, b.key2, b.perm, b.perm2, n, 0, 64, c.stream);
+    launch_gather_targets(c, x, xm, b.perm2, n, b.tx, b.ty, b.tz, b.tmesh);
+    if (b.pairs) {
+        LSS_HIP(hipMemsetAsync(b.pairs, 0, 3 * sizeof(double), c.stream));
+        c.ev_begin();
+    }
+    launch_p2p_direct(c, n, b.n_dev, b.tx, b.ty, b.tz, b.tmesh, b.perm2, phi, grad, 3, b.pairs);
+    if (b.pairs) c.ev_end();
+}
+
+namespace {
 
 void eval(Ctx &c, const double *x, const int32_t *xm, int64_t n, double *phi, double *grad, unsigned flags) {
     if (n < 0) fail(LSS_EINVAL, "lss_eval: n < 0");
@@ -217,25 +267,14 @@ void eval(Ctx &c, const double *x, const int32_t *xm, int64_t n, double *phi, do
         LSS_HIP(hipStreamSynchronize(c.stream));
         if (nb) fail(LSS_EINVAL, "lss_eval: x_mesh values outside [0, nmesh)");
     }
-    ensure_targets(c, n);
+    const EvalBufs b = eval_bufs_ctx(c, n);
     c.ev_reset();
     if (c.opt.far_field == LSS_FAR_FMM) {
-        launch_soa(c, dx, n, c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>());
-        if (dxm) LSS_HIP(hipMemcpyAsync(c.tmesh.p, dxm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c.stream));
-        eval_fmm_targets(c, n, nullptr, dphi, dgrad);
+        launch_soa(c, dx, n, b.tx, b.ty, b.tz);
+        if (dxm) LSS_HIP(hipMemcpyAsync(b.tmesh, dxm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c.stream));
+        eval_fmm_bufs(c, b, n, dphi, dgrad);
     } else {
-    launch_target_keys(c, dx, dxm, n, c.tkey.as<uint64_t>(), c.tperm.as<int32_t>());
-    size_t tb = sort_pairs_u64_tmp_bytes(n);
-    c.sort_tmp.ensure(tb);
-    sort_pairs_u64(c.sort_tmp.p, tb, c.tkey.as<uint64_t>(), c.tkey2.as<uint64_t>(), c.tperm.as<int32_t>(),
-                   c.tperm2.as<int32_t>(), n, 0, 64, c.stream);
-    launch_gather_targets(c, dx, dxm, c.tperm2.as<int32_t>(), n, c.tx.as<double>(), c.ty.as<double>(),
-                          c.tz.as<double>(), c.tmesh.as<int32_t>());
-    LSS_HIP(hipMemsetAsync(c.pairs.p, 0, 3 * sizeof(double), c.stream));
-    c.ev_begin();
-    launch_p2p_direct(c, n, nullptr, c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(),
-                      c.tmesh.as<int32_t>(), c.tperm2.as<int32_t>(), dphi, dgrad, 3);
-    c.ev_end();
+        eval_direct_bufs(c, b, dx, dxm, n, dphi, dgrad);
     }
     if (!dev) {
         LSS_HIP(hipMemcpyAsync(phi, dphi, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
@@ -256,12 +295,14 @@ void newton_iteration(Ctx &c, int64_t N, double tau, double *phi, double *grad) 
     launch_newton_targets(c, N);
     if (c.opt.far_field == LSS_FAR_FMM) {
         build_tiles_unsorted(c, N, nact, fmm_tile(c));
-        order_tiles(c, N, c.ntiles.as<int32_t>(), c.tstart.as<int32_t>(), c.tleaf.as<int32_t>());
+        order_tiles(c, N, c.ntiles.as<int32_t>(), c.tstart.as<int32_t>(), c.tleaf.as<int32_t>(),
+                    c.tile_order.as<int32_t>());
         launch_eval_fmm(c, N, c.ntiles.as<int32_t>(), c.tstart.as<int32_t>(), nact, N, c.tleaf.as<int32_t>(),
-                        nullptr, c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(), nullptr, phi, grad);
+                        nullptr, c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(), nullptr, phi, grad,
+                        c.tile_order.as<int32_t>(), c.pairs.as<double>());
     } else {
         launch_p2p_direct(c, N, nact, c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>(), c.tmesh.as<int32_t>(),
-                          nullptr, phi, grad, 3);
+                          nullptr, phi, grad, 3, c.pairs.as<double>());
     }
     launch_newton_update(c, N, tau, phi, grad);
     launch_compact_active(c, N);
@@ -457,11 +498,11 @@ void eval_hessian(Ctx &c, const double *x, const int32_t *xm, int64_t n, double 
         if (nb) fail(LSS_EINVAL, "lss_eval_hessian: x_mesh values outside [0, nmesh)");
     }
     if (c.opt.far_field == LSS_FAR_FMM) {       // near lists + expansions of the context's tree
-        ensure_targets(c, n);
+        const EvalBufs b = eval_bufs_ctx(c, n);
         c.ev_reset();
-        launch_soa(c, dx, n, c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>());
-        if (dxm) LSS_HIP(hipMemcpyAsync(c.tmesh.p, dxm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c.stream));
-        eval_fmm_targets(c, n, nullptr, dphi, dgrad, true, dhess);
+        launch_soa(c, dx, n, b.tx, b.ty, b.tz);
+        if (dxm) LSS_HIP(hipMemcpyAsync(b.tmesh, dxm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c.stream));
+        eval_fmm_bufs(c, b, n, dphi, dgrad, dhess);
     } else {
         launch_hessian_direct(c, n, dx, dxm, dphi, dgrad, dhess);
     }
@@ -574,12 +615,12 @@ void eval_multiscale(Ctx &c, double lambda, double sigma0, const double *x, cons
         c.built = false;
         build(c);
         upload(c, dscut, smax.data(), sizeof(double) * c.nmesh, 0);
-        ensure_targets(c, n);
+        const EvalBufs b = eval_bufs_ctx(c, n);
         c.ev_reset();
-        launch_soa(c, dx, n, c.tx.as<double>(), c.ty.as<double>(), c.tz.as<double>());
-        if (dxm) LSS_HIP(hipMemcpyAsync(c.tmesh.p, dxm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c.stream));
+        launch_soa(c, dx, n, b.tx, b.ty, b.tz);
+        if (dxm) LSS_HIP(hipMemcpyAsync(b.tmesh, dxm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c.stream));
         const MsArgs ms{tsig.as<double>(), tgs.as<double>(), dscut.as<double>()};
-        eval_fmm_targets(c, n, nullptr, dphi, dgrad, true, nullptr, &ms);
+        eval_fmm_bufs(c, b, n, dphi, dgrad, nullptr, &ms);
         if (dsig) LSS_HIP(hipMemcpyAsync(dsig, tsig.p, sizeof(double) * n, hipMemcpyDeviceToDevice, c.stream));
         LSS_HIP(hipStreamSynchronize(c.stream));
     } else {
@@ -802,6 +843,9 @@ int lss_create(lss_ctx **out, int hip_device, void *hip_stream) {
         return LSS_EHIP;
     }
     if (hip_device < 0 || hip_device >= ndev) { g_create_err = "lss_create: device index out of range"; return LSS_EINVAL; }
+    // look up the allocation-free path's scratch array on this device now (a
+    // failure is reported by lss_eval_noalloc, not here)
+    if (hipSetDevice(hip_device) == hipSuccess) (void)lss::noalloc_scratch(hip_device, nullptr);
     lss_ctx *ctx = new (std::nothrow) lss_ctx;
     if (!ctx) return LSS_ENOMEM;
     ctx->c.device = hip_device;
@@ -977,6 +1021,11 @@ int lss_build(lss_ctx *ctx) {
 int lss_eval(lss_ctx *ctx, const double *x, const int32_t *x_mesh, int64_t n, double *phi, double *grad,
              unsigned flags) {
     return lss::guarded(ctx, [&](Ctx &c) { lss::eval(c, x, x_mesh, n, phi, grad, flags); });
+}
+
+int lss_eval_noalloc(lss_ctx *ctx, const double *x, const int32_t *x_mesh, int64_t n, double *phi, double *grad,
+                     unsigned flags) {
+    return lss::guarded(ctx, [&](Ctx &c) { lss::eval_noalloc(c, x, x_mesh, n, phi, grad, flags); });
 }
 
 int lss_project(lss_ctx *ctx, const double *chart_uv, int32_t np, double *h, double *xout, int8_t *status,

@@ -282,10 +282,10 @@ void launch_target_keys(Ctx &c, const double *x, const int32_t *x_mesh, int64_t 
 void launch_gather_targets(Ctx &c, const double *x, const int32_t *x_mesh, const int32_t *perm,
                            int64_t n, double *tx, double *ty, double *tz, int32_t *tmesh);
 
-// pair kernels (lss_p2p.hip)
+// pair kernels (lss_p2p.hip); pairs: the statistics counters (null: none)
 void launch_p2p_direct(Ctx &c, int64_t n, const int32_t *n_dev, const double *tx, const double *ty,
                        const double *tz, const int32_t *tmesh, const int32_t *out_idx,
-                       double *phi, double *grad, int grad_stride);
+                       double *phi, double *grad, int grad_stride, double *pairs);
 
 // Newton (lss_kernels.hip)
 void launch_chart_init(Ctx &c, const double *chart_uv, int32_t np, int64_t N);
@@ -315,13 +315,18 @@ void build_tree(Ctx &c);
 void build_fmm(Ctx &c);
 void launch_locate_targets(Ctx &c, int64_t n_max, const int32_t *n_dev, const double *tx, const double *ty,
                            const double *tz, const int32_t *tmesh, uint64_t *keys, int32_t *idx);
+// tile heads of sorted targets; flag, pos (n_max + 1 each) and blocksum
+// (compact_blocks(n_max) + 2) are workspace; n_dev may be null (count n_max)
 int64_t build_tiles(Ctx &c, int64_t n_max, const int32_t *n_dev, const uint64_t *sorted_keys, int tile,
-                    int32_t *sorted_leaf, int32_t *tile_start, int32_t *ntiles_dev);
+                    int32_t *sorted_leaf, int32_t *tile_start, int32_t *ntiles_dev, int32_t *flag, int32_t *pos,
+                    int32_t *blocksum);
 int fmm_tile(const Ctx &c);
+// order: the tile order of order_tiles; pairs: statistics counters (null: none)
 void launch_eval_fmm(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const int32_t *tile_start,
                      const int32_t *n_dev, int64_t n_max, const int32_t *sorted_leaf, const int32_t *sorted_idx,
                      const double *tx, const double *ty, const double *tz, const int32_t *out_idx, double *phi,
-                     double *grad, double *hess = nullptr, const MsArgs *ms = nullptr);
+                     double *grad, const int32_t *order, double *pairs, double *hess = nullptr,
+                     const MsArgs *ms = nullptr);
 void launch_soa(Ctx &c, const double *x, int64_t n, double *tx, double *ty, double *tz);
 // Newton targets in FMM mode: leaf of each target in its current order and
 // tile heads at leaf changes and every TILE-th position (no sort; capturable)
@@ -330,7 +335,7 @@ void ensure_tiles(Ctx &c, int64_t n_max);
 // size, most expensive bucket first (kernels only: capturable)
 constexpr int kCostBuckets = 64;
 void order_tiles(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const int32_t *tile_start,
-                 const int32_t *leaf);
+                 const int32_t *leaf, int32_t *order);
 void build_tiles_unsorted(Ctx &c, int64_t n_max, const int32_t *n_dev, int tile);
 void rebin_active(Ctx &c, int64_t N, int64_t nact);
 
@@ -342,9 +347,43 @@ void sort_pairs_u64(void *tmp, size_t tmp_bytes, const uint64_t *kin, uint64_t *
 // sort (key, value) pairs with a context-owned temporary; keys/values end in kout/vout
 void sort_pairs(Ctx &c, const uint64_t *kin, uint64_t *kout, const int32_t *vin, int32_t *vout, int64_t n,
                 int end_bit = 64);
-// order-preserving compaction helpers (lss_kernels.hip)
+// order-preserving compaction helpers (lss_kernels.hip).  blocksum: null =
+// the context's own buffer (grown as needed), else compact_blocks(n_max) + 2
+// int32 of workspace, and then n_dev must be given.
+int32_t compact_blocks(int64_t n_max);
 void compact_flags(Ctx &c, int64_t n_max, const int32_t *n_dev, const int32_t *flag, const int32_t *in,
-                   int32_t *out, int32_t *count_dev);
+                   int32_t *out, int32_t *count_dev, int32_t *blocksum = nullptr);
+
+// Per-call device buffers of an evaluation (targets, keys, tiles, sort
+// workspace).  eval_bufs_ctx() takes them from the context's grow-only
+// buffers; the allocation-free entry point carves them out of its static
+// scratch array (lss_noalloc.hip).
+struct EvalBufs {
+    double *tx, *ty, *tz;
+    int32_t *tmesh;
+    uint64_t *key, *key2;
+    int32_t *perm, *perm2;
+    int32_t *flag, *pos, *blocksum;       // tile-head workspace
+    int32_t *tstart, *tleaf, *ntiles, *order;
+    void *sort_tmp;
+    size_t sort_bytes;
+    double *pairs;                        // statistics counters, or null
+    const int32_t *n_dev;                 // target count on the device, or null
+};
+EvalBufs eval_bufs_ctx(Ctx &c, int64_t n);
+// FMM evaluation of the n targets in b.tx/ty/tz (b.tmesh for batches);
+// outputs at the targets' indices
+void eval_fmm_bufs(Ctx &c, const EvalBufs &b, int64_t n, double *phi, double *grad, double *hess = nullptr,
+                   const MsArgs *ms = nullptr);
+// direct evaluation of n targets x (device, AoS), mesh ids xm (null: one mesh)
+void eval_direct_bufs(Ctx &c, const EvalBufs &b, const double *x, const int32_t *xm, int64_t n, double *phi,
+                      double *grad);
+
+// allocation-free evaluation (lss_noalloc.hip): the device address of the
+// static scratch array on `device` (looked up once per device; null on
+// failure, message in *err), and lss_eval_noalloc's body
+void *noalloc_scratch(int device, std::string *err);
+void eval_noalloc(Ctx &c, const double *x, const int32_t *xm, int64_t n, double *phi, double *grad, unsigned flags);
 
 // ------------------------------------------------------------ constants
 constexpr int kMaxIterDefault = 40;

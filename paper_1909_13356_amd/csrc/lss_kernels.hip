@@ -779,23 +779,30 @@ void launch_compact_active(Ctx &c, int64_t N) {
     LSS_CHECK_LAUNCH("compact");
 }
 
+int32_t compact_blocks(int64_t n_max) { return (int32_t)ceil_div(n_max > 0 ? n_max : 1, kCompBlk); }
+
 // out <- in[i] for flag[i] != 0, i < n (n = *n_dev if given, else n_max); count -> *count_dev
 void compact_flags(Ctx &c, int64_t n_max, const int32_t *n_dev, const int32_t *flag, const int32_t *in,
-                   int32_t *out, int32_t *count_dev) {
-    DBuf &bs = c.ns.blocksum;
-    int32_t nb = (int32_t)ceil_div(n_max > 0 ? n_max : 1, kCompBlk);
-    bs.ensure(sizeof(int32_t) * (nb + 2));
+                   int32_t *out, int32_t *count_dev, int32_t *blocksum) {
+    const int32_t nb = compact_blocks(n_max);
+    int32_t *bsp = blocksum;
+    if (!bsp) {
+        c.ns.blocksum.ensure(sizeof(int32_t) * (nb + 2));
+        bsp = c.ns.blocksum.as<int32_t>();
+    } else if (!n_dev) {
+        throw Error{LSS_EHIP, "compact_flags: a caller workspace needs the count on the device"};
+    }
     const int32_t *nd = n_dev;
     if (!nd) {
-        int32_t *tmp = bs.as<int32_t>() + nb;
+        int32_t *tmp = bsp + nb;
         int32_t v = (int32_t)n_max;
         LSS_HIP(hipMemcpyAsync(tmp, &v, sizeof(int32_t), hipMemcpyHostToDevice, c.stream));
         LSS_HIP(hipStreamSynchronize(c.stream));
         nd = tmp;
     }
-    hipLaunchKernelGGL(k_block_count, dim3(nb), dim3(kCompBlk), 0, c.stream, nd, flag, bs.as<int32_t>());
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kCompBlk), 0, c.stream, nb, bs.as<int32_t>(), count_dev);
-    hipLaunchKernelGGL(k_block_scatter, dim3(nb), dim3(kCompBlk), 0, c.stream, nd, flag, bs.as<int32_t>(), in, out);
+    hipLaunchKernelGGL(k_block_count, dim3(nb), dim3(kCompBlk), 0, c.stream, nd, flag, bsp);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kCompBlk), 0, c.stream, nb, bsp, count_dev);
+    hipLaunchKernelGGL(k_block_scatter, dim3(nb), dim3(kCompBlk), 0, c.stream, nd, flag, bsp, in, out);
     LSS_CHECK_LAUNCH("compact_flags");
 }
 

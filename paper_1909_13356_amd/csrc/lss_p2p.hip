@@ -1097,9 +1097,8 @@ __global__ __launch_bounds__(64) void k_eval_fmm_mixed(FmmEvalArgs a) {
 
 template <int TILE>
 void launch_tile(Ctx &c, int64_t n, const int32_t *n_dev, const double *tx, const double *ty, const double *tz,
-                 const int32_t *tmesh, const int32_t *out_idx, double *phi, double *grad) {
+                 const int32_t *tmesh, const int32_t *out_idx, double *phi, double *grad, double *pairs) {
     dim3 grid((unsigned)ceil_div(n, TILE)), block(TILE);
-    double *pairs = c.pairs.as<double>();
     if (c.opt.precision == LSS_MIXED)
         hipLaunchKernelGGL(k_p2p_direct_mixed<TILE>, grid, block, 0, c.stream, n, n_dev, tx, ty, tz, tmesh,
                            c.node_off.as<int64_t>(), c.src.as<Src>(), out_idx, phi, grad, pairs);
@@ -1139,7 +1138,7 @@ int fmm_tile(const Ctx &c) {
 void launch_eval_fmm(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const int32_t *tile_start,
                      const int32_t *n_dev, int64_t n_max, const int32_t *sorted_leaf, const int32_t *sorted_idx,
                      const double *tx, const double *ty, const double *tz, const int32_t *out_idx, double *phi,
-                     double *grad, double *hess, const MsArgs *ms) {
+                     double *grad, const int32_t *order, double *pairs, double *hess, const MsArgs *ms) {
     const Tree &t = c.tree;
     FmmEvalArgs a;
     a.ntiles_dev = ntiles_dev;
@@ -1171,9 +1170,9 @@ void launch_eval_fmm(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const
     a.ncp = t.ncp;
     a.root = t.root.as<double>();
     a.bmesh = t.bmesh.as<int32_t>();
-    a.pairs = c.pairs.as<double>();
+    a.pairs = pairs;
     a.queue = c.tile_queue.as<unsigned int>();
-    a.order = c.tile_order.as<int32_t>();
+    a.order = order;
     a.child = t.child.as<int32_t>();
     a.parent = t.parent.as<int32_t>();
     a.rmax = t.rmax.as<double>();
@@ -1227,12 +1226,12 @@ void launch_eval_fmm(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const
 
 void launch_p2p_direct(Ctx &c, int64_t n, const int32_t *n_dev, const double *tx, const double *ty,
                        const double *tz, const int32_t *tmesh, const int32_t *out_idx, double *phi,
-                       double *grad, int /*grad_stride*/) {
+                       double *grad, int /*grad_stride*/, double *pairs) {
     if (n <= 0) return;
     switch (c.opt.tile) {
-        case 64: launch_tile<64>(c, n, n_dev, tx, ty, tz, tmesh, out_idx, phi, grad); break;
-        case 128: launch_tile<128>(c, n, n_dev, tx, ty, tz, tmesh, out_idx, phi, grad); break;
-        default: launch_tile<256>(c, n, n_dev, tx, ty, tz, tmesh, out_idx, phi, grad); break;
+        case 64: launch_tile<64>(c, n, n_dev, tx, ty, tz, tmesh, out_idx, phi, grad, pairs); break;
+        case 128: launch_tile<128>(c, n, n_dev, tx, ty, tz, tmesh, out_idx, phi, grad, pairs); break;
+        default: launch_tile<256>(c, n, n_dev, tx, ty, tz, tmesh, out_idx, phi, grad, pairs); break;
     }
 }
 

@@ -865,19 +865,17 @@ void launch_locate_targets(Ctx &c, int64_t n_max, const int32_t *n_dev, const do
 // leaf of every sorted target, tile starts over the sorted list and their
 // count on the device
 int64_t build_tiles(Ctx &c, int64_t n_max, const int32_t *n_dev, const uint64_t *sorted_keys, int tile,
-                    int32_t *sorted_leaf, int32_t *tile_start, int32_t *ntiles_dev) {
+                    int32_t *sorted_leaf, int32_t *tile_start, int32_t *ntiles_dev, int32_t *flag, int32_t *pos,
+                    int32_t *blocksum) {
     Tree &t = c.tree;
-    DBuf &fl = c.tflag, &pos = c.tpos;
-    fl.ensure(4 * (n_max + 1));
-    pos.ensure(4 * (n_max + 1));
     hipLaunchKernelGGL(k_sorted_leaf, dim3(grid_for(n_max)), dim3(kBlk), 0, c.stream, n_max, n_dev, sorted_keys,
                        t.bits, t.child.as<int32_t>(), (int32_t)t.nboxes, sorted_leaf);
     LSS_CHECK_LAUNCH("k_sorted_leaf");
     hipLaunchKernelGGL(k_tile_flags, dim3(grid_for(n_max)), dim3(kBlk), 0, c.stream, n_max, n_dev, sorted_keys,
                        sorted_leaf, t.level.as<int32_t>(), t.ijk.as<int32_t>(), t.bmesh.as<int32_t>(), t.bits,
-                       (int32_t)t.nboxes, tile, fl.as<int32_t>(), pos.as<int32_t>());
+                       (int32_t)t.nboxes, tile, flag, pos);
     LSS_CHECK_LAUNCH("k_tile_flags");
-    compact_flags(c, n_max, nullptr, fl.as<int32_t>(), pos.as<int32_t>(), tile_start, ntiles_dev);
+    compact_flags(c, n_max, n_dev, flag, pos, tile_start, ntiles_dev, blocksum);
     return n_max;
 }
 
@@ -887,14 +885,14 @@ int64_t build_tiles(Ctx &c, int64_t n_max, const int32_t *n_dev, const uint64_t 
 // No sort, no host synchronisation, no allocation: safe under stream capture
 // once the buffers have been sized by ensure_tiles.
 void order_tiles(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const int32_t *tile_start,
-                 const int32_t *leaf) {
+                 const int32_t *leaf, int32_t *order) {
     Tree &t = c.tree;
     const unsigned g = grid_for(max_tiles) < 2048u ? grid_for(max_tiles) : 2048u;
     hipLaunchKernelGGL(k_tile_bucket_count, dim3(g), dim3(kBlk), 0, c.stream, max_tiles, ntiles_dev, tile_start, leaf,
                        t.near_cnt.as<int64_t>(), c.tile_bucket.as<int32_t>());
     hipLaunchKernelGGL(k_tile_bucket_scan, dim3(1), dim3(64), 0, c.stream, c.tile_bucket.as<int32_t>());
     hipLaunchKernelGGL(k_tile_bucket_scatter, dim3(g), dim3(kBlk), 0, c.stream, max_tiles, ntiles_dev, tile_start,
-                       leaf, t.near_cnt.as<int64_t>(), c.tile_bucket.as<int32_t>(), c.tile_order.as<int32_t>());
+                       leaf, t.near_cnt.as<int64_t>(), c.tile_bucket.as<int32_t>(), order);
     LSS_CHECK_LAUNCH("order_tiles");
 }
 
