@@ -488,9 +488,12 @@ def main():
         del cfg
         c3 = configs.config3()
         nn = len(c3["tris"]) * len(c3["chart_uv"])
-        newton = {"workload": "graded bumpy surface (%d tri, %d nodes), sigma_j = D_j/2, %d chart nodes "
-                              "(45 per triangle), Newton onto Phi = 1/2, octree + FMM" % (
-                                  len(c3["tris"]), 12 * len(c3["tris"]), nn)}
+        from workloads import triangle_diameters
+        dd = triangle_diameters(c3["verts"], c3["tris"])
+        newton = {"workload": "graded multiscale torus R=1 r=0.3 with 200 bumps (%d tri, %d nodes, triangle "
+                              "diameters graded %.0fx), sigma_j = D_j/2, %d chart nodes (45 per triangle), "
+                              "Newton onto Phi = 1/2, octree + FMM" % (
+                                  len(c3["tris"]), 12 * len(c3["tris"]), dd.max() / dd.min(), nn)}
         for prec, name in ((lss.FP64, "f64"), (lss.MIXED, "mixed")):
             log("bench: Newton", name)
             newton[name] = time_newton(lss, torch, c3, prec, max(1, min(args.steps, 3)), 1)

@@ -57,6 +57,22 @@ __global__ void k_sigma_set(int64_t ntris, const double *__restrict__ in, int64_
     atomicMax(&stat[2], b);
 }
 
+// triangle centroids as points (n,3) with their mesh ids, for sigma(x) there
+__global__ void k_cen_points(int64_t ntris, const Cen *__restrict__ cen, const int64_t *__restrict__ tri_off,
+                             int32_t nmesh, double *x, int32_t *xm) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ntris) return;
+    x[3 * j] = cen[j].cx;
+    x[3 * j + 1] = cen[j].cy;
+    x[3 * j + 2] = cen[j].cz;
+    int32_t lo = 0, hi = nmesh;                  // mesh m with tri_off[m] <= j < tri_off[m + 1]
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (tri_off[mid] <= j) lo = mid; else hi = mid;
+    }
+    xm[j] = lo;
+}
+
 __global__ void k_check_mesh_ids(int64_t n, const int32_t *__restrict__ xm, int32_t nmesh, unsigned long long *bad) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n && (xm[i] < 0 || xm[i] >= nmesh)) atomicAdd(bad, 1ull);
@@ -572,20 +588,31 @@ void eval_multiscale(Ctx &c, double lambda, double sigma0, const double *x, cons
         if (nb) fail(LSS_EINVAL, "lss_eval_multiscale: x_mesh values outside [0, nmesh)");
     }
     if (c.opt.far_field == LSS_FAR_FMM) {
-        // sigma(x) and grad sigma, then the tree of the cut widths sigma_cut =
-        // the mesh's largest sigma_j (>= sigma(x) everywhere: a convex
-        // combination), built in place of the caller's sigma, which is put
-        // back afterwards (the built state is then stale and rebuilt on use)
-        DBuf tsig, tgs, dscut, saved;
+        // sigma(x) and grad sigma at the targets; sigma at the centroids sizes
+        // the leaves (built in place of the caller's sigma, which is put back
+        // afterwards: the built state is then stale and rebuilt on use); the
+        // lists are built for these targets, with cut * sigma(x) as the
+        // radius every far interaction must clear
+        DBuf tsig, tgs, cpt, cxm, csig, cgs, saved;
         tsig.ensure(sizeof(double) * n);
         tgs.ensure(sizeof(double) * 3 * n);
         launch_sigma_field(c, n, dx, dxm, cen.as<Cen>(), cbox.as<double>(), s0.as<double>(), tsig.as<double>(),
                            tgs.as<double>());
-        std::vector<double> smax(c.nmesh, 0.0), scut(c.ntris);
-        for (int32_t m = 0; m < c.nmesh; ++m)
-            for (int64_t j = c.h_tri_off[m]; j < c.h_tri_off[m + 1]; ++j) smax[m] = std::max(smax[m], hD[j] / lambda);
-        for (int32_t m = 0; m < c.nmesh; ++m)
-            for (int64_t j = c.h_tri_off[m]; j < c.h_tri_off[m + 1]; ++j) scut[j] = smax[m];
+        cpt.ensure(sizeof(double) * 3 * c.ntris);
+        cxm.ensure(sizeof(int32_t) * c.ntris);
+        csig.ensure(sizeof(double) * c.ntris);
+        cgs.ensure(sizeof(double) * 3 * c.ntris);
+        hipLaunchKernelGGL(k_cen_points, dim3(grid_for(c.ntris)), dim3(256), 0, c.stream, c.ntris, cen.as<Cen>(),
+                           c.tri_off.as<int64_t>(), c.nmesh, cpt.as<double>(), cxm.as<int32_t>());
+        LSS_CHECK_LAUNCH("k_cen_points");
+        launch_sigma_field(c, c.ntris, cpt.as<double>(), c.nmesh > 1 ? cxm.as<int32_t>() : nullptr, cen.as<Cen>(),
+                           cbox.as<double>(), s0.as<double>(), csig.as<double>(), cgs.as<double>());
+        std::vector<double> hcs(c.ntris);
+        LSS_HIP(hipMemcpyAsync(hcs.data(), csig.p, sizeof(double) * c.ntris, hipMemcpyDeviceToHost, c.stream));
+        LSS_HIP(hipStreamSynchronize(c.stream));
+        double mn = INFINITY, mx = 0.0;
+        for (double v : hcs) { mn = std::min(mn, v); mx = std::max(mx, v); }
+        if (!(mn > 0.0) || !std::isfinite(mx)) fail(LSS_EINVAL, "lss_eval_multiscale: sigma at a centroid is not positive");
         struct Restore {
             Ctx &c;
             DBuf &saved;
@@ -599,27 +626,28 @@ void eval_multiscale(Ctx &c, double lambda, double sigma0, const double *x, cons
                 c.sigma_min = lo;
                 c.sigma_max = hi;
                 c.built = false;
+                c.target_widths = nullptr;
             }
         } restore{c, saved, c.have_sigma, c.sigma_min, c.sigma_max};
         if (c.have_sigma) {
             saved.ensure(sizeof(double) * c.ntris);
             LSS_HIP(hipMemcpyAsync(saved.p, c.sigma.p, sizeof(double) * c.ntris, hipMemcpyDeviceToDevice, c.stream));
         }
-        upload(c, c.sigma, scut.data(), sizeof(double) * c.ntris, 0);
-        double mn = INFINITY, mx = 0.0;
-        for (int32_t m = 0; m < c.nmesh; ++m)
-            if (c.h_tri_off[m + 1] > c.h_tri_off[m]) { mn = std::min(mn, smax[m]); mx = std::max(mx, smax[m]); }
+        c.sigma.ensure(sizeof(double) * c.ntris);
+        LSS_HIP(hipMemcpyAsync(c.sigma.p, csig.p, sizeof(double) * c.ntris, hipMemcpyDeviceToDevice, c.stream));
         c.have_sigma = true;
         c.sigma_min = mn;
         c.sigma_max = mx;
         c.built = false;
+        const TargetWidths tw{dx, dxm, tsig.as<double>(), n};
+        c.target_widths = &tw;
         build(c);
-        upload(c, dscut, smax.data(), sizeof(double) * c.nmesh, 0);
+        c.target_widths = nullptr;
         const EvalBufs b = eval_bufs_ctx(c, n);
         c.ev_reset();
         launch_soa(c, dx, n, b.tx, b.ty, b.tz);
         if (dxm) LSS_HIP(hipMemcpyAsync(b.tmesh, dxm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c.stream));
-        const MsArgs ms{tsig.as<double>(), tgs.as<double>(), dscut.as<double>()};
+        const MsArgs ms{tsig.as<double>(), tgs.as<double>()};
         eval_fmm_bufs(c, b, n, dphi, dgrad, nullptr, &ms);
         if (dsig) LSS_HIP(hipMemcpyAsync(dsig, tsig.p, sizeof(double) * n, hipMemcpyDeviceToDevice, c.stream));
         LSS_HIP(hipStreamSynchronize(c.stream));

@@ -92,10 +92,21 @@ struct Cen {
 };
 
 // Target-attached width through the tree: sigma(x) and grad sigma per target
-// (original order) and the cut width of each mesh's tree.
+// (original order).
 struct MsArgs {
     const double *sig, *gsig;
-    const double *scut;
+};
+
+// Targets whose own widths set the near/far split of the lists (target-
+// attached sigma): AoS positions x (n,3), mesh ids (null: one mesh) and
+// sigma(x).  While a context holds one, build_tree makes a box admissible for
+// M2L / M2P when its gap to the source box is at least cut * sigma(x) for
+// every target in it, instead of the source nodes' cut radii.
+struct TargetWidths {
+    const double *x;
+    const int32_t *xm;
+    const double *sig;
+    int64_t n;
 };
 
 // FP32 staging record of the mixed path: position relative to a tile origin
@@ -196,6 +207,8 @@ struct Tree {
     int ops_p = -1, ops_R = -1;
     // frontier scratch
     DBuf fr, fr2, cnt;
+    // target-side cut radius per box (built with Ctx::target_widths)
+    DBuf tcut;
 };
 
 struct Ctx {
@@ -228,6 +241,7 @@ struct Ctx {
     double bbox_lo[3] = {0, 0, 0}, bbox_hi[3] = {0, 0, 0};
 
     Tree tree;
+    const TargetWidths *target_widths = nullptr;   // set by lss_eval_multiscale around its build
 
     // --- per-eval scratch
     DBuf tkey, tkey2, tperm, tperm2, tx, ty, tz, tmesh, sort_tmp;

@@ -804,25 +804,21 @@ __global__ __launch_bounds__(256) void k_hess_outside(FmmEvalArgs a, double *hes
 
 // ------------------------------------------------ target-attached width
 // Phi and grad Phi with sigma(x) (section 2, eq. basemodelk, sigma2) through
-// a tree whose cut radii come from the mesh's largest sigma_j, which bounds
-// sigma(x) everywhere (a convex combination of the sigma_j): every pair within
+// a tree whose lists were built for these targets: a box is admissible when
+// its gap clears cut * sigma(x) of every target in it, so every pair within
 // the cut of sigma(x) is in a near list.  Near pairs use the target's width
-// (pair_ms) and are scaled by c(sigma(x)) / c(sigma_cut) = (sigma_cut /
-// sigma(x))^3; the far field (Laplace double layer) does not depend on the
-// width.  grad Phi gains (dPhi/dsigma) grad sigma, dPhi/dsigma = (2 c(x) /
-// sigma(x)) sum (a.d) exp(-t) over the near pairs (beyond the cut exp(-t) is
-// below the cut's truncation).  FP64.
-__device__ __forceinline__ void ms_finish(double sx, double sc, const MsAcc &A, const double *gs, double &ph,
-                                          double g[3]) {
-    // with a = a'/c(cut) and f = c(x)/c(cut) = (sigma_cut/sigma(x))^3:
-    // Phi = -f sum (a'.d) k1, grad = -f sum (a' k1 + (a'.d) k2 d),
-    // dPhi/dsigma = (2 c(x)/sigma(x)) sum (a.d) e^-t = (2 f/sigma(x)) sum (a'.d) e^-t
-    const double r = sc / sx, f = r * r * r;
-    const double dps = 2.0 * f * A.e / sx;
-    ph -= f * A.f;
-    g[0] += -f * A.gx + dps * gs[0];
-    g[1] += -f * A.gy + dps * gs[1];
-    g[2] += -f * A.gz + dps * gs[2];
+// (pair_ms, which carries c(sigma(x)) a); the far field (Laplace double
+// layer) does not depend on the width.  grad Phi gains (dPhi/dsigma) grad
+// sigma, dPhi/dsigma = (2 c(x) / sigma(x)) sum (a.d) exp(-t) over the near
+// pairs (beyond the cut exp(-t) is below the cut's truncation).  FP64.
+__device__ __forceinline__ void ms_finish(double sx, const MsAcc &A, const double *gs, double &ph, double g[3]) {
+    // Phi = -sum (c(x) a.d) k1, grad = -sum (c(x) a k1 + (c(x) a.d) k2 d),
+    // dPhi/dsigma = (2 / sigma(x)) sum (c(x) a.d) e^-t
+    const double dps = 2.0 * A.e / sx;
+    ph -= A.f;
+    g[0] += -A.gx + dps * gs[0];
+    g[1] += -A.gy + dps * gs[1];
+    g[2] += -A.gz + dps * gs[2];
 }
 
 template <int TILE>
@@ -869,7 +865,7 @@ __global__ __launch_bounds__(TILE) void k_multiscale_fmm(FmmEvalArgs a, MsArgs m
         }
         __syncthreads();
         if (valid) {
-            ms_finish(sx, ms.scut[a.bmesh[B]], A, ms.gsig + 3 * ti, ph, g);
+            ms_finish(sx, A, ms.gsig + 3 * ti, ph, g);
             const int64_t o = a.out_idx ? (int64_t)a.out_idx[ti] : ti;
             a.phi[o] = ph;
             if (a.grad) {
@@ -894,7 +890,7 @@ __global__ __launch_bounds__(256) void k_multiscale_outside(FmmEvalArgs a, MsArg
         MsAcc A;
         for (int64_t k = a.nb[m]; k < a.ne[m]; ++k) pair_ms(a.src[k], x, y, z, s2x, A);
         double ph = 0.0, g[3] = {0.0, 0.0, 0.0};
-        ms_finish(sx, ms.scut[m], A, ms.gsig + 3 * ti, ph, g);
+        ms_finish(sx, A, ms.gsig + 3 * ti, ph, g);
         const int64_t o = a.out_idx ? (int64_t)a.out_idx[ti] : ti;
         a.phi[o] = ph;
         if (a.grad) {

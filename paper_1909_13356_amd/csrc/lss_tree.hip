@@ -240,7 +240,14 @@ struct DttArgs {
     const double *root;
     const int32_t *bmesh;
     int K;
+    const double *tcut;     // target-side cut radius per box, or null (source radii rmax)
 };
+
+// cut radius an interaction (T, S) must clear: the largest cut radius of the
+// targets in T when the targets carry their own widths, else of S's nodes
+__device__ inline double dtt_cut(const DttArgs &a, int32_t T, int32_t S) {
+    return a.tcut ? a.tcut[T] : a.rmax[S];
+}
 
 __device__ inline bool is_empty(const DttArgs &a, int32_t S) { return a.ne[S] == a.nb[S]; }
 
@@ -271,7 +278,8 @@ __device__ inline bool m2p_ok(const DttArgs &a, int32_t T, int32_t S) {
         dc += e * e;
         gap += g * g;
     }
-    return dc >= (double)a.K * hs * hs && gap >= a.rmax[S] * a.rmax[S];
+    const double r = dtt_cut(a, T, S);
+    return dc >= (double)a.K * hs * hs && gap >= r * r;
 }
 
 __device__ inline int64_t box_nodes(const DttArgs &a, int32_t b) { return a.ne[b] - a.nb[b]; }
@@ -286,7 +294,7 @@ __device__ inline int dtt_action(const DttArgs &a, int32_t T, int32_t S, int &cl
         int m = max(abs(dx), max(abs(dy), abs(dz)));
         // admissible: K-criterion and a gap of at least the cut radius of S's nodes
         if (m >= 2 && dx * dx + dy * dy + dz * dz >= a.K && m <= kR &&
-            (double)(m - 1) * box_side(a.root, a.bmesh, S, lT) >= a.rmax[S]) {
+            (double)(m - 1) * box_side(a.root, a.bmesh, S, lT) >= dtt_cut(a, T, S)) {
             cls = ((dx + kR) * (2 * kR + 1) + (dy + kR)) * (2 * kR + 1) + (dz + kR);
             return A_M2L;
         }
@@ -472,6 +480,33 @@ __global__ void k_leaf_direct(int64_t n_max, const int32_t *__restrict__ n_dev, 
     bool inside;
     const uint64_t k = point_key(tx[i], ty[i], tz[i], m, root, bits, inside);
     leaf[i] = inside ? descend(k, m, bits, child) : nboxes + m;
+}
+
+// Target-side cut radii (targets with their own widths): cut * sigma(x) of
+// each target folded into its leaf by an atomic max on the bits of the
+// (positive) double, then into every ancestor, level by level.
+__global__ void k_tcut_scatter(int64_t n, const double *__restrict__ x, const int32_t *__restrict__ xm,
+                               const double *__restrict__ sig, double cut, const double *__restrict__ root, int bits,
+                               const int32_t *__restrict__ child, unsigned long long *tbits) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t m = xm ? xm[i] : 0;
+    bool inside;
+    const uint64_t k = point_key(x[3 * i], x[3 * i + 1], x[3 * i + 2], m, root, bits, inside);
+    const double r = cut * sig[i];
+    if (!inside || !(r > 0.0)) return;      // outside the root cube: summed directly
+    atomicMax(&tbits[descend(k, m, bits, child)], (unsigned long long)__double_as_longlong(r));
+}
+
+__global__ void k_tcut_up(int64_t lb, int64_t nl, const int32_t *__restrict__ child, double *tcut) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nl) return;
+    const int64_t b = lb + i;
+    const int32_t c0 = child[b];
+    if (c0 < 0) return;
+    double r = tcut[b];
+    for (int k = 0; k < 8; ++k) r = fmax(r, tcut[c0 + k]);
+    tcut[b] = r;
 }
 
 __global__ void k_tile_flags_runs(int64_t n_max, const int32_t *__restrict__ n_dev, const int32_t *__restrict__ leaf,
@@ -747,9 +782,27 @@ void build_tree(Ctx &c) {
         t.level_begin.push_back(le + 8 * (int64_t)ns);
     }
     t.nboxes = t.level_begin.back();
+    // targets with their own widths: the cut radius of each box's targets
+    const double *tcut = nullptr;
+    if (c.target_widths && c.target_widths->n > 0) {
+        const TargetWidths &tw = *c.target_widths;
+        t.tcut.ensure(sizeof(double) * t.nboxes);
+        LSS_HIP(hipMemsetAsync(t.tcut.p, 0, sizeof(double) * t.nboxes, c.stream));
+        hipLaunchKernelGGL(k_tcut_scatter, dim3(grid_for(tw.n)), dim3(kBlk), 0, c.stream, tw.n, tw.x,
+                           nm > 1 ? tw.xm : nullptr, tw.sig, cut, t.root.as<double>(), t.bits,
+                           t.child.as<int32_t>(), reinterpret_cast<unsigned long long *>(t.tcut.p));
+        LSS_CHECK_LAUNCH("k_tcut_scatter");
+        for (int l = t.depth - 1; l >= 0; --l) {
+            const int64_t lb = t.level_begin[l], nl = t.level_begin[l + 1] - lb;
+            hipLaunchKernelGGL(k_tcut_up, dim3(grid_for(nl)), dim3(kBlk), 0, c.stream, lb, nl, t.child.as<int32_t>(),
+                               t.tcut.as<double>());
+        }
+        LSS_CHECK_LAUNCH("k_tcut_up");
+        tcut = t.tcut.as<double>();
+    }
     // ---------------------------------------------------- dual traversal
     DttArgs a{t.level.as<int32_t>(), t.ijk.as<int32_t>(), t.child.as<int32_t>(), t.nb.as<int64_t>(),
-              t.ne.as<int64_t>(), t.rmax.as<double>(), t.root.as<double>(), t.bmesh.as<int32_t>(), t.K};
+              t.ne.as<int64_t>(), t.rmax.as<double>(), t.root.as<double>(), t.bmesh.as<int32_t>(), t.K, tcut};
     t.cnt.ensure(8 * 8);
     int64_t nfr = nm;                       // (root m, root m) pairs written by k_level0
     t.n_m2l = 0;

@@ -93,8 +93,10 @@ __device__ inline void pair_hess(const Src &s, double px, double py, double pz, 
 }
 
 // Phi, grad Phi and dPhi/dsigma-sum with a target-attached width: the node
-// record's a' carries the normalisation of its own (cut) width, the target's
-// s2x = 1/(2 sigma(x)^2) sets the kernel; the caller scales by c(x)/c(node).
+// record's a' carries the normalisation c(sigma_k) of its own width (s2 =
+// 1/(2 sigma_k^2)), the target's s2x = 1/(2 sigma(x)^2) sets the kernel, and
+// each pair is rescaled by c(sigma(x)) / c(sigma_k) = (s2x / s2)^(3/2), so the
+// sums carry c(sigma(x)) a.
 struct MsAcc {
     double f = 0.0, gx = 0.0, gy = 0.0, gz = 0.0, e = 0.0;
 };
@@ -104,12 +106,14 @@ __device__ inline void pair_ms(const Src &s, double px, double py, double pz, do
     const double t = (dx * dx + dy * dy + dz * dz) * s2x;
     double k1, k2, k3, et;
     radial3(t, s2x, k1, k2, k3, et);
-    const double ad = s.ax * dx + s.ay * dy + s.az * dz;
+    const double q = s2x / s.s2, fr = q * sqrt(q);
+    const double ax = fr * s.ax, ay = fr * s.ay, az = fr * s.az;
+    const double ad = ax * dx + ay * dy + az * dz;
     A.f += ad * k1;
     const double adk2 = ad * k2;
-    A.gx += s.ax * k1 + adk2 * dx;
-    A.gy += s.ay * k1 + adk2 * dy;
-    A.gz += s.az * k1 + adk2 * dz;
+    A.gx += ax * k1 + adk2 * dx;
+    A.gy += ay * k1 + adk2 * dy;
+    A.gz += az * k1 + adk2 * dz;
     A.e += ad * et;
 }
 

@@ -98,10 +98,12 @@ def test_multiscale_constant_diameter_is_the_constant_sigma_sum_and_device_tenso
 
 @pytest.mark.parametrize("prec", [lss.FP64, lss.MIXED])
 def test_multiscale_through_the_octree(prec):
-    """sigma(x) through the tree: cut radii from the mesh's largest sigma_j,
-    near pairs at the target's width, far field from the expansions.  Bars
-    1e-12 (FP64 settings) and 1e-6 (mixed settings: cut sqrt(40) sigma_cut,
-    p = 20).  The context's own sigma and results are unchanged afterwards."""
+    """sigma(x) through the tree: leaves sized by sigma at the centroids,
+    lists built for these targets (a far interaction clears cut * sigma(x) of
+    every target in the box), near pairs at the target's width, far field
+    from the expansions.  Bars 1e-12 (FP64 settings) and 1e-6 (mixed
+    settings: cut sqrt(40) sigma(x), p = 20).  The context's own sigma and
+    results are unchanged afterwards."""
     v, t = star_surface(10, lmax=8, var0=0.1, seed=9)
     sig = 0.5 * triangle_diameters(v, t)
     x = np.concatenate([surface_offset_targets(v, t, sig, 6000, tmax=3.0, seed=10),
@@ -126,3 +128,32 @@ def test_multiscale_through_the_octree(prec):
     assert rel(p, pd) <= bar and rel(g, gd) <= bar
     p1, g1 = c.eval(x)
     assert np.array_equal(p1, p0) and np.array_equal(g1, g0)
+
+
+@pytest.mark.parametrize("sigma0", [0.0, 0.04])
+def test_multiscale_octree_on_a_graded_torus(sigma0):
+    """A torus whose triangle diameters vary about 30x, so sigma(x) varies
+    strongly from one region to the next (sigma0 = 0.04 makes it follow the
+    local triangles closely): the octree path against the every-pair path on
+    all targets and the oracle on a sample, FP64 settings."""
+    from workloads import graded_torus
+    v, t = graded_torus(n_tris=12000, seed=21)
+    sig = 0.5 * triangle_diameters(v, t)
+    x = np.concatenate([surface_offset_targets(v, t, sig, 8000, tmax=3.0, seed=22),
+                        box_targets(300, -1.5, 1.5, seed=23)])
+    say("case: multiscale through the octree, graded torus %d tri (diameters %.0fx), sigma0 %g, %d targets"
+        % (len(t), (2 * sig).max() / (2 * sig).min(), sigma0, len(x)))
+    c = ctx(v, t)
+    c.set_options(precision=lss.FP64, far_field=lss.FAR_FMM)
+    p, g, s = c.eval_multiscale(x, 2.5, sigma0)
+    st = c.stats()
+    say("  leaves %d m2l %d pairs/target %.0f" % (st["n_leaves"], st["n_m2l"], st["last_pairs"] / len(x)))
+    cd = ctx(v, t)
+    pd, gd, sd = cd.eval_multiscale(x, 2.5, sigma0)
+    e = rel(p, pd), rel(g, gd), rel(s, sd)
+    say("  vs every pair: e_phi %.2e e_grad %.2e e_sigma %.2e" % e)
+    assert max(e) <= 1e-12
+    po, go, so = oracle.evaluate_multiscale(v, t, dunavant6(), x[::40], 2.5, sigma0)
+    e = rel(p[::40], po), rel(g[::40], go), rel(s[::40], so)
+    say("  vs oracle: e_phi %.2e e_grad %.2e e_sigma %.2e" % e)
+    assert max(e) <= 1e-12

@@ -150,3 +150,30 @@ def test_torus_and_quadratic_generators():
     vs, ts = icosphere(1)
     vq, tq = quadratic_from_flat(vs, ts, lift=lambda p: p / np.linalg.norm(p, axis=1, keepdims=True))
     assert np.allclose(np.linalg.norm(vq, axis=1), 1.0) and np.array_equal(tq[:, :3], ts)
+
+
+def test_graded_torus_config3():
+    """The C3 skeleton: a closed, consistently outward torus (Euler
+    characteristic 0), enclosing about the plain torus's 2 pi^2 R r^2 (the
+    bumps add and remove little), about 2e5 triangles, triangle diameters
+    graded over at least 90x, no sliver (every angle > 20 degrees); seeded."""
+    c = configs.config3()
+    v, t = c["verts"], c["tris"]
+    closed, vol = mesh_check(v, t)
+    assert closed
+    assert abs(vol - 2 * np.pi ** 2 * 0.09) < 0.01
+    edges = {tuple(sorted(e)) for tri in t.tolist() for e in ((tri[0], tri[1]), (tri[1], tri[2]), (tri[2], tri[0]))}
+    assert len(v) - len(edges) + len(t) == 0
+    assert 1.8e5 <= len(t) <= 2.6e5
+    D = triangle_diameters(v, t)
+    assert D.max() / D.min() >= 90
+    assert np.allclose(c["sigma"], 0.5 * D) and c["chart_uv"].shape == (45, 2)
+    p = v[t]
+    ang = []
+    for k in range(3):
+        a, b = p[:, (k + 1) % 3] - p[:, k], p[:, (k + 2) % 3] - p[:, k]
+        ang.append(np.degrees(np.arccos(np.clip((a * b).sum(1) / np.linalg.norm(a, axis=1)
+                                                / np.linalg.norm(b, axis=1), -1, 1))))
+    assert np.min(ang) > 20.0
+    c2 = configs.config3()
+    assert np.array_equal(c2["verts"], v) and np.array_equal(c2["tris"], t)

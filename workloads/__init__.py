@@ -12,7 +12,7 @@ PCG64).
 """
 from .rules import dunavant6, chart_nodes_45, chart_nodes
 from .meshes import (cube_mesh, icosphere, geodesic_sphere, star_surface,
-                     bumpy_sphere, mesh_check, triangle_diameters,
+                     bumpy_sphere, graded_torus, mesh_check, triangle_diameters,
                      refine_1to4, refine_1to4_quadratic, torus_mesh, quadratic_from_flat)
 from .targets import (box_targets, shell_targets, surface_offset_targets,
                       bbox_targets)
@@ -20,7 +20,7 @@ from . import configs
 
 __all__ = [
     "dunavant6", "chart_nodes_45", "chart_nodes", "cube_mesh", "icosphere",
-    "geodesic_sphere", "star_surface", "bumpy_sphere", "mesh_check",
+    "geodesic_sphere", "star_surface", "bumpy_sphere", "graded_torus", "mesh_check",
     "triangle_diameters", "refine_1to4", "refine_1to4_quadratic", "torus_mesh", "quadratic_from_flat", "box_targets", "shell_targets",
     "surface_offset_targets", "bbox_targets", "configs",
 ]

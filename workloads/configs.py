@@ -11,11 +11,11 @@ workload.
       4096 targets uniform in [-0.5, 1.5]^3, seed 0.
 * C2  icosphere level 5 (20,480 triangles), sigma = 0.05, 1e6 targets with
       radius U[0.5, 1.5] and isotropic direction, seed 2.
-* C3  multiscale torus stand-in: a star-shaped bumpy surface graded 10x in
-      edge length (see ``bumpy_sphere``), ~2e5 triangles, sigma_j = 0.5 D_j,
-      45 order-8 chart nodes per triangle, seed 3.  (A torus generator with
-      100x grading is not provided; the graded sphere carries the same
-      per-triangle-sigma workload shape.)
+* C3  multiscale torus (R = 1, r = 0.3) with 200 Gaussian bumps (heights
+      log-uniform in [0.002, 0.05], widths in [0.01, 0.1]), triangulated
+      with triangle diameters graded about 110x (see ``graded_torus``),
+      ~2.3e5 triangles, sigma_j = 0.5 D_j, 45 order-8 chart nodes per
+      triangle (~1e7 Newton targets), seed 3.
 * C4  64 star-shaped surfaces, triangle counts log-uniform in [500, 50000]
       (geodesic 20 nu^2), sigma_j = 0.5 D_j, 1e4 targets per surface in the
       25 %-padded bounding box, seed 4.
@@ -26,7 +26,7 @@ workload.
 import numpy as np
 
 from .rules import dunavant6, chart_nodes_45
-from .meshes import (cube_mesh, icosphere, star_surface, bumpy_sphere,
+from .meshes import (cube_mesh, icosphere, star_surface, bumpy_sphere, graded_torus,
                      triangle_diameters)
 from .targets import (box_targets, shell_targets, bbox_targets,
                       surface_offset_targets)
@@ -46,11 +46,11 @@ def config2(n_targets=1_000_000, level=5):
                 targets=shell_targets(n_targets, 0.5, 1.5, seed=2))
 
 
-def config3(nu=100, n_charts=None, seed=3):
-    v, t = bumpy_sphere(nu, grade=np.sqrt(10.0), lmax=16, amp=0.05, nbumps=200,
-                        seed=seed, height=(2e-3, 5e-2), width=(1e-2, 0.1))
+def config3(n_tris=200_000, seed=3):
+    v, t = graded_torus(n_tris=n_tris, R=1.0, r=0.3, nbumps=200, seed=seed, height=(2e-3, 5e-2),
+                        width=(1e-2, 0.1))
     sig = 0.5 * triangle_diameters(v, t)
-    return dict(name="graded-bumpy-%dtri" % len(t), verts=v, tris=t, sigma=sig,
+    return dict(name="graded-torus-%dtri" % len(t), verts=v, tris=t, sigma=sig,
                 rule=dunavant6(), chart_uv=chart_nodes_45(), targets=None)
 
 
@@ -88,9 +88,16 @@ def concat_batch(meshes):
                 target_mesh=np.concatenate(xm) if xm else None)
 
 
-def config5(nu=316, n_targets=50_000_000, seed=5, lmax=64, nbumps=2000):
+def config5(nu=316, n_targets=50_000_000, seed=5, lmax=64, nbumps=2000, meta=False):
+    """meta: also return, per target, the triangle it was drawn on
+    (``target_tri``) and its normal offset in units of that triangle's sigma
+    (``target_t``), for stratified samples; the targets are the same."""
     v, t = bumpy_sphere(nu, grade=10.0, lmax=lmax, amp=0.05, nbumps=nbumps, seed=seed)
     sig = 0.5 * triangle_diameters(v, t)
-    x = surface_offset_targets(v, t, sig, n_targets, tmax=3.0, seed=seed + 1000)
-    return dict(name="graded-bumpy-sphere-%dtri" % len(t), verts=v, tris=t, sigma=sig,
-                rule=dunavant6(), targets=x)
+    out = surface_offset_targets(v, t, sig, n_targets, tmax=3.0, seed=seed + 1000, meta=meta)
+    cfg = dict(name="graded-bumpy-sphere-%dtri" % len(t), verts=v, tris=t, sigma=sig, rule=dunavant6())
+    if meta:
+        cfg["targets"], cfg["target_tri"], cfg["target_t"] = out
+    else:
+        cfg["targets"] = out
+    return cfg

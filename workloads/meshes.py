@@ -420,3 +420,172 @@ def triangle_diameters(verts, tris):
     area2 = np.linalg.norm(np.cross(p1 - p0, p2 - p0), axis=1)   # 2 * area
     circ_d = np.sqrt(a2 * b2 * c2) / np.maximum(area2, 1e-300)   # 2R = abc / (2 area)
     return np.where(obtuse, np.sqrt(lmax2), circ_d)
+
+
+# ------------------------------------------------------- graded torus (C3)
+def _torus_p_of_v(v, R, r):
+    """Inverse of the conformal tube coordinate v(p) = int_0^p r / (R + r cos q) dq
+    of a torus: p in [0, 2 pi) for v in [0, V), V = 2 pi r / sqrt(R^2 - r^2)."""
+    k = np.sqrt(R * R - r * r) / (2.0 * r)
+    phi = v * k
+    return np.mod(2.0 * np.arctan2(np.sqrt((R + r) / (R - r)) * np.sin(phi), np.cos(phi)), 2.0 * np.pi)
+
+
+def _torus_point(t, p, R, r):
+    rho = R + r * np.cos(p)
+    return np.stack([rho * np.cos(t), rho * np.sin(t), r * np.sin(p)], axis=-1)
+
+
+def graded_torus(n_tris=200_000, R=1.0, r=0.3, nbumps=200, seed=3, height=(2e-3, 5e-2), width=(1e-2, 0.1),
+                 h_range=100.0, grade_rate=1.0, size_power=2.0, slope=0.3, tries=4):
+    """Multiscale torus: a torus (R, r) carrying ``nbumps`` Gaussian bumps,
+    triangulated with edge lengths graded over a ``h_range`` ratio.
+
+    Bumps: centres uniform by area on the torus, widths and heights
+    log-uniform in ``width`` / ``height`` (heights capped at ``slope`` x width),
+    random sign, displacement along the torus normal with a Gaussian of the
+    3D chord distance.  Size field: h(x) = c w_b (w_b / w_max)^(size_power - 1)
+    inside 3 w_b of bump b (finer, relative to its width, for a narrower bump:
+    with size_power 2 the tenfold width range spans a hundredfold size
+    range), growing by ``grade_rate`` per unit distance beyond, the smallest
+    over the bumps, clamped to [h_min, h_range h_min] (h_min the size at the
+    narrowest bump), with c chosen so that the mesh has about ``n_tris``
+    triangles.
+
+    Triangulation: conformal coordinates (u, v) = (t, int r dp / (R + r cos p))
+    make the torus a flat 2 pi x V rectangle with metric
+    (R + r cos p)^2 (du^2 + dv^2); a 2:1-balanced periodic quadtree is refined
+    until every cell's diagonal (in 3D) is at most h at its centre, and the
+    jittered cell corners are triangulated by a periodic Delaunay
+    triangulation in (u, v), which is angle-preserving up to the bumps.
+    Returns verts (n, 3), tris (m, 3) int32, outward (counter-clockwise in
+    (t, p))."""
+    from scipy.spatial import Delaunay, cKDTree
+    rng = np.random.default_rng(seed)
+    # bumps: t uniform, p with density (R + r cos p) / (2 pi R) by rejection
+    tb = rng.uniform(0.0, 2.0 * np.pi, nbumps)
+    pb = np.empty(nbumps)
+    k = 0
+    while k < nbumps:
+        p = rng.uniform(0.0, 2.0 * np.pi, 4 * nbumps)
+        acc = p[rng.uniform(0.0, R + r, p.size) < R + r * np.cos(p)]
+        take = min(acc.size, nbumps - k)
+        pb[k:k + take] = acc[:take]
+        k += take
+    wb = np.exp(rng.uniform(np.log(width[0]), np.log(width[1]), nbumps))
+    hb = np.minimum(np.exp(rng.uniform(np.log(height[0]), np.log(height[1]), nbumps)), slope * wb)
+    sb = rng.choice([-1.0, 1.0], nbumps)
+    cb = _torus_point(tb, pb, R, r)
+    tree_b = cKDTree(cb)
+    kb = min(32, nbumps)
+    U, V = 2.0 * np.pi, 2.0 * np.pi * r / np.sqrt(R * R - r * r)
+    nv0 = 6
+    nu0 = int(round(U / V * nv0))
+    du0, dv0 = U / nu0, V / nv0
+    wfine = wb * (wb / wb.max()) ** (size_power - 1.0)     # bump size in units of c
+    wmin = wfine.min()
+
+    def size_at(uv, c):
+        t, p = uv[:, 0], _torus_p_of_v(uv[:, 1], R, r)
+        x = _torus_point(t, p, R, r)
+        d, nb = tree_b.query(x, k=kb)                 # the nearest bumps decide the minimum
+        hb_i = c * wfine[nb] + grade_rate * np.maximum(0.0, d - 3.0 * wb[nb])
+        h = np.minimum(h_range * c * wmin, hb_i.min(axis=1))
+        return np.maximum(h, c * wmin), (R + r * np.cos(p))
+
+    def quadtree(c):
+        # leaves per level: lv[l] = {(i, j)}, level-l cells du0 / 2^l x dv0 / 2^l
+        lv = [{(i, j) for i in range(nu0) for j in range(nv0)}]
+        level = 0
+        while level < len(lv) and lv[level]:
+            arr = np.array(sorted(lv[level]), dtype=np.int64)
+            sc = 0.5 ** level
+            uv = np.stack([(arr[:, 0] + 0.5) * du0 * sc, (arr[:, 1] + 0.5) * dv0 * sc], 1)
+            h, lam = size_at(uv, c)
+            split = arr[lam * np.hypot(du0, dv0) * sc > h]
+            if len(split):
+                if len(lv) == level + 1:
+                    lv.append(set())
+                lv[level].difference_update(map(tuple, split.tolist()))
+                ch = (2 * split[:, None, :] + np.array([[0, 0], [0, 1], [1, 0], [1, 1]])[None]).reshape(-1, 2)
+                lv[level + 1].update(map(tuple, ch.tolist()))
+            level += 1
+        # 2:1 balance across edges and corners (periodic): every leaf of level
+        # m >= 2 sees leaves of level >= m - 1 around its parent
+        for m in range(len(lv) - 1, 1, -1):
+            par = {(i >> 1, j >> 1) for (i, j) in lv[m]}
+            l = m - 1
+            nl_u, nl_v = nu0 << l, nv0 << l
+            nbr = {((pi + a) % nl_u, (pj + b) % nl_v) for (pi, pj) in par for a in (-1, 0, 1) for b in (-1, 0, 1)}
+            for (i, j) in nbr - par:
+                _ensure_level(lv, l, i, j)
+        return lv
+
+    c = 2.6 * np.sqrt(200_000 / n_tris)        # about right for the defaults; refined below
+    for _ in range(tries):
+        lv = quadtree(c)
+        est = 2.0 * sum(len(q) for q in lv)
+        if abs(est / n_tris - 1.0) < 0.1:
+            break
+        c *= np.sqrt(est / n_tris)
+    leaves = {(l, i, j) for l, q in enumerate(lv) for (i, j) in q}
+    maxl = max(q[0] for q in leaves)
+    NU, NV = nu0 << maxl, nv0 << maxl
+    pts = set()
+    for (l, i, j) in leaves:
+        f = 1 << (maxl - l)
+        for a in (0, 1):
+            for b in (0, 1):
+                pts.add((((i + a) * f) % NU, ((j + b) * f) % NV))
+    pts = np.array(sorted(pts), dtype=np.int64)
+    uv = np.stack([pts[:, 0] * (U / NU), pts[:, 1] * (V / NV)], 1)
+    uv += rng.normal(0.0, 1e-4 * min(U / NU, V / NV), uv.shape)     # no cocircular quadruples
+    n = len(uv)
+    # periodic Delaunay: the points plus their images within a margin
+    m = 3.0 * max(du0, dv0)
+    ext, ids = [uv], [np.arange(n)]
+    for a in (-1, 0, 1):
+        for b in (-1, 0, 1):
+            if a == 0 and b == 0:
+                continue
+            q = uv + np.array([a * U, b * V])
+            sel = (q[:, 0] > -m) & (q[:, 0] < U + m) & (q[:, 1] > -m) & (q[:, 1] < V + m)
+            ext.append(q[sel])
+            ids.append(np.nonzero(sel)[0])
+    ext, ids = np.concatenate(ext), np.concatenate(ids)
+    tri = Delaunay(ext).simplices
+    cen = ext[tri].mean(axis=1)
+    eps = 1e-9
+    keep = (cen[:, 0] >= eps) & (cen[:, 0] < U + eps) & (cen[:, 1] >= eps) & (cen[:, 1] < V + eps)
+    tri = tri[keep]
+    p0, p1, p2 = ext[tri[:, 0]], ext[tri[:, 1]], ext[tri[:, 2]]
+    cr = (p1[:, 0] - p0[:, 0]) * (p2[:, 1] - p0[:, 1]) - (p1[:, 1] - p0[:, 1]) * (p2[:, 0] - p0[:, 0])
+    tris = ids[tri]
+    flip = cr < 0
+    tris[flip] = tris[flip][:, [0, 2, 1]]
+    t = uv[:, 0]
+    p = _torus_p_of_v(uv[:, 1], R, r)
+    x = _torus_point(t, p, R, r)
+    nrm = np.stack([np.cos(p) * np.cos(t), np.cos(p) * np.sin(t), np.sin(p)], axis=1)
+    disp = np.zeros(n)
+    for b, cand in enumerate(cKDTree(x).query_ball_point(cb, 6.0 * wb)):
+        cand = np.asarray(cand, dtype=np.int64)
+        if cand.size:
+            d2 = np.sum((x[cand] - cb[b]) ** 2, axis=1)
+            disp[cand] += sb[b] * hb[b] * np.exp(-d2 / (2.0 * wb[b] ** 2))
+    return x + disp[:, None] * nrm, tris.astype(np.int32)
+
+
+def _ensure_level(lv, l, i, j):
+    """Split quadtree leaves (lv[L] = {(i, j)} per level L) so that cell
+    (l, i, j) is a leaf or lies inside finer leaves (no coarser leaf covers it)."""
+    L = l
+    while L >= 0 and (i >> (l - L), j >> (l - L)) not in lv[L]:
+        L -= 1
+    if L < 0 or L == l:
+        return                       # already subdivided at least to level l
+    while L < l:
+        I, J = i >> (l - L), j >> (l - L)
+        lv[L].discard((I, J))
+        lv[L + 1].update({(2 * I + a, 2 * J + b) for a in (0, 1) for b in (0, 1)})
+        L += 1

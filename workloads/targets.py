@@ -27,11 +27,12 @@ def bbox_targets(verts, n, pad=0.25, seed=4):
     return rng.uniform(lo - pad * ext, hi + pad * ext, size=(n, 3))
 
 
-def surface_offset_targets(verts, tris, sigma, n, tmax=3.0, seed=5, chunk=1 << 22):
+def surface_offset_targets(verts, tris, sigma, n, tmax=3.0, seed=5, chunk=1 << 22, meta=False):
     """n points near the skeleton surface: a triangle drawn with probability
     proportional to its area, a uniform point on it, then an offset t * sigma_j
     along its unit normal with t ~ U[-tmax, tmax] (the spread of Newton
-    iterates around the level set).  Generated in chunks to bound memory."""
+    iterates around the level set).  Generated in chunks to bound memory.
+    With ``meta`` also returns each point's triangle j (int32) and t."""
     rng = np.random.default_rng(seed)
     p0, p1, p2 = verts[tris[:, 0]], verts[tris[:, 1]], verts[tris[:, 2]]
     nrm = np.cross(p1 - p0, p2 - p0)
@@ -39,6 +40,8 @@ def surface_offset_targets(verts, tris, sigma, n, tmax=3.0, seed=5, chunk=1 << 2
     cdf = np.cumsum(area2)
     cdf /= cdf[-1]
     out = np.empty((n, 3))
+    if meta:
+        mj, mt = np.empty(n, np.int32), np.empty(n)
     for s in range(0, n, chunk):
         m = min(chunk, n - s)
         j = np.minimum(np.searchsorted(cdf, rng.uniform(size=m)), len(tris) - 1)
@@ -48,4 +51,8 @@ def surface_offset_targets(verts, tris, sigma, n, tmax=3.0, seed=5, chunk=1 << 2
         t = rng.uniform(-tmax, tmax, size=m)
         q = p0[j] + a[:, None] * (p1[j] - p0[j]) + b[:, None] * (p2[j] - p0[j])
         out[s:s + m] = q + (t * sigma[j] / area2[j])[:, None] * nrm[j]
+        if meta:
+            mj[s:s + m], mt[s:s + m] = j, t
+    if meta:
+        return out, mj, mt
     return out
