@@ -143,6 +143,7 @@ def time_newton(lss, torch, cfg, prec, steps, warmup):
     c.set_sigma(s)
     c.set_options(precision=prec, far_field=lss.FAR_FMM)
     n_nodes = len(cfg["tris"]) * len(cfg["chart_uv"])
+    log("bench:   projection")
     for _ in range(warmup):
         c.set_sigma(s)
         c.project(uv, device=True)
@@ -160,6 +161,7 @@ def time_newton(lss, torch, cfg, prec, steps, warmup):
         iters = max(iters, stt["newton_iters"])
         gms += stt["pair_kernel_ms"]
     conv = float((st == 0).sum().item()) / n_nodes
+    log("bench:   chart geometry")
     # chart geometry (tangents, area element, normal) at the converged charts:
     # one evaluation of grad Phi at x = T + h H plus the per-node kernel
     c.chart_geometry(uv, h)
@@ -172,6 +174,7 @@ def time_newton(lss, torch, cfg, prec, steps, warmup):
     # degree-8 interpolation of the chart points to 66 new points per triangle
     # (the order-10 lattice), section 3.3
     from workloads import chart_nodes
+    log("bench:   chart interpolation")
     ev = torch.as_tensor(chart_nodes(10), device=dev)
     c.chart_interp(uv, x, ev)
     torch.cuda.synchronize()
@@ -182,6 +185,7 @@ def time_newton(lss, torch, cfg, prec, steps, warmup):
     ei = time.perf_counter() - t0
     # second derivatives and curvatures of every chart: the Hessian through
     # the octree at x = T + h H plus the per-node kernel (section 3.1)
+    log("bench:   chart curvature")
     c.chart_curvature(uv, h)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -191,6 +195,7 @@ def time_newton(lss, torch, cfg, prec, steps, warmup):
     ek = time.perf_counter() - t0
     # the paper's target-attached width sigma(x) (lambda 2.5, sigma0 = sqrt(5)
     # max D) at the converged chart points, through the octree: one call
+    log("bench:   target-attached sigma(x)")
     c.eval_multiscale(x, 2.5, 0.0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -4,9 +4,12 @@
 // layer, those inside it the full kernel).
 //
 // Tree: a forest with one root cube per mesh, holding that mesh's nodes
-// (padded by 2 R_max); a box is split in eight when it holds more than
-// `leaf_capacity` nodes and its children would still be at least 1/shrink as
-// wide as the largest near radius R_k of its nodes.  All eight children are
+// (padded by 2 R_max); a box is split in eight when more than
+// `leaf_capacity` of its nodes have near radii R_k at most shrink times the
+// children's side (on a smoothly graded mesh: when the children would still
+// be at least 1/shrink as wide as the box's largest R_k; where fine and coarse
+// triangles meet, the fine nodes still reach leaves of their own scale and
+// the box's largest R_k only governs the admissibility).  All eight children are
 // kept (empty ones too), so the leaves partition each root cube and any target
 // position has a leaf.  Node and target keys carry the mesh id above the
 // Morton bits, so a sort groups them by mesh first; meshes never interact.
@@ -152,43 +155,59 @@ __global__ void k_permute_src(int64_t n, const Src *__restrict__ in, const int32
     if (k < n) out[k] = in[perm[k]];
 }
 
-// largest near radius cut * sigma_k over the nodes of each box of a level:
-// block (i, g) reduces chunk g (kRmaxChunk nodes) of box lb + i and folds it
-// with an atomic max on the bits of the (positive) double
+// largest near radius cut * sigma_k over the nodes of each box of a level,
+// and how many of its nodes have a radius that the box's children could
+// carry (R_k <= child side * shrink): block (i, g) reduces chunk g
+// (kRmaxChunk nodes) of box lb + i and folds it with an atomic max on the bits
+// of the (positive) double and an atomic add of the count
 constexpr int64_t kRmaxChunk = 8192;
 
 __global__ void k_box_rmax(int64_t lb, const int64_t *__restrict__ nb, const int64_t *__restrict__ ne,
-                           const Src *__restrict__ src, double cut, unsigned long long *rmax_bits) {
+                           const Src *__restrict__ src, double cut, const double *__restrict__ root,
+                           const int32_t *__restrict__ bmesh, int level, double shrink,
+                           unsigned long long *rmax_bits, unsigned long long *fit) {
     __shared__ double sh[kBlk];
+    __shared__ unsigned long long shc[kBlk];
     const int64_t b = lb + blockIdx.x;
     const int64_t k0 = nb[b] + (int64_t)blockIdx.y * kRmaxChunk;
     const int64_t k1 = min(ne[b], k0 + kRmaxChunk);
     if (k0 >= k1) return;
+    const double cs = box_side(root, bmesh, (int32_t)b, level + 1) * shrink;   // child side * shrink
+    const double lim = cs * cs / (0.5 * cut * cut);     // R_k <= cs  <=>  1 / s2 <= lim
     double m = 0.0;
+    unsigned long long nf = 0;
     for (int64_t k = k0 + threadIdx.x; k < k1; k += kBlk) {
         const double s2 = src[k].s2;                   // sigma = sqrt(1 / (2 s2))
         m = fmax(m, cut * sqrt(0.5 / s2));
+        nf += (1.0 <= lim * s2) ? 1ull : 0ull;
     }
     sh[threadIdx.x] = m;
+    shc[threadIdx.x] = nf;
     __syncthreads();
     for (int s = kBlk / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        if ((int)threadIdx.x < s) {
+            sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+            shc[threadIdx.x] += shc[threadIdx.x + s];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicMax(&rmax_bits[b], (unsigned long long)__double_as_longlong(sh[0]));
+    if (threadIdx.x == 0) {
+        atomicMax(&rmax_bits[b], (unsigned long long)__double_as_longlong(sh[0]));
+        atomicAdd(&fit[blockIdx.x], shc[0]);
+    }
 }
 
-__global__ void k_split_flags(int64_t lb, int64_t nlev, int level, int max_level, const double *__restrict__ root,
-                              const int32_t *__restrict__ bmesh, int64_t cap, double shrink,
-                              const int64_t *__restrict__ nb, const int64_t *__restrict__ ne,
-                              const double *__restrict__ rmax, int32_t *flag, int32_t *ids) {
+// A box splits when more than `cap` of its nodes have near radii its
+// children can carry (and the depth allows): in a box where fine and coarse
+// triangles meet (steeply graded meshes), the fine nodes still get leaves of
+// their own scale, and only the few coarse nodes sit in leaves narrower than
+// their cut radius.
+__global__ void k_split_flags(int64_t lb, int64_t nlev, int level, int max_level, int64_t cap,
+                              const unsigned long long *__restrict__ fit, int32_t *flag, int32_t *ids) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nlev) return;
-    int64_t b = lb + i;
-    double half = box_side(root, bmesh, (int32_t)b, level + 1);      // side of the children
-    int64_t cnt = ne[b] - nb[b];
-    flag[i] = (cnt > cap && half * shrink >= rmax[b] && level < max_level) ? 1 : 0;
-    ids[i] = (int32_t)b;
+    flag[i] = ((int64_t)fit[i] > cap && level < max_level) ? 1 : 0;
+    ids[i] = (int32_t)(lb + i);
 }
 
 __device__ inline int64_t lower_bound_key(const uint64_t *keys, int64_t lo, int64_t hi, uint64_t v, int shift) {
@@ -746,20 +765,23 @@ void build_tree(Ctx &c) {
                        t.child.as<int32_t>(), t.parent.as<int32_t>(), t.bmesh.as<int32_t>(), t.fr.as<uint64_t>());
     LSS_CHECK_LAUNCH("k_level0");
     t.level_begin.assign({0, (int64_t)nm});
-    DBuf flag, ids, split, nsplit;
+    DBuf flag, ids, split, nsplit, fitc;
     int64_t maxcnt = 0;                     // largest node count of a box of the current level
     for (int m = 0; m < nm; ++m) maxcnt = std::max(maxcnt, (c.h_tri_off[m + 1] - c.h_tri_off[m]) * c.nq);
     for (int lvl = 0;; ++lvl) {
         int64_t lb = t.level_begin[lvl], le = t.level_begin[lvl + 1], nl = le - lb;
         LSS_HIP(hipMemsetAsync(t.rmax.as<double>() + lb, 0, sizeof(double) * nl, c.stream));
+        fitc.ensure(8 * nl);
+        LSS_HIP(hipMemsetAsync(fitc.p, 0, 8 * nl, c.stream));
         const unsigned gy = (unsigned)ceil_div(maxcnt > 0 ? maxcnt : 1, kRmaxChunk);
         hipLaunchKernelGGL(k_box_rmax, dim3((unsigned)nl, gy), dim3(kBlk), 0, c.stream, lb, t.nb.as<int64_t>(),
-                           t.ne.as<int64_t>(), t.src.as<Src>(), cut, reinterpret_cast<unsigned long long *>(t.rmax.p));
+                           t.ne.as<int64_t>(), t.src.as<Src>(), cut, t.root.as<double>(), t.bmesh.as<int32_t>(), lvl,
+                           shrink, reinterpret_cast<unsigned long long *>(t.rmax.p),
+                           fitc.as<unsigned long long>());
         LSS_CHECK_LAUNCH("k_box_rmax");
         flag.ensure(4 * nl); ids.ensure(4 * nl); split.ensure(4 * nl); nsplit.ensure(16);
-        hipLaunchKernelGGL(k_split_flags, dim3(grid_for(nl)), dim3(kBlk), 0, c.stream, lb, nl, lvl, t.bits - 1,
-                           t.root.as<double>(), t.bmesh.as<int32_t>(), cap, shrink, t.nb.as<int64_t>(),
-                           t.ne.as<int64_t>(), t.rmax.as<double>(), flag.as<int32_t>(), ids.as<int32_t>());
+        hipLaunchKernelGGL(k_split_flags, dim3(grid_for(nl)), dim3(kBlk), 0, c.stream, lb, nl, lvl, t.bits - 1, cap,
+                           fitc.as<unsigned long long>(), flag.as<int32_t>(), ids.as<int32_t>());
         LSS_CHECK_LAUNCH("k_split_flags");
         compact_flags(c, nl, nullptr, flag.as<int32_t>(), ids.as<int32_t>(), split.as<int32_t>(), nsplit.as<int32_t>());
         int32_t ns = 0;
