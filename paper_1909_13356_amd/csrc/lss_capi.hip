@@ -353,6 +353,35 @@ hipGraphExec_t capture_newton(Ctx &c, int64_t N, double tau, double *phi, double
 
 constexpr int kNewtonChunk = 8;   // iterations per graph launch between host checks
 
+// Everything the captured iterations bake in: the address of every buffer
+// their kernels touch, the sizes and scalars passed by value, and the options
+// that choose kernels.  A graph captured for an equal key is reused.
+std::vector<uint64_t> newton_key(const Ctx &c, int64_t N, double tau, int maxit, int chunk) {
+    const NewtonState &s = c.ns;
+    const Tree &t = c.tree;
+    uint64_t tb;
+    std::memcpy(&tb, &tau, 8);
+    std::vector<uint64_t> k = {(uint64_t)N, tb, (uint64_t)maxit, (uint64_t)chunk, (uint64_t)c.opt.precision,
+                               (uint64_t)c.opt.far_field, (uint64_t)c.opt.tile, (uint64_t)c.opt.count_useful,
+                               (uint64_t)c.nnodes, (uint64_t)c.nmesh, (uint64_t)t.nboxes, (uint64_t)t.p,
+                               (uint64_t)t.ncp, (uint64_t)t.K, (uint64_t)t.nroot, (uint64_t)t.bits};
+    const DBuf *bufs[] = {&s.T, &s.H, &s.h, &s.lo, &s.hi, &s.sig, &s.mesh, &s.orig, &s.status, &s.iters, &s.seen,
+                          &s.active, &s.active2, &s.flag, &s.blocksum, &s.nact, &s.hist, &s.phi, &s.grad,
+                          &c.tx, &c.ty, &c.tz, &c.tmesh, &c.tleaf, &c.tstart, &c.ntiles, &c.tflag, &c.tpos,
+                          &c.tile_order, &c.tile_bucket, &c.tile_queue, &c.pairs, &c.src, &c.node_off, &c.verts,
+                          &c.tris, &c.vH, &c.sigma, &c.tri_off, &t.p2p_beg, &t.p2p_end, &t.p2p_val2, &t.nb, &t.ne,
+                          &t.level, &t.ijk, &t.src, &t.L, &t.M, &t.m2p_beg, &t.m2p_end, &t.m2p_val2, &t.root,
+                          &t.bmesh, &t.child, &t.parent, &t.rmax, &t.near_cnt};
+    for (const DBuf *b : bufs) k.push_back((uint64_t)(uintptr_t)b->p);
+    return k;
+}
+
+void drop_newton_graph(NewtonState &s) {
+    if (s.exec) (void)hipGraphExecDestroy(s.exec);
+    s.exec = nullptr;
+    s.exec_key.clear();
+}
+
 void project(Ctx &c, const double *uv, int32_t np, double *h, double *xout, int8_t *st, int8_t *it, unsigned flags) {
     if (np <= 0) fail(LSS_EINVAL, "lss_project: np must be >= 1");
     if (!uv || !h) fail(LSS_EINVAL, "lss_project: chart_uv and h must be non-null");
@@ -368,16 +397,23 @@ void project(Ctx &c, const double *uv, int32_t np, double *h, double *xout, int8
     ensure_targets(c, N);
     if (c.opt.far_field == LSS_FAR_FMM) ensure_tiles(c, N);
     NewtonState &s = c.ns;
-    DBuf phi, grad;
+    DBuf &phi = s.phi, &grad = s.grad;
     phi.ensure(sizeof(double) * N);
     grad.ensure(sizeof(double) * 3 * N);
     LSS_HIP(hipMemsetAsync(c.pairs.p, 0, 3 * sizeof(double), c.stream));
     // Iterations run in captured chunks; a node leaves the active list when it
     // converges or reaches maxit, so iterations past the last active one are
-    // empty launches and the host only checks the count between chunks.
+    // empty launches and the host only checks the count between chunks.  The
+    // chunk is captured once and relaunched by later calls whose key matches.
     const bool fmm = c.opt.far_field == LSS_FAR_FMM;
     const int chunk = std::min(maxit, kNewtonChunk);
-    hipGraphExec_t exec = capture_newton(c, N, tau, phi.as<double>(), grad.as<double>(), chunk);
+    std::vector<uint64_t> key = newton_key(c, N, tau, maxit, chunk);
+    if (!s.exec || key != s.exec_key) {
+        drop_newton_graph(s);
+        s.exec = capture_newton(c, N, tau, phi.as<double>(), grad.as<double>(), chunk);
+        s.exec_key = std::move(key);
+    }
+    hipGraphExec_t exec = s.exec;
     c.ev_reset();
     try {
         int done = 0;
@@ -400,10 +436,9 @@ void project(Ctx &c, const double *uv, int32_t np, double *h, double *xout, int8
         LSS_HIP(hipStreamSynchronize(c.stream));
     } catch (...) {
         (void)hipStreamSynchronize(c.stream);
-        (void)hipGraphExecDestroy(exec);
+        drop_newton_graph(s);
         throw;
     }
-    (void)hipGraphExecDestroy(exec);
     double *oh = h, *ox = xout;
     int8_t *ost = st, *oit = it;
     if (!dev) {
@@ -893,6 +928,7 @@ void lss_destroy(lss_ctx *ctx) {
                     &c.ns.T, &c.ns.H, &c.ns.h, &c.ns.lo, &c.ns.hi, &c.ns.sig, &c.ns.mesh, &c.ns.orig,
                     &c.ns.status, &c.ns.iters, &c.ns.seen, &c.ns.active, &c.ns.active2, &c.ns.flag, &c.ns.blocksum,
                     &c.ns.nact, &c.ns.hist};
+    lss::drop_newton_graph(c.ns);
     for (DBuf *b : bufs) b->release();
     if (c.capture_stream) (void)hipStreamDestroy(c.capture_stream);
     for (hipEvent_t e : c.ev_start) (void)hipEventDestroy(e);

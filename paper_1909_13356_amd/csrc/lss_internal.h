@@ -135,6 +135,11 @@ struct NewtonState {
     DBuf blocksum;       // int32 per block counts
     DBuf nact;           // int32[4]: active count, count at iteration start, N
     DBuf hist;           // int32[kHistCap]: active count per iteration
+    DBuf phi, grad;      // Phi and grad Phi of the evaluated targets
+    // the captured iterations and what they were captured for (kernel
+    // arguments: buffer addresses, sizes, options); reused while it matches
+    hipGraphExec_t exec = nullptr;
+    std::vector<uint64_t> exec_key;
 };
 
 // Octree over the quadrature nodes and the FMM state (far_field = LSS_FAR_FMM).

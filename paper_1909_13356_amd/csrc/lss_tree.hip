@@ -16,7 +16,7 @@
 //
 // Lists: one dual-tree traversal over (target box T, source box S) pairs:
 //   same level and admissible (|d|_inf >= 2, |d|^2 >= K, d = integer offset
-//   of the boxes, and box gap >= R_max(S))  -> M2L(S -> T)
+//   of the boxes, and Euclidean box gap >= R_max(S))  -> M2L(S -> T)
 //   otherwise: T leaf -> direct pairs with all nodes of S, unless S is not a
 //   leaf and holds more than kDirectMax nodes: then S is split against the
 //   leaf T; a deeper S whose centre is at least sqrt(K) of its sides away from
@@ -311,9 +311,12 @@ __device__ inline int dtt_action(const DttArgs &a, int32_t T, int32_t S, int &cl
     if (lT == lS) {
         int dx = a.ijk[3 * T] - a.ijk[3 * S], dy = a.ijk[3 * T + 1] - a.ijk[3 * S + 1], dz = a.ijk[3 * T + 2] - a.ijk[3 * S + 2];
         int m = max(abs(dx), max(abs(dy), abs(dz)));
-        // admissible: K-criterion and a gap of at least the cut radius of S's nodes
+        // admissible: K-criterion and a gap of at least the cut radius; the
+        // gap between two equal boxes offset by d sides is side * |max(|d| - 1, 0)|
+        const int gx = max(abs(dx) - 1, 0), gy = max(abs(dy) - 1, 0), gz = max(abs(dz) - 1, 0);
+        const double side = box_side(a.root, a.bmesh, S, lT), cutr = dtt_cut(a, T, S);
         if (m >= 2 && dx * dx + dy * dy + dz * dz >= a.K && m <= kR &&
-            (double)(m - 1) * box_side(a.root, a.bmesh, S, lT) >= dtt_cut(a, T, S)) {
+            (double)(gx * gx + gy * gy + gz * gz) * side * side >= cutr * cutr) {
             cls = ((dx + kR) * (2 * kR + 1) + (dy + kR)) * (2 * kR + 1) + (dz + kR);
             return A_M2L;
         }

@@ -246,6 +246,30 @@ def test_fmm_mixed_eval_reproducible_and_counters(graded):
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
+@pytest.mark.parametrize("prec", [lss.FP64, lss.MIXED])
+def test_fmm_project_graph_reuse(graded, prec):
+    """The captured Newton iterations are reused by later projections whose
+    buffers, sizes and options match: the same call twice, then a new sigma
+    (rebuilt tree, same sizes) and back, each equal bit for bit to a fresh
+    context's projection."""
+    v, t, sig, _ = graded
+    uv = chart_nodes(2)
+    say("case: Newton graph reuse, precision %d" % prec)
+    cf = ctx(v, t, sig, prec, lss.FAR_FMM)
+    first = cf.project(uv)
+    again = cf.project(uv)
+    for a, b in zip(first, again):
+        assert np.array_equal(a, b)
+    for s in (0.9 * sig, sig):
+        cf.set_sigma(s)
+        got = cf.project(uv)
+        want = ctx(v, t, s, prec, lss.FAR_FMM).project(uv)
+        for a, b in zip(got, want):
+            assert np.array_equal(a, b)
+    for a, b in zip(got, first):
+        assert np.array_equal(a, b)
+
+
 def useful_pairs_brute(v, t, sig, x, cut):
     """Pairs (target, node) with |x - y_k| < cut * sigma_k, by a k-d tree over
     the nodes (every node within cut * max sigma, then each node's own radius)."""
