@@ -297,6 +297,7 @@ struct GemmArgs {
     const int32_t *parent, *lev;
     const double *root;
     const int32_t *bmesh;
+    int rows = 0;               // output rows (leading coefficients written); 0 = ncp
 };
 
 // destination box, first element of the input column and output scale of pair j
@@ -355,7 +356,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
         for (int i = 0; i < kNA; ++i) {
             const int e = threadIdx.x + 256 * i, kk = e / kTR, rr = e % kTR;
-            ra[i] = (r0 + rr < a.ncp) ? op[(int64_t)(k0 + kk) * a.ncp + r0 + rr] : 0.0;
+            ra[i] = (r0 + rr < a.rows) ? op[(int64_t)(k0 + kk) * a.ncp + r0 + rr] : 0.0;
         }
 #pragma unroll
         for (int i = 0; i < kNB; ++i) rb[i] = bcol >= 0 ? a.X[bcol + k0 + bk + i] : 0.0;
@@ -403,14 +404,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int row = r0 + 16 * i + (lane >> 4) + 4 * q;
-                if (row < a.ncp) y[row] += sc * acc[i][t][q];
+                if (row < a.rows) y[row] += sc * acc[i][t][q];
             }
     }
 }
 
 void gemm(Ctx &c, GemmArgs a) {
+    if (a.rows <= 0) a.rows = a.ncp;
     // short lists (fewer than four 128-pair workgroups per CU) take 64-pair workgroups
-    const bool small = a.npairs * (a.mode == G_L2L ? 8 : 1) * ceil_div(a.ncp, kTR) < 4 * 256 * 128;
+    const bool small = a.npairs * (a.mode == G_L2L ? 8 : 1) * ceil_div(a.rows, kTR) < 4 * 256 * 128;
     const int tp = small ? 64 : 128;
     // split long pair lists so that grid.y stays within the launch limit
     const int64_t chunk = (int64_t)32768 * tp;
@@ -419,7 +421,7 @@ void gemm(Ctx &c, GemmArgs a) {
         b.npairs = a.npairs - j0 < chunk ? a.npairs - j0 : chunk;
         if (a.mode == G_LIST) { b.mkey = a.mkey + j0; b.mval = a.mval + j0; }
         else b.base = a.base + 8 * j0;
-        dim3 grid((unsigned)ceil_div(b.ncp, kTR), (unsigned)ceil_div(b.npairs, tp), a.mode == G_L2L ? 8u : 1u);
+        dim3 grid((unsigned)ceil_div(b.rows, kTR), (unsigned)ceil_div(b.npairs, tp), a.mode == G_L2L ? 8u : 1u);
         if (small) hipLaunchKernelGGL(k_gemm<64>, grid, dim3(256), 0, c.stream, b);
         else hipLaunchKernelGGL(k_gemm<128>, grid, dim3(256), 0, c.stream, b);
         LSS_CHECK_LAUNCH("k_gemm");
@@ -432,6 +434,24 @@ void class_vec(int cls, double v[3]) {
     v[0] = cls / (W * W) - kR;
     v[1] = (cls / W) % W - kR;
     v[2] = cls % W - kR;
+}
+
+// Order of the M2L of displacement class v (in box sides, |v|^2 >= K): the
+// truncation error of the translation of a box's multipole to a same-size box
+// at centre distance |v| falls like r^(p+1), r = a / |v|, a = sqrt(3)/2 the
+// half-diagonal (on the octree workloads the error at the closest class
+// follows this rate: p = 18 mixed loses 1.5e-7 at |v| = 2).  A class farther
+// than the closest admissible one (|v| = sqrt(K)) reaches the same error at a
+// lower order; kM2lMargin orders are kept on top.
+constexpr int kM2lMargin = 2;
+
+int m2l_order(int p, int K, const double v[3]) {
+    const double a = 0.8660254037844386;
+    const double d = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    const double r0 = a / std::sqrt((double)K), r = a / d;
+    if (!(r < r0)) return p;
+    const int pv = (int)std::ceil((p + 1) * std::log(r0) / std::log(r)) - 1 + kM2lMargin;
+    return std::min(p, std::max(pv, 4));
 }
 
 void build_ops(Ctx &c, int kind, int nops, const std::vector<double> &vecs, int p, int ncp, double *dst) {
@@ -533,12 +553,18 @@ void build_fmm(Ctx &c) {
                    t.bmesh.as<int32_t>()};
         gemm(c, a);
     }
-    // M2L, one launch per displacement class
+    // M2L, one launch per displacement class, each at its own order: the
+    // leading (p_v + 1)^2 coefficients in and out (the real layout orders them
+    // by degree), p_v = m2l_order(p, K, v)
     for (int cls : t.class_used) {
         const int64_t b0 = t.class_beg[cls], n = t.class_end[cls] - b0;
-        GemmArgs a{G_LIST, ncp, ncp, n, t.opM2L.as<double>() + (int64_t)t.op_class_slot[cls] * per, t.M.as<double>(),
+        double v[3];
+        class_vec(cls, v);
+        const int pv = m2l_order(p, t.K, v);
+        const int nkv = std::min(ncp, (int)ceil_div((int64_t)(pv + 1) * (pv + 1), kKB) * kKB);
+        GemmArgs a{G_LIST, ncp, nkv, n, t.opM2L.as<double>() + (int64_t)t.op_class_slot[cls] * per, t.M.as<double>(),
                    t.L.as<double>(), t.m2l_key2.as<uint64_t>() + b0, t.m2l_val2.as<int32_t>() + b0, 0,
-                   t.parent.as<int32_t>(), t.level.as<int32_t>(), t.root.as<double>(), t.bmesh.as<int32_t>()};
+                   t.parent.as<int32_t>(), t.level.as<int32_t>(), t.root.as<double>(), t.bmesh.as<int32_t>(), nkv};
         gemm(c, a);
     }
     // downward pass: L2L from level 0 to depth-1 into their children
