@@ -266,6 +266,33 @@ __device__ __forceinline__ void nodes32(const SrcF *sh, float x, float y, float 
 }
 
 
+// K consecutive FP32 records of a "far" chunk against one target: every node
+// is beyond the cut of every target of the tile, so the kernel is the Laplace
+// dipole.  The record's a holds a'' = (sqrt(pi)/2) a' s2^(-3/2) (see
+// stage_far), which moves the width out of the pair:  with r2 = |d|^2,
+//   Phi -= (a''.d) r2^(-3/2),  grad Phi += 3 (a''.d) r2^(-5/2) d - a'' r2^(-3/2).
+// Positions are the FP32 offsets from the tile origin without the low parts:
+// at |d| beyond the cut the rounding of the offsets is a relative error of a
+// few units of FP32 rounding in d.
+template <int K>
+__device__ __forceinline__ void nodes32_far(const SrcF *sh, float x, float y, float z, float &p, float &gx, float &gy,
+                                            float &gz) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const SrcF s = sh[k];
+        const float dx = x - s.yx, dy = y - s.yy, dz = z - s.yz;
+        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        const float r = __builtin_amdgcn_rsqf(r2);
+        const float rr = r * r, S = rr * r;
+        const float adS = fmaf(s.ax, dx, fmaf(s.ay, dy, s.az * dz)) * S;
+        p -= adS;
+        const float h = 3.0f * adS * rr;
+        gx = fmaf(h, dx, fmaf(-s.ax, S, gx));
+        gy = fmaf(h, dy, fmaf(-s.ay, S, gy));
+        gz = fmaf(h, dz, fmaf(-s.az, S, gz));
+    }
+}
+
 __device__ __forceinline__ void pair32(const SrcF &s, float x, float y, float z, float xl, float yl, float zl,
                                        float &p, float &gx, float &gy, float &gz) {
     // d = (x_hi - y_hi) + (x_lo - y_lo): positions carried as float-float
@@ -520,6 +547,54 @@ __device__ __forceinline__ int64_t load_ranges(const FmmEvalArgs &a, RangeBatch<
         rb.off[t + 1] += v;
         __syncthreads();
     }
+    return rb.off[nr];
+}
+
+// As load_ranges, with the ranges of the batch reordered so that the boxes
+// that lie beyond the cut of every target of the tile come last: a box whose
+// gap to the tile's target bounding box [blo, bhi] (offsets from the tile
+// origin o) is at least its largest cut radius.  Returns the packed length;
+// *nnear receives the packed length of the other ranges (uniform).
+__device__ __forceinline__ int64_t load_ranges_split(const FmmEvalArgs &a, RangeBatch<64> &rb, int e, int nr,
+                                                     const double o[3], const double blo[3], const double bhi[3],
+                                                     int64_t *nnear) {
+    const int t = threadIdx.x;
+    int64_t len = 0, beg = 0;
+    bool far = false;
+    if (t < nr) {
+        const int32_t S = a.p2p_src[e + t];
+        beg = a.nb[S];
+        len = a.ne[S] - a.nb[S];
+        const double side = box_side(a.root, a.bmesh, S, a.lev[S]);
+        const double *r0 = a.root + 4 * a.bmesh[S];
+        double g2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const double lo = r0[c] + a.ijk[3 * S + c] * side - o[c], hi = lo + side;
+            const double g = fmax(fmax(lo - bhi[c], blo[c] - hi), 0.0);
+            g2 += g * g;
+        }
+        const double rc = a.rmax[S] * (1.0 + 1e-6);
+        far = g2 >= rc * rc;
+    }
+    const uint64_t fm = __ballot(far), below = t ? (~0ull >> (64 - t)) : 0ull;
+    const int nn = nr - __popcll(fm);
+    const int pos = far ? nn + __popcll(fm & below) : __popcll(~fm & below);
+    __syncthreads();
+    if (t < nr) {
+        rb.beg[pos] = beg;
+        rb.off[pos + 1] = len;
+    } else {
+        rb.off[t + 1] = 0;
+    }
+    if (t == 0) rb.off[0] = 0;
+    __syncthreads();
+    for (int d = 1; d < 64; d <<= 1) {      // inclusive scan of off[1..64]
+        int64_t v = (t >= d) ? rb.off[t + 1 - d] : 0;
+        __syncthreads();
+        rb.off[t + 1] += v;
+        __syncthreads();
+    }
+    *nnear = rb.off[nn];
     return rb.off[nr];
 }
 
@@ -1012,6 +1087,15 @@ __global__ __launch_bounds__(64) void k_eval_fmm_mixed(FmmEvalArgs a) {
         const float x = (float)dxo, y = (float)dyo, z = (float)dzo;
         const float xl = (float)(dxo - (double)x), yl = (float)(dyo - (double)y), zl = (float)(dzo - (double)z);
         const int e0 = a.p2p_beg[B], e1 = a.p2p_end[B];
+        // bounding box of the tile's targets (offsets from the origin; the
+        // lanes past the tile end hold the first target)
+        const double o[3] = {ox, oy, oz};
+        double blo[3] = {dxo, dyo, dzo}, bhi[3] = {dxo, dyo, dzo};
+        for (int off = 32; off > 0; off >>= 1)
+            for (int c = 0; c < 3; ++c) {
+                blo[c] = fmin(blo[c], __shfl_xor(blo[c], off));
+                bhi[c] = fmax(bhi[c], __shfl_xor(bhi[c], off));
+            }
         __syncthreads();                    // previous tile is done with Ls
         stage_local(a, B, Ls);
         float sp = 0, ep = 0, sx = 0, ex = 0, sy = 0, ey = 0, sz = 0, ez = 0;
@@ -1020,10 +1104,12 @@ __global__ __launch_bounds__(64) void k_eval_fmm_mixed(FmmEvalArgs a) {
         for (int eb = e0; eb < e1; eb += W) {
             const int nr = e1 - eb < W ? e1 - eb : W;
             __syncthreads();
-            const int64_t total = load_ranges<W>(a, rb, eb, nr);
+            int64_t nnear;
+            const int64_t total = load_ranges_split(a, rb, eb, nr, o, blo, bhi, &nnear);
             npair += (double)total;
             for (int64_t c0 = 0; c0 < total; c0 += W) {
                 const int cnt = (int)(total - c0 < W ? total - c0 : W);
+                const bool far = c0 >= nnear;   // uniform: every node of the chunk is far for the tile
                 __syncthreads();
                 SrcF f;
                 if (lane < cnt) {
@@ -1036,9 +1122,11 @@ __global__ __launch_bounds__(64) void k_eval_fmm_mixed(FmmEvalArgs a) {
                     f.ly = (float)(qy - (double)f.yy);
                     f.lz = (float)(qz - (double)f.yz);
                     f.s2 = (float)sr.s2;
-                    f.ax = (float)(kFoldA * sr.ax);
-                    f.ay = (float)(kFoldA * sr.ay);
-                    f.az = (float)(kFoldA * sr.az);
+                    // far chunks: a'' = (sqrt(pi)/2) a' s2^(-3/2) (nodes32_far)
+                    const double fa = far ? kFoldA / (sr.s2 * sqrt(sr.s2)) : kFoldA;
+                    f.ax = (float)(fa * sr.ax);
+                    f.ay = (float)(fa * sr.ay);
+                    f.az = (float)(fa * sr.az);
                     f.s2x2 = (float)(kFoldT * sr.s2x2);
                 } else {
                     f = pad_srcf();
@@ -1049,8 +1137,12 @@ __global__ __launch_bounds__(64) void k_eval_fmm_mixed(FmmEvalArgs a) {
                 for (int j0 = 0; j0 < cnt; j0 += 32) {
                     float p = 0, gx = 0, gy = 0, gz = 0;
                     const int j1 = j0 + 32 < cnt ? j0 + 32 : cnt;
-                    for (int j = j0; j < j1; j += kNodeGroup)
-                        nodes32<kNodeGroup, COUNT>(sh + j, x, y, z, xl, yl, zl, p, gx, gy, gz, &nuse);
+                    if (far) {
+                        for (int j = j0; j < j1; j += kNodeGroup) nodes32_far<kNodeGroup>(sh + j, x, y, z, p, gx, gy, gz);
+                    } else {
+                        for (int j = j0; j < j1; j += kNodeGroup)
+                            nodes32<kNodeGroup, COUNT>(sh + j, x, y, z, xl, yl, zl, p, gx, gy, gz, &nuse);
+                    }
                     two_sum_f(sp, ep, p);
                     two_sum_f(sx, ex, gx);
                     two_sum_f(sy, ey, gy);
