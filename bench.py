@@ -315,10 +315,12 @@ def time_batch(lss, torch, b, uv, prec, per_surface):
         ctxs.append(c)
 
     conv = [0, 0]
+    hist = torch.zeros(4, dtype=torch.int64, device=dev)
 
     def step():
         evals = 0
         conv[0] = conv[1] = 0
+        hist.zero_()
         for c, q in zip(ctxs, parts):
             c.set_sigma(q["s"])
             c.eval(q["x"], x_mesh=q.get("xm"))
@@ -326,6 +328,7 @@ def time_batch(lss, torch, b, uv, prec, per_surface):
             evals += q["x"].shape[0] + c.stats()["last_targets"]
             conv[0] += int((st == 0).sum().item())
             conv[1] += st.shape[0]
+            hist.add_(torch.bincount(st.to(torch.int64), minlength=4)[:4])
         return evals
 
     step()
@@ -337,8 +340,10 @@ def time_batch(lss, torch, b, uv, prec, per_surface):
     for c in ctxs:
         c.close()
     n_nodes = len(b["tris"]) * len(uv)
+    hs = hist.cpu().tolist()
     return {"ms_per_step": 1e3 * el, "target_evals_per_s": evals / el, "chart_nodes_per_s": n_nodes / el,
-            "contexts": len(ctxs), "converged_frac": conv[0] / max(conv[1], 1)}
+            "contexts": len(ctxs), "converged_frac": conv[0] / max(conv[1], 1),
+            "statuses": {"converged": hs[0], "maxiter": hs[1], "nobracket": hs[2], "degenerate_h": hs[3]}}
 
 
 def cpu_newton(cfg, n_tris=4):

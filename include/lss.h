@@ -118,7 +118,11 @@ typedef struct lss_options {
     int32_t count_useful;     /* LSS_FAR_FMM: nonzero makes the evaluation kernels also count the
                                  pairs inside the cut (lss_stats.useful_pairs), at a small cost in
                                  speed; 0 = off (useful_pairs stays 0 for the FMM path) */
-    int32_t reserved[5];      /* must be zero */
+    int32_t admissibility;    /* LSS_FAR_FMM: K of the multipole-to-local criterion |v|^2 >= K for
+                                 boxes v sides apart (a larger K needs a lower fmm_order for the
+                                 same accuracy but leaves more pairs to the near lists);
+                                 0 = default (4 MIXED, 8 FP64); otherwise in [4, 18] */
+    int32_t reserved[4];      /* must be zero */
 } lss_options;
 
 typedef struct lss_stats {
@@ -363,16 +367,22 @@ int lss_chart_curvature(lss_ctx *ctx, const double *chart_uv, int32_t np, const 
 int lss_chart_interp(lss_ctx *ctx, const double *chart_uv, int32_t np, const double *f, int32_t ncomp,
                      const double *eval_uv, int32_t ne, double *out, unsigned flags);
 
-/* Autotuner: choose the tile width and, for LSS_FAR_FMM, the leaf capacity
- * and leaf shrink for the current source set, sigma and precision by timing
- * candidates on the caller's targets: cost = (build time) + eval_weight *
- * (time to evaluate x), each from HIP events on the context stream.  Pass a
- * spatially compact subset of the real targets and eval_weight = (all
- * targets) / n to keep the local target density.  cache_path (may be NULL):
- * a text file of one JSON object per line keyed by device, sizes and
- * precision; a matching line is reused without timing, a new result is
- * appended.  On return the best options are set on ctx and written to *out
- * (may be NULL).  x: (n,3), host or device per flags; n >= 1. */
+/* Autotuner: choose the tile width and, for LSS_FAR_FMM, the near/far split
+ * (leaf shrink over [1, 3], leaf capacity, admissibility K and order p) for
+ * the current source set, sigma and precision by timing candidates on the
+ * caller's targets: cost = (build time) + eval_weight * (time to evaluate x),
+ * each from HIP events on the context stream.  A candidate is accepted only
+ * if, on a subset of up to 512 of the targets, its Phi and grad Phi agree
+ * with the exact discrete sum (the direct FP64 path) to a quarter of the
+ * precision's bar (1e-12 FP64, 1e-6 MIXED; maximum error relative to the
+ * largest value).  The search first times leaf shrink x capacity (x tile)
+ * at the default K and p, then K and p around their defaults at the best
+ * leaves.  Pass a spatially compact subset of the real targets and
+ * eval_weight = (all targets) / n to keep the local target density.
+ * cache_path (may be NULL): a text file of one JSON object per line keyed by
+ * device, sizes and precision; a matching line is reused without timing, a
+ * new result is appended.  On return the best options are set on ctx and
+ * written to *out (may be NULL).  x: (n,3), host or device per flags; n >= 1. */
 int lss_autotune(lss_ctx *ctx, const double *x, int64_t n, unsigned flags, double eval_weight,
                  const char *cache_path, lss_options *out);
 

@@ -135,7 +135,9 @@ void validate_options(const lss_options &o) {
     if (!(o.leaf_shrink == 0.0 || (o.leaf_shrink >= 1.0 && o.leaf_shrink <= 3.0)))
         fail(LSS_EINVAL, "leaf_shrink must be 0 (default) or in [1, 3]");
     if (o.count_useful != 0 && o.count_useful != 1) fail(LSS_EINVAL, "count_useful must be 0 or 1");
-    for (int k = 0; k < 5; ++k)
+    if (o.admissibility != 0 && (o.admissibility < 4 || o.admissibility > 18))
+        fail(LSS_EINVAL, "admissibility must be 0 (default) or in [4, 18]");
+    for (int k = 0; k < 4; ++k)
         if (o.reserved[k] != 0) fail(LSS_EINVAL, "reserved option fields must be zero");
 }
 
@@ -760,20 +762,22 @@ bool tune_lookup(const char *path, const std::string &key, lss_options &o) {
     std::ifstream f(path);
     std::string line;
     bool found = false;
+    auto num = [](const std::string &l, const char *name, double &v) {
+        const std::string tag = std::string("\"") + name + "\":";
+        const size_t at = l.find(tag);
+        if (at == std::string::npos) return false;
+        v = atof(l.c_str() + at + tag.size());
+        return true;
+    };
     while (std::getline(f, line)) {
         const std::string tag = "\"key\": \"" + key + "\"";
         if (line.find(tag) == std::string::npos) continue;
-        double shrink = 0;
-        int cap = 0, tile = 0;
-        const char *q = strstr(line.c_str(), "\"leaf_shrink\":");
-        if (q) shrink = atof(q + 14);
-        q = strstr(line.c_str(), "\"leaf_capacity\":");
-        if (q) cap = atoi(q + 16);
-        q = strstr(line.c_str(), "\"tile\":");
-        if (q) tile = atoi(q + 7);
-        o.leaf_shrink = shrink;
-        o.leaf_capacity = cap;
-        o.tile = tile;
+        double v;
+        if (num(line, "leaf_shrink", v)) o.leaf_shrink = v;
+        if (num(line, "leaf_capacity", v)) o.leaf_capacity = (int32_t)v;
+        if (num(line, "tile", v)) o.tile = (int32_t)v;
+        if (num(line, "admissibility", v)) o.admissibility = (int32_t)v;
+        if (num(line, "fmm_order", v)) o.fmm_order = (int32_t)v;
         found = true;               // the last matching line wins
     }
     return found;
@@ -782,7 +786,9 @@ bool tune_lookup(const char *path, const std::string &key, lss_options &o) {
 void autotune(Ctx &c, const double *x, int64_t n, unsigned flags, double w, const char *path, lss_options *out) {
     if (!c.have_sources || !c.have_sigma) fail(LSS_ESTATE, "lss_autotune: set sources and sigma first");
     if (!x || n < 1) fail(LSS_EINVAL, "lss_autotune: need n >= 1 targets");
+    if (n > (int64_t)INT32_MAX) fail(LSS_EINVAL, "lss_autotune: n exceeds 2^31-1");
     if (!(w > 0.0) || !std::isfinite(w)) fail(LSS_EINVAL, "lss_autotune: eval_weight must be positive");
+    if (c.nmesh > 1) fail(LSS_EINVAL, "lss_autotune: tunes one mesh at a time (the targets carry no mesh ids)");
     const lss_options base = c.opt;
     const std::string key = tune_key(c);
     lss_options best = base;
@@ -797,30 +803,35 @@ void autotune(Ctx &c, const double *x, int64_t n, unsigned flags, double w, cons
     upload(c, dx, x, sizeof(double) * 3 * n, flags);
     phi.ensure(sizeof(double) * n);
     grad.ensure(sizeof(double) * 3 * n);
-    struct Cand { double shrink; int cap, tile; };
-    std::vector<Cand> cands;
-    if (base.far_field == LSS_FAR_FMM) {
-        // candidate grids around the measured optimum of each precision
-        const bool mixed = base.precision == LSS_MIXED;
-        const std::vector<double> shr = mixed ? std::vector<double>{1.0, 1.5, 2.0} : std::vector<double>{1.5, 2.0, 3.0};
-        const std::vector<int> caps = {64, 256};
-        const std::vector<int> tiles = mixed ? std::vector<int>{64} : std::vector<int>{64, 128};
-        for (double sh : shr)
-            for (int cp : caps)
-                for (int tl : tiles) cands.push_back({sh, cp, tl});
-    } else {
-        for (int tl : {64, 128, 256}) cands.push_back({0.0, 0, tl});
+    // accuracy subset: every stride-th target, at most 512, against the exact
+    // discrete sum (direct FP64 path)
+    const int64_t ns = std::min<int64_t>(n, 512), stride = n / ns;
+    std::vector<double> hx(3 * (size_t)n), hs(3 * (size_t)ns);
+    LSS_HIP(hipMemcpyAsync(hx.data(), dx.p, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, c.stream));
+    LSS_HIP(hipStreamSynchronize(c.stream));
+    for (int64_t i = 0; i < ns; ++i)
+        for (int k = 0; k < 3; ++k) hs[3 * i + k] = hx[3 * (i * stride) + k];
+    std::vector<double> rp(ns), rg(3 * ns), cp(ns), cg(3 * ns);
+    c.opt = base;
+    c.opt.far_field = LSS_FAR_DIRECT;
+    c.opt.precision = LSS_FP64;
+    c.built = false;
+    eval(c, hs.data(), nullptr, ns, rp.data(), rg.data(), 0);
+    double mp = 0.0, mg = 0.0;
+    for (int64_t i = 0; i < ns; ++i) {
+        mp = std::max(mp, std::fabs(rp[i]));
+        mg = std::max(mg, std::sqrt(rg[3 * i] * rg[3 * i] + rg[3 * i + 1] * rg[3 * i + 1] + rg[3 * i + 2] * rg[3 * i + 2]));
     }
+    const double bar = 0.25 * (base.precision == LSS_MIXED ? 1e-6 : 1e-12);
     hipEvent_t e0, e1, e2;
     LSS_HIP(hipEventCreate(&e0));
     LSS_HIP(hipEventCreate(&e1));
     LSS_HIP(hipEventCreate(&e2));
     double best_cost = 1e300;
-    for (const Cand &k : cands) {
-        c.opt = base;
-        c.opt.leaf_shrink = k.shrink;
-        c.opt.leaf_capacity = k.cap;
-        c.opt.tile = k.tile;
+    // cost of one candidate (build + weighted evaluation), or infinity when it
+    // misses the accuracy bar on the subset
+    auto trial = [&](const lss_options &o) {
+        c.opt = o;
         c.built = false;
         LSS_HIP(hipEventRecord(e0, c.stream));
         build(c);
@@ -831,23 +842,75 @@ void autotune(Ctx &c, const double *x, int64_t n, unsigned flags, double w, cons
         float tb = 0, te = 0;
         LSS_HIP(hipEventElapsedTime(&tb, e0, e1));
         LSS_HIP(hipEventElapsedTime(&te, e1, e2));
-        const double cost = tb + w * te;
+        eval(c, hs.data(), nullptr, ns, cp.data(), cg.data(), 0);
+        double ep = 0.0, eg = 0.0;
+        for (int64_t i = 0; i < ns; ++i) {
+            ep = std::max(ep, std::fabs(cp[i] - rp[i]));
+            double d2 = 0.0;
+            for (int k = 0; k < 3; ++k) d2 += (cg[3 * i + k] - rg[3 * i + k]) * (cg[3 * i + k] - rg[3 * i + k]);
+            eg = std::max(eg, std::sqrt(d2));
+        }
+        const bool ok = ep <= bar * mp && eg <= bar * mg;
+        const double cost = ok ? tb + w * te : 1e300;
         if (cost < best_cost) {
             best_cost = cost;
-            best = c.opt;
+            best = o;
         }
+        return cost;
+    };
+    try {
+        if (base.far_field == LSS_FAR_FMM) {
+            const bool mixed = base.precision == LSS_MIXED;
+            // stage 1: leaves (shrink over [1, 3], capacity) and tile at the default K and p
+            for (double sh : {1.0, 1.25, 1.5, 2.0, 2.5, 3.0})
+                for (int cp_ : {64, 256})
+                    for (int tl : mixed ? std::vector<int>{64} : std::vector<int>{64, 128}) {
+                        lss_options o = base;
+                        o.leaf_shrink = sh;
+                        o.leaf_capacity = cp_;
+                        o.tile = tl;
+                        trial(o);
+                    }
+            // stage 2: admissibility K and order p at the best leaves (order
+            // outermost: the translation operators are rebuilt per order)
+            const lss_options leaves = best;
+            const int p0 = mixed ? 20 : 26, K0 = mixed ? 4 : 8;
+            for (int dp : {-4, -2, 0, 2})
+                for (int dK : {0, 2, 4}) {
+                    lss_options o = leaves;
+                    o.fmm_order = p0 + dp;
+                    o.admissibility = K0 + dK;
+                    trial(o);
+                }
+        } else {
+            for (int tl : {64, 128, 256}) {
+                lss_options o = base;
+                o.tile = tl;
+                trial(o);
+            }
+        }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        (void)hipEventDestroy(e2);
+        c.opt = base;
+        c.built = false;
+        throw;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipEventDestroy(e2);
+    if (best_cost >= 1e300) best = base;     // nothing met the bar: keep the caller's options
     c.opt = best;
     c.built = false;
-    if (path) {
+    if (path && best_cost < 1e300) {
         std::ofstream f(path, std::ios::app);
         if (f) {
-            char buf[256];
-            snprintf(buf, sizeof(buf), ", \"leaf_shrink\": %.3f, \"leaf_capacity\": %d, \"tile\": %d, \"cost_ms\": %.3f}",
-                     best.leaf_shrink, best.leaf_capacity, best.tile, best_cost);
+            char buf[320];
+            snprintf(buf, sizeof(buf),
+                     ", \"leaf_shrink\": %.3f, \"leaf_capacity\": %d, \"tile\": %d, \"admissibility\": %d, "
+                     "\"fmm_order\": %d, \"cost_ms\": %.3f}",
+                     best.leaf_shrink, best.leaf_capacity, best.tile, best.admissibility, best.fmm_order, best_cost);
             f << "{\"key\": \"" << key << "\"" << buf << "\n";
         }
     }
@@ -1066,7 +1129,7 @@ int lss_set_options(lss_ctx *ctx, const lss_options *opt) {
         lss::validate_options(o);
         if (o.precision != c.opt.precision || o.far_field != c.opt.far_field || o.fmm_order != c.opt.fmm_order ||
             o.leaf_capacity != c.opt.leaf_capacity || o.cut_factor != c.opt.cut_factor ||
-            o.leaf_shrink != c.opt.leaf_shrink)
+            o.leaf_shrink != c.opt.leaf_shrink || o.admissibility != c.opt.admissibility)
             c.built = false;
         c.opt = o;
     });

@@ -122,13 +122,17 @@ def test_fmm_determinism_and_device_pointers(graded):
 
 
 def test_autotune_and_cache(graded, tmp_path):
+    """lss_autotune searches leaf shrink, capacity, admissibility K and order
+    p, accepting only candidates within a quarter of the bar against the
+    exact sum; the choice meets the parity bar and is cached."""
     v, t, sig, x = graded
     cache = tmp_path / "tune.jsonl"
     for prec in (lss.MIXED, lss.FP64):
         cf = ctx(v, t, sig, prec, lss.FAR_FMM)
         o1 = cf.autotune(x[:20000], eval_weight=3.0, cache_path=cache)
         say("case: autotune precision %d -> %s" % (prec, o1))
-        assert o1["tile"] in (64, 128, 256) and o1["leaf_capacity"] > 0 and o1["leaf_shrink"] >= 1.0
+        assert o1["tile"] in (64, 128, 256) and o1["leaf_capacity"] > 0 and 1.0 <= o1["leaf_shrink"] <= 3.0
+        assert 4 <= o1["admissibility"] <= 18 and o1["fmm_order"] > 0   # K and p are searched too
         # the tuned options still meet the parity bar
         pf, gf = cf.eval(x[:3000])
         cd = ctx(v, t, sig, lss.FP64, lss.FAR_DIRECT)
