@@ -45,7 +45,8 @@ def _load():
         L.oracle_sigma_field.argtypes = [P, P, i32, i64, P, i32, f64, f64, P, P, i64, P, P, P, P]
         L.oracle_eval_multiscale.argtypes = [P, P, i32, i64, P, P, i32, P, P, i64, P, P, P, P, ctypes.c_int]
         L.oracle_project.argtypes = [P, i64, P, i32, i64, P, i32, P, i64, P, i32, P, i32, P, i64,
-                                     f64, i32, P, P, P, P, ctypes.c_int]
+                                     f64, i32, i32, P, P, P, P, ctypes.c_int]
+        L.oracle_pseudonormals_curved.argtypes = [P, i64, P, i64, P]
         L.oracle_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -170,19 +171,71 @@ def sym3(h6):
     return h6[:, i]
 
 
-def pseudonormals(verts, tris):
+def pseudonormals(verts, tris, curved=False):
+    """Vertex pseudonormals (eq. mkvertexpn): of the flat triangles (the
+    corners of a quadratic skeleton), or with ``curved`` of the quadratic
+    patches (tris (n, 6)): corner normals y_u x y_v and corner angles of the
+    curved triangles."""
     verts = _f64(verts)
     tris = np.ascontiguousarray(tris, dtype=np.int32)
     H = np.empty((len(verts), 3))
-    _load().oracle_pseudonormals(_p(verts), len(verts), _p(tris), len(tris), _p(H))
+    if curved and tris.shape[1] == 6:
+        _load().oracle_pseudonormals_curved(_p(verts), len(verts), _p(tris), len(tris), _p(H))
+    else:
+        tris = np.ascontiguousarray(tris[:, :3])
+        _load().oracle_pseudonormals(_p(verts), len(verts), _p(tris), len(tris), _p(H))
     return H
 
 
+def quad_shape(u, v):
+    """Quadratic Lagrange shape functions of the six-point triangle (corners,
+    then the edge points of P1P2, P2P3, P3P1) at (u, v) and their first and
+    second derivatives: N, Nu, Nv (..., 6) and the constants Nuu, Nuv, Nvv (6,)."""
+    u, v = np.asarray(u, float), np.asarray(v, float)
+    w = 1.0 - u - v
+    N = np.stack([w * (2 * w - 1), u * (2 * u - 1), v * (2 * v - 1), 4 * u * w, 4 * u * v, 4 * v * w], -1)
+    z = np.zeros_like(u)
+    Nu = np.stack([1 - 4 * w, 4 * u - 1, z, 4 * (w - u), 4 * v, -4 * v], -1)
+    Nv = np.stack([1 - 4 * w, z, 4 * v - 1, -4 * u, 4 * u, 4 * (w - v)], -1)
+    Nuu = np.array([4.0, 4.0, 0.0, -8.0, 0.0, 0.0])
+    Nuv = np.array([4.0, 0.0, 0.0, -4.0, 4.0, -4.0])
+    Nvv = np.array([4.0, 0.0, 4.0, 0.0, 0.0, -8.0])
+    return N, Nu, Nv, Nuu, Nuv, Nvv
+
+
+def chart_frame(verts, tris, sel, chart_uv, curved=False):
+    """Chart base T(u, v) of eq. tparam and its derivatives at the chart nodes
+    of the triangles ``sel``: T, Tu, Tv, Tuu, Tuv, Tvv of shape (nsel, np, 3).
+    Flat (the corner triangle): T linear, second derivatives zero; with
+    ``curved`` and six-point triangles: the quadratic patch."""
+    verts = _f64(verts)
+    tris = np.asarray(tris)
+    uv = _f64(chart_uv).reshape(-1, 2)
+    t = tris[np.asarray(sel, dtype=np.int64)]
+    if curved and tris.shape[1] == 6:
+        P = verts[t]                                            # (nsel, 6, 3)
+        N, Nu, Nv, Nuu, Nuv, Nvv = quad_shape(uv[:, 0], uv[:, 1])
+        T = np.einsum("ik,skc->sic", N, P)
+        Tu = np.einsum("ik,skc->sic", Nu, P)
+        Tv = np.einsum("ik,skc->sic", Nv, P)
+        Tuu = np.broadcast_to(np.einsum("k,skc->sc", Nuu, P)[:, None], T.shape)
+        Tuv = np.broadcast_to(np.einsum("k,skc->sc", Nuv, P)[:, None], T.shape)
+        Tvv = np.broadcast_to(np.einsum("k,skc->sc", Nvv, P)[:, None], T.shape)
+        return T, Tu, Tv, Tuu, Tuv, Tvv
+    P1, P2, P3 = verts[t[:, 0]][:, None], verts[t[:, 1]][:, None], verts[t[:, 2]][:, None]
+    u, v = uv[None, :, 0:1], uv[None, :, 1:2]
+    T = P1 + u * (P2 - P1) + v * (P3 - P1)
+    Tu, Tv = np.broadcast_to(P2 - P1, T.shape), np.broadcast_to(P3 - P1, T.shape)
+    z = np.zeros_like(T)
+    return T, Tu, Tv, z, z, z
+
+
 def project(verts, tris, sigma, rule, chart_uv, tau=1e-12, max_iter=40, sel=None,
-            tri_offsets=None, nthreads=0):
+            tri_offsets=None, nthreads=0, curved=False):
     """Newton chart projection onto Phi = 1/2 for the chart nodes of the
     triangles ``sel`` (all if None).  Returns h, x, status, iters with
-    index k * np + i."""
+    index k * np + i.  ``curved``: on a quadratic skeleton, chart bases on the
+    curved patches (see oracle_project)."""
     verts, rule, uv = _f64(verts), _f64(rule), _f64(chart_uv).reshape(-1, 2)
     sigma = _f64(np.atleast_1d(sigma))
     tris, nvt = _tris(tris)
@@ -196,32 +249,32 @@ def project(verts, tris, sigma, rule, chart_uv, tau=1e-12, max_iter=40, sel=None
     st, it = np.empty(tot, np.int8), np.empty(tot, np.int8)
     _load().oracle_project(_p(verts), len(verts), _p(tris), nvt, len(tris), _p(off), nmesh,
                            _p(sigma), sigma.size, _p(rule), len(rule), _p(uv), npn,
-                           _p(s), nsel, float(tau), int(max_iter), _p(h), _p(xo),
+                           _p(s), nsel, float(tau), int(max_iter), int(bool(curved)), _p(h), _p(xo),
                            _p(st), _p(it), int(nthreads))
     return h, xo, st, it
 
 
-def chart_geometry(verts, tris, sigma, rule, chart_uv, h, sel=None, tri_offsets=None, nthreads=0):
+def chart_geometry(verts, tris, sigma, rule, chart_uv, h, sel=None, tri_offsets=None, nthreads=0, curved=False):
     """Tangents x_u, x_v, area element |x_u x x_v| and outward unit normal of
     the charts x = T + h H (section 3.1, eq. chart, u_vector, U_vector_2,
     v_vector, v_vector_2, eq. da) at the chart nodes of the triangles ``sel``
     (all if None), for the given h (index k * np + i over sel).  T and H are
     the linear maps of eq. tparam and mkpseudovec (vertex pseudonormals of eq.
-    mkvertexpn), on the corner triangles when ``tris`` is quadratic; grad Phi
-    comes from ``evaluate``; the normal is -grad Phi / |grad Phi|, outward
-    because Phi grows inward."""
+    mkvertexpn), on the corner triangles when ``tris`` is quadratic, or with
+    ``curved`` T is the quadratic patch and H interpolates its curved-vertex
+    pseudonormals; grad Phi comes from ``evaluate``; the normal is
+    -grad Phi / |grad Phi|, outward because Phi grows inward."""
     verts = _f64(verts)
     tris, _ = _tris(tris)
     corner = np.ascontiguousarray(tris[:, :3])
     uv = _f64(chart_uv).reshape(-1, 2)
     s = np.arange(len(tris)) if sel is None else np.asarray(sel, dtype=np.int64)
     npn = len(uv)
-    Hv = pseudonormals(verts, corner)
+    Hv = pseudonormals(verts, tris, curved)
     t = corner[s]
-    P1, P2, P3 = verts[t[:, 0]][:, None], verts[t[:, 1]][:, None], verts[t[:, 2]][:, None]
     H1, H2, H3 = Hv[t[:, 0]][:, None], Hv[t[:, 1]][:, None], Hv[t[:, 2]][:, None]
     u, v = uv[None, :, 0:1], uv[None, :, 1:2]
-    T = P1 + u * (P2 - P1) + v * (P3 - P1)
+    T, Tu, Tv, _, _, _ = chart_frame(verts, tris, s, uv, curved)
     H = H1 + u * (H2 - H1) + v * (H3 - H1)
     hh = _f64(h).reshape(len(s), npn, 1)
     x = T + hh * H
@@ -232,7 +285,7 @@ def chart_geometry(verts, tris, sigma, rule, chart_uv, h, sel=None, tri_offsets=
     _, g = evaluate(verts, tris, sigma, rule, x.reshape(-1, 3), tri_offsets=tri_offsets, x_mesh=xm,
                     nthreads=nthreads)
     g = g.reshape(len(s), npn, 3)
-    Tu, Tv, Hu, Hvv = P2 - P1, P3 - P1, H2 - H1, H3 - H1
+    Hu, Hvv = H2 - H1, H3 - H1
     den = np.sum(H * g, axis=-1, keepdims=True)
     au, av = Tu + hh * Hu, Tv + hh * Hvv
     hu = -np.sum(au * g, axis=-1, keepdims=True) / den
@@ -243,16 +296,19 @@ def chart_geometry(verts, tris, sigma, rule, chart_uv, h, sel=None, tri_offsets=
     return xu.reshape(-1, 3), xv.reshape(-1, 3), da.reshape(-1), nrm.reshape(-1, 3)
 
 
-def chart_curvature(verts, tris, sigma, rule, chart_uv, h, sel=None, tri_offsets=None, nthreads=0):
+def chart_curvature(verts, tris, sigma, rule, chart_uv, h, sel=None, tri_offsets=None, nthreads=0, curved=False):
     """Second derivatives of the charts x = T + h H and the curvatures of the
     surface at the chart nodes (section 3.1, eq. uu_vector, uu_vector_aux1,
-    uu_vector_aux2 and the analogous uv, vv expressions).  T and H are linear
-    on the (corner) triangle, so T_uu = H_uu = 0 and, with w_u = x_u,
-    w_v = x_v, g = grad Phi, B = grad grad Phi, D = g . H:
-        h_uu = -(w_u B w_u + 2 h_u g.H_u) / D,   x_uu = 2 h_u H_u + h_uu H,
-        h_uv = -(w_u B w_v + g.(h_u H_v + h_v H_u)) / D,
-                                                 x_uv = h_u H_v + h_v H_u + h_uv H,
-        h_vv = -(w_v B w_v + 2 h_v g.H_v) / D,   x_vv = 2 h_v H_v + h_vv H.
+    uu_vector_aux2 and the analogous uv, vv expressions).  H is linear on the
+    triangle (H_uu = 0) and so is T on a flat base (T_uu = 0); with ``curved``
+    T is the quadratic patch, whose second derivatives are constant.  With
+    w_u = x_u, w_v = x_v, g = grad Phi, B = grad grad Phi, D = g . H:
+        h_uu = -(w_u B w_u + 2 h_u g.H_u + g.T_uu) / D,
+                                                 x_uu = T_uu + 2 h_u H_u + h_uu H,
+        h_uv = -(w_u B w_v + g.(h_u H_v + h_v H_u) + g.T_uv) / D,
+                                                 x_uv = T_uv + h_u H_v + h_v H_u + h_uv H,
+        h_vv = -(w_v B w_v + 2 h_v g.H_v + g.T_vv) / D,
+                                                 x_vv = T_vv + 2 h_v H_v + h_vv H.
     (The printed eq. uu_vector groups its last terms as 2 h_u + h_uu H_u; the
     derivative of eq. u_vector, and eq. uu_vector_aux1 itself, give
     2 h_u H_u + h_uu H.)  With the outward normal n = -g/|g| and the first and
@@ -266,12 +322,11 @@ def chart_curvature(verts, tris, sigma, rule, chart_uv, h, sel=None, tri_offsets
     uv = _f64(chart_uv).reshape(-1, 2)
     s = np.arange(len(tris)) if sel is None else np.asarray(sel, dtype=np.int64)
     npn = len(uv)
-    Hv = pseudonormals(verts, corner)
+    Hv = pseudonormals(verts, tris, curved)
     t = corner[s]
-    P1, P2, P3 = verts[t[:, 0]][:, None], verts[t[:, 1]][:, None], verts[t[:, 2]][:, None]
     H1, H2, H3 = Hv[t[:, 0]][:, None], Hv[t[:, 1]][:, None], Hv[t[:, 2]][:, None]
     u, v = uv[None, :, 0:1], uv[None, :, 1:2]
-    T = P1 + u * (P2 - P1) + v * (P3 - P1)
+    T, Tu, Tv, Tuu, Tuv, Tvv = chart_frame(verts, tris, s, uv, curved)
     H = H1 + u * (H2 - H1) + v * (H3 - H1)
     hh = _f64(h).reshape(len(s), npn, 1)
     x = (T + hh * H).reshape(-1, 3)
@@ -283,7 +338,7 @@ def chart_curvature(verts, tris, sigma, rule, chart_uv, h, sel=None, tri_offsets
     B = sym3(hessian(verts, tris, sigma, rule, x, tri_offsets=tri_offsets, x_mesh=xm, nthreads=nthreads))
     g = g.reshape(len(s), npn, 3)
     B = B.reshape(len(s), npn, 3, 3)
-    Tu, Tv, Hu, Hw = P2 - P1, P3 - P1, H2 - H1, H3 - H1
+    Hu, Hw = H2 - H1, H3 - H1
     Hu, Hw = np.broadcast_to(Hu, g.shape), np.broadcast_to(Hw, g.shape)
     dot = lambda a, b: np.sum(a * b, axis=-1, keepdims=True)
     D = dot(H, g)
@@ -292,12 +347,12 @@ def chart_curvature(verts, tris, sigma, rule, chart_uv, h, sel=None, tri_offsets
     xu = Tu + hu * H + hh * Hu
     xv = Tv + hv * H + hh * Hw
     quad = lambda a, b: np.einsum("...i,...ij,...j->...", a, B, b)[..., None]
-    huu = -(quad(xu, xu) + 2 * hu * dot(g, Hu)) / D
-    huv = -(quad(xu, xv) + dot(g, hu * Hw + hv * Hu)) / D
-    hvv = -(quad(xv, xv) + 2 * hv * dot(g, Hw)) / D
-    xuu = 2 * hu * Hu + huu * H
-    xuv = hu * Hw + hv * Hu + huv * H
-    xvv = 2 * hv * Hw + hvv * H
+    huu = -(quad(xu, xu) + 2 * hu * dot(g, Hu) + dot(g, Tuu)) / D
+    huv = -(quad(xu, xv) + dot(g, hu * Hw + hv * Hu) + dot(g, Tuv)) / D
+    hvv = -(quad(xv, xv) + 2 * hv * dot(g, Hw) + dot(g, Tvv)) / D
+    xuu = Tuu + 2 * hu * Hu + huu * H
+    xuv = Tuv + hu * Hw + hv * Hu + huv * H
+    xvv = Tvv + 2 * hv * Hw + hvv * H
     n = -g / np.linalg.norm(g, axis=-1, keepdims=True)
     E, F, G = dot(xu, xu), dot(xu, xv), dot(xv, xv)
     L, M, N = dot(xuu, n), dot(xuv, n), dot(xvv, n)

@@ -526,27 +526,109 @@ void oracle_pseudonormals(const double *verts, int64_t nverts, const int32_t *tr
     free(A);
 }
 
+/* Curved chart bases on quadratic skeleton triangles (the section on
+ * quadratic skeletons: the pseudonormal construction carries over to the
+ * curved triangles).  The quadratic Lagrange shape functions of the six
+ * points (corners P1 P2 P3, edge points P4 on P1P2, P5 on P2P3, P6 on P3P1),
+ * w = 1 - u - v:
+ *   N1 = w (2w - 1), N2 = u (2u - 1), N3 = v (2v - 1), N4 = 4uw, N5 = 4uv, N6 = 4vw,
+ * and their derivatives in u and v. */
+static void quad_shape(double u, double v, double N[6], double Nu[6], double Nv[6])
+{
+    const double w = 1.0 - u - v;
+    N[0] = w * (2.0 * w - 1.0); N[1] = u * (2.0 * u - 1.0); N[2] = v * (2.0 * v - 1.0);
+    N[3] = 4.0 * u * w;         N[4] = 4.0 * u * v;         N[5] = 4.0 * v * w;
+    Nu[0] = 1.0 - 4.0 * w; Nu[1] = 4.0 * u - 1.0; Nu[2] = 0.0;
+    Nu[3] = 4.0 * (w - u); Nu[4] = 4.0 * v;       Nu[5] = -4.0 * v;
+    Nv[0] = 1.0 - 4.0 * w; Nv[1] = 0.0;           Nv[2] = 4.0 * v - 1.0;
+    Nv[3] = -4.0 * u;      Nv[4] = 4.0 * u;       Nv[5] = 4.0 * (w - v);
+}
+
+/* Point and tangents of triangle j's quadratic patch at (u, v). */
+static void quad_point(const double *verts, const int32_t *t6, double u, double v, double y[3], double yu[3],
+                       double yv[3])
+{
+    double N[6], Nu[6], Nv[6];
+    quad_shape(u, v, N, Nu, Nv);
+    for (int c = 0; c < 3; ++c) {
+        y[c] = yu[c] = yv[c] = 0.0;
+        for (int k = 0; k < 6; ++k) {
+            const double P = verts[3 * (int64_t)t6[k] + c];
+            y[c] += N[k] * P;
+            yu[c] += Nu[k] * P;
+            yv[c] += Nv[k] * P;
+        }
+    }
+}
+
+/* Vertex pseudonormals of a quadratic skeleton (eq. mkvertexpn on the curved
+ * triangles): at each corner of each patch, the unit patch normal y_u x y_v
+ * weighted by the angle between the patch's two edges there (their tangent
+ * directions at the corner, from the edge directions (1,0), (0,1), (-1,1) of
+ * T0), summed over the corners of the vertex and divided by the summed
+ * angles, not renormalised. */
+void oracle_pseudonormals_curved(const double *verts, int64_t nverts, const int32_t *tris6, int64_t ntris, double *H)
+{
+    static const double cuv[3][2] = {{0.0, 0.0}, {1.0, 0.0}, {0.0, 1.0}};
+    /* edge directions in (u, v) leaving each corner */
+    static const double dir[3][2][2] = {{{1, 0}, {0, 1}}, {{-1, 1}, {-1, 0}}, {{0, -1}, {1, -1}}};
+    double *A = (double *)calloc((size_t)nverts, sizeof(double));
+    for (int64_t i = 0; i < 3 * nverts; ++i) H[i] = 0.0;
+    for (int64_t j = 0; j < ntris; ++j) {
+        const int32_t *t6 = tris6 + 6 * j;
+        for (int k = 0; k < 3; ++k) {
+            double y[3], yu[3], yv[3], N[3], p[3], q[3], cr[3];
+            quad_point(verts, t6, cuv[k][0], cuv[k][1], y, yu, yv);
+            N[0] = yu[1] * yv[2] - yu[2] * yv[1];
+            N[1] = yu[2] * yv[0] - yu[0] * yv[2];
+            N[2] = yu[0] * yv[1] - yu[1] * yv[0];
+            const double nn = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+            if (nn == 0.0) continue;
+            for (int c = 0; c < 3; ++c) {
+                p[c] = dir[k][0][0] * yu[c] + dir[k][0][1] * yv[c];
+                q[c] = dir[k][1][0] * yu[c] + dir[k][1][1] * yv[c];
+            }
+            cr[0] = p[1] * q[2] - p[2] * q[1];
+            cr[1] = p[2] * q[0] - p[0] * q[2];
+            cr[2] = p[0] * q[1] - p[1] * q[0];
+            const double theta = atan2(sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]),
+                                       p[0] * q[0] + p[1] * q[1] + p[2] * q[2]);
+            const int64_t v = t6[k];
+            for (int c = 0; c < 3; ++c) H[3 * v + c] += theta * N[c] / nn;
+            A[v] += theta;
+        }
+    }
+    for (int64_t v = 0; v < nverts; ++v)
+        if (A[v] > 0.0)
+            for (int c = 0; c < 3; ++c) H[3 * v + c] /= A[v];
+    free(A);
+}
+
 /* ---------------------------------------------------------- Newton projection */
 /* For each selected triangle j (sel[k], or k if sel is NULL) and each chart
  * node (u_i, v_i): T, H from eq. tparam / mkpseudovec, then the safeguarded
  * Newton iteration described in the header.  Output index k * np + i.
- * With quadratic sources (nvt = 6) Phi sums the curved triangles while the
- * chart base T and the pseudonormal field H come from their corner
- * triangles P1 P2 P3. */
+ * With quadratic sources (nvt = 6) Phi sums the curved triangles; the chart
+ * base T and the pseudonormal field H come from their corner triangles
+ * P1 P2 P3, or with `curved` from the patches themselves: T = the quadratic
+ * patch at (u, v), H linear in the curved-vertex pseudonormals
+ * (oracle_pseudonormals_curved). */
 void oracle_project(const double *verts, int64_t nverts, const int32_t *tris, int32_t nvt, int64_t ntris,
                     const int64_t *tri_off, int32_t nmesh,
                     const double *sigma, int64_t nsigma, const double *rule, int32_t nq,
                     const double *chart_uv, int32_t np, const int64_t *sel, int64_t nsel,
-                    double tau, int32_t max_iter,
+                    double tau, int32_t max_iter, int32_t curved,
                     double *h_out, double *x_out, int8_t *status, int8_t *iters,
                     int nthreads)
 {
     srcset S = {verts, tris, nvt, tri_off, ntris, sigma, nsigma, rule, nq};
+    const int cur = curved && nvt == 6;
     int32_t *corner = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)ntris);
     for (int64_t j = 0; j < ntris; ++j)
         for (int k = 0; k < 3; ++k) corner[3 * j + k] = tris[nvt * j + k];
     double *Hv = (double *)malloc(sizeof(double) * 3 * (size_t)nverts);
-    oracle_pseudonormals(verts, nverts, corner, ntris, Hv);
+    if (cur) oracle_pseudonormals_curved(verts, nverts, tris, ntris, Hv);
+    else oracle_pseudonormals(verts, nverts, corner, ntris, Hv);
     set_threads(nthreads);
     const int64_t total = nsel * (int64_t)np;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -568,6 +650,10 @@ void oracle_project(const double *verts, int64_t nverts, const int32_t *tris, in
             const double h1 = Hv[3 * (int64_t)t[0] + c], h2 = Hv[3 * (int64_t)t[1] + c], h3 = Hv[3 * (int64_t)t[2] + c];
             T[c] = p1 + u * (p2 - p1) + v * (p3 - p1);
             H[c] = h1 + u * (h2 - h1) + v * (h3 - h1);
+        }
+        if (cur) {
+            double yu[3], yv[3];
+            quad_point(verts, tris + 6 * j, u, v, T, yu, yv);
         }
         const double sj = nsigma == 1 ? sigma[0] : sigma[j];
         const double nH = sqrt(H[0] * H[0] + H[1] * H[1] + H[2] * H[2]);

@@ -909,3 +909,108 @@ def test_sigma_blend_nearest_centroid_dominates_far_away():
     sig, g, sj, _ = oracle.sigma_field(v, t, x, lam=2.0, sigma0=0.2)
     assert sig[0] == sj[1] and sig[1] == sj[0]
     assert np.abs(g).max() == 0.0
+
+
+# ------------------------------------- curved chart bases (quadratic skeletons)
+def test_quadratic_shape_functions_interpolate_and_differentiate():
+    """The six shape functions are 1 at their own point and 0 at the other
+    five (corners (0,0), (1,0), (0,1), edge midpoints), sum to 1, and their
+    first and second derivatives equal central differences of them."""
+    pts = np.array([[0, 0], [1, 0], [0, 1], [0.5, 0], [0.5, 0.5], [0, 0.5]], float)
+    N, Nu, Nv, Nuu, Nuv, Nvv = oracle.quad_shape(pts[:, 0], pts[:, 1])
+    assert np.allclose(N, np.eye(6), atol=1e-15)
+    rng = np.random.default_rng(2)
+    u, v = rng.uniform(0.05, 0.4, 20), rng.uniform(0.05, 0.4, 20)
+    assert np.allclose(oracle.quad_shape(u, v)[0].sum(1), 1.0, atol=1e-15)
+    d = 1e-5
+    f = lambda a, b: oracle.quad_shape(a, b)[0]
+    _, Nu, Nv, Nuu, Nuv, Nvv = oracle.quad_shape(u, v)
+    assert np.abs((f(u + d, v) - f(u - d, v)) / (2 * d) - Nu).max() < 1e-9
+    assert np.abs((f(u, v + d) - f(u, v - d)) / (2 * d) - Nv).max() < 1e-9
+    g = lambda a, b: oracle.quad_shape(a, b)[1]
+    assert np.abs((g(u + d, v) - g(u - d, v)) / (2 * d) - Nuu).max() < 1e-8
+    assert np.abs((g(u, v + d) - g(u, v - d)) / (2 * d) - Nuv).max() < 1e-8
+    h = lambda a, b: oracle.quad_shape(a, b)[2]
+    assert np.abs((h(u, v + d) - h(u, v - d)) / (2 * d) - Nvv).max() < 1e-8
+
+
+def test_curved_pseudonormals():
+    """Curved-vertex pseudonormals (eq. mkvertexpn on the quadratic patches):
+    with straight edges (edge points at the midpoints) each patch is its
+    flat triangle, so they equal the flat pseudonormals; on a sphere whose
+    edge points are lifted onto it they point radially to a fraction of the
+    flat ones' deviation (the corner normals are those of the curved patch)."""
+    v, t = icosphere(2)
+    vq, tq = quadratic_from_flat(v, t)
+    assert np.abs(oracle.pseudonormals(vq, tq, curved=True)[:len(v)] - oracle.pseudonormals(v, t)).max() < 1e-14
+    vs, ts = quadratic_from_flat(v, t, lift=lambda p: p / np.linalg.norm(p, axis=1, keepdims=True))
+    Hc = oracle.pseudonormals(vs, ts, curved=True)[:len(v)]
+    Hf = oracle.pseudonormals(vs, ts, curved=False)[:len(v)]
+    ang = lambda H: np.degrees(np.arccos(np.clip(np.sum(H * v, 1) / np.linalg.norm(H, axis=1)
+                                                 / np.linalg.norm(v, axis=1), -1, 1)))
+    assert ang(Hc).max() < 0.2 * ang(Hf).max() and ang(Hf).max() > 0.1
+
+
+def test_curved_charts_projection():
+    """Chart bases on the curved patches: the projected points lie on Phi = 1/2
+    (re-evaluated by the direct sum); with straight-edged quadratic triangles
+    they are the flat-based charts; on a torus whose six points per triangle
+    lie on it the chart base T = x - h H lies on the torus up to the patch's
+    interpolation error, far closer than the corner triangles' chords."""
+    v, t = torus_mesh(12, 6, quadratic=True)
+    D = triangle_diameters(v, np.ascontiguousarray(t[:, :3]))
+    sig = D / 4.0
+    uv = chart_nodes(2)
+    sel = np.arange(0, len(t), 11)
+    rule = dunavant6()
+    hc, xc, stc, _ = oracle.project(v, t, sig, rule, uv, tau=1e-13, sel=sel, curved=True)
+    hf, xf, stf, _ = oracle.project(v, t, sig, rule, uv, tau=1e-13, sel=sel, curved=False)
+    assert np.all(stc == 0) and np.all(stf == 0)
+    p, _ = oracle.evaluate(v, t, sig, rule, xc)
+    assert np.abs(p - 0.5).max() < 1e-12
+    def base(x, h, curved):
+        Hv = oracle.pseudonormals(v, t, curved)
+        c = t[sel][:, :3]
+        u_, w_ = uv[None, :, 0:1], uv[None, :, 1:2]
+        H = Hv[c[:, 0]][:, None] + u_ * (Hv[c[:, 1]] - Hv[c[:, 0]])[:, None] + w_ * (Hv[c[:, 2]] - Hv[c[:, 0]])[:, None]
+        return x - h[:, None] * H.reshape(-1, 3)
+    torus_dist = lambda p: np.abs(np.hypot(np.hypot(p[:, 0], p[:, 1]) - 1.0, p[:, 2]) - 0.4)
+    dc, df = torus_dist(base(xc, hc, True)), torus_dist(base(xf, hf, False))
+    assert dc.max() < 0.05 * df.max()
+    vf, tf = torus_mesh(12, 6)
+    vq, tq = quadratic_from_flat(vf, tf)                         # straight edges
+    sf = triangle_diameters(vf, tf) / 4.0
+    a = oracle.project(vq, tq, sf, rule, uv, tau=1e-13, sel=sel, curved=True)
+    b = oracle.project(vq, tq, sf, rule, uv, tau=1e-13, sel=sel, curved=False)
+    assert np.abs(a[0] - b[0]).max() < 1e-12 * sf.max() and np.array_equal(a[2], b[2])
+
+
+def test_curved_chart_tangents_and_second_derivatives():
+    """x_u, x_v of the curved charts against central differences of the
+    oracle's own curved Newton charts x(u +- d, v), x(u, v +- d), and x_uu,
+    x_uv, x_vv against differences of x_u, x_v: a missing T_u, T_uu term of
+    the patch (or the flat T_u in its place) fails it."""
+    v, t = torus_mesh(12, 6, quadratic=True)
+    sig = triangle_diameters(v, np.ascontiguousarray(t[:, :3])) / 4.0
+    uv = np.array([[0.2, 0.3], [0.55, 0.15], [0.1, 0.7]])
+    sel = np.array([3, 40, 111])
+    rule = dunavant6()
+    h, x, st, _ = oracle.project(v, t, sig, rule, uv, tau=1e-14, sel=sel, curved=True)
+    assert np.all(st == 0)
+    xu, xv, da, nrm = oracle.chart_geometry(v, t, sig, rule, uv, h, sel=sel, curved=True)
+    xuu, xuv, xvv, K, Hm = oracle.chart_curvature(v, t, sig, rule, uv, h, sel=sel, curved=True)
+    d = 1e-4
+    for k, (du, dv) in enumerate(((d, 0.0), (0.0, d))):
+        hp, up_x = oracle.project(v, t, sig, rule, uv + [du, dv], tau=1e-14, sel=sel, curved=True)[:2]
+        hm, dn_x = oracle.project(v, t, sig, rule, uv - [du, dv], tau=1e-14, sel=sel, curved=True)[:2]
+        fd = (up_x - dn_x) / (2 * d)
+        an = xu if k == 0 else xv
+        assert (np.linalg.norm(fd - an, axis=1) / np.linalg.norm(an, axis=1)).max() < 1e-6
+        up = oracle.chart_geometry(v, t, sig, rule, uv + [du, dv], hp, sel=sel, curved=True)
+        dn = oracle.chart_geometry(v, t, sig, rule, uv - [du, dv], hm, sel=sel, curved=True)
+        fdu, fdv = (up[0] - dn[0]) / (2 * d), (up[1] - dn[1]) / (2 * d)
+        an_u, an_v = (xuu, xuv) if k == 0 else (xuv, xvv)
+        scale = max(np.abs(xuu).max(), np.abs(xvv).max())
+        assert np.abs(fdu - an_u).max() < 1e-5 * scale
+        assert np.abs(fdv - an_v).max() < 1e-5 * scale
+    assert np.abs(np.sum(xu * nrm, axis=1)).max() < 1e-10 * np.linalg.norm(xu, axis=1).max()
