@@ -122,7 +122,12 @@ typedef struct lss_options {
                                  boxes v sides apart (a larger K needs a lower fmm_order for the
                                  same accuracy but leaves more pairs to the near lists);
                                  0 = default (4 MIXED, 8 FP64); otherwise in [4, 18] */
-    int32_t reserved[4];      /* must be zero */
+    int32_t curved_charts;    /* quadratic skeletons (LSS_TRI6): nonzero puts the chart bases on the
+                                 curved patches (T(u,v) the quadratic patch, H linear in the
+                                 vertex pseudonormals of the curved triangles: their corner
+                                 normals y_u x y_v weighted by their corner angles); 0 = bases on
+                                 the corner triangles.  No effect on flat skeletons. */
+    int32_t reserved[3];      /* must be zero */
 } lss_options;
 
 typedef struct lss_stats {
@@ -196,9 +201,11 @@ int lss_synchronize(lss_ctx *ctx);
  * corners P1 P2 P3 in the order above, then the edge points P4 (edge P1P2),
  * P5 (P2P3), P6 (P3P1), shared by the two triangles of an edge.  The patch is
  * y(u,v) = sum_k N_k(u,v) P_k with the quadratic Lagrange shape functions
- * and each node carries w (y_u x y_v).  The orientation check, the vertex
- * pseudonormals and the chart bases of lss_project / lss_chart_geometry use
- * the corner triangles P1 P2 P3; Phi sums the curved triangles. */
+ * and each node carries w (y_u x y_v).  The orientation check uses the
+ * corner triangles P1 P2 P3; the vertex pseudonormals and the chart bases of
+ * lss_project / lss_chart_geometry / lss_chart_curvature use the corner
+ * triangles too, or the curved patches with lss_options.curved_charts; Phi
+ * sums the curved triangles. */
 int lss_set_sources(lss_ctx *ctx,
                     const double *verts, int64_t nverts,
                     const int32_t *tris, int64_t ntris,

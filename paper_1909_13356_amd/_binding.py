@@ -41,7 +41,8 @@ class Options(ctypes.Structure):
                 ("cut_factor", ctypes.c_double), ("newton_tau", ctypes.c_double),
                 ("newton_max_iter", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("leaf_shrink", ctypes.c_double), ("count_useful", ctypes.c_int32),
-                ("admissibility", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("admissibility", ctypes.c_int32), ("curved_charts", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class Stats(ctypes.Structure):
@@ -207,9 +208,10 @@ class Context:
 
     def set_options(self, precision=FP64, far_field=FAR_DIRECT, fmm_order=0, leaf_capacity=0,
                     cut_factor=0.0, newton_tau=0.0, newton_max_iter=0, tile=0, leaf_shrink=0.0,
-                    count_useful=0, admissibility=0):
+                    count_useful=0, admissibility=0, curved_charts=0):
         o = Options(precision, far_field, fmm_order, leaf_capacity, cut_factor, newton_tau,
-                    newton_max_iter, tile, leaf_shrink, int(bool(count_useful)), admissibility)
+                    newton_max_iter, tile, leaf_shrink, int(bool(count_useful)), admissibility,
+                    int(bool(curved_charts)))
         self._check(self._lib.lss_set_options(self._h, ctypes.byref(o)))
 
     def get_options(self):

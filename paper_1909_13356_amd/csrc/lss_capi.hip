@@ -137,7 +137,8 @@ void validate_options(const lss_options &o) {
     if (o.count_useful != 0 && o.count_useful != 1) fail(LSS_EINVAL, "count_useful must be 0 or 1");
     if (o.admissibility != 0 && (o.admissibility < 4 || o.admissibility > 18))
         fail(LSS_EINVAL, "admissibility must be 0 (default) or in [4, 18]");
-    for (int k = 0; k < 4; ++k)
+    if (o.curved_charts != 0 && o.curved_charts != 1) fail(LSS_EINVAL, "curved_charts must be 0 or 1");
+    for (int k = 0; k < 3; ++k)
         if (o.reserved[k] != 0) fail(LSS_EINVAL, "reserved option fields must be zero");
 }
 
@@ -1129,7 +1130,8 @@ int lss_set_options(lss_ctx *ctx, const lss_options *opt) {
         lss::validate_options(o);
         if (o.precision != c.opt.precision || o.far_field != c.opt.far_field || o.fmm_order != c.opt.fmm_order ||
             o.leaf_capacity != c.opt.leaf_capacity || o.cut_factor != c.opt.cut_factor ||
-            o.leaf_shrink != c.opt.leaf_shrink || o.admissibility != c.opt.admissibility)
+            o.leaf_shrink != c.opt.leaf_shrink || o.admissibility != c.opt.admissibility ||
+            o.curved_charts != c.opt.curved_charts)
             c.built = false;
         c.opt = o;
     });

@@ -13,6 +13,7 @@
 
 #include "lss_internal.h"
 #include "radial_exact.h"
+#include "chart_frame.h"
 
 namespace lss {
 namespace {
@@ -322,35 +323,29 @@ __global__ void __launch_bounds__(256) k_eval_multiscale(int64_t n, const double
 }
 
 // Second derivatives and curvatures of chart j at node i (index q = j np + i).
-// T and H are linear on the corner triangle (T_uu = H_uu = 0); with w_u = x_u,
-// w_v = x_v, g = grad Phi, B = the Hessian, D = g . H:
-//   h_uu = -(w_u B w_u + 2 h_u g.H_u) / D,             x_uu = 2 h_u H_u + h_uu H
-//   h_uv = -(w_u B w_v + g.(h_u H_v + h_v H_u)) / D,   x_uv = h_u H_v + h_v H_u + h_uv H
-//   h_vv = -(w_v B w_v + 2 h_v g.H_v) / D,             x_vv = 2 h_v H_v + h_vv H
+// H is linear on the corner triangle (H_uu = 0); T is linear too, or with
+// curved charts the quadratic patch with constant T_uu, T_uv, T_vv.  With
+// w_u = x_u, w_v = x_v, g = grad Phi, B = the Hessian, D = g . H:
+//   h_uu = -(w_u B w_u + 2 h_u g.H_u + g.T_uu) / D,
+//   h_uv = -(w_u B w_v + g.(h_u H_v + h_v H_u) + g.T_uv) / D,
+//   h_vv = -(w_v B w_v + 2 h_v g.H_v + g.T_vv) / D,
+//   x_uu = T_uu + 2 h_u H_u + h_uu H,  x_uv = T_uv + h_u H_v + h_v H_u + h_uv H,
+//   x_vv = T_vv + 2 h_v H_v + h_vv H.
 // Curvatures from the fundamental forms with the outward normal n = -g/|g|:
 //   Gaussian (LN - M^2)/(EG - F^2), mean -(EN - 2FM + GL)/(2(EG - F^2)).
 __global__ void k_chart_curvature(int64_t N, const double *__restrict__ verts, const int32_t *__restrict__ tris,
-                                  const double *__restrict__ vH, const double *__restrict__ uv, int32_t np,
-                                  const double *__restrict__ h, const double *__restrict__ grad,
-                                  const double *__restrict__ hess, double *xuu, double *xuv, double *xvv,
-                                  double *gauss, double *mean) {
+                                  const int32_t *__restrict__ tris6, const double *__restrict__ vH,
+                                  const double *__restrict__ uv, int32_t np, const double *__restrict__ h,
+                                  const double *__restrict__ grad, const double *__restrict__ hess, double *xuu,
+                                  double *xuv, double *xvv, double *gauss, double *mean) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= N) return;
-    const int64_t j = q / np;
-    const int i = (int)(q - j * np);
-    const double u = uv[2 * i], v = uv[2 * i + 1];
-    const int32_t *t = tris + 3 * j;
-    double H[3], Tu[3], Tv[3], Hu[3], Hv[3], g[3];
-    for (int c = 0; c < 3; ++c) {
-        const double h1 = vH[3 * (int64_t)t[0] + c], h2 = vH[3 * (int64_t)t[1] + c], h3 = vH[3 * (int64_t)t[2] + c];
-        const double p1 = verts[3 * (int64_t)t[0] + c];
-        Tu[c] = verts[3 * (int64_t)t[1] + c] - p1;
-        Tv[c] = verts[3 * (int64_t)t[2] + c] - p1;
-        Hu[c] = h2 - h1;
-        Hv[c] = h3 - h1;
-        H[c] = h1 + u * Hu[c] + v * Hv[c];
-        g[c] = grad[3 * q + c];
-    }
+    ChartFrame f;
+    int64_t j;
+    chart_frame(verts, tris, tris6, vH, uv, np, q, f, j);
+    const double *H = f.H, *Tu = f.Tu, *Tv = f.Tv, *Hu = f.Hu, *Hv = f.Hv;
+    double g[3];
+    for (int c = 0; c < 3; ++c) g[c] = grad[3 * q + c];
     const double *b = hess + 6 * q;
     const double B[3][3] = {{b[0], b[1], b[2]}, {b[1], b[3], b[4]}, {b[2], b[4], b[5]}};
     const double hq = h[q];
@@ -376,14 +371,17 @@ __global__ void k_chart_curvature(int64_t N, const double *__restrict__ verts, c
     const double vBv = wv[0] * Bwv[0] + wv[1] * Bwv[1] + wv[2] * Bwv[2];
     const double gHu = g[0] * Hu[0] + g[1] * Hu[1] + g[2] * Hu[2];
     const double gHv = g[0] * Hv[0] + g[1] * Hv[1] + g[2] * Hv[2];
-    const double huu = -(uBu + 2.0 * hu * gHu) / D;
-    const double huv = -(uBv + hu * gHv + hv * gHu) / D;
-    const double hvv = -(vBv + 2.0 * hv * gHv) / D;
+    const double gTuu = g[0] * f.Tuu[0] + g[1] * f.Tuu[1] + g[2] * f.Tuu[2];
+    const double gTuv = g[0] * f.Tuv[0] + g[1] * f.Tuv[1] + g[2] * f.Tuv[2];
+    const double gTvv = g[0] * f.Tvv[0] + g[1] * f.Tvv[1] + g[2] * f.Tvv[2];
+    const double huu = -(uBu + 2.0 * hu * gHu + gTuu) / D;
+    const double huv = -(uBv + hu * gHv + hv * gHu + gTuv) / D;
+    const double hvv = -(vBv + 2.0 * hv * gHv + gTvv) / D;
     double a[3], m[3], e[3];
     for (int c = 0; c < 3; ++c) {
-        a[c] = 2.0 * hu * Hu[c] + huu * H[c];
-        m[c] = hu * Hv[c] + hv * Hu[c] + huv * H[c];
-        e[c] = 2.0 * hv * Hv[c] + hvv * H[c];
+        a[c] = f.Tuu[c] + 2.0 * hu * Hu[c] + huu * H[c];
+        m[c] = f.Tuv[c] + hu * Hv[c] + hv * Hu[c] + huv * H[c];
+        e[c] = f.Tvv[c] + 2.0 * hv * Hv[c] + hvv * H[c];
     }
     if (xuu)
         for (int c = 0; c < 3; ++c) xuu[3 * q + c] = a[c];
@@ -441,7 +439,7 @@ void launch_chart_curvature(Ctx &c, const double *uv, int32_t np, int64_t N, con
                             const double *hess, double *xuu, double *xuv, double *xvv, double *gauss,
                             double *mean) {
     hipLaunchKernelGGL(k_chart_curvature, dim3(blocks256(N)), dim3(256), 0, c.stream, N, c.verts.as<double>(),
-                       c.tris.as<int32_t>(), c.vH.as<double>(), uv, np, h, grad, hess, xuu, xuv, xvv, gauss,
+                       c.tris.as<int32_t>(), chart_tris6(c), c.vH.as<double>(), uv, np, h, grad, hess, xuu, xuv, xvv, gauss,
                        mean);
     LSS_CHECK_LAUNCH("k_chart_curvature");
 }

@@ -280,6 +280,12 @@ struct Ctx {
     }
 };
 
+// six-point triangles of a quadratic skeleton when the chart bases are the
+// curved patches (lss_options.curved_charts), else null (corner triangles)
+inline const int32_t *chart_tris6(const Ctx &c) {
+    return (c.quadratic && c.opt.curved_charts) ? c.tris6.as<int32_t>() : nullptr;
+}
+
 // ------------------------------------------------------- launch wrappers
 // prep (lss_kernels.hip)
 void launch_prep_sources(Ctx &c);

@@ -6,6 +6,7 @@
 #include <cmath>
 
 #include "lss_internal.h"
+#include "chart_frame.h"
 
 namespace lss {
 
@@ -212,6 +213,29 @@ __global__ void k_corner_fill(int64_t ncorner, const int32_t *__restrict__ tris,
     list[off[v] + slot] = q;
 }
 
+// Corner k of triangle q / 3 on a curved patch (tris6): unit normal y_u x y_v
+// at the corner and the angle between the patch's two edges there (their
+// tangents: y_u, y_v at P1; y_v - y_u, -y_u at P2; -y_v, y_u - y_v at P3).
+__device__ void corner_contrib_curved(const double *__restrict__ verts, const int32_t *__restrict__ tris6, int64_t q,
+                                      double &theta, double nh[3]) {
+    const int64_t j = q / 3;
+    const int k = (int)(q - 3 * j);
+    double P1[3], A[3], B[3], C[3], D[3], E[3], yu[3], yv[3], p[3], r[3], N[3], cr[3];
+    patch_coef(verts, tris6 + 6 * j, P1, A, B, C, D, E);
+    for (int c = 0; c < 3; ++c) {
+        yu[c] = A[c] + (k == 1 ? 2.0 * C[c] : (k == 2 ? E[c] : 0.0));
+        yv[c] = B[c] + (k == 1 ? E[c] : (k == 2 ? 2.0 * D[c] : 0.0));
+        p[c] = k == 0 ? yu[c] : (k == 1 ? yv[c] - yu[c] : -yv[c]);
+        r[c] = k == 0 ? yv[c] : (k == 1 ? -yu[c] : yu[c] - yv[c]);
+    }
+    cross3(yu, yv, N);
+    const double nn = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+    if (nn == 0.0) { theta = 0.0; nh[0] = nh[1] = nh[2] = 0.0; return; }
+    cross3(p, r, cr);
+    theta = atan2(sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]), p[0] * r[0] + p[1] * r[1] + p[2] * r[2]);
+    for (int c = 0; c < 3; ++c) nh[c] = N[c] / nn;
+}
+
 __device__ void corner_contrib(const double *__restrict__ verts, const int32_t *__restrict__ tris,
                                int64_t q, double &theta, double nh[3]) {
     int64_t j = q / 3;
@@ -235,8 +259,8 @@ __device__ void corner_contrib(const double *__restrict__ verts, const int32_t *
 }
 
 __global__ void k_vertex_H(int64_t nverts, const double *__restrict__ verts, const int32_t *__restrict__ tris,
-                           const int32_t *__restrict__ off, const int32_t *__restrict__ cnt,
-                           int64_t *list, double *H) {
+                           const int32_t *__restrict__ tris6, const int32_t *__restrict__ off,
+                           const int32_t *__restrict__ cnt, int64_t *list, double *H) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nverts) return;
     int64_t *L = list + off[v];
@@ -250,7 +274,8 @@ __global__ void k_vertex_H(int64_t nverts, const double *__restrict__ verts, con
     double sx = 0, sy = 0, sz = 0, sa = 0;
     for (int a = 0; a < n; ++a) {
         double th, nh[3];
-        corner_contrib(verts, tris, L[a], th, nh);
+        if (tris6) corner_contrib_curved(verts, tris6, L[a], th, nh);
+        else corner_contrib(verts, tris, L[a], th, nh);
         sx += th * nh[0]; sy += th * nh[1]; sz += th * nh[2]; sa += th;
     }
     double inv = sa > 0.0 ? 1.0 / sa : 0.0;
@@ -320,32 +345,28 @@ __device__ inline int32_t mesh_of_tri(const int64_t *tri_off, int32_t nmesh, int
     return lo;
 }
 
-// chart base point T (eq. tparam) and direction H (eq. mkpseudovec) of chart
-// node idx = j * np + i
+// chart base point T and direction H of chart node idx = j * np + i
 __device__ inline void chart_TH(const double *__restrict__ verts, const int32_t *__restrict__ tris,
-                                const double *__restrict__ vH, const double *__restrict__ uv, int32_t np,
-                                int64_t idx, double T[3], double H[3], int64_t &j) {
-    j = idx / np;
-    int i = (int)(idx - j * np);
-    const double u = uv[2 * i], v = uv[2 * i + 1];
-    const int32_t *t = tris + 3 * j;
+                                const int32_t *__restrict__ tris6, const double *__restrict__ vH,
+                                const double *__restrict__ uv, int32_t np, int64_t idx, double T[3], double H[3],
+                                int64_t &j) {
+    ChartFrame f;
+    chart_frame(verts, tris, tris6, vH, uv, np, idx, f, j);
     for (int c = 0; c < 3; ++c) {
-        double p1 = verts[3 * (int64_t)t[0] + c], p2 = verts[3 * (int64_t)t[1] + c], p3 = verts[3 * (int64_t)t[2] + c];
-        double h1 = vH[3 * (int64_t)t[0] + c], h2 = vH[3 * (int64_t)t[1] + c], h3 = vH[3 * (int64_t)t[2] + c];
-        T[c] = p1 + u * (p2 - p1) + v * (p3 - p1);
-        H[c] = h1 + u * (h2 - h1) + v * (h3 - h1);
+        T[c] = f.T[c];
+        H[c] = f.H[c];
     }
 }
 
 __global__ void k_chart_keys(int64_t N, const double *__restrict__ verts, const int32_t *__restrict__ tris,
-                             const double *__restrict__ vH, const double *__restrict__ uv, int32_t np,
+                             const int32_t *__restrict__ tris6, const double *__restrict__ vH, const double *__restrict__ uv, int32_t np,
                              const int64_t *__restrict__ tri_off, int32_t nmesh, Box box,
                              const double *__restrict__ troot, int tbits, uint64_t *keys, int32_t *idx) {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= N) return;
     double T[3], H[3];
     int64_t j;
-    chart_TH(verts, tris, vH, uv, np, q, T, H, j);
+    chart_TH(verts, tris, tris6, vH, uv, np, q, T, H, j);
     uint64_t m = nmesh > 1 ? (uint64_t)mesh_of_tri(tri_off, nmesh, j) : 0;
     if (troot) {        // octree order: the nodes of a leaf are contiguous
         bool inside;
@@ -359,7 +380,7 @@ __global__ void k_chart_keys(int64_t N, const double *__restrict__ verts, const 
 enum { ST_ACTIVE = -1 };
 
 __global__ void k_chart_init(int64_t N, const double *__restrict__ verts, const int32_t *__restrict__ tris,
-                             const double *__restrict__ vH, const double *__restrict__ uv, int32_t np,
+                             const int32_t *__restrict__ tris6, const double *__restrict__ vH, const double *__restrict__ uv, int32_t np,
                              const int64_t *__restrict__ tri_off, int32_t nmesh,
                              const double *__restrict__ sigma, const int32_t *__restrict__ perm,
                              double *Tout, double *Hout, double *h, double *lo, double *hi, double *sig,
@@ -370,7 +391,7 @@ __global__ void k_chart_init(int64_t N, const double *__restrict__ verts, const 
     int64_t q = perm[s];
     double T[3], H[3];
     int64_t j;
-    chart_TH(verts, tris, vH, uv, np, q, T, H, j);
+    chart_TH(verts, tris, tris6, vH, uv, np, q, T, H, j);
     for (int c = 0; c < 3; ++c) { Tout[3 * s + c] = T[c]; Hout[3 * s + c] = H[c]; }
     double sj = sigma[j];
     double nH = sqrt(H[0] * H[0] + H[1] * H[1] + H[2] * H[2]);
@@ -651,8 +672,8 @@ void launch_pseudonormals(Ctx &c) {
     LSS_CHECK_LAUNCH("k_corner_fill");
     c.vH.ensure(sizeof(double) * 3 * c.nverts);
     hipLaunchKernelGGL(k_vertex_H, dim3(grid_for(c.nverts)), dim3(kBlk), 0, c.stream, c.nverts,
-                       c.verts.as<double>(), c.tris.as<int32_t>(), off.as<int32_t>(), cnt.as<int32_t>(),
-                       list.as<int64_t>(), c.vH.as<double>());
+                       c.verts.as<double>(), c.tris.as<int32_t>(), chart_tris6(c), off.as<int32_t>(),
+                       cnt.as<int32_t>(), list.as<int64_t>(), c.vH.as<double>());
     LSS_CHECK_LAUNCH("k_vertex_H");
     LSS_HIP(hipStreamSynchronize(c.stream));
     cnt.release(); off.release(); fill.release(); list.release();
@@ -680,7 +701,7 @@ void launch_chart_init(Ctx &c, const double *uv, int32_t np, int64_t N) {
     c.tperm.ensure(sizeof(int32_t) * N);
     c.tperm2.ensure(sizeof(int32_t) * N);
     hipLaunchKernelGGL(k_chart_keys, dim3(grid_for(N)), dim3(kBlk), 0, c.stream, N, c.verts.as<double>(),
-                       c.tris.as<int32_t>(), c.vH.as<double>(), uv, np, c.tri_off.as<int64_t>(), c.nmesh,
+                       c.tris.as<int32_t>(), chart_tris6(c), c.vH.as<double>(), uv, np, c.tri_off.as<int64_t>(), c.nmesh,
                        make_box(c), fmm ? c.tree.root.as<double>() : nullptr, c.tree.bits, c.tkey.as<uint64_t>(),
                        c.tperm.as<int32_t>());
     LSS_CHECK_LAUNCH("k_chart_keys");
@@ -706,7 +727,7 @@ void launch_chart_init(Ctx &c, const double *uv, int32_t np, int64_t N) {
     s.nact.ensure(sizeof(int32_t) * 4);
     s.hist.ensure(sizeof(int32_t) * kHistCap);
     hipLaunchKernelGGL(k_chart_init, dim3(grid_for(N)), dim3(kBlk), 0, c.stream, N, c.verts.as<double>(),
-                       c.tris.as<int32_t>(), c.vH.as<double>(), uv, np, c.tri_off.as<int64_t>(), c.nmesh,
+                       c.tris.as<int32_t>(), chart_tris6(c), c.vH.as<double>(), uv, np, c.tri_off.as<int64_t>(), c.nmesh,
                        c.sigma.as<double>(), c.tperm2.as<int32_t>(), s.T.as<double>(), s.H.as<double>(),
                        s.h.as<double>(), s.lo.as<double>(), s.hi.as<double>(), s.sig.as<double>(),
                        s.mesh.as<int32_t>(), s.orig.as<int32_t>(), s.status.as<int8_t>(), s.iters.as<int8_t>(),
@@ -822,14 +843,14 @@ namespace {
 
 // chart point x = T + h H of node q (eq. chart) and its mesh (batches)
 __global__ void k_chart_points(int64_t N, const double *__restrict__ verts, const int32_t *__restrict__ tris,
-                               const double *__restrict__ vH, const double *__restrict__ uv, int32_t np,
+                               const int32_t *__restrict__ tris6, const double *__restrict__ vH, const double *__restrict__ uv, int32_t np,
                                const int64_t *__restrict__ tri_off, int32_t nmesh, const double *__restrict__ h,
                                double *x, int32_t *xmesh) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= N) return;
     double T[3], H[3];
     int64_t j;
-    chart_TH(verts, tris, vH, uv, np, q, T, H, j);
+    chart_TH(verts, tris, tris6, vH, uv, np, q, T, H, j);
     const double hq = h[q];
     for (int c = 0; c < 3; ++c) x[3 * q + c] = T[c] + hq * H[c];
     if (xmesh) xmesh[q] = mesh_of_tri(tri_off, nmesh, j);
@@ -837,30 +858,23 @@ __global__ void k_chart_points(int64_t N, const double *__restrict__ verts, cons
 
 // Tangents, area element and unit normal of the chart x = T + h H at node q
 // (section 3.1, eq. u_vector, U_vector_2, v_vector, v_vector_2, eq. da):
-// T and H are linear in (u, v) on the triangle (eq. tparam, mkpseudovec), so
-// T_u = P2 - P1, H_u = H2 - H1 (likewise in v); dh/du follows from x_u being
-// tangent to the level set, i.e. orthogonal to grad Phi; the outward unit
-// normal is -grad Phi / |grad Phi| (Phi grows inward).  Any output may be null.
+// H is linear in (u, v) on the triangle (eq. mkpseudovec), H_u = H2 - H1
+// (likewise in v); T_u, T_v are those of the chart base (the corner triangle,
+// or the curved patch); dh/du follows from x_u being tangent to the level
+// set, i.e. orthogonal to grad Phi; the outward unit normal is
+// -grad Phi / |grad Phi| (Phi grows inward).  Any output may be null.
 __global__ void k_chart_geometry(int64_t N, const double *__restrict__ verts, const int32_t *__restrict__ tris,
-                                 const double *__restrict__ vH, const double *__restrict__ uv, int32_t np,
-                                 const double *__restrict__ h, const double *__restrict__ grad, double *xu,
-                                 double *xv, double *da, double *nrm) {
+                                 const int32_t *__restrict__ tris6, const double *__restrict__ vH,
+                                 const double *__restrict__ uv, int32_t np, const double *__restrict__ h,
+                                 const double *__restrict__ grad, double *xu, double *xv, double *da, double *nrm) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= N) return;
-    double T[3], H[3];
+    ChartFrame f;
     int64_t j;
-    chart_TH(verts, tris, vH, uv, np, q, T, H, j);
-    const int32_t *t = tris + 3 * j;
-    double Tu[3], Tv[3], Hu[3], Hv[3], g[3];
-    for (int c = 0; c < 3; ++c) {
-        const double p1 = verts[3 * (int64_t)t[0] + c];
-        const double h1 = vH[3 * (int64_t)t[0] + c];
-        Tu[c] = verts[3 * (int64_t)t[1] + c] - p1;
-        Tv[c] = verts[3 * (int64_t)t[2] + c] - p1;
-        Hu[c] = vH[3 * (int64_t)t[1] + c] - h1;
-        Hv[c] = vH[3 * (int64_t)t[2] + c] - h1;
-        g[c] = grad[3 * q + c];
-    }
+    chart_frame(verts, tris, tris6, vH, uv, np, q, f, j);
+    const double *H = f.H, *Tu = f.Tu, *Tv = f.Tv, *Hu = f.Hu, *Hv = f.Hv;
+    double g[3];
+    for (int c = 0; c < 3; ++c) g[c] = grad[3 * q + c];
     const double hq = h[q];
     double au[3], av[3];                      // T_u + h H_u, T_v + h H_v
     for (int c = 0; c < 3; ++c) {
@@ -894,7 +908,7 @@ __global__ void k_chart_geometry(int64_t N, const double *__restrict__ verts, co
 void launch_chart_points(Ctx &c, const double *uv, int32_t np, int64_t N, const double *h, double *x,
                          int32_t *xmesh) {
     hipLaunchKernelGGL(k_chart_points, dim3(grid_for(N)), dim3(kBlk), 0, c.stream, N, c.verts.as<double>(),
-                       c.tris.as<int32_t>(), c.vH.as<double>(), uv, np, c.tri_off.as<int64_t>(), c.nmesh, h, x,
+                       c.tris.as<int32_t>(), chart_tris6(c), c.vH.as<double>(), uv, np, c.tri_off.as<int64_t>(), c.nmesh, h, x,
                        xmesh);
     LSS_CHECK_LAUNCH("k_chart_points");
 }
@@ -902,7 +916,7 @@ void launch_chart_points(Ctx &c, const double *uv, int32_t np, int64_t N, const 
 void launch_chart_geometry(Ctx &c, const double *uv, int32_t np, int64_t N, const double *h, const double *grad,
                            double *xu, double *xv, double *da, double *nrm) {
     hipLaunchKernelGGL(k_chart_geometry, dim3(grid_for(N)), dim3(kBlk), 0, c.stream, N, c.verts.as<double>(),
-                       c.tris.as<int32_t>(), c.vH.as<double>(), uv, np, h, grad, xu, xv, da, nrm);
+                       c.tris.as<int32_t>(), chart_tris6(c), c.vH.as<double>(), uv, np, h, grad, xu, xv, da, nrm);
     LSS_CHECK_LAUNCH("k_chart_geometry");
 }
 

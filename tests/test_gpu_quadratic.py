@@ -154,3 +154,63 @@ def test_quadratic_device_inputs_and_index_check():
     assert e.value.code == 1
     with pytest.raises(ValueError):
         lss.Context().set_sources(v, t[:, :5].copy(), dunavant6())
+
+
+def rel(a, b):
+    return np.max(np.abs(np.asarray(a) - b)) / np.max(np.abs(b))
+
+
+@pytest.mark.parametrize("prec", [lss.FP64, lss.MIXED])
+def test_curved_charts_vs_oracle(prec):
+    """Chart bases on the curved patches (curved_charts = 1): T is the
+    quadratic patch, H interpolates the curved-vertex pseudonormals.  The
+    projection, then (FP64) the chart tangents, area element, normal, second
+    derivatives and curvatures, against the oracle's curved charts."""
+    v, t = torus_mesh(24, 12, quadratic=True)
+    sigma = 0.05
+    uv = chart_nodes(2)
+    say("case: curved chart bases on a quadratic torus %d tri, np=6, FMM, precision %d" % (len(t), prec))
+    c = ctx(v, t, [sigma], prec, lss.FAR_FMM, curved_charts=1)
+    h, x, st, it = c.project(uv)
+    sel = np.arange(0, len(t), 17)
+    tau = 1e-12 if prec == lss.FP64 else 1e-6
+    ho, xo, sto, ito = oracle.project(v, t, [sigma], dunavant6(), uv, tau=tau, sel=sel, curved=True)
+    idx = (sel[:, None] * len(uv) + np.arange(len(uv))[None]).ravel()
+    assert np.all(st == 0) and np.all(sto == 0)
+    eh = np.max(np.abs(h[idx] - ho)) / sigma
+    ex = np.max(np.linalg.norm(x[idx] - xo, axis=1)) / sigma
+    hf, _, _, _ = ctx(v, t, [sigma], prec, lss.FAR_FMM).project(uv)
+    say("  e_h %.3e e_x %.3e iters max %d; max |h curved - h flat| / sigma %.3e"
+        % (eh, ex, it.max(), np.max(np.abs(h - hf)) / sigma))
+    bar = 1e-11 if prec == lss.FP64 else 2e-6
+    assert eh <= bar and ex <= bar
+    assert np.max(np.abs(h - hf)) / sigma > 1e-2          # the bases differ
+    if prec != lss.FP64:
+        return
+    geo = c.chart_geometry(uv, h)
+    ogeo = oracle.chart_geometry(v, t, [sigma], dunavant6(), uv, h[idx], sel=sel, curved=True)
+    eg = [rel(a[idx], b) for a, b in zip(geo, ogeo)]
+    cur = c.chart_curvature(uv, h)
+    ocur = oracle.chart_curvature(v, t, [sigma], dunavant6(), uv, h[idx], sel=sel, curved=True)
+    ec = [rel(a[idx], b) for a, b in zip(cur, ocur)]
+    say("  geometry e_xu %.2e e_xv %.2e e_da %.2e e_n %.2e" % tuple(eg))
+    say("  curvature e_xuu %.2e e_xuv %.2e e_xvv %.2e e_gauss %.2e e_mean %.2e" % tuple(ec))
+    assert max(eg) <= 1e-10 and max(ec) <= 1e-9
+
+
+def test_curved_charts_on_midpoint_edges_equal_flat():
+    """Edge points at the edge midpoints make every patch flat: the curved
+    chart bases then reproduce the flat ones."""
+    v, t = icosphere(2)
+    v6, t6 = quadratic_from_flat(v, t)
+    uv = chart_nodes(2)
+    say("case: curved chart bases with midpoint edge points vs flat charts, %d tri" % len(t))
+    h3, x3, s3, _ = ctx(v, t, [0.1], lss.FP64, lss.FAR_FMM).project(uv)
+    c6 = ctx(v6, t6, [0.1], lss.FP64, lss.FAR_FMM, curved_charts=1)
+    h6, x6, s6, _ = c6.project(uv)
+    e = np.max(np.abs(h6 - h3)) / 0.1
+    k3 = ctx(v, t, [0.1], lss.FP64, lss.FAR_FMM).chart_curvature(uv, h3)
+    k6 = c6.chart_curvature(uv, h6)
+    ek = max(rel(a, b) for a, b in zip(k6, k3))
+    say("  e_h %.2e e_curvature %.2e" % (e, ek))
+    assert np.array_equal(s3, s6) and e <= 1e-12 and ek <= 1e-9

@@ -96,20 +96,24 @@ def test_quadratic_torus_study():
     p = 4 charts at three resolutions.  The curved skeleton's charts lie
     several times closer to the torus and are more water-tight (eps_0 about
     x0 = (1, 0.05, 0.1), inside the tube); both distances fall with
-    refinement.  The coarsest quadratic level is checked against the oracle."""
+    refinement.  The quadratic skeleton is projected twice: with chart bases
+    on the corner triangles and on the curved patches (curved_charts = 1);
+    both land on the same level set, the curved bases from much closer
+    (smaller |h|).  The coarsest quadratic level is checked against the
+    oracle."""
     x0 = np.array([1.0, 0.05, 0.1])
     uv = chart_nodes(4)
     w = simplex_weights(uv, 4)
     rows = {}
     for lev, (nu, nv) in enumerate(((24, 12), (48, 24), (96, 48))):
-        for quad in (False, True):
+        for quad, curved in ((False, 0), (True, 0), (True, 1)):
             v, t = torus_mesh(nu, nv, quadratic=quad)
             corner = np.ascontiguousarray(t[:, :3])
             sig = triangle_diameters(v, corner) / 10.0
             c = lss.Context()
             c.set_sources(v, t, dunavant6())
             c.set_sigma(sig)
-            c.set_options(precision=lss.FP64, far_field=lss.FAR_FMM)
+            c.set_options(precision=lss.FP64, far_field=lss.FAR_FMM, curved_charts=curved)
             h, x, st, it = c.project(uv)
             assert np.all(st == lss.NODE_CONVERGED)
             xu, xv, da, nr = c.chart_geometry(uv, h)
@@ -119,22 +123,26 @@ def test_quadratic_torus_study():
             f = np.sum(nr * d, axis=1) / (4 * np.pi * r ** 3)
             e0 = 1.0 + np.sum((f * da).reshape(len(t), -1) * w[None, :])
             dist = torus_distance(x)
-            rows[(lev, quad)] = (dist.max(), e0)
-            say("torus %3d x %2d  %-9s  M %5d  max dist %.2e  mean dist %.2e  eps_0 %+.2e  k %d" % (
-                nu, nv, "quadratic" if quad else "flat", len(t), dist.max(), dist.mean(), e0, int(it.max())))
+            name = ("flat", "quadratic", "curved")[int(quad) + curved]
+            hs = np.abs(h) / np.repeat(sig, len(uv))
+            rows[(lev, name)] = (dist.max(), e0, hs.max())
+            say("torus %3d x %2d  %-9s  M %5d  max dist %.2e  mean dist %.2e  eps_0 %+.2e  max |h|/sigma %.2e  k %d"
+                % (nu, nv, name, len(t), dist.max(), dist.mean(), e0, hs.max(), int(it.max())))
             if lev == 0 and quad:
                 sel = np.arange(0, len(t), 11)
-                ho, xo, sto, ito = oracle.project(v, t, sig, dunavant6(), uv, sel=sel)
+                ho, xo, sto, ito = oracle.project(v, t, sig, dunavant6(), uv, sel=sel, curved=bool(curved))
                 idx = (sel[:, None] * len(uv) + np.arange(len(uv))[None]).ravel()
                 eh = np.max(np.abs(h[idx] - ho) / np.repeat(sig[sel], len(uv)))
                 say("  oracle: max |h - h_oracle| / sigma %.1e" % eh)
                 assert np.all(sto == 0) and eh < 1e-11
             c.close()
     for lev in range(3):
-        assert rows[(lev, True)][0] < 0.2 * rows[(lev, False)][0]
-        assert abs(rows[(lev, True)][1]) < abs(rows[(lev, False)][1])
-    for quad in (False, True):
-        assert rows[(2, quad)][0] < rows[(1, quad)][0] < rows[(0, quad)][0]
+        assert rows[(lev, "quadratic")][0] < 0.2 * rows[(lev, "flat")][0]
+        assert abs(rows[(lev, "quadratic")][1]) < abs(rows[(lev, "flat")][1])
+        assert rows[(lev, "curved")][0] < 1.5 * rows[(lev, "quadratic")][0]
+        assert rows[(lev, "curved")][2] < 0.5 * rows[(lev, "quadratic")][2]
+    for name in ("flat", "quadratic", "curved"):
+        assert rows[(2, name)][0] < rows[(1, name)][0] < rows[(0, name)][0]
 
 
 def test_refinement_of_quadratic_skeletons():
