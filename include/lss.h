@@ -127,7 +127,11 @@ typedef struct lss_options {
                                  vertex pseudonormals of the curved triangles: their corner
                                  normals y_u x y_v weighted by their corner angles); 0 = bases on
                                  the corner triangles.  No effect on flat skeletons. */
-    int32_t reserved[3];      /* must be zero */
+    int32_t sigma_interp;     /* how lss_eval_multiscale with LSS_FAR_FMM forms sigma(x): 0 = automatic
+                                 (interpolated when the cells' nodes number under a quarter of the
+                                 points, else the direct sum), 1 = always the direct sum, 2 =
+                                 interpolated wherever the cell grid applies */
+    int32_t reserved[2];      /* must be zero */
 } lss_options;
 
 typedef struct lss_stats {
@@ -326,15 +330,22 @@ int lss_eval_hessian(lss_ctx *ctx, const double *x, const int32_t *x_mesh, int64
  * paper's suggestion, with lambda about 2.5).  Phi sums every node of the
  * mesh with width sigma(x); grad Phi is the exact x-derivative, including
  * (dPhi/dsigma) grad sigma.  x (n,3), x_mesh as for lss_eval; phi (n); grad
- * (n,3) and sigma_x (n, receives sigma(x)) may be NULL.  sigma(x) is a direct
- * FP64 sum over the centroids of the target's mesh.  LSS_FAR_DIRECT: Phi is
- * a direct FP64 sum over the mesh's nodes.  LSS_FAR_FMM: an octree is built
- * with cut widths equal to each mesh's largest sigma_j (an upper bound of
- * sigma(x)), the near lists are summed at the target's width and the far
- * field comes from the expansions (accuracy as for lss_eval with the same
- * options); the context's own sigma is left as it was, and its built state
- * is rebuilt on the next call that needs it.  Needs sources, not sigma
- * (LSS_ESTATE otherwise).
+ * (n,3) and sigma_x (n, receives sigma(x)) may be NULL.
+ * LSS_FAR_DIRECT: sigma(x) is a direct FP64 sum over the centroids of the
+ * target's mesh and Phi a direct FP64 sum over the mesh's nodes.
+ * LSS_FAR_FMM: sigma(x) and grad sigma come from the direct sum, or (option
+ * sigma_interp) from tensor Chebyshev interpolation of the weight sums
+ * sum_j w_j, sum_j sigma_j w_j and their first moments in cells of side
+ * 1.5 sigma0 (17 nodes per axis, each node value a direct FP64 sum; the
+ * interpolation error is below the sums' own rounding), with the direct sum
+ * for points outside the cells or farther than 3 sigma0 from every centroid.
+ * The octree is built with leaves sized by sigma(x) at the centroids, the
+ * near lists are cut per box at the largest sigma(x) of its targets and
+ * summed at each target's width, and the far field comes from the
+ * expansions (accuracy as for lss_eval with the same options); the
+ * context's own sigma is left as it was, and its built state is rebuilt on
+ * the next call that needs it.  Needs sources, not sigma (LSS_ESTATE
+ * otherwise).
  * lambda <= 0, sigma0 < 0 or non-finite give LSS_EINVAL.  Host or device
  * arrays per flags; returns when the outputs are written. */
 int lss_eval_multiscale(lss_ctx *ctx, double lambda, double sigma0, const double *x, const int32_t *x_mesh,

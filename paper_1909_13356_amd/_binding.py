@@ -42,7 +42,7 @@ class Options(ctypes.Structure):
                 ("newton_max_iter", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("leaf_shrink", ctypes.c_double), ("count_useful", ctypes.c_int32),
                 ("admissibility", ctypes.c_int32), ("curved_charts", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("sigma_interp", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class Stats(ctypes.Structure):
@@ -208,10 +208,10 @@ class Context:
 
     def set_options(self, precision=FP64, far_field=FAR_DIRECT, fmm_order=0, leaf_capacity=0,
                     cut_factor=0.0, newton_tau=0.0, newton_max_iter=0, tile=0, leaf_shrink=0.0,
-                    count_useful=0, admissibility=0, curved_charts=0):
+                    count_useful=0, admissibility=0, curved_charts=0, sigma_interp=0):
         o = Options(precision, far_field, fmm_order, leaf_capacity, cut_factor, newton_tau,
                     newton_max_iter, tile, leaf_shrink, int(bool(count_useful)), admissibility,
-                    int(bool(curved_charts)))
+                    int(bool(curved_charts)), sigma_interp)
         self._check(self._lib.lss_set_options(self._h, ctypes.byref(o)))
 
     def get_options(self):

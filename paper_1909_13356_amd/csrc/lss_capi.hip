@@ -138,7 +138,8 @@ void validate_options(const lss_options &o) {
     if (o.admissibility != 0 && (o.admissibility < 4 || o.admissibility > 18))
         fail(LSS_EINVAL, "admissibility must be 0 (default) or in [4, 18]");
     if (o.curved_charts != 0 && o.curved_charts != 1) fail(LSS_EINVAL, "curved_charts must be 0 or 1");
-    for (int k = 0; k < 3; ++k)
+    if (o.sigma_interp < 0 || o.sigma_interp > 2) fail(LSS_EINVAL, "sigma_interp must be 0, 1 or 2");
+    for (int k = 0; k < 2; ++k)
         if (o.reserved[k] != 0) fail(LSS_EINVAL, "reserved option fields must be zero");
 }
 
@@ -631,22 +632,42 @@ void eval_multiscale(Ctx &c, double lambda, double sigma0, const double *x, cons
         // afterwards: the built state is then stale and rebuilt on use); the
         // lists are built for these targets, with cut * sigma(x) as the
         // radius every far interaction must clear
-        DBuf tsig, tgs, cpt, cxm, csig, cgs, saved;
-        tsig.ensure(sizeof(double) * n);
-        tgs.ensure(sizeof(double) * 3 * n);
-        launch_sigma_field(c, n, dx, dxm, cen.as<Cen>(), cbox.as<double>(), s0.as<double>(), tsig.as<double>(),
-                           tgs.as<double>());
-        cpt.ensure(sizeof(double) * 3 * c.ntris);
-        cxm.ensure(sizeof(int32_t) * c.ntris);
-        csig.ensure(sizeof(double) * c.ntris);
-        cgs.ensure(sizeof(double) * 3 * c.ntris);
-        hipLaunchKernelGGL(k_cen_points, dim3(grid_for(c.ntris)), dim3(256), 0, c.stream, c.ntris, cen.as<Cen>(),
+        DBuf sall, gall, xall, xmall, cpt, cxm, saved;
+        const int64_t nt = c.ntris, na = n + nt;
+        sall.ensure(sizeof(double) * na);
+        gall.ensure(sizeof(double) * 3 * na);
+        cpt.ensure(sizeof(double) * 3 * nt);
+        cxm.ensure(sizeof(int32_t) * nt);
+        hipLaunchKernelGGL(k_cen_points, dim3(grid_for(nt)), dim3(256), 0, c.stream, nt, cen.as<Cen>(),
                            c.tri_off.as<int64_t>(), c.nmesh, cpt.as<double>(), cxm.as<int32_t>());
         LSS_CHECK_LAUNCH("k_cen_points");
-        launch_sigma_field(c, c.ntris, cpt.as<double>(), c.nmesh > 1 ? cxm.as<int32_t>() : nullptr, cen.as<Cen>(),
-                           cbox.as<double>(), s0.as<double>(), csig.as<double>(), cgs.as<double>());
+        // one pass over the targets and the centroids together: the
+        // interpolation cells then serve both
+        bool done = false;
+        if (c.opt.sigma_interp != 1) {
+            xall.ensure(sizeof(double) * 3 * na);
+            LSS_HIP(hipMemcpyAsync(xall.p, dx, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, c.stream));
+            LSS_HIP(hipMemcpyAsync(xall.as<double>() + 3 * n, cpt.p, sizeof(double) * 3 * nt, hipMemcpyDeviceToDevice,
+                                   c.stream));
+            if (dxm) {
+                xmall.ensure(sizeof(int32_t) * na);
+                LSS_HIP(hipMemcpyAsync(xmall.p, dxm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c.stream));
+                LSS_HIP(hipMemcpyAsync(xmall.as<int32_t>() + n, cxm.p, sizeof(int32_t) * nt, hipMemcpyDeviceToDevice,
+                                       c.stream));
+            }
+            done = sigma_field_interp(c, na, xall.as<double>(), dxm ? xmall.as<int32_t>() : nullptr, cen.as<Cen>(),
+                                      cbox.as<double>(), s0.as<double>(), hs0.data(), sall.as<double>(),
+                                      gall.as<double>(), c.opt.sigma_interp == 2);
+        }
+        if (!done) {
+            launch_sigma_field(c, n, dx, dxm, cen.as<Cen>(), cbox.as<double>(), s0.as<double>(), sall.as<double>(),
+                               gall.as<double>());
+            launch_sigma_field(c, nt, cpt.as<double>(), c.nmesh > 1 ? cxm.as<int32_t>() : nullptr, cen.as<Cen>(),
+                               cbox.as<double>(), s0.as<double>(), sall.as<double>() + n, gall.as<double>() + 3 * n);
+        }
+        double *tsig = sall.as<double>(), *tgs = gall.as<double>(), *csig = sall.as<double>() + n;
         std::vector<double> hcs(c.ntris);
-        LSS_HIP(hipMemcpyAsync(hcs.data(), csig.p, sizeof(double) * c.ntris, hipMemcpyDeviceToHost, c.stream));
+        LSS_HIP(hipMemcpyAsync(hcs.data(), csig, sizeof(double) * c.ntris, hipMemcpyDeviceToHost, c.stream));
         LSS_HIP(hipStreamSynchronize(c.stream));
         double mn = INFINITY, mx = 0.0;
         for (double v : hcs) { mn = std::min(mn, v); mx = std::max(mx, v); }
@@ -672,12 +693,12 @@ void eval_multiscale(Ctx &c, double lambda, double sigma0, const double *x, cons
             LSS_HIP(hipMemcpyAsync(saved.p, c.sigma.p, sizeof(double) * c.ntris, hipMemcpyDeviceToDevice, c.stream));
         }
         c.sigma.ensure(sizeof(double) * c.ntris);
-        LSS_HIP(hipMemcpyAsync(c.sigma.p, csig.p, sizeof(double) * c.ntris, hipMemcpyDeviceToDevice, c.stream));
+        LSS_HIP(hipMemcpyAsync(c.sigma.p, csig, sizeof(double) * c.ntris, hipMemcpyDeviceToDevice, c.stream));
         c.have_sigma = true;
         c.sigma_min = mn;
         c.sigma_max = mx;
         c.built = false;
-        const TargetWidths tw{dx, dxm, tsig.as<double>(), n};
+        const TargetWidths tw{dx, dxm, tsig, n};
         c.target_widths = &tw;
         build(c);
         c.target_widths = nullptr;
@@ -685,9 +706,9 @@ void eval_multiscale(Ctx &c, double lambda, double sigma0, const double *x, cons
         c.ev_reset();
         launch_soa(c, dx, n, b.tx, b.ty, b.tz);
         if (dxm) LSS_HIP(hipMemcpyAsync(b.tmesh, dxm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c.stream));
-        const MsArgs ms{tsig.as<double>(), tgs.as<double>()};
+        const MsArgs ms{tsig, tgs};
         eval_fmm_bufs(c, b, n, dphi, dgrad, nullptr, &ms);
-        if (dsig) LSS_HIP(hipMemcpyAsync(dsig, tsig.p, sizeof(double) * n, hipMemcpyDeviceToDevice, c.stream));
+        if (dsig) LSS_HIP(hipMemcpyAsync(dsig, tsig, sizeof(double) * n, hipMemcpyDeviceToDevice, c.stream));
         LSS_HIP(hipStreamSynchronize(c.stream));
     } else {
         raw.ensure(sizeof(RawNode) * c.ntris * c.nq);

@@ -294,6 +294,13 @@ void launch_centroids(Ctx &c, double lambda, Cen *out, double *D);
 void launch_cen_boxes(Ctx &c, const Cen *cen, double *box);
 void launch_sigma_field(Ctx &c, int64_t n, const double *x, const int32_t *xm, const Cen *cen, const double *cbox,
                         const double *sigma0, double *sig, double *gsig);
+// sigma(x) and grad sigma by Chebyshev interpolation of the weight sums in
+// cells of side 1.5 sigma0 (lss_sigma.hip), the direct sum for the points no
+// cell serves; s0_host / s0_dev: sigma0 per mesh.  Returns false, having
+// written nothing, when the cells would hold more than a quarter as many
+// nodes as there are points (unless force) or more than the storage cap.
+bool sigma_field_interp(Ctx &c, int64_t n, const double *x, const int32_t *xm, const Cen *cen, const double *cbox,
+                        const double *s0_dev, const double *s0_host, double *sig, double *gsig, bool force);
 void launch_eval_multiscale(Ctx &c, int64_t n, const double *x, const int32_t *xm, const Cen *cen,
                             const double *cbox, const RawNode *nodes, const double *sigma0, double *phi,
                             double *grad, double *sig);

@@ -33,8 +33,8 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts():
     from paper_1909_13356_amd._binding import Options, Stats
     # lss_options: 4 int32, 2 double, 2 int32, 1 double, count_useful, admissibility, curved_charts,
-    # 3 int32 reserved
-    assert ctypes.sizeof(Options) == 4 * 4 + 2 * 8 + 2 * 4 + 8 + 4 + 4 + 4 + 3 * 4
+    # sigma_interp, 2 int32 reserved
+    assert ctypes.sizeof(Options) == 4 * 4 + 2 * 8 + 2 * 4 + 8 + 4 + 4 + 4 + 4 + 2 * 4
     assert ctypes.sizeof(Stats) == 8 * 2 + 4 * 2 + 8 * 3 + 4 * 2 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8 + 8
 
 

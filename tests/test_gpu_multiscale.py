@@ -45,8 +45,8 @@ def test_multiscale_vs_oracle(lam, sigma0):
     assert max(e) <= 1e-12
 
 
-@pytest.mark.parametrize("far", [lss.FAR_DIRECT, lss.FAR_FMM])
-def test_multiscale_batch_of_a_quadratic_torus_and_a_cube(far):
+@pytest.mark.parametrize("far,interp", [(lss.FAR_DIRECT, 0), (lss.FAR_FMM, 1), (lss.FAR_FMM, 2)])
+def test_multiscale_batch_of_a_quadratic_torus_and_a_cube(far, interp):
     vt, tt = torus_mesh(16, 8, quadratic=True)
     vc, tc = cube_mesh(4, 2.0, 3.0)
     # the cube as quadratic triangles with their own (unshared) edge midpoints
@@ -57,9 +57,9 @@ def test_multiscale_batch_of_a_quadratic_torus_and_a_cube(far):
     off = np.array([0, len(tt), len(t6)], np.int64)
     x = np.concatenate([box_targets(300, -1.5, 1.5, seed=1), box_targets(300, 1.8, 3.2, seed=3)])
     xm = np.repeat(np.array([0, 1], np.int32), [300, 300])
-    say("case: multiscale, batch of a quadratic torus and a cube, far field %d" % far)
+    say("case: multiscale, batch of a quadratic torus and a cube, far field %d, sigma_interp %d" % (far, interp))
     c = ctx(v, t6, offsets=off)
-    c.set_options(precision=lss.FP64, far_field=far)
+    c.set_options(precision=lss.FP64, far_field=far, sigma_interp=interp)
     p, g, s = c.eval_multiscale(x, 2.5, 0.0, x_mesh=xm)
     po, go, so = oracle.evaluate_multiscale(v, t6, dunavant6(), x, 2.5, 0.0, tri_offsets=off, x_mesh=xm)
     e = rel(p, po), rel(g, go), rel(s, so)
@@ -156,4 +156,48 @@ def test_multiscale_octree_on_a_graded_torus(sigma0):
     po, go, so = oracle.evaluate_multiscale(v, t, dunavant6(), x[::40], 2.5, sigma0)
     e = rel(p[::40], po), rel(g[::40], go), rel(s[::40], so)
     say("  vs oracle: e_phi %.2e e_grad %.2e e_sigma %.2e" % e)
+    assert max(e) <= 1e-12
+
+
+def test_sigma_interpolation_against_the_direct_sum():
+    """sigma(x) from the Chebyshev cells (sigma_interp = 2) against the direct
+    sum (sigma_interp = 1), octree path, on a graded torus with sigma0 =
+    sqrt(5) max D: near-surface and box targets, the centre of the hole
+    (within 3 sigma0 of the centroids: interpolated), points 4 sigma0 above
+    the torus (cells beyond 3 sigma0: direct sum) and far outside the grid
+    (direct sum).  sigma within 1e-13, Phi and grad Phi (which carries grad
+    sigma) within 1e-12; the automatic choice equals one of the two; the
+    oracle on a sample."""
+    from workloads import graded_torus
+    v, t = graded_torus(n_tris=12000, seed=21)
+    sig = 0.5 * triangle_diameters(v, t)
+    s0 = np.sqrt(5.0) * (2 * sig).max()
+    cen = v[t].mean(1)
+    lo, hi = cen.min(0), cen.max(0)
+    # two points within 3 sigma0 of the centroids' box (inside the grid) in
+    # corner cells more than 3 sigma0 from every centroid, two outside it
+    x = np.concatenate([surface_offset_targets(v, t, sig, 8000, tmax=3.0, seed=24),
+                        box_targets(300, -1.5, 1.5, seed=25),
+                        np.array([[0.0, 0.0, 0.0], [hi[0] + 2.5 * s0, hi[1] + 2.5 * s0, 0.0],
+                                  [lo[0] - 2.6 * s0, hi[1] + 2.4 * s0, 0.1], [9.0, 1.0, 2.0], [-40.0, 3.0, 0.0]])])
+    say("case: sigma(x) interpolation vs the direct sum, graded torus %d tri, sigma0 %.3f, %d targets"
+        % (len(t), s0, len(x)))
+    out = {}
+    for mode in (1, 2, 0):
+        c = ctx(v, t)
+        c.set_options(precision=lss.FP64, far_field=lss.FAR_FMM, sigma_interp=mode)
+        out[mode] = c.eval_multiscale(x, 2.5, 0.0)
+        c.close()
+    (pd, gd, sd), (pi, gi, si) = out[1], out[2]
+    e = rel(pi, pd), rel(gi, gd), rel(si, sd)
+    say("  interpolated vs direct sum: e_phi %.2e e_grad %.2e e_sigma %.2e" % e)
+    assert e[0] <= 1e-12 and e[1] <= 1e-12 and e[2] <= 1e-13
+    assert not np.array_equal(si, sd)                       # the cells were used
+    assert np.array_equal(si[-4:], sd[-4:])                 # the direct sum beyond 3 sigma0 and the grid
+    pa, ga, sa = out[0]
+    assert np.array_equal(sa, sd) or np.array_equal(sa, si)
+    sel = np.concatenate([np.arange(0, 8300, 83), np.arange(8300, len(x))])
+    po, go, so = oracle.evaluate_multiscale(v, t, dunavant6(), x[sel], 2.5, 0.0)
+    e = rel(pi[sel], po), rel(gi[sel], go), rel(si[sel], so)
+    say("  interpolated vs oracle: e_phi %.2e e_grad %.2e e_sigma %.2e" % e)
     assert max(e) <= 1e-12
