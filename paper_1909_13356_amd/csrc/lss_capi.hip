@@ -883,11 +883,15 @@ void autotune(Ctx &c, const double *x, int64_t n, unsigned flags, double w, cons
     try {
         if (base.far_field == LSS_FAR_FMM) {
             const bool mixed = base.precision == LSS_MIXED;
+            const int p0 = mixed ? 20 : 26, K0 = mixed ? 4 : 8;
             // stage 1: leaves (shrink over [1, 3], capacity) and tile at the default K and p
+            // (written out, so that the choice names them)
             for (double sh : {1.0, 1.25, 1.5, 2.0, 2.5, 3.0})
                 for (int cp_ : {64, 256})
                     for (int tl : mixed ? std::vector<int>{64} : std::vector<int>{64, 128}) {
                         lss_options o = base;
+                        o.fmm_order = p0;
+                        o.admissibility = K0;
                         o.leaf_shrink = sh;
                         o.leaf_capacity = cp_;
                         o.tile = tl;
@@ -896,9 +900,9 @@ void autotune(Ctx &c, const double *x, int64_t n, unsigned flags, double w, cons
             // stage 2: admissibility K and order p at the best leaves (order
             // outermost: the translation operators are rebuilt per order)
             const lss_options leaves = best;
-            const int p0 = mixed ? 20 : 26, K0 = mixed ? 4 : 8;
             for (int dp : {-4, -2, 0, 2})
                 for (int dK : {0, 2, 4}) {
+                    if (dp == 0 && dK == 0) continue;     // timed in stage 1
                     lss_options o = leaves;
                     o.fmm_order = p0 + dp;
                     o.admissibility = K0 + dK;
@@ -1016,6 +1020,9 @@ void lss_destroy(lss_ctx *ctx) {
     lss::drop_newton_graph(c.ns);
     for (DBuf *b : bufs) b->release();
     if (c.capture_stream) (void)hipStreamDestroy(c.capture_stream);
+    if (c.aux_stream) (void)hipStreamDestroy(c.aux_stream);
+    for (hipEvent_t e : c.aux_ev)
+        if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : c.ev_start) (void)hipEventDestroy(e);
     for (hipEvent_t e : c.ev_stop) (void)hipEventDestroy(e);
     delete ctx;

@@ -473,53 +473,15 @@ void build_ops(Ctx &c, int kind, int nops, const std::vector<double> &vecs, int 
 
 }  // namespace
 
-void build_fmm(Ctx &c) {
-    build_tree(c);
+// Expansions at the leaves (P2M) and up the tree (M2M) on c.stream; the
+// workspace buffers belong to the caller and must outlive the kernels.
+void upward_pass(Ctx &c, int p, int ncp, DBuf &flag, DBuf &ids, DBuf &leaves, DBuf &nleaf) {
     Tree &t = c.tree;
-    const int p = fmm_order_for(c);
-    const int ncp = (int)ceil_div(fmm::ncoef(p), kKB) * kKB;
-    const int64_t per = (int64_t)ncp * ncp;
-    // operators: M2M / L2L for the 8 octants, M2L for the classes in use
-    if (t.ops_p != p) {
-        std::vector<double> w(24);
-        for (int o = 0; o < 8; ++o) {
-            w[3 * o] = (o & 1) ? 0.5 : -0.5;
-            w[3 * o + 1] = ((o >> 1) & 1) ? 0.5 : -0.5;
-            w[3 * o + 2] = ((o >> 2) & 1) ? 0.5 : -0.5;
-        }
-        t.opM2M.ensure(sizeof(double) * 8 * per);
-        t.opL2L.ensure(sizeof(double) * 8 * per);
-        build_ops(c, 1, 8, w, p, ncp, t.opM2M.as<double>());
-        build_ops(c, 2, 8, w, p, ncp, t.opL2L.as<double>());
-        t.op_class_slot.assign(kNClass, -1);
-        t.opM2L.release();
-        t.ops_p = p;
-    }
-    {
-        std::vector<int> need;
-        for (int cls : t.class_used)
-            if (t.op_class_slot[cls] < 0) need.push_back(cls);
-        if (!need.empty()) {
-            int have = 0;
-            for (int s : t.op_class_slot) have += s >= 0;
-            t.opM2L.grow_copy(sizeof(double) * (size_t)(have + need.size()) * per, sizeof(double) * (size_t)have * per,
-                              c.stream);
-            std::vector<double> v(3 * need.size());
-            for (size_t i = 0; i < need.size(); ++i) class_vec(need[i], &v[3 * i]);
-            build_ops(c, 0, (int)need.size(), v, p, ncp, t.opM2L.as<double>() + (int64_t)have * per);
-            for (size_t i = 0; i < need.size(); ++i) t.op_class_slot[need[i]] = have + (int)i;
-        }
-    }
-    t.p = p;
-    t.ncp = ncp;
     // expansions
-    t.M.ensure(sizeof(double) * t.nboxes * ncp);
-    t.L.ensure(sizeof(double) * t.nboxes * ncp);
     LSS_HIP(hipMemsetAsync(t.M.p, 0, sizeof(double) * t.nboxes * ncp, c.stream));
     LSS_HIP(hipMemsetAsync(t.L.p, 0, sizeof(double) * t.nboxes * ncp, c.stream));
     Geo g{t.root.as<double>(), t.bmesh.as<int32_t>()};
     // P2M on the non-empty leaves
-    DBuf flag, ids, leaves, nleaf;
     flag.ensure(4 * t.nboxes); ids.ensure(4 * t.nboxes); leaves.ensure(4 * t.nboxes); nleaf.ensure(16);
     hipLaunchKernelGGL(k_leaf_flags, dim3(grid_for(t.nboxes)), dim3(kBlk), 0, c.stream, t.nboxes, t.child.as<int32_t>(),
                        t.nb.as<int64_t>(), t.ne.as<int64_t>(), flag.as<int32_t>(), ids.as<int32_t>());
@@ -552,6 +514,72 @@ void build_fmm(Ctx &c) {
                    nullptr, base, t.parent.as<int32_t>(), t.level.as<int32_t>(), t.root.as<double>(),
                    t.bmesh.as<int32_t>()};
         gemm(c, a);
+    }
+}
+
+void build_fmm(Ctx &c) {
+    build_tree_boxes(c);
+    Tree &t = c.tree;
+    const int p = fmm_order_for(c);
+    const int ncp = (int)ceil_div(fmm::ncoef(p), kKB) * kKB;
+    const int64_t per = (int64_t)ncp * ncp;
+    // operators: M2M / L2L for the 8 octants, M2L for the classes in use
+    if (t.ops_p != p) {
+        std::vector<double> w(24);
+        for (int o = 0; o < 8; ++o) {
+            w[3 * o] = (o & 1) ? 0.5 : -0.5;
+            w[3 * o + 1] = ((o >> 1) & 1) ? 0.5 : -0.5;
+            w[3 * o + 2] = ((o >> 2) & 1) ? 0.5 : -0.5;
+        }
+        t.opM2M.ensure(sizeof(double) * 8 * per);
+        t.opL2L.ensure(sizeof(double) * 8 * per);
+        build_ops(c, 1, 8, w, p, ncp, t.opM2M.as<double>());
+        build_ops(c, 2, 8, w, p, ncp, t.opL2L.as<double>());
+        t.op_class_slot.assign(kNClass, -1);
+        t.opM2L.release();
+        t.ops_p = p;
+    }
+    t.p = p;
+    t.ncp = ncp;
+    t.M.ensure(sizeof(double) * t.nboxes * ncp);
+    t.L.ensure(sizeof(double) * t.nboxes * ncp);
+    // The upward pass (P2M, M2M) needs only the boxes: it runs on the
+    // auxiliary stream while the interaction lists are built on the context
+    // stream; the M2L waits for both.  Same kernels, same order per buffer,
+    // so the results do not depend on the overlap.
+    if (!c.aux_stream) {
+        LSS_HIP(hipStreamCreateWithFlags(&c.aux_stream, hipStreamNonBlocking));
+        for (hipEvent_t &e : c.aux_ev) LSS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    LSS_HIP(hipEventRecord(c.aux_ev[0], c.stream));
+    LSS_HIP(hipStreamWaitEvent(c.aux_stream, c.aux_ev[0], 0));
+    DBuf flag, ids, leaves, nleaf;
+    {
+        struct StreamSwap {
+            Ctx &c;
+            hipStream_t saved;
+            ~StreamSwap() { c.stream = saved; }
+        } swap{c, c.stream};
+        c.stream = c.aux_stream;
+        upward_pass(c, p, ncp, flag, ids, leaves, nleaf);
+        LSS_HIP(hipEventRecord(c.aux_ev[1], c.aux_stream));
+    }
+    build_tree_lists(c);
+    LSS_HIP(hipStreamWaitEvent(c.stream, c.aux_ev[1], 0));
+    {   // M2L operators of the classes in use not built yet
+        std::vector<int> need;
+        for (int cls : t.class_used)
+            if (t.op_class_slot[cls] < 0) need.push_back(cls);
+        if (!need.empty()) {
+            int have = 0;
+            for (int s : t.op_class_slot) have += s >= 0;
+            t.opM2L.grow_copy(sizeof(double) * (size_t)(have + need.size()) * per, sizeof(double) * (size_t)have * per,
+                              c.stream);
+            std::vector<double> v(3 * need.size());
+            for (size_t i = 0; i < need.size(); ++i) class_vec(need[i], &v[3 * i]);
+            build_ops(c, 0, (int)need.size(), v, p, ncp, t.opM2L.as<double>() + (int64_t)have * per);
+            for (size_t i = 0; i < need.size(); ++i) t.op_class_slot[need[i]] = have + (int)i;
+        }
     }
     // M2L, one launch per displacement class, each at its own order: the
     // leading (p_v + 1)^2 coefficients in and out (the real layout orders them

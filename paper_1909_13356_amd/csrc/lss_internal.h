@@ -185,6 +185,7 @@ struct Tree {
     std::vector<double> h_root;     // host copy of root (4 per mesh)
     DBuf root, bmesh;               // double[4 * nroot], int32 per box
     int depth = 0;                  // deepest level
+    bool has_tcut = false;          // tcut holds target-side cut radii (else the source radii rule)
     int64_t nboxes = 0;
     std::vector<int64_t> level_begin;   // box ids of level l: [level_begin[l], level_begin[l+1])
     // boxes (BFS order; the 8 children of a box are consecutive)
@@ -220,6 +221,11 @@ struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     hipStream_t capture_stream = nullptr;   // created on first use (default priority) for graph capture
+    // second stream of the FMM build (created on first use, default priority,
+    // non-blocking): the upward pass runs on it while the interaction lists
+    // are built on `stream`; aux_ev orders the two
+    hipStream_t aux_stream = nullptr;
+    hipEvent_t aux_ev[2] = {nullptr, nullptr};
     std::string err;
     lss_options opt{};
     lss_stats stats{};
@@ -344,6 +350,10 @@ inline int fmm_order_for(const Ctx &c) {
     return c.opt.fmm_order > 0 ? c.opt.fmm_order : (c.opt.precision == LSS_MIXED ? 20 : 26);
 }
 void build_tree(Ctx &c);
+// the two halves of build_tree: the boxes (levels, radii, target cuts), then
+// the interaction lists of the dual traversal (sorted, per class)
+void build_tree_boxes(Ctx &c);
+void build_tree_lists(Ctx &c);
 void build_fmm(Ctx &c);
 void launch_locate_targets(Ctx &c, int64_t n_max, const int32_t *n_dev, const double *tx, const double *ty,
                            const double *tz, const int32_t *tmesh, uint64_t *keys, int32_t *idx);

@@ -643,7 +643,7 @@ __global__ void k_level0(int32_t nmesh, const int64_t *__restrict__ node_off, in
 }  // namespace
 
 // ======================================================== tree + lists
-void build_tree(Ctx &c) {
+void build_tree_boxes(Ctx &c) {
     Tree &t = c.tree;
     const int64_t n = c.nnodes;
     const int32_t nm = c.nmesh;
@@ -825,7 +825,14 @@ void build_tree(Ctx &c) {
         LSS_CHECK_LAUNCH("k_tcut_up");
         tcut = t.tcut.as<double>();
     }
-    // ---------------------------------------------------- dual traversal
+    t.has_tcut = tcut != nullptr;
+}
+
+// ---------------------------------------------------- dual traversal
+void build_tree_lists(Ctx &c) {
+    Tree &t = c.tree;
+    const int32_t nm = c.nmesh;
+    const double *tcut = t.has_tcut ? t.tcut.as<double>() : nullptr;
     DttArgs a{t.level.as<int32_t>(), t.ijk.as<int32_t>(), t.child.as<int32_t>(), t.nb.as<int64_t>(),
               t.ne.as<int64_t>(), t.rmax.as<double>(), t.root.as<double>(), t.bmesh.as<int32_t>(), t.K, tcut};
     t.cnt.ensure(8 * 8);
@@ -921,10 +928,14 @@ void build_tree(Ctx &c) {
     for (int k = 0; k < kNClass; ++k)
         if (t.class_end[k] > t.class_beg[k]) t.class_used.push_back(k);
     c.stats.n_boxes = t.nboxes;
-    c.stats.n_leaves = 0;
     c.stats.tree_depth = t.depth;
     c.stats.n_m2l = t.n_m2l;
     c.stats.n_m2p = t.n_m2p;
+}
+
+void build_tree(Ctx &c) {
+    build_tree_boxes(c);
+    build_tree_lists(c);
 }
 
 void launch_soa(Ctx &c, const double *x, int64_t n, double *tx, double *ty, double *tz) {
