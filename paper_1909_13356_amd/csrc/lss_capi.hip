@@ -706,7 +706,9 @@ void eval_multiscale(Ctx &c, double lambda, double sigma0, const double *x, cons
         c.ev_reset();
         launch_soa(c, dx, n, b.tx, b.ty, b.tz);
         if (dxm) LSS_HIP(hipMemcpyAsync(b.tmesh, dxm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c.stream));
-        const MsArgs ms{tsig, tgs};
+        const double cut = c.opt.cut_factor > 0 ? c.opt.cut_factor
+                                                 : (c.opt.precision == LSS_MIXED ? kCutMixed : kCutFP64);
+        const MsArgs ms{tsig, tgs, 0.5 * cut * cut};
         eval_fmm_bufs(c, b, n, dphi, dgrad, nullptr, &ms);
         if (dsig) LSS_HIP(hipMemcpyAsync(dsig, tsig, sizeof(double) * n, hipMemcpyDeviceToDevice, c.stream));
         LSS_HIP(hipStreamSynchronize(c.stream));

@@ -95,6 +95,7 @@ struct Cen {
 // (original order).
 struct MsArgs {
     const double *sig, *gsig;
+    double tcut;    // t = rho^2 / (2 sigma(x)^2) at the cut: pairs beyond it take the dipole form
 };
 
 // Targets whose own widths set the near/far split of the lists (target-

@@ -266,6 +266,56 @@ __device__ __forceinline__ void nodes32(const SrcF *sh, float x, float y, float 
 }
 
 
+// One (target, node) pair of a near list with the target's own width (see
+// pair_ms), the node record's a' rescaled to a' s2^(-3/2) when staged (the
+// caller multiplies the sums by s2x^(3/2) once): inside the cut and the FP64 fit's range the radial functions come
+// from the fit (k1 = (sqrt(pi)/2) S, k2 = -(3 sqrt(pi)/2) s2x T) and exp(-t)
+// from exp; inside the cut beyond that range from the exact forms (radial3);
+// beyond the cut the kernel is the Laplace dipole, as in the far field
+// (k1 = (sqrt(pi)/2) t^-3/2, k2 = -(3 sqrt(pi)/2) s2x t^-5/2, exp(-t) below
+// the cut's truncation).
+__device__ __forceinline__ void pair_ms_cut(const Src &s, double px, double py, double pz, double s2x, double tcut,
+                                            MsAcc &A) {
+    const double dx = px - s.yx, dy = py - s.yy, dz = pz - s.yz;
+    const double t = (dx * dx + dy * dy + dz * dz) * s2x;
+    double k1, k2, et = 0.0;
+    if (t < tcut && t < KF64_X) {
+        const double tt = t * KF64_INV_X;
+        double ps = kf64_ps[0], pt = kf64_pt[0], q = kf64_q[0], tk = 1.0;
+#pragma unroll
+        for (int i = 1; i <= KF64_Q_DEG; ++i) {
+            tk *= tt;
+            ps = fma(kf64_ps[i], tk, ps);
+            pt = fma(kf64_pt[i], tk, pt);
+            q = fma(kf64_q[i], tk, q);
+        }
+        double r = __builtin_amdgcn_rcp(q);
+        r = fma(r, fma(-q, r, 1.0), r);
+        r = fma(r, fma(-q, r, 1.0), r);
+        k1 = (0.5 * kSqrtPi) * (ps * r);
+        k2 = -(1.5 * kSqrtPi) * s2x * (pt * r);
+        et = exp(-t);
+    } else if (t < tcut) {
+        double k3;
+        radial3(t, s2x, k1, k2, k3, et);
+    } else {
+        double iu = __builtin_amdgcn_rsq(t);
+        const double ht = 0.5 * t;
+        iu = iu * fma(-ht * iu, iu, 1.5);
+        iu = iu * fma(-ht * iu, iu, 1.5);
+        const double iu3 = iu * iu * iu;
+        k1 = (0.5 * kSqrtPi) * iu3;
+        k2 = -(1.5 * kSqrtPi) * s2x * iu3 * iu * iu;
+    }
+    const double ad = s.ax * dx + s.ay * dy + s.az * dz;
+    A.f += ad * k1;
+    const double adk2 = ad * k2;
+    A.gx += s.ax * k1 + adk2 * dx;
+    A.gy += s.ay * k1 + adk2 * dy;
+    A.gz += s.az * k1 + adk2 * dz;
+    A.e += ad * et;
+}
+
 // K consecutive FP32 records of a "far" chunk against one target: every node
 // is beyond the cut of every target of the tile, so the kernel is the Laplace
 // dipole.  The record's a holds a'' = (sqrt(pi)/2) a' s2^(-3/2) (see
@@ -923,10 +973,25 @@ __global__ __launch_bounds__(TILE) void k_multiscale_fmm(FmmEvalArgs a, MsArgs m
             for (int64_t c0 = 0; c0 < total; c0 += TILE) {
                 const int cnt = (int)(total - c0 < TILE ? total - c0 : TILE);
                 __syncthreads();
-                if (lane < cnt) sh[lane] = a.src[packed_node<TILE>(rb, nr, c0 + lane)];
+                if (lane < cnt) {               // a' s2^(-3/2): the width moves to the target (pair_ms_cut)
+                    Src r = a.src[packed_node<TILE>(rb, nr, c0 + lane)];
+                    const double f = 1.0 / (r.s2 * sqrt(r.s2));
+                    r.ax *= f;
+                    r.ay *= f;
+                    r.az *= f;
+                    sh[lane] = r;
+                }
                 __syncthreads();
-                for (int j = 0; j < cnt; ++j) pair_ms(sh[j], x, y, z, s2x, A);
+                for (int j = 0; j < cnt; ++j) pair_ms_cut(sh[j], x, y, z, s2x, ms.tcut, A);
             }
+        }
+        {
+            const double fx = s2x * sqrt(s2x);
+            A.f *= fx;
+            A.gx *= fx;
+            A.gy *= fx;
+            A.gz *= fx;
+            A.e *= fx;
         }
         double ph = 0.0, g[3] = {0.0, 0.0, 0.0};
         if (a.m2p_end[B] > a.m2p_beg[B]) fmm_m2p_list(a, B, Ls, x, y, z, ph, g);
