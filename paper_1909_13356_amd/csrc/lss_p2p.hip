@@ -316,6 +316,43 @@ __device__ __forceinline__ void pair_ms_cut(const Src &s, double px, double py, 
     A.e += ad * et;
 }
 
+// pair_hess for the octree's near lists: beyond the cut (x >= tcut) the
+// radial functions are those of the Laplace double layer, as in the far
+// field: k1 = (sqrt(pi)/2) x^-3/2, k2 = -(3 sqrt(pi)/2) s2 x^-5/2,
+// k3 = (15 sqrt(pi)/2) s2^2 x^-7/2.
+__device__ __forceinline__ void pair_hess_cut(const Src &s, double px, double py, double pz, double tcut,
+                                              HessAcc &A) {
+    const double dx = px - s.yx, dy = py - s.yy, dz = pz - s.yz;
+    const double t = (dx * dx + dy * dy + dz * dz) * s.s2;
+    double k1, k2, k3;
+    if (t < tcut) {
+        double et;
+        radial3(t, s.s2, k1, k2, k3, et);
+    } else {
+        double iu = __builtin_amdgcn_rsq(t);
+        const double ht = 0.5 * t;
+        iu = iu * fma(-ht * iu, iu, 1.5);
+        iu = iu * fma(-ht * iu, iu, 1.5);
+        const double iu2 = iu * iu, iu3 = iu2 * iu, iu5 = iu3 * iu2;
+        k1 = (0.5 * kSqrtPi) * iu3;
+        k2 = -(1.5 * kSqrtPi) * s.s2 * iu5;
+        k3 = (7.5 * kSqrtPi) * s.s2 * s.s2 * iu5 * iu2;
+    }
+    const double ad = s.ax * dx + s.ay * dy + s.az * dz;
+    A.f -= ad * k1;
+    const double adk2 = ad * k2, adk3 = ad * k3;
+    A.gx -= s.ax * k1 + adk2 * dx;
+    A.gy -= s.ay * k1 + adk2 * dy;
+    A.gz -= s.az * k1 + adk2 * dz;
+    const double ex = adk3 * dx, ey = adk3 * dy, ez = adk3 * dz;
+    A.hxx -= 2.0 * k2 * s.ax * dx + adk2 + ex * dx;
+    A.hyy -= 2.0 * k2 * s.ay * dy + adk2 + ey * dy;
+    A.hzz -= 2.0 * k2 * s.az * dz + adk2 + ez * dz;
+    A.hxy -= k2 * (s.ax * dy + s.ay * dx) + ex * dy;
+    A.hxz -= k2 * (s.ax * dz + s.az * dx) + ex * dz;
+    A.hyz -= k2 * (s.ay * dz + s.az * dy) + ey * dz;
+}
+
 // K consecutive FP32 records of a "far" chunk against one target: every node
 // is beyond the cut of every target of the tile, so the kernel is the Laplace
 // dipole.  The record's a holds a'' = (sqrt(pi)/2) a' s2^(-3/2) (see
@@ -540,6 +577,7 @@ struct FmmEvalArgs {
     const double *rmax;         // largest cut radius of each box's nodes
     int K;                      // separation criterion of the M2P lists
     int p, ncp;
+    double tcut;                // x = rho^2 s2 at the cut (beyond it the Hessian pairs take the dipole form)
     const double *root;         // per-mesh root cubes (corner xyz, side)
     const int32_t *bmesh;
     double *pairs;
@@ -794,7 +832,8 @@ __global__ __launch_bounds__(256) void k_eval_outside(FmmEvalArgs a) {
 // ---------------------------------------------------------------- Hessian
 // Phi, grad Phi and the Hessian through the same tree and lists (section
 // 3.1 needs the Hessian for the charts' second derivatives): the near list
-// with the full kernel and its third radial function (pair_hess), the M2P
+// with the full kernel and its third radial function inside the cut
+// (pair_hess_cut: the double layer beyond it, as in the far field), the M2P
 // list and the leaf's local expansion with their second derivatives
 // (fmm::m2p_hess, fmm::l2p_hess).  Beyond the cut the kernel is the Laplace
 // double layer to the truncation of the cut (8 sigma: P(7/2, 32) differs from
@@ -855,7 +894,7 @@ __global__ __launch_bounds__(TILE) void k_hess_fmm(FmmEvalArgs a, double *hess) 
                 __syncthreads();
                 if (lane < cnt) sh[lane] = a.src[packed_node<TILE>(rb, nr, c0 + lane)];
                 __syncthreads();
-                for (int j = 0; j < cnt; ++j) pair_hess(sh[j], x, y, z, A);
+                for (int j = 0; j < cnt; ++j) pair_hess_cut(sh[j], x, y, z, a.tcut, A);
             }
         }
         double ph = 0.0, g[3] = {0.0, 0.0, 0.0}, H[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -1330,6 +1369,11 @@ void launch_eval_fmm(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const
     a.parent = t.parent.as<int32_t>();
     a.rmax = t.rmax.as<double>();
     a.K = t.K;
+    {
+        const double cut = c.opt.cut_factor > 0 ? c.opt.cut_factor
+                                                 : (c.opt.precision == LSS_MIXED ? kCutMixed : kCutFP64);
+        a.tcut = 0.5 * cut * cut;
+    }
     int64_t g = max_tiles < 16384 ? max_tiles : 16384;
     unsigned grid = (unsigned)(g > 0 ? g : 1);
     if (ms) {                               // target-attached width (FP64)
