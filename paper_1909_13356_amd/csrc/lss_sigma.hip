@@ -180,16 +180,23 @@ __global__ void __launch_bounds__(256) k_cell_ref(const int32_t *__restrict__ he
 __device__ inline bool cell_far(double cref, double s0) { return !(cref <= kRefMax * kRefMax * s0 * s0); }
 
 // the eight scaled sums at the Chebyshev points of each cell: block (x, y) =
-// points [256 x, 256 x + 256) of cell y; the mesh's centroids are staged in
-// LDS by runs of 256, a run skipped when its box is so far from the cell that
-// every weight is below e^-50 of the largest at any point of the cell
+// points [256 x, 256 x + 256) of cell y.  The weight factorises over the
+// axes, exp((d_ref - |p - c|^2) / (2 sigma0^2)) = E_x[a] E_y[b] E_z[e] with
+// E_x[a] = exp((d_ref - (x_a - c_x)^2) / (2 sigma0^2)) and E_y, E_z without
+// d_ref, so a chunk of 64 centroids needs 64 x 3 x 17 exponentials, shared
+// by the block's points, and each (point, centroid) term two products.
+// Runs of 256 centroids whose box is so far from the cell that every weight
+// is below e^-50 of the largest at any point of the cell are skipped.
+constexpr int kCenChunk = 64;
+
 __global__ void __launch_bounds__(256) k_cell_nodes(const int32_t *__restrict__ heads,
                                                     const uint64_t *__restrict__ key,
                                                     const SigGrid *__restrict__ grids,
                                                     const int64_t *__restrict__ tri_off,
                                                     const Cen *__restrict__ cen, const double *__restrict__ cbox,
                                                     const double *__restrict__ cref, double *nodes) {
-    __shared__ Cen ctile[256];
+    __shared__ Cen ctile[kCenChunk];
+    __shared__ double E[kCenChunk][3 * kQ];
     const int32_t cell = blockIdx.y;
     int32_t m;
     int ic[3];
@@ -199,15 +206,14 @@ __global__ void __launch_bounds__(256) k_cell_nodes(const int32_t *__restrict__ 
     if (cell_far(dref, g.s0)) return;                     // uniform over the block
     const int node = blockIdx.x * 256 + threadIdx.x;
     const bool act = node < kQ3;
-    const int a = node / kQ2, b = (node / kQ) % kQ, e = node % kQ;
+    const int a = act ? node / kQ2 : 0, b = act ? (node / kQ) % kQ : 0, e = act ? node % kQ : 0;
     double lo[3], p[3];
     for (int d = 0; d < 3; ++d) lo[d] = g.o[d] + ic[d] * g.h;
     p[0] = lo[0] + 0.5 * g.h * (1.0 + cheb_z(a));
     p[1] = lo[1] + 0.5 * g.h * (1.0 + cheb_z(b));
     p[2] = lo[2] + 0.5 * g.h * (1.0 + cheb_z(e));
     const double inv2s0 = 0.5 / (g.s0 * g.s0);
-    // every point of the cell has a centroid within R of it
-    const double R = sqrt(dref) + 0.8660254037844386 * g.h;
+    const double R = sqrt(dref) + 0.8660254037844386 * g.h;   // every point has a centroid within R
     const double R2 = R * R;
     double S0 = 0.0, S1 = 0.0, V0x = 0.0, V0y = 0.0, V0z = 0.0, V1x = 0.0, V1y = 0.0, V1z = 0.0;
     const int64_t j0 = tri_off[m], j1 = tri_off[m + 1];
@@ -218,29 +224,37 @@ __global__ void __launch_bounds__(256) k_cell_nodes(const int32_t *__restrict__ 
             near2 += gap * gap;
         }
         if ((near2 - R2) * inv2s0 > 50.0) continue;          // uniform over the block
-        const int64_t base = r * 256;
-        const int64_t jj = base + threadIdx.x;
-        __syncthreads();
-        if (jj >= j0 && jj < j1) ctile[threadIdx.x] = cen[jj];
-        __syncthreads();
-        const int k0 = j0 > base ? (int)(j0 - base) : 0;
-        const int k1 = j1 - base < 256 ? (int)(j1 - base) : 256;
-        if (act) {
-            for (int k = k0; k < k1; ++k) {
-                const Cen c = ctile[k];
-                const double dx = p[0] - c.cx, dy = p[1] - c.cy, dz = p[2] - c.cz;
-                const double d2 = dx * dx + dy * dy + dz * dz;
-                if ((d2 - R2) * inv2s0 > 50.0) continue;      // below e^-50 of the largest
-                const double w = exp((dref - d2) * inv2s0);
-                const double sw = c.sj * w;
-                S0 += w;
-                S1 += sw;
-                V0x += w * dx;
-                V0y += w * dy;
-                V0z += w * dz;
-                V1x += sw * dx;
-                V1y += sw * dy;
-                V1z += sw * dz;
+        for (int64_t base = r * 256; base < r * 256 + 256 && base < j1; base += kCenChunk) {
+            const int64_t c0 = base > j0 ? base : j0;
+            const int64_t c1 = base + kCenChunk < j1 ? base + kCenChunk : j1;
+            if (c1 <= c0) continue;                          // uniform
+            const int cnt = (int)(c1 - c0);
+            __syncthreads();                                 // the previous chunk is consumed
+            if ((int)threadIdx.x < cnt) ctile[threadIdx.x] = cen[c0 + threadIdx.x];
+            __syncthreads();
+            for (int it = threadIdx.x; it < cnt * 3 * kQ; it += 256) {
+                const int c = it / (3 * kQ), q = it - c * 3 * kQ, ax = q / kQ, k = q - ax * kQ;
+                const double pc = lo[ax] + 0.5 * g.h * (1.0 + cheb_z(k));
+                const double cc = ax == 0 ? ctile[c].cx : (ax == 1 ? ctile[c].cy : ctile[c].cz);
+                const double dd = pc - cc;
+                E[c][q] = exp(((ax == 0 ? dref : 0.0) - dd * dd) * inv2s0);
+            }
+            __syncthreads();
+            if (act) {
+                for (int c = 0; c < cnt; ++c) {
+                    const Cen cc = ctile[c];
+                    const double w = E[c][a] * E[c][kQ + b] * E[c][2 * kQ + e];
+                    const double sw = cc.sj * w;
+                    const double dx = p[0] - cc.cx, dy = p[1] - cc.cy, dz = p[2] - cc.cz;
+                    S0 += w;
+                    S1 += sw;
+                    V0x += w * dx;
+                    V0y += w * dy;
+                    V0z += w * dz;
+                    V1x += sw * dx;
+                    V1y += sw * dy;
+                    V1z += sw * dz;
+                }
             }
         }
     }
