@@ -102,8 +102,12 @@ enum {
 typedef struct lss_options {
     int32_t precision;        /* LSS_FP64 (default) or LSS_MIXED */
     int32_t far_field;        /* LSS_FAR_DIRECT (default) or LSS_FAR_FMM */
-    int32_t fmm_order;        /* multipole order p for LSS_FAR_FMM; 0 = default for the precision */
-    int32_t leaf_capacity;    /* octree: split a box holding more nodes than this; 0 = default 64 */
+    int32_t fmm_order;        /* multipole order p for LSS_FAR_FMM (M2L classes farther than the
+                                 closest admissible one are translated at the lower order that
+                                 reaches the same truncation error, plus two); 0 = default for the
+                                 precision (26 FP64, 20 MIXED) */
+    int32_t leaf_capacity;    /* octree: a box splits while more than this many of its nodes have a
+                                 cut radius <= leaf_shrink x its children's side; 0 = default 64 */
     double  cut_factor;       /* near/far cut radius in units of the source sigma; the near list of
                                  a leaf covers every node within cut_factor * sigma_node;
                                  0 = default (8 for FP64, sqrt(40) for MIXED) */
@@ -112,8 +116,9 @@ typedef struct lss_options {
     int32_t newton_max_iter;  /* 0 = default 40 */
     int32_t tile;             /* targets per workgroup of the pair kernels: 64, 128 or 256; 0 = default
                                  (direct sum 256; FMM 64; the mixed FMM kernel always uses 64) */
-    double  leaf_shrink;      /* LSS_FAR_FMM: leaves may be as narrow as (cut radius of their nodes) /
-                                 leaf_shrink; M2L then also needs a box gap >= the source's cut radius.
+    double  leaf_shrink;      /* LSS_FAR_FMM: boxes may be as narrow as (cut radius of their nodes) /
+                                 leaf_shrink (see leaf_capacity); M2L needs a Euclidean gap between
+                                 the boxes >= the source box's largest cut radius.
                                  0 = default (2 for FP64, 1.5 for MIXED); otherwise in [1, 3] */
     int32_t count_useful;     /* LSS_FAR_FMM: nonzero makes the evaluation kernels also count the
                                  pairs inside the cut (lss_stats.useful_pairs), at a small cost in
