@@ -214,3 +214,22 @@ def test_curved_charts_on_midpoint_edges_equal_flat():
     ek = max(rel(a, b) for a, b in zip(k6, k3))
     say("  e_h %.2e e_curvature %.2e" % (e, ek))
     assert np.array_equal(s3, s6) and e <= 1e-12 and ek <= 1e-9
+
+
+def test_curved_charts_batch_vs_oracle(batch):
+    """Curved chart bases on the ragged batch of a quadratic torus and a
+    quadratic sphere: each chart's patch, pseudonormals and level set come
+    from its own mesh (FP64, FMM) and match the oracle's curved charts."""
+    v, t, off, sig, x, xm = batch
+    uv = chart_nodes(2)
+    say("case: curved chart bases on a quadratic torus + sphere batch, %d tri" % len(t))
+    c = ctx(v, t, sig, lss.FP64, lss.FAR_FMM, offsets=off, curved_charts=1)
+    h, xs, st, it = c.project(uv)
+    sel = np.concatenate([np.arange(0, off[1], 97), np.arange(off[1], off[2], 31)])
+    ho, xo, sto, ito = oracle.project(v, t, sig, dunavant6(), uv, tau=1e-12, sel=sel, tri_offsets=off, curved=True)
+    idx = (sel[:, None] * len(uv) + np.arange(len(uv))[None]).ravel()
+    sg = np.repeat(sig[sel], len(uv))
+    ok = sto == 0
+    eh = np.max(np.abs(h[idx] - ho)[ok] / sg[ok])
+    say("  %d sampled nodes, statuses equal %s, e_h %.3e" % (len(idx), bool(np.array_equal(st[idx], sto)), eh))
+    assert np.array_equal(st[idx], sto) and ok.mean() > 0.99 and eh <= 1e-11
