@@ -121,11 +121,13 @@ def time_variant(lss, torch, cfg, prec, far, steps, warmup):
     # the cut (the method's own near-field work); results are unchanged
     c.set_options(precision=prec, far_field=far, count_useful=1)
     c.eval(x, phi=phi, grad=grad)
-    useful = c.stats()["useful_pairs"]
+    stu = c.stats()
+    useful, dipole = stu["useful_pairs"], stu["dipole_pairs"]
     c.close()
     return dict(ms_per_step=1e3 * el / steps, value=n * steps / el, eval_only_per_s=n * steps / el_eval,
                 pair_kernel_ms=kms, pair_kernel_launches=launches, pairs_per_step=pairs,
                 pairs_per_s=pairs * steps / el, useful_pairs_per_step=useful, useful_pairs_per_s=useful * steps / el,
+                dipole_pairs_per_step=dipole,
                 n_targets=n, lane_use=lane_use, tree=tree, phi=phi, grad=grad)
 
 
@@ -468,6 +470,11 @@ def main():
                 "l2p_flop_per_target": L2P_FLOP(p) if far else 0.0,
                 "executed_pairs_per_launch": r["pairs_per_step"] / r["pair_kernel_launches"],
                 "executed_over_useful": round(r["pairs_per_step"] / max(r["useful_pairs_per_step"], 1.0), 3),
+                # of the executed pairs, those of the dipole-only loop (leaves beyond the cut of
+                # every target of their tile; mixed kernel) and the rest, through the full kernel
+                "dipole_loop_pairs_per_launch": r["dipole_pairs_per_step"] / r["pair_kernel_launches"],
+                "full_kernel_over_useful": round((r["pairs_per_step"] - r["dipole_pairs_per_step"])
+                                                 / max(r["useful_pairs_per_step"], 1.0), 3),
                 "lane_use": r["lane_use"],
                 "executed_tflops": round(FLOP_PER_PAIR * r["pairs_per_step"] / r["pair_kernel_launches"]
                                          / per_launch / 1e12, 3)}

@@ -53,7 +53,7 @@ class Stats(ctypes.Structure):
                 ("n_degenerate", ctypes.c_int64), ("pair_kernel_ms", ctypes.c_double),
                 ("pair_kernel_launches", ctypes.c_int32), ("pad0", ctypes.c_int32),
                 ("lane_pairs", ctypes.c_double), ("n_m2p", ctypes.c_int64),
-                ("useful_pairs", ctypes.c_double)]
+                ("useful_pairs", ctypes.c_double), ("dipole_pairs", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -225,7 +225,7 @@ void eval_fmm_bufs(Ctx &c, const EvalBufs &b, int64_t n, double *phi, double *gr
     build_tiles(c, n, b.n_dev, b.key2, fmm_tile(c), b.tleaf, b.tstart, b.ntiles, b.flag, b.pos, b.blocksum);
     order_tiles(c, n, b.ntiles, b.tstart, b.tleaf, b.order);
     if (b.pairs) {
-        LSS_HIP(hipMemsetAsync(b.pairs, 0, 3 * sizeof(double), c.stream));
+        LSS_HIP(hipMemsetAsync(b.pairs, 0, 4 * sizeof(double), c.stream));
         c.ev_begin();
     }
     launch_eval_fmm(c, n, b.ntiles, b.tstart, b.n_dev, n, b.tleaf, b.perm2, b.tx, b.ty, b.tz, nullptr, phi, grad,
@@ -241,7 +241,7 @@ void eval_direct_bufs(Ctx &c, const EvalBufs &b, const double *x, const int32_t 
     sort_pairs_u64(b.sort_tmp, b.sort_bytes, b.key, b.key2, b.perm, b.perm2, n, 0, 64, c.stream);
     launch_gather_targets(c, x, xm, b.perm2, n, b.tx, b.ty, b.tz, b.tmesh);
     if (b.pairs) {
-        LSS_HIP(hipMemsetAsync(b.pairs, 0, 3 * sizeof(double), c.stream));
+        LSS_HIP(hipMemsetAsync(b.pairs, 0, 4 * sizeof(double), c.stream));
         c.ev_begin();
     }
     launch_p2p_direct(c, n, b.n_dev, b.tx, b.ty, b.tz, b.tmesh, b.perm2, phi, grad, 3, b.pairs);
@@ -404,7 +404,7 @@ void project(Ctx &c, const double *uv, int32_t np, double *h, double *xout, int8
     DBuf &phi = s.phi, &grad = s.grad;
     phi.ensure(sizeof(double) * N);
     grad.ensure(sizeof(double) * 3 * N);
-    LSS_HIP(hipMemsetAsync(c.pairs.p, 0, 3 * sizeof(double), c.stream));
+    LSS_HIP(hipMemsetAsync(c.pairs.p, 0, 4 * sizeof(double), c.stream));
     // Iterations run in captured chunks; a node leaves the active list when it
     // converges or reaches maxit, so iterations past the last active one are
     // empty launches and the host only checks the count between chunks.  The
@@ -1246,9 +1246,9 @@ int lss_get_stats(const lss_ctx *ctx, lss_stats *out) {
         c.ev_pending = false;
     }
     if (c.pairs_pending) {
-        double pr[3] = {0.0, 0.0, 0.0};
+        double pr[4] = {0.0, 0.0, 0.0, 0.0};
         (void)hipSetDevice(c.device);
-        if (hipMemcpyAsync(pr, c.pairs.p, 3 * sizeof(double), hipMemcpyDeviceToHost, c.stream) != hipSuccess ||
+        if (hipMemcpyAsync(pr, c.pairs.p, 4 * sizeof(double), hipMemcpyDeviceToHost, c.stream) != hipSuccess ||
             hipStreamSynchronize(c.stream) != hipSuccess) {
             c.err = "lss_get_stats: reading the pair counter failed";
             return LSS_EHIP;
@@ -1256,6 +1256,7 @@ int lss_get_stats(const lss_ctx *ctx, lss_stats *out) {
         c.stats.last_pairs = pr[0];
         c.stats.lane_pairs = pr[1];
         c.stats.useful_pairs = c.opt.far_field == LSS_FAR_FMM ? pr[2] : pr[0];
+        c.stats.dipole_pairs = c.opt.far_field == LSS_FAR_FMM ? pr[3] : 0.0;
         c.pairs_pending = false;
     }
     *out = c.stats;

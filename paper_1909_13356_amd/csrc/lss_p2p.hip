@@ -1203,7 +1203,7 @@ __global__ __launch_bounds__(64) void k_eval_fmm_mixed(FmmEvalArgs a) {
         __syncthreads();                    // previous tile is done with Ls
         stage_local(a, B, Ls);
         float sp = 0, ep = 0, sx = 0, ex = 0, sy = 0, ey = 0, sz = 0, ez = 0;
-        double npair = 0.0;
+        double npair = 0.0, nfar = 0.0;
         uint32_t nuse = 0;
         for (int eb = e0; eb < e1; eb += W) {
             const int nr = e1 - eb < W ? e1 - eb : W;
@@ -1211,6 +1211,7 @@ __global__ __launch_bounds__(64) void k_eval_fmm_mixed(FmmEvalArgs a) {
             int64_t nnear;
             const int64_t total = load_ranges_split(a, rb, eb, nr, o, blo, bhi, &nnear);
             npair += (double)total;
+            if (COUNT) nfar += (double)(total - nnear);
             for (int64_t c0 = 0; c0 < total; c0 += W) {
                 const int cnt = (int)(total - c0 < W ? total - c0 : W);
                 const bool far = c0 >= nnear;   // uniform: every node of the chunk is far for the tile
@@ -1274,13 +1275,18 @@ __global__ __launch_bounds__(64) void k_eval_fmm_mixed(FmmEvalArgs a) {
                 a.grad[3 * o + 2] = ((double)sz + (double)ez) + g[2];
             }
         }
-        if (a.pairs) {                      // [0] pairs of real targets, [1] lane slots spent, [2] inside the cut
+        if (a.pairs) {                      // [0] pairs of real targets, [1] lane slots spent, [2] inside the cut,
+                                            // [3] taken by the dipole-only loop
             const double w = wave_sum(valid ? npair : 0.0), wl = wave_sum(npair);
             const double wu = COUNT ? wave_sum(valid ? (double)nuse : 0.0) : 0.0;
+            const double wf = COUNT ? wave_sum(valid ? nfar : 0.0) : 0.0;
             if (lane == 0) {
                 atomicAdd(a.pairs, w);
                 atomicAdd(a.pairs + 1, wl);
-                if (COUNT) atomicAdd(a.pairs + 2, wu);
+                if (COUNT) {
+                    atomicAdd(a.pairs + 2, wu);
+                    atomicAdd(a.pairs + 3, wf);
+                }
             }
         }
     }

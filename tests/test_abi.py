@@ -35,7 +35,7 @@ def test_struct_layouts():
     # lss_options: 4 int32, 2 double, 2 int32, 1 double, count_useful, admissibility, curved_charts,
     # sigma_interp, 2 int32 reserved
     assert ctypes.sizeof(Options) == 4 * 4 + 2 * 8 + 2 * 4 + 8 + 4 + 4 + 4 + 4 + 2 * 4
-    assert ctypes.sizeof(Stats) == 8 * 2 + 4 * 2 + 8 * 3 + 4 * 2 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8 + 8
+    assert ctypes.sizeof(Stats) == 8 * 2 + 4 * 2 + 8 * 3 + 4 * 2 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8 + 8 + 8
 
 
 def test_struct_offsets_match_the_c_header(tmp_path):
