@@ -398,7 +398,7 @@ def cpu_baseline(cfg, budget_s=15.0, budget1_s=8.0):
 
 
 def error_report(phi, grad, ref):
-    """Errors of the GPU results at the oracle's sample (SURVEY c12 reading):
+    """Errors of the GPU results at the oracle's sample:
     e_phi = max |dPhi| / max |Phi_oracle|, e_grad likewise with norms;
     pointwise |dPhi| / |Phi_oracle| over targets with |Phi_oracle| >= 1e-3,
     and |dPhi| / A_Phi (A_Phi = sum of |terms|), at median, p99 and max."""
