@@ -20,6 +20,7 @@
 // chunks of TILE packed records; each lane sums the nodes of its own mesh
 // (per-lane node range, so a tile may straddle meshes of a ragged batch).
 // Chunk partial sums are folded into compensated totals (two-sum).
+#include <algorithm>
 #include <cstring>
 #include <hip/hip_runtime.h>
 
@@ -214,6 +215,47 @@ __device__ __forceinline__ void nodes64(const Src *sh, double x, double y, doubl
 
 constexpr int kNodeGroup64 = 4;
 
+// FP64 record of a node beyond the cut of every target of a tile: position
+// and a'' = (sqrt(pi)/2) a' s2^(-3/2)
+struct alignas(16) FarD {
+    double yx, yy, yz, ax, ay, az;
+};
+
+__device__ __forceinline__ FarD pad_fard() {
+    FarD f;
+    f.yx = f.yy = f.yz = 1.0e150;
+    f.ax = f.ay = f.az = 0.0;
+    return f;
+}
+
+// K consecutive FP64 far records against one target: the Laplace dipole with
+// the width moved into a'' and the gradient summed in two parts, as
+// nodes32_far; rsq refined by two Newton steps
+template <int K>
+__device__ __forceinline__ void nodes64_far(const FarD *sh, double x, double y, double z, double &p, double &gx,
+                                            double &gy, double &gz, double &hx, double &hy, double &hz) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const FarD s = sh[k];
+        const double dx = x - s.yx, dy = y - s.yy, dz = z - s.yz;
+        const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+        double r = __builtin_amdgcn_rsq(r2);
+        const double h2 = 0.5 * r2;
+        r = r * fma(-h2 * r, r, 1.5);
+        r = r * fma(-h2 * r, r, 1.5);
+        const double rr = r * r, S = rr * r;
+        const double ad = fma(s.ax, dx, fma(s.ay, dy, s.az * dz));
+        p = fma(-ad, S, p);
+        const double h = ad * S * rr;
+        gx = fma(h, dx, gx);
+        gy = fma(h, dy, gy);
+        gz = fma(h, dz, gz);
+        hx = fma(s.ax, S, hx);
+        hy = fma(s.ay, S, hy);
+        hz = fma(s.az, S, hz);
+    }
+}
+
 constexpr int kNodeGroup = 4;
 
 template <int K, bool COUNT = false>
@@ -353,30 +395,51 @@ __device__ __forceinline__ void pair_hess_cut(const Src &s, double px, double py
     A.hyz -= k2 * (s.ay * dz + s.az * dy) + ey * dz;
 }
 
-// K consecutive FP32 records of a "far" chunk against one target: every node
-// is beyond the cut of every target of the tile, so the kernel is the Laplace
-// dipole.  The record's a holds a'' = (sqrt(pi)/2) a' s2^(-3/2) (see
-// stage_far), which moves the width out of the pair:  with r2 = |d|^2,
-//   Phi -= (a''.d) r2^(-3/2),  grad Phi += 3 (a''.d) r2^(-5/2) d - a'' r2^(-3/2).
-// Positions are the FP32 offsets from the tile origin without the low parts:
-// at |d| beyond the cut the rounding of the offsets is a relative error of a
-// few units of FP32 rounding in d.
+// FP32 record of a node that lies beyond the cut of every target of a tile:
+// offset from the tile origin (no low part) and a'' = (sqrt(pi)/2) a' s2^(-3/2)
+struct alignas(16) FarF {
+    float yx, yy, yz, pad0;
+    float ax, ay, az, pad1;
+};
+
+// Padding record of the far ring: zero vector, placed so far away that its
+// terms underflow to zero.
+__device__ __forceinline__ FarF pad_farf() {
+    FarF f;
+    f.yx = f.yy = f.yz = 1.0e18f;
+    f.ax = f.ay = f.az = 0.0f;
+    f.pad0 = f.pad1 = 0.0f;
+    return f;
+}
+
+// K consecutive far records against one target: every node is beyond the cut
+// of every target of the tile, so the kernel is the Laplace dipole.  With the
+// width moved into a'' and r2 = |d|^2,
+//   Phi -= (a''.d) r2^(-3/2),  grad Phi += 3 (a''.d) r2^(-5/2) d - a'' r2^(-3/2);
+// the two gradient terms are summed apart (G += (a''.d) r2^(-5/2) d,
+// H += a'' r2^(-3/2); the caller forms 3G - H once per run).  Positions are
+// the FP32 offsets from the tile origin without the low parts: at |d| beyond
+// the cut the rounding of the offsets is a relative error of a few units of
+// FP32 rounding in d.
 template <int K>
-__device__ __forceinline__ void nodes32_far(const SrcF *sh, float x, float y, float z, float &p, float &gx, float &gy,
-                                            float &gz) {
+__device__ __forceinline__ void nodes32_far(const FarF *sh, float x, float y, float z, float &p, float &gx, float &gy,
+                                            float &gz, float &hx, float &hy, float &hz) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const SrcF s = sh[k];
+        const FarF s = sh[k];
         const float dx = x - s.yx, dy = y - s.yy, dz = z - s.yz;
         const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
         const float r = __builtin_amdgcn_rsqf(r2);
         const float rr = r * r, S = rr * r;
-        const float adS = fmaf(s.ax, dx, fmaf(s.ay, dy, s.az * dz)) * S;
-        p -= adS;
-        const float h = 3.0f * adS * rr;
-        gx = fmaf(h, dx, fmaf(-s.ax, S, gx));
-        gy = fmaf(h, dy, fmaf(-s.ay, S, gy));
-        gz = fmaf(h, dz, fmaf(-s.az, S, gz));
+        const float ad = fmaf(s.ax, dx, fmaf(s.ay, dy, s.az * dz));
+        p = fmaf(-ad, S, p);
+        const float h = ad * S * rr;
+        gx = fmaf(h, dx, gx);
+        gy = fmaf(h, dy, gy);
+        gz = fmaf(h, dz, gz);
+        hx = fmaf(s.ax, S, hx);
+        hy = fmaf(s.ay, S, hy);
+        hz = fmaf(s.az, S, hz);
     }
 }
 
@@ -635,54 +698,6 @@ __device__ __forceinline__ int64_t load_ranges(const FmmEvalArgs &a, RangeBatch<
         rb.off[t + 1] += v;
         __syncthreads();
     }
-    return rb.off[nr];
-}
-
-// As load_ranges, with the ranges of the batch reordered so that the boxes
-// that lie beyond the cut of every target of the tile come last: a box whose
-// gap to the tile's target bounding box [blo, bhi] (offsets from the tile
-// origin o) is at least its largest cut radius.  Returns the packed length;
-// *nnear receives the packed length of the other ranges (uniform).
-__device__ __forceinline__ int64_t load_ranges_split(const FmmEvalArgs &a, RangeBatch<64> &rb, int e, int nr,
-                                                     const double o[3], const double blo[3], const double bhi[3],
-                                                     int64_t *nnear) {
-    const int t = threadIdx.x;
-    int64_t len = 0, beg = 0;
-    bool far = false;
-    if (t < nr) {
-        const int32_t S = a.p2p_src[e + t];
-        beg = a.nb[S];
-        len = a.ne[S] - a.nb[S];
-        const double side = box_side(a.root, a.bmesh, S, a.lev[S]);
-        const double *r0 = a.root + 4 * a.bmesh[S];
-        double g2 = 0.0;
-        for (int c = 0; c < 3; ++c) {
-            const double lo = r0[c] + a.ijk[3 * S + c] * side - o[c], hi = lo + side;
-            const double g = fmax(fmax(lo - bhi[c], blo[c] - hi), 0.0);
-            g2 += g * g;
-        }
-        const double rc = a.rmax[S] * (1.0 + 1e-6);
-        far = g2 >= rc * rc;
-    }
-    const uint64_t fm = __ballot(far), below = t ? (~0ull >> (64 - t)) : 0ull;
-    const int nn = nr - __popcll(fm);
-    const int pos = far ? nn + __popcll(fm & below) : __popcll(~fm & below);
-    __syncthreads();
-    if (t < nr) {
-        rb.beg[pos] = beg;
-        rb.off[pos + 1] = len;
-    } else {
-        rb.off[t + 1] = 0;
-    }
-    if (t == 0) rb.off[0] = 0;
-    __syncthreads();
-    for (int d = 1; d < 64; d <<= 1) {      // inclusive scan of off[1..64]
-        int64_t v = (t >= d) ? rb.off[t + 1 - d] : 0;
-        __syncthreads();
-        rb.off[t + 1] += v;
-        __syncthreads();
-    }
-    *nnear = rb.off[nn];
     return rb.off[nr];
 }
 
@@ -1163,17 +1178,214 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(4))) void 
 }
 
 
-// Mixed path: one wavefront per tile of 64 targets; each staged chunk of 64
-// node records is padded with zero records to whole groups of kNodeGroup.
+// FP64 path with 64-target tiles: as the mixed kernel below, every staged
+// node is tested against the tile's target bounding box and goes to the near
+// ring (the general loop: the far form for every pair, the rational fit for
+// node groups with a pair inside the cut) or to the far ring (the dipole-only
+// loop).  Nodes are staged 32 at a time so that both rings fit beside three
+// other workgroups' in the LDS of a SIMD.
+constexpr int kNodeGroupSplit = 2;      // node group of the split kernel (fewer registers than 4)
+constexpr int kRun64 = 32;               // records per partial sum
+// number of set bits of a wave mask below this lane
+__device__ __forceinline__ int below(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+constexpr int kRing64 = 64;              // kRun64 - 1 left over + 32 staged
+constexpr size_t kF64RingBytes = kRing64 * (sizeof(Src) + sizeof(FarD));
+
 template <bool COUNT>
-__global__ __launch_bounds__(64) void k_eval_fmm_mixed(FmmEvalArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_fmm_f64_split(FmmEvalArgs a) {
     constexpr int W = 64;
-    __shared__ SrcF sh[W];
     __shared__ RangeBatch<W> rb;
-    extern __shared__ double Ls[];      // local expansion of the tile's leaf (ncp doubles)
+    __shared__ double tbox[6];          // the tile's target bounding box
+    // node rings while the pairs run, then the local expansion (ncp doubles)
+    // and the M2P staging buffer
+    extern __shared__ __attribute__((aligned(16))) double Ls[];
+    Src *ring_n = reinterpret_cast<Src *>(Ls);
+    FarD *ring_f = reinterpret_cast<FarD *>(ring_n + kRing64);
     const int ntiles = *a.ntiles_dev;
     const int64_t n = a.n_dev ? (int64_t)*a.n_dev : a.n_max;
     const int lane = threadIdx.x;
+    const double far_u = KF64_X * (1.0 + 1e-6);
+    __shared__ int slot;
+    for (int q = next_tile(a, &slot); q < ntiles; q = next_tile(a, &slot)) {
+        const int tile = a.order[q];
+        const int64_t s0 = a.tile_start[tile];
+        const int32_t B = a.sleaf[s0];
+        if (B >= a.nboxes) continue;        // outside the root cube: k_eval_outside
+        const int64_t s1 = tile + 1 < ntiles ? (int64_t)a.tile_start[tile + 1] : n;   // tile = [s0, s1)
+        const int64_t sp_ = s0 + lane;
+        const bool valid = sp_ < s1;
+        const int64_t ti = a.sidx ? (int64_t)a.sidx[valid ? sp_ : s0] : (valid ? sp_ : s0);
+        const double x = a.tx[ti], y = a.ty[ti], z = a.tz[ti];
+        const int e0 = a.p2p_beg[B], e1 = a.p2p_end[B];
+        {
+            double blo[3] = {x, y, z}, bhi[3] = {x, y, z};      // lanes past the tile end hold its first target
+            for (int off = 32; off > 0; off >>= 1)
+                for (int c = 0; c < 3; ++c) {
+                    blo[c] = fmin(blo[c], __shfl_xor(blo[c], off));
+                    bhi[c] = fmax(bhi[c], __shfl_xor(bhi[c], off));
+                }
+            __syncthreads();                // the previous tile is done with tbox
+            if (lane == 0)
+                for (int c = 0; c < 3; ++c) {
+                    tbox[c] = blo[c];
+                    tbox[3 + c] = bhi[c];
+                }
+        }
+        double sp = 0, ep = 0, sx = 0, ex = 0, sy = 0, ey = 0, sz = 0, ez = 0;
+        double npair = 0.0, nfar = 0.0;
+        uint32_t nuse = 0;
+        int hn = 0, nn = 0, hf = 0, nf = 0;     // head and fill of each ring (uniform)
+        int eb = e0, nr = 0;
+        int64_t total = 0, c0 = 0;
+        for (bool last = false; !last;) {
+            while (c0 >= total && eb < e1) {    // next batch of the leaf's direct list
+                nr = e1 - eb < W ? e1 - eb : W;
+                __syncthreads();
+                total = load_ranges<W>(a, rb, eb, nr);
+                npair += (double)total;
+                c0 = 0;
+                eb += nr;
+            }
+            last = c0 >= total;             // every node is staged: pad the remainders
+            const int cnt = last ? 0 : (int)(total - c0 < kRun64 ? total - c0 : kRun64);
+            Src sr;
+            bool isfar = false;
+            if (lane < cnt) {
+                sr = a.src[packed_node<W>(rb, nr, c0 + lane)];
+                const double gx_ = fmax(fmax(tbox[0] - sr.yx, sr.yx - tbox[3]), 0.0);
+                const double gy_ = fmax(fmax(tbox[1] - sr.yy, sr.yy - tbox[4]), 0.0);
+                const double gz_ = fmax(fmax(tbox[2] - sr.yz, sr.yz - tbox[5]), 0.0);
+                isfar = (gx_ * gx_ + gy_ * gy_ + gz_ * gz_) * sr.s2 >= far_u;
+            }
+            c0 += cnt;
+            const uint64_t fm = __ballot(isfar), nm = __ballot(lane < cnt && !isfar);
+            __syncthreads();                // the runs taken last are read
+            if (lane < cnt && !isfar) {
+                int pos = hn + nn + below(nm);
+                if (pos >= kRing64) pos -= kRing64;
+                ring_n[pos] = fold_src(sr);
+            } else if (isfar) {
+                int pos = hf + nf + below(fm);
+                if (pos >= kRing64) pos -= kRing64;
+                const double fa = kFoldA / (sr.s2 * sqrt(sr.s2));     // a'' (nodes64_far)
+                FarD f;
+                f.yx = sr.yx;
+                f.yy = sr.yy;
+                f.yz = sr.yz;
+                f.ax = fa * sr.ax;
+                f.ay = fa * sr.ay;
+                f.az = fa * sr.az;
+                ring_f[pos] = f;
+            }
+            nn += __popcll(nm);
+            nf += __popcll(fm);
+            if (COUNT) nfar += (double)__popcll(fm);
+            // a full run of a ring, or at the end its remainder (< kRun64 records,
+            // contiguous since the heads are multiples of kRun64) padded to whole
+            // node groups
+            const int ln = nn >= kRun64 ? kRun64 : (last ? (nn + kNodeGroupSplit - 1) / kNodeGroupSplit * kNodeGroupSplit : 0);
+            const int lf = nf >= kRun64 ? kRun64 : (last ? (nf + kNodeGroupSplit - 1) / kNodeGroupSplit * kNodeGroupSplit : 0);
+            if (last) {
+                if (lane >= nn && lane < ln) ring_n[hn + lane] = pad_src();
+                if (lane >= nf && lane < lf) ring_f[hf + lane] = pad_fard();
+            }
+            __syncthreads();
+            if (ln > 0) {
+                double p = 0, gx = 0, gy = 0, gz = 0;
+#pragma unroll 1
+                for (int j = 0; j < ln; j += kNodeGroupSplit)
+                    nodes64<kNodeGroupSplit, COUNT>(ring_n + hn + j, x, y, z, p, gx, gy, gz, &nuse);
+                two_sum(sp, ep, p);
+                two_sum(sx, ex, gx);
+                two_sum(sy, ey, gy);
+                two_sum(sz, ez, gz);
+                hn = hn + kRun64 == kRing64 ? 0 : hn + kRun64;
+                nn = nn > kRun64 ? nn - kRun64 : 0;
+            }
+            if (lf > 0) {
+                double p = 0, gx = 0, gy = 0, gz = 0, hx = 0, hy = 0, hz = 0;
+#pragma unroll 1
+                for (int j = 0; j < lf; j += kNodeGroupSplit)
+                    nodes64_far<kNodeGroupSplit>(ring_f + hf + j, x, y, z, p, gx, gy, gz, hx, hy, hz);
+                gx = fma(3.0, gx, -hx);
+                gy = fma(3.0, gy, -hy);
+                gz = fma(3.0, gz, -hz);
+                two_sum(sp, ep, p);
+                two_sum(sx, ex, gx);
+                two_sum(sy, ey, gy);
+                two_sum(sz, ez, gz);
+                hf = hf + kRun64 == kRing64 ? 0 : hf + kRun64;
+                nf = nf > kRun64 ? nf - kRun64 : 0;
+            }
+        }
+        double ph = 0.0, g[3] = {0.0, 0.0, 0.0}, mph = 0.0, mg[3] = {0.0, 0.0, 0.0};
+        if (a.m2p_end[B] > a.m2p_beg[B])    // uniform: Ls is the M2P staging buffer first
+            fmm_m2p_list(a, B, Ls, x, y, z, mph, mg);
+        __syncthreads();                    // the rings (or the M2P buffer) are done
+        stage_local(a, B, Ls);
+        __syncthreads();                    // Ls staged
+        fmm_l2p(a, B, Ls, x, y, z, ph, g);
+        ph += mph;
+        g[0] += mg[0];
+        g[1] += mg[1];
+        g[2] += mg[2];
+        if (valid) {
+            const int64_t o = a.out_idx ? (int64_t)a.out_idx[ti] : ti;
+            a.phi[o] = (sp + ph) + ep;
+            if (a.grad) {
+                a.grad[3 * o] = (sx + g[0]) + ex;
+                a.grad[3 * o + 1] = (sy + g[1]) + ey;
+                a.grad[3 * o + 2] = (sz + g[2]) + ez;
+            }
+        }
+        if (a.pairs) {                      // [0] pairs of real targets, [1] lane slots spent, [2] inside the cut,
+                                            // [3] taken by the dipole-only loop
+            const double w = wave_sum(valid ? npair : 0.0), wl = wave_sum(npair);
+            const double wu = COUNT ? wave_sum(valid ? (double)nuse : 0.0) : 0.0;
+            const double wf = COUNT ? wave_sum(valid ? nfar : 0.0) : 0.0;
+            if (lane == 0) {
+                atomicAdd(a.pairs, w);
+                atomicAdd(a.pairs + 1, wl);
+                if (COUNT) {
+                    atomicAdd(a.pairs + 2, wu);
+                    atomicAdd(a.pairs + 3, wf);
+                }
+            }
+        }
+    }
+    queue_done(a);
+}
+
+// Mixed path: one wavefront per tile of 64 targets.  Each staged node is
+// tested against the tile's target bounding box: a node whose distance to the
+// box is beyond its cut radius (u >= KF32_X for every target of the tile)
+// goes to the far ring and the dipole-only loop, every other node to the near
+// ring and the general loop (float-float offsets, the rational fit for node
+// groups with a pair inside the cut).  Each ring is drained in runs of kRun
+// records, one compensated partial sum per run; the remainders are padded to
+// whole node groups at the end of the tile.  The rings share the dynamic LDS
+// with the local expansion, which is staged once the pairs are done.
+constexpr int kRun = 32;                 // records per partial sum
+
+constexpr int kRing = 96;                // ring capacity: kRun - 1 left over + 64 staged
+constexpr size_t kMixedRingBytes = kRing * (sizeof(SrcF) + sizeof(FarF));
+
+template <bool COUNT>
+__global__ __launch_bounds__(64) void k_eval_fmm_mixed(FmmEvalArgs a) {
+    constexpr int W = 64;
+    __shared__ RangeBatch<W> rb;
+    __shared__ double tbox[6];          // the tile's target bounding box (offsets from its origin)
+    // node rings while the pairs run, then the local expansion (ncp doubles)
+    // and the M2P staging buffer
+    extern __shared__ __attribute__((aligned(16))) double Ls[];
+    SrcF *ring_n = reinterpret_cast<SrcF *>(Ls);
+    FarF *ring_f = reinterpret_cast<FarF *>(ring_n + kRing);
+    const int ntiles = *a.ntiles_dev;
+    const int64_t n = a.n_dev ? (int64_t)*a.n_dev : a.n_max;
+    const int lane = threadIdx.x;
+    const double far_u = (double)KF32_X * (1.0 + 1e-4);     // margin over the FP32 rounding of u
     __shared__ int slot;
     for (int q = next_tile(a, &slot); q < ntiles; q = next_tile(a, &slot)) {
         const int tile = a.order[q];
@@ -1186,40 +1398,54 @@ __global__ __launch_bounds__(64) void k_eval_fmm_mixed(FmmEvalArgs a) {
         const int64_t ti = a.sidx ? (int64_t)a.sidx[valid ? sp_ : s0] : (valid ? sp_ : s0);
         const int64_t t0 = a.sidx ? (int64_t)a.sidx[s0] : s0;
         const double ox = a.tx[t0], oy = a.ty[t0], oz = a.tz[t0];     // tile origin
-        const double X = a.tx[ti], Y = a.ty[ti], Z = a.tz[ti];
-        const double dxo = X - ox, dyo = Y - oy, dzo = Z - oz;
+        const double dxo = a.tx[ti] - ox, dyo = a.ty[ti] - oy, dzo = a.tz[ti] - oz;
         const float x = (float)dxo, y = (float)dyo, z = (float)dzo;
         const float xl = (float)(dxo - (double)x), yl = (float)(dyo - (double)y), zl = (float)(dzo - (double)z);
         const int e0 = a.p2p_beg[B], e1 = a.p2p_end[B];
         // bounding box of the tile's targets (offsets from the origin; the
         // lanes past the tile end hold the first target)
-        const double o[3] = {ox, oy, oz};
         double blo[3] = {dxo, dyo, dzo}, bhi[3] = {dxo, dyo, dzo};
         for (int off = 32; off > 0; off >>= 1)
             for (int c = 0; c < 3; ++c) {
                 blo[c] = fmin(blo[c], __shfl_xor(blo[c], off));
                 bhi[c] = fmax(bhi[c], __shfl_xor(bhi[c], off));
             }
-        __syncthreads();                    // previous tile is done with Ls
-        stage_local(a, B, Ls);
+        __syncthreads();                    // the previous tile is done with tbox
+        if (lane == 0)
+            for (int c = 0; c < 3; ++c) {
+                tbox[c] = blo[c];
+                tbox[3 + c] = bhi[c];
+            }
         float sp = 0, ep = 0, sx = 0, ex = 0, sy = 0, ey = 0, sz = 0, ez = 0;
         double npair = 0.0, nfar = 0.0;
         uint32_t nuse = 0;
+        int hn = 0, nn = 0, hf = 0, nf = 0;     // head and fill of each ring (uniform)
         for (int eb = e0; eb < e1; eb += W) {
             const int nr = e1 - eb < W ? e1 - eb : W;
             __syncthreads();
-            int64_t nnear;
-            const int64_t total = load_ranges_split(a, rb, eb, nr, o, blo, bhi, &nnear);
+            const int64_t total = load_ranges<W>(a, rb, eb, nr);
             npair += (double)total;
-            if (COUNT) nfar += (double)(total - nnear);
             for (int64_t c0 = 0; c0 < total; c0 += W) {
                 const int cnt = (int)(total - c0 < W ? total - c0 : W);
-                const bool far = c0 >= nnear;   // uniform: every node of the chunk is far for the tile
-                __syncthreads();
-                SrcF f;
+                Src sr;
+                double qx = 0.0, qy = 0.0, qz = 0.0;
+                bool isfar = false;
                 if (lane < cnt) {
-                    const Src sr = a.src[packed_node<W>(rb, nr, c0 + lane)];
-                    const double qx = sr.yx - ox, qy = sr.yy - oy, qz = sr.yz - oz;
+                    sr = a.src[packed_node<W>(rb, nr, c0 + lane)];
+                    qx = sr.yx - ox;
+                    qy = sr.yy - oy;
+                    qz = sr.yz - oz;
+                    const double gx_ = fmax(fmax(tbox[0] - qx, qx - tbox[3]), 0.0);
+                    const double gy_ = fmax(fmax(tbox[1] - qy, qy - tbox[4]), 0.0);
+                    const double gz_ = fmax(fmax(tbox[2] - qz, qz - tbox[5]), 0.0);
+                    isfar = (gx_ * gx_ + gy_ * gy_ + gz_ * gz_) * sr.s2 >= far_u;
+                }
+                const uint64_t fm = __ballot(isfar), nm = __ballot(lane < cnt && !isfar);
+                __syncthreads();                // the runs taken last are read
+                if (lane < cnt && !isfar) {
+                    int pos = hn + nn + below(nm);
+                    if (pos >= kRing) pos -= kRing;
+                    SrcF f;
                     f.yx = (float)qx;
                     f.yy = (float)qy;
                     f.yz = (float)qz;
@@ -1227,39 +1453,92 @@ __global__ __launch_bounds__(64) void k_eval_fmm_mixed(FmmEvalArgs a) {
                     f.ly = (float)(qy - (double)f.yy);
                     f.lz = (float)(qz - (double)f.yz);
                     f.s2 = (float)sr.s2;
-                    // far chunks: a'' = (sqrt(pi)/2) a' s2^(-3/2) (nodes32_far)
-                    const double fa = far ? kFoldA / (sr.s2 * sqrt(sr.s2)) : kFoldA;
+                    f.ax = (float)(kFoldA * sr.ax);
+                    f.ay = (float)(kFoldA * sr.ay);
+                    f.az = (float)(kFoldA * sr.az);
+                    f.s2x2 = (float)(kFoldT * sr.s2x2);
+                    f.pad = 0.0f;
+                    ring_n[pos] = f;
+                } else if (isfar) {
+                    int pos = hf + nf + below(fm);
+                    if (pos >= kRing) pos -= kRing;
+                    const double fa = kFoldA / (sr.s2 * sqrt(sr.s2));     // a'' (nodes32_far)
+                    FarF f;
+                    f.yx = (float)qx;
+                    f.yy = (float)qy;
+                    f.yz = (float)qz;
                     f.ax = (float)(fa * sr.ax);
                     f.ay = (float)(fa * sr.ay);
                     f.az = (float)(fa * sr.az);
-                    f.s2x2 = (float)(kFoldT * sr.s2x2);
-                } else {
-                    f = pad_srcf();
+                    f.pad0 = f.pad1 = 0.0f;
+                    ring_f[pos] = f;
                 }
-                f.pad = 0.0f;
-                sh[lane] = f;
+                nn += __popcll(nm);
+                nf += __popcll(fm);
+                if (COUNT) nfar += (double)__popcll(fm);
                 __syncthreads();
-                for (int j0 = 0; j0 < cnt; j0 += 32) {
+                for (; nn >= kRun; nn -= kRun) {
                     float p = 0, gx = 0, gy = 0, gz = 0;
-                    const int j1 = j0 + 32 < cnt ? j0 + 32 : cnt;
-                    if (far) {
-                        for (int j = j0; j < j1; j += kNodeGroup) nodes32_far<kNodeGroup>(sh + j, x, y, z, p, gx, gy, gz);
-                    } else {
-                        for (int j = j0; j < j1; j += kNodeGroup)
-                            nodes32<kNodeGroup, COUNT>(sh + j, x, y, z, xl, yl, zl, p, gx, gy, gz, &nuse);
-                    }
+#pragma unroll 1
+                    for (int j = 0; j < kRun; j += kNodeGroup)
+                        nodes32<kNodeGroup, COUNT>(ring_n + hn + j, x, y, z, xl, yl, zl, p, gx, gy, gz, &nuse);
                     two_sum_f(sp, ep, p);
                     two_sum_f(sx, ex, gx);
                     two_sum_f(sy, ey, gy);
                     two_sum_f(sz, ez, gz);
+                    hn = hn + kRun == kRing ? 0 : hn + kRun;
+                }
+                for (; nf >= kRun; nf -= kRun) {
+                    float p = 0, gx = 0, gy = 0, gz = 0, hx = 0, hy = 0, hz = 0;
+#pragma unroll 1
+                    for (int j = 0; j < kRun; j += kNodeGroup)
+                        nodes32_far<kNodeGroup>(ring_f + hf + j, x, y, z, p, gx, gy, gz, hx, hy, hz);
+                    gx = fmaf(3.0f, gx, -hx);
+                    gy = fmaf(3.0f, gy, -hy);
+                    gz = fmaf(3.0f, gz, -hz);
+                    two_sum_f(sp, ep, p);
+                    two_sum_f(sx, ex, gx);
+                    two_sum_f(sy, ey, gy);
+                    two_sum_f(sz, ez, gz);
+                    hf = hf + kRun == kRing ? 0 : hf + kRun;
                 }
             }
         }
-        double ph = 0.0, g[3] = {0.0, 0.0, 0.0}, mph = 0.0, mg[3] = {0.0, 0.0, 0.0};
-        if (a.m2p_end[B] > a.m2p_beg[B]) {  // uniform: Ls is the M2P staging buffer, then L again
-            fmm_m2p_list(a, B, Ls, X, Y, Z, mph, mg);
-            stage_local(a, B, Ls);
+        if (nn > 0 || nf > 0) {             // remainders (< kRun each), padded to whole node groups
+            const int pn = (nn + kNodeGroup - 1) / kNodeGroup * kNodeGroup;
+            const int pf = (nf + kNodeGroup - 1) / kNodeGroup * kNodeGroup;
+            __syncthreads();
+            if (lane >= nn && lane < pn) ring_n[hn + lane] = pad_srcf();    // hn + kRun <= kRing
+            if (lane >= nf && lane < pf) ring_f[hf + lane] = pad_farf();
+            __syncthreads();
+            if (nn > 0) {
+                float p = 0, gx = 0, gy = 0, gz = 0;
+                for (int j = 0; j < pn; j += kNodeGroup)
+                    nodes32<kNodeGroup, COUNT>(ring_n + hn + j, x, y, z, xl, yl, zl, p, gx, gy, gz, &nuse);
+                two_sum_f(sp, ep, p);
+                two_sum_f(sx, ex, gx);
+                two_sum_f(sy, ey, gy);
+                two_sum_f(sz, ez, gz);
+            }
+            if (nf > 0) {
+                float p = 0, gx = 0, gy = 0, gz = 0, hx = 0, hy = 0, hz = 0;
+                for (int j = 0; j < pf; j += kNodeGroup)
+                    nodes32_far<kNodeGroup>(ring_f + hf + j, x, y, z, p, gx, gy, gz, hx, hy, hz);
+                gx = fmaf(3.0f, gx, -hx);
+                gy = fmaf(3.0f, gy, -hy);
+                gz = fmaf(3.0f, gz, -hz);
+                two_sum_f(sp, ep, p);
+                two_sum_f(sx, ex, gx);
+                two_sum_f(sy, ey, gy);
+                two_sum_f(sz, ez, gz);
+            }
         }
+        const double X = a.tx[ti], Y = a.ty[ti], Z = a.tz[ti];
+        double ph = 0.0, g[3] = {0.0, 0.0, 0.0}, mph = 0.0, mg[3] = {0.0, 0.0, 0.0};
+        if (a.m2p_end[B] > a.m2p_beg[B])    // uniform: Ls is the M2P staging buffer first
+            fmm_m2p_list(a, B, Ls, X, Y, Z, mph, mg);
+        __syncthreads();                    // the rings (or the M2P buffer) are done
+        stage_local(a, B, Ls);
         __syncthreads();                    // Ls staged
         fmm_l2p(a, B, Ls, X, Y, Z, ph, g);
         ph += mph;
@@ -1289,6 +1568,7 @@ __global__ __launch_bounds__(64) void k_eval_fmm_mixed(FmmEvalArgs a) {
                 }
             }
         }
+        __syncthreads();                    // Ls is read before the next tile's rings overwrite it
     }
     queue_done(a);
 }
@@ -1315,6 +1595,15 @@ void launch_hess_tile(Ctx &c, unsigned grid, const FmmEvalArgs &a, double *hess)
 
 template <int TILE>
 void launch_fmm_tile(Ctx &c, unsigned grid, const FmmEvalArgs &a) {
+    if (TILE == 64) {
+        const size_t shm = std::max(kF64RingBytes, sizeof(double) * (size_t)a.ncp);
+        if (c.opt.count_useful)
+            hipLaunchKernelGGL(k_eval_fmm_f64_split<true>, dim3(grid), dim3(64), shm, c.stream, a);
+        else
+            hipLaunchKernelGGL(k_eval_fmm_f64_split<false>, dim3(grid), dim3(64), shm, c.stream, a);
+        LSS_CHECK_LAUNCH("k_eval_fmm_f64_split");
+        return;
+    }
     const size_t shm = sizeof(double) * (size_t)a.ncp;
     if (c.opt.count_useful)
         hipLaunchKernelGGL((k_eval_fmm_f64<TILE, true>), dim3(grid), dim3(TILE), shm, c.stream, a);
@@ -1408,12 +1697,11 @@ void launch_eval_fmm(Ctx &c, int64_t max_tiles, const int32_t *ntiles_dev, const
         return;
     }
     if (c.opt.precision == LSS_MIXED) {
+        const size_t shm = std::max(kMixedRingBytes, sizeof(double) * (size_t)a.ncp);
         if (c.opt.count_useful)
-            hipLaunchKernelGGL(k_eval_fmm_mixed<true>, dim3(grid), dim3(64), sizeof(double) * (size_t)a.ncp, c.stream,
-                               a);
+            hipLaunchKernelGGL(k_eval_fmm_mixed<true>, dim3(grid), dim3(64), shm, c.stream, a);
         else
-            hipLaunchKernelGGL(k_eval_fmm_mixed<false>, dim3(grid), dim3(64), sizeof(double) * (size_t)a.ncp, c.stream,
-                               a);
+            hipLaunchKernelGGL(k_eval_fmm_mixed<false>, dim3(grid), dim3(64), shm, c.stream, a);
         LSS_CHECK_LAUNCH("k_eval_fmm_mixed");
     } else {
         switch (fmm_tile(c)) {

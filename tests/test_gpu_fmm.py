@@ -312,12 +312,10 @@ def test_useful_pair_count(graded, prec):
         prec, st["useful_pairs"], want, st["last_pairs"], st["last_pairs"] / max(st["useful_pairs"], 1)))
     assert abs(st["useful_pairs"] - want) <= 2 + 1e-7 * want
     assert st["useful_pairs"] <= st["last_pairs"]
-    # the dipole-only loop (mixed kernel) takes none of the pairs inside the cut
+    # the dipole-only loop (nodes beyond the cut of every target of a tile)
+    # takes none of the pairs inside the cut
     say("  dipole-only pairs %.0f, full-kernel pairs %.0f" % (st["dipole_pairs"], st["last_pairs"] - st["dipole_pairs"]))
-    if prec == lss.MIXED:
-        assert 0.0 < st["dipole_pairs"] and st["useful_pairs"] <= st["last_pairs"] - st["dipole_pairs"]
-    else:
-        assert st["dipole_pairs"] == 0.0
+    assert 0.0 < st["dipole_pairs"] and st["useful_pairs"] <= st["last_pairs"] - st["dipole_pairs"]
     assert np.array_equal(p0, p1) and np.array_equal(g0, g1)
     cd = ctx(v, t, sig, prec, lss.FAR_DIRECT)
     cd.eval(xs[:100])
