@@ -454,7 +454,9 @@ def main():
         pair inside the cut (the near field the method asks for) plus the
         local-expansion evaluation, 8 (p+1)^2 per target; pairs evaluated
         beyond the cut (whole leaves of the near lists) are not counted."""
-        kname = ("k_eval_fmm_%s" if far else "k_p2p_direct_%s") % ("mixed" if dt == "f32" else "f64")
+        # the FP64 evaluation with the default 64-target tiles is k_eval_fmm_f64_split
+        kname = ("k_eval_fmm_%s" if far else "k_p2p_direct_%s") % (
+            "mixed" if dt == "f32" else ("f64_split" if far else "f64"))
         traffic = measured_traffic(kname, desc)
         if r["pair_kernel_launches"] <= 0 or r["pair_kernel_ms"] <= 0:
             return None
@@ -470,8 +472,8 @@ def main():
                 "l2p_flop_per_target": L2P_FLOP(p) if far else 0.0,
                 "executed_pairs_per_launch": r["pairs_per_step"] / r["pair_kernel_launches"],
                 "executed_over_useful": round(r["pairs_per_step"] / max(r["useful_pairs_per_step"], 1.0), 3),
-                # of the executed pairs, those of the dipole-only loop (leaves beyond the cut of
-                # every target of their tile; mixed kernel) and the rest, through the full kernel
+                # of the executed pairs, those of the dipole-only loop (nodes beyond the cut of
+                # every target of their tile) and the rest, through the full kernel
                 "dipole_loop_pairs_per_launch": r["dipole_pairs_per_step"] / r["pair_kernel_launches"],
                 "full_kernel_over_useful": round((r["pairs_per_step"] - r["dipole_pairs_per_step"])
                                                  / max(r["useful_pairs_per_step"], 1.0), 3),

@@ -175,11 +175,12 @@ typedef struct lss_stats {
                                  exact sum has no cut).  LSS_FAR_FMM: counted only with
                                  lss_options.count_useful, else 0.  last_pairs / useful_pairs is
                                  the overhead of evaluating whole leaves of the near lists. */
-    double  dipole_pairs;     /* LSS_FAR_FMM, LSS_MIXED, with lss_options.count_useful: pairs of the
-                                 last lss_eval / lss_project taken by the dipole-only loop (near-list
-                                 leaves beyond the cut of every target of their tile, summed with the
-                                 far kernel pair by pair); last_pairs - dipole_pairs went through the
-                                 full kernel.  Otherwise 0. */
+    double  dipole_pairs;     /* LSS_FAR_FMM with lss_options.count_useful (LSS_MIXED, or LSS_FP64
+                                 with 64-target tiles): pairs of the last lss_eval / lss_project
+                                 taken by the dipole-only loop (near-list nodes beyond their cut
+                                 radius of every target of their tile, summed with the far kernel
+                                 pair by pair); last_pairs - dipole_pairs went through the full
+                                 kernel.  Otherwise 0. */
 } lss_stats;
 
 /* Create a context on HIP device `hip_device`, queuing work on `hip_stream`

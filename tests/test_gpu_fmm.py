@@ -61,6 +61,32 @@ def test_fmm_vs_direct_all_targets(graded, prec):
     assert ep <= TOL[prec] and eg <= TOL[prec]
 
 
+def test_fmm_fp64_tile_widths_agree(graded):
+    """FP64 through the octree at 64-target tiles (the kernel that sends every
+    node beyond its cut radius of the whole tile to the dipole-only loop) and at
+    128 and 256 (one loop for every node): the same sums up to rounding order,
+    all within the FP64 bar of the direct sum; only the narrow tiles use the
+    dipole-only loop."""
+    v, t, sig, x = graded
+    say("case: FP64 FMM at tiles 64, 128, 256, %d targets" % len(x))
+    cd = ctx(v, t, sig, lss.FP64, lss.FAR_DIRECT)
+    pd, gd = cd.eval(x)
+    out = {}
+    for tile in (64, 128, 256):
+        cf = ctx(v, t, sig, lss.FP64, lss.FAR_FMM, tile=tile, count_useful=1)
+        out[tile] = cf.eval(x)
+        st = cf.stats()
+        ep, eg = errs(*out[tile], pd, gd)
+        say("  tile %d: e_phi %.3e e_grad %.3e, dipole-only pairs %.0f of %.0f" % (
+            tile, ep, eg, st["dipole_pairs"], st["last_pairs"]))
+        assert ep <= TOL[lss.FP64] and eg <= TOL[lss.FP64]
+        assert (st["dipole_pairs"] > 0) == (tile == 64)
+        assert st["useful_pairs"] <= st["last_pairs"] - st["dipole_pairs"]
+    for tile in (128, 256):
+        ep, eg = errs(*out[tile], *out[64])
+        assert ep <= 1e-13 and eg <= 1e-13
+
+
 @pytest.mark.parametrize("prec", [lss.FP64, lss.MIXED])
 def test_fmm_vs_oracle_sampled(graded, prec):
     v, t, sig, x = graded
