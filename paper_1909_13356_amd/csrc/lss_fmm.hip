@@ -60,6 +60,24 @@ __global__ void k_fill_op(int kind, int p, int ncp, int nops, const cd *__restri
 }
 
 // ------------------------------------------------------------------ P2M
+// Neighbour lanes through DPP wave shifts (one VALU move per 32-bit half, no
+// LDS round trip): the value of lane + 1 and of lane - 1; the lanes without a
+// neighbour (63 and 0) receive 0.
+__device__ __forceinline__ double dpp_f64(double v, int ctrl_is_next) {
+    const long long b = __double_as_longlong(v);
+    int lo = (int)b, hi = (int)(b >> 32);
+    if (ctrl_is_next) {
+        lo = __builtin_amdgcn_update_dpp(0, lo, 0x130, 0xf, 0xf, false);     // wave_shl:1
+        hi = __builtin_amdgcn_update_dpp(0, hi, 0x130, 0xf, 0xf, false);
+    } else {
+        lo = __builtin_amdgcn_update_dpp(0, lo, 0x138, 0xf, 0xf, false);     // wave_shr:1
+        hi = __builtin_amdgcn_update_dpp(0, hi, 0x138, 0xf, 0xf, false);
+    }
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double from_next_lane(double v) { return dpp_f64(v, 1); }
+__device__ __forceinline__ double from_prev_lane(double v) { return dpp_f64(v, 0); }
+
 struct Geo {
     const double *root;         // per-mesh root cubes (corner xyz, side)
     const int32_t *bmesh;
@@ -135,8 +153,8 @@ __global__ __launch_bounds__(64) void k_p2m_cols(const int32_t *__restrict__ nle
             }
             if (st >= m) { u2 = u1; u1 = u; }
             // neighbours' columns at order st (same node slot; U^{-1} = -conj(U^1))
-            const double upre = __shfl(u.re, lane + 1), upim = __shfl(u.im, lane + 1);
-            const double dnre = __shfl(u.re, lane - 1), dnim = __shfl(u.im, lane - 1);
+            const double upre = from_next_lane(u.re), upim = from_next_lane(u.im);
+            const double dnre = from_prev_lane(u.re), dnim = from_prev_lane(u.im);
             cd up = m + 1 < C ? cd{upre, upim} : cd{0.0, 0.0};
             cd dn = m >= 1 ? cd{dnre, dnim} : cd{-upre, upim};
             if (live && m <= st + 1) {
@@ -232,8 +250,8 @@ __global__ __launch_bounds__(64) void k_p2m_reg(const int32_t *__restrict__ nlea
                 d = fmm::cscale(fmm::cmul(d, cd{x, y}), dfac[st + 1]);
             }
             if (st >= m) { u2 = u1; u1 = u; }
-            const double upre = __shfl(u.re, lane + 1), upim = __shfl(u.im, lane + 1);
-            const double dnre = __shfl(u.re, lane - 1), dnim = __shfl(u.im, lane - 1);
+            const double upre = from_next_lane(u.re), upim = from_next_lane(u.im);
+            const double dnre = from_prev_lane(u.re), dnim = from_prev_lane(u.im);
             cd up = m + 1 < C ? cd{upre, upim} : cd{0.0, 0.0};
             cd dn = m >= 1 ? cd{dnre, dnim} : cd{-upre, upim};
             if (live && m <= st + 1) {
@@ -545,26 +563,38 @@ void build_fmm(Ctx &c) {
     t.L.ensure(sizeof(double) * t.nboxes * ncp);
     // The upward pass (P2M, M2M) needs only the boxes: it runs on the
     // auxiliary stream while the interaction lists are built on the context
-    // stream; the M2L waits for both.  Same kernels, same order per buffer,
-    // so the results do not depend on the overlap.
+    // stream; the M2L waits for both.  The direct and M2P lists are sorted
+    // on the auxiliary stream after the upward pass, beside the
+    // translations; the context stream waits for them before returning.
+    // Same kernels, same order per buffer, so the results do not depend on
+    // the overlap.
     if (!c.aux_stream) {
         LSS_HIP(hipStreamCreateWithFlags(&c.aux_stream, hipStreamNonBlocking));
         for (hipEvent_t &e : c.aux_ev) LSS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     }
+    struct StreamSwap {
+        Ctx &c;
+        hipStream_t saved;
+        ~StreamSwap() { c.stream = saved; }
+    };
     LSS_HIP(hipEventRecord(c.aux_ev[0], c.stream));
     LSS_HIP(hipStreamWaitEvent(c.aux_stream, c.aux_ev[0], 0));
     DBuf flag, ids, leaves, nleaf;
     {
-        struct StreamSwap {
-            Ctx &c;
-            hipStream_t saved;
-            ~StreamSwap() { c.stream = saved; }
-        } swap{c, c.stream};
+        StreamSwap swap{c, c.stream};
         c.stream = c.aux_stream;
         upward_pass(c, p, ncp, flag, ids, leaves, nleaf);
         LSS_HIP(hipEventRecord(c.aux_ev[1], c.aux_stream));
     }
     build_tree_lists(c);
+    LSS_HIP(hipEventRecord(c.aux_ev[2], c.stream));        // lists emitted, M2L list sorted
+    {
+        StreamSwap swap{c, c.stream};
+        c.stream = c.aux_stream;
+        LSS_HIP(hipStreamWaitEvent(c.aux_stream, c.aux_ev[2], 0));
+        sort_near_lists(c);
+        LSS_HIP(hipEventRecord(c.aux_ev[3], c.aux_stream));
+    }
     LSS_HIP(hipStreamWaitEvent(c.stream, c.aux_ev[1], 0));
     {   // M2L operators of the classes in use not built yet
         std::vector<int> need;
@@ -602,6 +632,7 @@ void build_fmm(Ctx &c) {
                    base, t.parent.as<int32_t>(), t.level.as<int32_t>(), t.root.as<double>(), t.bmesh.as<int32_t>()};
         gemm(c, a);
     }
+    LSS_HIP(hipStreamWaitEvent(c.stream, c.aux_ev[3], 0));   // the direct and M2P lists
     c.stats.fmm_order = p;
 }
 

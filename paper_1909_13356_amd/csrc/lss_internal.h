@@ -226,7 +226,7 @@ struct Ctx {
     // non-blocking): the upward pass runs on it while the interaction lists
     // are built on `stream`; aux_ev orders the two
     hipStream_t aux_stream = nullptr;
-    hipEvent_t aux_ev[2] = {nullptr, nullptr};
+    hipEvent_t aux_ev[4] = {nullptr, nullptr, nullptr, nullptr};
     std::string err;
     lss_options opt{};
     lss_stats stats{};
@@ -354,7 +354,8 @@ void build_tree(Ctx &c);
 // the two halves of build_tree: the boxes (levels, radii, target cuts), then
 // the interaction lists of the dual traversal (sorted, per class)
 void build_tree_boxes(Ctx &c);
-void build_tree_lists(Ctx &c);
+void build_tree_lists(Ctx &c);     // traversal and the sorted M2L list
+void sort_near_lists(Ctx &c);      // the sorted direct and M2P lists, per-box tile costs
 void build_fmm(Ctx &c);
 void launch_locate_targets(Ctx &c, int64_t n_max, const int32_t *n_dev, const double *tx, const double *ty,
                            const double *tz, const int32_t *tmesh, uint64_t *keys, int32_t *idx);

@@ -42,6 +42,13 @@ constexpr int kBlk = 256;
 constexpr int kR = 7;             // class offsets in [-kR, kR]^3
 constexpr int kNClass = (2 * kR + 1) * (2 * kR + 1) * (2 * kR + 1);
 
+// bits that hold every value below n (radix sorts skip the bits above)
+inline int bits_for(int64_t n) {
+    int b = 1;
+    while ((int64_t(1) << b) < n) ++b;
+    return b;
+}
+
 inline unsigned grid_for(int64_t n, int blk = kBlk) { return (unsigned)ceil_div(n > 0 ? n : 1, blk); }
 
 __device__ inline uint64_t spread21(uint64_t x) { return tree_spread21(x); }
@@ -881,36 +888,11 @@ void build_tree_lists(Ctx &c) {
         std::swap(t.fr.bytes, t.fr2.bytes);
         nfr = npush;
     }
-    // sort the lists; per-box direct ranges and per-class M2L segments
-    t.p2p_key2.ensure(8 * (t.n_p2p + 1)); t.p2p_val2.ensure(4 * (t.n_p2p + 1));
-    sort_pairs(c, t.p2p_key.as<uint64_t>(), t.p2p_key2.as<uint64_t>(), t.p2p_val.as<int32_t>(),
-               t.p2p_val2.as<int32_t>(), t.n_p2p);
-    t.p2p_beg.ensure(4 * (t.nboxes + 1)); t.p2p_end.ensure(4 * (t.nboxes + 1));
-    LSS_HIP(hipMemsetAsync(t.p2p_beg.p, 0, 4 * (t.nboxes + 1), c.stream));
-    LSS_HIP(hipMemsetAsync(t.p2p_end.p, 0, 4 * (t.nboxes + 1), c.stream));
-    if (t.n_p2p > 0)
-        hipLaunchKernelGGL(k_p2p_ranges, dim3(grid_for(t.n_p2p)), dim3(kBlk), 0, c.stream, t.n_p2p,
-                           t.p2p_key2.as<uint64_t>(), t.p2p_beg.as<int32_t>(), t.p2p_end.as<int32_t>());
-    t.m2p_key2.ensure(8 * (t.n_m2p + 1)); t.m2p_val2.ensure(4 * (t.n_m2p + 1));
-    sort_pairs(c, t.m2p_key.as<uint64_t>(), t.m2p_key2.as<uint64_t>(), t.m2p_val.as<int32_t>(),
-               t.m2p_val2.as<int32_t>(), t.n_m2p);
-    t.m2p_beg.ensure(4 * (t.nboxes + 1)); t.m2p_end.ensure(4 * (t.nboxes + 1));
-    LSS_HIP(hipMemsetAsync(t.m2p_beg.p, 0, 4 * (t.nboxes + 1), c.stream));
-    LSS_HIP(hipMemsetAsync(t.m2p_end.p, 0, 4 * (t.nboxes + 1), c.stream));
-    if (t.n_m2p > 0)
-        hipLaunchKernelGGL(k_p2p_ranges, dim3(grid_for(t.n_m2p)), dim3(kBlk), 0, c.stream, t.n_m2p,
-                           t.m2p_key2.as<uint64_t>(), t.m2p_beg.as<int32_t>(), t.m2p_end.as<int32_t>());
-    // an M2P costs about as much as (p + 2)^2 / 4 direct pairs
-    const int p_est = fmm_order_for(c);
-    t.near_cnt.ensure(8 * (t.nboxes + nm));
-    hipLaunchKernelGGL(k_near_count, dim3(grid_for(t.nboxes + nm)), dim3(kBlk), 0, c.stream, t.nboxes, nm,
-                       t.p2p_beg.as<int32_t>(), t.p2p_end.as<int32_t>(), t.p2p_val2.as<int32_t>(),
-                       t.m2p_beg.as<int32_t>(), t.m2p_end.as<int32_t>(), (int64_t)(p_est + 2) * (p_est + 2) / 4,
-                       t.nb.as<int64_t>(), t.ne.as<int64_t>(), t.near_cnt.as<int64_t>());
-    LSS_CHECK_LAUNCH("k_near_count");
+    // the M2L list sorted by class; the direct and M2P lists are sorted by
+    // sort_near_lists (the translations do not need them)
     t.m2l_key2.ensure(8 * (t.n_m2l + 1)); t.m2l_val2.ensure(4 * (t.n_m2l + 1));
     sort_pairs(c, t.m2l_key.as<uint64_t>(), t.m2l_key2.as<uint64_t>(), t.m2l_val.as<int32_t>(),
-               t.m2l_val2.as<int32_t>(), t.n_m2l);
+               t.m2l_val2.as<int32_t>(), t.n_m2l, 32 + bits_for(kNClass));
     DBuf cb, ce;
     cb.ensure(8 * kNClass); ce.ensure(8 * kNClass);
     LSS_HIP(hipMemsetAsync(cb.p, 0, 8 * kNClass, c.stream));
@@ -933,9 +915,46 @@ void build_tree_lists(Ctx &c) {
     c.stats.n_m2p = t.n_m2p;
 }
 
+// Direct and M2P lists sorted by target box (then source box), their
+// per-box ranges and each box's tile cost.  Keys are (T << 32) | S with
+// T, S < nboxes + nmesh, so only the low 32 + bits(nboxes + nmesh) bits
+// are sorted.
+void sort_near_lists(Ctx &c) {
+    Tree &t = c.tree;
+    const int32_t nm = c.nmesh;
+    const int kbits = 32 + bits_for(t.nboxes + nm);
+    t.p2p_key2.ensure(8 * (t.n_p2p + 1)); t.p2p_val2.ensure(4 * (t.n_p2p + 1));
+    sort_pairs(c, t.p2p_key.as<uint64_t>(), t.p2p_key2.as<uint64_t>(), t.p2p_val.as<int32_t>(),
+               t.p2p_val2.as<int32_t>(), t.n_p2p, kbits);
+    t.p2p_beg.ensure(4 * (t.nboxes + 1)); t.p2p_end.ensure(4 * (t.nboxes + 1));
+    LSS_HIP(hipMemsetAsync(t.p2p_beg.p, 0, 4 * (t.nboxes + 1), c.stream));
+    LSS_HIP(hipMemsetAsync(t.p2p_end.p, 0, 4 * (t.nboxes + 1), c.stream));
+    if (t.n_p2p > 0)
+        hipLaunchKernelGGL(k_p2p_ranges, dim3(grid_for(t.n_p2p)), dim3(kBlk), 0, c.stream, t.n_p2p,
+                           t.p2p_key2.as<uint64_t>(), t.p2p_beg.as<int32_t>(), t.p2p_end.as<int32_t>());
+    t.m2p_key2.ensure(8 * (t.n_m2p + 1)); t.m2p_val2.ensure(4 * (t.n_m2p + 1));
+    sort_pairs(c, t.m2p_key.as<uint64_t>(), t.m2p_key2.as<uint64_t>(), t.m2p_val.as<int32_t>(),
+               t.m2p_val2.as<int32_t>(), t.n_m2p, kbits);
+    t.m2p_beg.ensure(4 * (t.nboxes + 1)); t.m2p_end.ensure(4 * (t.nboxes + 1));
+    LSS_HIP(hipMemsetAsync(t.m2p_beg.p, 0, 4 * (t.nboxes + 1), c.stream));
+    LSS_HIP(hipMemsetAsync(t.m2p_end.p, 0, 4 * (t.nboxes + 1), c.stream));
+    if (t.n_m2p > 0)
+        hipLaunchKernelGGL(k_p2p_ranges, dim3(grid_for(t.n_m2p)), dim3(kBlk), 0, c.stream, t.n_m2p,
+                           t.m2p_key2.as<uint64_t>(), t.m2p_beg.as<int32_t>(), t.m2p_end.as<int32_t>());
+    // an M2P costs about as much as (p + 2)^2 / 4 direct pairs
+    const int p_est = fmm_order_for(c);
+    t.near_cnt.ensure(8 * (t.nboxes + nm));
+    hipLaunchKernelGGL(k_near_count, dim3(grid_for(t.nboxes + nm)), dim3(kBlk), 0, c.stream, t.nboxes, nm,
+                       t.p2p_beg.as<int32_t>(), t.p2p_end.as<int32_t>(), t.p2p_val2.as<int32_t>(),
+                       t.m2p_beg.as<int32_t>(), t.m2p_end.as<int32_t>(), (int64_t)(p_est + 2) * (p_est + 2) / 4,
+                       t.nb.as<int64_t>(), t.ne.as<int64_t>(), t.near_cnt.as<int64_t>());
+    LSS_CHECK_LAUNCH("k_near_count");
+}
+
 void build_tree(Ctx &c) {
     build_tree_boxes(c);
     build_tree_lists(c);
+    sort_near_lists(c);
 }
 
 void launch_soa(Ctx &c, const double *x, int64_t n, double *tx, double *ty, double *tz) {
