@@ -109,10 +109,7 @@ __device__ __forceinline__ void kfun64(double x, double &S, double &T) {
         S = ps * r;
         T = pt * r;
     } else {
-        double r = __builtin_amdgcn_rsq(x);
-        const double hx = 0.5 * x;
-        r = r * fma(-hx * r, r, 1.5);
-        r = r * fma(-hx * r, r, 1.5);
+        const double r = rsq64(x);
         const double r2 = r * r;
         S = r2 * r;
         T = S * r2;
@@ -173,10 +170,7 @@ __device__ __forceinline__ void nodes64(const Src *sh, double x, double y, doubl
         u[k] = r2 * s.s2;
         umin = fmin(umin, u[k]);
         const double ux = fmax(u[k], KF64_X);
-        double r = __builtin_amdgcn_rsq(ux);
-        const double hx = 0.5 * ux;
-        r = r * fma(-hx * r, r, 1.5);
-        r = r * fma(-hx * r, r, 1.5);
+        const double r = rsq64(ux);
         const double rr = r * r;
         S[k] = rr * r;                      // folded far form (see fold_src)
         T[k] = S[k] * rr;
@@ -230,7 +224,7 @@ __device__ __forceinline__ FarD pad_fard() {
 
 // K consecutive FP64 far records against one target: the Laplace dipole with
 // the width moved into a'' and the gradient summed in two parts, as
-// nodes32_far; rsq refined by two Newton steps
+// nodes32_far; 1/sqrt refined to FP64 (rsq64)
 template <int K>
 __device__ __forceinline__ void nodes64_far(const FarD *sh, double x, double y, double z, double &p, double &gx,
                                             double &gy, double &gz, double &hx, double &hy, double &hz) {
@@ -239,10 +233,7 @@ __device__ __forceinline__ void nodes64_far(const FarD *sh, double x, double y, 
         const FarD s = sh[k];
         const double dx = x - s.yx, dy = y - s.yy, dz = z - s.yz;
         const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-        double r = __builtin_amdgcn_rsq(r2);
-        const double h2 = 0.5 * r2;
-        r = r * fma(-h2 * r, r, 1.5);
-        r = r * fma(-h2 * r, r, 1.5);
+        const double r = rsq64(r2);
         const double rr = r * r, S = rr * r;
         const double ad = fma(s.ax, dx, fma(s.ay, dy, s.az * dz));
         p = fma(-ad, S, p);
@@ -341,10 +332,7 @@ __device__ __forceinline__ void pair_ms_cut(const Src &s, double px, double py, 
         double k3;
         radial3(t, s2x, k1, k2, k3, et);
     } else {
-        double iu = __builtin_amdgcn_rsq(t);
-        const double ht = 0.5 * t;
-        iu = iu * fma(-ht * iu, iu, 1.5);
-        iu = iu * fma(-ht * iu, iu, 1.5);
+        const double iu = rsq64(t);
         const double iu3 = iu * iu * iu;
         k1 = (0.5 * kSqrtPi) * iu3;
         k2 = -(1.5 * kSqrtPi) * s2x * iu3 * iu * iu;
@@ -371,10 +359,7 @@ __device__ __forceinline__ void pair_hess_cut(const Src &s, double px, double py
         double et;
         radial3(t, s.s2, k1, k2, k3, et);
     } else {
-        double iu = __builtin_amdgcn_rsq(t);
-        const double ht = 0.5 * t;
-        iu = iu * fma(-ht * iu, iu, 1.5);
-        iu = iu * fma(-ht * iu, iu, 1.5);
+        const double iu = rsq64(t);
         const double iu2 = iu * iu, iu3 = iu2 * iu, iu5 = iu3 * iu2;
         k1 = (0.5 * kSqrtPi) * iu3;
         k2 = -(1.5 * kSqrtPi) * s.s2 * iu5;

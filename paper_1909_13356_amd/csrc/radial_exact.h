@@ -40,11 +40,8 @@ __device__ inline void radial3(double t, double s2, double &k1, double &k2, doub
         e = a0;
         return;
     }
-    // 1/u = t^-1/2: hardware estimate and two Newton steps (to rounding)
-    double iu = __builtin_amdgcn_rsq(t);
-    const double ht = 0.5 * t;
-    iu = iu * fma(-ht * iu, iu, 1.5);
-    iu = iu * fma(-ht * iu, iu, 1.5);
+    // 1/u = t^-1/2: hardware estimate and one third-order correction (to rounding)
+    const double iu = rsq64(t);
     double P3 = 1.0, P5 = 1.0, P7 = 1.0;
     e = 0.0;
     if (t < 50.0) {
