@@ -8,6 +8,7 @@
 // box-scaled form); inside a launch every destination box appears once, so
 // the accumulation is race free and deterministic.
 #include <cstring>
+#include <algorithm>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -446,6 +447,30 @@ void gemm(Ctx &c, GemmArgs a) {
     }
 }
 
+__global__ void k_fill_zero(int64_t n, double *y) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = 0.0;
+}
+
+__global__ void k_add(int64_t n, double *y, const double *x) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] += x[i];
+}
+
+void launch_fill_zero(Ctx &c, double *y, int64_t n) {
+    if (n <= 0) return;
+    const int64_t g = ceil_div(n, kBlk);
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)(g < 65536 ? g : 65536)), dim3(kBlk), 0, c.stream, n, y);
+    LSS_CHECK_LAUNCH("k_fill_zero");
+}
+
+void launch_add(Ctx &c, double *y, const double *x, int64_t n) {
+    if (n <= 0) return;
+    const int64_t g = ceil_div(n, kBlk);
+    hipLaunchKernelGGL(k_add, dim3((unsigned)(g < 65536 ? g : 65536)), dim3(kBlk), 0, c.stream, n, y, x);
+    LSS_CHECK_LAUNCH("k_add");
+}
+
 // class index -> offset vector
 void class_vec(int cls, double v[3]) {
     const int W = 2 * kR + 1;
@@ -613,18 +638,55 @@ void build_fmm(Ctx &c) {
     }
     // M2L, one launch per displacement class, each at its own order: the
     // leading (p_v + 1)^2 coefficients in and out (the real layout orders them
-    // by degree), p_v = m2l_order(p, K, v)
+    // by degree), p_v = m2l_order(p, K, v).  Within a class every target box
+    // occurs once, so a launch has no write conflicts; the classes run in two
+    // sets, one on each stream, into two accumulators (L, and L2 on the
+    // auxiliary stream), so that each stream's launches fill the other's gaps;
+    // L += L2 once both are done.  The sets depend only on the class sizes, so
+    // every box sums its classes in a fixed order.
+    struct M2LJob { int cls; int nkv; int64_t b0, n; };
+    std::vector<M2LJob> jobs;
     for (int cls : t.class_used) {
-        const int64_t b0 = t.class_beg[cls], n = t.class_end[cls] - b0;
         double v[3];
         class_vec(cls, v);
         const int pv = m2l_order(p, t.K, v);
         const int nkv = std::min(ncp, (int)ceil_div((int64_t)(pv + 1) * (pv + 1), kKB) * kKB);
-        GemmArgs a{G_LIST, ncp, nkv, n, t.opM2L.as<double>() + (int64_t)t.op_class_slot[cls] * per, t.M.as<double>(),
-                   t.L.as<double>(), t.m2l_key2.as<uint64_t>() + b0, t.m2l_val2.as<int32_t>() + b0, 0,
-                   t.parent.as<int32_t>(), t.level.as<int32_t>(), t.root.as<double>(), t.bmesh.as<int32_t>(), nkv};
-        gemm(c, a);
+        jobs.push_back({cls, nkv, t.class_beg[cls], t.class_end[cls] - t.class_beg[cls]});
     }
+    std::vector<char> on_aux(jobs.size(), 0);
+    {   // largest work first to the less loaded set (ties: the class index)
+        std::vector<size_t> ord(jobs.size());
+        for (size_t i = 0; i < ord.size(); ++i) ord[i] = i;
+        auto work = [&](size_t i) { return (double)jobs[i].n * jobs[i].nkv * jobs[i].nkv; };
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return work(a) > work(b); });
+        double load[2] = {0.0, 0.0};
+        for (size_t i : ord) {
+            const int side = load[1] < load[0] ? 1 : 0;
+            on_aux[i] = (char)side;
+            load[side] += work(i);
+        }
+    }
+    t.L2.ensure(sizeof(double) * t.nboxes * ncp);
+    LSS_HIP(hipEventRecord(c.aux_ev[4], c.stream));         // operators built
+    auto m2l = [&](const M2LJob &j, double *L) {
+        GemmArgs a{G_LIST, ncp, j.nkv, j.n, t.opM2L.as<double>() + (int64_t)t.op_class_slot[j.cls] * per, t.M.as<double>(),
+                   L, t.m2l_key2.as<uint64_t>() + j.b0, t.m2l_val2.as<int32_t>() + j.b0, 0,
+                   t.parent.as<int32_t>(), t.level.as<int32_t>(), t.root.as<double>(), t.bmesh.as<int32_t>(), j.nkv};
+        gemm(c, a);
+    };
+    {
+        StreamSwap swap{c, c.stream};
+        c.stream = c.aux_stream;
+        LSS_HIP(hipStreamWaitEvent(c.aux_stream, c.aux_ev[4], 0));
+        launch_fill_zero(c, t.L2.as<double>(), t.nboxes * (int64_t)ncp);
+        for (size_t i = 0; i < jobs.size(); ++i)
+            if (on_aux[i]) m2l(jobs[i], t.L2.as<double>());
+        LSS_HIP(hipEventRecord(c.aux_ev[5], c.aux_stream));
+    }
+    for (size_t i = 0; i < jobs.size(); ++i)
+        if (!on_aux[i]) m2l(jobs[i], t.L.as<double>());
+    LSS_HIP(hipStreamWaitEvent(c.stream, c.aux_ev[5], 0));
+    launch_add(c, t.L.as<double>(), t.L2.as<double>(), t.nboxes * (int64_t)ncp);
     // downward pass: L2L from level 0 to depth-1 into their children
     for (int lvl = 1; lvl <= t.depth; ++lvl) {
         const int64_t base = t.level_begin[lvl], npar = (t.level_begin[lvl + 1] - base) / 8;

@@ -218,7 +218,7 @@ struct Tree {
     std::vector<int32_t> class_used;
     // expansions and operators
     int p = 0, ncp = 0, K = 4;
-    DBuf M, L;                                // nboxes * ncp doubles
+    DBuf M, L, L2;                            // nboxes * ncp doubles (L2: the M2L classes of the second stream)
     DBuf opM2M, opL2L, opM2L;                 // 8, 8 and nclass_used operators (ncp*ncp, k-major)
     std::vector<int32_t> op_class_slot;       // class -> slot in opM2L (-1 if not built)
     int ops_p = -1, ops_R = -1;
@@ -236,7 +236,7 @@ struct Ctx {
     // non-blocking): the upward pass runs on it while the interaction lists
     // are built on `stream`; aux_ev orders the two
     hipStream_t aux_stream = nullptr;
-    hipEvent_t aux_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t aux_ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     std::string err;
     lss_options opt{};
     lss_stats stats{};
