@@ -68,11 +68,11 @@ __device__ __forceinline__ double dpp_f64(double v, int ctrl_is_next) {
     const long long b = __double_as_longlong(v);
     int lo = (int)b, hi = (int)(b >> 32);
     if (ctrl_is_next) {
-        lo = __builtin_amdgcn_update_dpp(0, lo, 0x130, 0xf, 0xf, false);     // wave_shl:1
-        hi = __builtin_amdgcn_update_dpp(0, hi, 0x130, 0xf, 0xf, false);
+        lo = __builtin_amdgcn_mov_dpp(lo, 0x130, 0xf, 0xf, true);     // wave_shl:1
+        hi = __builtin_amdgcn_mov_dpp(hi, 0x130, 0xf, 0xf, true);
     } else {
-        lo = __builtin_amdgcn_update_dpp(0, lo, 0x138, 0xf, 0xf, false);     // wave_shr:1
-        hi = __builtin_amdgcn_update_dpp(0, hi, 0x138, 0xf, 0xf, false);
+        lo = __builtin_amdgcn_mov_dpp(lo, 0x138, 0xf, 0xf, true);     // wave_shr:1
+        hi = __builtin_amdgcn_mov_dpp(hi, 0x138, 0xf, 0xf, true);
     }
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
@@ -219,6 +219,9 @@ __global__ __launch_bounds__(64) void k_p2m_reg(const int32_t *__restrict__ nlea
     double are[P], aim[P];                                // contributions to M_{st+1}^m
 #pragma unroll
     for (int st = 0; st < P; ++st) are[st] = aim[st] = 0.0;
+    double w[P];                                          // recurrence weights of column m
+#pragma unroll
+    for (int st = 0; st < P; ++st) w[st] = rinv[fmm::tri(st, m)];     // in range for every m <= P
     const int64_t b0 = nb[b], b1 = ne[b];
     for (int64_t k0 = b0; k0 < b1; k0 += G) {
         const int64_t k = k0 + gi;
@@ -237,31 +240,46 @@ __global__ __launch_bounds__(64) void k_p2m_reg(const int32_t *__restrict__ nlea
             az = sr.az * f;
         }
         const double r2 = x * x + y * y + z * z;
-        cd d = {1.0, 0.0}, u1 = {0.0, 0.0}, u2 = {0.0, 0.0};
+        // The dipole term of M_{st+1}^m is t = hp U^{m+1} + hm U^{m-1} + az U^m
+        // (hp = (ax - i ay) / 2, hm = (-ax - i ay) / 2, U at order st), taken
+        // conjugated and times -1/(4 pi s).  Written out as real coefficients
+        // of (Re, Im) of U^{m+1}, U^{m-1} and U^m, with the two edge columns
+        // folded in: U^{-1} = -conj(U^1) for m = 0, and no U^{P+1} for m = P;
+        // a dead slot has all coefficients 0.
+        const double hpr = 0.5 * ax, hpi = -0.5 * ay, hmr = -0.5 * ax, hmi = -0.5 * ay;
+        double qr[4] = {hpr, -hpi, hmr, -hmi}, qi[4] = {hpi, hpr, hmi, hmr};
+        if (m == 0) {
+            qr[0] = hpr - hmr; qr[1] = -hpi - hmi; qr[2] = 0.0; qr[3] = 0.0;
+            qi[0] = hpi - hmi; qi[1] = hpr + hmr; qi[2] = 0.0; qi[3] = 0.0;
+        } else if (m == P) {
+            qr[0] = qr[1] = 0.0;
+            qi[0] = qi[1] = 0.0;
+        }
+        const double sr_ = -inv4pis, si_ = inv4pis;
+        const double cr0 = sr_ * qr[0], cr1 = sr_ * qr[1], cr2 = sr_ * qr[2], cr3 = sr_ * qr[3], cr4 = sr_ * az;
+        const double ci0 = si_ * qi[0], ci1 = si_ * qi[1], ci2 = si_ * qi[2], ci3 = si_ * qi[3], ci4 = si_ * az;
+        // U^m at order st, for every lane and step without branches: the
+        // diagonal d = U^m_m is carried up (multiplied by (x + i y) / (-2 t)
+        // at every step, read at st = m), the column recurrence starts from
+        // zeros (so it is 0 for st <= m)
+        double dr = 1.0, di = 0.0, u1r = 0.0, u1i = 0.0, u2r = 0.0, u2i = 0.0;
 #pragma unroll
         for (int st = 0; st < P; ++st) {
-            cd u = {0.0, 0.0};
-            if (st == m) {
-                u = d;
-            } else if (st > m) {
-                const double w = rinv[fmm::tri(st, m)];
-                const double a2 = (double)(2 * st - 1) * z;
-                u = cd{(a2 * u1.re - r2 * u2.re) * w, (a2 * u1.im - r2 * u2.im) * w};
-            } else {
-                d = fmm::cscale(fmm::cmul(d, cd{x, y}), dfac[st + 1]);
-            }
-            if (st >= m) { u2 = u1; u1 = u; }
-            const double upre = from_next_lane(u.re), upim = from_next_lane(u.im);
-            const double dnre = from_prev_lane(u.re), dnim = from_prev_lane(u.im);
-            cd up = m + 1 < C ? cd{upre, upim} : cd{0.0, 0.0};
-            cd dn = m >= 1 ? cd{dnre, dnim} : cd{-upre, upim};
-            if (live && m <= st + 1) {
-                const cd t = fmm::cadd(fmm::cadd(fmm::cmul(cd{0.5 * ax, -0.5 * ay}, up),
-                                                 fmm::cmul(cd{-0.5 * ax, -0.5 * ay}, dn)),
-                                       fmm::cscale(u, az));
-                are[st] -= inv4pis * t.re;      // conj, times -1/(4 pi s)
-                aim[st] += inv4pis * t.im;
-            }
+            const double a2 = (double)(2 * st - 1) * z;
+            double ur = (a2 * u1r - r2 * u2r) * w[st], ui = (a2 * u1i - r2 * u2i) * w[st];
+            const bool diag = st == m;
+            ur = diag ? dr : ur;
+            ui = diag ? di : ui;
+            const double sc = -0.5 / (double)(st + 1);
+            const double ndr = (dr * x - di * y) * sc, ndi = (dr * y + di * x) * sc;
+            dr = ndr;
+            di = ndi;
+            u2r = u1r; u2i = u1i;
+            u1r = ur; u1i = ui;
+            const double upr = from_next_lane(ur), upi = from_next_lane(ui);
+            const double dnr = from_prev_lane(ur), dni = from_prev_lane(ui);
+            are[st] = fma(cr0, upr, fma(cr1, upi, fma(cr2, dnr, fma(cr3, dni, fma(cr4, ur, are[st])))));
+            aim[st] = fma(ci0, upr, fma(ci1, upi, fma(ci2, dnr, fma(ci3, dni, fma(ci4, ui, aim[st])))));
         }
     }
     // sum the node slots into lanes (0, m) and write M~_n^m, n = 1..P
