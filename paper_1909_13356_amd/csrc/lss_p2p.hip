@@ -89,16 +89,19 @@ __device__ __forceinline__ void two_sum_f(float &s, float &e, float v) {
 // S / (sqrt(pi)/2) and T / (1.5 sqrt(pi)/2) in FP64, for folded records (fold_src)
 __device__ __forceinline__ void kfun64(double x, double &S, double &T) {
     if (x < KF64_X) {
-        // Horner in t = x / X in [0, 1) (the coefficients are of one sign
-        // but for a few small ones, so the recurrences stay well
-        // conditioned; the tables were validated with this evaluation)
+        // power basis with shared powers t^k (t = x / X in [0, 1)): the
+        // coefficients are the multiplicands, which the per-pair kernels keep
+        // as scalar operands; Horner's addends are hoisted into vector
+        // registers there, costing a wave per SIMD.  The coefficients are of
+        // one sign but for a few small ones, so the sums stay well conditioned.
         const double t = x * KF64_INV_X;
-        double ps = kf64_ps[KF64_Q_DEG], pt = kf64_pt[KF64_Q_DEG], q = kf64_q[KF64_Q_DEG];
+        double ps = kf64_ps[0], pt = kf64_pt[0], q = kf64_q[0], tk = 1.0;
 #pragma unroll
-        for (int k = KF64_Q_DEG - 1; k >= 0; --k) {
-            ps = fma(ps, t, kf64_ps[k]);
-            pt = fma(pt, t, kf64_pt[k]);
-            q = fma(q, t, kf64_q[k]);
+        for (int k = 1; k <= KF64_Q_DEG; ++k) {
+            tk *= t;
+            ps = fma(kf64_ps[k], tk, ps);
+            pt = fma(kf64_pt[k], tk, pt);
+            q = fma(kf64_q[k], tk, q);
         }
         double r = __builtin_amdgcn_rcp(q);
         const double er = fma(-q, r, 1.0);      // third-order correction of 1/q
@@ -310,12 +313,13 @@ __device__ __forceinline__ void pair_ms_cut(const Src &s, double px, double py, 
     double k1, k2, et = 0.0;
     if (t < tcut && t < KF64_X) {
         const double tt = t * KF64_INV_X;
-        double ps = kf64_ps[KF64_Q_DEG], pt = kf64_pt[KF64_Q_DEG], q = kf64_q[KF64_Q_DEG];
+        double ps = kf64_ps[0], pt = kf64_pt[0], q = kf64_q[0], tk = 1.0;     // power basis (see kfun64)
 #pragma unroll
-        for (int i = KF64_Q_DEG - 1; i >= 0; --i) {
-            ps = fma(ps, tt, kf64_ps[i]);
-            pt = fma(pt, tt, kf64_pt[i]);
-            q = fma(q, tt, kf64_q[i]);
+        for (int i = 1; i <= KF64_Q_DEG; ++i) {
+            tk *= tt;
+            ps = fma(kf64_ps[i], tk, ps);
+            pt = fma(kf64_pt[i], tk, pt);
+            q = fma(kf64_q[i], tk, q);
         }
         double r = __builtin_amdgcn_rcp(q);
         const double er = fma(-q, r, 1.0);      // third-order correction of 1/q
