@@ -1166,15 +1166,17 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(4))) void 
 // node is tested against the tile's target bounding box and goes to the near
 // ring (the general loop: the far form for every pair, the rational fit for
 // node groups with a pair inside the cut) or to the far ring (the dipole-only
-// loop).  Nodes are staged 32 at a time so that both rings fit beside three
-// other workgroups' in the LDS of a SIMD.
-constexpr int kNodeGroupSplit = 2;      // node group of the split kernel (fewer registers than 4)
+// loop).  Nodes are staged 32 at a time, so that the two rings (7 KB) leave
+// room for the 16 workgroups of four waves per SIMD in a CU's LDS.
+constexpr int kNodeGroupSplit = 2;       // node group of the split kernel (fewer registers than 4)
 constexpr int kRun64 = 32;               // records per partial sum
+constexpr int kRing64 = 64;              // kRun64 - 1 left over + 32 staged
+
 // number of set bits of a wave mask below this lane
 __device__ __forceinline__ int below(uint64_t m) {
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
-constexpr int kRing64 = 64;              // kRun64 - 1 left over + 32 staged
+
 constexpr size_t kF64RingBytes = kRing64 * (sizeof(Src) + sizeof(FarD));
 
 template <bool COUNT>
