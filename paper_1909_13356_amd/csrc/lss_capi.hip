@@ -151,7 +151,12 @@ void build(Ctx &c) {
     c.src.ensure(sizeof(Src) * (size_t)c.nnodes);
     launch_prep_sources(c);
     launch_bbox(c);
-    launch_pseudonormals(c);
+    if (c.vH_gen != c.sources_gen || c.vH_curved != c.opt.curved_charts) {
+        // the vertex pseudonormals depend on the skeleton alone, not on sigma
+        launch_pseudonormals(c);
+        c.vH_gen = c.sources_gen;
+        c.vH_curved = c.opt.curved_charts;
+    }
     c.pairs.ensure(sizeof(double) * 4);
     c.tile_queue.ensure(sizeof(unsigned int) * 4);
     LSS_HIP(hipMemsetAsync(c.tile_queue.p, 0, sizeof(unsigned int) * 4, c.stream));
@@ -1121,6 +1126,7 @@ int lss_set_sources(lss_ctx *ctx, const double *verts, int64_t nverts, const int
         c.stats.n_degenerate = ndeg;
         if (!(vmin > 0.0)) fail(LSS_EORIENT, "lss_set_sources: a mesh has non-positive signed volume (inward orientation?)");
         c.have_sources = true;
+        ++c.sources_gen;
     });
 }
 

@@ -249,6 +249,9 @@ struct Ctx {
     DBuf tris6;               // quadratic skeleton: 6 indices per triangle (tris then holds the corners)
     bool quadratic = false;
     bool have_sources = false;
+    uint64_t sources_gen = 0;           // bumped by every lss_set_sources
+    uint64_t vH_gen = ~0ull;            // sources_gen the vertex pseudonormals were built for
+    int vH_curved = -1;                 // and their curved_charts setting
 
     // --- sigma
     bool have_sigma = false;

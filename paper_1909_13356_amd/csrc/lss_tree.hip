@@ -766,8 +766,10 @@ void build_tree_boxes(Ctx &c) {
         t.rmax.grow_copy(8 * nc, 8 * have, c.stream);
         cap_boxes = nc;
     };
-    t.level.release(); t.ijk.release(); t.nb.release(); t.ne.release(); t.child.release(); t.parent.release();
-    t.bmesh.release(); t.rmax.release();
+    // the box arrays keep the capacity of the previous build (they grow
+    // together, so the level array's capacity holds for all eight): a rebuild
+    // after a change of sigma copies and reallocates nothing
+    if (t.level.p) cap_boxes = std::max<int64_t>(cap_boxes, (int64_t)(t.level.bytes / sizeof(int32_t)));
     grow(cap_boxes, 0);
     t.fr.ensure(8 * std::max<int64_t>(64, nm));
     hipLaunchKernelGGL(k_level0, dim3(grid_for(nm)), dim3(kBlk), 0, c.stream, nm, c.node_off.as<int64_t>(),
