@@ -126,7 +126,7 @@ typedef struct lss_options {
     int32_t admissibility;    /* LSS_FAR_FMM: K of the multipole-to-local criterion |v|^2 >= K for
                                  boxes v sides apart (a larger K needs a lower fmm_order for the
                                  same accuracy but leaves more pairs to the near lists);
-                                 0 = default (4 MIXED, 8 FP64); otherwise in [4, 18] */
+                                 0 = default (4 MIXED, 7 FP64); otherwise in [4, 18] */
     int32_t curved_charts;    /* quadratic skeletons (LSS_TRI6): nonzero puts the chart bases on the
                                  curved patches (T(u,v) the quadratic patch, H linear in the
                                  vertex pseudonormals of the curved triangles: their corner

@@ -890,7 +890,7 @@ void autotune(Ctx &c, const double *x, int64_t n, unsigned flags, double w, cons
     try {
         if (base.far_field == LSS_FAR_FMM) {
             const bool mixed = base.precision == LSS_MIXED;
-            const int p0 = mixed ? 20 : 26, K0 = mixed ? 4 : 8;
+            const int p0 = mixed ? 20 : 26, K0 = mixed ? 4 : 7;
             // stage 1: leaves (shrink over [1, 3], capacity) and tile at the default K and p
             // (written out, so that the choice names them)
             for (double sh : {1.0, 1.25, 1.5, 2.0, 2.5, 3.0})
@@ -908,8 +908,9 @@ void autotune(Ctx &c, const double *x, int64_t n, unsigned flags, double w, cons
             // outermost: the translation operators are rebuilt per order)
             const lss_options leaves = best;
             for (int dp : {-4, -2, 0, 2})
-                for (int dK : {0, 2, 4}) {
+                for (int dK : {-1, 0, 2, 4}) {
                     if (dp == 0 && dK == 0) continue;     // timed in stage 1
+                    if (K0 + dK < 4) continue;            // below the option's range
                     lss_options o = leaves;
                     o.fmm_order = p0 + dp;
                     o.admissibility = K0 + dK;

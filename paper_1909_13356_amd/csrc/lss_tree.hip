@@ -657,7 +657,7 @@ void build_tree_boxes(Ctx &c) {
     const double cut = c.opt.cut_factor > 0 ? c.opt.cut_factor : (c.opt.precision == LSS_MIXED ? kCutMixed : kCutFP64);
     const int64_t cap = c.opt.leaf_capacity > 0 ? c.opt.leaf_capacity : 64;
     const double shrink = c.opt.leaf_shrink > 0 ? c.opt.leaf_shrink : (c.opt.precision == LSS_MIXED ? 1.5 : 2.0);
-    t.K = c.opt.admissibility > 0 ? c.opt.admissibility : (c.opt.precision == LSS_MIXED ? 4 : 8);
+    t.K = c.opt.admissibility > 0 ? c.opt.admissibility : (c.opt.precision == LSS_MIXED ? 4 : 7);
     // key layout: mesh id above `bits` Morton bits per dimension, bit 63 free
     int mb = 0;
     while ((int64_t(1) << mb) < nm) ++mb;

@@ -73,9 +73,9 @@ def m2p_prog(tmp_path_factory):
 
 
 # (order, smallest distance in box sides, bound): the orders and separations of
-# the two precisions' M2P lists (K = 4 mixed at p = 20, K = 8 FP64 at p = 26)
+# the two precisions' M2P lists (K = 4 mixed at p = 20, K = 7 FP64 at p = 26)
 # and a low order that shows the series converging
-@pytest.mark.parametrize("p,rmin,bound", [(20, 2.0, 1e-7), (26, 2.83, 1e-13), (8, 2.0, 1e-2)])
+@pytest.mark.parametrize("p,rmin,bound", [(20, 2.0, 1e-7), (26, 2.64, 1e-13), (8, 2.0, 1e-2)])
 def test_m2p_series_matches_direct_sum(m2p_prog, p, rmin, bound):
     err = float(subprocess.check_output([m2p_prog, str(p), str(rmin)]).decode())
     assert err <= bound
