@@ -7,7 +7,8 @@ C5: graded bumpy sphere, 2M triangles, 2.4e7 nodes, 5e7 near-surface targets;
     a stratified sample of 256: targets on the 1 % smallest-sigma and the 1 %
     largest-sigma triangles (the finest leaves, and the coarsest with the
     longest direct lists and most multipole-at-target boxes), the extreme
-    offsets t near -3 and +3, and uniform ones.
+    offsets t near -3 and +3, and uniform ones; and the mixed results against
+    the FP64 path's at all 5e7 targets.
 C3: graded multiscale torus, 2.3e5 triangles, 1e7 chart nodes (Newton onto
     Phi = 1/2); sampled triangles include the smallest and largest."""
 import sys
@@ -85,6 +86,31 @@ def test_config5_full_size_sampled(c5, prec):
     c.close()
     assert len(sel) >= 250
     assert ep <= TOL[prec] and eg <= TOL[prec]
+
+
+def test_config5_mixed_every_target_vs_fp64(c5):
+    """The mixed path against the FP64 path at every one of the 5e7 targets
+    (the FP64 path meets 1e-12 against the oracle on the stratified sample
+    above, far below the mixed bar, so it stands in for the exact sum):
+    max |dPhi| / max |Phi| and max |d grad| / max |grad| within 1e-6."""
+    import torch
+    cfg = c5[0]
+    say("case: C5 full size, mixed against FP64 at every target")
+    dev = torch.device("cuda")
+    x = torch.as_tensor(cfg["targets"], device=dev)
+    c = device_ctx(torch, cfg, lss.FP64)
+    pr, gr = c.eval(x)
+    c.set_options(precision=lss.MIXED, far_field=lss.FAR_FMM)
+    pm, gm = c.eval(x)
+    torch.cuda.synchronize()
+    dphi = (pm - pr).abs()
+    dg = (gm - gr).norm(dim=1)
+    ep = float(dphi.max() / pr.abs().max())
+    eg = float(dg.max() / gr.norm(dim=1).max())
+    n_big = int((dphi > 1e-7 * pr.abs().max()).sum())
+    say("  %d targets: e_phi %.3e e_grad %.3e; %d above 1e-7" % (x.shape[0], ep, eg, n_big))
+    c.close()
+    assert ep <= TOL[lss.MIXED] and eg <= TOL[lss.MIXED]
 
 
 @pytest.mark.parametrize("prec", [lss.FP64, lss.MIXED])
