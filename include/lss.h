@@ -401,9 +401,9 @@ int lss_chart_interp(lss_ctx *ctx, const double *chart_uv, int32_t np, const dou
  * the current source set, sigma and precision by timing candidates on the
  * caller's targets: cost = (build time) + eval_weight * (time to evaluate x),
  * each from HIP events on the context stream.  A candidate is accepted only
- * if, on a subset of up to 512 of the targets, its Phi and grad Phi agree
- * with the exact discrete sum (the direct FP64 path) to a quarter of the
- * precision's bar (1e-12 FP64, 1e-6 MIXED; maximum error relative to the
+ * if, on up to 16384 of the targets (spread evenly over x), its Phi and
+ * grad Phi agree with the exact discrete sum (the direct FP64 path) to a
+ * quarter of the precision's bar (1e-12 FP64, 1e-6 MIXED; maximum error relative to the
  * largest value).  The search first times leaf shrink x capacity (x tile)
  * at the default K and p, then K and p around their defaults at the best
  * leaves.  Pass a spatially compact subset of the real targets and

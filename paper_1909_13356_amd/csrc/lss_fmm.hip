@@ -489,6 +489,71 @@ void launch_add(Ctx &c, double *y, const double *x, int64_t n) {
     LSS_CHECK_LAUNCH("k_add");
 }
 
+// M2L of the small displacement classes, target-major.  The pairs of all
+// small classes are sorted by (target box, class) (key = T << 12 | class);
+// the workgroup that meets the first pair of a target box applies every pair
+// of that box in key order, each a matrix-vector product with the class
+// operator (k-major, leading nkv coefficients in and out), and adds the sum,
+// times 1 / side of the box, once.  A box is written by one workgroup only.
+constexpr int kSmallClassPairs = 512;        // classes with at most this many pairs
+constexpr int kSmallRows = 8;                // rows per thread: ncp <= 2048
+constexpr int kSmallMaxCoeffs = 512;         // target-major only for ncp up to this
+__global__ __launch_bounds__(256) void k_m2l_small(int64_t npairs, const uint64_t *__restrict__ key,
+                                                   const int32_t *__restrict__ src, const int32_t *__restrict__ cls_slot,
+                                                   const int32_t *__restrict__ cls_nkv, const double *__restrict__ ops,
+                                                   const double *__restrict__ M, double *L, int ncp, Geo g,
+                                                   const int32_t *__restrict__ lev) {
+    extern __shared__ double xs[];           // the source box's leading coefficients
+    const int tid = threadIdx.x;
+    for (int64_t i = blockIdx.x; i < npairs; i += gridDim.x) {
+        const uint32_t T = (uint32_t)(key[i] >> 12);
+        if (i > 0 && (uint32_t)(key[i - 1] >> 12) == T) continue;      // uniform: not the box's first pair
+        double acc[kSmallRows];
+#pragma unroll
+        for (int q = 0; q < kSmallRows; ++q) acc[q] = 0.0;
+        for (int64_t j = i; j < npairs && (uint32_t)(key[j] >> 12) == T; ++j) {
+            const int cls = (int)(key[j] & 0xfffu);
+            const int nkv = cls_nkv[cls];
+            const double *__restrict__ op = ops + (int64_t)cls_slot[cls] * ncp * ncp;
+            const double *__restrict__ x = M + (int64_t)src[j] * ncp;
+            __syncthreads();                 // the previous pair is done with xs
+            for (int k = tid; k < nkv; k += 256) xs[k] = x[k];
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < kSmallRows; ++q) {
+                const int r = tid + 256 * q;
+                if (r < nkv) {
+                    double sum = 0.0;
+                    for (int k = 0; k < nkv; ++k) sum = fma(op[(int64_t)k * ncp + r], xs[k], sum);
+                    acc[q] += sum;
+                }
+            }
+        }
+        const double sc = 1.0 / box_side(g.root, g.bmesh, (int32_t)T, lev[T]);
+        double *y = L + (int64_t)T * ncp;
+#pragma unroll
+        for (int q = 0; q < kSmallRows; ++q) {
+            const int r = tid + 256 * q;
+            if (r < ncp) y[r] += sc * acc[q];
+        }
+    }
+}
+
+// keys (T << 12 | class) and sources of the pairs of the small classes:
+// block b copies class b's segment [beg[b], beg[b] + n[b]) of the class-sorted
+// M2L list to out + off[b]
+__global__ void k_small_pairs(const int64_t *__restrict__ beg, const int64_t *__restrict__ off,
+                              const int32_t *__restrict__ cls, const uint64_t *__restrict__ mkey,
+                              const int32_t *__restrict__ mval, uint64_t *okey, int32_t *oval) {
+    const int b = blockIdx.x;
+    const int64_t b0 = beg[b], o0 = off[b], n = off[b + 1] - off[b];
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+        const uint32_t T = (uint32_t)(mkey[b0 + j] & 0xffffffffu);
+        okey[o0 + j] = ((uint64_t)T << 12) | (uint64_t)cls[b];
+        oval[o0 + j] = mval[b0 + j];
+    }
+}
+
 // class index -> offset vector
 void class_vec(int cls, double v[3]) {
     const int W = 2 * kR + 1;
@@ -671,6 +736,18 @@ void build_fmm(Ctx &c) {
         const int nkv = std::min(ncp, (int)ceil_div((int64_t)(pv + 1) * (pv + 1), kKB) * kKB);
         jobs.push_back({cls, nkv, t.class_beg[cls], t.class_end[cls] - t.class_beg[cls]});
     }
+    // classes with few pairs would be one short launch each (graded meshes use
+    // thousands of classes): they go to one target-major launch instead.  That
+    // launch reads a class operator once per pair rather than once per tile of
+    // pairs, so it pays only while the operators are small (measured: faster
+    // at order 20, 441 coefficients; slower at order 26, 729)
+    std::vector<M2LJob> small;
+    {
+        std::vector<M2LJob> big;
+        const bool use_small = ncp <= kSmallMaxCoeffs;
+        for (const M2LJob &j : jobs) (use_small && j.n <= kSmallClassPairs ? small : big).push_back(j);
+        jobs.swap(big);
+    }
     std::vector<char> on_aux(jobs.size(), 0);
     {   // largest work first to the less loaded set (ties: the class index)
         std::vector<size_t> ord(jobs.size());
@@ -700,6 +777,53 @@ void build_fmm(Ctx &c) {
         for (size_t i = 0; i < jobs.size(); ++i)
             if (on_aux[i]) m2l(jobs[i], t.L2.as<double>());
         LSS_HIP(hipEventRecord(c.aux_ev[5], c.aux_stream));
+    }
+    if (!small.empty()) {
+        // host arrays kept in the tree until the next build: the copies below
+        // are asynchronous
+        std::vector<int64_t> &hb = t.sm_hb, &ho = t.sm_ho;
+        std::vector<int32_t> &hc = t.sm_hc, &hslot = t.sm_hslot, &hnkv = t.sm_hnkv;
+        hb.assign(small.size(), 0);
+        ho.assign(small.size() + 1, 0);
+        hc.assign(small.size(), 0);
+        hslot.assign(kNClass, 0);
+        hnkv.assign(kNClass, 0);
+        for (size_t i = 0; i < small.size(); ++i) {
+            hb[i] = small[i].b0;
+            hc[i] = small[i].cls;
+            ho[i + 1] = ho[i] + small[i].n;
+            hslot[small[i].cls] = t.op_class_slot[small[i].cls];
+            hnkv[small[i].cls] = small[i].nkv;
+        }
+        const int64_t nsp = ho.back();
+        const size_t ns = small.size();
+        t.sm_meta.ensure(sizeof(int64_t) * (2 * ns + 1) + sizeof(int32_t) * (ns + 2 * kNClass));
+        char *mp = t.sm_meta.as<char>();
+        int64_t *db = reinterpret_cast<int64_t *>(mp), *dofs = db + ns;
+        int32_t *dc = reinterpret_cast<int32_t *>(dofs + ns + 1), *dslot = dc + ns, *dnkv = dslot + kNClass;
+        LSS_HIP(hipMemcpyAsync(db, hb.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice, c.stream));
+        LSS_HIP(hipMemcpyAsync(dofs, ho.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, c.stream));
+        LSS_HIP(hipMemcpyAsync(dc, hc.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, c.stream));
+        LSS_HIP(hipMemcpyAsync(dslot, hslot.data(), sizeof(int32_t) * kNClass, hipMemcpyHostToDevice, c.stream));
+        LSS_HIP(hipMemcpyAsync(dnkv, hnkv.data(), sizeof(int32_t) * kNClass, hipMemcpyHostToDevice, c.stream));
+        t.sm_key.ensure(8 * nsp); t.sm_key2.ensure(8 * nsp); t.sm_val.ensure(4 * nsp); t.sm_val2.ensure(4 * nsp);
+        hipLaunchKernelGGL(k_small_pairs, dim3((unsigned)ns), dim3(kBlk), 0, c.stream, db, dofs, dc,
+                           t.m2l_key2.as<uint64_t>(), t.m2l_val2.as<int32_t>(), t.sm_key.as<uint64_t>(),
+                           t.sm_val.as<int32_t>());
+        LSS_CHECK_LAUNCH("k_small_pairs");
+        int tb = 1;
+        while ((int64_t(1) << tb) < t.nboxes) ++tb;
+        // own sort workspace: the near lists may be sorted on the other stream meanwhile
+        const size_t stb = sort_pairs_u64_tmp_bytes(nsp);
+        t.sm_tmp.ensure(stb);
+        sort_pairs_u64(t.sm_tmp.p, stb, t.sm_key.as<uint64_t>(), t.sm_key2.as<uint64_t>(), t.sm_val.as<int32_t>(),
+                       t.sm_val2.as<int32_t>(), nsp, 0, 12 + tb, c.stream);
+        const int64_t gs = std::min<int64_t>(nsp, 65535);
+        hipLaunchKernelGGL(k_m2l_small, dim3((unsigned)gs), dim3(256), sizeof(double) * (size_t)ncp, c.stream, nsp,
+                           t.sm_key2.as<uint64_t>(), t.sm_val2.as<int32_t>(), dslot, dnkv, t.opM2L.as<double>(),
+                           t.M.as<double>(), t.L.as<double>(), ncp, Geo{t.root.as<double>(), t.bmesh.as<int32_t>()},
+                           t.level.as<int32_t>());
+        LSS_CHECK_LAUNCH("k_m2l_small");
     }
     for (size_t i = 0; i < jobs.size(); ++i)
         if (!on_aux[i]) m2l(jobs[i], t.L.as<double>());

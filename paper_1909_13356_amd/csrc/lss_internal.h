@@ -219,6 +219,9 @@ struct Tree {
     // expansions and operators
     int p = 0, ncp = 0, K = 4;
     DBuf M, L, L2;                            // nboxes * ncp doubles (L2: the M2L classes of the second stream)
+    DBuf sm_meta, sm_key, sm_key2, sm_val, sm_val2, sm_tmp;   // M2L pairs of the small classes (target-major launch)
+    std::vector<int64_t> sm_hb, sm_ho;                       // and their host-side tables
+    std::vector<int32_t> sm_hc, sm_hslot, sm_hnkv;
     DBuf opM2M, opL2L, opM2L;                 // 8, 8 and nclass_used operators (ncp*ncp, k-major)
     std::vector<int32_t> op_class_slot;       // class -> slot in opM2L (-1 if not built)
     int ops_p = -1, ops_R = -1;
