@@ -496,8 +496,9 @@ void launch_add(Ctx &c, double *y, const double *x, int64_t n) {
 // operator (k-major, leading nkv coefficients in and out), and adds the sum,
 // times 1 / side of the box, once.  A box is written by one workgroup only.
 constexpr int kSmallClassPairs = 512;        // classes with at most this many pairs
-constexpr int kSmallRows = 8;                // rows per thread: ncp <= 2048
 constexpr int kSmallMaxCoeffs = 512;         // target-major only for ncp up to this
+constexpr int kSmallRows = 2;                // rows per thread (256 threads)
+static_assert(256 * kSmallRows >= kSmallMaxCoeffs, "k_m2l_small: every coefficient needs a thread");
 __global__ __launch_bounds__(256) void k_m2l_small(int64_t npairs, const uint64_t *__restrict__ key,
                                                    const int32_t *__restrict__ src, const int32_t *__restrict__ cls_slot,
                                                    const int32_t *__restrict__ cls_nkv, const double *__restrict__ ops,
