@@ -221,6 +221,11 @@ __device__ __forceinline__ FarD pad_fard() {
     return f;
 }
 
+// number of set bits of a wave mask below this lane
+__device__ __forceinline__ int below(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // K consecutive FP64 far records against one target: the Laplace dipole with
 // the width moved into a'' and the gradient summed in two parts, as
 // nodes32_far; 1/sqrt refined to FP64 (rsq64)
@@ -244,6 +249,23 @@ __device__ __forceinline__ void nodes64_far(const FarD *sh, double x, double y, 
         hy = fma(s.ay, S, hy);
         hz = fma(s.az, S, hz);
     }
+}
+
+// One FP64 far record against one target, the gradient accumulated whole
+// (four accumulators instead of the seven of nodes64_far):
+//   Phi -= (a''.d) S,  grad += 3 (a''.d) S |d|^-2 d - a'' S,  S = |d|^-3
+__device__ __forceinline__ void pair_far64(const FarD &s, double x, double y, double z, double &p, double &gx,
+                                           double &gy, double &gz) {
+    const double dx = x - s.yx, dy = y - s.yy, dz = z - s.yz;
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    const double r = rsq64(r2);
+    const double rr = r * r, S = rr * r;
+    const double ad = fma(s.ax, dx, fma(s.ay, dy, s.az * dz));
+    p = fma(-ad, S, p);
+    const double h = 3.0 * ad * S * rr;
+    gx = fma(h, dx, fma(-s.ax, S, gx));
+    gy = fma(h, dy, fma(-s.ay, S, gy));
+    gz = fma(h, dz, fma(-s.az, S, gz));
 }
 
 constexpr int kNodeGroup = 4;
@@ -377,6 +399,34 @@ __device__ __forceinline__ void pair_hess_cut(const Src &s, double px, double py
     A.hxy -= k2 * (s.ax * dy + s.ay * dx) + ex * dy;
     A.hxz -= k2 * (s.ax * dz + s.az * dx) + ex * dz;
     A.hyz -= k2 * (s.ay * dz + s.az * dy) + ey * dz;
+}
+
+// One (target, node) pair with the node beyond the cut of every target of the
+// tile: pair_hess_cut's far form with the width folded into the record,
+// a'' = (sqrt(pi)/2) a' s2^(-3/2) (FarD), S = |d|^-3, q = 3 S |d|^-2:
+//   Phi -= (a''.d) S,  grad -= a'' S - q (a''.d) d,
+//   Hess += q (a'' d^T + d a''^T) + q (a''.d) I - 5 q (a''.d) |d|^-2 d d^T
+__device__ __forceinline__ void pair_hess_far(const FarD &s, double px, double py, double pz, HessAcc &A) {
+    const double dx = px - s.yx, dy = py - s.yy, dz = pz - s.yz;
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    const double ir = rsq64(r2);
+    const double ir2 = ir * ir, S = ir2 * ir;
+    const double ad = fma(s.ax, dx, fma(s.ay, dy, s.az * dz));
+    A.f = fma(-ad, S, A.f);
+    const double q = 3.0 * S * ir2;
+    const double h = q * ad;
+    A.gx = fma(h, dx, fma(-s.ax, S, A.gx));
+    A.gy = fma(h, dy, fma(-s.ay, S, A.gy));
+    A.gz = fma(h, dz, fma(-s.az, S, A.gz));
+    const double e = 5.0 * h * ir2;
+    const double ux = q * s.ax, uy = q * s.ay, uz = q * s.az;
+    const double vx = e * dx, vy = e * dy, vz = e * dz;
+    A.hxx = fma(fma(2.0, ux, -vx), dx, A.hxx + h);
+    A.hyy = fma(fma(2.0, uy, -vy), dy, A.hyy + h);
+    A.hzz = fma(fma(2.0, uz, -vz), dz, A.hzz + h);
+    A.hxy = fma(ux - vx, dy, fma(uy, dx, A.hxy));
+    A.hxz = fma(ux - vx, dz, fma(uz, dx, A.hxz));
+    A.hyz = fma(uy - vy, dz, fma(uz, dy, A.hyz));
 }
 
 // FP32 record of a node that lies beyond the cut of every target of a tile:
@@ -864,15 +914,23 @@ __device__ __forceinline__ void fmm_m2p_list_hess(const FmmEvalArgs &a, int32_t 
 }
 
 // one workgroup of TILE lanes per tile (the tiles of the evaluation, at most
-// TILE targets of one leaf), tiles taken in a grid-stride loop
+// TILE targets of one leaf), tiles taken in a grid-stride loop.  With 64-lane
+// tiles (one wave) every staged node is tested against the tile's target
+// bounding box: nodes beyond the cut of every target of the tile take the
+// folded far form (pair_hess_far), the others pair_hess_cut, which still
+// chooses per pair.
 template <int TILE>
 __global__ __launch_bounds__(TILE) void k_hess_fmm(FmmEvalArgs a, double *hess) {
+    constexpr bool kSplit = TILE == 64;
     __shared__ Src sh[TILE];
+    __shared__ FarD shf[kSplit ? TILE : 1];
+    __shared__ double tbox[6];          // the tile's target bounding box
     __shared__ RangeBatch<TILE> rb;
     extern __shared__ double Ls[];      // local expansion of the tile's leaf (ncp doubles)
     const int ntiles = *a.ntiles_dev;
     const int64_t n = a.n_dev ? (int64_t)*a.n_dev : a.n_max;
     const int lane = threadIdx.x;
+    const double far_t = a.tcut * (1.0 + 1e-6);         // margin over the rounding of the box gap
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t s0 = a.tile_start[tile];
         const int32_t B = a.sleaf[s0];
@@ -883,6 +941,20 @@ __global__ __launch_bounds__(TILE) void k_hess_fmm(FmmEvalArgs a, double *hess) 
         const int64_t ti = a.sidx ? (int64_t)a.sidx[valid ? sp_ : s0] : (valid ? sp_ : s0);
         const double x = a.tx[ti], y = a.ty[ti], z = a.tz[ti];
         const int e0 = a.p2p_beg[B], e1 = a.p2p_end[B];
+        if (kSplit) {
+            double blo[3] = {x, y, z}, bhi[3] = {x, y, z};      // lanes past the tile end hold its first target
+            for (int off = 32; off > 0; off >>= 1)
+                for (int c = 0; c < 3; ++c) {
+                    blo[c] = fmin(blo[c], __shfl_xor(blo[c], off));
+                    bhi[c] = fmax(bhi[c], __shfl_xor(bhi[c], off));
+                }
+            __syncthreads();                // the previous tile is done with tbox
+            if (lane == 0)
+                for (int c = 0; c < 3; ++c) {
+                    tbox[c] = blo[c];
+                    tbox[3 + c] = bhi[c];
+                }
+        }
         HessAcc A;
         for (int eb = e0; eb < e1; eb += TILE) {
             const int nr = e1 - eb < TILE ? e1 - eb : TILE;
@@ -891,9 +963,39 @@ __global__ __launch_bounds__(TILE) void k_hess_fmm(FmmEvalArgs a, double *hess) 
             for (int64_t c0 = 0; c0 < total; c0 += TILE) {
                 const int cnt = (int)(total - c0 < TILE ? total - c0 : TILE);
                 __syncthreads();
-                if (lane < cnt) sh[lane] = a.src[packed_node<TILE>(rb, nr, c0 + lane)];
-                __syncthreads();
-                for (int j = 0; j < cnt; ++j) pair_hess_cut(sh[j], x, y, z, a.tcut, A);
+                if (kSplit) {
+                    Src sr;
+                    bool isfar = false;
+                    if (lane < cnt) {
+                        sr = a.src[packed_node<TILE>(rb, nr, c0 + lane)];
+                        const double gx_ = fmax(fmax(tbox[0] - sr.yx, sr.yx - tbox[3]), 0.0);
+                        const double gy_ = fmax(fmax(tbox[1] - sr.yy, sr.yy - tbox[4]), 0.0);
+                        const double gz_ = fmax(fmax(tbox[2] - sr.yz, sr.yz - tbox[5]), 0.0);
+                        isfar = (gx_ * gx_ + gy_ * gy_ + gz_ * gz_) * sr.s2 >= far_t;
+                    }
+                    const uint64_t fm = __ballot(isfar), nm = __ballot(lane < cnt && !isfar);
+                    if (lane < cnt && !isfar) {
+                        sh[below(nm)] = sr;
+                    } else if (isfar) {
+                        const double fa = kFoldA / (sr.s2 * sqrt(sr.s2));     // a''
+                        FarD f;
+                        f.yx = sr.yx;
+                        f.yy = sr.yy;
+                        f.yz = sr.yz;
+                        f.ax = fa * sr.ax;
+                        f.ay = fa * sr.ay;
+                        f.az = fa * sr.az;
+                        shf[below(fm)] = f;
+                    }
+                    __syncthreads();
+                    const int nn = __popcll(nm), nf = __popcll(fm);
+                    for (int j = 0; j < nn; ++j) pair_hess_cut(sh[j], x, y, z, a.tcut, A);
+                    for (int j = 0; j < nf; ++j) pair_hess_far(shf[j], x, y, z, A);
+                } else {
+                    if (lane < cnt) sh[lane] = a.src[packed_node<TILE>(rb, nr, c0 + lane)];
+                    __syncthreads();
+                    for (int j = 0; j < cnt; ++j) pair_hess_cut(sh[j], x, y, z, a.tcut, A);
+                }
             }
         }
         double ph = 0.0, g[3] = {0.0, 0.0, 0.0}, H[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -985,13 +1087,21 @@ __device__ __forceinline__ void ms_finish(double sx, const MsAcc &A, const doubl
 }
 
 template <int TILE>
-__global__ __launch_bounds__(TILE) void k_multiscale_fmm(FmmEvalArgs a, MsArgs ms) {
+__global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3))) void k_multiscale_fmm(FmmEvalArgs a, MsArgs ms) {
+    // with 64-lane tiles (one wave) nodes beyond the cut of every target of
+    // the tile (the gap to the tile's bounding box against the tile's largest
+    // sigma(x)) take the Laplace double layer (nodes64_far), the others
+    // pair_ms_cut, which still chooses per pair
+    constexpr bool kSplit = TILE == 64;
     __shared__ Src sh[TILE];
+    __shared__ FarD shf[kSplit ? TILE : 1];
+    __shared__ double tbox[7];          // the tile's target bounding box and smallest s2(x)
     __shared__ RangeBatch<TILE> rb;
     extern __shared__ double Ls[];
     const int ntiles = *a.ntiles_dev;
     const int64_t n = a.n_dev ? (int64_t)*a.n_dev : a.n_max;
     const int lane = threadIdx.x;
+    const double far_t = ms.tcut * (1.0 + 1e-6);        // margin over the rounding of the box gap
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t s0 = a.tile_start[tile];
         const int32_t B = a.sleaf[s0];
@@ -1003,7 +1113,26 @@ __global__ __launch_bounds__(TILE) void k_multiscale_fmm(FmmEvalArgs a, MsArgs m
         const double x = a.tx[ti], y = a.ty[ti], z = a.tz[ti];
         const double sx = ms.sig[ti], s2x = 0.5 / (sx * sx);
         const int e0 = a.p2p_beg[B], e1 = a.p2p_end[B];
+        if (kSplit) {
+            double blo[4] = {x, y, z, s2x}, bhi[3] = {x, y, z};     // lanes past the tile end hold its first target
+            for (int off = 32; off > 0; off >>= 1) {
+                for (int c = 0; c < 3; ++c) {
+                    blo[c] = fmin(blo[c], __shfl_xor(blo[c], off));
+                    bhi[c] = fmax(bhi[c], __shfl_xor(bhi[c], off));
+                }
+                blo[3] = fmin(blo[3], __shfl_xor(blo[3], off));
+            }
+            __syncthreads();                // the previous tile is done with tbox
+            if (lane == 0) {
+                for (int c = 0; c < 3; ++c) {
+                    tbox[c] = blo[c];
+                    tbox[3 + c] = bhi[c];
+                }
+                tbox[6] = blo[3];
+            }
+        }
         MsAcc A;
+        double pf = 0.0, gfx = 0.0, gfy = 0.0, gfz = 0.0;  // the far nodes' double layer
         for (int eb = e0; eb < e1; eb += TILE) {
             const int nr = e1 - eb < TILE ? e1 - eb : TILE;
             __syncthreads();
@@ -1011,16 +1140,51 @@ __global__ __launch_bounds__(TILE) void k_multiscale_fmm(FmmEvalArgs a, MsArgs m
             for (int64_t c0 = 0; c0 < total; c0 += TILE) {
                 const int cnt = (int)(total - c0 < TILE ? total - c0 : TILE);
                 __syncthreads();
-                if (lane < cnt) {               // a' s2^(-3/2): the width moves to the target (pair_ms_cut)
-                    Src r = a.src[packed_node<TILE>(rb, nr, c0 + lane)];
-                    const double f = 1.0 / (r.s2 * sqrt(r.s2));
-                    r.ax *= f;
-                    r.ay *= f;
-                    r.az *= f;
-                    sh[lane] = r;
+                if (kSplit) {
+                    Src r;
+                    bool isfar = false;
+                    if (lane < cnt) {
+                        r = a.src[packed_node<TILE>(rb, nr, c0 + lane)];
+                        const double gx_ = fmax(fmax(tbox[0] - r.yx, r.yx - tbox[3]), 0.0);
+                        const double gy_ = fmax(fmax(tbox[1] - r.yy, r.yy - tbox[4]), 0.0);
+                        const double gz_ = fmax(fmax(tbox[2] - r.yz, r.yz - tbox[5]), 0.0);
+                        isfar = (gx_ * gx_ + gy_ * gy_ + gz_ * gz_) * tbox[6] >= far_t;
+                    }
+                    const uint64_t fm = __ballot(isfar), nm = __ballot(lane < cnt && !isfar);
+                    if (lane < cnt) {           // a' s2^(-3/2): the width moves to the target
+                        const double f = 1.0 / (r.s2 * sqrt(r.s2));
+                        if (!isfar) {
+                            r.ax *= f;
+                            r.ay *= f;
+                            r.az *= f;
+                            sh[below(nm)] = r;
+                        } else {                // a'' = (sqrt(pi)/2) a' s2^(-3/2)
+                            FarD q;
+                            q.yx = r.yx;
+                            q.yy = r.yy;
+                            q.yz = r.yz;
+                            q.ax = kFoldA * f * r.ax;
+                            q.ay = kFoldA * f * r.ay;
+                            q.az = kFoldA * f * r.az;
+                            shf[below(fm)] = q;
+                        }
+                    }
+                    __syncthreads();
+                    const int nn = __popcll(nm), nf = __popcll(fm);
+                    for (int j = 0; j < nn; ++j) pair_ms_cut(sh[j], x, y, z, s2x, ms.tcut, A);
+                    for (int j = 0; j < nf; ++j) pair_far64(shf[j], x, y, z, pf, gfx, gfy, gfz);
+                } else {
+                    if (lane < cnt) {           // a' s2^(-3/2): the width moves to the target (pair_ms_cut)
+                        Src r = a.src[packed_node<TILE>(rb, nr, c0 + lane)];
+                        const double f = 1.0 / (r.s2 * sqrt(r.s2));
+                        r.ax *= f;
+                        r.ay *= f;
+                        r.az *= f;
+                        sh[lane] = r;
+                    }
+                    __syncthreads();
+                    for (int j = 0; j < cnt; ++j) pair_ms_cut(sh[j], x, y, z, s2x, ms.tcut, A);
                 }
-                __syncthreads();
-                for (int j = 0; j < cnt; ++j) pair_ms_cut(sh[j], x, y, z, s2x, ms.tcut, A);
             }
         }
         {
@@ -1044,6 +1208,10 @@ __global__ __launch_bounds__(TILE) void k_multiscale_fmm(FmmEvalArgs a, MsArgs m
         __syncthreads();
         if (valid) {
             ms_finish(sx, A, ms.gsig + 3 * ti, ph, g);
+            ph += pf;                       // the double layer of the far nodes
+            g[0] += gfx;
+            g[1] += gfy;
+            g[2] += gfz;
             const int64_t o = a.out_idx ? (int64_t)a.out_idx[ti] : ti;
             a.phi[o] = ph;
             if (a.grad) {
@@ -1171,11 +1339,6 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(4))) void 
 constexpr int kNodeGroupSplit = 2;       // node group of the split kernel (fewer registers than 4)
 constexpr int kRun64 = 32;               // records per partial sum
 constexpr int kRing64 = 64;              // kRun64 - 1 left over + 32 staged
-
-// number of set bits of a wave mask below this lane
-__device__ __forceinline__ int below(uint64_t m) {
-    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
 
 constexpr size_t kF64RingBytes = kRing64 * (sizeof(Src) + sizeof(FarD));
 
