@@ -19,10 +19,13 @@ mpmath.  Beyond X the kernel is the Laplace dipole to the tail bound of the
 cut (section 4.4, the 8 sigma bounds), so the kernels switch to
 S = (sqrt(pi)/2) x^(-3/2), T = 1.5 S / x there.
 
-Two fits are produced:
+Three fits are produced:
   * FP64: X = 32 (cut at 8 sigma), degree (13, 13) (fit error 7e-15; degree
     12 reaches only 1.7e-13, degree 15 7e-18);
-  * FP32: X = 20 (cut at sqrt(40) sigma = 6.32 sigma), degree (7, 7).
+  * FP32: X = 20 (cut at sqrt(40) sigma = 6.32 sigma), degree (7, 7);
+  * FP64 for the Hessian: S, T and U(x) = gamma(7/2, x) / x^(7/2) (U(0) = 2/7)
+    over one denominator, X = 32, degree (14, 14), not folded (fit error
+    9e-16; degree 13 reaches 3.1e-14).
 
 The pair kernels stage node records with the far-form constants folded in
 (dipole vector times sqrt(pi)/2, 2 s2 times 1.5), so they need S / (sqrt(pi)/2)
@@ -38,6 +41,7 @@ import mpmath as mp
 import numpy as np
 
 mp.mp.dps = 50
+HESS_X, HESS_DEG = 32.0, 14
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
@@ -49,6 +53,11 @@ def S(x):
 def T(x):
     x = mp.mpf(x)
     return mp.mpf(2) / 5 if x == 0 else mp.gammainc(mp.mpf(2.5), 0, x) / x ** mp.mpf(2.5)
+
+
+def U(x):
+    x = mp.mpf(x)
+    return mp.mpf(2) / 7 if x == 0 else mp.gammainc(mp.mpf(3.5), 0, x) / x ** mp.mpf(3.5)
 
 
 def fit_common(fs, X, n, m, K=300, iters=40):
@@ -91,13 +100,13 @@ def fit_common(fs, X, n, m, K=300, iters=40):
 FOLD = (mp.sqrt(mp.pi) / 2, mp.mpf(3) / 2 * mp.sqrt(mp.pi) / 2)   # S and T divisors
 
 
-def fold(P):
-    return [[c / FOLD[fi] for c in p] for fi, p in enumerate(P)]
+def fold(P, div=FOLD):
+    return [[c / div[fi] for c in p] for fi, p in enumerate(P)]
 
 
-def check(P, q, X, dt):
+def check(P, q, X, dt, fs=(S, T), div=FOLD):
     """Max relative error of the rounded (folded) coefficients evaluated in
-    dtype dt against S / FOLD[0] and T / FOLD[1] (FMA-free Horner, a
+    dtype dt against f / div for each fitted function f (FMA-free Horner, a
     pessimistic stand-in for the device evaluation)."""
     Pc = [np.array([float(c) for c in p], dtype=dt) for p in P]
     qc = np.array([float(c) for c in q], dtype=dt)
@@ -111,20 +120,21 @@ def check(P, q, X, dt):
         return r
     r = dt(1) / horner(qc)
     out = []
-    for fi, f in enumerate((S, T)):
+    for fi, f in enumerate(fs):
         v = horner(Pc[fi]) * r
-        out.append(max(abs(float(v[i]) / float(f(xs[i]) / FOLD[fi]) - 1) for i in range(len(xs))))
+        out.append(max(abs(float(v[i]) / float(f(xs[i]) / div[fi]) - 1) for i in range(len(xs))))
     return out
 
 
-def emit(f, name, ctype, P, q, X, fit_err, eval_err):
+def emit(f, name, ctype, P, q, X, fit_err, eval_err, labels=("PS", "PT")):
     lit = (lambda v: "%.17e" % v) if ctype == "double" else (lambda v: "%.9ef" % v)
     f.write("// %s: x in [0, %g], degree (%d, %d); fit max rel err %.2e; "
-            "rounded-coefficient Horner max rel err S %.2e, T %.2e\n"
-            % (name, X, len(P[0]) - 1, len(q) - 1, fit_err, eval_err[0], eval_err[1]))
+            "rounded-coefficient Horner max rel err %s\n"
+            % (name, X, len(P[0]) - 1, len(q) - 1, fit_err,
+               ", ".join("%s %.2e" % (lb[1], e) for lb, e in zip(labels, eval_err))))
     f.write("#define %s_X %s\n" % (name.upper(), lit(X)))
     f.write("#define %s_INV_X %s\n" % (name.upper(), lit(1.0 / X)))
-    for label, coef in (("PS", P[0]), ("PT", P[1]), ("Q", q)):
+    for label, coef in list(zip(labels, P)) + [("Q", q)]:
         f.write("#define %s_%s_DEG %d\n" % (name.upper(), label, len(coef) - 1))
         f.write("__device__ __constant__ static const %s %s_%s[%d] = {\n" % (ctype, name, label.lower(), len(coef)))
         f.write(",\n".join("    " + lit(float(c)) for c in coef) + "};\n")
@@ -147,6 +157,14 @@ def main():
             ee = check(P, q, X, dt)
             print(name, "fit", mp.nstr(fe, 3), "eval", ee, file=sys.stderr)
             emit(f, name, ctype, P, q, X, float(fe), ee)
+        # the Hessian's three radial functions S, T, U (not folded): k1 = S,
+        # k2 = -2 s2 T, k3 = 4 s2^2 U with U(x) = gamma(7/2,x)/x^(7/2)
+        f.write("// kf64h: S, T and U(x) = gamma(7/2,x)/x^(7/2) over one denominator (not folded),\n"
+                "// for the Hessian pairs inside the cut.\n")
+        fe, P, q = fit_common([S, T, U], mp.mpf(HESS_X), HESS_DEG, HESS_DEG)
+        ee = check(P, q, HESS_X, np.float64, fs=(S, T, U), div=(1, 1, 1))
+        print("kf64h", "fit", mp.nstr(fe, 3), "eval", ee, file=sys.stderr)
+        emit(f, "kf64h", "double", P, q, HESS_X, float(fe), ee, labels=("PS", "PT", "PU"))
     os.replace(out + ".tmp", out)
 
 

@@ -367,16 +367,38 @@ __device__ __forceinline__ void pair_ms_cut(const Src &s, double px, double py, 
     A.e += ad * et;
 }
 
-// pair_hess for the octree's near lists: beyond the cut (x >= tcut) the
-// radial functions are those of the Laplace double layer, as in the far
-// field: k1 = (sqrt(pi)/2) x^-3/2, k2 = -(3 sqrt(pi)/2) s2 x^-5/2,
+// pair_hess for the octree's near lists: inside the cut the three radial
+// functions come from one rational fit (kf64h: fit error near FP64 rounding),
+// beyond the cut (x >= tcut) they are those of the Laplace double layer, as in
+// the far field: k1 = (sqrt(pi)/2) x^-3/2, k2 = -(3 sqrt(pi)/2) s2 x^-5/2,
 // k3 = (15 sqrt(pi)/2) s2^2 x^-7/2.
+static_assert(KF64H_PS_DEG == KF64H_Q_DEG && KF64H_PT_DEG == KF64H_Q_DEG && KF64H_PU_DEG == KF64H_Q_DEG,
+              "pair_hess_cut evaluates the Hessian fit's numerators in one loop");
 __device__ __forceinline__ void pair_hess_cut(const Src &s, double px, double py, double pz, double tcut,
                                               HessAcc &A) {
     const double dx = px - s.yx, dy = py - s.yy, dz = pz - s.yz;
     const double t = (dx * dx + dy * dy + dz * dz) * s.s2;
     double k1, k2, k3;
-    if (t < tcut) {
+    if (t < tcut && t < KF64H_X) {
+        // S, T, U from one rational fit (power basis, as kfun64):
+        // k1 = S, k2 = -2 s2 T, k3 = 4 s2^2 U
+        const double tt = t * KF64H_INV_X;
+        double ps = kf64h_ps[0], pt = kf64h_pt[0], pu = kf64h_pu[0], q = kf64h_q[0], tk = 1.0;
+#pragma unroll
+        for (int i = 1; i <= KF64H_Q_DEG; ++i) {
+            tk *= tt;
+            ps = fma(kf64h_ps[i], tk, ps);
+            pt = fma(kf64h_pt[i], tk, pt);
+            pu = fma(kf64h_pu[i], tk, pu);
+            q = fma(kf64h_q[i], tk, q);
+        }
+        double r = __builtin_amdgcn_rcp(q);
+        const double er = fma(-q, r, 1.0);      // third-order correction of 1/q
+        r = fma(r, fma(er, er, er), r);
+        k1 = ps * r;
+        k2 = -2.0 * s.s2 * (pt * r);
+        k3 = 4.0 * s.s2 * s.s2 * (pu * r);
+    } else if (t < tcut) {
         double et;
         radial3(t, s.s2, k1, k2, k3, et);
     } else {
