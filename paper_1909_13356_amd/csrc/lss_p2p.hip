@@ -942,7 +942,7 @@ __device__ __forceinline__ void fmm_m2p_list_hess(const FmmEvalArgs &a, int32_t 
 // folded far form (pair_hess_far), the others pair_hess_cut, which still
 // chooses per pair.
 template <int TILE>
-__global__ __launch_bounds__(TILE) void k_hess_fmm(FmmEvalArgs a, double *hess) {
+__global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3))) void k_hess_fmm(FmmEvalArgs a, double *hess) {
     constexpr bool kSplit = TILE == 64;
     __shared__ Src sh[TILE];
     __shared__ FarD shf[kSplit ? TILE : 1];
