@@ -499,6 +499,7 @@ constexpr int kSmallClassPairs = 512;        // classes with at most this many p
 constexpr int kSmallMaxCoeffs = 512;         // target-major only for ncp up to this
 constexpr int kSmallRows = 2;                // rows per thread (256 threads)
 static_assert(256 * kSmallRows >= kSmallMaxCoeffs, "k_m2l_small: every coefficient needs a thread");
+static_assert(kNClass <= 4096, "k_m2l_small: the class index takes the low 12 bits of the key");
 __global__ __launch_bounds__(256) void k_m2l_small(int64_t npairs, const uint64_t *__restrict__ key,
                                                    const int32_t *__restrict__ src, const int32_t *__restrict__ cls_slot,
                                                    const int32_t *__restrict__ cls_nkv, const double *__restrict__ ops,
